@@ -1,0 +1,348 @@
+/*
+ * CPU brute-force oracle for the geometric-search hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline leg do.  It shares no code with the HIP library.
+ *
+ * What it computes is the plain definition of each query the paper's search
+ * index answers (Section 2.1, "Original interface" and "New interface";
+ * Section 2.2 for callbacks): for every query, every value is tested, so the
+ * result is the exact answer a hierarchy must reproduce.
+ *
+ *   - values: points [n][dim], or boxes [n][2][dim] (lo row then hi row);
+ *   - spatial (radius) query: the closed ball of radius r around a point;
+ *     result = indices of matching values, ascending, in CSR form (offsets +
+ *     indices, the compressed-sparse-row layout of Section 2.1);
+ *   - intersects(box) query: closed overlap of the query box with the value;
+ *   - nearest query: the k values closest to the query point, ordered by
+ *     (squared distance, index), padded with (+inf, -1) when k > n;
+ *   - pure-callback queries (Section 2.2, query form (1)): per-query COUNT, and
+ *     COUNT plus a fixed-point sum of distances, nothing stored per match;
+ *   - Chamfer loss of nearest-neighbour pairs and its gradient, in float64.
+ *
+ * Floating-point contract (the paper fixes none; this follows the exactness
+ * requirement of the hot path): squared distances in float32, one rounding per
+ * operation, summed over dimensions from 0 upwards starting at 0, no fused
+ * multiply-add (build with -ffp-contract=off), IEEE denormals, comparisons
+ * d2 <= fl(r*r).  Ties in nearest search go to the smaller index.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { KIND_POINTS = 0, KIND_BOXES = 1 };
+enum { RED_COUNT = 0, RED_COUNT_SUMDIST = 1 };
+
+/* Squared distance between two points: t_d = q_d - p_d, acc = acc + t_d*t_d. */
+static float dist2_point(const float *q, const float *p, int dim)
+{
+    float acc = 0.0f;
+    for (int d = 0; d < dim; ++d) {
+        float t = q[d] - p[d];
+        float s = t * t;
+        acc = acc + s;
+    }
+    return acc;
+}
+
+/* Squared distance from a point to a closed box: per dimension the gap to the
+ * nearer face (0 inside), accumulated as for two points. */
+static float dist2_box(const float *q, const float *lo, const float *hi, int dim)
+{
+    float acc = 0.0f;
+    for (int d = 0; d < dim; ++d) {
+        float t = 0.0f;
+        if (q[d] < lo[d])
+            t = lo[d] - q[d];
+        else if (q[d] > hi[d])
+            t = q[d] - hi[d];
+        float s = t * t;
+        acc = acc + s;
+    }
+    return acc;
+}
+
+/* Distance from query point q to value j. */
+static float dist2_value(const float *values, int64_t j, int dim, int kind, const float *q)
+{
+    if (kind == KIND_POINTS)
+        return dist2_point(q, values + j * dim, dim);
+    const float *lo = values + j * 2 * dim;
+    return dist2_box(q, lo, lo + dim, dim);
+}
+
+/* Closed overlap of query box [qlo,qhi] with value j. */
+static int overlaps_value(const float *values, int64_t j, int dim, int kind, const float *qlo, const float *qhi)
+{
+    const float *lo, *hi;
+    if (kind == KIND_POINTS) {
+        lo = hi = values + j * dim;
+    } else {
+        lo = values + j * 2 * dim;
+        hi = lo + dim;
+    }
+    for (int d = 0; d < dim; ++d)
+        if (!(lo[d] <= qhi[d] && qlo[d] <= hi[d]))
+            return 0;
+    return 1;
+}
+
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------ */
+/* spatial (radius) search                                              */
+/* ------------------------------------------------------------------ */
+
+int oracle_spatial_count(const float *values, int64_t n, int dim, int kind, const float *queries, int64_t m,
+                         float radius, int32_t *counts)
+{
+    const float r2 = radius * radius;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < m; ++i) {
+        const float *q = queries + i * dim;
+        int32_t c = 0;
+        for (int64_t j = 0; j < n; ++j)
+            if (dist2_value(values, j, dim, kind, q) <= r2)
+                ++c;
+        counts[i] = c;
+    }
+    return 0;
+}
+
+/* offsets[m+1] must hold the CSR offsets of the counts above. */
+int oracle_spatial_fill(const float *values, int64_t n, int dim, int kind, const float *queries, int64_t m,
+                        float radius, const int64_t *offsets, int32_t *indices)
+{
+    const float r2 = radius * radius;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < m; ++i) {
+        const float *q = queries + i * dim;
+        int64_t o = offsets[i];
+        for (int64_t j = 0; j < n; ++j)
+            if (dist2_value(values, j, dim, kind, q) <= r2)
+                indices[o++] = (int32_t)j;
+    }
+    return 0;
+}
+
+/* Query boxes are [m][2][dim]. */
+int oracle_intersects_count(const float *values, int64_t n, int dim, int kind, const float *qboxes, int64_t m,
+                            int32_t *counts)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < m; ++i) {
+        const float *qlo = qboxes + i * 2 * dim;
+        int32_t c = 0;
+        for (int64_t j = 0; j < n; ++j)
+            c += overlaps_value(values, j, dim, kind, qlo, qlo + dim);
+        counts[i] = c;
+    }
+    return 0;
+}
+
+int oracle_intersects_fill(const float *values, int64_t n, int dim, int kind, const float *qboxes, int64_t m,
+                           const int64_t *offsets, int32_t *indices)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < m; ++i) {
+        const float *qlo = qboxes + i * 2 * dim;
+        int64_t o = offsets[i];
+        for (int64_t j = 0; j < n; ++j)
+            if (overlaps_value(values, j, dim, kind, qlo, qlo + dim))
+                indices[o++] = (int32_t)j;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* pure-callback reductions                                             */
+/* ------------------------------------------------------------------ */
+
+/* COUNT: number of matches.  COUNT_SUMDIST: also the sum over matches of
+ * trunc(sqrtf(d2) * 2^scale_bits) as a 64-bit integer, which makes the sum
+ * independent of the order in which matches are visited. */
+int oracle_reduce(const float *values, int64_t n, int dim, int kind, const float *queries, int64_t m,
+                  float radius, int op, int scale_bits, int32_t *counts, int64_t *sum_fixed)
+{
+    const float r2 = radius * radius;
+    const float scale = ldexpf(1.0f, scale_bits);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < m; ++i) {
+        const float *q = queries + i * dim;
+        int32_t c = 0;
+        int64_t s = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            float d2 = dist2_value(values, j, dim, kind, q);
+            if (d2 <= r2) {
+                ++c;
+                if (op == RED_COUNT_SUMDIST) {
+                    float dist = sqrtf(d2);
+                    float scaled = dist * scale;
+                    s += (int64_t)scaled;
+                }
+            }
+        }
+        counts[i] = c;
+        if (op == RED_COUNT_SUMDIST)
+            sum_fixed[i] = s;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* nearest (kNN)                                                        */
+/* ------------------------------------------------------------------ */
+
+/* (da, ia) < (db, ib) in the order (squared distance, then index). */
+static int pair_less(float da, int32_t ia, float db, int32_t ib)
+{
+    return da < db || (da == db && ia < ib);
+}
+
+/* The first min(k, n) values in the order (d2, index), ascending; remaining
+ * slots (+inf, -1).  A sorted list of the best k so far is kept and each value
+ * is inserted where it belongs, which yields the first k of the full order. */
+int oracle_knn(const float *values, int64_t n, int dim, int kind, const float *queries, int64_t m, int k,
+               float *dist2, int32_t *indices)
+{
+    if (k <= 0)
+        return 1;
+#pragma omp parallel
+    {
+        float *bd = (float *)malloc(sizeof(float) * (size_t)k);
+        int32_t *bi = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < m; ++i) {
+            const float *q = queries + i * dim;
+            int have = 0;
+            for (int64_t j = 0; j < n; ++j) {
+                float d = dist2_value(values, j, dim, kind, q);
+                int32_t jj = (int32_t)j;
+                if (have == k && !pair_less(d, jj, bd[k - 1], bi[k - 1]))
+                    continue;
+                int pos = have < k ? have : k - 1;
+                while (pos > 0 && pair_less(d, jj, bd[pos - 1], bi[pos - 1])) {
+                    bd[pos] = bd[pos - 1];
+                    bi[pos] = bi[pos - 1];
+                    --pos;
+                }
+                bd[pos] = d;
+                bi[pos] = jj;
+                if (have < k)
+                    ++have;
+            }
+            for (int s = 0; s < k; ++s) {
+                dist2[i * k + s] = s < have ? bd[s] : INFINITY;
+                indices[i * k + s] = s < have ? bi[s] : -1;
+            }
+        }
+        free(bd);
+        free(bi);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Chamfer loss of nearest-neighbour pairs (float64 reference)          */
+/* ------------------------------------------------------------------ */
+
+/* Nearest neighbour (k = 1, ties to the smaller index) of each point of one
+ * cloud within another; -1 if the other cloud is empty. */
+static void nn_cloud(const float *src, int64_t ns, const float *dst, int64_t nd, int32_t *nn, float *d2out)
+{
+    for (int64_t i = 0; i < ns; ++i) {
+        float best = INFINITY;
+        int32_t bi = -1;
+        for (int64_t j = 0; j < nd; ++j) {
+            float d = dist2_point(src + i * 3, dst + j * 3, 3);
+            if (bi < 0 || pair_less(d, (int32_t)j, best, bi)) {
+                best = d;
+                bi = (int32_t)j;
+            }
+        }
+        nn[i] = bi;
+        d2out[i] = best;
+    }
+}
+
+/* Pair p holds a[a_off[p]..a_off[p+1]) and b[b_off[p]..b_off[p+1]) (3D).
+ * nn_ab[i] = local index in B_p of the nearest point to a_i; nn_ba likewise.
+ * loss[p] = sum_i d2(a_i, B_p) + sum_j d2(b_j, A_p), float32 terms summed in
+ * float64 in ascending point order (all of A_p, then all of B_p). */
+int oracle_chamfer_forward(const float *a, const int64_t *a_off, const float *b, const int64_t *b_off, int P,
+                           double *loss, int32_t *nn_ab, int32_t *nn_ba)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int p = 0; p < P; ++p) {
+        int64_t na = a_off[p + 1] - a_off[p], nb = b_off[p + 1] - b_off[p];
+        const float *ap = a + a_off[p] * 3, *bp = b + b_off[p] * 3;
+        float *da = (float *)malloc(sizeof(float) * (size_t)(na > 0 ? na : 1));
+        float *db = (float *)malloc(sizeof(float) * (size_t)(nb > 0 ? nb : 1));
+        nn_cloud(ap, na, bp, nb, nn_ab + a_off[p], da);
+        nn_cloud(bp, nb, ap, na, nn_ba + b_off[p], db);
+        double s = 0.0;
+        if (nb > 0)
+            for (int64_t i = 0; i < na; ++i)
+                s += (double)da[i];
+        if (na > 0)
+            for (int64_t j = 0; j < nb; ++j)
+                s += (double)db[j];
+        loss[p] = s;
+        free(da);
+        free(db);
+    }
+    return 0;
+}
+
+/* Gradient of loss[p] = sum_i |a_i - b_nn(i)|^2 + sum_j |b_j - a_nn(j)|^2 with
+ * the neighbour assignment held fixed, times grad_loss[p]:
+ *   dL/da_i = 2(a_i - b_nn(i)) + sum_{j : nn_ba(j) = i} 2(a_i - b_j)
+ * and symmetrically for b.  Computed in float64 from float32 coordinates. */
+int oracle_chamfer_backward(const float *a, const int64_t *a_off, const float *b, const int64_t *b_off, int P,
+                            const int32_t *nn_ab, const int32_t *nn_ba, const double *grad_loss, double *grad_a,
+                            double *grad_b)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int p = 0; p < P; ++p) {
+        int64_t a0 = a_off[p], na = a_off[p + 1] - a0, b0 = b_off[p], nb = b_off[p + 1] - b0;
+        double g = grad_loss[p];
+        for (int64_t i = 0; i < na * 3; ++i)
+            grad_a[a0 * 3 + i] = 0.0;
+        for (int64_t j = 0; j < nb * 3; ++j)
+            grad_b[b0 * 3 + j] = 0.0;
+        for (int64_t i = 0; i < na; ++i) {
+            int32_t j = nn_ab[a0 + i];
+            if (j < 0)
+                continue;
+            for (int d = 0; d < 3; ++d) {
+                double diff = (double)a[(a0 + i) * 3 + d] - (double)b[(b0 + j) * 3 + d];
+                grad_a[(a0 + i) * 3 + d] += 2.0 * g * diff;
+                grad_b[(b0 + j) * 3 + d] -= 2.0 * g * diff;
+            }
+        }
+        for (int64_t j = 0; j < nb; ++j) {
+            int32_t i = nn_ba[b0 + j];
+            if (i < 0)
+                continue;
+            for (int d = 0; d < 3; ++d) {
+                double diff = (double)b[(b0 + j) * 3 + d] - (double)a[(a0 + i) * 3 + d];
+                grad_b[(b0 + j) * 3 + d] += 2.0 * g * diff;
+                grad_a[(a0 + i) * 3 + d] -= 2.0 * g * diff;
+            }
+        }
+    }
+    return 0;
+}

@@ -1,0 +1,455 @@
+"""Pins for the CPU oracle, independent of the oracle's own code.
+
+Each check rests on something other than the oracle's formulas: hand-worked
+fixtures (tests/golden), scipy's k-d tree in float64 (a different algorithm and
+precision), an exact-rational emulation of the binary32 rounding contract,
+pure-Python brute force on tiny inputs, closed-form invariants, and float64
+finite differences for the Chamfer gradient.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+
+import oracle
+from conftest import golden
+from paper_2507_23700_amd import inputs
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+# ---------------------------------------------------------------------------
+# hand-worked fixtures
+# ---------------------------------------------------------------------------
+
+def test_golden_line4():
+    rows = golden("line4_query.txt")
+    vals = np.array([float(x) for x in rows[0][1]], dtype=np.float32).reshape(-1, 3)
+    q = np.array([[float(x) for x in rows[1][1]]], dtype=np.float32)
+    i = 2
+    while i < len(rows):
+        key, v = rows[i]
+        if key == "radius":
+            r = np.float32(v[0])
+            want = [int(x) for x in rows[i + 1][1]]
+            off, idx = oracle.spatial(vals, q, r)
+            assert off.tolist() == [0, len(want)]
+            assert idx.tolist() == want
+            i += 2
+            continue
+        if key == "knn":
+            k = int(v[0])
+            d2, ix = oracle.knn(vals, q, k)
+            exp = [(float(a), int(b)) for a, b in (t.split(":") for t in v[1:])]
+            assert [(float(d), int(j)) for d, j in zip(d2[0], ix[0])] == exp
+        if key == "sumdist":
+            c, s = oracle.reduce(vals, q, np.float32(v[0]))
+            assert int(c[0]) == int(v[1]) and int(s[0]) == int(v[2])
+        i += 1
+
+
+def test_golden_line4_radius_just_below():
+    # r = 0.5 - 2^-25 must be the float32 nextafter(0.5, 0) used in the fixture.
+    assert np.float32(0.49999997) == np.nextafter(np.float32(0.5), np.float32(0))
+
+
+def test_golden_chamfer():
+    g = dict(golden("chamfer_tiny.txt"))
+    a = np.array(g["a"], dtype=np.float32).reshape(-1, 3)
+    b = np.array(g["b"], dtype=np.float32).reshape(-1, 3)
+    loss, nab, nba = oracle.chamfer_forward(a, [0, len(a)], b, [0, len(b)])
+    assert nab.tolist() == [int(x) for x in g["nn_ab"]]
+    assert nba.tolist() == [int(x) for x in g["nn_ba"]]
+    assert loss[0] == float(g["loss"][0])
+    ga, gb = oracle.chamfer_backward(a, [0, len(a)], b, [0, len(b)], nab, nba, [1.0])
+    assert ga.ravel().tolist() == [float(x) for x in g["grad_a"]]
+    assert gb.ravel().tolist() == [float(x) for x in g["grad_b"]]
+
+
+# ---------------------------------------------------------------------------
+# binary32 rounding contract, by exact rational arithmetic
+# ---------------------------------------------------------------------------
+
+def rne32(x: Fraction) -> Fraction:
+    """Round a rational to the nearest binary32 value, ties to even (normal and subnormal range)."""
+    if x == 0:
+        return Fraction(0)
+    s = -1 if x < 0 else 1
+    a = abs(x)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if Fraction(2) ** e > a:
+        e -= 1
+    e = max(e, -126)
+    ulp = Fraction(2) ** (e - 23)
+    q = a / ulp
+    n = q.numerator // q.denominator
+    rem = q - n
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and n % 2 == 1):
+        n += 1
+    return s * n * ulp
+
+
+def exact_d2(q, p):
+    acc = Fraction(0)
+    for qd, pd in zip(q, p):
+        t = rne32(Fraction(float(qd)) - Fraction(float(pd)))
+        acc = rne32(acc + rne32(t * t))
+    return acc
+
+
+def fused_d2(q, p):
+    """What a fused multiply-add accumulation would give (the contract forbids it)."""
+    acc = Fraction(0)
+    for qd, pd in zip(q, p):
+        t = rne32(Fraction(float(qd)) - Fraction(float(pd)))
+        acc = rne32(acc + t * t)
+    return acc
+
+
+def wide_d2(q, p):
+    """Accumulate exactly and round once (also forbidden)."""
+    acc = Fraction(0)
+    for qd, pd in zip(q, p):
+        t = rne32(Fraction(float(qd)) - Fraction(float(pd)))
+        acc += t * t
+    return rne32(acc)
+
+
+@pytest.mark.parametrize("dim", [3, 6])
+def test_rounding_contract_exact(dim):
+    g = np.random.default_rng(7 + dim)
+    vals = (g.random((200, dim)) * g.choice([1e-3, 1.0, 100.0], size=(200, 1))).astype(np.float32)
+    qs = (g.random((4, dim))).astype(np.float32)
+    d2, ix = oracle.knn(vals, qs, len(vals), dim=dim)
+    differs_fused = differs_wide = 0
+    for i in range(len(qs)):
+        for d, j in zip(d2[i], ix[i]):
+            e = exact_d2(qs[i], vals[j])
+            assert Fraction(float(d)) == e
+            differs_fused += fused_d2(qs[i], vals[j]) != e
+            differs_wide += wide_d2(qs[i], vals[j]) != e
+    # the check has teeth: the forbidden evaluation orders differ on these inputs
+    assert differs_fused > 0 and differs_wide > 0
+
+
+def test_denormal_distances_preserved():
+    # points 1e-20 apart: d2 = 1e-40 is subnormal in binary32 and must not flush to 0
+    vals = np.array([[0, 0, 0], [1e-20, 0, 0]], dtype=np.float32)
+    q = np.array([[0, 0, 0]], dtype=np.float32)
+    d2, ix = oracle.knn(vals, q, 2)
+    assert ix[0].tolist() == [0, 1]
+    assert d2[0, 1] > 0 and Fraction(float(d2[0, 1])) == exact_d2(q[0], vals[1])
+    off, idx = oracle.spatial(vals, q, np.float32(0.0))
+    assert idx.tolist() == [0]
+
+
+# ---------------------------------------------------------------------------
+# against scipy's k-d tree in float64
+# ---------------------------------------------------------------------------
+
+def _bracket_sets(data, queries, r, tol=1e-5):
+    t = cKDTree(data.astype(np.float64))
+    inner = t.query_ball_point(queries.astype(np.float64), float(r) * (1 - tol))
+    outer = t.query_ball_point(queries.astype(np.float64), float(r) * (1 + tol))
+    return inner, outer
+
+
+@pytest.mark.parametrize("dist", ["cube", "shell", "gmm6"])
+def test_spatial_vs_kdtree(dist):
+    if dist == "cube":
+        cfg = inputs.config_small(n=4000, m=400)
+        dim = 3
+    elif dist == "shell":
+        cfg = inputs.config_paper("shell", n=4000, m=400)
+        dim = 3
+    else:
+        cfg = inputs.config_gmm6(n=4000, m=400)
+        dim = 6
+    data, q, r = cfg["data"], cfg["queries"], cfg["radius"]
+    off, idx = oracle.spatial(data, q, r, dim=dim)
+    inner, outer = _bracket_sets(data, q, r)
+    total = 0
+    for i in range(len(q)):
+        row = idx[off[i]:off[i + 1]]
+        assert np.all(np.diff(row) > 0), "rows ascending, no duplicates"
+        s = set(row.tolist())
+        assert set(inner[i]) <= s <= set(outer[i])
+        total += len(row)
+    assert total > len(q)  # non-trivial workload
+
+
+@pytest.mark.parametrize("k", [1, 10, 16])
+def test_knn_vs_kdtree(k):
+    cfg = inputs.config_small(n=3000, m=300)
+    data, q = cfg["data"], cfg["queries"]
+    d2, ix = oracle.knn(data, q, k)
+    dd, ii = cKDTree(data.astype(np.float64)).query(q.astype(np.float64), k=k + 1)
+    dd = dd ** 2
+    np.testing.assert_allclose(d2, dd[:, :k], rtol=2e-6, atol=1e-12)
+    for i in range(len(q)):
+        # compare index sets where the float64 order is well separated from ties
+        sep = np.abs(np.diff(dd[i])) > 1e-5 * dd[i, 1:]
+        for s in range(k):
+            left_ok = s == 0 or sep[s - 1]
+            right_ok = sep[s]
+            if left_ok and right_ok:
+                assert ix[i, s] == ii[i, s]
+
+
+def test_reduce_sumdist_vs_kdtree():
+    cfg = inputs.config_small(n=3000, m=300)
+    data, q, r = cfg["data"], cfg["queries"], cfg["radius"]
+    c, s = oracle.reduce(data, q, r)
+    c0, _ = oracle.reduce(data, q, r, op=oracle.COUNT)
+    assert np.array_equal(c, c0)
+    t = cKDTree(data.astype(np.float64))
+    inner, outer = _bracket_sets(data, q, r)
+    for i in range(len(q)):
+        assert len(inner[i]) <= c[i] <= len(outer[i])
+        if len(inner[i]) == len(outer[i]):
+            dist = np.linalg.norm(data[inner[i]].astype(np.float64) - q[i].astype(np.float64), axis=1)
+            # each term is trunc(d*2^32) with d correctly rounded to binary32
+            assert abs(s[i] / 2.0 ** 32 - dist.sum()) <= c[i] * (2.0 ** -32 + 1e-6)
+    del t
+
+
+# ---------------------------------------------------------------------------
+# boxes and intersects: pure-Python brute force on tiny inputs, special cases
+# ---------------------------------------------------------------------------
+
+def _py_box_d2(q, lo, hi):
+    acc = np.float32(0)
+    for d in range(len(q)):
+        if q[d] < lo[d]:
+            t = np.float32(lo[d] - q[d])
+        elif q[d] > hi[d]:
+            t = np.float32(q[d] - hi[d])
+        else:
+            t = np.float32(0)
+        acc = np.float32(acc + np.float32(t * t))
+    return acc
+
+
+def _random_boxes(g, n, dim):
+    c = g.random((n, dim)).astype(np.float32)
+    h = (g.random((n, dim)) * 0.05).astype(np.float32)
+    return np.ascontiguousarray(np.stack([c - h, c + h], axis=1))
+
+
+def test_boxes_radius_and_knn_tiny_bruteforce():
+    g = np.random.default_rng(11)
+    boxes = _random_boxes(g, 60, 3)
+    q = g.random((15, 3)).astype(np.float32)
+    r = np.float32(0.12)
+    off, idx = oracle.spatial(boxes, q, r, kind=oracle.BOXES)
+    d2, ix = oracle.knn(boxes, q, 7, kind=oracle.BOXES)
+    for i in range(len(q)):
+        d = [_py_box_d2(q[i], boxes[j, 0], boxes[j, 1]) for j in range(len(boxes))]
+        want = [j for j in range(len(boxes)) if d[j] <= np.float32(r * r)]
+        assert idx[off[i]:off[i + 1]].tolist() == want
+        order = sorted(range(len(boxes)), key=lambda j: (d[j], j))[:7]
+        assert ix[i].tolist() == order
+        assert d2[i].tolist() == [float(d[j]) for j in order]
+
+
+def test_degenerate_boxes_equal_points():
+    cfg = inputs.config_small(n=1500, m=200)
+    data, q, r = cfg["data"], cfg["queries"], cfg["radius"]
+    boxes = np.ascontiguousarray(np.stack([data, data], axis=1))
+    o1, i1 = oracle.spatial(data, q, r)
+    o2, i2 = oracle.spatial(boxes, q, r, kind=oracle.BOXES)
+    assert np.array_equal(o1, o2) and np.array_equal(i1, i2)
+    a1, b1 = oracle.knn(data, q, 10)
+    a2, b2 = oracle.knn(boxes, q, 10, kind=oracle.BOXES)
+    assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+
+
+def test_intersects_tiny_bruteforce_and_special_cases():
+    g = np.random.default_rng(12)
+    for kind in (oracle.POINTS, oracle.BOXES):
+        vals = g.random((80, 3)).astype(np.float32) if kind == oracle.POINTS else _random_boxes(g, 80, 3)
+        qb = _random_boxes(g, 20, 3) * np.float32(1)
+        qb[:, 1] += np.float32(0.1)
+        off, idx = oracle.intersects(vals, qb, kind=kind)
+        for i in range(len(qb)):
+            want = []
+            for j in range(len(vals)):
+                lo, hi = (vals[j], vals[j]) if kind == oracle.POINTS else (vals[j, 0], vals[j, 1])
+                if all(lo[d] <= qb[i, 1, d] and qb[i, 0, d] <= hi[d] for d in range(3)):
+                    want.append(j)
+            assert idx[off[i]:off[i + 1]].tolist() == want
+    # a degenerate query box {q} against boxes is the radius-0 search (inside the closed box)
+    boxes = _random_boxes(g, 300, 3)
+    q = g.random((50, 3)).astype(np.float32)
+    o1, i1 = oracle.intersects(boxes, np.ascontiguousarray(np.stack([q, q], axis=1)), kind=oracle.BOXES)
+    o2, i2 = oracle.spatial(boxes, q, np.float32(0), kind=oracle.BOXES)
+    assert np.array_equal(o1, o2) and np.array_equal(i1, i2)
+
+
+# ---------------------------------------------------------------------------
+# invariants and edge cases
+# ---------------------------------------------------------------------------
+
+def test_knn_order_and_prefix():
+    cfg = inputs.config_small(n=2000, m=300)
+    data = np.concatenate([cfg["data"], cfg["data"][:200]])  # exact duplicates -> ties
+    q = np.concatenate([cfg["queries"], data[:50]])
+    d8, i8 = oracle.knn(data, q, 8)
+    d9, i9 = oracle.knn(data, q, 9)
+    assert np.array_equal(d8, d9[:, :8]) and np.array_equal(i8, i9[:, :8])
+    for i in range(len(q)):
+        pairs = list(zip(d9[i].tolist(), i9[i].tolist()))
+        assert pairs == sorted(pairs)
+        assert len(set(i9[i].tolist())) == 9
+
+
+def test_knn_inside_radius_of_kth():
+    cfg = inputs.config_small(n=2000, m=200)
+    data, q = cfg["data"], cfg["queries"]
+    k = 12
+    d2, ix = oracle.knn(data, q, k)
+    for i in range(0, len(q), 10):
+        dk = d2[i, -1]
+        r = np.float32(np.sqrt(np.float64(dk)))
+        while np.float32(r * r) < dk:
+            r = np.nextafter(r, np.float32(np.inf))
+        off, idx = oracle.spatial(data, q[i:i + 1], r)
+        assert set(ix[i].tolist()) <= set(idx.tolist())
+
+
+def test_self_join_symmetry_and_monotonicity():
+    cfg = inputs.config_small(n=1500, m=10)
+    data, r = cfg["data"], cfg["radius"]
+    off, idx = oracle.spatial(data, data, r)
+    pairs = set()
+    for i in range(len(data)):
+        for j in idx[off[i]:off[i + 1]]:
+            pairs.add((i, int(j)))
+    assert all((j, i) in pairs for i, j in pairs)
+    assert all((i, i) in pairs for i in range(len(data)))
+    c1 = np.diff(off)
+    c2 = oracle.spatial_count(data, data, np.float32(r * 1.5))
+    assert np.all(c2 >= c1)
+
+
+def test_radius_zero_and_infinite():
+    g = np.random.default_rng(3)
+    data = g.random((300, 3)).astype(np.float32)
+    data[100:110] = data[5]
+    q = np.concatenate([data[:20], g.random((5, 3)).astype(np.float32)])
+    off, idx = oracle.spatial(data, q, np.float32(0))
+    for i in range(len(q)):
+        want = np.nonzero(np.all(data == q[i], axis=1))[0].tolist()
+        assert idx[off[i]:off[i + 1]].tolist() == want
+    c = oracle.spatial_count(data, q, np.float32(np.inf))
+    assert np.all(c == len(data))
+
+
+def test_empty_and_small_k():
+    q = np.zeros((3, 3), dtype=np.float32)
+    empty = np.zeros((0, 3), dtype=np.float32)
+    off, idx = oracle.spatial(empty, q, np.float32(1))
+    assert off.tolist() == [0, 0, 0, 0] and len(idx) == 0
+    d2, ix = oracle.knn(empty, q, 4)
+    assert np.all(np.isinf(d2)) and np.all(ix == -1)
+    one = np.ones((1, 3), dtype=np.float32)
+    d2, ix = oracle.knn(one, q, 3)
+    assert ix[:, 0].tolist() == [0, 0, 0] and np.all(ix[:, 1:] == -1)
+    assert d2[0, 0] == 3.0
+    off, idx = oracle.spatial(one, np.zeros((0, 3), dtype=np.float32), np.float32(1))
+    assert off.tolist() == [0]
+
+
+def test_planar_and_all_equal_inputs():
+    g = np.random.default_rng(5)
+    data = g.random((500, 3)).astype(np.float32)
+    data[:, 2] = 0
+    q = g.random((40, 3)).astype(np.float32)
+    q[:, 2] = 0
+    inner, outer = _bracket_sets(data, q, 0.1)
+    off, idx = oracle.spatial(data, q, np.float32(0.1))
+    for i in range(len(q)):
+        assert set(inner[i]) <= set(idx[off[i]:off[i + 1]].tolist()) <= set(outer[i])
+    same = np.tile(np.float32([0.25, 0.5, 0.75]), (64, 1))
+    d2, ix = oracle.knn(same, q[:3], 5)
+    assert np.all(ix == np.arange(5))
+
+
+# ---------------------------------------------------------------------------
+# Chamfer: float64 finite differences and invariants
+# ---------------------------------------------------------------------------
+
+def _np_chamfer64(a, b):
+    d = ((a[:, None, :] - b[None, :, :]) ** 2).sum(-1)
+    return d.min(1).sum() + d.min(0).sum(), d.argmin(1), d.argmin(0)
+
+
+def test_chamfer_finite_differences():
+    cfg = inputs.chamfer_pairs(pairs=4, lo=64, hi=64, cfg=40)
+    a, ao, b, bo = cfg["a"], cfg["a_off"], cfg["b"], cfg["b_off"]
+    loss, nab, nba = oracle.chamfer_forward(a, ao, b, bo)
+    gw = np.array([1.0, -0.5, 2.0, 0.25])
+    ga, gb = oracle.chamfer_backward(a, ao, b, bo, nab, nba, gw)
+    h = 1e-4
+    for p in range(4):
+        A = a[ao[p]:ao[p + 1]].astype(np.float64)
+        B = b[bo[p]:bo[p + 1]].astype(np.float64)
+        L, nn1, nn2 = _np_chamfer64(A, B)
+        assert np.array_equal(nn1, nab[ao[p]:ao[p + 1]]) and np.array_equal(nn2, nba[bo[p]:bo[p + 1]])
+        assert abs(loss[p] - L) <= 1e-6 * L
+        fd_a = np.zeros_like(A)
+        for i in range(len(A)):
+            for d in range(3):
+                Ap, Am = A.copy(), A.copy()
+                Ap[i, d] += h
+                Am[i, d] -= h
+                lp, n1p, n2p = _np_chamfer64(Ap, B)
+                lm, n1m, n2m = _np_chamfer64(Am, B)
+                assert np.array_equal(n1p, nn1) and np.array_equal(n2m, nn2)
+                fd_a[i, d] = gw[p] * (lp - lm) / (2 * h)
+        g = ga[ao[p]:ao[p + 1]]
+        assert np.max(np.abs(g - fd_a)) <= 1e-5 * np.max(np.abs(fd_a))
+        fd_b = np.zeros_like(B)
+        for j in range(0, len(B), 7):
+            for d in range(3):
+                Bp, Bm = B.copy(), B.copy()
+                Bp[j, d] += h
+                Bm[j, d] -= h
+                fd_b[j, d] = gw[p] * (_np_chamfer64(A, Bp)[0] - _np_chamfer64(A, Bm)[0]) / (2 * h)
+        gbp = gb[bo[p]:bo[p + 1]]
+        sel = slice(0, len(B), 7)
+        assert np.max(np.abs(gbp[sel] - fd_b[sel])) <= 1e-5 * np.max(np.abs(fd_b[sel]))
+
+
+def test_chamfer_invariants():
+    cfg = inputs.chamfer_pairs(pairs=6, lo=200, hi=900, cfg=41)
+    a, ao, b, bo = cfg["a"], cfg["a_off"], cfg["b"], cfg["b_off"]
+    loss, nab, nba = oracle.chamfer_forward(a, ao, b, bo)
+    ga, gb = oracle.chamfer_backward(a, ao, b, bo, nab, nba, np.ones(6))
+    for p in range(6):
+        gA, gB = ga[ao[p]:ao[p + 1]], gb[bo[p]:bo[p + 1]]
+        A, B = a[ao[p]:ao[p + 1]].astype(np.float64), b[bo[p]:bo[p + 1]].astype(np.float64)
+        # translation invariance: the gradient sums to zero
+        scale = np.abs(gA).sum() + np.abs(gB).sum()
+        assert np.abs(gA.sum(0) + gB.sum(0)).max() <= 1e-12 * scale
+        # degree-2 homogeneity: sum x . dL/dx = 2 L
+        assert abs((A * gA).sum() + (B * gB).sum() - 2 * loss[p]) <= 1e-6 * loss[p]
+
+
+def test_forest_is_per_tree():
+    g = np.random.default_rng(9)
+    values = g.random((700, 3)).astype(np.float32)
+    toff = np.array([0, 300, 300, 700])
+    q = g.random((90, 3)).astype(np.float32)
+    boff = np.array([0, 30, 60, 90])
+    bt = np.array([2, 0, 1], dtype=np.int32)
+    br = np.array([0.1, 0.2, 0.3], dtype=np.float32)
+    c, s = oracle.forest_reduce(values, toff, q, boff, bt, br)
+    c2, s2 = oracle.reduce(values[300:700], q[:30], br[0])
+    assert np.array_equal(c[:30], c2) and np.array_equal(s[:30], s2)
+    assert np.all(c[60:] == 0)  # the empty tree
+    d2, ix = oracle.forest_knn(values, toff, q, boff, bt, 4)
+    assert np.all(ix[60:] == -1)
+    assert ix[:30].max() < 400  # local indices
