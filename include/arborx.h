@@ -1,0 +1,210 @@
+/*
+ * arborx.h — C ABI of an MI355X (gfx950) linear-BVH geometric search library.
+ *
+ * The operations follow the search index of the ArborX 2.0 paper (arXiv
+ * 2507.23700): a bounding volume hierarchy built from an array of values
+ * (Section 2.1, "New interface": the index constructor), queried with arrays of
+ * predicates in three forms (Section 2.1, query calls (1)-(3)): a storage query
+ * returning compressed-sparse-row offsets plus indices (Section 2.1, original
+ * interface and its footnote on the CSR format), and pure-callback queries that
+ * reduce per match without storing anything (Section 2.2).  Every call takes a
+ * stream, the counterpart of the paper's execution-space argument (Section
+ * 2.1, "Lack of execution spaces").  size/empty/bounds are `arborx_bvh_info`.
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers are DEVICE pointers unless marked [host].  Coordinates are
+ *     float32, row-major: points [n][dim]; boxes [n][2][dim] (the lo row, then
+ *     the hi row).  Result indices are int32 indices into the build input.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls are stream-ordered and asynchronous unless they return a [host]
+ *     value, in which case they synchronise `stream` before returning.
+ *   - The caller owns inputs and outputs and keeps them alive until `stream`
+ *     has passed the call.  Trees and forests own their device memory.
+ *   - Errors are status codes; nothing throws across the ABI.  Arguments are
+ *     validated on the host before any device work, and on error no output is
+ *     written.  arborx_last_error() returns a thread-local message.
+ *   - Distances are squared Euclidean distances computed in float32 with one
+ *     rounding per operation, dimensions summed from 0 upwards, no fused
+ *     multiply-add.  A radius r matches values with d2 <= fl(r*r) (closed ball).
+ *     For box values d2 is the distance to the nearest point of the box.
+ *   - Coordinates must be finite; results for NaN or infinite inputs are
+ *     unspecified (never a fault).
+ *   - Supported dimensions: 2, 3 and 6.  Other dim in 1..10 returns
+ *     ARBORX_E_UNSUPPORTED; dim outside 1..10 returns ARBORX_E_INVALID.
+ */
+#ifndef ARBORX355_ARBORX_H
+#define ARBORX355_ARBORX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct arborx_tree_s *arborx_tree;     /* opaque; immutable after build */
+typedef struct arborx_forest_s *arborx_forest; /* opaque; many trees in one structure */
+
+typedef enum {
+    ARBORX_OK = 0,
+    ARBORX_E_INVALID = 1,     /* bad argument (null pointer, negative size, NaN radius, ...) */
+    ARBORX_E_UNSUPPORTED = 2, /* valid but not compiled in (e.g. dim 4) */
+    ARBORX_E_NOMEM = 3,       /* device allocation failed */
+    ARBORX_E_CAPACITY = 4,    /* output buffer too small; *total says how much is needed */
+    ARBORX_E_DEVICE = 5       /* no usable GPU, or a HIP runtime error */
+} arborx_status;
+
+typedef enum { ARBORX_POINTS = 0, ARBORX_BOXES = 1 } arborx_kind;
+
+/* Pure-callback reducers (Section 2.2, query form (1)).
+ * COUNT:         counts[i] = number of values within the radius of query i.
+ * COUNT_SUMDIST: also sum_fixed[i] = sum over matches of trunc(sqrtf(d2) * 2^S),
+ *                an integer sum that does not depend on visiting order. */
+typedef enum { ARBORX_COUNT = 0, ARBORX_COUNT_SUMDIST = 1 } arborx_reducer;
+
+/* Traversal schedule knobs; every schedule returns identical results. */
+typedef struct arborx_tuning {
+    int32_t block;        /* threads per workgroup for traversal kernels: 64, 128, 256 (0 = default) */
+    int32_t order;        /* 1 = sort queries along the Morton curve before traversal, 0 = input order */
+    int32_t stack;        /* LDS short-stack entries per thread: 4..64 (0 = default); deeper trees spill */
+    int32_t schedule;     /* 0 = thread per query; 1 = wavefront packet (64 queries share node fetches) */
+} arborx_tuning;
+
+/* Library version string, e.g. "arborx355 0.1". [host] */
+const char *arborx_version(void);
+
+/* Thread-local message describing the last error of this thread ("" if none). [host] */
+const char *arborx_last_error(void);
+
+/* Set the traversal schedule used by later queries; NULL restores the defaults.  [host] */
+arborx_status arborx_set_tuning(const arborx_tuning *tuning);
+
+/* Current traversal schedule. [host] */
+arborx_status arborx_get_tuning(arborx_tuning *tuning);
+
+/*
+ * Build a BVH over n values (Section 2.1, index constructor; Section 2.6: 64-bit
+ * Morton codes and a bottom-up hierarchy construction).
+ *   values  [n][dim] points or [n][2][dim] boxes (kind), device, read during the call only
+ *   n       0 <= n < 2^31-1; n = 0 gives an empty tree (queries return nothing)
+ *   out     [host] receives the tree handle; destroy with arborx_bvh_destroy
+ * Work is queued on `stream`; the tree may be queried on any stream afterwards
+ * (queries on other streams wait for the build).  Returns ARBORX_E_NOMEM if
+ * device memory runs out.
+ */
+arborx_status arborx_bvh_build(const float *values, int64_t n, int32_t dim, int32_t kind, void *stream,
+                               arborx_tree *out);
+
+/* Release a tree.  Waits for outstanding work on the tree.  NULL is allowed. [host] */
+arborx_status arborx_bvh_destroy(arborx_tree tree);
+
+/*
+ * Tree metadata (Section 2.1: size(), empty(), bounds()).  Synchronises with the build.
+ *   n       [host] number of values (0 = empty)
+ *   dim     [host] dimension;  kind [host] ARBORX_POINTS or ARBORX_BOXES
+ *   bounds  [host] 2*dim floats: lo then hi of the scene box (+inf/-inf when empty); may be NULL
+ *   height  [host] edges on the longest root-to-leaf path; may be NULL
+ */
+arborx_status arborx_bvh_info(arborx_tree tree, int64_t *n, int32_t *dim, int32_t *kind, float *bounds,
+                              int32_t *height);
+
+/*
+ * Radius (sphere) search with CSR output (Section 2.1, storage query (3)).
+ *   queries   [m][dim] query points
+ *   radius    >= 0 (may be +inf); NaN is ARBORX_E_INVALID
+ *   offsets   [m+1] int64, caller-allocated: offsets[0] = 0, offsets[i+1]-offsets[i] = matches of query i
+ *   indices   int32 matches, row i at [offsets[i], offsets[i+1]), ascending within each row
+ *   capacity  number of int32 slots in indices
+ *   total     [host] receives offsets[m]
+ * Two-phase protocol: if indices is NULL or capacity < total, offsets and
+ * *total are filled and ARBORX_E_CAPACITY is returned; call again with a
+ * large enough buffer.  Synchronises `stream` (to read the total).
+ */
+arborx_status arborx_query_spatial(arborx_tree tree, const float *queries, int64_t m, float radius, int64_t *offsets,
+                                   int32_t *indices, int64_t capacity, int64_t *total, void *stream);
+
+/*
+ * Box-overlap search with CSR output (Section 2.1, intersects predicate).
+ *   qboxes  [m][2][dim] query boxes; a value matches if its box (a point is a
+ *           degenerate box) overlaps the closed query box in every dimension.
+ * Everything else as arborx_query_spatial.
+ */
+arborx_status arborx_query_intersects(arborx_tree tree, const float *qboxes, int64_t m, int64_t *offsets,
+                                      int32_t *indices, int64_t capacity, int64_t *total, void *stream);
+
+/*
+ * k-nearest search (Section 2.1, nearest predicate: a point and a number of
+ * neighbours).  Row i of the [m][k] outputs holds the min(k, n) values nearest
+ * to query i in ascending (d2, index) order (ties go to the smaller index);
+ * the rest of the row is (+inf, -1).
+ *   k       1..64
+ *   dist2   [m][k] float32 squared distances;  indices [m][k] int32
+ * Does not synchronise.
+ */
+arborx_status arborx_query_knn(arborx_tree tree, const float *queries, int64_t m, int32_t k, float *dist2,
+                               int32_t *indices, void *stream);
+
+/*
+ * Radius search fused with a per-query reduction; nothing is stored per match
+ * (Section 2.2, pure callback).
+ *   op          ARBORX_COUNT or ARBORX_COUNT_SUMDIST
+ *   counts      [m] int32
+ *   sum_fixed   [m] int64, required for COUNT_SUMDIST (ignored, may be NULL, for COUNT)
+ *   scale_bits  S in 0..40 for COUNT_SUMDIST; each match adds trunc(sqrtf(d2) * 2^S)
+ * Does not synchronise.
+ */
+arborx_status arborx_query_spatial_reduce(arborx_tree tree, const float *queries, int64_t m, float radius,
+                                          int32_t op, int32_t *counts, int64_t *sum_fixed, int32_t scale_bits,
+                                          void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics: building blocks exposed for component tests.                */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Stable LSD radix sort of (key, value) pairs by key bits [begin_bit, end_bit),
+ * in place.  keys: uint64 when key_bits == 64, uint32 when key_bits == 32.
+ * Equal keys keep their input order.  Does not synchronise.
+ */
+arborx_status arborx_debug_radix_sort(void *keys, uint32_t *values, int64_t n, int32_t key_bits, int32_t begin_bit,
+                                      int32_t end_bit, void *stream);
+
+/*
+ * 64-bit Morton codes of n points [n][dim] normalised by the box bounds [2][dim]
+ * (device, lo row then hi row): b = floor(63/dim) bits per dimension, cell
+ * q_d = clamp(floor((x_d - lo_d) / (hi_d - lo_d) * 2^b), 0, 2^b - 1) (0 when
+ * hi_d == lo_d), bits interleaved from the most significant down with
+ * dimension 0 first within each group.  Does not synchronise.
+ */
+arborx_status arborx_debug_morton64(const float *points, int64_t n, int32_t dim, const float *bounds, uint64_t *codes,
+                                    void *stream);
+
+/*
+ * Copy the tree's nodes to host memory for invariant checks.  Synchronises.
+ *   child   [host] [n-1][2] int32: >= 0 internal node, < 0 leaf holding value ~child
+ *   lo, hi  [host] [n-1][2][dim] float32 boxes of the two children
+ *   root    [host] index of the root node
+ * For n == 1 the single node holds the leaf and an empty slot (INT32_MIN).
+ */
+arborx_status arborx_debug_tree_nodes(arborx_tree tree, int32_t *child, float *lo, float *hi, int32_t *root);
+
+/* ------------------------------------------------------------------------ */
+/* Profiling: per-phase GPU time measured with events on the launch stream.  */
+/* ------------------------------------------------------------------------ */
+
+/* Enable (1) or disable (0) phase timing for later calls.  [host] */
+arborx_status arborx_profile_enable(int32_t on);
+
+/*
+ * Wait for the recorded phases, then report and reset them, one entry per phase
+ * name: names [host] char[cap][32] (NUL-terminated), ms [host] total
+ * milliseconds, launches [host] number of timed phase instances, *count [host]
+ * entries written (at most cap).
+ */
+arborx_status arborx_profile_collect(char *names, double *ms, int64_t *launches, int32_t cap, int32_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ARBORX355_ARBORX_H */

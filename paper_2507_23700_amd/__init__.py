@@ -1,0 +1,258 @@
+"""MI355X linear-BVH geometric search (the hot path of ArborX 2.0, arXiv 2507.23700).
+
+A thin binding over the C ABI in include/arborx.h: functions carry the C names
+and only marshal arguments (torch tensors in device memory, the current HIP
+stream); every step runs in the library's HIP kernels.  The ``BVH`` class is a
+convenience wrapper over the same calls.
+
+Importing the package does not load the library; the first call does, and it
+raises if ``libarborx355.so`` has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+
+POINTS, BOXES = 0, 1
+COUNT, COUNT_SUMDIST = 0, 1
+
+OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_CAPACITY, E_DEVICE = range(6)
+_NAMES = {1: "E_INVALID", 2: "E_UNSUPPORTED", 3: "E_NOMEM", 4: "E_CAPACITY", 5: "E_DEVICE"}
+
+
+class ArborXError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def _check(st: int) -> None:
+    if st != OK:
+        raise ArborXError(st, _lib.lib().arborx_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def version() -> str:
+    return _lib.lib().arborx_version().decode()
+
+
+def arborx_set_tuning(block=0, order=1, stack=0, schedule=0) -> None:
+    t = _lib.Tuning(block, order, stack, schedule)
+    _check(_lib.lib().arborx_set_tuning(ctypes.byref(t)))
+
+
+def arborx_reset_tuning() -> None:
+    _check(_lib.lib().arborx_set_tuning(None))
+
+
+def arborx_get_tuning() -> dict:
+    t = _lib.Tuning()
+    _check(_lib.lib().arborx_get_tuning(ctypes.byref(t)))
+    return dict(block=t.block, order=t.order, stack=t.stack, schedule=t.schedule)
+
+
+class Tree:
+    """Owns an arborx_tree handle; destroyed with the object."""
+
+    def __init__(self, handle, n, dim, kind, values):
+        self.handle, self.n, self.dim, self.kind = handle, n, dim, kind
+        self._values = values  # keep the build input alive until the build has run
+        self.last_total = 0
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None and _lib._lib is not None:
+            _lib._lib.arborx_bvh_destroy(h)
+        self.handle = None
+
+
+def arborx_bvh_build(values, kind=POINTS, stream=None) -> Tree:
+    """values: float32 [n, dim] points or [n, 2, dim] boxes on the GPU."""
+    torch = _torch()
+    values = _dev(values, torch.float32, "values")
+    if kind == POINTS and values.dim() != 2:
+        raise ValueError("points must be [n, dim]")
+    if kind == BOXES and (values.dim() != 3 or values.shape[1] != 2):
+        raise ValueError("boxes must be [n, 2, dim]")
+    n, dim = values.shape[0], values.shape[-1]
+    h = ctypes.c_void_p()
+    _check(_lib.lib().arborx_bvh_build(_ptr(values), n, dim, kind, _stream(stream), ctypes.byref(h)))
+    return Tree(h, n, dim, kind, values)
+
+
+def arborx_bvh_destroy(tree: Tree) -> None:
+    if tree.handle:
+        _check(_lib.lib().arborx_bvh_destroy(tree.handle))
+        tree.handle = None
+
+
+def arborx_bvh_info(tree: Tree) -> dict:
+    n, dim, kind, height = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    b = (ctypes.c_float * 20)()
+    _check(_lib.lib().arborx_bvh_info(tree.handle, ctypes.byref(n), ctypes.byref(dim), ctypes.byref(kind), b,
+                                      ctypes.byref(height)))
+    d = dim.value
+    return dict(n=n.value, dim=d, kind=kind.value, lo=list(b[:d]), hi=list(b[d:2 * d]), height=height.value,
+                empty=n.value == 0)
+
+
+def _queries(tree, q, boxes):
+    torch = _torch()
+    q = _dev(q, torch.float32, "queries")
+    want = (2, tree.dim) if boxes else (tree.dim,)
+    if tuple(q.shape[1:]) != want:
+        raise ValueError(f"queries must be [m, {', '.join(map(str, want))}]")
+    return q
+
+
+def _csr(fn, tree, q, extra, capacity, stream):
+    torch = _torch()
+    m = q.shape[0]
+    offsets = torch.empty(m + 1, dtype=torch.int64, device=q.device)
+    cap = max(int(capacity if capacity is not None else tree.last_total), 1)
+    indices = torch.empty(cap, dtype=torch.int32, device=q.device)
+    total = ctypes.c_int64()
+    st = fn(tree.handle, _ptr(q), m, *extra, _ptr(offsets), _ptr(indices), cap, ctypes.byref(total), _stream(stream))
+    if st == E_CAPACITY:
+        cap = max(total.value, 1)
+        indices = torch.empty(cap, dtype=torch.int32, device=q.device)
+        st = fn(tree.handle, _ptr(q), m, *extra, _ptr(offsets), _ptr(indices), cap, ctypes.byref(total),
+                _stream(stream))
+    _check(st)
+    tree.last_total = total.value
+    return offsets, indices[:total.value]
+
+
+def arborx_query_spatial(tree: Tree, queries, radius: float, capacity=None, stream=None):
+    """Radius search: (offsets int64[m+1], indices int32[total]), rows ascending."""
+    q = _queries(tree, queries, False)
+    return _csr(lambda h, qp, m, r, *a: _lib.lib().arborx_query_spatial(h, qp, m, r, *a), tree, q,
+                [ctypes.c_float(radius)], capacity, stream)
+
+
+def arborx_query_intersects(tree: Tree, qboxes, capacity=None, stream=None):
+    """Box-overlap search with [m, 2, dim] query boxes: CSR (offsets, indices)."""
+    q = _queries(tree, qboxes, True)
+    return _csr(lambda h, qp, m, *a: _lib.lib().arborx_query_intersects(h, qp, m, *a), tree, q, [], capacity, stream)
+
+
+def arborx_query_knn(tree: Tree, queries, k: int, stream=None):
+    """k nearest: (dist2 float32[m, k], indices int32[m, k]) in (d2, index) order, padded (+inf, -1)."""
+    torch = _torch()
+    q = _queries(tree, queries, False)
+    m = q.shape[0]
+    d2 = torch.empty((m, k), dtype=torch.float32, device=q.device)
+    idx = torch.empty((m, k), dtype=torch.int32, device=q.device)
+    _check(_lib.lib().arborx_query_knn(tree.handle, _ptr(q), m, k, _ptr(d2), _ptr(idx), _stream(stream)))
+    return d2, idx
+
+
+def arborx_query_spatial_reduce(tree: Tree, queries, radius: float, op=COUNT_SUMDIST, scale_bits=32, stream=None):
+    """Fused radius reduce: counts int32[m] and (COUNT_SUMDIST) sum_fixed int64[m]."""
+    torch = _torch()
+    q = _queries(tree, queries, False)
+    m = q.shape[0]
+    counts = torch.empty(m, dtype=torch.int32, device=q.device)
+    sums = torch.empty(m, dtype=torch.int64, device=q.device) if op == COUNT_SUMDIST else None
+    _check(_lib.lib().arborx_query_spatial_reduce(tree.handle, _ptr(q), m, ctypes.c_float(radius), op, _ptr(counts),
+                                                  _ptr(sums), scale_bits, _stream(stream)))
+    return counts, sums
+
+
+def arborx_debug_radix_sort(keys, values, begin_bit=0, end_bit=None, stream=None):
+    """In-place stable sort of (keys int64/int32 viewed as unsigned, values int32) by key bits."""
+    torch = _torch()
+    if keys.dtype not in (torch.int64, torch.int32):
+        raise TypeError("keys must be int64 or int32 (bit patterns of unsigned keys)")
+    _dev(keys, keys.dtype, "keys")
+    _dev(values, torch.int32, "values")
+    bits = 64 if keys.dtype == torch.int64 else 32
+    end_bit = bits if end_bit is None else end_bit
+    _check(_lib.lib().arborx_debug_radix_sort(_ptr(keys), _ptr(values), keys.numel(), bits, begin_bit, end_bit,
+                                              _stream(stream)))
+
+
+def arborx_debug_morton64(points, bounds, stream=None):
+    """Morton-64 codes (as int64 bit patterns) of [n, dim] points under bounds [2, dim]."""
+    torch = _torch()
+    points = _dev(points, torch.float32, "points")
+    bounds = _dev(bounds, torch.float32, "bounds")
+    codes = torch.empty(points.shape[0], dtype=torch.int64, device=points.device)
+    _check(_lib.lib().arborx_debug_morton64(_ptr(points), points.shape[0], points.shape[1], _ptr(bounds),
+                                            _ptr(codes), _stream(stream)))
+    return codes
+
+
+def arborx_debug_tree_nodes(tree: Tree):
+    """Host copies (child [nn,2] int32, lo [nn,2,dim], hi [nn,2,dim], root) of the tree's nodes."""
+    import numpy as np
+    nn = tree.n - 1 if tree.n > 1 else tree.n
+    child = np.zeros((max(nn, 1), 2), dtype=np.int32)
+    lo = np.zeros((max(nn, 1), 2, tree.dim), dtype=np.float32)
+    hi = np.zeros_like(lo)
+    root = ctypes.c_int32()
+    _check(_lib.lib().arborx_debug_tree_nodes(tree.handle, child.ctypes.data_as(ctypes.c_void_p),
+                                              lo.ctypes.data_as(ctypes.c_void_p), hi.ctypes.data_as(ctypes.c_void_p),
+                                              ctypes.byref(root)))
+    return child[:nn], lo[:nn], hi[:nn], root.value
+
+
+class BVH:
+    """Convenience wrapper: BVH(points) then .spatial / .intersects / .knn / .count / .count_sumdist."""
+
+    def __init__(self, values, kind=POINTS, stream=None):
+        self.tree = arborx_bvh_build(values, kind, stream)
+
+    def info(self):
+        return arborx_bvh_info(self.tree)
+
+    def size(self):
+        return self.tree.n
+
+    def empty(self):
+        return self.tree.n == 0
+
+    def bounds(self):
+        i = self.info()
+        return i["lo"], i["hi"]
+
+    def spatial(self, queries, radius, **kw):
+        return arborx_query_spatial(self.tree, queries, radius, **kw)
+
+    def intersects(self, qboxes, **kw):
+        return arborx_query_intersects(self.tree, qboxes, **kw)
+
+    def knn(self, queries, k, **kw):
+        return arborx_query_knn(self.tree, queries, k, **kw)
+
+    def count(self, queries, radius, **kw):
+        return arborx_query_spatial_reduce(self.tree, queries, radius, COUNT, **kw)[0]
+
+    def count_sumdist(self, queries, radius, scale_bits=32, **kw):
+        return arborx_query_spatial_reduce(self.tree, queries, radius, COUNT_SUMDIST, scale_bits, **kw)

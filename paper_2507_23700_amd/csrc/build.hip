@@ -1,0 +1,357 @@
+// BVH construction (Section 2.6 of the ArborX 2.0 paper: 64-bit Morton codes,
+// a sort, and Apetrei's bottom-up hierarchy construction).
+//
+//   1. scene bounds      : min/max per dimension over all values;
+//   2. Morton-64         : quantise each value's centre to floor(63/D) bits per
+//                          dimension and interleave;
+//   3. radix sort        : stable sort of (code, value index);
+//   4. hierarchy + refit : one thread per leaf climbs the tree.  Internal node
+//                          p separates sorted leaves p and p+1.  A subtree over
+//                          leaves [l, r] becomes the left child of node r or the
+//                          right child of node l-1, whichever boundary is the
+//                          smaller split key (the XOR of neighbouring codes,
+//                          ties between equal codes broken by position).  Each
+//                          thread writes its box into its slot of the parent
+//                          and swaps an arrival word into the parent's flag;
+//                          the first to arrive stops, the second merges the
+//                          sibling's box and continues upwards.  Writing a
+//                          leaf's box straight into its parent slot is the
+//                          "leaf gather": leaves need no array of their own.
+#include <cstddef>
+
+#include "device_util.hpp"
+#include "geometry.hpp"
+#include "internal.hpp"
+#include "profile.hpp"
+
+namespace ax {
+namespace {
+
+constexpr int kBuildBlock = 256;
+
+template <int D>
+__global__ __launch_bounds__(kBuildBlock) void bounds_partial(const float *__restrict__ values, int64_t n, int kind,
+                                                              float *__restrict__ partial)
+{
+    __shared__ float s_lo[kBuildBlock / kWave][D];
+    __shared__ float s_hi[kBuildBlock / kWave][D];
+    float lo[D], hi[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = INFINITY;
+        hi[d] = -INFINITY;
+    }
+    const int stride_v = kind == ARBORX_BOXES ? 2 * D : D;
+    const int hoff = kind == ARBORX_BOXES ? D : 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBuildBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBuildBlock) {
+        const float *v = values + i * stride_v;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            lo[d] = fminf(lo[d], v[d]);
+            hi[d] = fmaxf(hi[d], v[hoff + d]);
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            lo[d] = fminf(lo[d], __shfl_xor(lo[d], o, kWave));
+            hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], o, kWave));
+        }
+    }
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            s_lo[wave_id()][d] = lo[d];
+            s_hi[wave_id()][d] = hi[d];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < D) {
+        const int d = threadIdx.x;
+        float a = INFINITY, b = -INFINITY;
+        for (int w = 0; w < kBuildBlock / kWave; ++w) {
+            a = fminf(a, s_lo[w][d]);
+            b = fmaxf(b, s_hi[w][d]);
+        }
+        partial[(int64_t)blockIdx.x * 2 * D + d] = a;
+        partial[(int64_t)blockIdx.x * 2 * D + D + d] = b;
+    }
+}
+
+template <int D>
+__global__ void bounds_final(const float *__restrict__ partial, int blocks, int64_t n, TreeHeader *hdr)
+{
+    const int d = threadIdx.x;
+    if (d < D) {
+        float a = INFINITY, b = -INFINITY;
+        for (int k = 0; k < blocks; ++k) {
+            a = fminf(a, partial[(int64_t)k * 2 * D + d]);
+            b = fmaxf(b, partial[(int64_t)k * 2 * D + D + d]);
+        }
+        hdr->lo[d] = a;
+        hdr->hi[d] = b;
+    }
+    if (d == 0) {
+        hdr->n = (int32_t)n;
+        hdr->root = n > 0 ? 0 : -1;
+        hdr->height = 0;
+    }
+}
+
+// Codes of value centres (points: the point; boxes: the box centre).
+template <int D>
+__global__ __launch_bounds__(kBuildBlock) void morton_kernel(const float *__restrict__ values, int64_t n, int kind,
+                                                             const float *__restrict__ blo,
+                                                             const float *__restrict__ bhi,
+                                                             uint64_t *__restrict__ codes, uint32_t *__restrict__ ids)
+{
+    constexpr int bits = 63 / D;
+    float lo[D], inv[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = blo[d];
+        const float ext = bhi[d] - blo[d];
+        inv[d] = ext > 0.0f ? 1.0f / ext : 0.0f;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * kBuildBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBuildBlock) {
+        uint32_t c[D];
+        if (kind == ARBORX_BOXES) {
+            const float *v = values + i * 2 * D;
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                c[d] = quantise(v[d] + 0.5f * (v[D + d] - v[d]), lo[d], inv[d], bits);
+        } else {
+            const float *v = values + i * D;
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                c[d] = quantise(v[d], lo[d], inv[d], bits);
+        }
+        codes[i] = interleave<D>(c, bits);
+        if (ids)
+            ids[i] = (uint32_t)i;
+    }
+}
+
+// Split key between sorted leaves i and i+1: code differences rank above
+// position differences (equal codes), so the order is total once ties are
+// broken by node index.
+__device__ __forceinline__ uint64_t split_key(const uint64_t *__restrict__ codes, int i)
+{
+    const uint64_t x = codes[i] ^ codes[i + 1];
+    return x ? (x | (1ull << 63)) : (uint64_t)(uint32_t)(i ^ (i + 1));
+}
+
+template <int D>
+__global__ __launch_bounds__(kBuildBlock) void hierarchy_kernel(const uint64_t *__restrict__ codes,
+                                                                const uint32_t *__restrict__ ids,
+                                                                const float *__restrict__ values, int kind, int n,
+                                                                Node<D> *nodes, unsigned long long *flags,
+                                                                TreeHeader *hdr)
+{
+    const int i = blockIdx.x * kBuildBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint32_t id = ids[i];
+    if (id >= (uint32_t)n)
+        return;
+    float lo[D], hi[D];
+    if (kind == ARBORX_BOXES) {
+        const float *v = values + (int64_t)id * 2 * D;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            lo[d] = v[d];
+            hi[d] = v[D + d];
+        }
+    } else {
+        const float *v = values + (int64_t)id * D;
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            lo[d] = hi[d] = v[d];
+    }
+    int32_t ref = ~(int32_t)id;
+    if (n == 1) {
+        Node<D> &nd = nodes[0];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            nd.lo[0][d] = lo[d];
+            nd.hi[0][d] = hi[d];
+            nd.lo[1][d] = INFINITY;
+            nd.hi[1][d] = -INFINITY;
+        }
+        nd.child[0] = ref;
+        nd.child[1] = kEmptyRef;
+        nd.range_l = 0;
+        nd.range_r = 0;
+        hdr->root = 0;
+        hdr->height = 1;
+        return;
+    }
+    int l = i, r = i, h = 0;
+    while (true) {
+        int p, side;
+        if (l == 0 || (r != n - 1 && split_key(codes, r) < split_key(codes, l - 1))) {
+            p = r;
+            side = 0;
+        } else {
+            p = l - 1;
+            side = 1;
+        }
+        Node<D> *np = nodes + p;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            np->lo[side][d] = lo[d];
+            np->hi[side][d] = hi[d];
+        }
+        np->child[side] = ref;
+        // arrival word: (height + 1) << 32 | the outer bound of this subtree's range
+        const unsigned long long mine =
+            ((unsigned long long)(uint32_t)(h + 1) << 32) | (uint32_t)(side == 0 ? l : r);
+        const unsigned long long other =
+            __hip_atomic_exchange(flags + p, mine, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (other == 0)
+            return;  // first arrival: the sibling's thread finishes this node
+        const int oh = (int)(other >> 32) - 1;
+        const int ob = (int)(uint32_t)other;
+        if (side == 0)
+            r = ob;
+        else
+            l = ob;
+        h = (h > oh ? h : oh) + 1;
+        const int os = 1 - side;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            lo[d] = fminf(lo[d], np->lo[os][d]);
+            hi[d] = fmaxf(hi[d], np->hi[os][d]);
+        }
+        np->range_l = l;
+        np->range_r = r;
+        ref = p;
+        if (l == 0 && r == n - 1) {
+            hdr->root = p;
+            hdr->height = h;
+            return;
+        }
+    }
+}
+
+__global__ void empty_header(TreeHeader *hdr, int dim)
+{
+    hdr->root = -1;
+    hdr->height = 0;
+    hdr->n = 0;
+    for (int d = 0; d < kMaxDim; ++d) {
+        hdr->lo[d] = INFINITY;
+        hdr->hi[d] = -INFINITY;
+    }
+    (void)dim;
+}
+
+template <int D>
+arborx_status build_impl(const float *values, int64_t n, int kind, TreeDev &t, hipStream_t s)
+{
+    AX_HIP(hipGetLastError());  // clear stale errors from earlier user work
+    arborx_status st = dalloc((void **)&t.hdr, sizeof(TreeHeader), s);
+    if (st != ARBORX_OK)
+        return st;
+    t.n = n;
+    t.dim = D;
+    t.kind = kind;
+    if (n == 0) {
+        empty_header<<<1, 1, 0, s>>>(t.hdr, D);
+        AX_HIP(hipGetLastError());
+        return ARBORX_OK;
+    }
+    const int64_t nn = n > 1 ? n - 1 : 1;
+    st = dalloc(&t.nodes, (size_t)nn * sizeof(Node<D>), s);
+    if (st != ARBORX_OK)
+        return st;
+
+    Temps tmp(s);
+    const int pblocks = (int)grid_for(n, kBuildBlock, 1024);
+    float *partial;
+    uint64_t *codes, *codes2;
+    uint32_t *ids, *ids2;
+    unsigned long long *flags;
+    uint8_t *ws;
+    if ((st = tmp.get(&partial, (size_t)pblocks * 2 * D)) != ARBORX_OK || (st = tmp.get(&codes, n)) != ARBORX_OK ||
+        (st = tmp.get(&codes2, n)) != ARBORX_OK || (st = tmp.get(&ids, n)) != ARBORX_OK ||
+        (st = tmp.get(&ids2, n)) != ARBORX_OK || (st = tmp.get(&flags, nn)) != ARBORX_OK ||
+        (st = tmp.get(&ws, radix_workspace_bytes(n))) != ARBORX_OK)
+        return st;
+
+    {
+        ProfScope ps("build_bounds", s);
+        bounds_partial<D><<<pblocks, kBuildBlock, 0, s>>>(values, n, kind, partial);
+        bounds_final<D><<<1, 64, 0, s>>>(partial, pblocks, n, t.hdr);
+    }
+    const float *blo = reinterpret_cast<const float *>(reinterpret_cast<const char *>(t.hdr) + offsetof(TreeHeader, lo));
+    const float *bhi = reinterpret_cast<const float *>(reinterpret_cast<const char *>(t.hdr) + offsetof(TreeHeader, hi));
+    {
+        ProfScope ps("build_morton", s);
+        morton_kernel<D><<<grid_for(n, kBuildBlock, 65536), kBuildBlock, 0, s>>>(values, n, kind, blo, bhi, codes,
+                                                                                ids);
+    }
+    bool alt = false;
+    {
+        ProfScope ps("build_sort", s);
+        AX_HIP(radix_sort_pairs<uint64_t>(codes, ids, codes2, ids2, n, 0, (63 / D) * D, ws, s, &alt));
+    }
+    if (alt) {
+        codes = codes2;
+        ids = ids2;
+    }
+    fill_kernel<unsigned long long><<<grid_for(nn, 256, 65536), 256, 0, s>>>(flags, nn, 0ull);
+    {
+        ProfScope ps("build_hierarchy", s);
+        hierarchy_kernel<D><<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(codes, ids, values, kind, (int)n,
+                                                                             static_cast<Node<D> *>(t.nodes), flags,
+                                                                             t.hdr);
+    }
+    AX_HIP(hipGetLastError());
+    return ARBORX_OK;
+}
+
+template <int D>
+hipError_t morton_impl(const float *pts, int64_t n, const float *bounds, uint64_t *codes, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    morton_kernel<D><<<grid_for(n, kBuildBlock, 65536), kBuildBlock, 0, s>>>(pts, n, ARBORX_POINTS, bounds,
+                                                                            bounds + D, codes, nullptr);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t node_bytes(int dim)
+{
+    switch (dim) {
+    case 2: return sizeof(Node<2>);
+    case 3: return sizeof(Node<3>);
+    case 6: return sizeof(Node<6>);
+    default: return 0;
+    }
+}
+
+arborx_status build_tree(const float *values, int64_t n, int dim, int kind, TreeDev &t, hipStream_t s)
+{
+    switch (dim) {
+    case 2: return build_impl<2>(values, n, kind, t, s);
+    case 3: return build_impl<3>(values, n, kind, t, s);
+    case 6: return build_impl<6>(values, n, kind, t, s);
+    default: return fail(ARBORX_E_UNSUPPORTED, "dimension not compiled in");
+    }
+}
+
+hipError_t morton64_points(const float *pts, int64_t n, int dim, const float *bounds, uint64_t *codes, hipStream_t s)
+{
+    switch (dim) {
+    case 2: return morton_impl<2>(pts, n, bounds, codes, s);
+    case 3: return morton_impl<3>(pts, n, bounds, codes, s);
+    case 6: return morton_impl<6>(pts, n, bounds, codes, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace ax

@@ -1,0 +1,459 @@
+// extern "C" entry points declared in include/arborx.h: argument validation,
+// stream handling, temporaries, and dispatch to the kernels.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "device_util.hpp"
+#include "internal.hpp"
+#include "profile.hpp"
+
+struct arborx_tree_s {
+    ax::TreeDev dev;
+    hipEvent_t ready = nullptr;
+};
+
+namespace ax {
+
+static thread_local std::string g_error;
+static Tuning g_tuning;
+static std::mutex g_pool_mutex;
+static bool g_pool_ready[64] = {};
+
+const Tuning &tuning() { return g_tuning; }
+
+void set_error(const std::string &msg) { g_error = msg; }
+
+arborx_status fail(arborx_status st, const std::string &msg)
+{
+    set_error(msg);
+    return st;
+}
+
+arborx_status hip_fail(hipError_t e, const char *what)
+{
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? ARBORX_E_NOMEM : ARBORX_E_DEVICE;
+}
+
+// Keep freed stream-ordered memory in the device pool for reuse.
+static void ensure_pool()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return;
+    std::lock_guard<std::mutex> lock(g_pool_mutex);
+    if (g_pool_ready[dev])
+        return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t threshold = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold);
+    }
+    g_pool_ready[dev] = true;
+}
+
+arborx_status dalloc(void **p, size_t bytes, hipStream_t s)
+{
+    ensure_pool();
+    *p = nullptr;
+    hipError_t e = hipMallocAsync(p, bytes ? bytes : 1, s);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(ARBORX_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    return ARBORX_OK;
+}
+
+void dfree(void *p, hipStream_t s)
+{
+    if (p)
+        (void)hipFreeAsync(p, s);
+}
+
+static arborx_status check_device()
+{
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return fail(ARBORX_E_DEVICE, "no usable GPU");
+    }
+    return ARBORX_OK;
+}
+
+static bool dim_valid(int dim) { return dim >= 1 && dim <= kMaxDim; }
+static bool dim_compiled(int dim) { return dim == 2 || dim == 3 || dim == 6; }
+
+static arborx_status check_tree(arborx_tree t)
+{
+    if (!t)
+        return fail(ARBORX_E_INVALID, "tree is NULL");
+    return ARBORX_OK;
+}
+
+static void release_tree(arborx_tree t)
+{
+    if (!t)
+        return;
+    if (t->ready)
+        (void)hipEventSynchronize(t->ready);
+    (void)hipDeviceSynchronize();
+    dfree(t->dev.nodes, nullptr);
+    dfree(t->dev.hdr, nullptr);
+    (void)hipStreamSynchronize(nullptr);
+    if (t->ready)
+        (void)hipEventDestroy(t->ready);
+    delete t;
+}
+
+static arborx_status wait_tree(arborx_tree t, hipStream_t s)
+{
+    AX_HIP(hipStreamWaitEvent(s, t->ready, 0));
+    return ARBORX_OK;
+}
+
+}  // namespace ax
+
+using namespace ax;
+
+extern "C" {
+
+const char *arborx_version(void) { return "arborx355 0.1"; }
+
+const char *arborx_last_error(void) { return g_error.c_str(); }
+
+arborx_status arborx_set_tuning(const arborx_tuning *t)
+{
+    if (!t) {
+        g_tuning = Tuning();
+        return ARBORX_OK;
+    }
+    Tuning n = g_tuning;
+    if (t->block) {
+        if (t->block != 64 && t->block != 128 && t->block != 256)
+            return fail(ARBORX_E_INVALID, "block must be 64, 128 or 256");
+        n.block = t->block;
+    }
+    if (t->order != 0 && t->order != 1)
+        return fail(ARBORX_E_INVALID, "order must be 0 or 1");
+    n.order = t->order;
+    if (t->stack) {
+        if (t->stack < 1 || t->stack > 64 || (t->stack & (t->stack - 1)))
+            return fail(ARBORX_E_INVALID, "stack must be a power of two in 1..64");
+        n.stack = t->stack;
+    }
+    if (t->schedule != 0)
+        return fail(ARBORX_E_UNSUPPORTED, "only the thread-per-query schedule is available");
+    n.schedule = t->schedule;
+    g_tuning = n;
+    return ARBORX_OK;
+}
+
+arborx_status arborx_get_tuning(arborx_tuning *t)
+{
+    if (!t)
+        return fail(ARBORX_E_INVALID, "tuning is NULL");
+    t->block = g_tuning.block;
+    t->order = g_tuning.order;
+    t->stack = g_tuning.stack;
+    t->schedule = g_tuning.schedule;
+    return ARBORX_OK;
+}
+
+arborx_status arborx_bvh_build(const float *values, int64_t n, int32_t dim, int32_t kind, void *stream,
+                               arborx_tree *out)
+{
+    if (!out)
+        return fail(ARBORX_E_INVALID, "out is NULL");
+    if (n < 0 || n >= INT32_MAX)
+        return fail(ARBORX_E_INVALID, "n must be in [0, 2^31-1)");
+    if (!dim_valid(dim))
+        return fail(ARBORX_E_INVALID, "dim must be in 1..10");
+    if (kind != ARBORX_POINTS && kind != ARBORX_BOXES)
+        return fail(ARBORX_E_INVALID, "kind must be ARBORX_POINTS or ARBORX_BOXES");
+    if (n > 0 && !values)
+        return fail(ARBORX_E_INVALID, "values is NULL");
+    if (!dim_compiled(dim))
+        return fail(ARBORX_E_UNSUPPORTED, "dimension not compiled in (2, 3 and 6 are)");
+    arborx_status st = check_device();
+    if (st != ARBORX_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    arborx_tree t = new arborx_tree_s();
+    st = build_tree(values, n, dim, kind, t->dev, s);
+    if (st == ARBORX_OK) {
+        hipError_t e = hipEventCreateWithFlags(&t->ready, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventRecord(t->ready, s);
+        if (e != hipSuccess)
+            st = hip_fail(e, "hipEventRecord");
+    }
+    if (st != ARBORX_OK) {
+        std::string msg = g_error;
+        (void)hipStreamSynchronize(s);
+        release_tree(t);
+        set_error(msg);
+        return st;
+    }
+    *out = t;
+    return ARBORX_OK;
+}
+
+arborx_status arborx_bvh_destroy(arborx_tree t)
+{
+    release_tree(t);
+    return ARBORX_OK;
+}
+
+arborx_status arborx_bvh_info(arborx_tree t, int64_t *n, int32_t *dim, int32_t *kind, float *bounds, int32_t *height)
+{
+    arborx_status st = check_tree(t);
+    if (st != ARBORX_OK)
+        return st;
+    AX_HIP(hipEventSynchronize(t->ready));
+    TreeHeader h;
+    AX_HIP(hipMemcpy(&h, t->dev.hdr, sizeof(h), hipMemcpyDeviceToHost));
+    if (n)
+        *n = t->dev.n;
+    if (dim)
+        *dim = t->dev.dim;
+    if (kind)
+        *kind = t->dev.kind;
+    if (bounds)
+        for (int d = 0; d < t->dev.dim; ++d) {
+            bounds[d] = h.lo[d];
+            bounds[t->dev.dim + d] = h.hi[d];
+        }
+    if (height)
+        *height = h.height;
+    return ARBORX_OK;
+}
+
+static arborx_status csr_query(arborx_tree t, Pred pred, const float *queries, int64_t m, float radius,
+                               int64_t *offsets, int32_t *indices, int64_t capacity, int64_t *total, void *stream)
+{
+    arborx_status st = check_tree(t);
+    if (st != ARBORX_OK)
+        return st;
+    if (m < 0)
+        return fail(ARBORX_E_INVALID, "m must be >= 0");
+    if (m > 0 && !queries)
+        return fail(ARBORX_E_INVALID, "queries is NULL");
+    if (!offsets)
+        return fail(ARBORX_E_INVALID, "offsets is NULL");
+    if (!total)
+        return fail(ARBORX_E_INVALID, "total is NULL");
+    if (capacity < 0)
+        return fail(ARBORX_E_INVALID, "capacity must be >= 0");
+    if (pred == Pred::Sphere && (std::isnan(radius) || radius < 0.0f))
+        return fail(ARBORX_E_INVALID, "radius must be >= 0 and not NaN");
+    if ((st = check_device()) != ARBORX_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = wait_tree(t, s)) != ARBORX_OK)
+        return st;
+    Temps tmp(s);
+    QueryHeader *qh;
+    int32_t *counts;
+    uint8_t *sws;
+    if ((st = tmp.get(&qh, 1)) != ARBORX_OK || (st = tmp.get(&counts, m > 0 ? m : 1)) != ARBORX_OK ||
+        (st = tmp.get(&sws, scan_workspace_bytes(m))) != ARBORX_OK)
+        return st;
+    fill_kernel<unsigned long long><<<1, 64, 0, s>>>(reinterpret_cast<unsigned long long *>(qh),
+                                                     sizeof(QueryHeader) / 8, 0ull);
+    AX_HIP(hipGetLastError());
+    uint32_t *perm = nullptr;
+    if ((st = query_order(t->dev, queries, m, pred, &perm, tmp, s)) != ARBORX_OK)
+        return st;
+    if ((st = spatial_count(t->dev, pred, queries, m, radius, perm, counts, qh, s)) != ARBORX_OK)
+        return st;
+    {
+        ProfScope ps("scan", s);
+        AX_HIP(csr_offsets(counts, m, offsets, reinterpret_cast<int64_t *>(&qh->total), sws, s));
+    }
+    QueryHeader h;
+    AX_HIP(hipMemcpyAsync(&h, qh, sizeof(h), hipMemcpyDeviceToHost, s));
+    AX_HIP(hipStreamSynchronize(s));
+    *total = (int64_t)h.total;
+    if (!indices || capacity < (int64_t)h.total)
+        return fail(ARBORX_E_CAPACITY, "indices capacity " + std::to_string(capacity) + " < total " +
+                                           std::to_string((long long)h.total));
+    if (h.total == 0)
+        return ARBORX_OK;
+    int64_t *big_list, *huge_list;
+    if ((st = tmp.get(&big_list, h.big_rows + 1)) != ARBORX_OK || (st = tmp.get(&huge_list, h.huge_rows + 1)) != ARBORX_OK)
+        return st;
+    if ((st = spatial_fill(t->dev, pred, queries, m, radius, perm, offsets, indices, qh, big_list, (int64_t)h.big_rows,
+                           huge_list, (int64_t)h.huge_rows, s)) !=
+        ARBORX_OK)
+        return st;
+    if ((st = sort_big_rows(offsets, indices, qh, big_list, (int64_t)h.big_rows, s)) != ARBORX_OK)
+        return st;
+    return sort_huge_rows(t->dev.n, offsets, indices, huge_list, (int64_t)h.huge_rows, tmp, s);
+}
+
+arborx_status arborx_query_spatial(arborx_tree t, const float *queries, int64_t m, float radius, int64_t *offsets,
+                                   int32_t *indices, int64_t capacity, int64_t *total, void *stream)
+{
+    return csr_query(t, Pred::Sphere, queries, m, radius, offsets, indices, capacity, total, stream);
+}
+
+arborx_status arborx_query_intersects(arborx_tree t, const float *qboxes, int64_t m, int64_t *offsets,
+                                      int32_t *indices, int64_t capacity, int64_t *total, void *stream)
+{
+    return csr_query(t, Pred::Box, qboxes, m, 0.0f, offsets, indices, capacity, total, stream);
+}
+
+arborx_status arborx_query_knn(arborx_tree t, const float *queries, int64_t m, int32_t k, float *dist2,
+                               int32_t *indices, void *stream)
+{
+    arborx_status st = check_tree(t);
+    if (st != ARBORX_OK)
+        return st;
+    if (m < 0)
+        return fail(ARBORX_E_INVALID, "m must be >= 0");
+    if (k < 1 || k > 64)
+        return fail(ARBORX_E_INVALID, "k must be in 1..64");
+    if (m > 0 && (!queries || !dist2 || !indices))
+        return fail(ARBORX_E_INVALID, "queries, dist2 and indices must not be NULL");
+    if ((st = check_device()) != ARBORX_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = wait_tree(t, s)) != ARBORX_OK)
+        return st;
+    Temps tmp(s);
+    uint32_t *perm = nullptr;
+    if ((st = query_order(t->dev, queries, m, Pred::Sphere, &perm, tmp, s)) != ARBORX_OK)
+        return st;
+    return knn_query(t->dev, queries, m, k, perm, dist2, indices, s);
+}
+
+arborx_status arborx_query_spatial_reduce(arborx_tree t, const float *queries, int64_t m, float radius, int32_t op,
+                                          int32_t *counts, int64_t *sum_fixed, int32_t scale_bits, void *stream)
+{
+    arborx_status st = check_tree(t);
+    if (st != ARBORX_OK)
+        return st;
+    if (m < 0)
+        return fail(ARBORX_E_INVALID, "m must be >= 0");
+    if (op != ARBORX_COUNT && op != ARBORX_COUNT_SUMDIST)
+        return fail(ARBORX_E_INVALID, "unknown reducer");
+    if (std::isnan(radius) || radius < 0.0f)
+        return fail(ARBORX_E_INVALID, "radius must be >= 0 and not NaN");
+    if (op == ARBORX_COUNT_SUMDIST && (scale_bits < 0 || scale_bits > 40))
+        return fail(ARBORX_E_INVALID, "scale_bits must be in 0..40");
+    if (m > 0 && (!queries || !counts || (op == ARBORX_COUNT_SUMDIST && !sum_fixed)))
+        return fail(ARBORX_E_INVALID, "queries, counts (and sum_fixed for COUNT_SUMDIST) must not be NULL");
+    if ((st = check_device()) != ARBORX_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = wait_tree(t, s)) != ARBORX_OK)
+        return st;
+    Temps tmp(s);
+    uint32_t *perm = nullptr;
+    if ((st = query_order(t->dev, queries, m, Pred::Sphere, &perm, tmp, s)) != ARBORX_OK)
+        return st;
+    return spatial_reduce(t->dev, queries, m, radius, op, scale_bits, perm, counts, sum_fixed, s);
+}
+
+arborx_status arborx_debug_radix_sort(void *keys, uint32_t *values, int64_t n, int32_t key_bits, int32_t begin_bit,
+                                      int32_t end_bit, void *stream)
+{
+    if (n < 0 || n > (int64_t)UINT32_MAX)
+        return fail(ARBORX_E_INVALID, "n out of range");
+    if (key_bits != 32 && key_bits != 64)
+        return fail(ARBORX_E_INVALID, "key_bits must be 32 or 64");
+    if (begin_bit < 0 || end_bit > key_bits || begin_bit > end_bit || end_bit - begin_bit > 64)
+        return fail(ARBORX_E_INVALID, "bad bit range");
+    if (n > 0 && (!keys || !values))
+        return fail(ARBORX_E_INVALID, "keys and values must not be NULL");
+    arborx_status st = check_device();
+    if (st != ARBORX_OK)
+        return st;
+    if (n <= 1)
+        return ARBORX_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Temps tmp(s);
+    uint32_t *v2;
+    uint8_t *ws;
+    bool alt = false;
+    if ((st = tmp.get(&v2, n)) != ARBORX_OK || (st = tmp.get(&ws, radix_workspace_bytes(n))) != ARBORX_OK)
+        return st;
+    if (key_bits == 64) {
+        uint64_t *k2;
+        if ((st = tmp.get(&k2, n)) != ARBORX_OK)
+            return st;
+        AX_HIP(radix_sort_pairs<uint64_t>(static_cast<uint64_t *>(keys), values, k2, v2, n, begin_bit, end_bit, ws, s,
+                                          &alt));
+        if (alt)
+            AX_HIP(hipMemcpyAsync(keys, k2, n * 8, hipMemcpyDeviceToDevice, s));
+    } else {
+        uint32_t *k2;
+        if ((st = tmp.get(&k2, n)) != ARBORX_OK)
+            return st;
+        AX_HIP(radix_sort_pairs<uint32_t>(static_cast<uint32_t *>(keys), values, k2, v2, n, begin_bit, end_bit, ws, s,
+                                          &alt));
+        if (alt)
+            AX_HIP(hipMemcpyAsync(keys, k2, n * 4, hipMemcpyDeviceToDevice, s));
+    }
+    if (alt)
+        AX_HIP(hipMemcpyAsync(values, v2, n * 4, hipMemcpyDeviceToDevice, s));
+    return ARBORX_OK;
+}
+
+arborx_status arborx_debug_morton64(const float *points, int64_t n, int32_t dim, const float *bounds, uint64_t *codes,
+                                    void *stream)
+{
+    if (n < 0)
+        return fail(ARBORX_E_INVALID, "n must be >= 0");
+    if (!dim_valid(dim))
+        return fail(ARBORX_E_INVALID, "dim must be in 1..10");
+    if (!dim_compiled(dim))
+        return fail(ARBORX_E_UNSUPPORTED, "dimension not compiled in");
+    if (n > 0 && (!points || !bounds || !codes))
+        return fail(ARBORX_E_INVALID, "NULL pointer");
+    arborx_status st = check_device();
+    if (st != ARBORX_OK)
+        return st;
+    AX_HIP(morton64_points(points, n, dim, bounds, codes, static_cast<hipStream_t>(stream)));
+    return ARBORX_OK;
+}
+
+arborx_status arborx_debug_tree_nodes(arborx_tree t, int32_t *child, float *lo, float *hi, int32_t *root)
+{
+    arborx_status st = check_tree(t);
+    if (st != ARBORX_OK)
+        return st;
+    if (!child || !lo || !hi || !root)
+        return fail(ARBORX_E_INVALID, "NULL pointer");
+    AX_HIP(hipEventSynchronize(t->ready));
+    TreeHeader h;
+    AX_HIP(hipMemcpy(&h, t->dev.hdr, sizeof(h), hipMemcpyDeviceToHost));
+    *root = h.root;
+    const int64_t nn = t->dev.n > 1 ? t->dev.n - 1 : (t->dev.n == 1 ? 1 : 0);
+    if (nn == 0)
+        return ARBORX_OK;
+    const int D = t->dev.dim;
+    const size_t nb = node_bytes(D);
+    std::string buf(nn * nb, '\0');
+    AX_HIP(hipMemcpy(&buf[0], t->dev.nodes, nn * nb, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < nn; ++i) {
+        const char *p = buf.data() + i * nb;
+        const float *flo = reinterpret_cast<const float *>(p);
+        const float *fhi = flo + 2 * D;
+        const int32_t *ch = reinterpret_cast<const int32_t *>(fhi + 2 * D);
+        for (int s2 = 0; s2 < 2; ++s2) {
+            child[i * 2 + s2] = ch[s2];
+            for (int d = 0; d < D; ++d) {
+                lo[(i * 2 + s2) * D + d] = flo[s2 * D + d];
+                hi[(i * 2 + s2) * D + d] = fhi[s2 * D + d];
+            }
+        }
+    }
+    return ARBORX_OK;
+}
+
+}  // extern "C"

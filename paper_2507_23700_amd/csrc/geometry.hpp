@@ -1,0 +1,111 @@
+// Device-side geometry: node layout, squared distances, overlap, Morton codes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ax {
+
+// Child reference stored in a node: >= 0 is an internal node index, < 0 is a
+// leaf holding value ~ref.  kEmptyRef marks the unused slot of a one-value tree.
+constexpr int32_t kEmptyRef = INT32_MIN;
+
+// Internal node of the binary hierarchy.  It stores the bounding boxes of its
+// two children, so one 16*D+16 byte fetch decides both children (64 B in 3D).
+// A leaf needs no storage of its own: its box is the value's box (a point is
+// the degenerate box [p, p]) held in the parent slot, and its reference is the
+// value's input index.
+template <int D>
+struct alignas(16) Node {
+    float lo[2][D];
+    float hi[2][D];
+    int32_t child[2];
+    int32_t range_l;  // leaf range [range_l, range_r] in sorted order
+    int32_t range_r;
+};
+static_assert(sizeof(Node<3>) == 64, "3D node is 64 bytes");
+static_assert(sizeof(Node<6>) == 112, "6D node is 112 bytes");
+
+template <int D>
+__device__ __forceinline__ void load_node(const Node<D> *__restrict__ nodes, int32_t i, Node<D> &out)
+{
+    const float4 *src = reinterpret_cast<const float4 *>(nodes + i);
+    float4 *dst = reinterpret_cast<float4 *>(&out);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(Node<D>) / 16); ++k)
+        dst[k] = src[k];
+}
+
+// Squared distance from point q to the closed box [lo, hi]: per dimension the
+// gap to the nearer face (0 inside), each square and each sum rounded once,
+// dimensions summed from 0 upwards.  For a degenerate box [p, p] it equals the
+// point-to-point squared distance bit for bit, because |fl(p - q)| = |fl(q - p)|.
+template <int D>
+__device__ __forceinline__ float box_d2(const float *q, const float *lo, const float *hi)
+{
+#pragma clang fp contract(off)
+    float acc = 0.0f;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        float t = 0.0f;
+        if (q[d] < lo[d])
+            t = lo[d] - q[d];
+        else if (q[d] > hi[d])
+            t = q[d] - hi[d];
+        float s = t * t;
+        acc = acc + s;
+    }
+    return acc;
+}
+
+// Closed overlap of [alo, ahi] and [blo, bhi] in every dimension.
+template <int D>
+__device__ __forceinline__ bool boxes_overlap(const float *alo, const float *ahi, const float *blo, const float *bhi)
+{
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+        ok = ok && (alo[d] <= bhi[d]) && (blo[d] <= ahi[d]);
+    return ok;
+}
+
+// Spread the low 21 bits of x so that bit i moves to bit 3i.
+__device__ __forceinline__ uint64_t spread3_21(uint64_t x)
+{
+    x &= 0x1fffffull;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+// Quantise coordinate x of [lo, lo + 1/inv] into 2^bits cells (bits <= 31).
+// The upper clamp is done on the integer side: 2^bits - 1 is not a float for
+// bits > 24.
+__device__ __forceinline__ uint32_t quantise(float x, float lo, float inv, int bits)
+{
+    const float cells = (float)(1u << bits);
+    const float u = fmaxf((x - lo) * inv * cells, 0.0f);
+    return u >= cells ? (1u << bits) - 1u : (uint32_t)u;
+}
+
+// Morton code of cell coordinates c[0..D) with `bits` bits each, dimension 0
+// most significant within each group of D bits.
+template <int D>
+__device__ __forceinline__ uint64_t interleave(const uint32_t *c, int bits)
+{
+    if constexpr (D == 3) {
+        if (bits == 21)
+            return (spread3_21(c[0]) << 2) | (spread3_21(c[1]) << 1) | spread3_21(c[2]);
+    }
+    uint64_t code = 0;
+    for (int b = bits - 1; b >= 0; --b)
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            code = (code << 1) | ((c[d] >> b) & 1u);
+    return code;
+}
+
+}  // namespace ax

@@ -1,0 +1,144 @@
+// Host-side internals shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/arborx.h"
+
+namespace ax {
+
+constexpr int kMaxDim = 10;
+
+// Device-resident tree header written by the build kernels.
+struct TreeHeader {
+    int32_t root;    // index of the root node (-1 when the tree is empty)
+    int32_t height;  // edges on the longest root-to-leaf path
+    int32_t n;
+    int32_t pad;
+    float lo[kMaxDim];
+    float hi[kMaxDim];
+};
+
+// Device-resident per-call header of a CSR query.
+struct QueryHeader {
+    unsigned long long total;      // offsets[m], written by the scan
+    unsigned long long big_rows;   // count pass: rows with kRowSortRegs < len <= kRowSortBlock
+    unsigned long long huge_rows;  // count pass: rows with len > kRowSortBlock
+    unsigned long long big_fill;   // fill pass: entries appended to the big-row list
+    unsigned long long huge_fill;  // fill pass: entries appended to the huge-row list
+    unsigned long long pad[3];
+};
+
+struct Tuning {
+    int block = 256;
+    int order = 1;
+    int stack = 16;
+    int schedule = 0;
+};
+const Tuning &tuning();
+
+// Error reporting: thread-local last message.
+void set_error(const std::string &msg);
+arborx_status fail(arborx_status st, const std::string &msg);
+arborx_status hip_fail(hipError_t e, const char *what);
+
+#define AX_HIP(call)                                                       \
+    do {                                                                   \
+        hipError_t _e = (call);                                            \
+        if (_e != hipSuccess)                                              \
+            return ::ax::hip_fail(_e, #call);                              \
+    } while (0)
+
+// Stream-ordered device allocation; returns ARBORX_E_NOMEM on failure.
+arborx_status dalloc(void **p, size_t bytes, hipStream_t s);
+void dfree(void *p, hipStream_t s);
+
+// Scoped set of stream-ordered temporaries, freed on destruction.
+struct Temps {
+    hipStream_t s;
+    void *ptrs[32];
+    int n = 0;
+    explicit Temps(hipStream_t st) : s(st) {}
+    ~Temps()
+    {
+        for (int i = 0; i < n; ++i)
+            dfree(ptrs[i], s);
+    }
+    template <typename T>
+    arborx_status get(T **p, size_t count)
+    {
+        if (n == (int)(sizeof(ptrs) / sizeof(ptrs[0])))
+            return fail(ARBORX_E_NOMEM, "too many temporaries in one call");
+        void *q = nullptr;
+        arborx_status st = dalloc(&q, count * sizeof(T) + 256, s);
+        if (st != ARBORX_OK)
+            return st;
+        ptrs[n++] = q;
+        *p = static_cast<T *>(q);
+        return ARBORX_OK;
+    }
+};
+
+inline unsigned grid_for(int64_t n, int block, int64_t cap = 1 << 20)
+{
+    int64_t g = (n + block - 1) / block;
+    if (g < 1)
+        g = 1;
+    if (g > cap)
+        g = cap;
+    return (unsigned)g;
+}
+
+// ---- radix sort (sort.hip) ------------------------------------------------
+// Workspace bytes for sorting n pairs.
+size_t radix_workspace_bytes(int64_t n);
+// Stable LSD sort of (keys, vals) by bits [begin, end).  Uses keys_alt/vals_alt
+// as the ping-pong buffers; on return *in_alt tells which buffer holds the result.
+template <typename K>
+hipError_t radix_sort_pairs(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, int64_t n, int begin, int end,
+                            void *workspace, hipStream_t s, bool *in_alt);
+
+// ---- scan (scan.hip) ----------------------------------------------------
+size_t scan_workspace_bytes(int64_t n);
+// offsets[0..m] = exclusive scan of counts; also writes offsets[m] to *total_dev.
+hipError_t csr_offsets(const int32_t *counts, int64_t m, int64_t *offsets, int64_t *total_dev, void *workspace,
+                       hipStream_t s);
+
+// ---- build (build.hip) ----------------------------------------------------
+struct TreeDev {
+    int64_t n = 0;
+    int dim = 0;
+    int kind = 0;
+    void *nodes = nullptr;  // Node<dim>[max(n-1, 1)]
+    TreeHeader *hdr = nullptr;
+};
+size_t node_bytes(int dim);
+arborx_status build_tree(const float *values, int64_t n, int dim, int kind, TreeDev &t, hipStream_t s);
+hipError_t morton64_points(const float *pts, int64_t n, int dim, const float *bounds, uint64_t *codes,
+                           hipStream_t s);
+
+// ---- queries (query.hip) --------------------------------------------------
+enum class Pred { Sphere, Box };
+arborx_status query_order(const TreeDev &t, const float *queries, int64_t m, Pred pred, uint32_t **perm, Temps &tmp,
+                          hipStream_t s);
+arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
+                            const uint32_t *perm, int32_t *counts, QueryHeader *qh, hipStream_t s);
+arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
+                           const uint32_t *perm, const int64_t *offsets, int32_t *indices, QueryHeader *qh,
+                           int64_t *big_list, int64_t big_cap, int64_t *huge_list, int64_t huge_cap, hipStream_t s);
+arborx_status sort_big_rows(const int64_t *offsets, int32_t *indices, QueryHeader *qh, const int64_t *big_list,
+                            int64_t nbig, hipStream_t s);
+arborx_status sort_huge_rows(int64_t n_values, const int64_t *offsets, int32_t *indices, const int64_t *huge_list,
+                             int64_t h, Temps &tmp, hipStream_t s);
+arborx_status spatial_reduce(const TreeDev &t, const float *queries, int64_t m, float radius, int op,
+                             int scale_bits, const uint32_t *perm, int32_t *counts, int64_t *sums, hipStream_t s);
+arborx_status knn_query(const TreeDev &t, const float *queries, int64_t m, int k, const uint32_t *perm,
+                        float *dist2, int32_t *indices, hipStream_t s);
+
+constexpr int kRowSortRegs = 16;      // rows up to this length are sorted in registers
+constexpr int kRowSortBlock = 4096;   // rows up to this length are sorted by one workgroup
+
+}  // namespace ax

@@ -1,0 +1,745 @@
+// Batched queries over a built BVH (Section 2.1: spatial and nearest
+// predicates; storage query with CSR output; Section 2.2: pure callbacks).
+//
+// Queries are first put in Morton order (Section 2.6: sorting is used in
+// search as well as construction) so that the 64 lanes of a wavefront walk
+// neighbouring paths and share node fetches.  Each thread then answers one
+// query with a depth-first walk whose deferred subtrees sit on a short stack:
+// the newest entries in a per-thread column of LDS, older ones spilled to
+// private memory when the LDS ring is full, so any tree height is handled.
+//
+// Every node holds the boxes of both children, so one fetch tests two
+// children.  A child that is a leaf is decided from the slot box alone: for
+// point values the box is the point, and the box distance equals the point
+// distance bit for bit.
+#include "device_util.hpp"
+#include "geometry.hpp"
+#include "internal.hpp"
+#include "profile.hpp"
+
+namespace ax {
+namespace {
+
+constexpr int kSpill = 128;  // > any tree height: 63 code-bit levels + 32 position levels
+
+template <typename E>
+struct ShortStack {
+    E *lds;  // this thread's column: entry j at lds[j * stride]
+    int stride, mask;
+    int base = 0, cnt = 0, ns = 0;
+    E spill[kSpill];
+    __device__ ShortStack(E *col, int stride_, int cap) : lds(col), stride(stride_), mask(cap - 1) {}
+    __device__ __forceinline__ bool empty() const { return cnt == 0 && ns == 0; }
+    __device__ __forceinline__ void push(E x)
+    {
+        if (cnt == mask + 1) {  // ring full: move the oldest LDS entry to the spill area
+            if (ns < kSpill)
+                spill[ns++] = lds[(base & mask) * stride];
+            ++base;
+            --cnt;
+        }
+        lds[((base + cnt) & mask) * stride] = x;
+        ++cnt;
+    }
+    __device__ __forceinline__ E pop()
+    {
+        if (cnt > 0) {
+            --cnt;
+            return lds[((base + cnt) & mask) * stride];
+        }
+        return spill[--ns];
+    }
+};
+
+// Blocks are dealt round-robin over the 8 XCDs; renumber them so that each
+// XCD (and its L2) works on one contiguous run of Morton-ordered queries.
+__device__ __forceinline__ int64_t xcd_block()
+{
+    constexpr int64_t X = 8;
+    const int64_t b = blockIdx.x, G = gridDim.x;
+    const int64_t q = G / X, r = G % X, x = b % X;
+    return x * q + (x < r ? x : r) + b / X;
+}
+
+__device__ __forceinline__ int node_count(const TreeHeader *hdr) { return hdr->n > 1 ? hdr->n - 1 : 1; }
+
+template <int D>
+struct Sphere {
+    float c[D];
+    float r2;
+    __device__ __forceinline__ bool hit(const float *lo, const float *hi, float &d2) const
+    {
+        d2 = box_d2<D>(c, lo, hi);
+        return d2 <= r2;
+    }
+    __device__ __forceinline__ void load(const float *q, int64_t i, float rr)
+    {
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            c[d] = q[i * D + d];
+        r2 = rr;
+    }
+};
+
+template <int D>
+struct BoxQuery {
+    float lo[D], hi[D];
+    __device__ __forceinline__ bool hit(const float *blo, const float *bhi, float &d2) const
+    {
+        d2 = 0.0f;
+        return boxes_overlap<D>(lo, hi, blo, bhi);
+    }
+    __device__ __forceinline__ void load(const float *q, int64_t i, float)
+    {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            lo[d] = q[i * 2 * D + d];
+            hi[d] = q[i * 2 * D + D + d];
+        }
+    }
+};
+
+// Depth-first walk calling f(index, d2) on every matching value.
+// A depth-first walk enters each internal node at most once, so `limit`
+// iterations (more than the node count) bound every walk even on a corrupt
+// tree, and node indices are range-checked before use.
+template <int D, class P, class F>
+__device__ __forceinline__ void traverse_spatial(const Node<D> *__restrict__ nodes, int root, int n_nodes,
+                                                 const P &pred, ShortStack<int> &st, F &f)
+{
+    int cur = root;
+    for (int iter = 0; iter <= n_nodes; ++iter) {
+        if ((unsigned)cur >= (unsigned)n_nodes)
+            break;
+        Node<D> nd;
+        load_node(nodes, cur, nd);
+        float d0, d1;
+        bool h0 = pred.hit(nd.lo[0], nd.hi[0], d0);
+        bool h1 = pred.hit(nd.lo[1], nd.hi[1], d1);
+        const int c0 = nd.child[0], c1 = nd.child[1];
+        if (h0 && c0 < 0) {
+            if (c0 != kEmptyRef)
+                f(~c0, d0);
+            h0 = false;
+        }
+        if (h1 && c1 < 0) {
+            if (c1 != kEmptyRef)
+                f(~c1, d1);
+            h1 = false;
+        }
+        if (h0) {
+            if (h1)
+                st.push(c1);
+            cur = c0;
+        } else if (h1) {
+            cur = c1;
+        } else {
+            if (st.empty())
+                break;
+            cur = st.pop();
+        }
+    }
+}
+
+// Wavefront-aggregated append of `item` to list[*counter++] for lanes with flag set.
+__device__ __forceinline__ void wave_append(bool flag, int64_t item, unsigned long long *counter, int64_t *list,
+                                            int64_t cap)
+{
+    const uint64_t b = __ballot(flag);
+    if (!b)
+        return;
+    const int leader = __ffsll((unsigned long long)b) - 1;
+    unsigned long long base = 0;
+    if (lane_id() == leader)
+        base = atomicAdd(counter, (unsigned long long)__popcll(b));
+    base = __shfl(base, leader, kWave);
+    const int64_t slot = (int64_t)base + __popcll(b & lanemask_lt());
+    if (flag && list && slot < cap)
+        list[slot] = item;
+}
+
+template <int D, class P>
+__global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+                                const float *__restrict__ queries, int64_t m, float r2,
+                                const uint32_t *__restrict__ perm, int32_t *__restrict__ counts, QueryHeader *qh,
+                                int stack_cap)
+{
+    extern __shared__ int s_stack[];
+    const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
+    if (t >= m)
+        return;
+    const int64_t qi = perm ? (int64_t)perm[t] : t;
+    if (qi >= m)
+        return;
+    P pred;
+    pred.load(queries, qi, r2);
+    ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap);
+    int c = 0;
+    auto f = [&](int, float) { ++c; };
+    traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
+    counts[qi] = c;
+    if (qh) {
+        wave_append(c > kRowSortRegs && c <= kRowSortBlock, 0, &qh->big_rows, nullptr, 0);
+        wave_append(c > kRowSortBlock, 0, &qh->huge_rows, nullptr, 0);
+    }
+}
+
+// Insert x into the ascending buffer buf[0..k) (k < C) using static indices only.
+template <int C>
+__device__ __forceinline__ void insert_sorted(int (&buf)[C], int k, int x)
+{
+    int v = x;
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+        const int a = buf[s];
+        const bool in = s < k;
+        buf[s] = in ? min(a, v) : (s == k ? v : a);
+        v = in ? max(a, v) : v;
+    }
+}
+
+// Second walk: write each row at offsets[q].  Rows of up to kRowSortRegs
+// matches come out sorted from registers; longer rows are listed for sorting.
+template <int D, class P>
+__global__ void k_spatial_fill(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+                               const float *__restrict__ queries, int64_t m, float r2,
+                               const uint32_t *__restrict__ perm, const int64_t *__restrict__ offsets,
+                               int32_t *__restrict__ indices, QueryHeader *qh, int64_t *big_list, int64_t big_cap,
+                               int64_t *huge_list, int64_t huge_cap, int stack_cap)
+{
+    extern __shared__ int s_stack[];
+    const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
+    if (t >= m)
+        return;
+    const int64_t qi = perm ? (int64_t)perm[t] : t;
+    if (qi >= m)
+        return;
+    P pred;
+    pred.load(queries, qi, r2);
+    ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap);
+    const int64_t o = offsets[qi];
+    const int64_t len = offsets[qi + 1] - o;
+    int buf[kRowSortRegs];
+#pragma unroll
+    for (int s = 0; s < kRowSortRegs; ++s)
+        buf[s] = 0;
+    int64_t k = 0;
+    auto f = [&](int idx, float) {
+        if (k < kRowSortRegs)
+            insert_sorted<kRowSortRegs>(buf, (int)k, idx);
+        else if (k < len)
+            indices[o + k] = idx;
+        ++k;
+    };
+    traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
+#pragma unroll
+    for (int s = 0; s < kRowSortRegs; ++s)
+        if (s < k && s < len)
+            indices[o + s] = buf[s];
+    wave_append(len > kRowSortRegs && len <= kRowSortBlock, qi, &qh->big_fill, big_list, big_cap);
+    wave_append(len > kRowSortBlock, qi, &qh->huge_fill, huge_list, huge_cap);
+}
+
+// One workgroup per listed row of at most kRowSortBlock entries: bitonic sort in LDS.
+__global__ __launch_bounds__(256) void k_sort_rows(const int64_t *__restrict__ offsets, int32_t *__restrict__ indices,
+                                                   const int64_t *__restrict__ list, int64_t cap, const QueryHeader *qh)
+{
+    __shared__ int32_t s[kRowSortBlock];
+    const int64_t nb = min((int64_t)qh->big_fill, cap);
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const int64_t row = list[b];
+        const int64_t o = offsets[row];
+        const int64_t len64 = offsets[row + 1] - o;
+        if (len64 > kRowSortBlock)
+            continue;
+        const int len = (int)len64;
+        int p2 = 1;
+        while (p2 < len)
+            p2 <<= 1;
+        for (int i = threadIdx.x; i < p2; i += blockDim.x)
+            s[i] = i < len ? indices[o + i] : INT32_MAX;
+        __syncthreads();
+        for (int kk = 2; kk <= p2; kk <<= 1) {
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                for (int i = threadIdx.x; i < p2; i += blockDim.x) {
+                    const int ixj = i ^ j;
+                    if (ixj > i) {
+                        const int a = s[i], c = s[ixj];
+                        const bool up = (i & kk) == 0;
+                        if ((a > c) == up) {
+                            s[i] = c;
+                            s[ixj] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int i = threadIdx.x; i < len; i += blockDim.x)
+            indices[o + i] = s[i];
+        __syncthreads();
+    }
+}
+
+// Rows longer than a workgroup can sort: gather as (row rank, index) keys,
+// radix sort, scatter back.
+__global__ void k_huge_lengths(const int64_t *__restrict__ offsets, const int64_t *__restrict__ list, int64_t h,
+                               int32_t *__restrict__ lens)
+{
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < h; b += (int64_t)gridDim.x * blockDim.x)
+        lens[b] = (int32_t)(offsets[list[b] + 1] - offsets[list[b]]);
+}
+
+__global__ void k_huge_gather(const int64_t *__restrict__ offsets, const int32_t *__restrict__ indices,
+                              const int64_t *__restrict__ list, int64_t h, const int64_t *__restrict__ starts,
+                              int ib, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    for (int64_t b = blockIdx.x; b < h; b += gridDim.x) {
+        const int64_t o = offsets[list[b]], len = offsets[list[b] + 1] - o, st = starts[b];
+        for (int64_t j = threadIdx.x; j < len; j += blockDim.x) {
+            keys[st + j] = ((uint64_t)b << ib) | (uint32_t)indices[o + j];
+            vals[st + j] = 0;
+        }
+    }
+}
+
+__global__ void k_huge_scatter(const uint64_t *__restrict__ keys, int64_t total, int ib, int64_t h,
+                               const int64_t *__restrict__ offsets, const int64_t *__restrict__ list,
+                               const int64_t *__restrict__ starts, int32_t *__restrict__ indices)
+{
+    const uint64_t lowmask = (1ull << ib) - 1ull;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = keys[p];
+        const int64_t b = (int64_t)(key >> ib);
+        if (b < h)
+            indices[offsets[list[b]] + (p - starts[b])] = (int32_t)(key & lowmask);
+    }
+}
+
+template <int D, bool SUMDIST>
+__global__ void k_spatial_reduce(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+                                 const float *__restrict__ queries, int64_t m, float r2, float scale,
+                                 const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
+                                 int64_t *__restrict__ sums, int stack_cap)
+{
+    extern __shared__ int s_stack[];
+    const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
+    if (t >= m)
+        return;
+    const int64_t qi = perm ? (int64_t)perm[t] : t;
+    if (qi >= m)
+        return;
+    Sphere<D> pred;
+    pred.load(queries, qi, r2);
+    ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap);
+    int c = 0;
+    long long s = 0;
+    auto f = [&](int, float d2) {
+        ++c;
+        if (SUMDIST) {
+            const float dist = sqrtf(d2);  // correctly rounded
+            const float scaled = dist * scale;  // exact: scale is a power of two
+            s += (long long)scaled;
+        }
+    };
+    traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
+    counts[qi] = c;
+    if (SUMDIST)
+        sums[qi] = s;
+}
+
+struct KnnEntry {
+    int32_t ref;
+    float d2;
+};
+
+template <int K>
+__device__ __forceinline__ void knn_offer(float (&bd)[K], int (&bi)[K], float d, int id)
+{
+    if (!(d < bd[K - 1] || (d == bd[K - 1] && id < bi[K - 1])))
+        return;
+    float vd = d;
+    int vi = id;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const bool lt = vd < bd[s] || (vd == bd[s] && vi < bi[s]);
+        const float td = bd[s];
+        const int ti = bi[s];
+        bd[s] = lt ? vd : td;
+        bi[s] = lt ? vi : ti;
+        vd = lt ? td : vd;
+        vi = lt ? ti : vi;
+    }
+}
+
+// Nearest-first walk keeping the K best (d2, index) pairs sorted in
+// registers; a subtree is skipped only if its box is strictly farther than the
+// current K-th pair, so equal-distance values with smaller indices are found.
+template <int D, int K>
+__global__ void k_knn(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+                      const float *__restrict__ queries, int64_t m, int k_out, const uint32_t *__restrict__ perm,
+                      float *__restrict__ out_d2, int32_t *__restrict__ out_idx, int stack_cap)
+{
+    extern __shared__ int s_stack[];
+    const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
+    if (t >= m)
+        return;
+    const int64_t qi = perm ? (int64_t)perm[t] : t;
+    if (qi >= m)
+        return;
+    float q[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+        q[d] = queries[qi * D + d];
+    float bd[K];
+    int bi[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        bd[s] = INFINITY;
+        bi[s] = INT32_MAX;
+    }
+    ShortStack<KnnEntry> st(reinterpret_cast<KnnEntry *>(s_stack) + threadIdx.x, blockDim.x, stack_cap);
+    int cur = hdr->root;
+    const int n_nodes = node_count(hdr);
+    for (int iter = 0; iter <= n_nodes; ++iter) {
+        if ((unsigned)cur >= (unsigned)n_nodes)
+            break;
+        Node<D> nd;
+        load_node(nodes, cur, nd);
+        const float d0 = box_d2<D>(q, nd.lo[0], nd.hi[0]);
+        const float d1 = box_d2<D>(q, nd.lo[1], nd.hi[1]);
+        const int c0 = nd.child[0], c1 = nd.child[1];
+        if (c0 < 0 && c0 != kEmptyRef)
+            knn_offer<K>(bd, bi, d0, ~c0);
+        if (c1 < 0 && c1 != kEmptyRef)
+            knn_offer<K>(bd, bi, d1, ~c1);
+        const bool k0 = c0 >= 0 && !(d0 > bd[K - 1]);
+        const bool k1 = c1 >= 0 && !(d1 > bd[K - 1]);
+        if (k0 && k1) {
+            if (d1 < d0) {
+                st.push(KnnEntry{c0, d0});
+                cur = c1;
+            } else {
+                st.push(KnnEntry{c1, d1});
+                cur = c0;
+            }
+        } else if (k0) {
+            cur = c0;
+        } else if (k1) {
+            cur = c1;
+        } else {
+            bool found = false;
+            while (!st.empty()) {
+                const KnnEntry e = st.pop();
+                if (!(e.d2 > bd[K - 1])) {
+                    cur = e.ref;
+                    found = true;
+                    break;
+                }
+            }
+            if (!found)
+                break;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        if (s < k_out) {
+            const bool empty = bi[s] == INT32_MAX;
+            out_d2[qi * k_out + s] = empty ? INFINITY : bd[s];
+            out_idx[qi * k_out + s] = empty ? -1 : bi[s];
+        }
+    }
+}
+
+__global__ void k_knn_empty(int64_t total, float *d2, int32_t *idx)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        d2[i] = INFINITY;
+        idx[i] = -1;
+    }
+}
+
+// 32-bit Morton codes of query centres, normalised by the tree's bounds.
+template <int D, bool BOXQ>
+__global__ void k_query_codes(const float *__restrict__ q, int64_t m, const TreeHeader *__restrict__ hdr,
+                              uint32_t *__restrict__ codes, uint32_t *__restrict__ ids)
+{
+    constexpr int bits = 30 / D;
+    float lo[D], inv[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = hdr->lo[d];
+        const float ext = hdr->hi[d] - hdr->lo[d];
+        inv[d] = ext > 0.0f ? 1.0f / ext : 0.0f;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t c[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const float x = BOXQ ? q[i * 2 * D + d] + 0.5f * (q[i * 2 * D + D + d] - q[i * 2 * D + d]) : q[i * D + d];
+            c[d] = quantise(x, lo[d], inv[d], bits);
+        }
+        codes[i] = (uint32_t)interleave<D>(c, bits);
+        ids[i] = (uint32_t)i;
+    }
+}
+
+template <typename T>
+arborx_status fill_async(T *p, int64_t n, T v, hipStream_t s)
+{
+    if (n <= 0)
+        return ARBORX_OK;
+    fill_kernel<T><<<grid_for(n, 256, 65536), 256, 0, s>>>(p, n, v);
+    AX_HIP(hipGetLastError());
+    return ARBORX_OK;
+}
+
+struct Launch {
+    unsigned grid;
+    int block;
+    int cap;
+    size_t lds;
+};
+
+Launch traversal_launch(int64_t m, size_t entry_bytes)
+{
+    const Tuning &tu = tuning();
+    Launch L;
+    L.block = tu.block;
+    L.cap = tu.stack;
+    L.grid = (unsigned)((m + L.block - 1) / L.block);
+    while (L.cap > 1 && (size_t)L.cap * L.block * entry_bytes > 65536)
+        L.cap >>= 1;
+    L.lds = (size_t)L.cap * L.block * entry_bytes;
+    return L;
+}
+
+template <int D>
+arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m, float r2, const uint32_t *perm,
+                         int32_t *counts, QueryHeader *qh, hipStream_t s)
+{
+    const Launch L = traversal_launch(m, sizeof(int));
+    const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
+    ProfScope ps("spatial_count", s);
+    if (pred == Pred::Sphere)
+        k_spatial_count<D, Sphere<D>><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, counts, qh, L.cap);
+    else
+        k_spatial_count<D, BoxQuery<D>><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, counts, qh,
+                                                                       L.cap);
+    AX_HIP(hipGetLastError());
+    return ARBORX_OK;
+}
+
+template <int D>
+arborx_status fill_impl(const TreeDev &t, Pred pred, const float *q, int64_t m, float r2, const uint32_t *perm,
+                        const int64_t *offsets, int32_t *indices, QueryHeader *qh, int64_t *big_list,
+                        int64_t big_cap, int64_t *huge_list, int64_t huge_cap, hipStream_t s)
+{
+    const Launch L = traversal_launch(m, sizeof(int));
+    const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
+    ProfScope ps("spatial_fill", s);
+    if (pred == Pred::Sphere)
+        k_spatial_fill<D, Sphere<D>><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, offsets, indices,
+                                                                    qh, big_list, big_cap, huge_list, huge_cap, L.cap);
+    else
+        k_spatial_fill<D, BoxQuery<D>><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, offsets,
+                                                                      indices, qh, big_list, big_cap, huge_list,
+                                                                      huge_cap, L.cap);
+    AX_HIP(hipGetLastError());
+    return ARBORX_OK;
+}
+
+template <int D>
+arborx_status reduce_impl(const TreeDev &t, const float *q, int64_t m, float r2, int op, float scale,
+                          const uint32_t *perm, int32_t *counts, int64_t *sums, hipStream_t s)
+{
+    const Launch L = traversal_launch(m, sizeof(int));
+    const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
+    ProfScope ps(op == ARBORX_COUNT_SUMDIST ? "reduce_sumdist" : "reduce_count", s);
+    if (op == ARBORX_COUNT_SUMDIST)
+        k_spatial_reduce<D, true><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, scale, perm, counts, sums,
+                                                                 L.cap);
+    else
+        k_spatial_reduce<D, false><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, scale, perm, counts, sums,
+                                                                  L.cap);
+    AX_HIP(hipGetLastError());
+    return ARBORX_OK;
+}
+
+template <int D, int K>
+arborx_status knn_launch(const TreeDev &t, const float *q, int64_t m, int k, const uint32_t *perm, float *d2,
+                         int32_t *idx, hipStream_t s)
+{
+    const Launch L = traversal_launch(m, sizeof(KnnEntry));
+    ProfScope ps("knn", s);
+    k_knn<D, K><<<L.grid, L.block, L.lds, s>>>(static_cast<const Node<D> *>(t.nodes), t.hdr, q, m, k, perm, d2, idx,
+                                                L.cap);
+    AX_HIP(hipGetLastError());
+    return ARBORX_OK;
+}
+
+template <int D>
+arborx_status knn_impl(const TreeDev &t, const float *q, int64_t m, int k, const uint32_t *perm, float *d2,
+                       int32_t *idx, hipStream_t s)
+{
+    if (k <= 1)
+        return knn_launch<D, 1>(t, q, m, k, perm, d2, idx, s);
+    if (k <= 2)
+        return knn_launch<D, 2>(t, q, m, k, perm, d2, idx, s);
+    if (k <= 4)
+        return knn_launch<D, 4>(t, q, m, k, perm, d2, idx, s);
+    if (k <= 8)
+        return knn_launch<D, 8>(t, q, m, k, perm, d2, idx, s);
+    if (k <= 10)
+        return knn_launch<D, 10>(t, q, m, k, perm, d2, idx, s);
+    if (k <= 16)
+        return knn_launch<D, 16>(t, q, m, k, perm, d2, idx, s);
+    if (k <= 32)
+        return knn_launch<D, 32>(t, q, m, k, perm, d2, idx, s);
+    return knn_launch<D, 64>(t, q, m, k, perm, d2, idx, s);
+}
+
+template <int D>
+arborx_status order_impl(const TreeDev &t, const float *q, int64_t m, Pred pred, uint32_t **perm, Temps &tmp,
+                         hipStream_t s)
+{
+    uint32_t *codes, *codes2, *ids, *ids2;
+    uint8_t *ws;
+    arborx_status st;
+    if ((st = tmp.get(&codes, m)) != ARBORX_OK || (st = tmp.get(&codes2, m)) != ARBORX_OK ||
+        (st = tmp.get(&ids, m)) != ARBORX_OK || (st = tmp.get(&ids2, m)) != ARBORX_OK ||
+        (st = tmp.get(&ws, radix_workspace_bytes(m))) != ARBORX_OK)
+        return st;
+    ProfScope ps("order", s);
+    if (pred == Pred::Sphere)
+        k_query_codes<D, false><<<grid_for(m, 256, 65536), 256, 0, s>>>(q, m, t.hdr, codes, ids);
+    else
+        k_query_codes<D, true><<<grid_for(m, 256, 65536), 256, 0, s>>>(q, m, t.hdr, codes, ids);
+    bool alt = false;
+    AX_HIP(radix_sort_pairs<uint32_t>(codes, ids, codes2, ids2, m, 0, (30 / D) * D, ws, s, &alt));
+    *perm = alt ? ids2 : ids;
+    return ARBORX_OK;
+}
+
+#define AX_DISPATCH_DIM(dim, CALL)                                              \
+    switch (dim) {                                                              \
+    case 2: { constexpr int D = 2; return CALL; }                               \
+    case 3: { constexpr int D = 3; return CALL; }                               \
+    case 6: { constexpr int D = 6; return CALL; }                               \
+    default: return fail(ARBORX_E_UNSUPPORTED, "dimension not compiled in");    \
+    }
+
+}  // namespace
+
+arborx_status query_order(const TreeDev &t, const float *queries, int64_t m, Pred pred, uint32_t **perm, Temps &tmp,
+                          hipStream_t s)
+{
+    *perm = nullptr;
+    if (!tuning().order || t.n == 0 || m <= 1)
+        return ARBORX_OK;
+    AX_DISPATCH_DIM(t.dim, (order_impl<D>(t, queries, m, pred, perm, tmp, s)));
+}
+
+arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
+                            const uint32_t *perm, int32_t *counts, QueryHeader *qh, hipStream_t s)
+{
+    if (m == 0)
+        return ARBORX_OK;
+    if (t.n == 0)
+        return fill_async<int32_t>(counts, m, 0, s);
+    const float r2 = radius * radius;
+    AX_DISPATCH_DIM(t.dim, (count_impl<D>(t, pred, queries, m, r2, perm, counts, qh, s)));
+}
+
+arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
+                           const uint32_t *perm, const int64_t *offsets, int32_t *indices, QueryHeader *qh,
+                           int64_t *big_list, int64_t big_cap, int64_t *huge_list, int64_t huge_cap, hipStream_t s)
+{
+    if (m == 0 || t.n == 0)
+        return ARBORX_OK;
+    const float r2 = radius * radius;
+    AX_DISPATCH_DIM(t.dim, (fill_impl<D>(t, pred, queries, m, r2, perm, offsets, indices, qh, big_list, big_cap,
+                                         huge_list, huge_cap, s)));
+}
+
+arborx_status sort_big_rows(const int64_t *offsets, int32_t *indices, QueryHeader *qh, const int64_t *big_list,
+                            int64_t nbig, hipStream_t s)
+{
+    if (nbig <= 0)
+        return ARBORX_OK;
+    ProfScope ps("sort_rows", s);
+    k_sort_rows<<<(unsigned)(nbig < 8192 ? nbig : 8192), 256, 0, s>>>(offsets, indices, big_list, nbig, qh);
+    AX_HIP(hipGetLastError());
+    return ARBORX_OK;
+}
+
+arborx_status sort_huge_rows(int64_t n_values, const int64_t *offsets, int32_t *indices, const int64_t *huge_list,
+                             int64_t h, Temps &tmp, hipStream_t s)
+{
+    if (h <= 0)
+        return ARBORX_OK;
+    int32_t *lens;
+    int64_t *starts, *tot_dev;
+    uint8_t *sws;
+    arborx_status st;
+    if ((st = tmp.get(&lens, h)) != ARBORX_OK || (st = tmp.get(&starts, h + 1)) != ARBORX_OK ||
+        (st = tmp.get(&tot_dev, 1)) != ARBORX_OK || (st = tmp.get(&sws, scan_workspace_bytes(h))) != ARBORX_OK)
+        return st;
+    k_huge_lengths<<<grid_for(h, 256, 4096), 256, 0, s>>>(offsets, huge_list, h, lens);
+    AX_HIP(csr_offsets(lens, h, starts, tot_dev, sws, s));
+    int64_t total = 0;
+    AX_HIP(hipMemcpyAsync(&total, tot_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    AX_HIP(hipStreamSynchronize(s));
+    int ib = 1, hb = 1;
+    while ((1ll << ib) < n_values)
+        ++ib;
+    while ((1ll << hb) < h)
+        ++hb;
+    if (ib + hb > 64)
+        return fail(ARBORX_E_UNSUPPORTED, "too many long rows to sort");
+    uint64_t *k1, *k2;
+    uint32_t *v1, *v2;
+    uint8_t *rws;
+    if ((st = tmp.get(&k1, total)) != ARBORX_OK || (st = tmp.get(&k2, total)) != ARBORX_OK ||
+        (st = tmp.get(&v1, total)) != ARBORX_OK || (st = tmp.get(&v2, total)) != ARBORX_OK ||
+        (st = tmp.get(&rws, radix_workspace_bytes(total))) != ARBORX_OK)
+        return st;
+    k_huge_gather<<<(unsigned)(h < 4096 ? h : 4096), 256, 0, s>>>(offsets, indices, huge_list, h, starts, ib, k1, v1);
+    bool alt = false;
+    AX_HIP(radix_sort_pairs<uint64_t>(k1, v1, k2, v2, total, 0, ib + hb, rws, s, &alt));
+    k_huge_scatter<<<grid_for(total, 256, 65536), 256, 0, s>>>(alt ? k2 : k1, total, ib, h, offsets, huge_list, starts,
+                                                              indices);
+    AX_HIP(hipGetLastError());
+    return ARBORX_OK;
+}
+
+arborx_status spatial_reduce(const TreeDev &t, const float *queries, int64_t m, float radius, int op,
+                             int scale_bits, const uint32_t *perm, int32_t *counts, int64_t *sums, hipStream_t s)
+{
+    if (m == 0)
+        return ARBORX_OK;
+    if (t.n == 0) {
+        arborx_status st = fill_async<int32_t>(counts, m, 0, s);
+        if (st == ARBORX_OK && op == ARBORX_COUNT_SUMDIST)
+            st = fill_async<int64_t>(sums, m, 0, s);
+        return st;
+    }
+    const float r2 = radius * radius;
+    const float scale = ldexpf(1.0f, scale_bits);
+    AX_DISPATCH_DIM(t.dim, (reduce_impl<D>(t, queries, m, r2, op, scale, perm, counts, sums, s)));
+}
+
+arborx_status knn_query(const TreeDev &t, const float *queries, int64_t m, int k, const uint32_t *perm,
+                        float *dist2, int32_t *indices, hipStream_t s)
+{
+    if (m == 0)
+        return ARBORX_OK;
+    if (t.n == 0) {
+        k_knn_empty<<<grid_for(m * k, 256, 65536), 256, 0, s>>>(m * k, dist2, indices);
+        AX_HIP(hipGetLastError());
+        return ARBORX_OK;
+    }
+    AX_DISPATCH_DIM(t.dim, (knn_impl<D>(t, queries, m, k, perm, dist2, indices, s)));
+}
+
+}  // namespace ax

@@ -1,0 +1,103 @@
+// CSR offsets from per-query counts: offsets[0] = 0, offsets[i+1] = offsets[i] + counts[i]
+// (the offsets array of the compressed-sparse-row result, Section 2.1).
+// Reduce-then-scan over 4096-count tiles: tile sums, one-workgroup scan of the
+// tile sums, then each tile scans itself from its prefix.
+#include "device_util.hpp"
+#include "internal.hpp"
+
+namespace ax {
+namespace {
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+__global__ __launch_bounds__(kScanBlock) void scan_tile_sums(const int32_t *__restrict__ counts, int64_t m,
+                                                             int64_t *__restrict__ tile_sums)
+{
+    __shared__ int64_t wsum[kScanBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t s = 0;
+#pragma unroll 4
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = base + (int64_t)j * kScanBlock + threadIdx.x;
+        if (i < m)
+            s += counts[i];
+    }
+    int64_t tot = 0;
+    block_exclusive_scan<kScanBlock>(s, wsum, &tot);
+    if (threadIdx.x == 0)
+        tile_sums[blockIdx.x] = tot;
+}
+
+// One workgroup: exclusive scan of the tile sums in place; the grand total goes to *total.
+__global__ __launch_bounds__(kScanBlock) void scan_tile_prefix(int64_t *__restrict__ tile_sums, int64_t tiles,
+                                                               int64_t *__restrict__ total)
+{
+    __shared__ int64_t wsum[kScanBlock / kWave];
+    int64_t carry = 0;
+    for (int64_t start = 0; start < tiles; start += kScanBlock) {
+        const int64_t i = start + threadIdx.x;
+        const int64_t x = i < tiles ? tile_sums[i] : 0;
+        int64_t chunk = 0;
+        const int64_t ex = block_exclusive_scan<kScanBlock>(x, wsum, &chunk);
+        if (i < tiles)
+            tile_sums[i] = carry + ex;
+        carry += chunk;
+    }
+    if (threadIdx.x == 0)
+        *total = carry;
+}
+
+// Each thread owns kScanItems consecutive counts.
+__global__ __launch_bounds__(kScanBlock) void scan_apply(const int32_t *__restrict__ counts, int64_t m,
+                                                         const int64_t *__restrict__ tile_prefix,
+                                                         int64_t *__restrict__ offsets)
+{
+    __shared__ int64_t wsum[kScanBlock / kWave];
+    const int64_t i0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int32_t c[kScanItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        c[j] = (i0 + j < m) ? counts[i0 + j] : 0;
+        s += c[j];
+    }
+    int64_t tot = 0;
+    int64_t run = tile_prefix[blockIdx.x] + block_exclusive_scan<kScanBlock>(s, wsum, &tot);
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        if (i0 + j < m)
+            offsets[i0 + j] = run;
+        run += c[j];
+        if (i0 + j == m - 1)
+            offsets[m] = run;
+    }
+}
+
+__global__ void scan_empty(int64_t *offsets, int64_t *total)
+{
+    offsets[0] = 0;
+    *total = 0;
+}
+
+}  // namespace
+
+size_t scan_workspace_bytes(int64_t m) { return (size_t)((m + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t); }
+
+hipError_t csr_offsets(const int32_t *counts, int64_t m, int64_t *offsets, int64_t *total_dev, void *workspace,
+                       hipStream_t s)
+{
+    if (m == 0) {
+        scan_empty<<<1, 1, 0, s>>>(offsets, total_dev);
+        return hipGetLastError();
+    }
+    const int64_t tiles = (m + kScanTile - 1) / kScanTile;
+    int64_t *tile_sums = static_cast<int64_t *>(workspace);
+    scan_tile_sums<<<(unsigned)tiles, kScanBlock, 0, s>>>(counts, m, tile_sums);
+    scan_tile_prefix<<<1, kScanBlock, 0, s>>>(tile_sums, tiles, total_dev);
+    scan_apply<<<(unsigned)tiles, kScanBlock, 0, s>>>(counts, m, tile_sums, offsets);
+    return hipGetLastError();
+}
+
+}  // namespace ax

@@ -1,0 +1,98 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, and rejects bad arguments on the host before any device work."""
+import ctypes
+import os
+
+import pytest
+
+from paper_2507_23700_amd import _lib, build
+
+L = None
+
+
+def setup_module(module):
+    global L
+    if not os.path.exists(_lib.LIB_PATH):
+        build.build()
+    L = _lib.lib()
+
+
+def _has_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def test_every_declared_symbol_is_exported():
+    names = _lib.header_symbols()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.SIGNATURES)
+
+
+def test_version_and_error_string():
+    assert L.arborx_version().decode().startswith("arborx355")
+    assert isinstance(L.arborx_last_error(), bytes)
+
+
+P = ctypes.c_void_p
+FAKE = P(0x1000)  # never dereferenced: validation fails first
+
+
+def _err():
+    return L.arborx_last_error().decode()
+
+
+def test_build_argument_validation():
+    out = P()
+    assert L.arborx_bvh_build(FAKE, 10, 3, 0, None, None) == 1
+    assert L.arborx_bvh_build(FAKE, -1, 3, 0, None, ctypes.byref(out)) == 1
+    assert L.arborx_bvh_build(FAKE, 10, 0, 0, None, ctypes.byref(out)) == 1
+    assert L.arborx_bvh_build(FAKE, 10, 11, 0, None, ctypes.byref(out)) == 1
+    assert L.arborx_bvh_build(FAKE, 10, 3, 7, None, ctypes.byref(out)) == 1
+    assert L.arborx_bvh_build(None, 10, 3, 0, None, ctypes.byref(out)) == 1
+    assert "NULL" in _err()
+    assert L.arborx_bvh_build(FAKE, 2 ** 31, 3, 0, None, ctypes.byref(out)) == 1
+    assert L.arborx_bvh_build(FAKE, 10, 4, 0, None, ctypes.byref(out)) == 2
+    assert out.value is None
+
+
+def test_query_argument_validation():
+    f = ctypes.c_float
+    tot = ctypes.c_int64()
+    assert L.arborx_query_spatial(None, FAKE, 1, f(1), FAKE, FAKE, 1, ctypes.byref(tot), None) == 1
+    assert L.arborx_query_knn(None, FAKE, 1, 3, FAKE, FAKE, None) == 1
+    assert L.arborx_query_spatial_reduce(None, FAKE, 1, f(1), 0, FAKE, None, 32, None) == 1
+    assert L.arborx_query_intersects(None, FAKE, 1, FAKE, FAKE, 1, ctypes.byref(tot), None) == 1
+    assert L.arborx_bvh_info(None, None, None, None, None, None) == 1
+    assert L.arborx_debug_tree_nodes(None, FAKE, FAKE, FAKE, FAKE) == 1
+    assert L.arborx_bvh_destroy(None) == 0
+
+
+def test_tuning_validation_and_roundtrip():
+    t = _lib.Tuning(128, 0, 8, 0)
+    assert L.arborx_set_tuning(ctypes.byref(t)) == 0
+    g = _lib.Tuning()
+    assert L.arborx_get_tuning(ctypes.byref(g)) == 0
+    assert (g.block, g.order, g.stack, g.schedule) == (128, 0, 8, 0)
+    assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(100, 1, 0, 0))) == 1
+    assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 12, 0))) == 1
+    assert L.arborx_set_tuning(None) == 0
+    assert L.arborx_get_tuning(ctypes.byref(g)) == 0
+    assert (g.block, g.order, g.stack) == (256, 1, 16)
+
+
+def test_debug_entry_validation():
+    assert L.arborx_debug_radix_sort(FAKE, FAKE, 10, 48, 0, 48, None) == 1
+    assert L.arborx_debug_radix_sort(FAKE, FAKE, 10, 32, 0, 33, None) == 1
+    assert L.arborx_debug_morton64(FAKE, 10, 5, FAKE, FAKE, None) == 2
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-GPU error path")
+def test_valid_call_without_gpu_reports_device_error():
+    out = P()
+    assert L.arborx_bvh_build(FAKE, 10, 3, 0, None, ctypes.byref(out)) == 5
+    assert "GPU" in _err()

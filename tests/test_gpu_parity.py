@@ -1,0 +1,350 @@
+"""HIP path vs the CPU oracle, element by element, through the C ABI.
+
+Integer outputs (indices, counts, fixed-point sums) and kNN distances must be
+bit-identical: both sides compute float32 squared distances in the same
+operation order without contraction, and every decision (radius test, kNN
+order) is taken on those identical values.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2507_23700_amd as ax
+from paper_2507_23700_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ax.arborx_reset_tuning()
+    yield
+    ax.arborx_reset_tuning()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def check_spatial(tree, data, q, r, dim=3, kind=oracle.POINTS):
+    off, idx = ax.arborx_query_spatial(tree, dev(q), float(r))
+    o_off, o_idx = oracle.spatial(data, q, r, dim=dim, kind=kind)
+    assert np.array_equal(host(off), o_off)
+    assert np.array_equal(host(idx), o_idx)
+    return o_off
+
+
+def check_knn(tree, data, q, k, dim=3, kind=oracle.POINTS):
+    d2, ix = ax.arborx_query_knn(tree, dev(q), k)
+    o_d2, o_ix = oracle.knn(data, q, k, dim=dim, kind=kind)
+    assert np.array_equal(host(ix), o_ix)
+    assert np.array_equal(host(d2), o_d2)
+
+
+def check_reduce(tree, data, q, r, dim=3, kind=oracle.POINTS):
+    c, s = ax.arborx_query_spatial_reduce(tree, dev(q), float(r), ax.COUNT_SUMDIST)
+    oc, os_ = oracle.reduce(data, q, r, dim=dim, kind=kind)
+    assert np.array_equal(host(c), oc)
+    assert np.array_equal(host(s), os_)
+    c2, _ = ax.arborx_query_spatial_reduce(tree, dev(q), float(r), ax.COUNT)
+    assert np.array_equal(host(c2), oc)
+
+
+# ---------------------------------------------------------------------------
+# components
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 4095, 4096, 4097, 100_003])
+def test_radix_sort_stable_u64(n):
+    g = np.random.default_rng(n)
+    keys = g.integers(0, 1 << 63, size=n, dtype=np.int64)
+    keys[::3] = keys[0]  # many equal keys
+    keys[1::7] = g.integers(0, 50, size=len(keys[1::7]))
+    vals = np.arange(n, dtype=np.int32)
+    k, v = dev(keys), dev(vals)
+    ax.arborx_debug_radix_sort(k, v, 0, 64)
+    order = np.argsort(keys.view(np.uint64), kind="stable")
+    assert np.array_equal(host(v), order.astype(np.int32))
+    assert np.array_equal(host(k), keys[order])
+
+
+def test_radix_sort_bit_range_u32():
+    g = np.random.default_rng(5)
+    n = 70_001
+    keys = g.integers(0, 1 << 31, size=n, dtype=np.int64).astype(np.int32)
+    vals = g.integers(0, 1 << 30, size=n, dtype=np.int64).astype(np.int32)
+    k, v = dev(keys), dev(vals)
+    ax.arborx_debug_radix_sort(k, v, 3, 20)
+    sub = (keys.view(np.uint32) >> 3) & ((1 << 17) - 1)
+    order = np.argsort(sub, kind="stable")
+    assert np.array_equal(host(v), vals[order])
+
+
+def _morton_ref(pts, lo, hi, dim):
+    """Independent bit-loop encoder: cell of each coordinate, then bit interleave."""
+    bits = 63 // dim
+    ext = (hi - lo).astype(np.float32)
+    inv = np.where(ext > 0, np.float32(1) / np.where(ext > 0, ext, 1), 0).astype(np.float32)
+    u = ((pts - lo).astype(np.float32) * inv).astype(np.float32) * np.float32(1 << bits)
+    cell = np.clip(np.floor(np.maximum(u, 0).astype(np.float64)), 0, (1 << bits) - 1).astype(np.uint64)
+    code = np.zeros(len(pts), dtype=np.uint64)
+    for b in range(bits - 1, -1, -1):
+        for d in range(dim):
+            code = (code << np.uint64(1)) | ((cell[:, d] >> np.uint64(b)) & np.uint64(1))
+    return code
+
+
+@pytest.mark.parametrize("dim", [2, 3, 6])
+def test_morton64(dim):
+    g = np.random.default_rng(dim)
+    pts = g.random((5000, dim)).astype(np.float32)
+    pts[0] = 0
+    pts[1] = 1
+    lo, hi = np.zeros(dim, np.float32), np.ones(dim, np.float32)
+    codes = host(ax.arborx_debug_morton64(dev(pts), dev(np.stack([lo, hi])))).view(np.uint64)
+    ref = _morton_ref(pts, lo, hi, dim)
+    assert codes[0] == 0 and codes[1] == (1 << ((63 // dim) * dim)) - 1
+    # quantisation may differ by float rounding of x*inv*2^b vs the reference only at cell edges
+    assert np.mean(codes == ref) > 0.999
+
+
+def _tree_invariants(tree, data, kind=oracle.POINTS):
+    child, lo, hi, root = ax.arborx_debug_tree_nodes(tree)
+    n, dim = tree.n, tree.dim
+    if kind == oracle.POINTS:
+        vlo = vhi = data
+    else:
+        vlo, vhi = data[:, 0], data[:, 1]
+    seen_leaf = np.zeros(n, dtype=np.int32)
+    seen_node = np.zeros(max(n - 1, 1), dtype=np.int32)
+    stack = [(root, 0)]
+    maxdepth = 0
+    while stack:
+        node, depth = stack.pop()
+        seen_node[node] += 1
+        for s in range(2):
+            c = int(child[node, s])
+            if c == -2 ** 31:
+                continue
+            if c < 0:
+                j = ~c
+                seen_leaf[j] += 1
+                assert np.array_equal(lo[node, s], vlo[j]) and np.array_equal(hi[node, s], vhi[j])
+                maxdepth = max(maxdepth, depth + 1)
+            else:
+                # the slot box is the exact union of the child's two slots
+                cl = np.minimum(lo[c, 0], lo[c, 1]) if child[c, 1] != -2 ** 31 else lo[c, 0]
+                ch = np.maximum(hi[c, 0], hi[c, 1]) if child[c, 1] != -2 ** 31 else hi[c, 0]
+                assert np.array_equal(lo[node, s], cl) and np.array_equal(hi[node, s], ch)
+                stack.append((c, depth + 1))
+    assert np.all(seen_leaf == 1)
+    assert np.all(seen_node == 1)
+    info = ax.arborx_bvh_info(tree)
+    assert info["height"] == maxdepth
+    return child, lo, hi
+
+
+def test_tree_invariants_and_repeatable_builds():
+    cfg = inputs.config_small(n=30_000, m=10)
+    data = cfg["data"]
+    d = dev(data)
+    t0 = ax.arborx_bvh_build(d)
+    c0, l0, h0 = _tree_invariants(t0, data)
+    info = ax.arborx_bvh_info(t0)
+    assert info["n"] == 30_000 and info["dim"] == 3
+    assert np.array_equal(np.float32(info["lo"]), data.min(0)) and np.array_equal(np.float32(info["hi"]), data.max(0))
+    for _ in range(20):  # the hierarchy is a deterministic function of the input; races would show
+        t = ax.arborx_bvh_build(d)
+        c, l, h, _r = ax.arborx_debug_tree_nodes(t)
+        assert np.array_equal(c, c0) and np.array_equal(l, l0) and np.array_equal(h, h0)
+
+
+def test_tree_invariants_duplicates_and_boxes():
+    g = np.random.default_rng(1)
+    data = g.random((3000, 3)).astype(np.float32)
+    data[1000:2500] = data[7]  # long run of equal Morton codes
+    _tree_invariants(ax.arborx_bvh_build(dev(data)), data)
+    c = g.random((2000, 3)).astype(np.float32)
+    h = (g.random((2000, 3)) * 0.02).astype(np.float32)
+    boxes = np.ascontiguousarray(np.stack([c - h, c + h], axis=1))
+    _tree_invariants(ax.arborx_bvh_build(dev(boxes), ax.BOXES), boxes, oracle.BOXES)
+
+
+# ---------------------------------------------------------------------------
+# parity with the oracle
+# ---------------------------------------------------------------------------
+
+def test_small_cube_all_queries():
+    cfg = inputs.config_small()
+    data, q, r = cfg["data"], cfg["queries"], cfg["radius"]
+    tree = ax.arborx_bvh_build(dev(data))
+    off = check_spatial(tree, data, q, r)
+    assert off[-1] > 9 * len(q)
+    check_knn(tree, data, q, cfg["k"])
+    check_reduce(tree, data, q, r)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 8, 16, 17, 64])
+def test_knn_k_values(k):
+    cfg = inputs.config_small(n=5000, m=3000)
+    tree = ax.arborx_bvh_build(dev(cfg["data"]))
+    check_knn(tree, cfg["data"], cfg["queries"], k)
+
+
+def test_shell_and_gmm6():
+    s = inputs.config_paper("shell", n=40_000, m=5000)
+    t = ax.arborx_bvh_build(dev(s["data"]))
+    check_spatial(t, s["data"], s["queries"], inputs.radius_shell(40_000, 10.0))
+    check_knn(t, s["data"], s["queries"], 16)
+    g = inputs.config_gmm6(n=30_000, m=4000)
+    r6 = inputs.radius_gmm(30_000, 20.0)
+    t6 = ax.arborx_bvh_build(dev(g["data"]))
+    check_spatial(t6, g["data"], g["queries"], r6, dim=6)
+    check_knn(t6, g["data"], g["queries"], 8, dim=6)
+    check_reduce(t6, g["data"], g["queries"], r6, dim=6)
+
+
+def test_dim2():
+    g = np.random.default_rng(2)
+    data = g.random((7000, 2)).astype(np.float32)
+    q = g.random((900, 2)).astype(np.float32)
+    t = ax.arborx_bvh_build(dev(data))
+    check_spatial(t, data, q, 0.02, dim=2)
+    check_knn(t, data, q, 5, dim=2)
+
+
+def test_box_values_and_intersects():
+    g = np.random.default_rng(3)
+    c = g.random((6000, 3)).astype(np.float32)
+    h = (g.random((6000, 3)) * 0.01).astype(np.float32)
+    boxes = np.ascontiguousarray(np.stack([c - h, c + h], axis=1))
+    q = g.random((2000, 3)).astype(np.float32)
+    t = ax.arborx_bvh_build(dev(boxes), ax.BOXES)
+    check_spatial(t, boxes, q, 0.03, kind=oracle.BOXES)
+    check_knn(t, boxes, q, 10, kind=oracle.BOXES)
+    check_reduce(t, boxes, q, 0.03, kind=oracle.BOXES)
+    qc = g.random((1500, 3)).astype(np.float32)
+    qh = (g.random((1500, 3)) * 0.03).astype(np.float32)
+    qb = np.ascontiguousarray(np.stack([qc - qh, qc + qh], axis=1))
+    off, idx = ax.arborx_query_intersects(t, dev(qb))
+    o_off, o_idx = oracle.intersects(boxes, qb, kind=oracle.BOXES)
+    assert np.array_equal(host(off), o_off) and np.array_equal(host(idx), o_idx)
+    tp = ax.arborx_bvh_build(dev(c))
+    off, idx = ax.arborx_query_intersects(tp, dev(qb))
+    o_off, o_idx = oracle.intersects(c, qb)
+    assert np.array_equal(host(off), o_off) and np.array_equal(host(idx), o_idx)
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+
+def test_empty_tree_and_empty_queries():
+    q = np.random.default_rng(0).random((50, 3)).astype(np.float32)
+    t = ax.arborx_bvh_build(torch.zeros((0, 3), dtype=torch.float32, device="cuda"))
+    info = ax.arborx_bvh_info(t)
+    assert info["empty"] and info["n"] == 0
+    off, idx = ax.arborx_query_spatial(t, dev(q), 1.0)
+    assert np.all(host(off) == 0) and idx.numel() == 0
+    d2, ix = ax.arborx_query_knn(t, dev(q), 4)
+    assert np.all(np.isinf(host(d2))) and np.all(host(ix) == -1)
+    c, s = ax.arborx_query_spatial_reduce(t, dev(q), 1.0)
+    assert np.all(host(c) == 0) and np.all(host(s) == 0)
+    data = q[:10]
+    t2 = ax.arborx_bvh_build(dev(data))
+    e = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
+    off, idx = ax.arborx_query_spatial(t2, e, 1.0)
+    assert host(off).tolist() == [0] and idx.numel() == 0
+    d2, ix = ax.arborx_query_knn(t2, e, 3)
+    assert d2.shape == (0, 3)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 64, 65])
+def test_tiny_trees(n):
+    g = np.random.default_rng(n)
+    data = g.random((n, 3)).astype(np.float32)
+    q = g.random((300, 3)).astype(np.float32)
+    t = ax.arborx_bvh_build(dev(data))
+    check_spatial(t, data, q, 0.5)
+    check_knn(t, data, q, 4)
+    check_reduce(t, data, q, 0.5)
+    check_spatial(t, data, q, float("inf"))
+
+
+def test_all_equal_points_and_zero_radius():
+    data = np.tile(np.float32([0.3, 0.6, 0.9]), (5000, 1))
+    data[::10] += np.float32(1e-3)
+    q = np.concatenate([data[:5], np.random.default_rng(1).random((20, 3)).astype(np.float32)])
+    t = ax.arborx_bvh_build(dev(data))
+    check_spatial(t, data, q, 0.0)  # exact duplicates only
+    check_knn(t, data, q, 12)       # all ties: smallest indices first
+    check_spatial(t, data, q, 1e-3)
+
+
+def test_infinite_radius_long_rows():
+    g = np.random.default_rng(4)
+    data = g.random((9000, 3)).astype(np.float32)
+    q = g.random((40, 3)).astype(np.float32)
+    t = ax.arborx_bvh_build(dev(data))
+    off = check_spatial(t, data, q, float("inf"))
+    assert off[-1] == 9000 * 40
+    check_spatial(t, data, q, 0.35)  # rows of a few thousand: workgroup sort
+
+
+def test_denormal_distances():
+    data = np.array([[0, 0, 0], [1e-20, 0, 0], [0, 3e-20, 0], [1, 1, 1]], dtype=np.float32)
+    q = np.array([[0, 0, 0], [1e-20, 1e-20, 0]], dtype=np.float32)
+    t = ax.arborx_bvh_build(dev(data))
+    check_knn(t, data, q, 4)
+    check_spatial(t, data, q, 2e-20)
+    check_reduce(t, data, q, 2e-20)
+
+
+def test_capacity_protocol():
+    cfg = inputs.config_small(n=2000, m=500)
+    t = ax.arborx_bvh_build(dev(cfg["data"]))
+    import ctypes
+    from paper_2507_23700_amd import _lib
+    q = dev(cfg["queries"])
+    off = torch.empty(501, dtype=torch.int64, device="cuda")
+    total = ctypes.c_int64()
+    st = _lib.lib().arborx_query_spatial(t.handle, ctypes.c_void_p(q.data_ptr()), 500, ctypes.c_float(cfg["radius"]),
+                                         ctypes.c_void_p(off.data_ptr()), None, 0, ctypes.byref(total), None)
+    assert st == ax.E_CAPACITY
+    o_off, _ = oracle.spatial(cfg["data"], cfg["queries"], cfg["radius"])
+    assert total.value == o_off[-1] and np.array_equal(host(off), o_off)
+
+
+@pytest.mark.parametrize("block,order,stack", [(64, 1, 1), (128, 0, 2), (256, 1, 4), (256, 0, 64), (64, 0, 16)])
+def test_schedules_identical(block, order, stack):
+    cfg = inputs.config_small(n=20_000, m=4000)
+    data, q, r = cfg["data"], cfg["queries"], cfg["radius"]
+    t = ax.arborx_bvh_build(dev(data))
+    ax.arborx_set_tuning(block=block, order=order, stack=stack)
+    try:
+        check_spatial(t, data, q, r)
+        check_knn(t, data, q, 10)
+        check_reduce(t, data, q, r)
+    finally:
+        ax.arborx_reset_tuning()
+
+
+def test_stream_argument():
+    cfg = inputs.config_small(n=3000, m=700)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        d = dev(cfg["data"])
+        q = dev(cfg["queries"])
+        t = ax.arborx_bvh_build(d, stream=s)
+        d2, ix = ax.arborx_query_knn(t, q, 7, stream=s)
+    s.synchronize()
+    o_d2, o_ix = oracle.knn(cfg["data"], cfg["queries"], 7)
+    assert np.array_equal(host(ix), o_ix)
