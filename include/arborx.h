@@ -68,6 +68,8 @@ typedef struct arborx_tuning {
     int32_t order;        /* 1 = sort queries along the Morton curve before traversal, 0 = input order */
     int32_t stack;        /* LDS short-stack entries per thread: 4..64 (0 = default); deeper trees spill */
     int32_t schedule;     /* 0 = thread per query; 1 = wavefront packet (64 queries share node fetches) */
+    int32_t build;        /* hierarchy handoff: 0 = chunked (LDS inside chunks), 1 = single pass (device scope);
+                             both give the identical tree */
 } arborx_tuning;
 
 /* Library version string, e.g. "arborx355 0.1". [host] */

@@ -62,8 +62,8 @@ def version() -> str:
     return _lib.lib().arborx_version().decode()
 
 
-def arborx_set_tuning(block=0, order=1, stack=0, schedule=0) -> None:
-    t = _lib.Tuning(block, order, stack, schedule)
+def arborx_set_tuning(block=0, order=1, stack=0, schedule=0, build=0) -> None:
+    t = _lib.Tuning(block, order, stack, schedule, build)
     _check(_lib.lib().arborx_set_tuning(ctypes.byref(t)))
 
 
@@ -74,7 +74,7 @@ def arborx_reset_tuning() -> None:
 def arborx_get_tuning() -> dict:
     t = _lib.Tuning()
     _check(_lib.lib().arborx_get_tuning(ctypes.byref(t)))
-    return dict(block=t.block, order=t.order, stack=t.stack, schedule=t.schedule)
+    return dict(block=t.block, order=t.order, stack=t.stack, schedule=t.schedule, build=t.build)
 
 
 class Tree:

@@ -38,7 +38,7 @@ _lib = None
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("block", I32), ("order", I32), ("stack", I32), ("schedule", I32)]
+    _fields_ = [("block", I32), ("order", I32), ("stack", I32), ("schedule", I32), ("build", I32)]
 
 
 def header_symbols() -> list[str]:

@@ -235,6 +235,288 @@ __global__ __launch_bounds__(kBuildBlock) void hierarchy_kernel(const uint64_t *
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two-phase form of the same climb.  The tree is identical to the single-pass
+// kernel's; only where the arrival handoff happens differs.
+//
+// Phase 1: one workgroup per chunk of C consecutive sorted leaves.  Arrivals at
+// splits p with both neighbours inside the chunk (cs <= p <= ce-2) hand off
+// through LDS: flags and the two child slots of each local split live in
+// shared memory, so the exchange needs only workgroup scope.  A split whose
+// second child reaches outside the chunk gets a single arrival here; its slot
+// and arrival word are written to global memory at the end ("pending").  A
+// climb that reaches split cs-1 or ce-1 (the chunk's borders) stops and is
+// recorded as one of at most two escapes of the chunk.
+// Phase 2: one thread per escape continues the climb over the splits whose
+// subtrees span chunks, handing off through global memory with device-scope
+// acquire/release.  Only these few percent of nodes pay for device-wide
+// coherence.
+// ---------------------------------------------------------------------------
+
+template <int D>
+struct Escape {
+    int32_t valid, p, side, l, r, h, ref, pad;
+    float lo[D], hi[D];
+};
+
+constexpr unsigned long long kDone = ~0ull;
+
+__device__ __forceinline__ unsigned long long arrival_word(int side, int h, int bound)
+{
+    return ((unsigned long long)side << 48) | ((unsigned long long)(uint32_t)(h + 1) << 32) | (uint32_t)bound;
+}
+
+template <int D>
+__device__ __forceinline__ void store_node(Node<D> *dst, const Node<D> &nd)
+{
+    float4 *d4 = reinterpret_cast<float4 *>(dst);
+    const float4 *s4 = reinterpret_cast<const float4 *>(&nd);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(Node<D>) / 16); ++k)
+        d4[k] = s4[k];
+}
+
+template <int D>
+__device__ __forceinline__ void load_value_box(const float *values, int kind, uint32_t id, float *lo, float *hi)
+{
+    if (kind == ARBORX_BOXES) {
+        const float *v = values + (int64_t)id * 2 * D;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            lo[d] = v[d];
+            hi[d] = v[D + d];
+        }
+    } else {
+        const float *v = values + (int64_t)id * D;
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            lo[d] = hi[d] = v[d];
+    }
+}
+
+template <int D>
+__device__ void write_single_leaf_tree(Node<D> *nodes, TreeHeader *hdr, const float *lo, const float *hi,
+                                       int32_t ref)
+{
+    Node<D> nd;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        nd.lo[0][d] = lo[d];
+        nd.hi[0][d] = hi[d];
+        nd.lo[1][d] = INFINITY;
+        nd.hi[1][d] = -INFINITY;
+    }
+    nd.child[0] = ref;
+    nd.child[1] = kEmptyRef;
+    nd.range_l = 0;
+    nd.range_r = 0;
+    store_node(nodes, nd);
+    hdr->root = 0;
+    hdr->height = 1;
+}
+
+template <int D> constexpr int chunk_leaves() { return D <= 3 ? 1024 : 512; }
+
+template <int D>
+__global__ __launch_bounds__(kBuildBlock) void hierarchy_chunk_kernel(const uint64_t *__restrict__ codes,
+                                                                      const uint32_t *__restrict__ ids,
+                                                                      const float *__restrict__ values, int kind,
+                                                                      int n, Node<D> *__restrict__ nodes,
+                                                                      unsigned long long *__restrict__ gflags,
+                                                                      Escape<D> *__restrict__ escapes,
+                                                                      TreeHeader *hdr)
+{
+    constexpr int C = chunk_leaves<D>();
+    __shared__ uint64_t s_key[C + 1];             // split keys of splits cs-1 .. ce-1
+    __shared__ unsigned long long s_flag[C];      // arrival words of local splits cs .. ce-2
+    __shared__ float s_lo[C][2][D], s_hi[C][2][D];  // both child slots of each local split
+    __shared__ int32_t s_ref[C][2];
+
+    const int cs = blockIdx.x * C;
+    const int ce = min(n, cs + C);
+    const int tid = threadIdx.x;
+    if (n == 1) {
+        if (tid == 0) {
+            float lo[D], hi[D];
+            load_value_box<D>(values, kind, ids[0], lo, hi);
+            write_single_leaf_tree<D>(nodes, hdr, lo, hi, ~(int32_t)ids[0]);
+        }
+        return;
+    }
+    for (int j = tid; j < C; j += kBuildBlock)
+        s_flag[j] = 0;
+    for (int j = tid; j <= C; j += kBuildBlock) {
+        const int g = cs - 1 + j;
+        s_key[j] = (g >= 0 && g <= ce - 1 && g <= n - 2) ? split_key(codes, g) : 0ull;
+    }
+    for (int j = cs + tid; j < ce && j <= n - 2; j += kBuildBlock)
+        gflags[j] = 0;
+    if (tid < 2)
+        escapes[2 * blockIdx.x + tid].valid = 0;
+    __syncthreads();
+
+    for (int i = cs + tid; i < ce; i += kBuildBlock) {
+        const uint32_t id = ids[i];
+        if (id >= (uint32_t)n)
+            continue;
+        float lo[D], hi[D];
+        load_value_box<D>(values, kind, id, lo, hi);
+        int32_t ref = ~(int32_t)id;
+        int l = i, r = i, h = 0;
+        while (true) {
+            int p, side;
+            if (l == 0 || (r != n - 1 && s_key[r - cs + 1] < s_key[l - 1 - cs + 1])) {
+                p = r;
+                side = 0;
+            } else {
+                p = l - 1;
+                side = 1;
+            }
+            if (p < cs || p > ce - 2) {  // a border split of the chunk: continue in phase 2
+                Escape<D> &e = escapes[2 * blockIdx.x + (p >= cs ? 1 : 0)];
+                e.p = p;
+                e.side = side;
+                e.l = l;
+                e.r = r;
+                e.h = h;
+                e.ref = ref;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    e.lo[d] = lo[d];
+                    e.hi[d] = hi[d];
+                }
+                e.valid = 1;
+                break;
+            }
+            const int lp = p - cs;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                s_lo[lp][side][d] = lo[d];
+                s_hi[lp][side][d] = hi[d];
+            }
+            s_ref[lp][side] = ref;
+            const unsigned long long other = __hip_atomic_exchange(
+                &s_flag[lp], arrival_word(side, h, side == 0 ? l : r), __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (other == 0)
+                break;  // first arrival
+            const int os = 1 - side;
+            const int oh = (int)((other >> 32) & 0xffff) - 1;
+            const int ob = (int)(uint32_t)other;
+            Node<D> nd;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const float slo = s_lo[lp][os][d], shi = s_hi[lp][os][d];
+                nd.lo[0][d] = side == 0 ? lo[d] : slo;
+                nd.hi[0][d] = side == 0 ? hi[d] : shi;
+                nd.lo[1][d] = side == 0 ? slo : lo[d];
+                nd.hi[1][d] = side == 0 ? shi : hi[d];
+                lo[d] = fminf(lo[d], slo);
+                hi[d] = fmaxf(hi[d], shi);
+            }
+            const int32_t sref = s_ref[lp][os];
+            nd.child[0] = side == 0 ? ref : sref;
+            nd.child[1] = side == 0 ? sref : ref;
+            if (side == 0)
+                r = ob;
+            else
+                l = ob;
+            h = (h > oh ? h : oh) + 1;
+            nd.range_l = l;
+            nd.range_r = r;
+            store_node(nodes + p, nd);
+            s_flag[lp] = kDone;
+            ref = p;
+            if (l == 0 && r == n - 1) {
+                hdr->root = p;
+                hdr->height = h;
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    // splits with a single arrival: publish that child's slot for phase 2
+    for (int lp = tid; lp <= ce - 2 - cs; lp += kBuildBlock) {
+        const unsigned long long w = s_flag[lp];
+        if (w != 0 && w != kDone) {
+            const int side = (int)(w >> 48);
+            Node<D> *np = nodes + cs + lp;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                np->lo[side][d] = s_lo[lp][side][d];
+                np->hi[side][d] = s_hi[lp][side][d];
+            }
+            np->child[side] = s_ref[lp][side];
+            gflags[cs + lp] = w;
+        }
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBuildBlock) void hierarchy_top_kernel(const uint64_t *__restrict__ codes, int n,
+                                                                    Node<D> *nodes, unsigned long long *gflags,
+                                                                    const Escape<D> *__restrict__ escapes,
+                                                                    int n_escapes, TreeHeader *hdr)
+{
+    const int e_i = blockIdx.x * kBuildBlock + threadIdx.x;
+    if (e_i >= n_escapes)
+        return;
+    const Escape<D> &e = escapes[e_i];
+    if (!e.valid)
+        return;
+    float lo[D], hi[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = e.lo[d];
+        hi[d] = e.hi[d];
+    }
+    int p = e.p, side = e.side, l = e.l, r = e.r, h = e.h;
+    int32_t ref = e.ref;
+    // a climb visits at most n-1 splits
+    for (int guard = 0; guard < n; ++guard) {
+        if (p < 0 || p > n - 2)
+            return;
+        Node<D> *np = nodes + p;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            np->lo[side][d] = lo[d];
+            np->hi[side][d] = hi[d];
+        }
+        np->child[side] = ref;
+        const unsigned long long other = __hip_atomic_exchange(
+            gflags + p, arrival_word(side, h, side == 0 ? l : r), __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (other == 0)
+            return;
+        const int oh = (int)((other >> 32) & 0xffff) - 1;
+        const int ob = (int)(uint32_t)other;
+        if (side == 0)
+            r = ob;
+        else
+            l = ob;
+        h = (h > oh ? h : oh) + 1;
+        const int os = 1 - side;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            lo[d] = fminf(lo[d], np->lo[os][d]);
+            hi[d] = fmaxf(hi[d], np->hi[os][d]);
+        }
+        np->range_l = l;
+        np->range_r = r;
+        ref = p;
+        if (l == 0 && r == n - 1) {
+            hdr->root = p;
+            hdr->height = h;
+            return;
+        }
+        if (l == 0 || (r != n - 1 && split_key(codes, r) < split_key(codes, l - 1))) {
+            p = r;
+            side = 0;
+        } else {
+            p = l - 1;
+            side = 1;
+        }
+    }
+}
+
 __global__ void empty_header(TreeHeader *hdr, int dim)
 {
     hdr->root = -1;
@@ -301,12 +583,26 @@ arborx_status build_impl(const float *values, int64_t n, int kind, TreeDev &t, h
         codes = codes2;
         ids = ids2;
     }
-    fill_kernel<unsigned long long><<<grid_for(nn, 256, 65536), 256, 0, s>>>(flags, nn, 0ull);
-    {
+    Node<D> *nodes = static_cast<Node<D> *>(t.nodes);
+    if (tuning().build == 1) {
+        // single pass: every handoff through device-scope acquire/release
+        fill_kernel<unsigned long long><<<grid_for(nn, 256, 65536), 256, 0, s>>>(flags, nn, 0ull);
         ProfScope ps("build_hierarchy", s);
-        hierarchy_kernel<D><<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(codes, ids, values, kind, (int)n,
-                                                                             static_cast<Node<D> *>(t.nodes), flags,
-                                                                             t.hdr);
+        hierarchy_kernel<D><<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(codes, ids, values, kind, (int)n, nodes,
+                                                                             flags, t.hdr);
+    } else {
+        constexpr int C = chunk_leaves<D>();
+        const int chunks = (int)((n + C - 1) / C);
+        Escape<D> *esc;
+        if ((st = tmp.get(&esc, (size_t)2 * chunks)) != ARBORX_OK)
+            return st;
+        ProfScope ps("build_hierarchy", s);
+        hierarchy_chunk_kernel<D><<<chunks, kBuildBlock, 0, s>>>(codes, ids, values, kind, (int)n, nodes, flags, esc,
+                                                                 t.hdr);
+        if (chunks > 1)
+            hierarchy_top_kernel<D><<<grid_for(2 * chunks, kBuildBlock), kBuildBlock, 0, s>>>(codes, (int)n, nodes,
+                                                                                            flags, esc, 2 * chunks,
+                                                                                            t.hdr);
     }
     AX_HIP(hipGetLastError());
     return ARBORX_OK;

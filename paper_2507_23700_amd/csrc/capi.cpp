@@ -148,6 +148,9 @@ arborx_status arborx_set_tuning(const arborx_tuning *t)
     if (t->schedule != 0)
         return fail(ARBORX_E_UNSUPPORTED, "only the thread-per-query schedule is available");
     n.schedule = t->schedule;
+    if (t->build != 0 && t->build != 1)
+        return fail(ARBORX_E_INVALID, "build must be 0 or 1");
+    n.build = t->build;
     g_tuning = n;
     return ARBORX_OK;
 }
@@ -160,6 +163,7 @@ arborx_status arborx_get_tuning(arborx_tuning *t)
     t->order = g_tuning.order;
     t->stack = g_tuning.stack;
     t->schedule = g_tuning.schedule;
+    t->build = g_tuning.build;
     return ARBORX_OK;
 }
 

@@ -37,6 +37,7 @@ struct Tuning {
     int order = 1;
     int stack = 16;
     int schedule = 0;
+    int build = 0;
 };
 const Tuning &tuning();
 

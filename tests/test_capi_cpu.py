@@ -73,16 +73,17 @@ def test_query_argument_validation():
 
 
 def test_tuning_validation_and_roundtrip():
-    t = _lib.Tuning(128, 0, 8, 0)
+    t = _lib.Tuning(128, 0, 8, 0, 1)
     assert L.arborx_set_tuning(ctypes.byref(t)) == 0
     g = _lib.Tuning()
     assert L.arborx_get_tuning(ctypes.byref(g)) == 0
-    assert (g.block, g.order, g.stack, g.schedule) == (128, 0, 8, 0)
-    assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(100, 1, 0, 0))) == 1
-    assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 12, 0))) == 1
+    assert (g.block, g.order, g.stack, g.schedule, g.build) == (128, 0, 8, 0, 1)
+    assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(100, 1, 0, 0, 0))) == 1
+    assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 0, 0, 2))) == 1
+    assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 12, 0, 0))) == 1
     assert L.arborx_set_tuning(None) == 0
     assert L.arborx_get_tuning(ctypes.byref(g)) == 0
-    assert (g.block, g.order, g.stack) == (256, 1, 16)
+    assert (g.block, g.order, g.stack, g.build) == (256, 1, 16, 0)
 
 
 def test_debug_entry_validation():

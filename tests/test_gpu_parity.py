@@ -167,6 +167,35 @@ def test_tree_invariants_and_repeatable_builds():
         assert np.array_equal(c, c0) and np.array_equal(l, l0) and np.array_equal(h, h0)
 
 
+@pytest.mark.parametrize("n", [1023, 1024, 1025, 70_001])
+def test_chunked_and_single_pass_builds_identical(n):
+    g = np.random.default_rng(n)
+    data = g.random((n, 3)).astype(np.float32)
+    data[n // 3:n // 3 + n // 5] = data[1]  # equal codes across chunk borders
+    d = dev(data)
+    ax.arborx_set_tuning(build=1)
+    try:
+        ref = ax.arborx_debug_tree_nodes(ax.arborx_bvh_build(d))
+    finally:
+        ax.arborx_reset_tuning()
+    t = ax.arborx_bvh_build(d)
+    got = ax.arborx_debug_tree_nodes(t)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+    _tree_invariants(t, data)
+    g6 = g.random((n, 6)).astype(np.float32)
+    d6 = dev(g6)
+    ax.arborx_set_tuning(build=1)
+    try:
+        ref6 = ax.arborx_debug_tree_nodes(ax.arborx_bvh_build(d6))
+    finally:
+        ax.arborx_reset_tuning()
+    t6 = ax.arborx_bvh_build(d6)
+    for a, b in zip(ref6, ax.arborx_debug_tree_nodes(t6)):
+        assert np.array_equal(a, b)
+    _tree_invariants(t6, g6)
+
+
 def test_tree_invariants_duplicates_and_boxes():
     g = np.random.default_rng(1)
     data = g.random((3000, 3)).astype(np.float32)
