@@ -70,6 +70,8 @@ typedef struct arborx_tuning {
     int32_t schedule;     /* 0 = thread per query; 1 = wavefront packet (64 queries share node fetches) */
     int32_t build;        /* hierarchy handoff: 0 = chunked (LDS inside chunks), 1 = single pass (device scope);
                              both give the identical tree */
+    int32_t no_seed;      /* kNN: 0 = start the walk with an upper bound from the 2k leaves nearest in Morton
+                             order (default), 1 = start from +inf */
 } arborx_tuning;
 
 /* Library version string, e.g. "arborx355 0.1". [host] */
@@ -124,6 +126,25 @@ arborx_status arborx_bvh_info(arborx_tree tree, int64_t *n, int32_t *dim, int32_
  */
 arborx_status arborx_query_spatial(arborx_tree tree, const float *queries, int64_t m, float radius, int64_t *offsets,
                                    int32_t *indices, int64_t capacity, int64_t *total, void *stream);
+
+/*
+ * The same radius search in two calls, so that a caller can size `indices`
+ * from the count without a second counting walk:
+ *   arborx_query_spatial_begin  orders the queries, counts the matches, fills
+ *     offsets[m+1] and *total [host], and returns a plan (synchronises);
+ *   arborx_query_finish         writes the indices (capacity >= *total, else
+ *     ARBORX_E_CAPACITY and the plan stays usable); asynchronous;
+ *   arborx_plan_destroy         releases the plan's device memory.
+ * queries and offsets must stay unchanged until the plan is destroyed, and
+ * every call of a plan uses the stream given to begin.
+ */
+typedef struct arborx_plan_s *arborx_plan;
+arborx_status arborx_query_spatial_begin(arborx_tree tree, const float *queries, int64_t m, float radius,
+                                         int64_t *offsets, int64_t *total, arborx_plan *plan, void *stream);
+arborx_status arborx_query_intersects_begin(arborx_tree tree, const float *qboxes, int64_t m, int64_t *offsets,
+                                            int64_t *total, arborx_plan *plan, void *stream);
+arborx_status arborx_query_finish(arborx_plan plan, int32_t *indices, int64_t capacity);
+arborx_status arborx_plan_destroy(arborx_plan plan);
 
 /*
  * Box-overlap search with CSR output (Section 2.1, intersects predicate).

@@ -62,8 +62,8 @@ def version() -> str:
     return _lib.lib().arborx_version().decode()
 
 
-def arborx_set_tuning(block=0, order=1, stack=0, schedule=0, build=0) -> None:
-    t = _lib.Tuning(block, order, stack, schedule, build)
+def arborx_set_tuning(block=0, order=1, stack=0, schedule=0, build=0, no_seed=0) -> None:
+    t = _lib.Tuning(block, order, stack, schedule, build, no_seed)
     _check(_lib.lib().arborx_set_tuning(ctypes.byref(t)))
 
 
@@ -74,7 +74,7 @@ def arborx_reset_tuning() -> None:
 def arborx_get_tuning() -> dict:
     t = _lib.Tuning()
     _check(_lib.lib().arborx_get_tuning(ctypes.byref(t)))
-    return dict(block=t.block, order=t.order, stack=t.stack, schedule=t.schedule, build=t.build)
+    return dict(block=t.block, order=t.order, stack=t.stack, schedule=t.schedule, build=t.build, no_seed=t.no_seed)
 
 
 class Tree:
@@ -83,7 +83,6 @@ class Tree:
     def __init__(self, handle, n, dim, kind, values):
         self.handle, self.n, self.dim, self.kind = handle, n, dim, kind
         self._values = values  # keep the build input alive until the build has run
-        self.last_total = 0
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -131,35 +130,34 @@ def _queries(tree, q, boxes):
     return q
 
 
-def _csr(fn, tree, q, extra, capacity, stream):
+def _csr(begin, tree, q, extra, stream):
+    """Count (begin), size indices exactly, fill (finish), release the plan."""
     torch = _torch()
     m = q.shape[0]
     offsets = torch.empty(m + 1, dtype=torch.int64, device=q.device)
-    cap = max(int(capacity if capacity is not None else tree.last_total), 1)
-    indices = torch.empty(cap, dtype=torch.int32, device=q.device)
     total = ctypes.c_int64()
-    st = fn(tree.handle, _ptr(q), m, *extra, _ptr(offsets), _ptr(indices), cap, ctypes.byref(total), _stream(stream))
-    if st == E_CAPACITY:
-        cap = max(total.value, 1)
-        indices = torch.empty(cap, dtype=torch.int32, device=q.device)
-        st = fn(tree.handle, _ptr(q), m, *extra, _ptr(offsets), _ptr(indices), cap, ctypes.byref(total),
-                _stream(stream))
-    _check(st)
-    tree.last_total = total.value
+    plan = ctypes.c_void_p()
+    L = _lib.lib()
+    _check(begin(tree.handle, _ptr(q), m, *extra, _ptr(offsets), ctypes.byref(total), ctypes.byref(plan),
+                 _stream(stream)))
+    try:
+        indices = torch.empty(max(total.value, 1), dtype=torch.int32, device=q.device)
+        _check(L.arborx_query_finish(plan, _ptr(indices), indices.numel()))
+    finally:
+        L.arborx_plan_destroy(plan)
     return offsets, indices[:total.value]
 
 
-def arborx_query_spatial(tree: Tree, queries, radius: float, capacity=None, stream=None):
+def arborx_query_spatial(tree: Tree, queries, radius: float, stream=None):
     """Radius search: (offsets int64[m+1], indices int32[total]), rows ascending."""
     q = _queries(tree, queries, False)
-    return _csr(lambda h, qp, m, r, *a: _lib.lib().arborx_query_spatial(h, qp, m, r, *a), tree, q,
-                [ctypes.c_float(radius)], capacity, stream)
+    return _csr(_lib.lib().arborx_query_spatial_begin, tree, q, [ctypes.c_float(radius)], stream)
 
 
-def arborx_query_intersects(tree: Tree, qboxes, capacity=None, stream=None):
+def arborx_query_intersects(tree: Tree, qboxes, stream=None):
     """Box-overlap search with [m, 2, dim] query boxes: CSR (offsets, indices)."""
     q = _queries(tree, qboxes, True)
-    return _csr(lambda h, qp, m, *a: _lib.lib().arborx_query_intersects(h, qp, m, *a), tree, q, [], capacity, stream)
+    return _csr(_lib.lib().arborx_query_intersects_begin, tree, q, [], stream)
 
 
 def arborx_query_knn(tree: Tree, queries, k: int, stream=None):

@@ -30,6 +30,10 @@ SIGNATURES = {
     "arborx_debug_radix_sort": (I32, [P, P, I64, I32, I32, I32, P]),
     "arborx_debug_morton64": (I32, [P, I64, I32, P, P, P]),
     "arborx_debug_tree_nodes": (I32, [P, P, P, P, P]),
+    "arborx_query_spatial_begin": (I32, [P, P, I64, F32, P, P, P, P]),
+    "arborx_query_intersects_begin": (I32, [P, P, I64, P, P, P, P]),
+    "arborx_query_finish": (I32, [P, P, I64]),
+    "arborx_plan_destroy": (I32, [P]),
     "arborx_profile_enable": (I32, [I32]),
     "arborx_profile_collect": (I32, [P, P, P, I32, P]),
 }
@@ -38,7 +42,8 @@ _lib = None
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("block", I32), ("order", I32), ("stack", I32), ("schedule", I32), ("build", I32)]
+    _fields_ = [("block", I32), ("order", I32), ("stack", I32), ("schedule", I32), ("build", I32),
+                ("no_seed", I32)]
 
 
 def header_symbols() -> list[str]:

@@ -146,8 +146,8 @@ template <int D>
 __global__ __launch_bounds__(kBuildBlock) void hierarchy_kernel(const uint64_t *__restrict__ codes,
                                                                 const uint32_t *__restrict__ ids,
                                                                 const float *__restrict__ values, int kind, int n,
-                                                                Node<D> *nodes, unsigned long long *flags,
-                                                                TreeHeader *hdr)
+                                                                Node<D> *nodes, float *__restrict__ leaves,
+                                                                unsigned long long *flags, TreeHeader *hdr)
 {
     const int i = blockIdx.x * kBuildBlock + threadIdx.x;
     if (i >= n)
@@ -170,6 +170,7 @@ __global__ __launch_bounds__(kBuildBlock) void hierarchy_kernel(const uint64_t *
             lo[d] = hi[d] = v[d];
     }
     int32_t ref = ~(int32_t)id;
+    store_leaf<D>(leaves, i, kind, lo, hi, (int32_t)id);
     if (n == 1) {
         Node<D> &nd = nodes[0];
 #pragma unroll
@@ -322,6 +323,7 @@ __global__ __launch_bounds__(kBuildBlock) void hierarchy_chunk_kernel(const uint
                                                                       const uint32_t *__restrict__ ids,
                                                                       const float *__restrict__ values, int kind,
                                                                       int n, Node<D> *__restrict__ nodes,
+                                                                      float *__restrict__ leaves,
                                                                       unsigned long long *__restrict__ gflags,
                                                                       Escape<D> *__restrict__ escapes,
                                                                       TreeHeader *hdr)
@@ -339,6 +341,7 @@ __global__ __launch_bounds__(kBuildBlock) void hierarchy_chunk_kernel(const uint
         if (tid == 0) {
             float lo[D], hi[D];
             load_value_box<D>(values, kind, ids[0], lo, hi);
+            store_leaf<D>(leaves, 0, kind, lo, hi, (int32_t)ids[0]);
             write_single_leaf_tree<D>(nodes, hdr, lo, hi, ~(int32_t)ids[0]);
         }
         return;
@@ -361,6 +364,7 @@ __global__ __launch_bounds__(kBuildBlock) void hierarchy_chunk_kernel(const uint
             continue;
         float lo[D], hi[D];
         load_value_box<D>(values, kind, id, lo, hi);
+        store_leaf<D>(leaves, i, kind, lo, hi, (int32_t)id);
         int32_t ref = ~(int32_t)id;
         int l = i, r = i, h = 0;
         while (true) {
@@ -548,6 +552,9 @@ arborx_status build_impl(const float *values, int64_t n, int kind, TreeDev &t, h
     st = dalloc(&t.nodes, (size_t)nn * sizeof(Node<D>), s);
     if (st != ARBORX_OK)
         return st;
+    st = dalloc((void **)&t.leaves, (size_t)n * leaf_floats(D, kind) * sizeof(float), s);
+    if (st != ARBORX_OK)
+        return st;
 
     Temps tmp(s);
     const int pblocks = (int)grid_for(n, kBuildBlock, 1024);
@@ -589,7 +596,7 @@ arborx_status build_impl(const float *values, int64_t n, int kind, TreeDev &t, h
         fill_kernel<unsigned long long><<<grid_for(nn, 256, 65536), 256, 0, s>>>(flags, nn, 0ull);
         ProfScope ps("build_hierarchy", s);
         hierarchy_kernel<D><<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(codes, ids, values, kind, (int)n, nodes,
-                                                                             flags, t.hdr);
+                                                                             t.leaves, flags, t.hdr);
     } else {
         constexpr int C = chunk_leaves<D>();
         const int chunks = (int)((n + C - 1) / C);
@@ -597,8 +604,8 @@ arborx_status build_impl(const float *values, int64_t n, int kind, TreeDev &t, h
         if ((st = tmp.get(&esc, (size_t)2 * chunks)) != ARBORX_OK)
             return st;
         ProfScope ps("build_hierarchy", s);
-        hierarchy_chunk_kernel<D><<<chunks, kBuildBlock, 0, s>>>(codes, ids, values, kind, (int)n, nodes, flags, esc,
-                                                                 t.hdr);
+        hierarchy_chunk_kernel<D><<<chunks, kBuildBlock, 0, s>>>(codes, ids, values, kind, (int)n, nodes, t.leaves,
+                                                                 flags, esc, t.hdr);
         if (chunks > 1)
             hierarchy_top_kernel<D><<<grid_for(2 * chunks, kBuildBlock), kBuildBlock, 0, s>>>(codes, (int)n, nodes,
                                                                                             flags, esc, 2 * chunks,

@@ -14,6 +14,22 @@ struct arborx_tree_s {
     hipEvent_t ready = nullptr;
 };
 
+// State carried from the count call of a CSR query to its fill call.
+struct arborx_plan_s {
+    arborx_tree tree;
+    ax::Pred pred;
+    const float *queries;
+    int64_t m;
+    float radius;
+    int64_t *offsets;
+    hipStream_t stream;
+    ax::Temps tmp;
+    uint32_t *perm = nullptr;
+    int32_t *counts = nullptr, *stash = nullptr, *big_list = nullptr, *huge_list = nullptr;
+    ax::QueryHeader h{};
+    arborx_plan_s(hipStream_t s) : tmp(s) {}
+};
+
 namespace ax {
 
 static thread_local std::string g_error;
@@ -102,6 +118,7 @@ static void release_tree(arborx_tree t)
         (void)hipEventSynchronize(t->ready);
     (void)hipDeviceSynchronize();
     dfree(t->dev.nodes, nullptr);
+    dfree(t->dev.leaves, nullptr);
     dfree(t->dev.hdr, nullptr);
     (void)hipStreamSynchronize(nullptr);
     if (t->ready)
@@ -151,6 +168,9 @@ arborx_status arborx_set_tuning(const arborx_tuning *t)
     if (t->build != 0 && t->build != 1)
         return fail(ARBORX_E_INVALID, "build must be 0 or 1");
     n.build = t->build;
+    if (t->no_seed != 0 && t->no_seed != 1)
+        return fail(ARBORX_E_INVALID, "no_seed must be 0 or 1");
+    n.seed = t->no_seed ? 0 : 1;
     g_tuning = n;
     return ARBORX_OK;
 }
@@ -164,6 +184,7 @@ arborx_status arborx_get_tuning(arborx_tuning *t)
     t->stack = g_tuning.stack;
     t->schedule = g_tuning.schedule;
     t->build = g_tuning.build;
+    t->no_seed = g_tuning.seed ? 0 : 1;
     return ARBORX_OK;
 }
 
@@ -236,22 +257,22 @@ arborx_status arborx_bvh_info(arborx_tree t, int64_t *n, int32_t *dim, int32_t *
     return ARBORX_OK;
 }
 
-static arborx_status csr_query(arborx_tree t, Pred pred, const float *queries, int64_t m, float radius,
-                               int64_t *offsets, int32_t *indices, int64_t capacity, int64_t *total, void *stream)
+static arborx_status csr_begin(arborx_tree t, Pred pred, const float *queries, int64_t m, float radius,
+                               int64_t *offsets, int64_t *total, arborx_plan *out, void *stream)
 {
     arborx_status st = check_tree(t);
     if (st != ARBORX_OK)
         return st;
-    if (m < 0)
-        return fail(ARBORX_E_INVALID, "m must be >= 0");
+    if (!out)
+        return fail(ARBORX_E_INVALID, "plan is NULL");
+    if (m < 0 || m >= INT32_MAX)
+        return fail(ARBORX_E_INVALID, "m must be in [0, 2^31-1)");
     if (m > 0 && !queries)
         return fail(ARBORX_E_INVALID, "queries is NULL");
     if (!offsets)
         return fail(ARBORX_E_INVALID, "offsets is NULL");
     if (!total)
         return fail(ARBORX_E_INVALID, "total is NULL");
-    if (capacity < 0)
-        return fail(ARBORX_E_INVALID, "capacity must be >= 0");
     if (pred == Pred::Sphere && (std::isnan(radius) || radius < 0.0f))
         return fail(ARBORX_E_INVALID, "radius must be >= 0 and not NaN");
     if ((st = check_device()) != ARBORX_OK)
@@ -259,44 +280,107 @@ static arborx_status csr_query(arborx_tree t, Pred pred, const float *queries, i
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((st = wait_tree(t, s)) != ARBORX_OK)
         return st;
-    Temps tmp(s);
+    arborx_plan p = new arborx_plan_s(s);
+    p->tree = t;
+    p->pred = pred;
+    p->queries = queries;
+    p->m = m;
+    p->radius = radius;
+    p->offsets = offsets;
+    p->stream = s;
+    auto bail = [&](arborx_status e) {
+        std::string msg = g_error;
+        delete p;
+        set_error(msg);
+        return e;
+    };
     QueryHeader *qh;
-    int32_t *counts;
     uint8_t *sws;
-    if ((st = tmp.get(&qh, 1)) != ARBORX_OK || (st = tmp.get(&counts, m > 0 ? m : 1)) != ARBORX_OK ||
-        (st = tmp.get(&sws, scan_workspace_bytes(m))) != ARBORX_OK)
-        return st;
-    fill_kernel<unsigned long long><<<1, 64, 0, s>>>(reinterpret_cast<unsigned long long *>(qh),
-                                                     sizeof(QueryHeader) / 8, 0ull);
-    AX_HIP(hipGetLastError());
-    uint32_t *perm = nullptr;
-    if ((st = query_order(t->dev, queries, m, pred, &perm, tmp, s)) != ARBORX_OK)
-        return st;
-    if ((st = spatial_count(t->dev, pred, queries, m, radius, perm, counts, qh, s)) != ARBORX_OK)
-        return st;
+    const int64_t mm = m > 0 ? m : 1;
+    if ((st = p->tmp.get(&qh, 1)) != ARBORX_OK || (st = p->tmp.get(&p->counts, mm)) != ARBORX_OK ||
+        (st = p->tmp.get(&p->stash, mm * kRowSortRegs)) != ARBORX_OK ||
+        (st = p->tmp.get(&p->big_list, mm)) != ARBORX_OK || (st = p->tmp.get(&p->huge_list, mm)) != ARBORX_OK ||
+        (st = p->tmp.get(&sws, scan_workspace_bytes(m))) != ARBORX_OK)
+        return bail(st);
+    if ((st = query_order(t->dev, queries, m, pred, &p->perm, p->tmp, s)) != ARBORX_OK)
+        return bail(st);
+    if ((st = spatial_count(t->dev, pred, queries, m, radius, p->perm, p->counts, p->stash, s)) != ARBORX_OK)
+        return bail(st);
     {
         ProfScope ps("scan", s);
-        AX_HIP(csr_offsets(counts, m, offsets, reinterpret_cast<int64_t *>(&qh->total), sws, s));
+        hipError_t e = csr_offsets_lists(p->counts, m, offsets, p->big_list, p->huge_list, qh, sws, s);
+        if (e != hipSuccess)
+            return bail(hip_fail(e, "csr_offsets_lists"));
     }
-    QueryHeader h;
-    AX_HIP(hipMemcpyAsync(&h, qh, sizeof(h), hipMemcpyDeviceToHost, s));
-    AX_HIP(hipStreamSynchronize(s));
-    *total = (int64_t)h.total;
-    if (!indices || capacity < (int64_t)h.total)
+    hipError_t e = hipMemcpyAsync(&p->h, qh, sizeof(p->h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return bail(hip_fail(e, "reading the match total"));
+    *total = (int64_t)p->h.total;
+    *out = p;
+    return ARBORX_OK;
+}
+
+static arborx_status csr_finish(arborx_plan p, int32_t *indices, int64_t capacity)
+{
+    if (!p)
+        return fail(ARBORX_E_INVALID, "plan is NULL");
+    if (capacity < 0)
+        return fail(ARBORX_E_INVALID, "capacity must be >= 0");
+    if (!indices || capacity < (int64_t)p->h.total)
         return fail(ARBORX_E_CAPACITY, "indices capacity " + std::to_string(capacity) + " < total " +
-                                           std::to_string((long long)h.total));
-    if (h.total == 0)
+                                           std::to_string((long long)p->h.total));
+    if (p->h.total == 0)
         return ARBORX_OK;
-    int64_t *big_list, *huge_list;
-    if ((st = tmp.get(&big_list, h.big_rows + 1)) != ARBORX_OK || (st = tmp.get(&huge_list, h.huge_rows + 1)) != ARBORX_OK)
+    arborx_status st = spatial_fill(p->tree->dev, p->pred, p->queries, p->m, p->radius, p->perm, p->counts, p->stash,
+                                    p->offsets, p->big_list, (int64_t)p->h.big_rows, p->huge_list,
+                                    (int64_t)p->h.huge_rows, indices, p->stream);
+    if (st != ARBORX_OK)
         return st;
-    if ((st = spatial_fill(t->dev, pred, queries, m, radius, perm, offsets, indices, qh, big_list, (int64_t)h.big_rows,
-                           huge_list, (int64_t)h.huge_rows, s)) !=
-        ARBORX_OK)
+    if ((st = sort_big_rows(p->offsets, indices, p->big_list, (int64_t)p->h.big_rows, p->stream)) != ARBORX_OK)
         return st;
-    if ((st = sort_big_rows(offsets, indices, qh, big_list, (int64_t)h.big_rows, s)) != ARBORX_OK)
+    return sort_huge_rows(p->tree->dev.n, p->offsets, indices, p->huge_list, (int64_t)p->h.huge_rows, p->tmp,
+                          p->stream);
+}
+
+static arborx_status csr_query(arborx_tree t, Pred pred, const float *queries, int64_t m, float radius,
+                               int64_t *offsets, int32_t *indices, int64_t capacity, int64_t *total, void *stream)
+{
+    if (capacity < 0)
+        return fail(ARBORX_E_INVALID, "capacity must be >= 0");
+    arborx_plan p = nullptr;
+    arborx_status st = csr_begin(t, pred, queries, m, radius, offsets, total, &p, stream);
+    if (st != ARBORX_OK)
         return st;
-    return sort_huge_rows(t->dev.n, offsets, indices, huge_list, (int64_t)h.huge_rows, tmp, s);
+    st = csr_finish(p, indices, capacity);
+    std::string msg = g_error;
+    delete p;
+    set_error(msg);
+    return st;
+}
+
+arborx_status arborx_query_spatial_begin(arborx_tree t, const float *queries, int64_t m, float radius,
+                                         int64_t *offsets, int64_t *total, arborx_plan *plan, void *stream)
+{
+    return csr_begin(t, Pred::Sphere, queries, m, radius, offsets, total, plan, stream);
+}
+
+arborx_status arborx_query_intersects_begin(arborx_tree t, const float *qboxes, int64_t m, int64_t *offsets,
+                                            int64_t *total, arborx_plan *plan, void *stream)
+{
+    return csr_begin(t, Pred::Box, qboxes, m, 0.0f, offsets, total, plan, stream);
+}
+
+arborx_status arborx_query_finish(arborx_plan plan, int32_t *indices, int64_t capacity)
+{
+    return csr_finish(plan, indices, capacity);
+}
+
+arborx_status arborx_plan_destroy(arborx_plan plan)
+{
+    delete plan;
+    return ARBORX_OK;
 }
 
 arborx_status arborx_query_spatial(arborx_tree t, const float *queries, int64_t m, float radius, int64_t *offsets,

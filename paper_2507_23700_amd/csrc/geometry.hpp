@@ -26,6 +26,50 @@ struct alignas(16) Node {
 static_assert(sizeof(Node<3>) == 64, "3D node is 64 bytes");
 static_assert(sizeof(Node<6>) == 112, "6D node is 112 bytes");
 
+// Leaves in sorted (Morton) order, one record per value: the point (or the
+// box lo and hi rows) followed by the value's input index, padded to 16 bytes.
+// A 3D point leaf is {x, y, z, index}: 16 bytes.
+__host__ __device__ constexpr int leaf_floats(int dim, int kind)
+{
+    return ((kind == 1 ? 2 * dim : dim) + 1 + 3) / 4 * 4;
+}
+
+template <int D>
+__device__ __forceinline__ void store_leaf(float *leaves, int64_t pos, int kind, const float *lo, const float *hi,
+                                           int32_t id)
+{
+    float4 *dst = reinterpret_cast<float4 *>(leaves + pos * leaf_floats(D, kind));
+    if (kind == 1) {
+        constexpr int F = leaf_floats(D, 1);
+        float v[F];
+#pragma unroll
+        for (int k = 0; k < F; ++k)
+            v[k] = 0.0f;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            v[d] = lo[d];
+            v[D + d] = hi[d];
+        }
+        v[2 * D] = __int_as_float(id);
+#pragma unroll
+        for (int k = 0; k < F / 4; ++k)
+            dst[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+    } else {
+        constexpr int F = leaf_floats(D, 0);
+        float v[F];
+#pragma unroll
+        for (int k = 0; k < F; ++k)
+            v[k] = 0.0f;
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            v[d] = lo[d];
+        v[D] = __int_as_float(id);
+#pragma unroll
+        for (int k = 0; k < F / 4; ++k)
+            dst[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+    }
+}
+
 template <int D>
 __device__ __forceinline__ void load_node(const Node<D> *__restrict__ nodes, int32_t i, Node<D> &out)
 {

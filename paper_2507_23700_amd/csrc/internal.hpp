@@ -22,14 +22,12 @@ struct TreeHeader {
     float hi[kMaxDim];
 };
 
-// Device-resident per-call header of a CSR query.
+// Device-resident per-call header of a CSR query, written by the scan.
 struct QueryHeader {
-    unsigned long long total;      // offsets[m], written by the scan
-    unsigned long long big_rows;   // count pass: rows with kRowSortRegs < len <= kRowSortBlock
-    unsigned long long huge_rows;  // count pass: rows with len > kRowSortBlock
-    unsigned long long big_fill;   // fill pass: entries appended to the big-row list
-    unsigned long long huge_fill;  // fill pass: entries appended to the huge-row list
-    unsigned long long pad[3];
+    unsigned long long total;      // offsets[m]
+    unsigned long long big_rows;   // rows with kRowSortRegs < len <= kRowSortBlock
+    unsigned long long huge_rows;  // rows with len > kRowSortBlock
+    unsigned long long pad;
 };
 
 struct Tuning {
@@ -38,6 +36,7 @@ struct Tuning {
     int stack = 16;
     int schedule = 0;
     int build = 0;
+    int seed = 1;  // kNN: bound the walk with nearby leaves first
 };
 const Tuning &tuning();
 
@@ -107,6 +106,11 @@ size_t scan_workspace_bytes(int64_t n);
 // offsets[0..m] = exclusive scan of counts; also writes offsets[m] to *total_dev.
 hipError_t csr_offsets(const int32_t *counts, int64_t m, int64_t *offsets, int64_t *total_dev, void *workspace,
                        hipStream_t s);
+// As csr_offsets, and also lists (in row order) the rows longer than
+// kRowSortRegs (big_list, up to kRowSortBlock) and longer than kRowSortBlock
+// (huge_list); totals go to *qh.  Lists need room for m entries.
+hipError_t csr_offsets_lists(const int32_t *counts, int64_t m, int64_t *offsets, int32_t *big_list,
+                             int32_t *huge_list, QueryHeader *qh, void *workspace, hipStream_t s);
 
 // ---- build (build.hip) ----------------------------------------------------
 struct TreeDev {
@@ -114,6 +118,7 @@ struct TreeDev {
     int dim = 0;
     int kind = 0;
     void *nodes = nullptr;  // Node<dim>[max(n-1, 1)]
+    float *leaves = nullptr; // n leaf records in sorted order (see leaf_floats)
     TreeHeader *hdr = nullptr;
 };
 size_t node_bytes(int dim);
@@ -125,14 +130,18 @@ hipError_t morton64_points(const float *pts, int64_t n, int dim, const float *bo
 enum class Pred { Sphere, Box };
 arborx_status query_order(const TreeDev &t, const float *queries, int64_t m, Pred pred, uint32_t **perm, Temps &tmp,
                           hipStream_t s);
+// Count pass; also stores each query's first kRowSortRegs matches, sorted, in
+// stash[sorted position][kRowSortRegs].
 arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
-                            const uint32_t *perm, int32_t *counts, QueryHeader *qh, hipStream_t s);
+                            const uint32_t *perm, int32_t *counts, int32_t *stash, hipStream_t s);
+// Fill pass: stash rows are copied; listed longer rows are walked again.
 arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
-                           const uint32_t *perm, const int64_t *offsets, int32_t *indices, QueryHeader *qh,
-                           int64_t *big_list, int64_t big_cap, int64_t *huge_list, int64_t huge_cap, hipStream_t s);
-arborx_status sort_big_rows(const int64_t *offsets, int32_t *indices, QueryHeader *qh, const int64_t *big_list,
-                            int64_t nbig, hipStream_t s);
-arborx_status sort_huge_rows(int64_t n_values, const int64_t *offsets, int32_t *indices, const int64_t *huge_list,
+                           const uint32_t *perm, const int32_t *counts, const int32_t *stash,
+                           const int64_t *offsets, const int32_t *big_list, int64_t nbig, const int32_t *huge_list,
+                           int64_t nhuge, int32_t *indices, hipStream_t s);
+arborx_status sort_big_rows(const int64_t *offsets, int32_t *indices, const int32_t *big_list, int64_t nbig,
+                            hipStream_t s);
+arborx_status sort_huge_rows(int64_t n_values, const int64_t *offsets, int32_t *indices, const int32_t *huge_list,
                              int64_t h, Temps &tmp, hipStream_t s);
 arborx_status spatial_reduce(const TreeDev &t, const float *queries, int64_t m, float radius, int op,
                              int scale_bits, const uint32_t *perm, int32_t *counts, int64_t *sums, hipStream_t s);

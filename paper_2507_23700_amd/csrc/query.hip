@@ -141,49 +141,6 @@ __device__ __forceinline__ void traverse_spatial(const Node<D> *__restrict__ nod
     }
 }
 
-// Wavefront-aggregated append of `item` to list[*counter++] for lanes with flag set.
-__device__ __forceinline__ void wave_append(bool flag, int64_t item, unsigned long long *counter, int64_t *list,
-                                            int64_t cap)
-{
-    const uint64_t b = __ballot(flag);
-    if (!b)
-        return;
-    const int leader = __ffsll((unsigned long long)b) - 1;
-    unsigned long long base = 0;
-    if (lane_id() == leader)
-        base = atomicAdd(counter, (unsigned long long)__popcll(b));
-    base = __shfl(base, leader, kWave);
-    const int64_t slot = (int64_t)base + __popcll(b & lanemask_lt());
-    if (flag && list && slot < cap)
-        list[slot] = item;
-}
-
-template <int D, class P>
-__global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
-                                const float *__restrict__ queries, int64_t m, float r2,
-                                const uint32_t *__restrict__ perm, int32_t *__restrict__ counts, QueryHeader *qh,
-                                int stack_cap)
-{
-    extern __shared__ int s_stack[];
-    const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
-    if (t >= m)
-        return;
-    const int64_t qi = perm ? (int64_t)perm[t] : t;
-    if (qi >= m)
-        return;
-    P pred;
-    pred.load(queries, qi, r2);
-    ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap);
-    int c = 0;
-    auto f = [&](int, float) { ++c; };
-    traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
-    counts[qi] = c;
-    if (qh) {
-        wave_append(c > kRowSortRegs && c <= kRowSortBlock, 0, &qh->big_rows, nullptr, 0);
-        wave_append(c > kRowSortBlock, 0, &qh->huge_rows, nullptr, 0);
-    }
-}
-
 // Insert x into the ascending buffer buf[0..k) (k < C) using static indices only.
 template <int C>
 __device__ __forceinline__ void insert_sorted(int (&buf)[C], int k, int x)
@@ -198,14 +155,15 @@ __device__ __forceinline__ void insert_sorted(int (&buf)[C], int k, int x)
     }
 }
 
-// Second walk: write each row at offsets[q].  Rows of up to kRowSortRegs
-// matches come out sorted from registers; longer rows are listed for sorting.
-template <int D, class P>
-__global__ void k_spatial_fill(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
-                               const float *__restrict__ queries, int64_t m, float r2,
-                               const uint32_t *__restrict__ perm, const int64_t *__restrict__ offsets,
-                               int32_t *__restrict__ indices, QueryHeader *qh, int64_t *big_list, int64_t big_cap,
-                               int64_t *huge_list, int64_t huge_cap, int stack_cap)
+// Count pass of a CSR query.  With a stash, each query also keeps its first
+// kRowSortRegs matches sorted in registers and stores them in the stash row of
+// its Morton position (64 contiguous bytes per thread, so a wavefront writes
+// one coalesced 4 KiB block); rows that fit need no second walk.
+template <int D, class P, bool STASH>
+__global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+                                const float *__restrict__ queries, int64_t m, float r2,
+                                const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
+                                int32_t *__restrict__ stash, int stack_cap)
 {
     extern __shared__ int s_stack[];
     const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
@@ -217,35 +175,94 @@ __global__ void k_spatial_fill(const Node<D> *__restrict__ nodes, const TreeHead
     P pred;
     pred.load(queries, qi, r2);
     ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap);
+    int c = 0;
+    if (STASH) {
+        int buf[kRowSortRegs];
+#pragma unroll
+        for (int k = 0; k < kRowSortRegs; ++k)
+            buf[k] = 0;
+        auto f = [&](int idx, float) {
+            if (c < kRowSortRegs)
+                insert_sorted<kRowSortRegs>(buf, c, idx);
+            ++c;
+        };
+        traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
+        int4 *row = reinterpret_cast<int4 *>(stash + t * kRowSortRegs);
+#pragma unroll
+        for (int k = 0; k < kRowSortRegs / 4; ++k)
+            row[k] = make_int4(buf[4 * k], buf[4 * k + 1], buf[4 * k + 2], buf[4 * k + 3]);
+    } else {
+        auto f = [&](int, float) { ++c; };
+        traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
+    }
+    counts[qi] = c;
+}
+
+// Rows of at most kRowSortRegs matches: copy the sorted stash row to the CSR slot.
+__global__ void k_copy_stash(const int32_t *__restrict__ stash, const uint32_t *__restrict__ perm, int64_t m,
+                             const int32_t *__restrict__ counts, const int64_t *__restrict__ offsets,
+                             int32_t *__restrict__ indices)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m)
+        return;
+    const int64_t qi = perm ? (int64_t)perm[t] : t;
+    if (qi >= m)
+        return;
+    const int c = counts[qi];
+    if (c > kRowSortRegs)
+        return;
+    const int4 *row = reinterpret_cast<const int4 *>(stash + t * kRowSortRegs);
+    const int64_t o = offsets[qi];
+    int v[kRowSortRegs];
+#pragma unroll
+    for (int k = 0; k < kRowSortRegs / 4; ++k) {
+        const int4 x = row[k];
+        v[4 * k] = x.x;
+        v[4 * k + 1] = x.y;
+        v[4 * k + 2] = x.z;
+        v[4 * k + 3] = x.w;
+    }
+#pragma unroll
+    for (int k = 0; k < kRowSortRegs; ++k)
+        if (k < c)
+            indices[o + k] = v[k];
+}
+
+// Second walk for listed rows (longer than the stash): matches written in
+// traversal order, sorted afterwards.
+template <int D, class P>
+__global__ void k_spatial_fill_rows(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+                                    const float *__restrict__ queries, int64_t m, float r2,
+                                    const int32_t *__restrict__ rows, int64_t nrows,
+                                    const int64_t *__restrict__ offsets, int32_t *__restrict__ indices, int stack_cap)
+{
+    extern __shared__ int s_stack[];
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nrows)
+        return;
+    const int64_t qi = rows[j];
+    if (qi < 0 || qi >= m)
+        return;
+    P pred;
+    pred.load(queries, qi, r2);
+    ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap);
     const int64_t o = offsets[qi];
     const int64_t len = offsets[qi + 1] - o;
-    int buf[kRowSortRegs];
-#pragma unroll
-    for (int s = 0; s < kRowSortRegs; ++s)
-        buf[s] = 0;
     int64_t k = 0;
     auto f = [&](int idx, float) {
-        if (k < kRowSortRegs)
-            insert_sorted<kRowSortRegs>(buf, (int)k, idx);
-        else if (k < len)
+        if (k < len)
             indices[o + k] = idx;
         ++k;
     };
     traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
-#pragma unroll
-    for (int s = 0; s < kRowSortRegs; ++s)
-        if (s < k && s < len)
-            indices[o + s] = buf[s];
-    wave_append(len > kRowSortRegs && len <= kRowSortBlock, qi, &qh->big_fill, big_list, big_cap);
-    wave_append(len > kRowSortBlock, qi, &qh->huge_fill, huge_list, huge_cap);
 }
 
 // One workgroup per listed row of at most kRowSortBlock entries: bitonic sort in LDS.
 __global__ __launch_bounds__(256) void k_sort_rows(const int64_t *__restrict__ offsets, int32_t *__restrict__ indices,
-                                                   const int64_t *__restrict__ list, int64_t cap, const QueryHeader *qh)
+                                                   const int32_t *__restrict__ list, int64_t nb)
 {
     __shared__ int32_t s[kRowSortBlock];
-    const int64_t nb = min((int64_t)qh->big_fill, cap);
     for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
         const int64_t row = list[b];
         const int64_t o = offsets[row];
@@ -283,7 +300,7 @@ __global__ __launch_bounds__(256) void k_sort_rows(const int64_t *__restrict__ o
 
 // Rows longer than a workgroup can sort: gather as (row rank, index) keys,
 // radix sort, scatter back.
-__global__ void k_huge_lengths(const int64_t *__restrict__ offsets, const int64_t *__restrict__ list, int64_t h,
+__global__ void k_huge_lengths(const int64_t *__restrict__ offsets, const int32_t *__restrict__ list, int64_t h,
                                int32_t *__restrict__ lens)
 {
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < h; b += (int64_t)gridDim.x * blockDim.x)
@@ -291,7 +308,7 @@ __global__ void k_huge_lengths(const int64_t *__restrict__ offsets, const int64_
 }
 
 __global__ void k_huge_gather(const int64_t *__restrict__ offsets, const int32_t *__restrict__ indices,
-                              const int64_t *__restrict__ list, int64_t h, const int64_t *__restrict__ starts,
+                              const int32_t *__restrict__ list, int64_t h, const int64_t *__restrict__ starts,
                               int ib, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals)
 {
     for (int64_t b = blockIdx.x; b < h; b += gridDim.x) {
@@ -304,7 +321,7 @@ __global__ void k_huge_gather(const int64_t *__restrict__ offsets, const int32_t
 }
 
 __global__ void k_huge_scatter(const uint64_t *__restrict__ keys, int64_t total, int ib, int64_t h,
-                               const int64_t *__restrict__ offsets, const int64_t *__restrict__ list,
+                               const int64_t *__restrict__ offsets, const int32_t *__restrict__ list,
                                const int64_t *__restrict__ starts, int32_t *__restrict__ indices)
 {
     const uint64_t lowmask = (1ull << ib) - 1ull;
@@ -372,13 +389,36 @@ __device__ __forceinline__ void knn_offer(float (&bd)[K], int (&bi)[K], float d,
     }
 }
 
+// Squared distance from q to the value stored in leaf record `pos`.
+template <int D>
+__device__ __forceinline__ float leaf_d2(const float *__restrict__ leaves, int kind, int64_t pos, const float *q)
+{
+    const float *lf = leaves + pos * leaf_floats(D, kind);
+    float lo[D], hi[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = lf[d];
+        hi[d] = kind == ARBORX_BOXES ? lf[D + d] : lf[d];
+    }
+    return box_d2<D>(q, lo, hi);
+}
+
 // Nearest-first walk keeping the K best (d2, index) pairs sorted in
 // registers; a subtree is skipped only if its box is strictly farther than the
 // current K-th pair, so equal-distance values with smaller indices are found.
+//
+// Seeding: a greedy descent (nearer child first) finds the query's position in
+// the sorted leaves; the K-th smallest distance among the 2K leaves around it
+// bounds the K-th nearest distance from above, so the walk starts with that
+// bound instead of +inf.  The heap starts as K copies of (bound, INT32_MAX):
+// every value at distance < bound, or == bound, orders before them, so all
+// true results are still admitted and none of the placeholders survive when
+// n >= K.
 template <int D, int K>
-__global__ void k_knn(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
-                      const float *__restrict__ queries, int64_t m, int k_out, const uint32_t *__restrict__ perm,
-                      float *__restrict__ out_d2, int32_t *__restrict__ out_idx, int stack_cap)
+__global__ void k_knn(const Node<D> *__restrict__ nodes, const float *__restrict__ leaves, int kind,
+                      const TreeHeader *__restrict__ hdr, const float *__restrict__ queries, int64_t m, int k_out,
+                      const uint32_t *__restrict__ perm, float *__restrict__ out_d2, int32_t *__restrict__ out_idx,
+                      int stack_cap, int seed)
 {
     extern __shared__ int s_stack[];
     const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
@@ -391,6 +431,8 @@ __global__ void k_knn(const Node<D> *__restrict__ nodes, const TreeHeader *__res
 #pragma unroll
     for (int d = 0; d < D; ++d)
         q[d] = queries[qi * D + d];
+    const int n = hdr->n;
+    const int n_nodes = node_count(hdr);
     float bd[K];
     int bi[K];
 #pragma unroll
@@ -398,9 +440,41 @@ __global__ void k_knn(const Node<D> *__restrict__ nodes, const TreeHeader *__res
         bd[s] = INFINITY;
         bi[s] = INT32_MAX;
     }
+    if (seed && n >= K) {
+        int cur = hdr->root, pos = 0;
+        for (int iter = 0; iter <= n_nodes; ++iter) {
+            if ((unsigned)cur >= (unsigned)n_nodes)
+                break;
+            Node<D> nd;
+            load_node(nodes, cur, nd);
+            const float d0 = box_d2<D>(q, nd.lo[0], nd.hi[0]);
+            const float d1 = box_d2<D>(q, nd.lo[1], nd.hi[1]);
+            const int go = d1 < d0 ? 1 : 0;
+            const int c = go ? nd.child[1] : nd.child[0];
+            if (c < 0) {
+                pos = cur + go;  // node cur separates sorted leaves cur and cur + 1
+                break;
+            }
+            cur = c;
+        }
+        int w0 = pos - K;
+        w0 = w0 < 0 ? 0 : w0;
+        w0 = w0 > n - 2 * K ? n - 2 * K : w0;
+        w0 = w0 < 0 ? 0 : w0;
+        const int w1 = (w0 + 2 * K < n) ? w0 + 2 * K : n;
+        for (int p = w0; p < w1; ++p) {
+            const float d = leaf_d2<D>(leaves, kind, p, q);
+            knn_offer<K>(bd, bi, d, p);  // positions are distinct keys; only the distances matter here
+        }
+        const float bound = bd[K - 1];
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            bd[s] = bound;
+            bi[s] = INT32_MAX;
+        }
+    }
     ShortStack<KnnEntry> st(reinterpret_cast<KnnEntry *>(s_stack) + threadIdx.x, blockDim.x, stack_cap);
     int cur = hdr->root;
-    const int n_nodes = node_count(hdr);
     for (int iter = 0; iter <= n_nodes; ++iter) {
         if ((unsigned)cur >= (unsigned)n_nodes)
             break;
@@ -459,12 +533,16 @@ __global__ void k_knn_empty(int64_t total, float *d2, int32_t *idx)
     }
 }
 
-// 32-bit Morton codes of query centres, normalised by the tree's bounds.
+// Morton codes of query centres on a coarse grid (kOrderBits bits in all),
+// normalised by the tree's bounds.  The order only affects speed: queries in
+// one cell of the grid are treated alike.
+constexpr int kOrderBits = 24;
+
 template <int D, bool BOXQ>
 __global__ void k_query_codes(const float *__restrict__ q, int64_t m, const TreeHeader *__restrict__ hdr,
                               uint32_t *__restrict__ codes, uint32_t *__restrict__ ids)
 {
-    constexpr int bits = 30 / D;
+    constexpr int bits = kOrderBits / D;
     float lo[D], inv[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -516,35 +594,36 @@ Launch traversal_launch(int64_t m, size_t entry_bytes)
 
 template <int D>
 arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m, float r2, const uint32_t *perm,
-                         int32_t *counts, QueryHeader *qh, hipStream_t s)
+                         int32_t *counts, int32_t *stash, hipStream_t s)
 {
     const Launch L = traversal_launch(m, sizeof(int));
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     ProfScope ps("spatial_count", s);
     if (pred == Pred::Sphere)
-        k_spatial_count<D, Sphere<D>><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, counts, qh, L.cap);
+        k_spatial_count<D, Sphere<D>, true><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, counts,
+                                                                           stash, L.cap);
     else
-        k_spatial_count<D, BoxQuery<D>><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, counts, qh,
-                                                                       L.cap);
+        k_spatial_count<D, BoxQuery<D>, true><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, counts,
+                                                                             stash, L.cap);
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
 
 template <int D>
-arborx_status fill_impl(const TreeDev &t, Pred pred, const float *q, int64_t m, float r2, const uint32_t *perm,
-                        const int64_t *offsets, int32_t *indices, QueryHeader *qh, int64_t *big_list,
-                        int64_t big_cap, int64_t *huge_list, int64_t huge_cap, hipStream_t s)
+arborx_status fill_rows_impl(const TreeDev &t, Pred pred, const float *q, int64_t m, float r2, const int32_t *rows,
+                             int64_t nrows, const int64_t *offsets, int32_t *indices, hipStream_t s)
 {
-    const Launch L = traversal_launch(m, sizeof(int));
+    if (nrows <= 0)
+        return ARBORX_OK;
+    Launch L = traversal_launch(nrows, sizeof(int));
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     ProfScope ps("spatial_fill", s);
     if (pred == Pred::Sphere)
-        k_spatial_fill<D, Sphere<D>><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, offsets, indices,
-                                                                    qh, big_list, big_cap, huge_list, huge_cap, L.cap);
+        k_spatial_fill_rows<D, Sphere<D>><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, rows, nrows, offsets,
+                                                                         indices, L.cap);
     else
-        k_spatial_fill<D, BoxQuery<D>><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, offsets,
-                                                                      indices, qh, big_list, big_cap, huge_list,
-                                                                      huge_cap, L.cap);
+        k_spatial_fill_rows<D, BoxQuery<D>><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, rows, nrows,
+                                                                           offsets, indices, L.cap);
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
@@ -572,8 +651,8 @@ arborx_status knn_launch(const TreeDev &t, const float *q, int64_t m, int k, con
 {
     const Launch L = traversal_launch(m, sizeof(KnnEntry));
     ProfScope ps("knn", s);
-    k_knn<D, K><<<L.grid, L.block, L.lds, s>>>(static_cast<const Node<D> *>(t.nodes), t.hdr, q, m, k, perm, d2, idx,
-                                                L.cap);
+    k_knn<D, K><<<L.grid, L.block, L.lds, s>>>(static_cast<const Node<D> *>(t.nodes), t.leaves, t.kind, t.hdr, q, m,
+                                                k, perm, d2, idx, L.cap, tuning().seed);
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
@@ -616,7 +695,7 @@ arborx_status order_impl(const TreeDev &t, const float *q, int64_t m, Pred pred,
     else
         k_query_codes<D, true><<<grid_for(m, 256, 65536), 256, 0, s>>>(q, m, t.hdr, codes, ids);
     bool alt = false;
-    AX_HIP(radix_sort_pairs<uint32_t>(codes, ids, codes2, ids2, m, 0, (30 / D) * D, ws, s, &alt));
+    AX_HIP(radix_sort_pairs<uint32_t>(codes, ids, codes2, ids2, m, 0, (kOrderBits / D) * D, ws, s, &alt));
     *perm = alt ? ids2 : ids;
     return ARBORX_OK;
 }
@@ -641,39 +720,60 @@ arborx_status query_order(const TreeDev &t, const float *queries, int64_t m, Pre
 }
 
 arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
-                            const uint32_t *perm, int32_t *counts, QueryHeader *qh, hipStream_t s)
+                            const uint32_t *perm, int32_t *counts, int32_t *stash, hipStream_t s)
 {
     if (m == 0)
         return ARBORX_OK;
     if (t.n == 0)
         return fill_async<int32_t>(counts, m, 0, s);
     const float r2 = radius * radius;
-    AX_DISPATCH_DIM(t.dim, (count_impl<D>(t, pred, queries, m, r2, perm, counts, qh, s)));
+    AX_DISPATCH_DIM(t.dim, (count_impl<D>(t, pred, queries, m, r2, perm, counts, stash, s)));
 }
 
 arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
-                           const uint32_t *perm, const int64_t *offsets, int32_t *indices, QueryHeader *qh,
-                           int64_t *big_list, int64_t big_cap, int64_t *huge_list, int64_t huge_cap, hipStream_t s)
+                           const uint32_t *perm, const int32_t *counts, const int32_t *stash,
+                           const int64_t *offsets, const int32_t *big_list, int64_t nbig, const int32_t *huge_list,
+                           int64_t nhuge, int32_t *indices, hipStream_t s)
 {
     if (m == 0 || t.n == 0)
         return ARBORX_OK;
+    {
+        ProfScope ps("copy_stash", s);
+        k_copy_stash<<<grid_for(m, 256, INT32_MAX), 256, 0, s>>>(stash, perm, m, counts, offsets, indices);
+        AX_HIP(hipGetLastError());
+    }
     const float r2 = radius * radius;
-    AX_DISPATCH_DIM(t.dim, (fill_impl<D>(t, pred, queries, m, r2, perm, offsets, indices, qh, big_list, big_cap,
-                                         huge_list, huge_cap, s)));
+    arborx_status st = ARBORX_OK;
+    switch (t.dim) {
+    case 2:
+        if ((st = fill_rows_impl<2>(t, pred, queries, m, r2, big_list, nbig, offsets, indices, s)) == ARBORX_OK)
+            st = fill_rows_impl<2>(t, pred, queries, m, r2, huge_list, nhuge, offsets, indices, s);
+        return st;
+    case 3:
+        if ((st = fill_rows_impl<3>(t, pred, queries, m, r2, big_list, nbig, offsets, indices, s)) == ARBORX_OK)
+            st = fill_rows_impl<3>(t, pred, queries, m, r2, huge_list, nhuge, offsets, indices, s);
+        return st;
+    case 6:
+        if ((st = fill_rows_impl<6>(t, pred, queries, m, r2, big_list, nbig, offsets, indices, s)) == ARBORX_OK)
+            st = fill_rows_impl<6>(t, pred, queries, m, r2, huge_list, nhuge, offsets, indices, s);
+        return st;
+    default:
+        return fail(ARBORX_E_UNSUPPORTED, "dimension not compiled in");
+    }
 }
 
-arborx_status sort_big_rows(const int64_t *offsets, int32_t *indices, QueryHeader *qh, const int64_t *big_list,
-                            int64_t nbig, hipStream_t s)
+arborx_status sort_big_rows(const int64_t *offsets, int32_t *indices, const int32_t *big_list, int64_t nbig,
+                            hipStream_t s)
 {
     if (nbig <= 0)
         return ARBORX_OK;
     ProfScope ps("sort_rows", s);
-    k_sort_rows<<<(unsigned)(nbig < 8192 ? nbig : 8192), 256, 0, s>>>(offsets, indices, big_list, nbig, qh);
+    k_sort_rows<<<(unsigned)(nbig < 8192 ? nbig : 8192), 256, 0, s>>>(offsets, indices, big_list, nbig);
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
 
-arborx_status sort_huge_rows(int64_t n_values, const int64_t *offsets, int32_t *indices, const int64_t *huge_list,
+arborx_status sort_huge_rows(int64_t n_values, const int64_t *offsets, int32_t *indices, const int32_t *huge_list,
                              int64_t h, Temps &tmp, hipStream_t s)
 {
     if (h <= 0)

@@ -75,6 +75,112 @@ __global__ __launch_bounds__(kScanBlock) void scan_apply(const int32_t *__restri
     }
 }
 
+// CSR offsets plus ordered lists of long rows.  Per tile the scan carries the
+// count sum and a packed pair of flag counts (low 32 bits: rows longer than
+// kRowSortRegs but at most kRowSortBlock; high 32 bits: longer rows), so the
+// row ids of both kinds are compacted in row order without atomics.
+__device__ __forceinline__ int64_t row_flags(int32_t c)
+{
+    return (c > kRowSortRegs && c <= kRowSortBlock) ? 1ll : (c > kRowSortBlock ? (1ll << 32) : 0ll);
+}
+
+__global__ __launch_bounds__(kScanBlock) void csr_tile_sums(const int32_t *__restrict__ counts, int64_t m,
+                                                            int64_t *__restrict__ tile_sums,
+                                                            int64_t *__restrict__ tile_flags)
+{
+    __shared__ int64_t wsum[kScanBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t s = 0, f = 0;
+#pragma unroll 4
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = base + (int64_t)j * kScanBlock + threadIdx.x;
+        if (i < m) {
+            const int32_t c = counts[i];
+            s += c;
+            f += row_flags(c);
+        }
+    }
+    int64_t tot = 0, ftot = 0;
+    block_exclusive_scan<kScanBlock>(s, wsum, &tot);
+    block_exclusive_scan<kScanBlock>(f, wsum, &ftot);
+    if (threadIdx.x == 0) {
+        tile_sums[blockIdx.x] = tot;
+        tile_flags[blockIdx.x] = ftot;
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void csr_tile_prefix(int64_t *__restrict__ tile_sums,
+                                                              int64_t *__restrict__ tile_flags, int64_t tiles,
+                                                              QueryHeader *__restrict__ qh)
+{
+    __shared__ int64_t wsum[kScanBlock / kWave];
+    int64_t carry = 0, fcarry = 0;
+    for (int64_t start = 0; start < tiles; start += kScanBlock) {
+        const int64_t i = start + threadIdx.x;
+        const int64_t x = i < tiles ? tile_sums[i] : 0;
+        const int64_t f = i < tiles ? tile_flags[i] : 0;
+        int64_t chunk = 0, fchunk = 0;
+        const int64_t ex = block_exclusive_scan<kScanBlock>(x, wsum, &chunk);
+        const int64_t fex = block_exclusive_scan<kScanBlock>(f, wsum, &fchunk);
+        if (i < tiles) {
+            tile_sums[i] = carry + ex;
+            tile_flags[i] = fcarry + fex;
+        }
+        carry += chunk;
+        fcarry += fchunk;
+    }
+    if (threadIdx.x == 0) {
+        qh->total = (unsigned long long)carry;
+        qh->big_rows = (unsigned long long)(fcarry & 0xffffffffll);
+        qh->huge_rows = (unsigned long long)(fcarry >> 32);
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void csr_apply(const int32_t *__restrict__ counts, int64_t m,
+                                                        const int64_t *__restrict__ tile_prefix,
+                                                        const int64_t *__restrict__ tile_flags,
+                                                        int64_t *__restrict__ offsets, int32_t *__restrict__ big_list,
+                                                        int32_t *__restrict__ huge_list)
+{
+    __shared__ int64_t wsum[kScanBlock / kWave];
+    const int64_t i0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int32_t c[kScanItems];
+    int64_t s = 0, f = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        c[j] = (i0 + j < m) ? counts[i0 + j] : 0;
+        s += c[j];
+        f += row_flags(c[j]);
+    }
+    int64_t tot = 0, ftot = 0;
+    int64_t run = tile_prefix[blockIdx.x] + block_exclusive_scan<kScanBlock>(s, wsum, &tot);
+    int64_t frun = tile_flags[blockIdx.x] + block_exclusive_scan<kScanBlock>(f, wsum, &ftot);
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = i0 + j;
+        if (i < m) {
+            offsets[i] = run;
+            const int64_t fl = row_flags(c[j]);
+            if (fl == 1)
+                big_list[frun & 0xffffffffll] = (int32_t)i;
+            else if (fl != 0)
+                huge_list[frun >> 32] = (int32_t)i;
+            frun += fl;
+        }
+        run += c[j];
+        if (i == m - 1)
+            offsets[m] = run;
+    }
+}
+
+__global__ void csr_empty(int64_t *offsets, QueryHeader *qh)
+{
+    offsets[0] = 0;
+    qh->total = 0;
+    qh->big_rows = 0;
+    qh->huge_rows = 0;
+}
+
 __global__ void scan_empty(int64_t *offsets, int64_t *total)
 {
     offsets[0] = 0;
@@ -83,7 +189,23 @@ __global__ void scan_empty(int64_t *offsets, int64_t *total)
 
 }  // namespace
 
-size_t scan_workspace_bytes(int64_t m) { return (size_t)((m + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t); }
+size_t scan_workspace_bytes(int64_t m) { return (size_t)2 * ((m + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t); }
+
+hipError_t csr_offsets_lists(const int32_t *counts, int64_t m, int64_t *offsets, int32_t *big_list,
+                             int32_t *huge_list, QueryHeader *qh, void *workspace, hipStream_t s)
+{
+    if (m == 0) {
+        csr_empty<<<1, 1, 0, s>>>(offsets, qh);
+        return hipGetLastError();
+    }
+    const int64_t tiles = (m + kScanTile - 1) / kScanTile;
+    int64_t *tile_sums = static_cast<int64_t *>(workspace);
+    int64_t *tile_flags = tile_sums + tiles + 1;
+    csr_tile_sums<<<(unsigned)tiles, kScanBlock, 0, s>>>(counts, m, tile_sums, tile_flags);
+    csr_tile_prefix<<<1, kScanBlock, 0, s>>>(tile_sums, tile_flags, tiles, qh);
+    csr_apply<<<(unsigned)tiles, kScanBlock, 0, s>>>(counts, m, tile_sums, tile_flags, offsets, big_list, huge_list);
+    return hipGetLastError();
+}
 
 hipError_t csr_offsets(const int32_t *counts, int64_t m, int64_t *offsets, int64_t *total_dev, void *workspace,
                        hipStream_t s)

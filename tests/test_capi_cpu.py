@@ -70,20 +70,25 @@ def test_query_argument_validation():
     assert L.arborx_bvh_info(None, None, None, None, None, None) == 1
     assert L.arborx_debug_tree_nodes(None, FAKE, FAKE, FAKE, FAKE) == 1
     assert L.arborx_bvh_destroy(None) == 0
+    plan = P()
+    assert L.arborx_query_spatial_begin(None, FAKE, 1, f(1), FAKE, ctypes.byref(tot), ctypes.byref(plan), None) == 1
+    assert L.arborx_query_intersects_begin(None, FAKE, 1, FAKE, ctypes.byref(tot), ctypes.byref(plan), None) == 1
+    assert L.arborx_query_finish(None, FAKE, 1) == 1
+    assert L.arborx_plan_destroy(None) == 0
 
 
 def test_tuning_validation_and_roundtrip():
-    t = _lib.Tuning(128, 0, 8, 0, 1)
+    t = _lib.Tuning(128, 0, 8, 0, 1, 1)
     assert L.arborx_set_tuning(ctypes.byref(t)) == 0
     g = _lib.Tuning()
     assert L.arborx_get_tuning(ctypes.byref(g)) == 0
-    assert (g.block, g.order, g.stack, g.schedule, g.build) == (128, 0, 8, 0, 1)
+    assert (g.block, g.order, g.stack, g.schedule, g.build, g.no_seed) == (128, 0, 8, 0, 1, 1)
     assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(100, 1, 0, 0, 0))) == 1
     assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 0, 0, 2))) == 1
     assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 12, 0, 0))) == 1
     assert L.arborx_set_tuning(None) == 0
     assert L.arborx_get_tuning(ctypes.byref(g)) == 0
-    assert (g.block, g.order, g.stack, g.build) == (256, 1, 16, 0)
+    assert (g.block, g.order, g.stack, g.build, g.no_seed) == (256, 1, 16, 0, 0)
 
 
 def test_debug_entry_validation():
