@@ -86,6 +86,79 @@ def traffic_for(kernel, workload):
     return e.get("bytes_per_launch")
 
 
+KERNEL_PHASE = [  # rocprofv3 kernel name fragment -> phase name used by the in-library profiler
+    ("k_knn<", "knn"), ("k_spatial_count<", "spatial_count"), ("k_spatial_reduce<3, false>", "reduce_count"),
+    ("k_spatial_reduce<3, true>", "reduce_sumdist"), ("k_spatial_fill_rows<", "spatial_fill"),
+    ("hierarchy_chunk_kernel<", "build_hierarchy"), ("hierarchy_top_kernel<", "build_hierarchy"),
+    ("k_copy_stash", "copy_stash"), ("radix_scatter<", "radix_scatter"), ("radix_hist<", "radix_hist"),
+]
+
+
+def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, stats_csv, workload, copy_bytes):
+    """Per-phase HBM bytes per launch from rocprofv3 --pmc runs, scaled by what the same
+    counters read for a plain device copy of copy_bytes bytes.  Writes profiles/traffic.json
+    and returns a markdown table."""
+    import collections
+    import csv
+
+    def phase(name):
+        nm = name.replace("(anonymous namespace)::", "")
+        for frag, ph in KERNEL_PHASE:
+            if frag in nm:
+                return ph
+        return None
+
+    def per_dispatch(path, counter):
+        out = collections.defaultdict(float)
+        launches = collections.defaultdict(set)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            ph = phase(r["Kernel_Name"]) or r["Kernel_Name"]
+            out[ph] += float(r["Counter_Value"]) * 1024.0
+            launches[ph].add(r["Dispatch_Id"])
+        return out, launches
+
+    cf, _ = per_dispatch(copy_fetch_csv, "FETCH_SIZE")
+    cw, _ = per_dispatch(copy_write_csv, "WRITE_SIZE")
+    fscale = 3 * copy_bytes / cf["__amd_rocclr_copyBuffer"]
+    wscale = 3 * copy_bytes / cw["__amd_rocclr_copyBuffer"]
+    fetch, fl = per_dispatch(fetch_csv, "FETCH_SIZE")
+    write, wl = per_dispatch(write_csv, "WRITE_SIZE")
+    hit, _ = per_dispatch(write_csv, "TCC_HIT_sum")
+    miss, _ = per_dispatch(write_csv, "TCC_MISS_sum")
+    dur = collections.defaultdict(list)
+    for r in csv.DictReader(open(stats_csv)):
+        ph = phase(r["Name"])
+        if ph:
+            dur[ph].append((float(r["AverageNs"]), int(r["Calls"])))
+    src = source_hash()
+    table = {}
+    lines = [f"| phase | launches | avg ms (kernel trace) | HBM read MB/launch | HBM write MB/launch | L2 hit |",
+             "|---|---|---|---|---|---|"]
+    for ph in sorted(fetch, key=lambda k: -fetch[k]):
+        if ph not in dict(KERNEL_PHASE).values():
+            continue
+        nl = max(len(fl[ph]), 1)
+        rd = fetch[ph] * fscale / nl
+        wr = write.get(ph, 0.0) * wscale / max(len(wl.get(ph, ())), 1)
+        h = hit.get(ph, 0.0) / max(hit.get(ph, 0.0) + miss.get(ph, 0.0), 1e-9)
+        ms = sum(a * c for a, c in dur[ph]) / max(sum(c for _, c in dur[ph]), 1) / 1e6 if dur[ph] else float("nan")
+        table[ph] = {"bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr, "l2_hit": h,
+                     "source_hash": src}
+        lines.append(f"| {ph} | {nl} | {ms:.3f} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | {h:.3f} |")
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    allw = json.load(open(path)) if os.path.exists(path) else {}
+    allw[workload] = table
+    allw["_calibration"] = {"fetch_scale": fscale, "write_scale": wscale, "copy_bytes": copy_bytes}
+    with open(path, "w") as f:
+        json.dump(allw, f, indent=1, sort_keys=True)
+    lines.append("")
+    lines.append(f"Counter scale from a {copy_bytes / 2 ** 30:.0f} GiB device copy: FETCH_SIZE x {fscale:.3f}, "
+                 f"WRITE_SIZE x {wscale:.3f}.  Kernel sources hash {src}.")
+    return "\n".join(lines)
+
+
 def cpu_baseline(data, queries, radius, k, target_s=15.0, max_sample=20000):
     import numpy as np
 
@@ -111,6 +184,104 @@ def cpu_baseline(data, queries, radius, k, target_s=15.0, max_sample=20000):
                        f"against all {len(data)} points; {dt:.1f} s"), sel, res
 
 
+def timed(fn, reps=3):
+    """Median milliseconds of fn() between two device synchronisations."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(1000.0 * (time.perf_counter() - t0))
+    return sorted(ts)[len(ts) // 2]
+
+
+def forest_bench(reps=3):
+    """Batched forest path vs the per-tree loop on the same inputs, with identical outputs."""
+    import torch
+
+    import paper_2507_23700_amd as ax
+    from paper_2507_23700_amd import inputs
+
+    log("generating forest workload (64 trees, 4096 batches)")
+    cfg = inputs.forest()
+    k = cfg["k"]
+    toff, boff, bt, br = cfg["tree_offsets"], cfg["batch_offsets"], cfg["batch_tree"], cfg["batch_radius"]
+    v = torch.from_numpy(cfg["values"]).cuda()
+    q = torch.from_numpy(cfg["queries"]).cuda()
+    dbo, dbt, dbr = (torch.from_numpy(x).cuda() for x in (boff, bt, br))
+    m = q.shape[0]
+    out = {}
+
+    def batched():
+        f = ax.arborx_forest_build(v, toff)
+        c, s = ax.arborx_forest_query_reduce(f, q, dbo, dbt, dbr, ax.COUNT_SUMDIST)
+        d2, ix = ax.arborx_forest_query_knn(f, q, dbo, dbt, k)
+        out["batched"] = (c, s, d2, ix)
+
+    tree_views = [v[toff[t]:toff[t + 1]] for t in range(len(toff) - 1)]
+    q_views = [q[boff[b]:boff[b + 1]] for b in range(len(bt))]
+
+    def plain():
+        trees = [ax.arborx_bvh_build(tv) for tv in tree_views]
+        c = torch.empty(m, dtype=torch.int32, device="cuda")
+        s = torch.empty(m, dtype=torch.int64, device="cuda")
+        d2 = torch.empty((m, k), dtype=torch.float32, device="cuda")
+        ix = torch.empty((m, k), dtype=torch.int32, device="cuda")
+        for b in range(len(bt)):
+            sl = slice(int(boff[b]), int(boff[b + 1]))
+            cb, sb = ax.arborx_query_spatial_reduce(trees[bt[b]], q_views[b], float(br[b]), ax.COUNT_SUMDIST)
+            db, ib = ax.arborx_query_knn(trees[bt[b]], q_views[b], k)
+            c[sl], s[sl], d2[sl], ix[sl] = cb, sb, db, ib
+        out["plain"] = (c, s, d2, ix)
+
+    batched()
+    plain()
+    t_b = timed(batched, reps)
+    t_p = timed(plain, reps)
+    same = all(torch.equal(a, b) for a, b in zip(out["batched"], out["plain"]))
+    log(f"forest: batched {t_b:.1f} ms, per-tree loop {t_p:.1f} ms, identical={same}")
+    res = {"workload": "forest_t64_b4096", "trees": len(toff) - 1, "points": int(toff[-1]), "batches": len(bt),
+           "queries": int(m), "ops": f"build + COUNT_SUMDIST + kNN k={k}", "batched_ms": t_b, "plain_ms": t_p,
+           "speedup": t_p / t_b, "identical": bool(same),
+           "batched_queries_per_s": 2 * m / (t_b * 1e-3)}
+    del out
+    torch.cuda.empty_cache()
+    return res
+
+
+def chamfer_bench(reps=3):
+    """Chamfer forward (forest build + kNN k=1 both ways + loss) and backward on 256 pairs."""
+    import torch
+
+    import paper_2507_23700_amd as ax
+    from paper_2507_23700_amd import inputs
+
+    log("generating Chamfer workload (256 pairs)")
+    cfg = inputs.chamfer_pairs()
+    a = torch.from_numpy(cfg["a"]).cuda()
+    b = torch.from_numpy(cfg["b"]).cuda()
+    ao, bo = cfg["a_off"], cfg["b_off"]
+    P = len(ao) - 1
+    g = torch.ones(P, dtype=torch.float32, device="cuda")
+    st = {}
+
+    def fwd():
+        st["f"] = ax.arborx_chamfer_forward(a, ao, b, bo)
+
+    def bwd():
+        _, nab, nba = st["f"]
+        ax.arborx_chamfer_backward(a, ao, b, bo, nab, nba, g)
+
+    fwd()
+    t_f = timed(fwd, reps)
+    t_b = timed(bwd, reps)
+    pts = int(ao[-1] + bo[-1])
+    return {"workload": f"chamfer_p{P}", "pairs": P, "points": pts, "forward_ms": t_f, "backward_ms": t_b,
+            "pairs_per_s": P / ((t_f + t_b) * 1e-3), "points_per_s": pts / ((t_f + t_b) * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,7 +291,27 @@ def main():
     ap.add_argument("--dist", default="cube", choices=["cube", "shell"])
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-forest", action="store_true", help="skip the batched-vs-plain forest comparison")
+    ap.add_argument("--no-chamfer", action="store_true", help="skip the Chamfer timing")
+    ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device copy of GIB gibibytes (counter calibration) and exit")
+    ap.add_argument("--summarize-counters", nargs=5, metavar=("FETCH", "WRITE", "COPYFETCH", "COPYWRITE", "STATS"),
+                    help="turn rocprofv3 counter CSVs into profiles/traffic.json and print a markdown table")
     args = ap.parse_args()
+    if args.summarize_counters:
+        print(summarize_counters(*args.summarize_counters, workload=f"{args.dist}3d_n{args.n}_m{args.n}",
+                                 copy_bytes=2 ** 30))
+        return
+    if args.calibrate_copy > 0:
+        import torch
+        nbytes = int(args.calibrate_copy * 2 ** 30)
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "launches": 3}))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -221,6 +412,11 @@ def main():
         parity = f"{'exact' if ok else 'MISMATCH'} on {len(sel)} sampled queries"
         log(f"parity: {parity}")
 
+    state.clear()
+    torch.cuda.empty_cache()
+    forest = None if args.no_forest else forest_bench()
+    chamfer = None if args.no_chamfer else chamfer_bench()
+
     line = {
         "metric": "radius/kNN queries/s at 10M 3D pts; BVH build Mpts/s; batched vs plain",
         "value": value, "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -230,7 +426,7 @@ def main():
                    "radius": radius, "k": k,
                    "step": "build + radius CSR + COUNT + COUNT_SUMDIST + kNN; value counts 4*M queries per step"},
         "components": comps, "roofline": roofline, "cpu_baseline": cpu, "parity": parity,
-        "batched_vs_plain": None,
+        "batched_vs_plain": forest, "chamfer": chamfer,
     }
     print(json.dumps(line), flush=True)
 

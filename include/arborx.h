@@ -74,6 +74,9 @@ typedef struct arborx_tuning {
                              order (default), 1 = start from +inf */
 } arborx_tuning;
 
+/* Operation kinds that carry their own tuning. */
+typedef enum { ARBORX_OP_SPATIAL = 0, ARBORX_OP_REDUCE = 1, ARBORX_OP_KNN = 2 } arborx_op;
+
 /* Library version string, e.g. "arborx355 0.1". [host] */
 const char *arborx_version(void);
 
@@ -83,8 +86,27 @@ const char *arborx_last_error(void);
 /* Set the traversal schedule used by later queries; NULL restores the defaults.  [host] */
 arborx_status arborx_set_tuning(const arborx_tuning *tuning);
 
-/* Current traversal schedule. [host] */
+/* Current traversal schedule (of ARBORX_OP_SPATIAL). [host] */
 arborx_status arborx_get_tuning(arborx_tuning *tuning);
+
+/* Per-operation forms: op is an arborx_op; NULL restores that operation's defaults. [host] */
+arborx_status arborx_set_tuning_op(int32_t op, const arborx_tuning *tuning);
+arborx_status arborx_get_tuning_op(int32_t op, arborx_tuning *tuning);
+
+/*
+ * Pick the fastest schedule for one operation on the caller's own queries:
+ * every candidate (block size, short-stack depth, thread or wavefront-packet
+ * schedule, query ordering, kNN seeding) runs on `queries`; all must produce
+ * identical outputs (checked with a device hash, else ARBORX_E_DEVICE); the
+ * fastest by event timing on `stream` becomes the tuning of `op`.  radius is
+ * used for ARBORX_OP_SPATIAL / ARBORX_OP_REDUCE, k for ARBORX_OP_KNN.  If the
+ * environment variable ARBORX_TUNING_CACHE names a file, a choice recorded
+ * there for the same operation, dimension, kind, k and size classes is reused
+ * (*best_ms = -1) and new choices are appended.  Synchronises.
+ *   best [host, may be NULL] receives the chosen schedule; best_ms [host, may be NULL] its time.
+ */
+arborx_status arborx_autotune(arborx_tree tree, int32_t op, const float *queries, int64_t m, float radius, int32_t k,
+                              arborx_tuning *best, double *best_ms, void *stream);
 
 /*
  * Build a BVH over n values (Section 2.1, index constructor; Section 2.6: 64-bit
@@ -179,6 +201,74 @@ arborx_status arborx_query_knn(arborx_tree tree, const float *queries, int64_t m
 arborx_status arborx_query_spatial_reduce(arborx_tree tree, const float *queries, int64_t m, float radius,
                                           int32_t op, int32_t *counts, int64_t *sum_fixed, int32_t scale_bits,
                                           void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Forest: many independent trees in one structure, queried in one launch.  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Build T trees at once.  Tree t holds values [tree_offsets[t], tree_offsets[t+1])
+ * of the packed array `values` (points [n][dim] or boxes [n][2][dim]); trees may
+ * be empty.  tree_offsets [host] has T+1 nondecreasing entries starting at 0.
+ * Each tree is the tree arborx_bvh_build would give for its values alone.
+ */
+arborx_status arborx_forest_build(const float *values, const int64_t *tree_offsets, int32_t T, int32_t dim,
+                                  int32_t kind, void *stream, arborx_forest *out);
+arborx_status arborx_forest_destroy(arborx_forest forest);
+
+/* Forest metadata [host]: T, total values, dim, and per-tree root and height
+ * arrays of T entries (roots/heights may be NULL; -1 root = empty tree). */
+arborx_status arborx_forest_info(arborx_forest forest, int32_t *T, int64_t *n, int32_t *dim, int32_t *roots,
+                                 int32_t *heights);
+
+/* Grow the query workspace so that forest queries of up to m queries allocate
+ * nothing (required before capturing them in a hipGraph). */
+arborx_status arborx_forest_reserve(arborx_forest forest, int64_t m, void *stream);
+
+/*
+ * Batched queries: batch b is queries [batch_offsets[b], batch_offsets[b+1]) of
+ * the packed query array, searched in tree batch_tree[b] only.  batch_offsets
+ * ([B+1], int64), batch_tree ([B], int32) and batch_radius ([B], float) are
+ * DEVICE arrays; m [host] must equal batch_offsets[B].  Queries of a batch
+ * whose tree index is out of range match nothing.  Results are per query, in
+ * input order, with indices LOCAL to the target tree (identical to querying
+ * that tree built alone).  All batches run in one persistent launch that takes
+ * Morton-ordered blocks of queries from a work counter; nothing synchronises,
+ * and after arborx_forest_reserve nothing allocates (graph-capturable; while
+ * capturing, the call does not wait for the build: order it before capture).
+ */
+arborx_status arborx_forest_query_reduce(arborx_forest forest, const float *queries, int64_t m,
+                                         const int64_t *batch_offsets, const int32_t *batch_tree,
+                                         const float *batch_radius, int32_t B, int32_t op, int32_t *counts,
+                                         int64_t *sum_fixed, int32_t scale_bits, void *stream);
+arborx_status arborx_forest_query_knn(arborx_forest forest, const float *queries, int64_t m,
+                                      const int64_t *batch_offsets, const int32_t *batch_tree, int32_t B, int32_t k,
+                                      float *dist2, int32_t *indices, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Chamfer loss of nearest neighbours between paired 3D point clouds.        */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Pair p holds clouds a[a_off[p]..a_off[p+1]) and b[b_off[p]..b_off[p+1]) (3D
+ * points, device); a_off, b_off are [P+1] HOST offsets.  nn_ab[i] receives the
+ * index, local to B_p, of the nearest point of B_p to a_i (the k = 1 nearest
+ * query of Section 2.1, ties to the smaller index; -1 if B_p is empty), nn_ba
+ * likewise; loss[p] (device float) = sum of those float32 squared distances
+ * over both directions, accumulated in float64.
+ */
+arborx_status arborx_chamfer_forward(const float *a, const int64_t *a_off, const float *b, const int64_t *b_off,
+                                     int32_t P, float *loss, int32_t *nn_ab, int32_t *nn_ba, void *stream);
+
+/*
+ * Gradient of sum_p grad_loss[p] * loss[p] with the neighbour indices of the
+ * forward pass held fixed: dL/da_i = 2(a_i - b_nn(i)) + sum_{j: nn(j)=i} 2(a_i - b_j)
+ * (symmetrically for b), evaluated in float64 and rounded once to float32.
+ * grad_loss [P], grad_a [na][3], grad_b [nb][3] are device arrays.
+ */
+arborx_status arborx_chamfer_backward(const float *a, const int64_t *a_off, const float *b, const int64_t *b_off,
+                                      int32_t P, const int32_t *nn_ab, const int32_t *nn_ba, const float *grad_loss,
+                                      float *grad_a, float *grad_b, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Diagnostics: building blocks exposed for component tests.                */

@@ -77,6 +77,35 @@ def arborx_get_tuning() -> dict:
     return dict(block=t.block, order=t.order, stack=t.stack, schedule=t.schedule, build=t.build, no_seed=t.no_seed)
 
 
+OP_SPATIAL, OP_REDUCE, OP_KNN = 0, 1, 2
+
+
+def _tuning_dict(t):
+    return dict(block=t.block, order=t.order, stack=t.stack, schedule=t.schedule, build=t.build, no_seed=t.no_seed)
+
+
+def arborx_set_tuning_op(op, block=0, order=1, stack=0, schedule=0, build=0, no_seed=0) -> None:
+    t = _lib.Tuning(block, order, stack, schedule, build, no_seed)
+    _check(_lib.lib().arborx_set_tuning_op(op, ctypes.byref(t)))
+
+
+def arborx_get_tuning_op(op) -> dict:
+    t = _lib.Tuning()
+    _check(_lib.lib().arborx_get_tuning_op(op, ctypes.byref(t)))
+    return _tuning_dict(t)
+
+
+def arborx_autotune(tree, op, queries, radius=0.0, k=1, stream=None):
+    """Time the candidate schedules on these queries and keep the fastest for `op`: (tuning dict, ms)."""
+    torch = _torch()
+    q = _dev(queries, torch.float32, "queries")
+    best = _lib.Tuning()
+    ms = ctypes.c_double()
+    _check(_lib.lib().arborx_autotune(tree.handle, op, _ptr(q), q.shape[0], ctypes.c_float(radius), k,
+                                      ctypes.byref(best), ctypes.byref(ms), _stream(stream)))
+    return _tuning_dict(best), ms.value
+
+
 class Tree:
     """Owns an arborx_tree handle; destroyed with the object."""
 
@@ -219,6 +248,167 @@ def arborx_debug_tree_nodes(tree: Tree):
                                               lo.ctypes.data_as(ctypes.c_void_p), hi.ctypes.data_as(ctypes.c_void_p),
                                               ctypes.byref(root)))
     return child[:nn], lo[:nn], hi[:nn], root.value
+
+
+# ---------------------------------------------------------------------------
+# forest
+# ---------------------------------------------------------------------------
+
+class Forest:
+    """Owns an arborx_forest handle; destroyed with the object."""
+
+    def __init__(self, handle, T, n, dim, kind, values):
+        self.handle, self.T, self.n, self.dim, self.kind = handle, T, n, dim, kind
+        self._values = values
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None and _lib._lib is not None:
+            _lib._lib.arborx_forest_destroy(h)
+        self.handle = None
+
+
+def _host_i64(a):
+    import numpy as np
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int64))
+
+
+def arborx_forest_build(values, tree_offsets, kind=POINTS, stream=None) -> Forest:
+    """values: packed float32 [n, dim] (or [n, 2, dim] boxes) on the GPU; tree_offsets: host ints [T+1]."""
+    torch = _torch()
+    values = _dev(values, torch.float32, "values")
+    off = _host_i64(tree_offsets)
+    T = len(off) - 1
+    n, dim = values.shape[0], values.shape[-1]
+    if T < 1 or off[-1] != n:
+        raise ValueError("tree_offsets must have T+1 >= 2 entries ending at n")
+    h = ctypes.c_void_p()
+    _check(_lib.lib().arborx_forest_build(_ptr(values), off.ctypes.data_as(ctypes.c_void_p), T, dim, kind,
+                                          _stream(stream), ctypes.byref(h)))
+    return Forest(h, T, n, dim, kind, values)
+
+
+def arborx_forest_info(forest: Forest) -> dict:
+    import numpy as np
+    T, n, dim = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+    roots = np.zeros(forest.T, dtype=np.int32)
+    heights = np.zeros(forest.T, dtype=np.int32)
+    _check(_lib.lib().arborx_forest_info(forest.handle, ctypes.byref(T), ctypes.byref(n), ctypes.byref(dim),
+                                         roots.ctypes.data_as(ctypes.c_void_p),
+                                         heights.ctypes.data_as(ctypes.c_void_p)))
+    return dict(T=T.value, n=n.value, dim=dim.value, roots=roots, heights=heights)
+
+
+def arborx_forest_reserve(forest: Forest, m: int, stream=None) -> None:
+    _check(_lib.lib().arborx_forest_reserve(forest.handle, int(m), _stream(stream)))
+
+
+def _batches(queries, batch_offsets, batch_tree, dim):
+    torch = _torch()
+    q = _dev(queries, torch.float32, "queries")
+    if q.dim() != 2 or q.shape[1] != dim:
+        raise ValueError(f"queries must be [m, {dim}]")
+    bo = _dev(batch_offsets, torch.int64, "batch_offsets")
+    bt = _dev(batch_tree, torch.int32, "batch_tree")
+    if bo.numel() != bt.numel() + 1:
+        raise ValueError("batch_offsets must have B+1 entries")
+    return q, bo, bt, bt.numel()
+
+
+def arborx_forest_query_reduce(forest: Forest, queries, batch_offsets, batch_tree, batch_radius, op=COUNT_SUMDIST,
+                               scale_bits=32, stream=None):
+    """Per query: count (and fixed-point distance sum) within its batch's radius in its batch's tree."""
+    torch = _torch()
+    q, bo, bt, B = _batches(queries, batch_offsets, batch_tree, forest.dim)
+    br = _dev(batch_radius, torch.float32, "batch_radius")
+    m = q.shape[0]
+    counts = torch.empty(m, dtype=torch.int32, device=q.device)
+    sums = torch.empty(m, dtype=torch.int64, device=q.device) if op == COUNT_SUMDIST else None
+    _check(_lib.lib().arborx_forest_query_reduce(forest.handle, _ptr(q), m, _ptr(bo), _ptr(bt), _ptr(br), B, op,
+                                                 _ptr(counts), _ptr(sums), scale_bits, _stream(stream)))
+    return counts, sums
+
+
+def arborx_forest_query_knn(forest: Forest, queries, batch_offsets, batch_tree, k: int, stream=None):
+    """Per query: k nearest in its batch's tree, indices local to that tree, padded (+inf, -1)."""
+    torch = _torch()
+    q, bo, bt, B = _batches(queries, batch_offsets, batch_tree, forest.dim)
+    m = q.shape[0]
+    d2 = torch.empty((m, k), dtype=torch.float32, device=q.device)
+    idx = torch.empty((m, k), dtype=torch.int32, device=q.device)
+    _check(_lib.lib().arborx_forest_query_knn(forest.handle, _ptr(q), m, _ptr(bo), _ptr(bt), B, k, _ptr(d2),
+                                              _ptr(idx), _stream(stream)))
+    return d2, idx
+
+
+# ---------------------------------------------------------------------------
+# Chamfer
+# ---------------------------------------------------------------------------
+
+def arborx_chamfer_forward(a, a_off, b, b_off, stream=None):
+    """(loss float32[P], nn_ab int32[na], nn_ba int32[nb]); a_off, b_off host ints [P+1]."""
+    torch = _torch()
+    a = _dev(a, torch.float32, "a")
+    b = _dev(b, torch.float32, "b")
+    ao, bo = _host_i64(a_off), _host_i64(b_off)
+    P = len(ao) - 1
+    loss = torch.empty(P, dtype=torch.float32, device=a.device)
+    nab = torch.empty(a.shape[0], dtype=torch.int32, device=a.device)
+    nba = torch.empty(b.shape[0], dtype=torch.int32, device=a.device)
+    _check(_lib.lib().arborx_chamfer_forward(_ptr(a), ao.ctypes.data_as(ctypes.c_void_p), _ptr(b),
+                                             bo.ctypes.data_as(ctypes.c_void_p), P, _ptr(loss), _ptr(nab), _ptr(nba),
+                                             _stream(stream)))
+    return loss, nab, nba
+
+
+def arborx_chamfer_backward(a, a_off, b, b_off, nn_ab, nn_ba, grad_loss, stream=None):
+    """(grad_a float32[na, 3], grad_b float32[nb, 3]) with the forward's neighbours held fixed."""
+    torch = _torch()
+    a = _dev(a, torch.float32, "a")
+    b = _dev(b, torch.float32, "b")
+    g = _dev(grad_loss.contiguous(), torch.float32, "grad_loss")
+    ao, bo = _host_i64(a_off), _host_i64(b_off)
+    P = len(ao) - 1
+    ga = torch.empty_like(a)
+    gb = torch.empty_like(b)
+    _check(_lib.lib().arborx_chamfer_backward(_ptr(a), ao.ctypes.data_as(ctypes.c_void_p), _ptr(b),
+                                              bo.ctypes.data_as(ctypes.c_void_p), P, _ptr(nn_ab), _ptr(nn_ba),
+                                              _ptr(g), _ptr(ga), _ptr(gb), _stream(stream)))
+    return ga, gb
+
+
+def _chamfer_function():
+    torch = _torch()
+
+    class ChamferFn(torch.autograd.Function):
+        """Per-pair nearest-neighbour Chamfer loss; backward is the library's kernel."""
+
+        @staticmethod
+        def forward(ctx, a, b, a_off, b_off):
+            loss, nab, nba = arborx_chamfer_forward(a.detach().contiguous(), a_off, b.detach().contiguous(), b_off)
+            ctx.save_for_backward(a.detach(), b.detach(), nab, nba)
+            ctx.offsets = (a_off, b_off)
+            return loss
+
+        @staticmethod
+        def backward(ctx, grad_loss):
+            a, b, nab, nba = ctx.saved_tensors
+            ga, gb = arborx_chamfer_backward(a.contiguous(), ctx.offsets[0], b.contiguous(), ctx.offsets[1], nab, nba,
+                                             grad_loss.float())
+            return ga, gb, None, None
+
+    return ChamferFn
+
+
+_CHAMFER = None
+
+
+def chamfer(a, a_off, b, b_off):
+    """Differentiable per-pair Chamfer loss: a [na, 3], b [nb, 3] packed clouds, host offsets [P+1]."""
+    global _CHAMFER
+    if _CHAMFER is None:
+        _CHAMFER = _chamfer_function()
+    return _CHAMFER.apply(a, b, a_off, b_off)
 
 
 class BVH:

@@ -20,6 +20,9 @@ SIGNATURES = {
     "arborx_last_error": (ctypes.c_char_p, []),
     "arborx_set_tuning": (I32, [P]),
     "arborx_get_tuning": (I32, [P]),
+    "arborx_set_tuning_op": (I32, [I32, P]),
+    "arborx_get_tuning_op": (I32, [I32, P]),
+    "arborx_autotune": (I32, [P, I32, P, I64, F32, I32, P, P, P]),
     "arborx_bvh_build": (I32, [P, I64, I32, I32, P, P]),
     "arborx_bvh_destroy": (I32, [P]),
     "arborx_bvh_info": (I32, [P, P, P, P, P, P]),
@@ -34,6 +37,14 @@ SIGNATURES = {
     "arborx_query_intersects_begin": (I32, [P, P, I64, P, P, P, P]),
     "arborx_query_finish": (I32, [P, P, I64]),
     "arborx_plan_destroy": (I32, [P]),
+    "arborx_forest_build": (I32, [P, P, I32, I32, I32, P, P]),
+    "arborx_forest_destroy": (I32, [P]),
+    "arborx_forest_info": (I32, [P, P, P, P, P, P]),
+    "arborx_forest_reserve": (I32, [P, I64, P]),
+    "arborx_forest_query_reduce": (I32, [P, P, I64, P, P, P, I32, I32, P, P, I32, P]),
+    "arborx_forest_query_knn": (I32, [P, P, I64, P, P, I32, I32, P, P, P]),
+    "arborx_chamfer_forward": (I32, [P, P, P, P, I32, P, P, P, P]),
+    "arborx_chamfer_backward": (I32, [P, P, P, P, I32, P, P, P, P, P, P]),
     "arborx_profile_enable": (I32, [I32]),
     "arborx_profile_collect": (I32, [P, P, P, I32, P]),
 }

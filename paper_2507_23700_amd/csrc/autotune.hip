@@ -1,0 +1,281 @@
+// Schedule autotuner.  For one operation kind (radius CSR, radius reduce, kNN)
+// it runs the caller's own queries under each candidate schedule, checks that
+// every candidate produced the same outputs (an order-independent 64-bit hash
+// of the output words, computed on the device), times each with events on the
+// caller's stream, and installs the fastest as that operation's tuning.
+// Choices can be cached in a JSON-lines file named by ARBORX_TUNING_CACHE,
+// keyed by operation, dimension, kind, k and the size classes of n and m.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device_util.hpp"
+#include "internal.hpp"
+
+namespace ax {
+namespace {
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long x)
+{
+    x += 0x9e3779b97f4a7c15ull;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+}
+
+// Sum over i of mix(word_i, i): equal inputs give equal hashes whatever the
+// summation order.
+__global__ void k_hash(const uint32_t *__restrict__ w, int64_t n, unsigned long long salt,
+                       unsigned long long *__restrict__ out)
+{
+    unsigned long long h = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        h += mix64(((unsigned long long)w[i] << 32) ^ (unsigned long long)i ^ salt);
+    h = wave_sum(h);
+    if (lane_id() == 0)
+        atomicAdd(out, h);
+}
+
+struct Candidate {
+    Tuning t;
+    double ms = 0;
+};
+
+std::string cache_key(int op, int dim, int kind, int k, int64_t n, int64_t m)
+{
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), "op=%d dim=%d kind=%d k=%d logn=%d logm=%d", op, dim, kind, op == OP_KNN ? k : 0,
+                  n > 0 ? (int)std::floor(std::log2((double)n)) : -1, m > 0 ? (int)std::floor(std::log2((double)m)) : -1);
+    return buf;
+}
+
+bool cache_lookup(const std::string &key, Tuning &t)
+{
+    const char *path = std::getenv("ARBORX_TUNING_CACHE");
+    if (!path || !*path)
+        return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f)
+        return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        char k[200];
+        int block, order, stack, schedule, seed;
+        if (std::sscanf(line, "{\"key\": \"%199[^\"]\", \"block\": %d, \"order\": %d, \"stack\": %d, \"schedule\": %d, "
+                              "\"seed\": %d",
+                        k, &block, &order, &stack, &schedule, &seed) == 6 &&
+            key == k) {
+            t.block = block;
+            t.order = order;
+            t.stack = stack;
+            t.schedule = schedule;
+            t.seed = seed;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const std::string &key, const Tuning &t, double ms)
+{
+    const char *path = std::getenv("ARBORX_TUNING_CACHE");
+    if (!path || !*path)
+        return;
+    FILE *f = std::fopen(path, "a");
+    if (!f)
+        return;
+    std::fprintf(f,
+                 "{\"key\": \"%s\", \"block\": %d, \"order\": %d, \"stack\": %d, \"schedule\": %d, \"seed\": %d, "
+                 "\"ms\": %.4f}\n",
+                 key.c_str(), t.block, t.order, t.stack, t.schedule, t.seed, ms);
+    std::fclose(f);
+}
+
+}  // namespace
+}  // namespace ax
+
+using namespace ax;
+
+extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const float *queries, int64_t m, float radius,
+                                         int32_t k, arborx_tuning *best, double *best_ms, void *stream)
+{
+    if (!tree)
+        return fail(ARBORX_E_INVALID, "tree is NULL");
+    if (op < 0 || op >= OP_KINDS)
+        return fail(ARBORX_E_INVALID, "unknown operation");
+    if (m <= 0 || !queries)
+        return fail(ARBORX_E_INVALID, "autotuning needs queries");
+    if (op == OP_KNN && (k < 1 || k > 64))
+        return fail(ARBORX_E_INVALID, "k must be in 1..64");
+    if (op != OP_KNN && (std::isnan(radius) || radius < 0.0f))
+        return fail(ARBORX_E_INVALID, "radius must be >= 0 and not NaN");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int64_t n = 0;
+    int32_t dim = 0, kind = 0;
+    arborx_status st = arborx_bvh_info(tree, &n, &dim, &kind, nullptr, nullptr);
+    if (st != ARBORX_OK)
+        return st;
+    const std::string key = cache_key(op, dim, kind, k, n, m);
+    Tuning cached = tuning(op);
+    if (cache_lookup(key, cached)) {
+        set_tuning_op(op, cached);
+        if (best) {
+            best->block = cached.block;
+            best->order = cached.order;
+            best->stack = cached.stack;
+            best->schedule = cached.schedule;
+            best->build = cached.build;
+            best->no_seed = cached.seed ? 0 : 1;
+        }
+        if (best_ms)
+            *best_ms = -1.0;
+        return ARBORX_OK;
+    }
+
+    const Tuning base = tuning(op);
+    std::vector<Candidate> cands;
+    for (int block : {64, 128, 256})
+        for (int stack : {8, 16, 32}) {
+            Candidate c;
+            c.t = base;
+            c.t.block = block;
+            c.t.stack = stack;
+            c.t.schedule = 0;
+            c.t.order = 1;
+            cands.push_back(c);
+        }
+    for (int block : {64, 128, 256}) {
+        Candidate c;
+        c.t = base;
+        c.t.block = block;
+        c.t.schedule = 1;
+        c.t.order = 1;
+        cands.push_back(c);
+    }
+    {
+        Candidate c;
+        c.t = base;
+        c.t.order = 0;
+        c.t.schedule = 0;
+        cands.push_back(c);
+    }
+    if (op == OP_KNN) {
+        const size_t nbase = cands.size();
+        for (size_t i = 0; i < nbase; i += 4) {
+            Candidate c = cands[i];
+            c.t.seed = 1 - c.t.seed;
+            cands.push_back(c);
+        }
+    }
+
+    Temps tmp(s);
+    unsigned long long *hash;
+    int32_t *o1 = nullptr;
+    int64_t *o2 = nullptr, *offsets = nullptr;
+    float *d2 = nullptr;
+    int32_t *indices = nullptr;
+    int64_t total = 0;
+    if ((st = tmp.get(&hash, 1)) != ARBORX_OK)
+        return st;
+    if (op == OP_KNN) {
+        if ((st = tmp.get(&d2, m * k)) != ARBORX_OK || (st = tmp.get(&o1, m * k)) != ARBORX_OK)
+            return st;
+    } else if (op == OP_REDUCE) {
+        if ((st = tmp.get(&o1, m)) != ARBORX_OK || (st = tmp.get(&o2, m)) != ARBORX_OK)
+            return st;
+    } else {
+        if ((st = tmp.get(&offsets, m + 1)) != ARBORX_OK)
+            return st;
+        arborx_plan plan = nullptr;
+        if ((st = arborx_query_spatial_begin(tree, queries, m, radius, offsets, &total, &plan, stream)) != ARBORX_OK)
+            return st;
+        arborx_plan_destroy(plan);
+        if ((st = tmp.get(&indices, total > 0 ? total : 1)) != ARBORX_OK)
+            return st;
+    }
+    auto run = [&]() -> arborx_status {
+        if (op == OP_KNN)
+            return arborx_query_knn(tree, queries, m, k, d2, o1, stream);
+        if (op == OP_REDUCE)
+            return arborx_query_spatial_reduce(tree, queries, m, radius, ARBORX_COUNT_SUMDIST, o1, o2, 32, stream);
+        int64_t tot = 0;
+        return arborx_query_spatial(tree, queries, m, radius, offsets, indices, total > 0 ? total : 1, &tot, stream);
+    };
+    auto digest = [&](unsigned long long *h) -> arborx_status {
+        fill_kernel<unsigned long long><<<1, 64, 0, s>>>(hash, 1, 0ull);
+        auto add = [&](const void *p, int64_t words, unsigned long long salt) {
+            if (words > 0)
+                k_hash<<<grid_for(words, 256, 4096), 256, 0, s>>>(static_cast<const uint32_t *>(p), words, salt, hash);
+        };
+        if (op == OP_KNN) {
+            add(d2, m * k, 1);
+            add(o1, m * k, 2);
+        } else if (op == OP_REDUCE) {
+            add(o1, m, 3);
+            add(o2, 2 * m, 4);
+        } else {
+            add(offsets, 2 * (m + 1), 5);
+            add(indices, total, 6);
+        }
+        AX_HIP(hipMemcpyAsync(h, hash, 8, hipMemcpyDeviceToHost, s));
+        AX_HIP(hipStreamSynchronize(s));
+        return ARBORX_OK;
+    };
+    hipEvent_t e0, e1;
+    AX_HIP(hipEventCreate(&e0));
+    AX_HIP(hipEventCreate(&e1));
+    unsigned long long ref = 0;
+    int besti = -1;
+    for (size_t i = 0; i < cands.size() && st == ARBORX_OK; ++i) {
+        set_tuning_op(op, cands[i].t);
+        if ((st = run()) != ARBORX_OK)
+            break;
+        unsigned long long h = 0;
+        if ((st = digest(&h)) != ARBORX_OK)
+            break;
+        if (i == 0)
+            ref = h;
+        else if (h != ref)
+            st = fail(ARBORX_E_DEVICE, "schedule candidate " + std::to_string(i) + " changed the results");
+        if (st != ARBORX_OK)
+            break;
+        float best_t = 1e30f;
+        for (int rep = 0; rep < 2 && st == ARBORX_OK; ++rep) {
+            (void)hipEventRecord(e0, s);
+            st = run();
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            best_t = ms < best_t ? ms : best_t;
+        }
+        cands[i].ms = best_t;
+        if (besti < 0 || cands[i].ms < cands[besti].ms)
+            besti = (int)i;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != ARBORX_OK || besti < 0) {
+        set_tuning_op(op, base);
+        return st != ARBORX_OK ? st : fail(ARBORX_E_DEVICE, "no candidate ran");
+    }
+    const Tuning &b = cands[besti].t;
+    set_tuning_op(op, b);
+    cache_store(key, b, cands[besti].ms);
+    if (best) {
+        best->block = b.block;
+        best->order = b.order;
+        best->stack = b.stack;
+        best->schedule = b.schedule;
+        best->build = b.build;
+        best->no_seed = b.seed ? 0 : 1;
+    }
+    if (best_ms)
+        *best_ms = cands[besti].ms;
+    return ARBORX_OK;
+}

@@ -17,7 +17,9 @@
 //                          sibling's box and continues upwards.  Writing a
 //                          leaf's box straight into its parent slot is the
 //                          "leaf gather": leaves need no array of their own.
+#include <algorithm>
 #include <cstddef>
+#include <vector>
 
 #include "device_util.hpp"
 #include "geometry.hpp"
@@ -96,6 +98,7 @@ __global__ void bounds_final(const float *__restrict__ partial, int blocks, int6
         hdr->n = (int32_t)n;
         hdr->root = n > 0 ? 0 : -1;
         hdr->height = 0;
+        hdr->start = 0;
     }
 }
 
@@ -296,8 +299,8 @@ __device__ __forceinline__ void load_value_box(const float *values, int kind, ui
 }
 
 template <int D>
-__device__ void write_single_leaf_tree(Node<D> *nodes, TreeHeader *hdr, const float *lo, const float *hi,
-                                       int32_t ref)
+__device__ void write_single_leaf_tree(Node<D> *node, TreeHeader *hdr, const float *lo, const float *hi, int32_t ref,
+                                       int index)
 {
     Node<D> nd;
 #pragma unroll
@@ -309,14 +312,39 @@ __device__ void write_single_leaf_tree(Node<D> *nodes, TreeHeader *hdr, const fl
     }
     nd.child[0] = ref;
     nd.child[1] = kEmptyRef;
-    nd.range_l = 0;
-    nd.range_r = 0;
-    store_node(nodes, nd);
-    hdr->root = 0;
+    nd.range_l = index;
+    nd.range_r = index;
+    store_node(node, nd);
+    hdr->root = index;
     hdr->height = 1;
 }
 
 template <int D> constexpr int chunk_leaves() { return D <= 3 ? 1024 : 512; }
+
+// Tree (segment) holding sorted leaf i: seg[s] <= i < seg[s+1].  Without
+// segments the whole array is one tree.  Climbs never cross a tree's ends, so
+// every tree of a forest gets its own root.
+__device__ __forceinline__ void segment_of(int i, const int64_t *__restrict__ seg, int nseg, int n, int &s, int &ts,
+                                           int &te)
+{
+    if (!seg) {
+        s = 0;
+        ts = 0;
+        te = n - 1;
+        return;
+    }
+    int lo = 0, hi = nseg;  // find the last s with seg[s] <= i
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (seg[mid] <= i)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    s = lo;
+    ts = (int)seg[lo];
+    te = (int)seg[lo + 1] - 1;
+}
 
 template <int D>
 __global__ __launch_bounds__(kBuildBlock) void hierarchy_chunk_kernel(const uint64_t *__restrict__ codes,
@@ -326,7 +354,8 @@ __global__ __launch_bounds__(kBuildBlock) void hierarchy_chunk_kernel(const uint
                                                                       float *__restrict__ leaves,
                                                                       unsigned long long *__restrict__ gflags,
                                                                       Escape<D> *__restrict__ escapes,
-                                                                      TreeHeader *hdr)
+                                                                      const int64_t *__restrict__ seg, int nseg,
+                                                                      TreeHeader *hdrs)
 {
     constexpr int C = chunk_leaves<D>();
     __shared__ uint64_t s_key[C + 1];             // split keys of splits cs-1 .. ce-1
@@ -337,15 +366,6 @@ __global__ __launch_bounds__(kBuildBlock) void hierarchy_chunk_kernel(const uint
     const int cs = blockIdx.x * C;
     const int ce = min(n, cs + C);
     const int tid = threadIdx.x;
-    if (n == 1) {
-        if (tid == 0) {
-            float lo[D], hi[D];
-            load_value_box<D>(values, kind, ids[0], lo, hi);
-            store_leaf<D>(leaves, 0, kind, lo, hi, (int32_t)ids[0]);
-            write_single_leaf_tree<D>(nodes, hdr, lo, hi, ~(int32_t)ids[0]);
-        }
-        return;
-    }
     for (int j = tid; j < C; j += kBuildBlock)
         s_flag[j] = 0;
     for (int j = tid; j <= C; j += kBuildBlock) {
@@ -366,10 +386,16 @@ __global__ __launch_bounds__(kBuildBlock) void hierarchy_chunk_kernel(const uint
         load_value_box<D>(values, kind, id, lo, hi);
         store_leaf<D>(leaves, i, kind, lo, hi, (int32_t)id);
         int32_t ref = ~(int32_t)id;
+        int sg, ts, te;
+        segment_of(i, seg, nseg, n, sg, ts, te);
+        if (ts == te) {  // a one-value tree: its node slot is the unused split at its end
+            write_single_leaf_tree<D>(nodes + ts, hdrs + sg, lo, hi, ref, ts);
+            continue;
+        }
         int l = i, r = i, h = 0;
         while (true) {
             int p, side;
-            if (l == 0 || (r != n - 1 && s_key[r - cs + 1] < s_key[l - 1 - cs + 1])) {
+            if (l == ts || (r != te && s_key[r - cs + 1] < s_key[l - 1 - cs + 1])) {
                 p = r;
                 side = 0;
             } else {
@@ -430,9 +456,9 @@ __global__ __launch_bounds__(kBuildBlock) void hierarchy_chunk_kernel(const uint
             store_node(nodes + p, nd);
             s_flag[lp] = kDone;
             ref = p;
-            if (l == 0 && r == n - 1) {
-                hdr->root = p;
-                hdr->height = h;
+            if (l == ts && r == te) {
+                hdrs[sg].root = p;
+                hdrs[sg].height = h;
                 break;
             }
         }
@@ -459,7 +485,8 @@ template <int D>
 __global__ __launch_bounds__(kBuildBlock) void hierarchy_top_kernel(const uint64_t *__restrict__ codes, int n,
                                                                     Node<D> *nodes, unsigned long long *gflags,
                                                                     const Escape<D> *__restrict__ escapes,
-                                                                    int n_escapes, TreeHeader *hdr)
+                                                                    int n_escapes, const int64_t *__restrict__ seg,
+                                                                    int nseg, TreeHeader *hdrs)
 {
     const int e_i = blockIdx.x * kBuildBlock + threadIdx.x;
     if (e_i >= n_escapes)
@@ -475,6 +502,8 @@ __global__ __launch_bounds__(kBuildBlock) void hierarchy_top_kernel(const uint64
     }
     int p = e.p, side = e.side, l = e.l, r = e.r, h = e.h;
     int32_t ref = e.ref;
+    int sg, ts, te;
+    segment_of(l, seg, nseg, n, sg, ts, te);
     // a climb visits at most n-1 splits
     for (int guard = 0; guard < n; ++guard) {
         if (p < 0 || p > n - 2)
@@ -506,12 +535,12 @@ __global__ __launch_bounds__(kBuildBlock) void hierarchy_top_kernel(const uint64
         np->range_l = l;
         np->range_r = r;
         ref = p;
-        if (l == 0 && r == n - 1) {
-            hdr->root = p;
-            hdr->height = h;
+        if (l == ts && r == te) {
+            hdrs[sg].root = p;
+            hdrs[sg].height = h;
             return;
         }
-        if (l == 0 || (r != n - 1 && split_key(codes, r) < split_key(codes, l - 1))) {
+        if (l == ts || (r != te && split_key(codes, r) < split_key(codes, l - 1))) {
             p = r;
             side = 0;
         } else {
@@ -526,6 +555,7 @@ __global__ void empty_header(TreeHeader *hdr, int dim)
     hdr->root = -1;
     hdr->height = 0;
     hdr->n = 0;
+    hdr->start = 0;
     for (int d = 0; d < kMaxDim; ++d) {
         hdr->lo[d] = INFINITY;
         hdr->hi[d] = -INFINITY;
@@ -591,7 +621,7 @@ arborx_status build_impl(const float *values, int64_t n, int kind, TreeDev &t, h
         ids = ids2;
     }
     Node<D> *nodes = static_cast<Node<D> *>(t.nodes);
-    if (tuning().build == 1) {
+    if (tuning(OP_SPATIAL).build == 1) {
         // single pass: every handoff through device-scope acquire/release
         fill_kernel<unsigned long long><<<grid_for(nn, 256, 65536), 256, 0, s>>>(flags, nn, 0ull);
         ProfScope ps("build_hierarchy", s);
@@ -605,11 +635,10 @@ arborx_status build_impl(const float *values, int64_t n, int kind, TreeDev &t, h
             return st;
         ProfScope ps("build_hierarchy", s);
         hierarchy_chunk_kernel<D><<<chunks, kBuildBlock, 0, s>>>(codes, ids, values, kind, (int)n, nodes, t.leaves,
-                                                                 flags, esc, t.hdr);
+                                                                 flags, esc, nullptr, 0, t.hdr);
         if (chunks > 1)
-            hierarchy_top_kernel<D><<<grid_for(2 * chunks, kBuildBlock), kBuildBlock, 0, s>>>(codes, (int)n, nodes,
-                                                                                            flags, esc, 2 * chunks,
-                                                                                            t.hdr);
+            hierarchy_top_kernel<D><<<grid_for(2 * chunks, kBuildBlock), kBuildBlock, 0, s>>>(
+                codes, (int)n, nodes, flags, esc, 2 * chunks, nullptr, 0, t.hdr);
     }
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
@@ -623,6 +652,233 @@ hipError_t morton_impl(const float *pts, int64_t n, const float *bounds, uint64_
     morton_kernel<D><<<grid_for(n, kBuildBlock, 65536), kBuildBlock, 0, s>>>(pts, n, ARBORX_POINTS, bounds,
                                                                             bounds + D, codes, nullptr);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Forest build: many trees over one packed value array, tree t holding values
+// [seg[t], seg[t+1]).  Work is cut into tiles that never straddle a tree so
+// each workgroup knows its tree.  Per-tree bounds are reduced per tile and
+// combined with atomics on order-preserving integer images of the floats;
+// Morton keys are (tree << mbits) | tree-local code, so one global sort keeps
+// every tree contiguous and Morton-ordered inside; the climb then stops at the
+// tree ends (segment_of).
+// ---------------------------------------------------------------------------
+
+constexpr int kForestTile = 4096;
+
+__device__ __forceinline__ uint32_t float_order(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float order_float(uint32_t k)
+{
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+template <int D>
+__global__ __launch_bounds__(kBuildBlock) void forest_tile_bounds(const float *__restrict__ values, int kind,
+                                                                  const int32_t *__restrict__ tile_tree,
+                                                                  const int32_t *__restrict__ tile_start,
+                                                                  const int32_t *__restrict__ tile_end,
+                                                                  uint32_t *__restrict__ tmin,
+                                                                  uint32_t *__restrict__ tmax)
+{
+    __shared__ float s_lo[kBuildBlock / kWave][D];
+    __shared__ float s_hi[kBuildBlock / kWave][D];
+    const int b = blockIdx.x;
+    const int t = tile_tree[b];
+    float lo[D], hi[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = INFINITY;
+        hi[d] = -INFINITY;
+    }
+    const int stride_v = kind == ARBORX_BOXES ? 2 * D : D;
+    const int hoff = kind == ARBORX_BOXES ? D : 0;
+    for (int i = tile_start[b] + threadIdx.x; i < tile_end[b]; i += kBuildBlock) {
+        const float *v = values + (int64_t)i * stride_v;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            lo[d] = fminf(lo[d], v[d]);
+            hi[d] = fmaxf(hi[d], v[hoff + d]);
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            lo[d] = fminf(lo[d], __shfl_xor(lo[d], o, kWave));
+            hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], o, kWave));
+        }
+    }
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            s_lo[wave_id()][d] = lo[d];
+            s_hi[wave_id()][d] = hi[d];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < D) {
+        const int d = threadIdx.x;
+        float a = INFINITY, c = -INFINITY;
+        for (int w = 0; w < kBuildBlock / kWave; ++w) {
+            a = fminf(a, s_lo[w][d]);
+            c = fmaxf(c, s_hi[w][d]);
+        }
+        atomicMin(&tmin[t * D + d], float_order(a));
+        atomicMax(&tmax[t * D + d], float_order(c));
+    }
+}
+
+template <int D>
+__global__ void forest_headers(const int64_t *__restrict__ seg, int T, const uint32_t *__restrict__ tmin,
+                               const uint32_t *__restrict__ tmax, TreeHeader *__restrict__ hdrs)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T)
+        return;
+    const int n = (int)(seg[t + 1] - seg[t]);
+    TreeHeader &h = hdrs[t];
+    h.n = n;
+    h.start = (int)seg[t];
+    h.root = -1;
+    h.height = 0;
+    for (int d = 0; d < kMaxDim; ++d) {
+        h.lo[d] = (d < D && n > 0) ? order_float(tmin[t * D + d]) : INFINITY;
+        h.hi[d] = (d < D && n > 0) ? order_float(tmax[t * D + d]) : -INFINITY;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBuildBlock) void forest_tile_morton(const float *__restrict__ values, int kind,
+                                                                  const int32_t *__restrict__ tile_tree,
+                                                                  const int32_t *__restrict__ tile_start,
+                                                                  const int32_t *__restrict__ tile_end,
+                                                                  const TreeHeader *__restrict__ hdrs, int mbits,
+                                                                  uint64_t *__restrict__ codes,
+                                                                  uint32_t *__restrict__ ids)
+{
+    const int b = blockIdx.x;
+    const int t = tile_tree[b];
+    const int bits = mbits / D;
+    float lo[D], inv[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = hdrs[t].lo[d];
+        const float ext = hdrs[t].hi[d] - lo[d];
+        inv[d] = ext > 0.0f ? 1.0f / ext : 0.0f;
+    }
+    for (int i = tile_start[b] + threadIdx.x; i < tile_end[b]; i += kBuildBlock) {
+        uint32_t c[D];
+        if (kind == ARBORX_BOXES) {
+            const float *v = values + (int64_t)i * 2 * D;
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                c[d] = quantise(v[d] + 0.5f * (v[D + d] - v[d]), lo[d], inv[d], bits);
+        } else {
+            const float *v = values + (int64_t)i * D;
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                c[d] = quantise(v[d], lo[d], inv[d], bits);
+        }
+        codes[i] = ((uint64_t)t << mbits) | interleave<D>(c, bits);
+        ids[i] = (uint32_t)i;
+    }
+}
+
+template <int D>
+arborx_status forest_build_impl(const float *values, const int64_t *seg_host, int T, int kind, ForestDev &f,
+                                hipStream_t s)
+{
+    AX_HIP(hipGetLastError());
+    const int64_t n = seg_host[T];
+    f.n = n;
+    f.dim = D;
+    f.kind = kind;
+    f.T = T;
+    f.seg_host.assign(seg_host, seg_host + T + 1);
+    arborx_status st;
+    if ((st = dalloc((void **)&f.hdrs, sizeof(TreeHeader) * T, s)) != ARBORX_OK ||
+        (st = dalloc((void **)&f.seg, sizeof(int64_t) * (T + 1), s)) != ARBORX_OK ||
+        (st = dalloc(&f.nodes, (size_t)(n > 0 ? n : 1) * sizeof(Node<D>), s)) != ARBORX_OK ||
+        (st = dalloc((void **)&f.leaves, (size_t)(n > 0 ? n : 1) * leaf_floats(D, kind) * sizeof(float), s)) !=
+            ARBORX_OK)
+        return st;
+    AX_HIP(hipMemcpyAsync(f.seg, seg_host, sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, s));
+    // tiles that never straddle a tree
+    std::vector<int32_t> tt, ts, te;
+    for (int t = 0; t < T; ++t)
+        for (int64_t a = seg_host[t]; a < seg_host[t + 1]; a += kForestTile) {
+            tt.push_back(t);
+            ts.push_back((int32_t)a);
+            te.push_back((int32_t)std::min<int64_t>(a + kForestTile, seg_host[t + 1]));
+        }
+    const int tiles = (int)tt.size();
+    Temps tmp(s);
+    uint32_t *tmin, *tmax, *ids, *ids2;
+    int32_t *dtiles;
+    uint64_t *codes, *codes2;
+    unsigned long long *flags;
+    uint8_t *ws;
+    const int64_t nn = n > 0 ? n : 1;
+    if ((st = tmp.get(&tmin, (size_t)T * D)) != ARBORX_OK || (st = tmp.get(&tmax, (size_t)T * D)) != ARBORX_OK ||
+        (st = tmp.get(&dtiles, (size_t)3 * (tiles > 0 ? tiles : 1))) != ARBORX_OK ||
+        (st = tmp.get(&codes, nn)) != ARBORX_OK || (st = tmp.get(&codes2, nn)) != ARBORX_OK ||
+        (st = tmp.get(&ids, nn)) != ARBORX_OK || (st = tmp.get(&ids2, nn)) != ARBORX_OK ||
+        (st = tmp.get(&flags, nn)) != ARBORX_OK || (st = tmp.get(&ws, radix_workspace_bytes(nn))) != ARBORX_OK)
+        return st;
+    if (tiles > 0) {
+        AX_HIP(hipMemcpyAsync(dtiles, tt.data(), 4 * tiles, hipMemcpyHostToDevice, s));
+        AX_HIP(hipMemcpyAsync(dtiles + tiles, ts.data(), 4 * tiles, hipMemcpyHostToDevice, s));
+        AX_HIP(hipMemcpyAsync(dtiles + 2 * tiles, te.data(), 4 * tiles, hipMemcpyHostToDevice, s));
+    }
+    fill_kernel<uint32_t><<<grid_for((int64_t)T * D, 256), 256, 0, s>>>(tmin, (int64_t)T * D, 0xffffffffu);
+    fill_kernel<uint32_t><<<grid_for((int64_t)T * D, 256), 256, 0, s>>>(tmax, (int64_t)T * D, 0u);
+    {
+        ProfScope ps("build_bounds", s);
+        if (tiles > 0)
+            forest_tile_bounds<D><<<tiles, kBuildBlock, 0, s>>>(values, kind, dtiles, dtiles + tiles,
+                                                                dtiles + 2 * tiles, tmin, tmax);
+        forest_headers<D><<<grid_for(T, 256), 256, 0, s>>>(f.seg, T, tmin, tmax, f.hdrs);
+    }
+    AX_HIP(hipGetLastError());
+    if (n == 0)
+        return ARBORX_OK;
+    int tb = 1;
+    while ((1 << tb) < T)
+        ++tb;
+    const int mbits = (63 - tb) / D * D;
+    {
+        ProfScope ps("build_morton", s);
+        forest_tile_morton<D><<<tiles, kBuildBlock, 0, s>>>(values, kind, dtiles, dtiles + tiles, dtiles + 2 * tiles,
+                                                            f.hdrs, mbits, codes, ids);
+    }
+    bool alt = false;
+    {
+        ProfScope ps("build_sort", s);
+        AX_HIP(radix_sort_pairs<uint64_t>(codes, ids, codes2, ids2, n, 0, mbits + tb, ws, s, &alt));
+    }
+    if (alt) {
+        codes = codes2;
+        ids = ids2;
+    }
+    constexpr int C = chunk_leaves<D>();
+    const int chunks = (int)((n + C - 1) / C);
+    Escape<D> *esc;
+    if ((st = tmp.get(&esc, (size_t)2 * chunks)) != ARBORX_OK)
+        return st;
+    Node<D> *nodes = static_cast<Node<D> *>(f.nodes);
+    ProfScope ps("build_hierarchy", s);
+    hierarchy_chunk_kernel<D><<<chunks, kBuildBlock, 0, s>>>(codes, ids, values, kind, (int)n, nodes, f.leaves, flags,
+                                                             esc, f.seg, T, f.hdrs);
+    if (chunks > 1)
+        hierarchy_top_kernel<D><<<grid_for(2 * chunks, kBuildBlock), kBuildBlock, 0, s>>>(
+            codes, (int)n, nodes, flags, esc, 2 * chunks, f.seg, T, f.hdrs);
+    AX_HIP(hipGetLastError());
+    return ARBORX_OK;
 }
 
 }  // namespace
@@ -643,6 +899,32 @@ arborx_status build_tree(const float *values, int64_t n, int dim, int kind, Tree
     case 2: return build_impl<2>(values, n, kind, t, s);
     case 3: return build_impl<3>(values, n, kind, t, s);
     case 6: return build_impl<6>(values, n, kind, t, s);
+    default: return fail(ARBORX_E_UNSUPPORTED, "dimension not compiled in");
+    }
+}
+
+void forest_release(ForestDev &f, hipStream_t s)
+{
+    dfree(f.nodes, s);
+    dfree(f.leaves, s);
+    dfree(f.hdrs, s);
+    dfree(f.seg, s);
+    dfree(f.ws, s);
+    f.nodes = nullptr;
+    f.leaves = nullptr;
+    f.hdrs = nullptr;
+    f.seg = nullptr;
+    f.ws = nullptr;
+    f.ws_bytes = 0;
+}
+
+arborx_status build_forest(const float *values, const int64_t *seg_host, int T, int dim, int kind, ForestDev &f,
+                           hipStream_t s)
+{
+    switch (dim) {
+    case 2: return forest_build_impl<2>(values, seg_host, T, kind, f, s);
+    case 3: return forest_build_impl<3>(values, seg_host, T, kind, f, s);
+    case 6: return forest_build_impl<6>(values, seg_host, T, kind, f, s);
     default: return fail(ARBORX_E_UNSUPPORTED, "dimension not compiled in");
     }
 }

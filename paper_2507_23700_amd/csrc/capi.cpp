@@ -4,6 +4,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "device_util.hpp"
 #include "internal.hpp"
@@ -11,6 +12,11 @@
 
 struct arborx_tree_s {
     ax::TreeDev dev;
+    hipEvent_t ready = nullptr;
+};
+
+struct arborx_forest_s {
+    ax::ForestDev dev;
     hipEvent_t ready = nullptr;
 };
 
@@ -33,11 +39,17 @@ struct arborx_plan_s {
 namespace ax {
 
 static thread_local std::string g_error;
-static Tuning g_tuning;
+static Tuning g_tuning[OP_KINDS];
 static std::mutex g_pool_mutex;
 static bool g_pool_ready[64] = {};
 
-const Tuning &tuning() { return g_tuning; }
+const Tuning &tuning(int op) { return g_tuning[op >= 0 && op < OP_KINDS ? op : 0]; }
+
+void set_tuning_op(int op, const Tuning &t)
+{
+    if (op >= 0 && op < OP_KINDS)
+        g_tuning[op] = t;
+}
 
 void set_error(const std::string &msg) { g_error = msg; }
 
@@ -142,13 +154,9 @@ const char *arborx_version(void) { return "arborx355 0.1"; }
 
 const char *arborx_last_error(void) { return g_error.c_str(); }
 
-arborx_status arborx_set_tuning(const arborx_tuning *t)
+static arborx_status to_tuning(const arborx_tuning *t, const Tuning &base, Tuning &n)
 {
-    if (!t) {
-        g_tuning = Tuning();
-        return ARBORX_OK;
-    }
-    Tuning n = g_tuning;
+    n = base;
     if (t->block) {
         if (t->block != 64 && t->block != 128 && t->block != 256)
             return fail(ARBORX_E_INVALID, "block must be 64, 128 or 256");
@@ -162,8 +170,8 @@ arborx_status arborx_set_tuning(const arborx_tuning *t)
             return fail(ARBORX_E_INVALID, "stack must be a power of two in 1..64");
         n.stack = t->stack;
     }
-    if (t->schedule != 0)
-        return fail(ARBORX_E_UNSUPPORTED, "only the thread-per-query schedule is available");
+    if (t->schedule != 0 && t->schedule != 1)
+        return fail(ARBORX_E_INVALID, "schedule must be 0 (thread per query) or 1 (wavefront packet)");
     n.schedule = t->schedule;
     if (t->build != 0 && t->build != 1)
         return fail(ARBORX_E_INVALID, "build must be 0 or 1");
@@ -171,20 +179,65 @@ arborx_status arborx_set_tuning(const arborx_tuning *t)
     if (t->no_seed != 0 && t->no_seed != 1)
         return fail(ARBORX_E_INVALID, "no_seed must be 0 or 1");
     n.seed = t->no_seed ? 0 : 1;
-    g_tuning = n;
     return ARBORX_OK;
+}
+
+static void from_tuning(const Tuning &g, arborx_tuning *t)
+{
+    t->block = g.block;
+    t->order = g.order;
+    t->stack = g.stack;
+    t->schedule = g.schedule;
+    t->build = g.build;
+    t->no_seed = g.seed ? 0 : 1;
+}
+
+arborx_status arborx_set_tuning(const arborx_tuning *t)
+{
+    if (!t) {
+        for (auto &g : g_tuning)
+            g = Tuning();
+        return ARBORX_OK;
+    }
+    Tuning n;
+    arborx_status st = to_tuning(t, g_tuning[0], n);
+    if (st != ARBORX_OK)
+        return st;
+    for (auto &g : g_tuning)
+        g = n;
+    return ARBORX_OK;
+}
+
+arborx_status arborx_set_tuning_op(int32_t op, const arborx_tuning *t)
+{
+    if (op < 0 || op >= OP_KINDS)
+        return fail(ARBORX_E_INVALID, "unknown operation");
+    if (!t) {
+        g_tuning[op] = Tuning();
+        return ARBORX_OK;
+    }
+    Tuning n;
+    arborx_status st = to_tuning(t, g_tuning[op], n);
+    if (st == ARBORX_OK)
+        g_tuning[op] = n;
+    return st;
 }
 
 arborx_status arborx_get_tuning(arborx_tuning *t)
 {
     if (!t)
         return fail(ARBORX_E_INVALID, "tuning is NULL");
-    t->block = g_tuning.block;
-    t->order = g_tuning.order;
-    t->stack = g_tuning.stack;
-    t->schedule = g_tuning.schedule;
-    t->build = g_tuning.build;
-    t->no_seed = g_tuning.seed ? 0 : 1;
+    from_tuning(g_tuning[0], t);
+    return ARBORX_OK;
+}
+
+arborx_status arborx_get_tuning_op(int32_t op, arborx_tuning *t)
+{
+    if (!t)
+        return fail(ARBORX_E_INVALID, "tuning is NULL");
+    if (op < 0 || op >= OP_KINDS)
+        return fail(ARBORX_E_INVALID, "unknown operation");
+    from_tuning(g_tuning[op], t);
     return ARBORX_OK;
 }
 
@@ -302,7 +355,7 @@ static arborx_status csr_begin(arborx_tree t, Pred pred, const float *queries, i
         (st = p->tmp.get(&p->big_list, mm)) != ARBORX_OK || (st = p->tmp.get(&p->huge_list, mm)) != ARBORX_OK ||
         (st = p->tmp.get(&sws, scan_workspace_bytes(m))) != ARBORX_OK)
         return bail(st);
-    if ((st = query_order(t->dev, queries, m, pred, &p->perm, p->tmp, s)) != ARBORX_OK)
+    if ((st = query_order(t->dev, queries, m, pred, OP_SPATIAL, &p->perm, p->tmp, s)) != ARBORX_OK)
         return bail(st);
     if ((st = spatial_count(t->dev, pred, queries, m, radius, p->perm, p->counts, p->stash, s)) != ARBORX_OK)
         return bail(st);
@@ -414,7 +467,7 @@ arborx_status arborx_query_knn(arborx_tree t, const float *queries, int64_t m, i
         return st;
     Temps tmp(s);
     uint32_t *perm = nullptr;
-    if ((st = query_order(t->dev, queries, m, Pred::Sphere, &perm, tmp, s)) != ARBORX_OK)
+    if ((st = query_order(t->dev, queries, m, Pred::Sphere, OP_KNN, &perm, tmp, s)) != ARBORX_OK)
         return st;
     return knn_query(t->dev, queries, m, k, perm, dist2, indices, s);
 }
@@ -442,9 +495,226 @@ arborx_status arborx_query_spatial_reduce(arborx_tree t, const float *queries, i
         return st;
     Temps tmp(s);
     uint32_t *perm = nullptr;
-    if ((st = query_order(t->dev, queries, m, Pred::Sphere, &perm, tmp, s)) != ARBORX_OK)
+    if ((st = query_order(t->dev, queries, m, Pred::Sphere, OP_REDUCE, &perm, tmp, s)) != ARBORX_OK)
         return st;
     return spatial_reduce(t->dev, queries, m, radius, op, scale_bits, perm, counts, sum_fixed, s);
+}
+
+// ---------------------------------------------------------------------------
+// forest
+// ---------------------------------------------------------------------------
+
+static arborx_status forest_wait(arborx_forest f, hipStream_t s)
+{
+    // A graph being captured cannot wait on an event recorded outside it; the
+    // caller orders the build before the capture in that case.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return ARBORX_OK;
+    AX_HIP(hipStreamWaitEvent(s, f->ready, 0));
+    return ARBORX_OK;
+}
+
+arborx_status arborx_forest_build(const float *values, const int64_t *tree_offsets, int32_t T, int32_t dim,
+                                  int32_t kind, void *stream, arborx_forest *out)
+{
+    if (!out)
+        return fail(ARBORX_E_INVALID, "out is NULL");
+    if (T < 1)
+        return fail(ARBORX_E_INVALID, "T must be >= 1");
+    if (!tree_offsets)
+        return fail(ARBORX_E_INVALID, "tree_offsets is NULL");
+    if (tree_offsets[0] != 0)
+        return fail(ARBORX_E_INVALID, "tree_offsets[0] must be 0");
+    for (int t = 0; t < T; ++t)
+        if (tree_offsets[t + 1] < tree_offsets[t])
+            return fail(ARBORX_E_INVALID, "tree_offsets must be nondecreasing");
+    if (tree_offsets[T] >= INT32_MAX)
+        return fail(ARBORX_E_INVALID, "too many values");
+    if (!dim_valid(dim))
+        return fail(ARBORX_E_INVALID, "dim must be in 1..10");
+    if (kind != ARBORX_POINTS && kind != ARBORX_BOXES)
+        return fail(ARBORX_E_INVALID, "kind must be ARBORX_POINTS or ARBORX_BOXES");
+    if (tree_offsets[T] > 0 && !values)
+        return fail(ARBORX_E_INVALID, "values is NULL");
+    if (!dim_compiled(dim))
+        return fail(ARBORX_E_UNSUPPORTED, "dimension not compiled in (2, 3 and 6 are)");
+    arborx_status st = check_device();
+    if (st != ARBORX_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    arborx_forest f = new arborx_forest_s();
+    st = build_forest(values, tree_offsets, T, dim, kind, f->dev, s);
+    if (st == ARBORX_OK) {
+        hipError_t e = hipEventCreateWithFlags(&f->ready, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventRecord(f->ready, s);
+        if (e != hipSuccess)
+            st = hip_fail(e, "hipEventRecord");
+    }
+    if (st != ARBORX_OK) {
+        std::string msg = g_error;
+        (void)hipStreamSynchronize(s);
+        forest_release(f->dev, s);
+        (void)hipStreamSynchronize(s);
+        if (f->ready)
+            (void)hipEventDestroy(f->ready);
+        delete f;
+        set_error(msg);
+        return st;
+    }
+    *out = f;
+    return ARBORX_OK;
+}
+
+arborx_status arborx_forest_destroy(arborx_forest f)
+{
+    if (!f)
+        return ARBORX_OK;
+    if (f->ready)
+        (void)hipEventSynchronize(f->ready);
+    (void)hipDeviceSynchronize();
+    forest_release(f->dev, nullptr);
+    (void)hipStreamSynchronize(nullptr);
+    if (f->ready)
+        (void)hipEventDestroy(f->ready);
+    delete f;
+    return ARBORX_OK;
+}
+
+arborx_status arborx_forest_info(arborx_forest f, int32_t *T, int64_t *n, int32_t *dim, int32_t *roots,
+                                 int32_t *heights)
+{
+    if (!f)
+        return fail(ARBORX_E_INVALID, "forest is NULL");
+    if (T)
+        *T = f->dev.T;
+    if (n)
+        *n = f->dev.n;
+    if (dim)
+        *dim = f->dev.dim;
+    if (roots || heights) {
+        AX_HIP(hipEventSynchronize(f->ready));
+        std::vector<TreeHeader> h(f->dev.T);
+        AX_HIP(hipMemcpy(h.data(), f->dev.hdrs, sizeof(TreeHeader) * f->dev.T, hipMemcpyDeviceToHost));
+        for (int t = 0; t < f->dev.T; ++t) {
+            if (roots)
+                roots[t] = h[t].root;
+            if (heights)
+                heights[t] = h[t].height;
+        }
+    }
+    return ARBORX_OK;
+}
+
+arborx_status arborx_forest_reserve(arborx_forest f, int64_t m, void *stream)
+{
+    if (!f)
+        return fail(ARBORX_E_INVALID, "forest is NULL");
+    if (m < 0 || m >= INT32_MAX)
+        return fail(ARBORX_E_INVALID, "m must be in [0, 2^31-1)");
+    arborx_status st = check_device();
+    if (st != ARBORX_OK)
+        return st;
+    return forest_reserve(f->dev, m, static_cast<hipStream_t>(stream));
+}
+
+static arborx_status forest_query_args(arborx_forest f, const float *queries, int64_t m, const int64_t *boff,
+                                       const int32_t *btree, int32_t B)
+{
+    if (!f)
+        return fail(ARBORX_E_INVALID, "forest is NULL");
+    if (m < 0 || m >= INT32_MAX)
+        return fail(ARBORX_E_INVALID, "m must be in [0, 2^31-1)");
+    if (B < 1)
+        return fail(ARBORX_E_INVALID, "B must be >= 1");
+    if (m > 0 && (!queries || !boff || !btree))
+        return fail(ARBORX_E_INVALID, "queries, batch_offsets and batch_tree must not be NULL");
+    return check_device();
+}
+
+arborx_status arborx_forest_query_reduce(arborx_forest f, const float *queries, int64_t m,
+                                         const int64_t *batch_offsets, const int32_t *batch_tree,
+                                         const float *batch_radius, int32_t B, int32_t op, int32_t *counts,
+                                         int64_t *sum_fixed, int32_t scale_bits, void *stream)
+{
+    arborx_status st = forest_query_args(f, queries, m, batch_offsets, batch_tree, B);
+    if (st != ARBORX_OK)
+        return st;
+    if (op != ARBORX_COUNT && op != ARBORX_COUNT_SUMDIST)
+        return fail(ARBORX_E_INVALID, "unknown reducer");
+    if (op == ARBORX_COUNT_SUMDIST && (scale_bits < 0 || scale_bits > 40))
+        return fail(ARBORX_E_INVALID, "scale_bits must be in 0..40");
+    if (m > 0 && (!batch_radius || !counts || (op == ARBORX_COUNT_SUMDIST && !sum_fixed)))
+        return fail(ARBORX_E_INVALID, "batch_radius, counts (and sum_fixed) must not be NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = forest_wait(f, s)) != ARBORX_OK)
+        return st;
+    return forest_query_reduce(f->dev, queries, m, batch_offsets, batch_tree, batch_radius, B, op, scale_bits, counts,
+                               sum_fixed, s);
+}
+
+arborx_status arborx_forest_query_knn(arborx_forest f, const float *queries, int64_t m, const int64_t *batch_offsets,
+                                      const int32_t *batch_tree, int32_t B, int32_t k, float *dist2, int32_t *indices,
+                                      void *stream)
+{
+    arborx_status st = forest_query_args(f, queries, m, batch_offsets, batch_tree, B);
+    if (st != ARBORX_OK)
+        return st;
+    if (k < 1 || k > 64)
+        return fail(ARBORX_E_INVALID, "k must be in 1..64");
+    if (m > 0 && (!dist2 || !indices))
+        return fail(ARBORX_E_INVALID, "dist2 and indices must not be NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = forest_wait(f, s)) != ARBORX_OK)
+        return st;
+    return forest_query_knn(f->dev, queries, m, batch_offsets, batch_tree, B, k, dist2, indices, s);
+}
+
+// ---------------------------------------------------------------------------
+// Chamfer
+// ---------------------------------------------------------------------------
+
+static arborx_status chamfer_args(const float *a, const int64_t *a_off, const float *b, const int64_t *b_off, int P)
+{
+    if (P < 1)
+        return fail(ARBORX_E_INVALID, "P must be >= 1");
+    if (!a_off || !b_off)
+        return fail(ARBORX_E_INVALID, "offsets must not be NULL");
+    if (a_off[0] != 0 || b_off[0] != 0)
+        return fail(ARBORX_E_INVALID, "offsets must start at 0");
+    for (int p = 0; p < P; ++p)
+        if (a_off[p + 1] < a_off[p] || b_off[p + 1] < b_off[p])
+            return fail(ARBORX_E_INVALID, "offsets must be nondecreasing");
+    if (a_off[P] + b_off[P] >= INT32_MAX)
+        return fail(ARBORX_E_INVALID, "too many points");
+    if ((a_off[P] > 0 && !a) || (b_off[P] > 0 && !b))
+        return fail(ARBORX_E_INVALID, "point arrays must not be NULL");
+    return check_device();
+}
+
+arborx_status arborx_chamfer_forward(const float *a, const int64_t *a_off, const float *b, const int64_t *b_off,
+                                     int32_t P, float *loss, int32_t *nn_ab, int32_t *nn_ba, void *stream)
+{
+    arborx_status st = chamfer_args(a, a_off, b, b_off, P);
+    if (st != ARBORX_OK)
+        return st;
+    if (!loss || (a_off[P] > 0 && !nn_ab) || (b_off[P] > 0 && !nn_ba))
+        return fail(ARBORX_E_INVALID, "outputs must not be NULL");
+    return chamfer_forward(a, a_off, b, b_off, P, loss, nn_ab, nn_ba, static_cast<hipStream_t>(stream));
+}
+
+arborx_status arborx_chamfer_backward(const float *a, const int64_t *a_off, const float *b, const int64_t *b_off,
+                                      int32_t P, const int32_t *nn_ab, const int32_t *nn_ba, const float *grad_loss,
+                                      float *grad_a, float *grad_b, void *stream)
+{
+    arborx_status st = chamfer_args(a, a_off, b, b_off, P);
+    if (st != ARBORX_OK)
+        return st;
+    if (!grad_loss || (a_off[P] > 0 && (!nn_ab || !grad_a)) || (b_off[P] > 0 && (!nn_ba || !grad_b)))
+        return fail(ARBORX_E_INVALID, "inputs and outputs must not be NULL");
+    return chamfer_backward(a, a_off, b, b_off, P, nn_ab, nn_ba, grad_loss, grad_a, grad_b,
+                            static_cast<hipStream_t>(stream));
 }
 
 arborx_status arborx_debug_radix_sort(void *keys, uint32_t *values, int64_t n, int32_t key_bits, int32_t begin_bit,

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/arborx.h"
 
@@ -13,11 +14,13 @@ namespace ax {
 constexpr int kMaxDim = 10;
 
 // Device-resident tree header written by the build kernels.
+// Device-resident tree header written by the build kernels (one per tree of
+// a forest).
 struct TreeHeader {
     int32_t root;    // index of the root node (-1 when the tree is empty)
     int32_t height;  // edges on the longest root-to-leaf path
-    int32_t n;
-    int32_t pad;
+    int32_t n;       // values in the tree
+    int32_t start;   // position of the tree's first leaf in the sorted leaf array
     float lo[kMaxDim];
     float hi[kMaxDim];
 };
@@ -38,7 +41,10 @@ struct Tuning {
     int build = 0;
     int seed = 1;  // kNN: bound the walk with nearby leaves first
 };
-const Tuning &tuning();
+// Tuning is kept per operation kind so the autotuner can pick each separately.
+enum Op { OP_SPATIAL = 0, OP_REDUCE = 1, OP_KNN = 2, OP_KINDS = 3 };
+const Tuning &tuning(int op = OP_SPATIAL);
+void set_tuning_op(int op, const Tuning &t);
 
 // Error reporting: thread-local last message.
 void set_error(const std::string &msg);
@@ -122,14 +128,46 @@ struct TreeDev {
     TreeHeader *hdr = nullptr;
 };
 size_t node_bytes(int dim);
+// Number of node slots allocated for a tree of n values.
+inline int tree_nodes(const TreeDev &t) { return t.n > 1 ? (int)(t.n - 1) : 1; }
 arborx_status build_tree(const float *values, int64_t n, int dim, int kind, TreeDev &t, hipStream_t s);
 hipError_t morton64_points(const float *pts, int64_t n, int dim, const float *bounds, uint64_t *codes,
                            hipStream_t s);
 
+// Forest: T trees over one packed value array; tree t = values [seg[t], seg[t+1]).
+struct ForestDev {
+    int64_t n = 0;
+    int dim = 0, kind = 0, T = 0;
+    void *nodes = nullptr;     // Node<dim>[n]: one slot per split plus a spare for a last one-value tree
+    float *leaves = nullptr;   // n leaf records, sorted inside each tree
+    TreeHeader *hdrs = nullptr;  // [T]
+    int64_t *seg = nullptr;    // [T+1] device copy of the tree offsets
+    std::vector<int64_t> seg_host;
+    void *ws = nullptr;        // query workspace, grown on demand (reserve before graph capture)
+    size_t ws_bytes = 0;
+};
+arborx_status build_forest(const float *values, const int64_t *seg_host, int T, int dim, int kind, ForestDev &f,
+                           hipStream_t s);
+void forest_release(ForestDev &f, hipStream_t s);
+// Grow the query workspace to serve m queries without allocating.
+arborx_status forest_reserve(ForestDev &f, int64_t m, hipStream_t s);
+arborx_status forest_query_reduce(ForestDev &f, const float *q, int64_t m, const int64_t *boff, const int32_t *btree,
+                                  const float *brad, int B, int op, int scale_bits, int32_t *counts, int64_t *sums,
+                                  hipStream_t s);
+arborx_status forest_query_knn(ForestDev &f, const float *q, int64_t m, const int64_t *boff, const int32_t *btree,
+                               int B, int k, float *d2, int32_t *idx, hipStream_t s);
+
+// ---- Chamfer (chamfer.hip); offsets are host arrays -----------------------
+arborx_status chamfer_forward(const float *a, const int64_t *a_off, const float *b, const int64_t *b_off, int P,
+                              float *loss, int32_t *nn_ab, int32_t *nn_ba, hipStream_t s);
+arborx_status chamfer_backward(const float *a, const int64_t *a_off, const float *b, const int64_t *b_off, int P,
+                               const int32_t *nn_ab, const int32_t *nn_ba, const float *grad_loss, float *grad_a,
+                               float *grad_b, hipStream_t s);
+
 // ---- queries (query.hip) --------------------------------------------------
 enum class Pred { Sphere, Box };
-arborx_status query_order(const TreeDev &t, const float *queries, int64_t m, Pred pred, uint32_t **perm, Temps &tmp,
-                          hipStream_t s);
+arborx_status query_order(const TreeDev &t, const float *queries, int64_t m, Pred pred, int op, uint32_t **perm,
+                          Temps &tmp, hipStream_t s);
 // Count pass; also stores each query's first kRowSortRegs matches, sorted, in
 // stash[sorted position][kRowSortRegs].
 arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,

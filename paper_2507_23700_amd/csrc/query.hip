@@ -16,150 +16,19 @@
 #include "geometry.hpp"
 #include "internal.hpp"
 #include "profile.hpp"
+#include "traverse.hpp"
 
 namespace ax {
 namespace {
 
-constexpr int kSpill = 128;  // > any tree height: 63 code-bit levels + 32 position levels
-
-template <typename E>
-struct ShortStack {
-    E *lds;  // this thread's column: entry j at lds[j * stride]
-    int stride, mask;
-    int base = 0, cnt = 0, ns = 0;
-    E spill[kSpill];
-    __device__ ShortStack(E *col, int stride_, int cap) : lds(col), stride(stride_), mask(cap - 1) {}
-    __device__ __forceinline__ bool empty() const { return cnt == 0 && ns == 0; }
-    __device__ __forceinline__ void push(E x)
-    {
-        if (cnt == mask + 1) {  // ring full: move the oldest LDS entry to the spill area
-            if (ns < kSpill)
-                spill[ns++] = lds[(base & mask) * stride];
-            ++base;
-            --cnt;
-        }
-        lds[((base + cnt) & mask) * stride] = x;
-        ++cnt;
-    }
-    __device__ __forceinline__ E pop()
-    {
-        if (cnt > 0) {
-            --cnt;
-            return lds[((base + cnt) & mask) * stride];
-        }
-        return spill[--ns];
-    }
-};
-
-// Blocks are dealt round-robin over the 8 XCDs; renumber them so that each
-// XCD (and its L2) works on one contiguous run of Morton-ordered queries.
-__device__ __forceinline__ int64_t xcd_block()
-{
-    constexpr int64_t X = 8;
-    const int64_t b = blockIdx.x, G = gridDim.x;
-    const int64_t q = G / X, r = G % X, x = b % X;
-    return x * q + (x < r ? x : r) + b / X;
-}
-
+// Node slots of a single tree (one-value trees still have one node).
 __device__ __forceinline__ int node_count(const TreeHeader *hdr) { return hdr->n > 1 ? hdr->n - 1 : 1; }
-
-template <int D>
-struct Sphere {
-    float c[D];
-    float r2;
-    __device__ __forceinline__ bool hit(const float *lo, const float *hi, float &d2) const
-    {
-        d2 = box_d2<D>(c, lo, hi);
-        return d2 <= r2;
-    }
-    __device__ __forceinline__ void load(const float *q, int64_t i, float rr)
-    {
-#pragma unroll
-        for (int d = 0; d < D; ++d)
-            c[d] = q[i * D + d];
-        r2 = rr;
-    }
-};
-
-template <int D>
-struct BoxQuery {
-    float lo[D], hi[D];
-    __device__ __forceinline__ bool hit(const float *blo, const float *bhi, float &d2) const
-    {
-        d2 = 0.0f;
-        return boxes_overlap<D>(lo, hi, blo, bhi);
-    }
-    __device__ __forceinline__ void load(const float *q, int64_t i, float)
-    {
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            lo[d] = q[i * 2 * D + d];
-            hi[d] = q[i * 2 * D + D + d];
-        }
-    }
-};
-
-// Depth-first walk calling f(index, d2) on every matching value.
-// A depth-first walk enters each internal node at most once, so `limit`
-// iterations (more than the node count) bound every walk even on a corrupt
-// tree, and node indices are range-checked before use.
-template <int D, class P, class F>
-__device__ __forceinline__ void traverse_spatial(const Node<D> *__restrict__ nodes, int root, int n_nodes,
-                                                 const P &pred, ShortStack<int> &st, F &f)
-{
-    int cur = root;
-    for (int iter = 0; iter <= n_nodes; ++iter) {
-        if ((unsigned)cur >= (unsigned)n_nodes)
-            break;
-        Node<D> nd;
-        load_node(nodes, cur, nd);
-        float d0, d1;
-        bool h0 = pred.hit(nd.lo[0], nd.hi[0], d0);
-        bool h1 = pred.hit(nd.lo[1], nd.hi[1], d1);
-        const int c0 = nd.child[0], c1 = nd.child[1];
-        if (h0 && c0 < 0) {
-            if (c0 != kEmptyRef)
-                f(~c0, d0);
-            h0 = false;
-        }
-        if (h1 && c1 < 0) {
-            if (c1 != kEmptyRef)
-                f(~c1, d1);
-            h1 = false;
-        }
-        if (h0) {
-            if (h1)
-                st.push(c1);
-            cur = c0;
-        } else if (h1) {
-            cur = c1;
-        } else {
-            if (st.empty())
-                break;
-            cur = st.pop();
-        }
-    }
-}
-
-// Insert x into the ascending buffer buf[0..k) (k < C) using static indices only.
-template <int C>
-__device__ __forceinline__ void insert_sorted(int (&buf)[C], int k, int x)
-{
-    int v = x;
-#pragma unroll
-    for (int s = 0; s < C; ++s) {
-        const int a = buf[s];
-        const bool in = s < k;
-        buf[s] = in ? min(a, v) : (s == k ? v : a);
-        v = in ? max(a, v) : v;
-    }
-}
 
 // Count pass of a CSR query.  With a stash, each query also keeps its first
 // kRowSortRegs matches sorted in registers and stores them in the stash row of
 // its Morton position (64 contiguous bytes per thread, so a wavefront writes
 // one coalesced 4 KiB block); rows that fit need no second walk.
-template <int D, class P, bool STASH>
+template <int D, class P, bool STASH, bool WAVE>
 __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
                                 const float *__restrict__ queries, int64_t m, float r2,
                                 const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
@@ -167,33 +36,41 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const TreeHea
 {
     extern __shared__ int s_stack[];
     const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
-    if (t >= m)
+    if (!WAVE && t >= m)
         return;
-    const int64_t qi = perm ? (int64_t)perm[t] : t;
-    if (qi >= m)
+    int64_t qi = t < m ? (perm ? (int64_t)perm[t] : t) : m;
+    const bool active = qi < m;
+    if (!WAVE && !active)
         return;
     P pred;
-    pred.load(queries, qi, r2);
-    ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap);
+    if (active)
+        pred.load(queries, qi, r2);
+    else
+        pred.dead();
+    int spill[kSpill];
+    ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap, spill);
+    int *wstack = s_stack + wave_id() * kWaveStack;
     int c = 0;
-    if (STASH) {
-        int buf[kRowSortRegs];
+    int buf[kRowSortRegs];
 #pragma unroll
-        for (int k = 0; k < kRowSortRegs; ++k)
-            buf[k] = 0;
-        auto f = [&](int idx, float) {
-            if (c < kRowSortRegs)
-                insert_sorted<kRowSortRegs>(buf, c, idx);
-            ++c;
-        };
+    for (int k = 0; k < kRowSortRegs; ++k)
+        buf[k] = 0;
+    auto f = [&](int idx, float) {
+        if (STASH && c < kRowSortRegs)
+            insert_sorted<kRowSortRegs>(buf, c, idx);
+        ++c;
+    };
+    if (WAVE)
+        traverse_spatial_wave<D>(nodes, hdr->root, node_count(hdr), pred, wstack, f);
+    else
         traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
+    if (!active)
+        return;
+    if (STASH) {
         int4 *row = reinterpret_cast<int4 *>(stash + t * kRowSortRegs);
 #pragma unroll
         for (int k = 0; k < kRowSortRegs / 4; ++k)
             row[k] = make_int4(buf[4 * k], buf[4 * k + 1], buf[4 * k + 2], buf[4 * k + 3]);
-    } else {
-        auto f = [&](int, float) { ++c; };
-        traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
     }
     counts[qi] = c;
 }
@@ -246,7 +123,8 @@ __global__ void k_spatial_fill_rows(const Node<D> *__restrict__ nodes, const Tre
         return;
     P pred;
     pred.load(queries, qi, r2);
-    ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap);
+    int spill[kSpill];
+    ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap, spill);
     const int64_t o = offsets[qi];
     const int64_t len = offsets[qi + 1] - o;
     int64_t k = 0;
@@ -333,7 +211,7 @@ __global__ void k_huge_scatter(const uint64_t *__restrict__ keys, int64_t total,
     }
 }
 
-template <int D, bool SUMDIST>
+template <int D, bool SUMDIST, bool WAVE>
 __global__ void k_spatial_reduce(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
                                  const float *__restrict__ queries, int64_t m, float r2, float scale,
                                  const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
@@ -341,14 +219,20 @@ __global__ void k_spatial_reduce(const Node<D> *__restrict__ nodes, const TreeHe
 {
     extern __shared__ int s_stack[];
     const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
-    if (t >= m)
+    if (!WAVE && t >= m)
         return;
-    const int64_t qi = perm ? (int64_t)perm[t] : t;
-    if (qi >= m)
+    const int64_t qi = t < m ? (perm ? (int64_t)perm[t] : t) : m;
+    const bool active = qi < m;
+    if (!WAVE && !active)
         return;
     Sphere<D> pred;
-    pred.load(queries, qi, r2);
-    ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap);
+    if (active)
+        pred.load(queries, qi, r2);
+    else
+        pred.dead();
+    int spill[kSpill];
+    ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap, spill);
+    int *wstack = s_stack + wave_id() * kWaveStack;
     int c = 0;
     long long s = 0;
     auto f = [&](int, float d2) {
@@ -359,170 +243,47 @@ __global__ void k_spatial_reduce(const Node<D> *__restrict__ nodes, const TreeHe
             s += (long long)scaled;
         }
     };
-    traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
+    if (WAVE)
+        traverse_spatial_wave<D>(nodes, hdr->root, node_count(hdr), pred, wstack, f);
+    else
+        traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
+    if (!active)
+        return;
     counts[qi] = c;
     if (SUMDIST)
         sums[qi] = s;
 }
 
-struct KnnEntry {
-    int32_t ref;
-    float d2;
-};
-
-template <int K>
-__device__ __forceinline__ void knn_offer(float (&bd)[K], int (&bi)[K], float d, int id)
-{
-    if (!(d < bd[K - 1] || (d == bd[K - 1] && id < bi[K - 1])))
-        return;
-    float vd = d;
-    int vi = id;
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
-        const bool lt = vd < bd[s] || (vd == bd[s] && vi < bi[s]);
-        const float td = bd[s];
-        const int ti = bi[s];
-        bd[s] = lt ? vd : td;
-        bi[s] = lt ? vi : ti;
-        vd = lt ? td : vd;
-        vi = lt ? ti : vi;
-    }
-}
-
-// Squared distance from q to the value stored in leaf record `pos`.
-template <int D>
-__device__ __forceinline__ float leaf_d2(const float *__restrict__ leaves, int kind, int64_t pos, const float *q)
-{
-    const float *lf = leaves + pos * leaf_floats(D, kind);
-    float lo[D], hi[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        lo[d] = lf[d];
-        hi[d] = kind == ARBORX_BOXES ? lf[D + d] : lf[d];
-    }
-    return box_d2<D>(q, lo, hi);
-}
-
-// Nearest-first walk keeping the K best (d2, index) pairs sorted in
-// registers; a subtree is skipped only if its box is strictly farther than the
-// current K-th pair, so equal-distance values with smaller indices are found.
-//
-// Seeding: a greedy descent (nearer child first) finds the query's position in
-// the sorted leaves; the K-th smallest distance among the 2K leaves around it
-// bounds the K-th nearest distance from above, so the walk starts with that
-// bound instead of +inf.  The heap starts as K copies of (bound, INT32_MAX):
-// every value at distance < bound, or == bound, orders before them, so all
-// true results are still admitted and none of the placeholders survive when
-// n >= K.
-template <int D, int K>
-__global__ void k_knn(const Node<D> *__restrict__ nodes, const float *__restrict__ leaves, int kind,
+template <int D, int K, bool WAVE>
+__global__ void k_knn(const Node<D> *__restrict__ nodes, int n_nodes, const float *__restrict__ leaves, int kind,
                       const TreeHeader *__restrict__ hdr, const float *__restrict__ queries, int64_t m, int k_out,
                       const uint32_t *__restrict__ perm, float *__restrict__ out_d2, int32_t *__restrict__ out_idx,
                       int stack_cap, int seed)
 {
     extern __shared__ int s_stack[];
     const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
-    if (t >= m)
+    if (!WAVE && t >= m)
         return;
-    const int64_t qi = perm ? (int64_t)perm[t] : t;
-    if (qi >= m)
+    const int64_t qi = t < m ? (perm ? (int64_t)perm[t] : t) : m;
+    const bool active = qi < m;
+    if (!WAVE && !active)
         return;
     float q[D];
 #pragma unroll
     for (int d = 0; d < D; ++d)
-        q[d] = queries[qi * D + d];
-    const int n = hdr->n;
-    const int n_nodes = node_count(hdr);
+        q[d] = active ? queries[qi * D + d] : 0.0f;
     float bd[K];
     int bi[K];
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
-        bd[s] = INFINITY;
-        bi[s] = INT32_MAX;
+    if (WAVE) {
+        KnnEntry *wstack = reinterpret_cast<KnnEntry *>(s_stack) + wave_id() * kWaveStack;
+        knn_search_wave<D, K>(nodes, n_nodes, leaves, kind, *hdr, q, active, bd, bi, wstack, seed);
+    } else {
+        KnnEntry spill[kSpill];
+        ShortStack<KnnEntry> st(reinterpret_cast<KnnEntry *>(s_stack) + threadIdx.x, blockDim.x, stack_cap, spill);
+        knn_search<D, K>(nodes, n_nodes, leaves, kind, *hdr, q, bd, bi, st, seed);
     }
-    if (seed && n >= K) {
-        int cur = hdr->root, pos = 0;
-        for (int iter = 0; iter <= n_nodes; ++iter) {
-            if ((unsigned)cur >= (unsigned)n_nodes)
-                break;
-            Node<D> nd;
-            load_node(nodes, cur, nd);
-            const float d0 = box_d2<D>(q, nd.lo[0], nd.hi[0]);
-            const float d1 = box_d2<D>(q, nd.lo[1], nd.hi[1]);
-            const int go = d1 < d0 ? 1 : 0;
-            const int c = go ? nd.child[1] : nd.child[0];
-            if (c < 0) {
-                pos = cur + go;  // node cur separates sorted leaves cur and cur + 1
-                break;
-            }
-            cur = c;
-        }
-        int w0 = pos - K;
-        w0 = w0 < 0 ? 0 : w0;
-        w0 = w0 > n - 2 * K ? n - 2 * K : w0;
-        w0 = w0 < 0 ? 0 : w0;
-        const int w1 = (w0 + 2 * K < n) ? w0 + 2 * K : n;
-        for (int p = w0; p < w1; ++p) {
-            const float d = leaf_d2<D>(leaves, kind, p, q);
-            knn_offer<K>(bd, bi, d, p);  // positions are distinct keys; only the distances matter here
-        }
-        const float bound = bd[K - 1];
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            bd[s] = bound;
-            bi[s] = INT32_MAX;
-        }
-    }
-    ShortStack<KnnEntry> st(reinterpret_cast<KnnEntry *>(s_stack) + threadIdx.x, blockDim.x, stack_cap);
-    int cur = hdr->root;
-    for (int iter = 0; iter <= n_nodes; ++iter) {
-        if ((unsigned)cur >= (unsigned)n_nodes)
-            break;
-        Node<D> nd;
-        load_node(nodes, cur, nd);
-        const float d0 = box_d2<D>(q, nd.lo[0], nd.hi[0]);
-        const float d1 = box_d2<D>(q, nd.lo[1], nd.hi[1]);
-        const int c0 = nd.child[0], c1 = nd.child[1];
-        if (c0 < 0 && c0 != kEmptyRef)
-            knn_offer<K>(bd, bi, d0, ~c0);
-        if (c1 < 0 && c1 != kEmptyRef)
-            knn_offer<K>(bd, bi, d1, ~c1);
-        const bool k0 = c0 >= 0 && !(d0 > bd[K - 1]);
-        const bool k1 = c1 >= 0 && !(d1 > bd[K - 1]);
-        if (k0 && k1) {
-            if (d1 < d0) {
-                st.push(KnnEntry{c0, d0});
-                cur = c1;
-            } else {
-                st.push(KnnEntry{c1, d1});
-                cur = c0;
-            }
-        } else if (k0) {
-            cur = c0;
-        } else if (k1) {
-            cur = c1;
-        } else {
-            bool found = false;
-            while (!st.empty()) {
-                const KnnEntry e = st.pop();
-                if (!(e.d2 > bd[K - 1])) {
-                    cur = e.ref;
-                    found = true;
-                    break;
-                }
-            }
-            if (!found)
-                break;
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
-        if (s < k_out) {
-            const bool empty = bi[s] == INT32_MAX;
-            out_d2[qi * k_out + s] = empty ? INFINITY : bd[s];
-            out_idx[qi * k_out + s] = empty ? -1 : bi[s];
-        }
-    }
+    if (active)
+        knn_store<K>(bd, bi, k_out, out_d2 + qi * k_out, out_idx + qi * k_out);
 }
 
 __global__ void k_knn_empty(int64_t total, float *d2, int32_t *idx)
@@ -579,16 +340,16 @@ struct Launch {
     size_t lds;
 };
 
-Launch traversal_launch(int64_t m, size_t entry_bytes)
+Launch traversal_launch(int64_t m, size_t entry_bytes, int op, bool wave = false)
 {
-    const Tuning &tu = tuning();
+    const Tuning &tu = tuning(op);
     Launch L;
     L.block = tu.block;
     L.cap = tu.stack;
     L.grid = (unsigned)((m + L.block - 1) / L.block);
     while (L.cap > 1 && (size_t)L.cap * L.block * entry_bytes > 65536)
         L.cap >>= 1;
-    L.lds = (size_t)L.cap * L.block * entry_bytes;
+    L.lds = wave ? (size_t)(L.block / kWave) * kWaveStack * entry_bytes : (size_t)L.cap * L.block * entry_bytes;
     return L;
 }
 
@@ -596,15 +357,25 @@ template <int D>
 arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m, float r2, const uint32_t *perm,
                          int32_t *counts, int32_t *stash, hipStream_t s)
 {
-    const Launch L = traversal_launch(m, sizeof(int));
+    const bool wave = tuning(OP_SPATIAL).schedule == 1;
+    const Launch L = traversal_launch(m, sizeof(int), OP_SPATIAL, wave);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     ProfScope ps("spatial_count", s);
-    if (pred == Pred::Sphere)
-        k_spatial_count<D, Sphere<D>, true><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, counts,
-                                                                           stash, L.cap);
-    else
-        k_spatial_count<D, BoxQuery<D>, true><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, counts,
-                                                                             stash, L.cap);
+    if (pred == Pred::Sphere) {
+        if (wave)
+            k_spatial_count<D, Sphere<D>, true, true><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm,
+                                                                                     counts, stash, L.cap);
+        else
+            k_spatial_count<D, Sphere<D>, true, false><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm,
+                                                                                      counts, stash, L.cap);
+    } else {
+        if (wave)
+            k_spatial_count<D, BoxQuery<D>, true, true><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm,
+                                                                                       counts, stash, L.cap);
+        else
+            k_spatial_count<D, BoxQuery<D>, true, false><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm,
+                                                                                        counts, stash, L.cap);
+    }
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
@@ -615,7 +386,7 @@ arborx_status fill_rows_impl(const TreeDev &t, Pred pred, const float *q, int64_
 {
     if (nrows <= 0)
         return ARBORX_OK;
-    Launch L = traversal_launch(nrows, sizeof(int));
+    Launch L = traversal_launch(nrows, sizeof(int), OP_SPATIAL);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     ProfScope ps("spatial_fill", s);
     if (pred == Pred::Sphere)
@@ -632,15 +403,25 @@ template <int D>
 arborx_status reduce_impl(const TreeDev &t, const float *q, int64_t m, float r2, int op, float scale,
                           const uint32_t *perm, int32_t *counts, int64_t *sums, hipStream_t s)
 {
-    const Launch L = traversal_launch(m, sizeof(int));
+    const bool wave = tuning(OP_REDUCE).schedule == 1;
+    const Launch L = traversal_launch(m, sizeof(int), OP_REDUCE, wave);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     ProfScope ps(op == ARBORX_COUNT_SUMDIST ? "reduce_sumdist" : "reduce_count", s);
-    if (op == ARBORX_COUNT_SUMDIST)
-        k_spatial_reduce<D, true><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, scale, perm, counts, sums,
-                                                                 L.cap);
-    else
-        k_spatial_reduce<D, false><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, scale, perm, counts, sums,
-                                                                  L.cap);
+    if (op == ARBORX_COUNT_SUMDIST) {
+        if (wave)
+            k_spatial_reduce<D, true, true><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, scale, perm,
+                                                                           counts, sums, L.cap);
+        else
+            k_spatial_reduce<D, true, false><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, scale, perm,
+                                                                            counts, sums, L.cap);
+    } else {
+        if (wave)
+            k_spatial_reduce<D, false, true><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, scale, perm,
+                                                                            counts, sums, L.cap);
+        else
+            k_spatial_reduce<D, false, false><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, scale, perm,
+                                                                             counts, sums, L.cap);
+    }
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
@@ -649,10 +430,17 @@ template <int D, int K>
 arborx_status knn_launch(const TreeDev &t, const float *q, int64_t m, int k, const uint32_t *perm, float *d2,
                          int32_t *idx, hipStream_t s)
 {
-    const Launch L = traversal_launch(m, sizeof(KnnEntry));
+    const bool wave = tuning(OP_KNN).schedule == 1;
+    const Launch L = traversal_launch(m, sizeof(KnnEntry), OP_KNN, wave);
     ProfScope ps("knn", s);
-    k_knn<D, K><<<L.grid, L.block, L.lds, s>>>(static_cast<const Node<D> *>(t.nodes), t.leaves, t.kind, t.hdr, q, m,
-                                                k, perm, d2, idx, L.cap, tuning().seed);
+    if (wave)
+        k_knn<D, K, true><<<L.grid, L.block, L.lds, s>>>(static_cast<const Node<D> *>(t.nodes), tree_nodes(t),
+                                                          t.leaves, t.kind, t.hdr, q, m, k, perm, d2, idx, L.cap,
+                                                          tuning(OP_KNN).seed);
+    else
+        k_knn<D, K, false><<<L.grid, L.block, L.lds, s>>>(static_cast<const Node<D> *>(t.nodes), tree_nodes(t),
+                                                           t.leaves, t.kind, t.hdr, q, m, k, perm, d2, idx, L.cap,
+                                                           tuning(OP_KNN).seed);
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
@@ -710,11 +498,11 @@ arborx_status order_impl(const TreeDev &t, const float *q, int64_t m, Pred pred,
 
 }  // namespace
 
-arborx_status query_order(const TreeDev &t, const float *queries, int64_t m, Pred pred, uint32_t **perm, Temps &tmp,
-                          hipStream_t s)
+arborx_status query_order(const TreeDev &t, const float *queries, int64_t m, Pred pred, int op, uint32_t **perm,
+                          Temps &tmp, hipStream_t s)
 {
     *perm = nullptr;
-    if (!tuning().order || t.n == 0 || m <= 1)
+    if (!tuning(op).order || t.n == 0 || m <= 1)
         return ARBORX_OK;
     AX_DISPATCH_DIM(t.dim, (order_impl<D>(t, queries, m, pred, perm, tmp, s)));
 }

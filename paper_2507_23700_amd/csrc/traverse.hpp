@@ -1,0 +1,481 @@
+// Device-side traversal pieces shared by the single-tree and forest queries:
+// the short stack, query predicates, the depth-first spatial walk, the sorted
+// register buffers, and the seeded nearest-first kNN walk.
+#pragma once
+
+#include "device_util.hpp"
+#include "geometry.hpp"
+#include "internal.hpp"
+
+namespace ax {
+namespace {
+
+constexpr int kSpill = 128;  // > any tree height: 63 code-bit levels + 32 position levels
+
+// The ring indices live in registers; only the rarely used spill area (a
+// separate private array owned by the caller) sits in scratch memory.  Keeping
+// the array out of this struct lets the compiler hold the counters in
+// registers instead of reloading them from scratch on every push and pop.
+template <typename E>
+struct ShortStack {
+    E *lds;  // this thread's column: entry j at lds[j * stride]
+    E *spill;
+    int stride, mask;
+    int base = 0, cnt = 0, ns = 0;
+    __device__ ShortStack(E *col, int stride_, int cap, E *spill_) : lds(col), spill(spill_), stride(stride_),
+                                                                      mask(cap - 1) {}
+    __device__ __forceinline__ bool empty() const { return cnt == 0 && ns == 0; }
+    __device__ __forceinline__ void push(E x)
+    {
+        if (cnt == mask + 1) {  // ring full: move the oldest LDS entry to the spill area
+            if (ns < kSpill)
+                spill[ns++] = lds[(base & mask) * stride];
+            ++base;
+            --cnt;
+        }
+        lds[((base + cnt) & mask) * stride] = x;
+        ++cnt;
+    }
+    __device__ __forceinline__ E pop()
+    {
+        if (cnt > 0) {
+            --cnt;
+            return lds[((base + cnt) & mask) * stride];
+        }
+        return spill[--ns];
+    }
+};
+
+// Blocks are dealt round-robin over the 8 XCDs; renumber them so that each
+// XCD (and its L2) works on one contiguous run of Morton-ordered queries.
+__device__ __forceinline__ int64_t xcd_block()
+{
+    constexpr int64_t X = 8;
+    const int64_t b = blockIdx.x, G = gridDim.x;
+    const int64_t q = G / X, r = G % X, x = b % X;
+    return x * q + (x < r ? x : r) + b / X;
+}
+
+template <int D>
+struct Sphere {
+    float c[D];
+    float r2;
+    __device__ __forceinline__ bool hit(const float *lo, const float *hi, float &d2) const
+    {
+        d2 = box_d2<D>(c, lo, hi);
+        return d2 <= r2;
+    }
+    __device__ __forceinline__ void load(const float *q, int64_t i, float rr)
+    {
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            c[d] = q[i * D + d];
+        r2 = rr;
+    }
+    __device__ __forceinline__ void dead()  // matches nothing: d2 >= 0 > r2
+    {
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            c[d] = 0.0f;
+        r2 = -1.0f;
+    }
+};
+
+template <int D>
+struct BoxQuery {
+    float lo[D], hi[D];
+    __device__ __forceinline__ bool hit(const float *blo, const float *bhi, float &d2) const
+    {
+        d2 = 0.0f;
+        return boxes_overlap<D>(lo, hi, blo, bhi);
+    }
+    __device__ __forceinline__ void load(const float *q, int64_t i, float)
+    {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            lo[d] = q[i * 2 * D + d];
+            hi[d] = q[i * 2 * D + D + d];
+        }
+    }
+    __device__ __forceinline__ void dead()  // an empty box overlaps nothing
+    {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            lo[d] = INFINITY;
+            hi[d] = -INFINITY;
+        }
+    }
+};
+
+// Depth-first walk calling f(index, d2) on every matching value.
+// A depth-first walk enters each internal node at most once, so `limit`
+// iterations (more than the node count) bound every walk even on a corrupt
+// tree, and node indices are range-checked before use.
+template <int D, class P, class F>
+__device__ __forceinline__ void traverse_spatial(const Node<D> *__restrict__ nodes, int root, int n_nodes,
+                                                 const P &pred, ShortStack<int> &st, F &f)
+{
+    int cur = root;
+    for (int iter = 0; iter <= n_nodes; ++iter) {
+        if ((unsigned)cur >= (unsigned)n_nodes)
+            break;
+        Node<D> nd;
+        load_node(nodes, cur, nd);
+        float d0, d1;
+        bool h0 = pred.hit(nd.lo[0], nd.hi[0], d0);
+        bool h1 = pred.hit(nd.lo[1], nd.hi[1], d1);
+        const int c0 = nd.child[0], c1 = nd.child[1];
+        if (h0 && c0 < 0) {
+            if (c0 != kEmptyRef)
+                f(~c0, d0);
+            h0 = false;
+        }
+        if (h1 && c1 < 0) {
+            if (c1 != kEmptyRef)
+                f(~c1, d1);
+            h1 = false;
+        }
+        if (h0) {
+            if (h1)
+                st.push(c1);
+            cur = c0;
+        } else if (h1) {
+            cur = c1;
+        } else {
+            if (st.empty())
+                break;
+            cur = st.pop();
+        }
+    }
+}
+
+// Wavefront-packet form of the walk: the 64 lanes (64 Morton-neighbouring
+// queries) visit the union of their paths together.  The node index is the
+// same in every lane, so each node is fetched once per wavefront through the
+// scalar cache, and the stack of deferred nodes is one per wavefront in LDS.
+// A stack entry is pushed only at a level where some lane needs both
+// children, so its depth never exceeds the tree height (at most 63 code-bit
+// levels plus 32 position levels), below kWaveStack.  Lanes without a query
+// (`active` false) carry a predicate that matches nothing.
+constexpr int kWaveStack = 128;
+
+template <int D, class P, class F>
+__device__ __forceinline__ void traverse_spatial_wave(const Node<D> *__restrict__ nodes, int root, int n_nodes,
+                                                      const P &pred, int *wstack, F &f)
+{
+    int sp = 0;
+    int cur = root;
+    for (int iter = 0; iter <= n_nodes; ++iter) {
+        cur = __builtin_amdgcn_readfirstlane(cur);
+        if ((unsigned)cur >= (unsigned)n_nodes)
+            break;
+        Node<D> nd;
+        load_node(nodes, cur, nd);
+        float d0, d1;
+        bool h0 = pred.hit(nd.lo[0], nd.hi[0], d0);
+        bool h1 = pred.hit(nd.lo[1], nd.hi[1], d1);
+        const int c0 = nd.child[0], c1 = nd.child[1];
+        if (c0 < 0) {
+            if (h0 && c0 != kEmptyRef)
+                f(~c0, d0);
+            h0 = false;
+        }
+        if (c1 < 0) {
+            if (h1 && c1 != kEmptyRef)
+                f(~c1, d1);
+            h1 = false;
+        }
+        const bool any0 = __ballot(h0) != 0, any1 = __ballot(h1) != 0;
+        if (any0) {
+            if (any1) {
+                if (sp < kWaveStack)
+                    wstack[sp] = c1;
+                ++sp;
+            }
+            cur = c0;
+        } else if (any1) {
+            cur = c1;
+        } else {
+            if (sp == 0)
+                break;
+            --sp;
+            cur = sp < kWaveStack ? wstack[sp] : -1;
+        }
+    }
+}
+
+// Insert x into the ascending buffer buf[0..k) (k < C) using static indices only.
+template <int C>
+__device__ __forceinline__ void insert_sorted(int (&buf)[C], int k, int x)
+{
+    int v = x;
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+        const int a = buf[s];
+        const bool in = s < k;
+        buf[s] = in ? min(a, v) : (s == k ? v : a);
+        v = in ? max(a, v) : v;
+    }
+}
+
+struct KnnEntry {
+    int32_t ref;
+    float d2;
+};
+
+template <int K>
+__device__ __forceinline__ void knn_offer(float (&bd)[K], int (&bi)[K], float d, int id)
+{
+    if (!(d < bd[K - 1] || (d == bd[K - 1] && id < bi[K - 1])))
+        return;
+    float vd = d;
+    int vi = id;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const bool lt = vd < bd[s] || (vd == bd[s] && vi < bi[s]);
+        const float td = bd[s];
+        const int ti = bi[s];
+        bd[s] = lt ? vd : td;
+        bi[s] = lt ? vi : ti;
+        vd = lt ? td : vd;
+        vi = lt ? ti : vi;
+    }
+}
+
+// Squared distance from q to the value stored in leaf record `pos`.
+template <int D>
+__device__ __forceinline__ float leaf_d2(const float *__restrict__ leaves, int kind, int64_t pos, const float *q)
+{
+    const float *lf = leaves + pos * leaf_floats(D, kind);
+    float lo[D], hi[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = lf[d];
+        hi[d] = kind == ARBORX_BOXES ? lf[D + d] : lf[d];
+    }
+    return box_d2<D>(q, lo, hi);
+}
+
+// Nearest-first walk keeping the K best (d2, index) pairs sorted in
+// registers; a subtree is skipped only if its box is strictly farther than the
+// current K-th pair, so equal-distance values with smaller indices are found.
+//
+// Seeding: a greedy descent (nearer child first) finds the query's position in
+// the tree's sorted leaves; the K-th smallest distance among the 2K leaves
+// around it bounds the K-th nearest distance from above, so the walk starts
+// with that bound instead of +inf.  The heap then starts as K copies of
+// (bound, INT32_MAX): every value at distance < bound, or == bound, orders
+// before them, so all true results are still admitted, and none of the
+// placeholders survive when the tree has at least K values.
+template <int D, int K>
+__device__ __forceinline__ void knn_search(const Node<D> *__restrict__ nodes, int n_nodes,
+                                           const float *__restrict__ leaves, int kind, const TreeHeader &hdr,
+                                           const float *q, float (&bd)[K], int (&bi)[K], ShortStack<KnnEntry> &st,
+                                           int seed)
+{
+    const int n = hdr.n;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        bd[s] = INFINITY;
+        bi[s] = INT32_MAX;
+    }
+    if (n <= 0)
+        return;
+    if (seed && n >= K) {
+        int cur = hdr.root, pos = hdr.start;
+        for (int iter = 0; iter <= n_nodes; ++iter) {
+            if ((unsigned)cur >= (unsigned)n_nodes)
+                break;
+            Node<D> nd;
+            load_node(nodes, cur, nd);
+            const float d0 = box_d2<D>(q, nd.lo[0], nd.hi[0]);
+            const float d1 = box_d2<D>(q, nd.lo[1], nd.hi[1]);
+            const int go = d1 < d0 ? 1 : 0;
+            const int c = go ? nd.child[1] : nd.child[0];
+            if (c < 0) {
+                pos = cur + go;  // node cur separates sorted leaves cur and cur + 1
+                break;
+            }
+            cur = c;
+        }
+        // window of 2K leaves around pos inside [start, start + n)
+        int w0 = pos - K;
+        const int lo_lim = hdr.start, hi_lim = hdr.start + n;
+        w0 = w0 > hi_lim - 2 * K ? hi_lim - 2 * K : w0;
+        w0 = w0 < lo_lim ? lo_lim : w0;
+        const int w1 = (w0 + 2 * K < hi_lim) ? w0 + 2 * K : hi_lim;
+        for (int p = w0; p < w1; ++p)
+            knn_offer<K>(bd, bi, leaf_d2<D>(leaves, kind, p, q), p);  // distinct keys; only distances matter
+        const float bound = bd[K - 1];
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            bd[s] = bound;
+            bi[s] = INT32_MAX;
+        }
+    }
+    int cur = hdr.root;
+    for (int iter = 0; iter <= n_nodes; ++iter) {
+        if ((unsigned)cur >= (unsigned)n_nodes)
+            break;
+        Node<D> nd;
+        load_node(nodes, cur, nd);
+        const float d0 = box_d2<D>(q, nd.lo[0], nd.hi[0]);
+        const float d1 = box_d2<D>(q, nd.lo[1], nd.hi[1]);
+        const int c0 = nd.child[0], c1 = nd.child[1];
+        if (c0 < 0 && c0 != kEmptyRef)
+            knn_offer<K>(bd, bi, d0, ~c0);
+        if (c1 < 0 && c1 != kEmptyRef)
+            knn_offer<K>(bd, bi, d1, ~c1);
+        const bool k0 = c0 >= 0 && !(d0 > bd[K - 1]);
+        const bool k1 = c1 >= 0 && !(d1 > bd[K - 1]);
+        if (k0 && k1) {
+            if (d1 < d0) {
+                st.push(KnnEntry{c0, d0});
+                cur = c1;
+            } else {
+                st.push(KnnEntry{c1, d1});
+                cur = c0;
+            }
+        } else if (k0) {
+            cur = c0;
+        } else if (k1) {
+            cur = c1;
+        } else {
+            bool found = false;
+            while (!st.empty()) {
+                const KnnEntry e = st.pop();
+                if (!(e.d2 > bd[K - 1])) {
+                    cur = e.ref;
+                    found = true;
+                    break;
+                }
+            }
+            if (!found)
+                break;
+        }
+    }
+}
+
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1)
+        v = fminf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Wavefront-packet kNN walk (single tree: every lane shares the root).  Each
+// lane keeps its own top-K and bound; a child is entered when some lane's
+// bound admits it.  The nearer child for most lanes goes first; the deferred
+// child is stored with the smallest distance any lane has to it, and is
+// skipped at pop time only when that distance exceeds every lane's bound.
+// Seeding (per lane) is as in knn_search.
+template <int D, int K>
+__device__ __forceinline__ void knn_search_wave(const Node<D> *__restrict__ nodes, int n_nodes,
+                                                const float *__restrict__ leaves, int kind, const TreeHeader &hdr,
+                                                const float *q, bool active, float (&bd)[K], int (&bi)[K],
+                                                KnnEntry *wstack, int seed)
+{
+    const int n = hdr.n;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        bd[s] = INFINITY;
+        bi[s] = INT32_MAX;
+    }
+    if (n <= 0)
+        return;
+    if (active && seed && n >= K) {
+        int cur = hdr.root, pos = hdr.start;
+        for (int iter = 0; iter <= n_nodes; ++iter) {
+            if ((unsigned)cur >= (unsigned)n_nodes)
+                break;
+            Node<D> nd;
+            load_node(nodes, cur, nd);
+            const float d0 = box_d2<D>(q, nd.lo[0], nd.hi[0]);
+            const float d1 = box_d2<D>(q, nd.lo[1], nd.hi[1]);
+            const int go = d1 < d0 ? 1 : 0;
+            const int c = go ? nd.child[1] : nd.child[0];
+            if (c < 0) {
+                pos = cur + go;
+                break;
+            }
+            cur = c;
+        }
+        int w0 = pos - K;
+        const int lo_lim = hdr.start, hi_lim = hdr.start + n;
+        w0 = w0 > hi_lim - 2 * K ? hi_lim - 2 * K : w0;
+        w0 = w0 < lo_lim ? lo_lim : w0;
+        const int w1 = (w0 + 2 * K < hi_lim) ? w0 + 2 * K : hi_lim;
+        for (int p = w0; p < w1; ++p)
+            knn_offer<K>(bd, bi, leaf_d2<D>(leaves, kind, p, q), p);
+        const float bound = bd[K - 1];
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            bd[s] = bound;
+            bi[s] = INT32_MAX;
+        }
+    }
+    int sp = 0;
+    int cur = hdr.root;
+    for (int iter = 0; iter <= n_nodes; ++iter) {
+        cur = __builtin_amdgcn_readfirstlane(cur);
+        if ((unsigned)cur >= (unsigned)n_nodes)
+            break;
+        Node<D> nd;
+        load_node(nodes, cur, nd);
+        const float d0 = box_d2<D>(q, nd.lo[0], nd.hi[0]);
+        const float d1 = box_d2<D>(q, nd.lo[1], nd.hi[1]);
+        const int c0 = nd.child[0], c1 = nd.child[1];
+        if (active && c0 < 0 && c0 != kEmptyRef)
+            knn_offer<K>(bd, bi, d0, ~c0);
+        if (active && c1 < 0 && c1 != kEmptyRef)
+            knn_offer<K>(bd, bi, d1, ~c1);
+        const bool k0 = active && c0 >= 0 && !(d0 > bd[K - 1]);
+        const bool k1 = active && c1 >= 0 && !(d1 > bd[K - 1]);
+        const bool any0 = __ballot(k0) != 0, any1 = __ballot(k1) != 0;
+        if (any0 && any1) {
+            const bool want1 = (k0 || k1) && d1 < d0;
+            const bool want0 = (k0 || k1) && !(d1 < d0);
+            const bool first1 = __popcll(__ballot(want1)) > __popcll(__ballot(want0));
+            const int far = first1 ? c0 : c1;
+            const float dfar = wave_min(first1 ? (k0 ? d0 : INFINITY) : (k1 ? d1 : INFINITY));
+            if (sp < kWaveStack)
+                wstack[sp] = KnnEntry{far, dfar};
+            ++sp;
+            cur = first1 ? c1 : c0;
+        } else if (any0) {
+            cur = c0;
+        } else if (any1) {
+            cur = c1;
+        } else {
+            cur = -1;
+            while (sp > 0) {
+                --sp;
+                const KnnEntry e = sp < kWaveStack ? wstack[sp] : KnnEntry{-1, INFINITY};
+                if (__ballot(active && !(e.d2 > bd[K - 1])) != 0) {
+                    cur = e.ref;
+                    break;
+                }
+            }
+            if (cur < 0)
+                break;
+        }
+    }
+}
+
+// Write the first k_out of the K best; empty slots become (+inf, -1).
+template <int K>
+__device__ __forceinline__ void knn_store(const float (&bd)[K], const int (&bi)[K], int k_out, float *d2, int32_t *idx)
+{
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        if (s < k_out) {
+            const bool empty = bi[s] == INT32_MAX;
+            d2[s] = empty ? INFINITY : bd[s];
+            idx[s] = empty ? -1 : bi[s];
+        }
+    }
+}
+
+}  // namespace
+}  // namespace ax

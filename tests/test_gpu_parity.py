@@ -352,12 +352,13 @@ def test_capacity_protocol():
     assert total.value == o_off[-1] and np.array_equal(host(off), o_off)
 
 
-@pytest.mark.parametrize("block,order,stack", [(64, 1, 1), (128, 0, 2), (256, 1, 4), (256, 0, 64), (64, 0, 16)])
-def test_schedules_identical(block, order, stack):
+@pytest.mark.parametrize("block,order,stack,schedule", [(64, 1, 1, 0), (128, 0, 2, 0), (256, 1, 4, 0), (256, 0, 64, 0),
+                                                        (64, 0, 16, 0), (256, 1, 16, 1), (64, 0, 16, 1), (128, 1, 4, 1)])
+def test_schedules_identical(block, order, stack, schedule):
     cfg = inputs.config_small(n=20_000, m=4000)
     data, q, r = cfg["data"], cfg["queries"], cfg["radius"]
     t = ax.arborx_bvh_build(dev(data))
-    ax.arborx_set_tuning(block=block, order=order, stack=stack)
+    ax.arborx_set_tuning(block=block, order=order, stack=stack, schedule=schedule)
     try:
         check_spatial(t, data, q, r)
         check_knn(t, data, q, 10)
@@ -419,8 +420,10 @@ def test_knn_seeding_off_identical(k):
     s = inputs.config_paper("shell", n=30_000, m=3000)
     t = ax.arborx_bvh_build(dev(s["data"]))
     check_knn(t, s["data"], s["queries"], k)
-    ax.arborx_set_tuning(no_seed=1)
-    try:
-        check_knn(t, s["data"], s["queries"], k)
-    finally:
-        ax.arborx_reset_tuning()
+    for kw in (dict(no_seed=1), dict(schedule=1), dict(schedule=1, no_seed=1)):
+        ax.arborx_set_tuning(**kw)
+        try:
+            check_knn(t, s["data"], s["queries"], k)
+            check_spatial(t, s["data"], s["queries"], 0.01)
+        finally:
+            ax.arborx_reset_tuning()
