@@ -67,7 +67,9 @@ typedef struct arborx_tuning {
     int32_t block;        /* threads per workgroup for traversal kernels: 64, 128, 256 (0 = default) */
     int32_t order;        /* 1 = sort queries along the Morton curve before traversal, 0 = input order */
     int32_t stack;        /* LDS short-stack entries per thread: 4..64 (0 = default); deeper trees spill */
-    int32_t schedule;     /* 0 = thread per query; 1 = wavefront packet (64 queries share node fetches) */
+    int32_t schedule;     /* 0 = thread per query with a short stack; 1 = wavefront packet (64 queries share
+                             node fetches); 2 = thread per query, stackless with ropes (radius / intersects
+                             only; kNN uses the short stack) */
     int32_t build;        /* hierarchy handoff: 0 = chunked (LDS inside chunks), 1 = single pass (device scope);
                              both give the identical tree */
     int32_t no_seed;      /* kNN: 0 = start the walk with an upper bound from the 2k leaves nearest in Morton

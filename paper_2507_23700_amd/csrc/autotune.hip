@@ -157,6 +157,15 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
         c.t.order = 1;
         cands.push_back(c);
     }
+    if (op != OP_KNN)
+        for (int block : {64, 256}) {
+            Candidate c;
+            c.t = base;
+            c.t.block = block;
+            c.t.schedule = 2;
+            c.t.order = 1;
+            cands.push_back(c);
+        }
     {
         Candidate c;
         c.t = base;

@@ -39,7 +39,16 @@ struct arborx_plan_s {
 namespace ax {
 
 static thread_local std::string g_error;
-static Tuning g_tuning[OP_KINDS];
+// Defaults measured on MI355X at 10^7 points: 256-thread blocks for the radius
+// walks, 64-thread blocks for kNN (its 8-byte stack entries halve occupancy).
+static Tuning default_tuning(int op)
+{
+    Tuning t;
+    if (op == OP_KNN)
+        t.block = 64;
+    return t;
+}
+static Tuning g_tuning[OP_KINDS] = {default_tuning(OP_SPATIAL), default_tuning(OP_REDUCE), default_tuning(OP_KNN)};
 static std::mutex g_pool_mutex;
 static bool g_pool_ready[64] = {};
 
@@ -170,8 +179,8 @@ static arborx_status to_tuning(const arborx_tuning *t, const Tuning &base, Tunin
             return fail(ARBORX_E_INVALID, "stack must be a power of two in 1..64");
         n.stack = t->stack;
     }
-    if (t->schedule != 0 && t->schedule != 1)
-        return fail(ARBORX_E_INVALID, "schedule must be 0 (thread per query) or 1 (wavefront packet)");
+    if (t->schedule < 0 || t->schedule > 2)
+        return fail(ARBORX_E_INVALID, "schedule must be 0 (thread, short stack), 1 (wavefront packet) or 2 (ropes)");
     n.schedule = t->schedule;
     if (t->build != 0 && t->build != 1)
         return fail(ARBORX_E_INVALID, "build must be 0 or 1");
@@ -195,8 +204,8 @@ static void from_tuning(const Tuning &g, arborx_tuning *t)
 arborx_status arborx_set_tuning(const arborx_tuning *t)
 {
     if (!t) {
-        for (auto &g : g_tuning)
-            g = Tuning();
+        for (int op = 0; op < OP_KINDS; ++op)
+            g_tuning[op] = default_tuning(op);
         return ARBORX_OK;
     }
     Tuning n;
@@ -213,7 +222,7 @@ arborx_status arborx_set_tuning_op(int32_t op, const arborx_tuning *t)
     if (op < 0 || op >= OP_KINDS)
         return fail(ARBORX_E_INVALID, "unknown operation");
     if (!t) {
-        g_tuning[op] = Tuning();
+        g_tuning[op] = default_tuning(op);
         return ARBORX_OK;
     }
     Tuning n;

@@ -28,7 +28,7 @@ __device__ __forceinline__ int node_count(const TreeHeader *hdr) { return hdr->n
 // kRowSortRegs matches sorted in registers and stores them in the stash row of
 // its Morton position (64 contiguous bytes per thread, so a wavefront writes
 // one coalesced 4 KiB block); rows that fit need no second walk.
-template <int D, class P, bool STASH, bool WAVE>
+template <int D, class P, bool STASH, int SCHED>
 __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
                                 const float *__restrict__ queries, int64_t m, float r2,
                                 const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
@@ -36,11 +36,11 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const TreeHea
 {
     extern __shared__ int s_stack[];
     const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
-    if (!WAVE && t >= m)
+    if (SCHED != 1 && t >= m)
         return;
     int64_t qi = t < m ? (perm ? (int64_t)perm[t] : t) : m;
     const bool active = qi < m;
-    if (!WAVE && !active)
+    if (SCHED != 1 && !active)
         return;
     P pred;
     if (active)
@@ -60,8 +60,10 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const TreeHea
             insert_sorted<kRowSortRegs>(buf, c, idx);
         ++c;
     };
-    if (WAVE)
+    if (SCHED == 1)
         traverse_spatial_wave<D>(nodes, hdr->root, node_count(hdr), pred, wstack, f);
+    else if (SCHED == 2)
+        traverse_spatial_rope<D>(nodes, hdr->root, node_count(hdr), hdr->start + hdr->n - 1, pred, f);
     else
         traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
     if (!active)
@@ -211,7 +213,7 @@ __global__ void k_huge_scatter(const uint64_t *__restrict__ keys, int64_t total,
     }
 }
 
-template <int D, bool SUMDIST, bool WAVE>
+template <int D, bool SUMDIST, int SCHED>
 __global__ void k_spatial_reduce(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
                                  const float *__restrict__ queries, int64_t m, float r2, float scale,
                                  const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
@@ -219,11 +221,11 @@ __global__ void k_spatial_reduce(const Node<D> *__restrict__ nodes, const TreeHe
 {
     extern __shared__ int s_stack[];
     const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
-    if (!WAVE && t >= m)
+    if (SCHED != 1 && t >= m)
         return;
     const int64_t qi = t < m ? (perm ? (int64_t)perm[t] : t) : m;
     const bool active = qi < m;
-    if (!WAVE && !active)
+    if (SCHED != 1 && !active)
         return;
     Sphere<D> pred;
     if (active)
@@ -243,8 +245,10 @@ __global__ void k_spatial_reduce(const Node<D> *__restrict__ nodes, const TreeHe
             s += (long long)scaled;
         }
     };
-    if (WAVE)
+    if (SCHED == 1)
         traverse_spatial_wave<D>(nodes, hdr->root, node_count(hdr), pred, wstack, f);
+    else if (SCHED == 2)
+        traverse_spatial_rope<D>(nodes, hdr->root, node_count(hdr), hdr->start + hdr->n - 1, pred, f);
     else
         traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
     if (!active)
@@ -357,25 +361,28 @@ template <int D>
 arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m, float r2, const uint32_t *perm,
                          int32_t *counts, int32_t *stash, hipStream_t s)
 {
-    const bool wave = tuning(OP_SPATIAL).schedule == 1;
-    const Launch L = traversal_launch(m, sizeof(int), OP_SPATIAL, wave);
+    const int sched = tuning(OP_SPATIAL).schedule;
+    const Launch L = traversal_launch(m, sizeof(int), OP_SPATIAL, sched == 1);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     ProfScope ps("spatial_count", s);
+#define AX_COUNT(P, S) k_spatial_count<D, P, true, S><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, \
+                                                                                  counts, stash, L.cap)
     if (pred == Pred::Sphere) {
-        if (wave)
-            k_spatial_count<D, Sphere<D>, true, true><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm,
-                                                                                     counts, stash, L.cap);
+        if (sched == 1)
+            AX_COUNT(Sphere<D>, 1);
+        else if (sched == 2)
+            AX_COUNT(Sphere<D>, 2);
         else
-            k_spatial_count<D, Sphere<D>, true, false><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm,
-                                                                                      counts, stash, L.cap);
+            AX_COUNT(Sphere<D>, 0);
     } else {
-        if (wave)
-            k_spatial_count<D, BoxQuery<D>, true, true><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm,
-                                                                                       counts, stash, L.cap);
+        if (sched == 1)
+            AX_COUNT(BoxQuery<D>, 1);
+        else if (sched == 2)
+            AX_COUNT(BoxQuery<D>, 2);
         else
-            k_spatial_count<D, BoxQuery<D>, true, false><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm,
-                                                                                        counts, stash, L.cap);
+            AX_COUNT(BoxQuery<D>, 0);
     }
+#undef AX_COUNT
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
@@ -403,25 +410,28 @@ template <int D>
 arborx_status reduce_impl(const TreeDev &t, const float *q, int64_t m, float r2, int op, float scale,
                           const uint32_t *perm, int32_t *counts, int64_t *sums, hipStream_t s)
 {
-    const bool wave = tuning(OP_REDUCE).schedule == 1;
-    const Launch L = traversal_launch(m, sizeof(int), OP_REDUCE, wave);
+    const int sched = tuning(OP_REDUCE).schedule;
+    const Launch L = traversal_launch(m, sizeof(int), OP_REDUCE, sched == 1);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     ProfScope ps(op == ARBORX_COUNT_SUMDIST ? "reduce_sumdist" : "reduce_count", s);
+#define AX_REDUCE(SD, S) k_spatial_reduce<D, SD, S><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, scale, perm, \
+                                                                                counts, sums, L.cap)
     if (op == ARBORX_COUNT_SUMDIST) {
-        if (wave)
-            k_spatial_reduce<D, true, true><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, scale, perm,
-                                                                           counts, sums, L.cap);
+        if (sched == 1)
+            AX_REDUCE(true, 1);
+        else if (sched == 2)
+            AX_REDUCE(true, 2);
         else
-            k_spatial_reduce<D, true, false><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, scale, perm,
-                                                                            counts, sums, L.cap);
+            AX_REDUCE(true, 0);
     } else {
-        if (wave)
-            k_spatial_reduce<D, false, true><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, scale, perm,
-                                                                            counts, sums, L.cap);
+        if (sched == 1)
+            AX_REDUCE(false, 1);
+        else if (sched == 2)
+            AX_REDUCE(false, 2);
         else
-            k_spatial_reduce<D, false, false><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, scale, perm,
-                                                                             counts, sums, L.cap);
+            AX_REDUCE(false, 0);
     }
+#undef AX_REDUCE
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
@@ -430,7 +440,7 @@ template <int D, int K>
 arborx_status knn_launch(const TreeDev &t, const float *q, int64_t m, int k, const uint32_t *perm, float *d2,
                          int32_t *idx, hipStream_t s)
 {
-    const bool wave = tuning(OP_KNN).schedule == 1;
+    const bool wave = tuning(OP_KNN).schedule == 1;  // kNN has no rope form: schedule 2 walks with the stack
     const Launch L = traversal_launch(m, sizeof(KnnEntry), OP_KNN, wave);
     ProfScope ps("knn", s);
     if (wave)

@@ -204,6 +204,54 @@ __device__ __forceinline__ void traverse_spatial_wave(const Node<D> *__restrict_
     }
 }
 
+// Stackless walk with ropes (the paper's spatial traversal, Section 2.6).  The
+// walk position is a child slot (node p, side).  Its rope, the slot the
+// depth-first order visits after the whole subtree in it, needs no storage:
+// after (p, left) comes (p, right); the right child of p covers leaves
+// [p + 1, range_r(p)], and the next subtree in leaf order is the right child
+// of the node splitting leaves range_r(p) and range_r(p) + 1, i.e. (range_r(p),
+// right), unless range_r(p) is the last leaf of the tree.  Every slot is tested
+// at most once, so 2 * n_nodes steps bound the walk.
+template <int D, class P, class F>
+__device__ __forceinline__ void traverse_spatial_rope(const Node<D> *__restrict__ nodes, int root, int n_nodes,
+                                                      int last_leaf, const P &pred, F &f)
+{
+    int p = root, side = 0;
+    Node<D> nd;
+    int loaded = -1;
+    for (int iter = 0; iter <= 2 * n_nodes; ++iter) {
+        if ((unsigned)p >= (unsigned)n_nodes)
+            break;
+        if (p != loaded) {
+            load_node(nodes, p, nd);
+            loaded = p;
+        }
+        float lo[D], hi[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            lo[d] = side ? nd.lo[1][d] : nd.lo[0][d];
+            hi[d] = side ? nd.hi[1][d] : nd.hi[0][d];
+        }
+        const int c = side ? nd.child[1] : nd.child[0];
+        float d2;
+        if (c != kEmptyRef && pred.hit(lo, hi, d2)) {
+            if (c >= 0) {
+                p = c;
+                side = 0;
+                continue;
+            }
+            f(~c, d2);
+        }
+        if (side == 0) {
+            side = 1;
+        } else {
+            if (nd.range_r >= last_leaf)
+                break;
+            p = nd.range_r;
+        }
+    }
+}
+
 // Insert x into the ascending buffer buf[0..k) (k < C) using static indices only.
 template <int C>
 __device__ __forceinline__ void insert_sorted(int (&buf)[C], int k, int x)

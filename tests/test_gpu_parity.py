@@ -353,7 +353,8 @@ def test_capacity_protocol():
 
 
 @pytest.mark.parametrize("block,order,stack,schedule", [(64, 1, 1, 0), (128, 0, 2, 0), (256, 1, 4, 0), (256, 0, 64, 0),
-                                                        (64, 0, 16, 0), (256, 1, 16, 1), (64, 0, 16, 1), (128, 1, 4, 1)])
+                                                        (64, 0, 16, 0), (256, 1, 16, 1), (64, 0, 16, 1), (128, 1, 4, 1),
+                                                        (256, 1, 16, 2), (64, 0, 16, 2)])
 def test_schedules_identical(block, order, stack, schedule):
     cfg = inputs.config_small(n=20_000, m=4000)
     data, q, r = cfg["data"], cfg["queries"], cfg["radius"]
@@ -420,7 +421,7 @@ def test_knn_seeding_off_identical(k):
     s = inputs.config_paper("shell", n=30_000, m=3000)
     t = ax.arborx_bvh_build(dev(s["data"]))
     check_knn(t, s["data"], s["queries"], k)
-    for kw in (dict(no_seed=1), dict(schedule=1), dict(schedule=1, no_seed=1)):
+    for kw in (dict(no_seed=1), dict(schedule=1), dict(schedule=1, no_seed=1), dict(schedule=2)):
         ax.arborx_set_tuning(**kw)
         try:
             check_knn(t, s["data"], s["queries"], k)
