@@ -74,6 +74,8 @@ typedef struct arborx_tuning {
                              both give the identical tree */
     int32_t no_seed;      /* kNN: 0 = start the walk with an upper bound from the 2k leaves nearest in Morton
                              order (default), 1 = start from +inf */
+    int32_t quantized_nodes; /* thread schedules: 0 = walk float child boxes (default), 1 = walk child boxes stored
+                                as 16-bit codes rounded outward, deciding leaves on their exact records */
 } arborx_tuning;
 
 /* Operation kinds that carry their own tuning. */
@@ -197,7 +199,8 @@ arborx_status arborx_query_knn(arborx_tree tree, const float *queries, int64_t m
  *   op          ARBORX_COUNT or ARBORX_COUNT_SUMDIST
  *   counts      [m] int32
  *   sum_fixed   [m] int64, required for COUNT_SUMDIST (ignored, may be NULL, for COUNT)
- *   scale_bits  S in 0..40 for COUNT_SUMDIST; each match adds trunc(sqrtf(d2) * 2^S)
+ *   scale_bits  S in 0..40 for COUNT_SUMDIST; each match adds trunc(sqrtf(d2) * 2^S);
+ *               the sum is unspecified unless every term and the sum stay below 2^63
  * Does not synchronise.
  */
 arborx_status arborx_query_spatial_reduce(arborx_tree tree, const float *queries, int64_t m, float radius,

@@ -62,8 +62,8 @@ def version() -> str:
     return _lib.lib().arborx_version().decode()
 
 
-def arborx_set_tuning(block=0, order=1, stack=0, schedule=0, build=0, no_seed=0) -> None:
-    t = _lib.Tuning(block, order, stack, schedule, build, no_seed)
+def arborx_set_tuning(block=0, order=1, stack=0, schedule=0, build=0, no_seed=0, quantized_nodes=0) -> None:
+    t = _lib.Tuning(block, order, stack, schedule, build, no_seed, quantized_nodes)
     _check(_lib.lib().arborx_set_tuning(ctypes.byref(t)))
 
 
@@ -74,18 +74,19 @@ def arborx_reset_tuning() -> None:
 def arborx_get_tuning() -> dict:
     t = _lib.Tuning()
     _check(_lib.lib().arborx_get_tuning(ctypes.byref(t)))
-    return dict(block=t.block, order=t.order, stack=t.stack, schedule=t.schedule, build=t.build, no_seed=t.no_seed)
+    return _tuning_dict(t)
 
 
 OP_SPATIAL, OP_REDUCE, OP_KNN = 0, 1, 2
 
 
 def _tuning_dict(t):
-    return dict(block=t.block, order=t.order, stack=t.stack, schedule=t.schedule, build=t.build, no_seed=t.no_seed)
+    return dict(block=t.block, order=t.order, stack=t.stack, schedule=t.schedule, build=t.build, no_seed=t.no_seed,
+                quantized_nodes=t.quantized_nodes)
 
 
-def arborx_set_tuning_op(op, block=0, order=1, stack=0, schedule=0, build=0, no_seed=0) -> None:
-    t = _lib.Tuning(block, order, stack, schedule, build, no_seed)
+def arborx_set_tuning_op(op, block=0, order=1, stack=0, schedule=0, build=0, no_seed=0, quantized_nodes=0) -> None:
+    t = _lib.Tuning(block, order, stack, schedule, build, no_seed, quantized_nodes)
     _check(_lib.lib().arborx_set_tuning_op(op, ctypes.byref(t)))
 
 

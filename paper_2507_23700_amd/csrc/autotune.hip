@@ -64,16 +64,17 @@ bool cache_lookup(const std::string &key, Tuning &t)
     bool found = false;
     while (std::fgets(line, sizeof(line), f)) {
         char k[200];
-        int block, order, stack, schedule, seed;
+        int block, order, stack, schedule, seed, nodes;
         if (std::sscanf(line, "{\"key\": \"%199[^\"]\", \"block\": %d, \"order\": %d, \"stack\": %d, \"schedule\": %d, "
-                              "\"seed\": %d",
-                        k, &block, &order, &stack, &schedule, &seed) == 6 &&
+                              "\"seed\": %d, \"nodes\": %d",
+                        k, &block, &order, &stack, &schedule, &seed, &nodes) == 7 &&
             key == k) {
             t.block = block;
             t.order = order;
             t.stack = stack;
             t.schedule = schedule;
             t.seed = seed;
+            t.nodes = nodes;
             found = true;
         }
     }
@@ -91,8 +92,8 @@ void cache_store(const std::string &key, const Tuning &t, double ms)
         return;
     std::fprintf(f,
                  "{\"key\": \"%s\", \"block\": %d, \"order\": %d, \"stack\": %d, \"schedule\": %d, \"seed\": %d, "
-                 "\"ms\": %.4f}\n",
-                 key.c_str(), t.block, t.order, t.stack, t.schedule, t.seed, ms);
+                 "\"nodes\": %d, \"ms\": %.4f}\n",
+                 key.c_str(), t.block, t.order, t.stack, t.schedule, t.seed, t.nodes, ms);
     std::fclose(f);
 }
 
@@ -131,6 +132,7 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
             best->schedule = cached.schedule;
             best->build = cached.build;
             best->no_seed = cached.seed ? 0 : 1;
+            best->quantized_nodes = cached.nodes;
         }
         if (best_ms)
             *best_ms = -1.0;
@@ -146,6 +148,7 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
             c.t.block = block;
             c.t.stack = stack;
             c.t.schedule = 0;
+            c.t.nodes = 0;
             c.t.order = 1;
             cands.push_back(c);
         }
@@ -154,6 +157,17 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
         c.t = base;
         c.t.block = block;
         c.t.schedule = 1;
+        c.t.order = 1;
+        cands.push_back(c);
+    }
+    for (int block : {64, 256}) {  // quantized child boxes, when the tree holds them
+        if (!tree_has_qnodes(tree))
+            break;
+        Candidate c;
+        c.t = base;
+        c.t.block = block;
+        c.t.schedule = 0;
+        c.t.nodes = 1;
         c.t.order = 1;
         cands.push_back(c);
     }
@@ -283,6 +297,7 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
         best->schedule = b.schedule;
         best->build = b.build;
         best->no_seed = b.seed ? 0 : 1;
+        best->quantized_nodes = b.nodes;
     }
     if (best_ms)
         *best_ms = cands[besti].ms;

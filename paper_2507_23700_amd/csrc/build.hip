@@ -31,6 +31,50 @@ namespace {
 
 constexpr int kBuildBlock = 256;
 
+// Step of the 16-bit frame of [lo, hi]: a hair above (hi - lo) / 65535 so that
+// code 65535 decodes at or beyond hi.
+// Step of the 16-bit frame [lo, hi]: the smallest float found upward from
+// about (hi - lo) / kQMax whose top code decodes to at least hi.  The two
+// products are taken before the difference so that an extent beyond the float
+// range stays finite; the check makes the guarantee independent of rounding
+// and of underflow for tiny extents.
+__device__ __forceinline__ float quant_scale(float lo, float hi)
+{
+    if (!(hi > lo))
+        return 0.0f;
+    constexpr float k = 1.0f / (float)kQMax;
+    float s = (hi * k - lo * k) * (1.0f + 0x1p-18f);
+    while (qdecode((uint32_t)kQMax, lo, s) < hi)
+        s = nextafterf(s, INFINITY);
+    return s;
+}
+
+// Largest code whose decoded value is <= x, and smallest whose decoded value is >= x.
+__device__ __forceinline__ uint32_t qcode_down(float x, float lo, float scale)
+{
+    if (!(scale > 0.0f) || !(x > lo))
+        return 0u;
+    float u = floorf((x - lo) / scale);
+    uint32_t c = u >= (float)kQMax ? (uint32_t)kQMax : (uint32_t)u;
+    while (c > 0 && qdecode(c, lo, scale) > x)
+        --c;
+    return c;
+}
+
+__device__ __forceinline__ uint32_t qcode_up(float x, float lo, float scale)
+{
+    if (!(scale > 0.0f))
+        return 0u;
+    if (!(x > lo))
+        return 0u;
+    float u = ceilf((x - lo) / scale);
+    uint32_t c = u >= (float)kQMax ? (uint32_t)kQMax : (uint32_t)u;
+    while (c < (uint32_t)kQMax && qdecode(c, lo, scale) < x)
+        ++c;
+    return c;
+}
+
+
 template <int D>
 __global__ __launch_bounds__(kBuildBlock) void bounds_partial(const float *__restrict__ values, int64_t n, int kind,
                                                               float *__restrict__ partial)
@@ -93,6 +137,7 @@ __global__ void bounds_final(const float *__restrict__ partial, int blocks, int6
         }
         hdr->lo[d] = a;
         hdr->hi[d] = b;
+        hdr->qscale[d] = quant_scale(a, b);
     }
     if (d == 0) {
         hdr->n = (int32_t)n;
@@ -346,6 +391,53 @@ __device__ __forceinline__ void segment_of(int i, const int64_t *__restrict__ se
     te = (int)seg[lo + 1] - 1;
 }
 
+// Float nodes -> quantized nodes.  Node p belongs to the tree holding sorted
+// leaf p (a one-value tree's node sits at its own leaf position).  Leaf child
+// references become sorted leaf positions: the left child of node p is leaf p,
+// the right child leaf p + 1.
+template <int D>
+__global__ void quantize_nodes(const Node<D> *__restrict__ nodes, int n_nodes, const int64_t *__restrict__ seg,
+                               int nseg, int n, const TreeHeader *__restrict__ hdrs, QNode<D> *__restrict__ qnodes)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_nodes)
+        return;
+    int sg, ts, te;
+    segment_of(p < n ? p : n - 1, seg, nseg, n, sg, ts, te);
+    const TreeHeader &h = hdrs[sg];
+    Node<D> nd;
+    load_node(nodes, p, nd);
+    QNode<D> qn;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(qn.pad) / sizeof(qn.pad[0])); ++k)
+        qn.pad[k] = 0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int32_t ref = nd.child[c];
+        if (ref == kEmptyRef) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                qn.q[c][0][d] = (uint16_t)kQMax;
+                qn.q[c][1][d] = 0;
+            }
+            qn.child[c] = kEmptyRef;
+            continue;
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            qn.q[c][0][d] = (uint16_t)qcode_down(nd.lo[c][d], h.lo[d], h.qscale[d]);
+            qn.q[c][1][d] = (uint16_t)qcode_up(nd.hi[c][d], h.lo[d], h.qscale[d]);
+        }
+        qn.child[c] = ref >= 0 ? ref : ~(p + c);
+    }
+    float4 *dst = reinterpret_cast<float4 *>(qnodes + p);
+    const float4 *src = reinterpret_cast<const float4 *>(&qn);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(QNode<D>) / 16); ++k)
+        dst[k] = src[k];
+}
+
+
 template <int D>
 __global__ __launch_bounds__(kBuildBlock) void hierarchy_chunk_kernel(const uint64_t *__restrict__ codes,
                                                                       const uint32_t *__restrict__ ids,
@@ -552,6 +644,8 @@ __global__ __launch_bounds__(kBuildBlock) void hierarchy_top_kernel(const uint64
 
 __global__ void empty_header(TreeHeader *hdr, int dim)
 {
+    for (int d = 0; d < kMaxDim; ++d)
+        hdr->qscale[d] = 0.0f;
     hdr->root = -1;
     hdr->height = 0;
     hdr->n = 0;
@@ -584,6 +678,9 @@ arborx_status build_impl(const float *values, int64_t n, int kind, TreeDev &t, h
         return st;
     st = dalloc((void **)&t.leaves, (size_t)n * leaf_floats(D, kind) * sizeof(float), s);
     if (st != ARBORX_OK)
+        return st;
+    const bool quantized = quantized_requested();
+    if (quantized && (st = dalloc(&t.qnodes, (size_t)nn * sizeof(QNode<D>), s)) != ARBORX_OK)
         return st;
 
     Temps tmp(s);
@@ -639,6 +736,11 @@ arborx_status build_impl(const float *values, int64_t n, int kind, TreeDev &t, h
         if (chunks > 1)
             hierarchy_top_kernel<D><<<grid_for(2 * chunks, kBuildBlock), kBuildBlock, 0, s>>>(
                 codes, (int)n, nodes, flags, esc, 2 * chunks, nullptr, 0, t.hdr);
+    }
+    if (quantized) {
+        ProfScope ps("build_quantize", s);
+        quantize_nodes<D><<<grid_for(nn, kBuildBlock), kBuildBlock, 0, s>>>(nodes, (int)nn, nullptr, 0, (int)n, t.hdr,
+                                                                            static_cast<QNode<D> *>(t.qnodes));
     }
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
@@ -749,6 +851,7 @@ __global__ void forest_headers(const int64_t *__restrict__ seg, int T, const uin
     for (int d = 0; d < kMaxDim; ++d) {
         h.lo[d] = (d < D && n > 0) ? order_float(tmin[t * D + d]) : INFINITY;
         h.hi[d] = (d < D && n > 0) ? order_float(tmax[t * D + d]) : -INFINITY;
+        h.qscale[d] = (d < D && n > 0) ? quant_scale(h.lo[d], h.hi[d]) : 0.0f;
     }
 }
 
@@ -806,6 +909,9 @@ arborx_status forest_build_impl(const float *values, const int64_t *seg_host, in
         (st = dalloc(&f.nodes, (size_t)(n > 0 ? n : 1) * sizeof(Node<D>), s)) != ARBORX_OK ||
         (st = dalloc((void **)&f.leaves, (size_t)(n > 0 ? n : 1) * leaf_floats(D, kind) * sizeof(float), s)) !=
             ARBORX_OK)
+        return st;
+    const bool quantized = quantized_requested();
+    if (quantized && (st = dalloc(&f.qnodes, (size_t)(n > 0 ? n : 1) * sizeof(QNode<D>), s)) != ARBORX_OK)
         return st;
     AX_HIP(hipMemcpyAsync(f.seg, seg_host, sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, s));
     // tiles that never straddle a tree
@@ -877,6 +983,9 @@ arborx_status forest_build_impl(const float *values, const int64_t *seg_host, in
     if (chunks > 1)
         hierarchy_top_kernel<D><<<grid_for(2 * chunks, kBuildBlock), kBuildBlock, 0, s>>>(
             codes, (int)n, nodes, flags, esc, 2 * chunks, f.seg, T, f.hdrs);
+    if (quantized)
+        quantize_nodes<D><<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(nodes, (int)n, f.seg, T, (int)n, f.hdrs,
+                                                                           static_cast<QNode<D> *>(f.qnodes));
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
@@ -906,6 +1015,8 @@ arborx_status build_tree(const float *values, int64_t n, int dim, int kind, Tree
 void forest_release(ForestDev &f, hipStream_t s)
 {
     dfree(f.nodes, s);
+    dfree(f.qnodes, s);
+    f.qnodes = nullptr;
     dfree(f.leaves, s);
     dfree(f.hdrs, s);
     dfree(f.seg, s);

@@ -54,6 +54,25 @@ static bool g_pool_ready[64] = {};
 
 const Tuning &tuning(int op) { return g_tuning[op >= 0 && op < OP_KINDS ? op : 0]; }
 
+bool quantized_requested()
+{
+    for (int op = 0; op < OP_KINDS; ++op)
+        if (g_tuning[op].nodes == 1)
+            return true;
+    return false;
+}
+
+bool tree_has_qnodes(arborx_tree tree) { return tree && tree->dev.qnodes; }
+
+arborx_status check_qnodes(const void *qnodes, int64_t n, int op)
+{
+    const Tuning &t = tuning(op);
+    if (n > 0 && t.nodes == 1 && t.schedule == 0 && !qnodes)
+        return fail(ARBORX_E_INVALID, "quantized_nodes is set but the structure was built without quantized nodes; "
+                                      "set it before building");
+    return ARBORX_OK;
+}
+
 void set_tuning_op(int op, const Tuning &t)
 {
     if (op >= 0 && op < OP_KINDS)
@@ -139,6 +158,7 @@ static void release_tree(arborx_tree t)
         (void)hipEventSynchronize(t->ready);
     (void)hipDeviceSynchronize();
     dfree(t->dev.nodes, nullptr);
+    dfree(t->dev.qnodes, nullptr);
     dfree(t->dev.leaves, nullptr);
     dfree(t->dev.hdr, nullptr);
     (void)hipStreamSynchronize(nullptr);
@@ -188,6 +208,9 @@ static arborx_status to_tuning(const arborx_tuning *t, const Tuning &base, Tunin
     if (t->no_seed != 0 && t->no_seed != 1)
         return fail(ARBORX_E_INVALID, "no_seed must be 0 or 1");
     n.seed = t->no_seed ? 0 : 1;
+    if (t->quantized_nodes != 0 && t->quantized_nodes != 1)
+        return fail(ARBORX_E_INVALID, "quantized_nodes must be 0 or 1");
+    n.nodes = t->quantized_nodes;
     return ARBORX_OK;
 }
 
@@ -199,6 +222,7 @@ static void from_tuning(const Tuning &g, arborx_tuning *t)
     t->schedule = g.schedule;
     t->build = g.build;
     t->no_seed = g.seed ? 0 : 1;
+    t->quantized_nodes = g.nodes;
 }
 
 arborx_status arborx_set_tuning(const arborx_tuning *t)

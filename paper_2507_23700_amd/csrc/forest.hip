@@ -79,9 +79,10 @@ __device__ __forceinline__ int64_t next_block(unsigned long long *counter, int64
     return start < m ? start : -1;
 }
 
-template <int D, bool SUMDIST>
+template <int D, bool SUMDIST, bool QN>
 __global__ __launch_bounds__(kForestBlock) void k_forest_reduce(
-    const Node<D> *__restrict__ nodes, int n_nodes, const TreeHeader *__restrict__ hdrs, int T,
+    const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes, const float *__restrict__ leaves, int kind,
+    int n_nodes, const TreeHeader *__restrict__ hdrs, int T,
     const float *__restrict__ queries, int64_t m, const uint32_t *__restrict__ perm, const int64_t *__restrict__ boff,
     int B, const int32_t *__restrict__ btree, const float *__restrict__ bradius, float scale, int32_t *__restrict__ counts,
     int64_t *__restrict__ sums, unsigned long long *counter, int stack_cap)
@@ -112,7 +113,10 @@ __global__ __launch_bounds__(kForestBlock) void k_forest_reduce(
                     s += (long long)scaled;
                 }
             };
-            traverse_spatial<D>(nodes, hdrs[tr].root, n_nodes, pred, st, f);
+            if (QN)
+                traverse_spatial_q<D>(qnodes, hdrs[tr], n_nodes, leaves, kind, pred, st, f);
+            else
+                traverse_spatial<D>(nodes, hdrs[tr].root, n_nodes, pred, st, f);
         }
         counts[qi] = c;
         if (SUMDIST)
@@ -120,9 +124,10 @@ __global__ __launch_bounds__(kForestBlock) void k_forest_reduce(
     }
 }
 
-template <int D, int K>
+template <int D, int K, bool QN>
 __global__ __launch_bounds__(kForestBlock) void k_forest_knn(
-    const Node<D> *__restrict__ nodes, int n_nodes, const float *__restrict__ leaves, int kind,
+    const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes, int n_nodes,
+    const float *__restrict__ leaves, int kind,
     const TreeHeader *__restrict__ hdrs, int T, const float *__restrict__ queries, int64_t m,
     const uint32_t *__restrict__ perm, const int64_t *__restrict__ boff, int B, const int32_t *__restrict__ btree,
     int k_out, float *__restrict__ out_d2, int32_t *__restrict__ out_idx, unsigned long long *counter, int stack_cap,
@@ -154,7 +159,10 @@ __global__ __launch_bounds__(kForestBlock) void k_forest_knn(
         for (int d = 0; d < D; ++d)
             q[d] = queries[qi * D + d];
         ShortStack<KnnEntry> st(reinterpret_cast<KnnEntry *>(s_stack) + threadIdx.x, blockDim.x, stack_cap, spill);
-        knn_search<D, K>(nodes, n_nodes, leaves, kind, h, q, bd, bi, st, seed);
+        if (QN)
+            knn_search_q<D, K>(qnodes, n_nodes, leaves, kind, h, q, bd, bi, st, seed);
+        else
+            knn_search<D, K>(nodes, n_nodes, leaves, kind, h, q, bd, bi, st, seed);
 #pragma unroll
         for (int s = 0; s < K; ++s)  // value index -> index local to the tree
             bi[s] = bi[s] == INT32_MAX ? INT32_MAX : bi[s] - h.start;
@@ -253,16 +261,28 @@ arborx_status forest_reduce_impl(ForestDev &f, const float *q, int64_t m, const 
     const float scale = ldexpf(1.0f, scale_bits);
     ProfScope ps(op == ARBORX_COUNT_SUMDIST ? "forest_reduce_sumdist" : "forest_reduce_count", s);
     const Node<D> *nodes = static_cast<const Node<D> *>(f.nodes);
+    const QNode<D> *qnodes = static_cast<const QNode<D> *>(f.qnodes);
     const int nn = (int)(f.n > 0 ? f.n : 1);
+    const bool qn = tu.nodes == 1;
+#define AX_FREDUCE(SD, Q)                                                                                        \
+    do {                                                                                                         \
+        const int grid = persistent_grid((const void *)k_forest_reduce<D, SD, Q>, kForestBlock, lds);           \
+        k_forest_reduce<D, SD, Q><<<grid, kForestBlock, lds, s>>>(nodes, qnodes, f.leaves, f.kind, nn, f.hdrs, f.T, q, \
+                                                                  m, perm, boff, B, btree, brad, scale, counts, sums, \
+                                                                  counter, cap);                               \
+    } while (0)
     if (op == ARBORX_COUNT_SUMDIST) {
-        const int grid = persistent_grid((const void *)k_forest_reduce<D, true>, kForestBlock, lds);
-        k_forest_reduce<D, true><<<grid, kForestBlock, lds, s>>>(nodes, nn, f.hdrs, f.T, q, m, perm, boff, B, btree,
-                                                                 brad, scale, counts, sums, counter, cap);
+        if (qn)
+            AX_FREDUCE(true, true);
+        else
+            AX_FREDUCE(true, false);
     } else {
-        const int grid = persistent_grid((const void *)k_forest_reduce<D, false>, kForestBlock, lds);
-        k_forest_reduce<D, false><<<grid, kForestBlock, lds, s>>>(nodes, nn, f.hdrs, f.T, q, m, perm, boff, B, btree,
-                                                                  brad, scale, counts, sums, counter, cap);
+        if (qn)
+            AX_FREDUCE(false, true);
+        else
+            AX_FREDUCE(false, false);
     }
+#undef AX_FREDUCE
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
@@ -286,11 +306,19 @@ arborx_status forest_knn_launch(ForestDev &f, const float *q, int64_t m, const i
     while (cap > 1 && (size_t)cap * kForestBlock * sizeof(KnnEntry) > 65536)
         cap >>= 1;
     const size_t lds = (size_t)cap * kForestBlock * sizeof(KnnEntry);
-    const int grid = persistent_grid((const void *)k_forest_knn<D, K>, kForestBlock, lds);
     ProfScope ps("forest_knn", s);
-    k_forest_knn<D, K><<<grid, kForestBlock, lds, s>>>(static_cast<const Node<D> *>(f.nodes),
-                                                       (int)(f.n > 0 ? f.n : 1), f.leaves, f.kind, f.hdrs, f.T, q, m,
-                                                       perm, boff, B, btree, k, d2, idx, counter, cap, tu.seed);
+#define AX_FKNN(Q)                                                                                                 \
+    do {                                                                                                           \
+        const int grid = persistent_grid((const void *)k_forest_knn<D, K, Q>, kForestBlock, lds);                 \
+        k_forest_knn<D, K, Q><<<grid, kForestBlock, lds, s>>>(                                                    \
+            static_cast<const Node<D> *>(f.nodes), static_cast<const QNode<D> *>(f.qnodes), (int)(f.n > 0 ? f.n : 1), \
+            f.leaves, f.kind, f.hdrs, f.T, q, m, perm, boff, B, btree, k, d2, idx, counter, cap, tu.seed);       \
+    } while (0)
+    if (tu.nodes == 1)
+        AX_FKNN(true);
+    else
+        AX_FKNN(false);
+#undef AX_FKNN
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
@@ -322,7 +350,9 @@ arborx_status forest_query_reduce(ForestDev &f, const float *q, int64_t m, const
 {
     if (m == 0)
         return ARBORX_OK;
-    arborx_status st = reserve_ws(f, m, s);
+    arborx_status st = check_qnodes(f.qnodes, f.n, OP_REDUCE);
+    if (st == ARBORX_OK)
+        st = reserve_ws(f, m, s);
     if (st != ARBORX_OK)
         return st;
     switch (f.dim) {
@@ -338,7 +368,9 @@ arborx_status forest_query_knn(ForestDev &f, const float *q, int64_t m, const in
 {
     if (m == 0)
         return ARBORX_OK;
-    arborx_status st = reserve_ws(f, m, s);
+    arborx_status st = check_qnodes(f.qnodes, f.n, OP_KNN);
+    if (st == ARBORX_OK)
+        st = reserve_ws(f, m, s);
     if (st != ARBORX_OK)
         return st;
     switch (f.dim) {

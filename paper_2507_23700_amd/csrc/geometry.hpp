@@ -70,6 +70,33 @@ __device__ __forceinline__ void store_leaf(float *leaves, int64_t pos, int kind,
     }
 }
 
+// The same node with each child box stored as 16-bit codes in the tree's
+// frame (lo + code * qscale per dimension), rounded outward so that the
+// decoded box always contains the true one: tests on it are conservative.
+// A leaf child refers to its sorted leaf record (~position), whose exact
+// coordinates decide the match.  32 bytes in 3D, half the float node.
+template <int D>
+struct alignas(16) QNode {
+    uint16_t q[2][2][D];  // [child][lo, hi][dim]
+    int32_t child[2];     // >= 0 node, < 0 leaf record ~ref, kEmptyRef empty
+    int32_t pad[(16 - (8 * D + 8) % 16) % 16 / 4];
+};
+static_assert(sizeof(QNode<3>) == 32, "3D quantized node is 32 bytes");
+
+constexpr int kQMax = 65535;
+
+__device__ __forceinline__ float qdecode(uint32_t code, float lo, float scale) { return fmaf((float)code, scale, lo); }
+
+template <int D>
+__device__ __forceinline__ void load_qnode(const QNode<D> *__restrict__ nodes, int32_t i, QNode<D> &out)
+{
+    const float4 *src = reinterpret_cast<const float4 *>(nodes + i);
+    float4 *dst = reinterpret_cast<float4 *>(&out);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(QNode<D>) / 16); ++k)
+        dst[k] = src[k];
+}
+
 template <int D>
 __device__ __forceinline__ void load_node(const Node<D> *__restrict__ nodes, int32_t i, Node<D> &out)
 {
@@ -84,6 +111,9 @@ __device__ __forceinline__ void load_node(const Node<D> *__restrict__ nodes, int
 // gap to the nearer face (0 inside), each square and each sum rounded once,
 // dimensions summed from 0 upwards.  For a degenerate box [p, p] it equals the
 // point-to-point squared distance bit for bit, because |fl(p - q)| = |fl(q - p)|.
+// The gap is max(lo - q, q - hi, 0) without branches: when q < lo <= hi the
+// second difference is <= 0 and the first is the rounded gap itself, and
+// symmetrically above hi; inside both are <= 0.
 template <int D>
 __device__ __forceinline__ float box_d2(const float *q, const float *lo, const float *hi)
 {
@@ -91,11 +121,7 @@ __device__ __forceinline__ float box_d2(const float *q, const float *lo, const f
     float acc = 0.0f;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        float t = 0.0f;
-        if (q[d] < lo[d])
-            t = lo[d] - q[d];
-        else if (q[d] > hi[d])
-            t = q[d] - hi[d];
+        const float t = fmaxf(fmaxf(lo[d] - q[d], q[d] - hi[d]), 0.0f);
         float s = t * t;
         acc = acc + s;
     }
@@ -109,7 +135,7 @@ __device__ __forceinline__ bool boxes_overlap(const float *alo, const float *ahi
     bool ok = true;
 #pragma unroll
     for (int d = 0; d < D; ++d)
-        ok = ok && (alo[d] <= bhi[d]) && (blo[d] <= ahi[d]);
+        ok = ok & (alo[d] <= bhi[d]) & (blo[d] <= ahi[d]);
     return ok;
 }
 

@@ -23,6 +23,7 @@ struct TreeHeader {
     int32_t start;   // position of the tree's first leaf in the sorted leaf array
     float lo[kMaxDim];
     float hi[kMaxDim];
+    float qscale[kMaxDim];  // quantized-node frame: coordinate = lo + code * qscale
 };
 
 // Device-resident per-call header of a CSR query, written by the scan.
@@ -39,12 +40,18 @@ struct Tuning {
     int stack = 16;
     int schedule = 0;
     int build = 0;
-    int seed = 1;  // kNN: bound the walk with nearby leaves first
+    int seed = 1;   // kNN: bound the walk with nearby leaves first
+    int nodes = 0;  // 0: float child boxes, 1: quantized 16-bit child boxes (exact leaf tests)
 };
 // Tuning is kept per operation kind so the autotuner can pick each separately.
 enum Op { OP_SPATIAL = 0, OP_REDUCE = 1, OP_KNN = 2, OP_KINDS = 3 };
 const Tuning &tuning(int op = OP_SPATIAL);
 void set_tuning_op(int op, const Tuning &t);
+// Quantized nodes are built only while some operation asks for them.
+bool quantized_requested();
+// ARBORX_E_INVALID unless the structure holds quantized nodes or `op` does not use them.
+arborx_status check_qnodes(const void *qnodes, int64_t n, int op);
+bool tree_has_qnodes(arborx_tree tree);
 
 // Error reporting: thread-local last message.
 void set_error(const std::string &msg);
@@ -124,6 +131,7 @@ struct TreeDev {
     int dim = 0;
     int kind = 0;
     void *nodes = nullptr;  // Node<dim>[max(n-1, 1)]
+    void *qnodes = nullptr; // QNode<dim>[max(n-1, 1)]: the same tree with 16-bit child boxes
     float *leaves = nullptr; // n leaf records in sorted order (see leaf_floats)
     TreeHeader *hdr = nullptr;
 };
@@ -139,6 +147,7 @@ struct ForestDev {
     int64_t n = 0;
     int dim = 0, kind = 0, T = 0;
     void *nodes = nullptr;     // Node<dim>[n]: one slot per split plus a spare for a last one-value tree
+    void *qnodes = nullptr;    // QNode<dim>[n]
     float *leaves = nullptr;   // n leaf records, sorted inside each tree
     TreeHeader *hdrs = nullptr;  // [T]
     int64_t *seg = nullptr;    // [T+1] device copy of the tree offsets

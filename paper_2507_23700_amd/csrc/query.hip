@@ -29,7 +29,8 @@ __device__ __forceinline__ int node_count(const TreeHeader *hdr) { return hdr->n
 // its Morton position (64 contiguous bytes per thread, so a wavefront writes
 // one coalesced 4 KiB block); rows that fit need no second walk.
 template <int D, class P, bool STASH, int SCHED>
-__global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+__global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
+                                const float *__restrict__ leaves, int kind, const TreeHeader *__restrict__ hdr,
                                 const float *__restrict__ queries, int64_t m, float r2,
                                 const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
                                 int32_t *__restrict__ stash, int stack_cap)
@@ -64,6 +65,8 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const TreeHea
         traverse_spatial_wave<D>(nodes, hdr->root, node_count(hdr), pred, wstack, f);
     else if (SCHED == 2)
         traverse_spatial_rope<D>(nodes, hdr->root, node_count(hdr), hdr->start + hdr->n - 1, pred, f);
+    else if (SCHED == 3)
+        traverse_spatial_q<D>(qnodes, *hdr, node_count(hdr), leaves, kind, pred, st, f);
     else
         traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
     if (!active)
@@ -110,8 +113,9 @@ __global__ void k_copy_stash(const int32_t *__restrict__ stash, const uint32_t *
 
 // Second walk for listed rows (longer than the stash): matches written in
 // traversal order, sorted afterwards.
-template <int D, class P>
-__global__ void k_spatial_fill_rows(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+template <int D, class P, bool QN>
+__global__ void k_spatial_fill_rows(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
+                                    const float *__restrict__ leaves, int kind, const TreeHeader *__restrict__ hdr,
                                     const float *__restrict__ queries, int64_t m, float r2,
                                     const int32_t *__restrict__ rows, int64_t nrows,
                                     const int64_t *__restrict__ offsets, int32_t *__restrict__ indices, int stack_cap)
@@ -135,7 +139,10 @@ __global__ void k_spatial_fill_rows(const Node<D> *__restrict__ nodes, const Tre
             indices[o + k] = idx;
         ++k;
     };
-    traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
+    if (QN)
+        traverse_spatial_q<D>(qnodes, *hdr, node_count(hdr), leaves, kind, pred, st, f);
+    else
+        traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
 }
 
 // One workgroup per listed row of at most kRowSortBlock entries: bitonic sort in LDS.
@@ -214,7 +221,8 @@ __global__ void k_huge_scatter(const uint64_t *__restrict__ keys, int64_t total,
 }
 
 template <int D, bool SUMDIST, int SCHED>
-__global__ void k_spatial_reduce(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+__global__ void k_spatial_reduce(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
+                                 const float *__restrict__ leaves, int kind, const TreeHeader *__restrict__ hdr,
                                  const float *__restrict__ queries, int64_t m, float r2, float scale,
                                  const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
                                  int64_t *__restrict__ sums, int stack_cap)
@@ -249,6 +257,8 @@ __global__ void k_spatial_reduce(const Node<D> *__restrict__ nodes, const TreeHe
         traverse_spatial_wave<D>(nodes, hdr->root, node_count(hdr), pred, wstack, f);
     else if (SCHED == 2)
         traverse_spatial_rope<D>(nodes, hdr->root, node_count(hdr), hdr->start + hdr->n - 1, pred, f);
+    else if (SCHED == 3)
+        traverse_spatial_q<D>(qnodes, *hdr, node_count(hdr), leaves, kind, pred, st, f);
     else
         traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
     if (!active)
@@ -258,8 +268,9 @@ __global__ void k_spatial_reduce(const Node<D> *__restrict__ nodes, const TreeHe
         sums[qi] = s;
 }
 
-template <int D, int K, bool WAVE>
-__global__ void k_knn(const Node<D> *__restrict__ nodes, int n_nodes, const float *__restrict__ leaves, int kind,
+template <int D, int K, bool WAVE, bool QN>
+__global__ void k_knn(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes, int n_nodes,
+                      const float *__restrict__ leaves, int kind,
                       const TreeHeader *__restrict__ hdr, const float *__restrict__ queries, int64_t m, int k_out,
                       const uint32_t *__restrict__ perm, float *__restrict__ out_d2, int32_t *__restrict__ out_idx,
                       int stack_cap, int seed)
@@ -284,7 +295,10 @@ __global__ void k_knn(const Node<D> *__restrict__ nodes, int n_nodes, const floa
     } else {
         KnnEntry spill[kSpill];
         ShortStack<KnnEntry> st(reinterpret_cast<KnnEntry *>(s_stack) + threadIdx.x, blockDim.x, stack_cap, spill);
-        knn_search<D, K>(nodes, n_nodes, leaves, kind, *hdr, q, bd, bi, st, seed);
+        if (QN)
+            knn_search_q<D, K>(qnodes, n_nodes, leaves, kind, *hdr, q, bd, bi, st, seed);
+        else
+            knn_search<D, K>(nodes, n_nodes, leaves, kind, *hdr, q, bd, bi, st, seed);
     }
     if (active)
         knn_store<K>(bd, bi, k_out, out_d2 + qi * k_out, out_idx + qi * k_out);
@@ -357,21 +371,32 @@ Launch traversal_launch(int64_t m, size_t entry_bytes, int op, bool wave = false
     return L;
 }
 
+// Schedule 0 over quantized nodes runs as internal schedule 3.
+int effective_schedule(int op)
+{
+    const Tuning &tu = tuning(op);
+    return tu.schedule == 0 && tu.nodes == 1 ? 3 : tu.schedule;
+}
+
 template <int D>
 arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m, float r2, const uint32_t *perm,
                          int32_t *counts, int32_t *stash, hipStream_t s)
 {
-    const int sched = tuning(OP_SPATIAL).schedule;
+    const int sched = effective_schedule(OP_SPATIAL);
     const Launch L = traversal_launch(m, sizeof(int), OP_SPATIAL, sched == 1);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
+    const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
     ProfScope ps("spatial_count", s);
-#define AX_COUNT(P, S) k_spatial_count<D, P, true, S><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, \
-                                                                                  counts, stash, L.cap)
+#define AX_COUNT(P, S)                                                                                     \
+    k_spatial_count<D, P, true, S><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, t.leaves, t.kind, t.hdr, q, m, r2, \
+                                                                  perm, counts, stash, L.cap)
     if (pred == Pred::Sphere) {
         if (sched == 1)
             AX_COUNT(Sphere<D>, 1);
         else if (sched == 2)
             AX_COUNT(Sphere<D>, 2);
+        else if (sched == 3)
+            AX_COUNT(Sphere<D>, 3);
         else
             AX_COUNT(Sphere<D>, 0);
     } else {
@@ -379,6 +404,8 @@ arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m,
             AX_COUNT(BoxQuery<D>, 1);
         else if (sched == 2)
             AX_COUNT(BoxQuery<D>, 2);
+        else if (sched == 3)
+            AX_COUNT(BoxQuery<D>, 3);
         else
             AX_COUNT(BoxQuery<D>, 0);
     }
@@ -395,13 +422,24 @@ arborx_status fill_rows_impl(const TreeDev &t, Pred pred, const float *q, int64_
         return ARBORX_OK;
     Launch L = traversal_launch(nrows, sizeof(int), OP_SPATIAL);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
+    const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
+    const bool qn = tuning(OP_SPATIAL).nodes == 1;
     ProfScope ps("spatial_fill", s);
-    if (pred == Pred::Sphere)
-        k_spatial_fill_rows<D, Sphere<D>><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, rows, nrows, offsets,
-                                                                         indices, L.cap);
-    else
-        k_spatial_fill_rows<D, BoxQuery<D>><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, rows, nrows,
-                                                                           offsets, indices, L.cap);
+#define AX_FILL(P, Q)                                                                                              \
+    k_spatial_fill_rows<D, P, Q><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, t.leaves, t.kind, t.hdr, q, m, r2, rows, \
+                                                                nrows, offsets, indices, L.cap)
+    if (pred == Pred::Sphere) {
+        if (qn)
+            AX_FILL(Sphere<D>, true);
+        else
+            AX_FILL(Sphere<D>, false);
+    } else {
+        if (qn)
+            AX_FILL(BoxQuery<D>, true);
+        else
+            AX_FILL(BoxQuery<D>, false);
+    }
+#undef AX_FILL
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
@@ -410,17 +448,21 @@ template <int D>
 arborx_status reduce_impl(const TreeDev &t, const float *q, int64_t m, float r2, int op, float scale,
                           const uint32_t *perm, int32_t *counts, int64_t *sums, hipStream_t s)
 {
-    const int sched = tuning(OP_REDUCE).schedule;
+    const int sched = effective_schedule(OP_REDUCE);
     const Launch L = traversal_launch(m, sizeof(int), OP_REDUCE, sched == 1);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
+    const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
     ProfScope ps(op == ARBORX_COUNT_SUMDIST ? "reduce_sumdist" : "reduce_count", s);
-#define AX_REDUCE(SD, S) k_spatial_reduce<D, SD, S><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, scale, perm, \
-                                                                                counts, sums, L.cap)
+#define AX_REDUCE(SD, S)                                                                                      \
+    k_spatial_reduce<D, SD, S><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, t.leaves, t.kind, t.hdr, q, m, r2, scale, \
+                                                              perm, counts, sums, L.cap)
     if (op == ARBORX_COUNT_SUMDIST) {
         if (sched == 1)
             AX_REDUCE(true, 1);
         else if (sched == 2)
             AX_REDUCE(true, 2);
+        else if (sched == 3)
+            AX_REDUCE(true, 3);
         else
             AX_REDUCE(true, 0);
     } else {
@@ -428,6 +470,8 @@ arborx_status reduce_impl(const TreeDev &t, const float *q, int64_t m, float r2,
             AX_REDUCE(false, 1);
         else if (sched == 2)
             AX_REDUCE(false, 2);
+        else if (sched == 3)
+            AX_REDUCE(false, 3);
         else
             AX_REDUCE(false, 0);
     }
@@ -441,16 +485,22 @@ arborx_status knn_launch(const TreeDev &t, const float *q, int64_t m, int k, con
                          int32_t *idx, hipStream_t s)
 {
     const bool wave = tuning(OP_KNN).schedule == 1;  // kNN has no rope form: schedule 2 walks with the stack
+    const bool qn = !wave && tuning(OP_KNN).nodes == 1;
     const Launch L = traversal_launch(m, sizeof(KnnEntry), OP_KNN, wave);
+    const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
+    const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
+    const int seed = tuning(OP_KNN).seed;
     ProfScope ps("knn", s);
+#define AX_KNN(W, Q)                                                                                              \
+    k_knn<D, K, W, Q><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, tree_nodes(t), t.leaves, t.kind, t.hdr, q, m, k, \
+                                                     perm, d2, idx, L.cap, seed)
     if (wave)
-        k_knn<D, K, true><<<L.grid, L.block, L.lds, s>>>(static_cast<const Node<D> *>(t.nodes), tree_nodes(t),
-                                                          t.leaves, t.kind, t.hdr, q, m, k, perm, d2, idx, L.cap,
-                                                          tuning(OP_KNN).seed);
+        AX_KNN(true, false);
+    else if (qn)
+        AX_KNN(false, true);
     else
-        k_knn<D, K, false><<<L.grid, L.block, L.lds, s>>>(static_cast<const Node<D> *>(t.nodes), tree_nodes(t),
-                                                           t.leaves, t.kind, t.hdr, q, m, k, perm, d2, idx, L.cap,
-                                                           tuning(OP_KNN).seed);
+        AX_KNN(false, false);
+#undef AX_KNN
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
@@ -524,6 +574,9 @@ arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, i
         return ARBORX_OK;
     if (t.n == 0)
         return fill_async<int32_t>(counts, m, 0, s);
+    arborx_status st = check_qnodes(t.qnodes, t.n, OP_SPATIAL);
+    if (st != ARBORX_OK)
+        return st;
     const float r2 = radius * radius;
     AX_DISPATCH_DIM(t.dim, (count_impl<D>(t, pred, queries, m, r2, perm, counts, stash, s)));
 }
@@ -535,13 +588,15 @@ arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, in
 {
     if (m == 0 || t.n == 0)
         return ARBORX_OK;
+    arborx_status st = check_qnodes(t.qnodes, t.n, OP_SPATIAL);
+    if (st != ARBORX_OK)
+        return st;
     {
         ProfScope ps("copy_stash", s);
         k_copy_stash<<<grid_for(m, 256, INT32_MAX), 256, 0, s>>>(stash, perm, m, counts, offsets, indices);
         AX_HIP(hipGetLastError());
     }
     const float r2 = radius * radius;
-    arborx_status st = ARBORX_OK;
     switch (t.dim) {
     case 2:
         if ((st = fill_rows_impl<2>(t, pred, queries, m, r2, big_list, nbig, offsets, indices, s)) == ARBORX_OK)
@@ -622,6 +677,9 @@ arborx_status spatial_reduce(const TreeDev &t, const float *queries, int64_t m, 
             st = fill_async<int64_t>(sums, m, 0, s);
         return st;
     }
+    arborx_status st = check_qnodes(t.qnodes, t.n, OP_REDUCE);
+    if (st != ARBORX_OK)
+        return st;
     const float r2 = radius * radius;
     const float scale = ldexpf(1.0f, scale_bits);
     AX_DISPATCH_DIM(t.dim, (reduce_impl<D>(t, queries, m, r2, op, scale, perm, counts, sums, s)));
@@ -637,6 +695,9 @@ arborx_status knn_query(const TreeDev &t, const float *queries, int64_t m, int k
         AX_HIP(hipGetLastError());
         return ARBORX_OK;
     }
+    arborx_status st = check_qnodes(t.qnodes, t.n, OP_KNN);
+    if (st != ARBORX_OK)
+        return st;
     AX_DISPATCH_DIM(t.dim, (knn_impl<D>(t, queries, m, k, perm, dist2, indices, s)));
 }
 

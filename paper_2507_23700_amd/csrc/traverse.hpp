@@ -36,13 +36,17 @@ struct ShortStack {
         lds[((base + cnt) & mask) * stride] = x;
         ++cnt;
     }
+    // The newest spilled entry sits just below the ring's oldest one: when the
+    // ring is empty it moves back first, so every pop reads LDS.
     __device__ __forceinline__ E pop()
     {
-        if (cnt > 0) {
-            --cnt;
-            return lds[((base + cnt) & mask) * stride];
+        if (cnt == 0) {
+            --base;
+            lds[(base & mask) * stride] = spill[--ns];
+            cnt = 1;
         }
-        return spill[--ns];
+        --cnt;
+        return lds[((base + cnt) & mask) * stride];
     }
 };
 
@@ -248,6 +252,86 @@ __device__ __forceinline__ void traverse_spatial_rope(const Node<D> *__restrict_
             if (nd.range_r >= last_leaf)
                 break;
             p = nd.range_r;
+        }
+    }
+}
+
+// Exact test of sorted leaf record `pos`: f(value index, d2) on a match.
+template <int D, class P, class F>
+__device__ __forceinline__ void leaf_exact(const float *__restrict__ leaves, int kind, int pos, const P &pred, F &f)
+{
+    const float *lf = leaves + (int64_t)pos * leaf_floats(D, kind);
+    float lo[D], hi[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = lf[d];
+        hi[d] = kind == ARBORX_BOXES ? lf[D + d] : lf[d];
+    }
+    float d2;
+    if (pred.hit(lo, hi, d2))
+        f(__float_as_int(lf[kind == ARBORX_BOXES ? 2 * D : D]), d2);
+}
+
+// Decode both child boxes of a quantized node in the tree's frame.
+template <int D>
+__device__ __forceinline__ void qboxes(const QNode<D> &nd, const float *flo, const float *fsc, float (&lo)[2][D],
+                                       float (&hi)[2][D])
+{
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            lo[c][d] = qdecode(nd.q[c][0][d], flo[d], fsc[d]);
+            hi[c][d] = qdecode(nd.q[c][1][d], flo[d], fsc[d]);
+        }
+}
+
+// The short-stack walk over quantized nodes.  Child boxes decode to supersets
+// of the true boxes, so no matching subtree is skipped; a leaf whose decoded
+// box passes is then tested exactly on its leaf record.
+template <int D, class P, class F>
+__device__ __forceinline__ void traverse_spatial_q(const QNode<D> *__restrict__ nodes, const TreeHeader &h,
+                                                   int n_nodes, const float *__restrict__ leaves, int kind,
+                                                   const P &pred, ShortStack<int> &st, F &f)
+{
+    float flo[D], fsc[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        flo[d] = h.lo[d];
+        fsc[d] = h.qscale[d];
+    }
+    int cur = h.root;
+    for (int iter = 0; iter <= n_nodes; ++iter) {
+        if ((unsigned)cur >= (unsigned)n_nodes)
+            break;
+        QNode<D> nd;
+        load_qnode(nodes, cur, nd);
+        float lo[2][D], hi[2][D];
+        qboxes<D>(nd, flo, fsc, lo, hi);
+        float d0, d1;
+        bool h0 = pred.hit(lo[0], hi[0], d0);
+        bool h1 = pred.hit(lo[1], hi[1], d1);
+        const int c0 = nd.child[0], c1 = nd.child[1];
+        if (h0 && c0 < 0) {
+            if (c0 != kEmptyRef)
+                leaf_exact<D>(leaves, kind, ~c0, pred, f);
+            h0 = false;
+        }
+        if (h1 && c1 < 0) {
+            if (c1 != kEmptyRef)
+                leaf_exact<D>(leaves, kind, ~c1, pred, f);
+            h1 = false;
+        }
+        if (h0) {
+            if (h1)
+                st.push(c1);
+            cur = c0;
+        } else if (h1) {
+            cur = c1;
+        } else {
+            if (st.empty())
+                break;
+            cur = st.pop();
         }
     }
 }
@@ -506,6 +590,111 @@ __device__ __forceinline__ void knn_search_wave(const Node<D> *__restrict__ node
                 }
             }
             if (cur < 0)
+                break;
+        }
+    }
+}
+
+// kNN over quantized nodes: as knn_search, pruning with the decoded (larger)
+// boxes and offering leaves with exact distances from their records.
+template <int D, int K>
+__device__ __forceinline__ void knn_search_q(const QNode<D> *__restrict__ nodes, int n_nodes,
+                                             const float *__restrict__ leaves, int kind, const TreeHeader &hdr,
+                                             const float *q, float (&bd)[K], int (&bi)[K], ShortStack<KnnEntry> &st,
+                                             int seed)
+{
+    const int n = hdr.n;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        bd[s] = INFINITY;
+        bi[s] = INT32_MAX;
+    }
+    if (n <= 0)
+        return;
+    float flo[D], fsc[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        flo[d] = hdr.lo[d];
+        fsc[d] = hdr.qscale[d];
+    }
+    const int lf = leaf_floats(D, kind);
+    if (seed && n >= K) {
+        int cur = hdr.root, pos = hdr.start;
+        for (int iter = 0; iter <= n_nodes; ++iter) {
+            if ((unsigned)cur >= (unsigned)n_nodes)
+                break;
+            QNode<D> nd;
+            load_qnode(nodes, cur, nd);
+            float lo[2][D], hi[2][D];
+            qboxes<D>(nd, flo, fsc, lo, hi);
+            const float d0 = box_d2<D>(q, lo[0], hi[0]);
+            const float d1 = box_d2<D>(q, lo[1], hi[1]);
+            const int go = (d1 < d0 && nd.child[1] != kEmptyRef) ? 1 : 0;
+            const int c = go ? nd.child[1] : nd.child[0];
+            if (c < 0) {
+                pos = ~c;
+                break;
+            }
+            cur = c;
+        }
+        int w0 = pos - K;
+        const int lo_lim = hdr.start, hi_lim = hdr.start + n;
+        w0 = w0 > hi_lim - 2 * K ? hi_lim - 2 * K : w0;
+        w0 = w0 < lo_lim ? lo_lim : w0;
+        const int w1 = (w0 + 2 * K < hi_lim) ? w0 + 2 * K : hi_lim;
+        for (int p = w0; p < w1; ++p)
+            knn_offer<K>(bd, bi, leaf_d2<D>(leaves, kind, p, q), p);
+        const float bound = bd[K - 1];
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            bd[s] = bound;
+            bi[s] = INT32_MAX;
+        }
+    }
+    int cur = hdr.root;
+    for (int iter = 0; iter <= n_nodes; ++iter) {
+        if ((unsigned)cur >= (unsigned)n_nodes)
+            break;
+        QNode<D> nd;
+        load_qnode(nodes, cur, nd);
+        float lo[2][D], hi[2][D];
+        qboxes<D>(nd, flo, fsc, lo, hi);
+        const float d0 = box_d2<D>(q, lo[0], hi[0]);
+        const float d1 = box_d2<D>(q, lo[1], hi[1]);
+        const int c0 = nd.child[0], c1 = nd.child[1];
+        if (c0 < 0 && c0 != kEmptyRef && !(d0 > bd[K - 1])) {
+            const float *r = leaves + (int64_t)(~c0) * lf;
+            knn_offer<K>(bd, bi, leaf_d2<D>(leaves, kind, ~c0, q), __float_as_int(r[kind == ARBORX_BOXES ? 2 * D : D]));
+        }
+        if (c1 < 0 && c1 != kEmptyRef && !(d1 > bd[K - 1])) {
+            const float *r = leaves + (int64_t)(~c1) * lf;
+            knn_offer<K>(bd, bi, leaf_d2<D>(leaves, kind, ~c1, q), __float_as_int(r[kind == ARBORX_BOXES ? 2 * D : D]));
+        }
+        const bool k0 = c0 >= 0 && !(d0 > bd[K - 1]);
+        const bool k1 = c1 >= 0 && !(d1 > bd[K - 1]);
+        if (k0 && k1) {
+            if (d1 < d0) {
+                st.push(KnnEntry{c0, d0});
+                cur = c1;
+            } else {
+                st.push(KnnEntry{c1, d1});
+                cur = c0;
+            }
+        } else if (k0) {
+            cur = c0;
+        } else if (k1) {
+            cur = c1;
+        } else {
+            bool found = false;
+            while (!st.empty()) {
+                const KnnEntry e = st.pop();
+                if (!(e.d2 > bd[K - 1])) {
+                    cur = e.ref;
+                    found = true;
+                    break;
+                }
+            }
+            if (!found)
                 break;
         }
     }

@@ -56,10 +56,14 @@ def run_forest(f, cfg, k):
     return fo, host(c), host(s), host(c0), host(d2), host(ix)
 
 
-@pytest.mark.parametrize("k", [1, 8, 16])
-def test_forest_vs_oracle(k):
+@pytest.mark.parametrize("k,quantized_nodes", [(1, 0), (8, 0), (16, 0), (1, 1), (8, 1)])
+def test_forest_vs_oracle(k, quantized_nodes):
     cfg = small_forest(k)
-    fo, c, s, c0, d2, ix = run_forest(None, cfg, k)
+    ax.arborx_set_tuning(quantized_nodes=quantized_nodes)  # before the build: it decides what is stored
+    try:
+        fo, c, s, c0, d2, ix = run_forest(None, cfg, k)
+    finally:
+        ax.arborx_reset_tuning()
     oc, os_ = oracle.forest_reduce(cfg["values"], cfg["tree_offsets"], cfg["queries"], cfg["batch_offsets"],
                                    cfg["batch_tree"], cfg["batch_radius"])
     od2, oix = oracle.forest_knn(cfg["values"], cfg["tree_offsets"], cfg["queries"], cfg["batch_offsets"],

@@ -49,11 +49,12 @@ def check_knn(tree, data, q, k, dim=3, kind=oracle.POINTS):
     assert np.array_equal(host(d2), o_d2)
 
 
-def check_reduce(tree, data, q, r, dim=3, kind=oracle.POINTS):
+def check_reduce(tree, data, q, r, dim=3, kind=oracle.POINTS, sums=True):
     c, s = ax.arborx_query_spatial_reduce(tree, dev(q), float(r), ax.COUNT_SUMDIST)
     oc, os_ = oracle.reduce(data, q, r, dim=dim, kind=kind)
     assert np.array_equal(host(c), oc)
-    assert np.array_equal(host(s), os_)
+    if sums:  # fixed-point sums are only defined while the scaled distances fit in 63 bits
+        assert np.array_equal(host(s), os_)
     c2, _ = ax.arborx_query_spatial_reduce(tree, dev(q), float(r), ax.COUNT)
     assert np.array_equal(host(c2), oc)
 
@@ -352,15 +353,17 @@ def test_capacity_protocol():
     assert total.value == o_off[-1] and np.array_equal(host(off), o_off)
 
 
-@pytest.mark.parametrize("block,order,stack,schedule", [(64, 1, 1, 0), (128, 0, 2, 0), (256, 1, 4, 0), (256, 0, 64, 0),
-                                                        (64, 0, 16, 0), (256, 1, 16, 1), (64, 0, 16, 1), (128, 1, 4, 1),
-                                                        (256, 1, 16, 2), (64, 0, 16, 2)])
-def test_schedules_identical(block, order, stack, schedule):
+@pytest.mark.parametrize("block,order,stack,schedule,quantized_nodes",
+                         [(64, 1, 1, 0, 0), (128, 0, 2, 0, 0), (256, 1, 4, 0, 0), (256, 0, 64, 0, 0), (64, 0, 16, 0, 0),
+                          (64, 1, 1, 0, 1), (256, 0, 64, 0, 1), (128, 1, 16, 0, 1),
+                          (256, 1, 16, 1, 0), (64, 0, 16, 1, 0), (128, 1, 4, 1, 0),
+                          (256, 1, 16, 2, 0), (64, 0, 16, 2, 0)])
+def test_schedules_identical(block, order, stack, schedule, quantized_nodes):
     cfg = inputs.config_small(n=20_000, m=4000)
     data, q, r = cfg["data"], cfg["queries"], cfg["radius"]
-    t = ax.arborx_bvh_build(dev(data))
-    ax.arborx_set_tuning(block=block, order=order, stack=stack, schedule=schedule)
+    ax.arborx_set_tuning(block=block, order=order, stack=stack, schedule=schedule, quantized_nodes=quantized_nodes)
     try:
+        t = ax.arborx_bvh_build(dev(data))
         check_spatial(t, data, q, r)
         check_knn(t, data, q, 10)
         check_reduce(t, data, q, r)
@@ -421,10 +424,83 @@ def test_knn_seeding_off_identical(k):
     s = inputs.config_paper("shell", n=30_000, m=3000)
     t = ax.arborx_bvh_build(dev(s["data"]))
     check_knn(t, s["data"], s["queries"], k)
-    for kw in (dict(no_seed=1), dict(schedule=1), dict(schedule=1, no_seed=1), dict(schedule=2)):
+    for kw in (dict(no_seed=1), dict(schedule=1), dict(schedule=1, no_seed=1), dict(schedule=2),
+               dict(quantized_nodes=1), dict(quantized_nodes=1, no_seed=1)):
         ax.arborx_set_tuning(**kw)
         try:
+            if "quantized_nodes" in kw:
+                t = ax.arborx_bvh_build(dev(s["data"]))
             check_knn(t, s["data"], s["queries"], k)
             check_spatial(t, s["data"], s["queries"], 0.01)
         finally:
             ax.arborx_reset_tuning()
+
+
+def _both_node_forms(build, fn):
+    for qn in (0, 1):
+        ax.arborx_set_tuning(quantized_nodes=qn)
+        try:
+            fn(build())
+        finally:
+            ax.arborx_reset_tuning()
+
+
+@pytest.mark.parametrize("case", ["huge_extent", "denormal_extent", "offset_tiny_extent", "flat_dimension"])
+def test_quantized_frames(case):
+    # frames where 16-bit codes collapse, the extent leaves the float range or
+    # the step underflows: decoded child boxes must still contain the true ones
+    g = np.random.default_rng(11)
+    x = g.random((6000, 3))
+    y = g.random((500, 3))
+    if case == "huge_extent":
+        data, q, r = (x * 4e37 - 2e37).astype(np.float32), (y * 4e37 - 2e37).astype(np.float32), 3e36
+        data[0, 0], data[1, 0] = np.float32(-3.3e38), np.float32(3.3e38)
+    elif case == "denormal_extent":
+        data, q, r = (x * 1e-39).astype(np.float32), (y * 1e-39).astype(np.float32), 0.0
+    elif case == "offset_tiny_extent":
+        data, q, r = (1e6 + x * 2e-2).astype(np.float32), (1e6 + y * 2e-2).astype(np.float32), 2e-3
+    else:
+        x[:, 2] = 0.25
+        y[:, 2] = 0.25
+        data, q, r = x.astype(np.float32), y.astype(np.float32), 0.02
+    def run(t):
+        check_spatial(t, data, q, r)
+        check_knn(t, data, q, 9)
+        check_reduce(t, data, q, r, sums=case != "huge_extent")
+    _both_node_forms(lambda: ax.arborx_bvh_build(dev(data)), run)
+
+
+def test_quantized_boxes_and_dims():
+    g = np.random.default_rng(12)
+    for dim in (2, 6):
+        data = g.random((7000, dim)).astype(np.float32)
+        q = g.random((400, dim)).astype(np.float32)
+        r = 0.03 if dim == 2 else 0.3
+
+        def run(t):
+            check_spatial(t, data, q, r, dim=dim)
+            check_knn(t, data, q, 5, dim=dim)
+        _both_node_forms(lambda: ax.arborx_bvh_build(dev(data)), run)
+    lo = g.random((5000, 3)).astype(np.float32)
+    boxes = np.ascontiguousarray(np.stack([lo, lo + (0.02 * g.random((5000, 3))).astype(np.float32)], axis=1))
+    q = g.random((300, 3)).astype(np.float32)
+    def run_boxes(t):
+        check_spatial(t, boxes, q, 0.01, kind=oracle.BOXES)
+        check_knn(t, boxes, q, 6, kind=oracle.BOXES)
+    _both_node_forms(lambda: ax.arborx_bvh_build(dev(boxes), kind=ax.BOXES), run_boxes)
+
+
+def test_quantized_request_needs_quantized_build():
+    cfg = inputs.config_small(n=3000, m=200)
+    t = ax.arborx_bvh_build(dev(cfg["data"]))
+    ax.arborx_set_tuning(quantized_nodes=1)
+    try:
+        with pytest.raises(ax.ArborXError, match="built without quantized nodes"):
+            ax.arborx_query_knn(t, dev(cfg["queries"]), 4)
+        with pytest.raises(ax.ArborXError, match="built without quantized nodes"):
+            ax.arborx_query_spatial_reduce(t, dev(cfg["queries"]), 0.05, ax.COUNT)
+        t2 = ax.arborx_bvh_build(dev(cfg["data"]))
+        check_knn(t2, cfg["data"], cfg["queries"], 4)
+    finally:
+        ax.arborx_reset_tuning()
+    check_knn(t2, cfg["data"], cfg["queries"], 4)  # float nodes are always there
