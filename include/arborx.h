@@ -72,8 +72,9 @@ typedef struct arborx_tuning {
                              only; kNN uses the short stack) */
     int32_t build;        /* hierarchy handoff: 0 = chunked (LDS inside chunks), 1 = single pass (device scope);
                              both give the identical tree */
-    int32_t no_seed;      /* kNN: 0 = start the walk with an upper bound from the 2k leaves nearest in Morton
-                             order (default), 1 = start from +inf */
+    int32_t seed_mode;    /* kNN starting bound: 0 = the k-th smallest distance among the 2k leaves around the
+                             query's Morton position (default), 1 = none (+inf), 2 = the largest distance
+                             among the k leaves around it */
     int32_t quantized_nodes; /* thread schedules: 0 = walk float child boxes (default), 1 = walk child boxes stored
                                 as 16-bit codes rounded outward, deciding leaves on their exact records */
 } arborx_tuning;

@@ -131,7 +131,7 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
             best->stack = cached.stack;
             best->schedule = cached.schedule;
             best->build = cached.build;
-            best->no_seed = cached.seed ? 0 : 1;
+            best->seed_mode = cached.seed;
             best->quantized_nodes = cached.nodes;
         }
         if (best_ms)
@@ -189,11 +189,13 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
     }
     if (op == OP_KNN) {
         const size_t nbase = cands.size();
-        for (size_t i = 0; i < nbase; i += 4) {
-            Candidate c = cands[i];
-            c.t.seed = 1 - c.t.seed;
-            cands.push_back(c);
-        }
+        for (size_t i = 0; i < nbase; i += 4)
+            for (int mode = 0; mode < 3; ++mode)
+                if (mode != cands[i].t.seed) {
+                    Candidate c = cands[i];
+                    c.t.seed = mode;
+                    cands.push_back(c);
+                }
     }
 
     Temps tmp(s);
@@ -296,7 +298,7 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
         best->stack = b.stack;
         best->schedule = b.schedule;
         best->build = b.build;
-        best->no_seed = b.seed ? 0 : 1;
+        best->seed_mode = b.seed;
         best->quantized_nodes = b.nodes;
     }
     if (best_ms)

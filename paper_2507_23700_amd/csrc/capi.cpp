@@ -205,9 +205,9 @@ static arborx_status to_tuning(const arborx_tuning *t, const Tuning &base, Tunin
     if (t->build != 0 && t->build != 1)
         return fail(ARBORX_E_INVALID, "build must be 0 or 1");
     n.build = t->build;
-    if (t->no_seed != 0 && t->no_seed != 1)
-        return fail(ARBORX_E_INVALID, "no_seed must be 0 or 1");
-    n.seed = t->no_seed ? 0 : 1;
+    if (t->seed_mode < 0 || t->seed_mode > 2)
+        return fail(ARBORX_E_INVALID, "seed_mode must be 0, 1 or 2");
+    n.seed = t->seed_mode;
     if (t->quantized_nodes != 0 && t->quantized_nodes != 1)
         return fail(ARBORX_E_INVALID, "quantized_nodes must be 0 or 1");
     n.nodes = t->quantized_nodes;
@@ -221,7 +221,7 @@ static void from_tuning(const Tuning &g, arborx_tuning *t)
     t->stack = g.stack;
     t->schedule = g.schedule;
     t->build = g.build;
-    t->no_seed = g.seed ? 0 : 1;
+    t->seed_mode = g.seed;
     t->quantized_nodes = g.nodes;
 }
 

@@ -144,8 +144,7 @@ __global__ __launch_bounds__(kForestBlock) void k_forest_knn(
             continue;
         const int b = batch_of(boff, B, qi);
         const int tr = btree[b];
-        float bd[K];
-        int bi[K];
+        TopK<K> best;
         TreeHeader h;
         if (tr >= 0 && tr < T) {
             h = hdrs[tr];
@@ -160,13 +159,10 @@ __global__ __launch_bounds__(kForestBlock) void k_forest_knn(
             q[d] = queries[qi * D + d];
         ShortStack<KnnEntry> st(reinterpret_cast<KnnEntry *>(s_stack) + threadIdx.x, blockDim.x, stack_cap, spill);
         if (QN)
-            knn_search_q<D, K>(qnodes, n_nodes, leaves, kind, h, q, bd, bi, st, seed);
+            knn_search_q<D, K>(qnodes, n_nodes, leaves, kind, h, q, best, st, seed);
         else
-            knn_search<D, K>(nodes, n_nodes, leaves, kind, h, q, bd, bi, st, seed);
-#pragma unroll
-        for (int s = 0; s < K; ++s)  // value index -> index local to the tree
-            bi[s] = bi[s] == INT32_MAX ? INT32_MAX : bi[s] - h.start;
-        knn_store<K>(bd, bi, k_out, out_d2 + qi * k_out, out_idx + qi * k_out);
+            knn_search<D, K>(nodes, n_nodes, leaves, kind, h, q, best, st, seed);
+        best.store(k_out, out_d2 + qi * k_out, out_idx + qi * k_out, h.start);  // indices local to the tree
     }
 }
 

@@ -40,7 +40,7 @@ struct Tuning {
     int stack = 16;
     int schedule = 0;
     int build = 0;
-    int seed = 1;   // kNN: bound the walk with nearby leaves first
+    int seed = 0;   // kNN starting bound: 0 k-th of 2k nearby leaves, 1 none, 2 farthest of k nearby leaves
     int nodes = 0;  // 0: float child boxes, 1: quantized 16-bit child boxes (exact leaf tests)
 };
 // Tuning is kept per operation kind so the autotuner can pick each separately.
@@ -178,7 +178,7 @@ enum class Pred { Sphere, Box };
 arborx_status query_order(const TreeDev &t, const float *queries, int64_t m, Pred pred, int op, uint32_t **perm,
                           Temps &tmp, hipStream_t s);
 // Count pass; also stores each query's first kRowSortRegs matches, sorted, in
-// stash[sorted position][kRowSortRegs].
+// stash[query][kRowSortRegs].
 arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
                             const uint32_t *perm, int32_t *counts, int32_t *stash, hipStream_t s);
 // Fill pass: stash rows are copied; listed longer rows are walked again.

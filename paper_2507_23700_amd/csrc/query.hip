@@ -26,8 +26,9 @@ __device__ __forceinline__ int node_count(const TreeHeader *hdr) { return hdr->n
 
 // Count pass of a CSR query.  With a stash, each query also keeps its first
 // kRowSortRegs matches sorted in registers and stores them in the stash row of
-// its Morton position (64 contiguous bytes per thread, so a wavefront writes
-// one coalesced 4 KiB block); rows that fit need no second walk.
+// its input position (one aligned 64-byte segment per thread), so that the
+// copy into the CSR array later streams rows, counts and offsets in input
+// order; rows that fit need no second walk.
 template <int D, class P, bool STASH, int SCHED>
 __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
                                 const float *__restrict__ leaves, int kind, const TreeHeader *__restrict__ hdr,
@@ -72,7 +73,7 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D
     if (!active)
         return;
     if (STASH) {
-        int4 *row = reinterpret_cast<int4 *>(stash + t * kRowSortRegs);
+        int4 *row = reinterpret_cast<int4 *>(stash + qi * kRowSortRegs);
 #pragma unroll
         for (int k = 0; k < kRowSortRegs / 4; ++k)
             row[k] = make_int4(buf[4 * k], buf[4 * k + 1], buf[4 * k + 2], buf[4 * k + 3]);
@@ -80,21 +81,18 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D
     counts[qi] = c;
 }
 
-// Rows of at most kRowSortRegs matches: copy the sorted stash row to the CSR slot.
-__global__ void k_copy_stash(const int32_t *__restrict__ stash, const uint32_t *__restrict__ perm, int64_t m,
-                             const int32_t *__restrict__ counts, const int64_t *__restrict__ offsets,
-                             int32_t *__restrict__ indices)
+// Rows of at most kRowSortRegs matches: copy the sorted stash row to the CSR
+// slot.  Thread i handles query i, so consecutive lanes fill adjacent rows.
+__global__ void k_copy_stash(const int32_t *__restrict__ stash, int64_t m, const int32_t *__restrict__ counts,
+                             const int64_t *__restrict__ offsets, int32_t *__restrict__ indices)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= m)
-        return;
-    const int64_t qi = perm ? (int64_t)perm[t] : t;
+    const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (qi >= m)
         return;
     const int c = counts[qi];
     if (c > kRowSortRegs)
         return;
-    const int4 *row = reinterpret_cast<const int4 *>(stash + t * kRowSortRegs);
+    const int4 *row = reinterpret_cast<const int4 *>(stash + qi * kRowSortRegs);
     const int64_t o = offsets[qi];
     int v[kRowSortRegs];
 #pragma unroll
@@ -287,21 +285,20 @@ __global__ void k_knn(const Node<D> *__restrict__ nodes, const QNode<D> *__restr
 #pragma unroll
     for (int d = 0; d < D; ++d)
         q[d] = active ? queries[qi * D + d] : 0.0f;
-    float bd[K];
-    int bi[K];
+    TopK<K> best;
     if (WAVE) {
         KnnEntry *wstack = reinterpret_cast<KnnEntry *>(s_stack) + wave_id() * kWaveStack;
-        knn_search_wave<D, K>(nodes, n_nodes, leaves, kind, *hdr, q, active, bd, bi, wstack, seed);
+        knn_search_wave<D, K>(nodes, n_nodes, leaves, kind, *hdr, q, active, best, wstack, seed);
     } else {
         KnnEntry spill[kSpill];
         ShortStack<KnnEntry> st(reinterpret_cast<KnnEntry *>(s_stack) + threadIdx.x, blockDim.x, stack_cap, spill);
         if (QN)
-            knn_search_q<D, K>(qnodes, n_nodes, leaves, kind, *hdr, q, bd, bi, st, seed);
+            knn_search_q<D, K>(qnodes, n_nodes, leaves, kind, *hdr, q, best, st, seed);
         else
-            knn_search<D, K>(nodes, n_nodes, leaves, kind, *hdr, q, bd, bi, st, seed);
+            knn_search<D, K>(nodes, n_nodes, leaves, kind, *hdr, q, best, st, seed);
     }
     if (active)
-        knn_store<K>(bd, bi, k_out, out_d2 + qi * k_out, out_idx + qi * k_out);
+        best.store(k_out, out_d2 + qi * k_out, out_idx + qi * k_out, 0);
 }
 
 __global__ void k_knn_empty(int64_t total, float *d2, int32_t *idx)
@@ -593,7 +590,7 @@ arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, in
         return st;
     {
         ProfScope ps("copy_stash", s);
-        k_copy_stash<<<grid_for(m, 256, INT32_MAX), 256, 0, s>>>(stash, perm, m, counts, offsets, indices);
+        k_copy_stash<<<grid_for(m, 256, INT32_MAX), 256, 0, s>>>(stash, m, counts, offsets, indices);
         AX_HIP(hipGetLastError());
     }
     const float r2 = radius * radius;

@@ -111,6 +111,23 @@ struct BoxQuery {
     }
 };
 
+// Exact test of the sorted leaf record `pos` (the value's own box) against
+// the predicate, calling f(index, d2) on a match.
+template <int D, class P, class F>
+__device__ __forceinline__ void leaf_exact(const float *__restrict__ leaves, int kind, int pos, const P &pred, F &f)
+{
+    const float *lf = leaves + (int64_t)pos * leaf_floats(D, kind);
+    float lo[D], hi[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = lf[d];
+        hi[d] = kind == ARBORX_BOXES ? lf[D + d] : lf[d];
+    }
+    float d2;
+    if (pred.hit(lo, hi, d2))
+        f(__float_as_int(lf[kind == ARBORX_BOXES ? 2 * D : D]), d2);
+}
+
 // Depth-first walk calling f(index, d2) on every matching value.
 // A depth-first walk enters each internal node at most once, so `limit`
 // iterations (more than the node count) bound every walk even on a corrupt
@@ -256,22 +273,6 @@ __device__ __forceinline__ void traverse_spatial_rope(const Node<D> *__restrict_
     }
 }
 
-// Exact test of sorted leaf record `pos`: f(value index, d2) on a match.
-template <int D, class P, class F>
-__device__ __forceinline__ void leaf_exact(const float *__restrict__ leaves, int kind, int pos, const P &pred, F &f)
-{
-    const float *lf = leaves + (int64_t)pos * leaf_floats(D, kind);
-    float lo[D], hi[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        lo[d] = lf[d];
-        hi[d] = kind == ARBORX_BOXES ? lf[D + d] : lf[d];
-    }
-    float d2;
-    if (pred.hit(lo, hi, d2))
-        f(__float_as_int(lf[kind == ARBORX_BOXES ? 2 * D : D]), d2);
-}
-
 // Decode both child boxes of a quantized node in the tree's frame.
 template <int D>
 __device__ __forceinline__ void qboxes(const QNode<D> &nd, const float *flo, const float *fsc, float (&lo)[2][D],
@@ -355,24 +356,54 @@ struct KnnEntry {
     float d2;
 };
 
+// The K best (distance, index) pairs of one query in ascending order, each
+// packed as one 64-bit key: the float32 bits of a distance >= 0 order like the
+// distance itself, so comparing keys compares distances first and breaks ties
+// by the smaller index, with no mask arithmetic.  An empty slot holds index
+// INT32_MAX.
 template <int K>
-__device__ __forceinline__ void knn_offer(float (&bd)[K], int (&bi)[K], float d, int id)
-{
-    if (!(d < bd[K - 1] || (d == bd[K - 1] && id < bi[K - 1])))
-        return;
-    float vd = d;
-    int vi = id;
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
-        const bool lt = vd < bd[s] || (vd == bd[s] && vi < bi[s]);
-        const float td = bd[s];
-        const int ti = bi[s];
-        bd[s] = lt ? vd : td;
-        bi[s] = lt ? vi : ti;
-        vd = lt ? td : vd;
-        vi = lt ? ti : vi;
+struct TopK {
+    uint64_t key[K];
+
+    __device__ static __forceinline__ uint64_t pack(float d, int id)
+    {
+        return ((uint64_t)__float_as_uint(d) << 32) | (uint32_t)id;
     }
-}
+    __device__ __forceinline__ void reset(float bound)
+    {
+#pragma unroll
+        for (int s = 0; s < K; ++s)
+            key[s] = pack(bound, INT32_MAX);
+    }
+    // distance of the K-th best: a box farther than this cannot contribute
+    __device__ __forceinline__ float bound() const { return __uint_as_float((uint32_t)(key[K - 1] >> 32)); }
+    __device__ __forceinline__ void offer(float d, int id)
+    {
+        uint64_t v = pack(d, id);
+        if (!(v < key[K - 1]))
+            return;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            const uint64_t a = key[s];
+            const bool lt = v < a;
+            key[s] = lt ? v : a;
+            v = lt ? a : v;
+        }
+    }
+    // Write the first k_out, indices relative to `base`; empty slots become (+inf, -1).
+    __device__ __forceinline__ void store(int k_out, float *d2, int32_t *idx, int base) const
+    {
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            if (s < k_out) {
+                const int id = (int)(uint32_t)key[s];
+                const bool empty = id == INT32_MAX;
+                d2[s] = empty ? INFINITY : __uint_as_float((uint32_t)(key[s] >> 32));
+                idx[s] = empty ? -1 : id - base;
+            }
+        }
+    }
+};
 
 // Squared distance from q to the value stored in leaf record `pos`.
 template <int D>
@@ -386,6 +417,37 @@ __device__ __forceinline__ float leaf_d2(const float *__restrict__ leaves, int k
         hi[d] = kind == ARBORX_BOXES ? lf[D + d] : lf[d];
     }
     return box_d2<D>(q, lo, hi);
+}
+
+// Starting bound for the kNN walk from the sorted leaves around position pos
+// (where a greedy descent towards q ends).  mode 0: the k-th smallest distance
+// among the 2k leaves around pos; mode 2: the largest distance among the k
+// leaves around pos (no insertion work, a looser bound).  Either is at least
+// the true k-th neighbour distance, so the slots start as k copies of
+// (bound, INT32_MAX), which admit every true result.  Needs n >= k.
+template <int D, int K>
+__device__ __forceinline__ void seed_window(const float *__restrict__ leaves, int kind, const TreeHeader &hdr, int pos,
+                                            const float *q, TopK<K> &best, int mode)
+{
+    const int lo_lim = hdr.start, hi_lim = hdr.start + hdr.n;
+    if (mode == 2) {
+        int w0 = pos - K / 2;
+        w0 = w0 > hi_lim - K ? hi_lim - K : w0;
+        w0 = w0 < lo_lim ? lo_lim : w0;
+        float b = 0.0f;
+#pragma unroll 4
+        for (int p = w0; p < w0 + K; ++p)
+            b = fmaxf(b, leaf_d2<D>(leaves, kind, p, q));
+        best.reset(b);
+        return;
+    }
+    int w0 = pos - K;
+    w0 = w0 > hi_lim - 2 * K ? hi_lim - 2 * K : w0;
+    w0 = w0 < lo_lim ? lo_lim : w0;
+    const int w1 = (w0 + 2 * K < hi_lim) ? w0 + 2 * K : hi_lim;
+    for (int p = w0; p < w1; ++p)
+        best.offer(leaf_d2<D>(leaves, kind, p, q), p);  // distinct keys; only distances matter
+    best.reset(best.bound());
 }
 
 // Nearest-first walk keeping the K best (d2, index) pairs sorted in
@@ -402,18 +464,14 @@ __device__ __forceinline__ float leaf_d2(const float *__restrict__ leaves, int k
 template <int D, int K>
 __device__ __forceinline__ void knn_search(const Node<D> *__restrict__ nodes, int n_nodes,
                                            const float *__restrict__ leaves, int kind, const TreeHeader &hdr,
-                                           const float *q, float (&bd)[K], int (&bi)[K], ShortStack<KnnEntry> &st,
+                                           const float *q, TopK<K> &best, ShortStack<KnnEntry> &st,
                                            int seed)
 {
     const int n = hdr.n;
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
-        bd[s] = INFINITY;
-        bi[s] = INT32_MAX;
-    }
+best.reset(INFINITY);
     if (n <= 0)
         return;
-    if (seed && n >= K) {
+    if (seed != 1 && n >= K) {
         int cur = hdr.root, pos = hdr.start;
         for (int iter = 0; iter <= n_nodes; ++iter) {
             if ((unsigned)cur >= (unsigned)n_nodes)
@@ -431,19 +489,7 @@ __device__ __forceinline__ void knn_search(const Node<D> *__restrict__ nodes, in
             cur = c;
         }
         // window of 2K leaves around pos inside [start, start + n)
-        int w0 = pos - K;
-        const int lo_lim = hdr.start, hi_lim = hdr.start + n;
-        w0 = w0 > hi_lim - 2 * K ? hi_lim - 2 * K : w0;
-        w0 = w0 < lo_lim ? lo_lim : w0;
-        const int w1 = (w0 + 2 * K < hi_lim) ? w0 + 2 * K : hi_lim;
-        for (int p = w0; p < w1; ++p)
-            knn_offer<K>(bd, bi, leaf_d2<D>(leaves, kind, p, q), p);  // distinct keys; only distances matter
-        const float bound = bd[K - 1];
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            bd[s] = bound;
-            bi[s] = INT32_MAX;
-        }
+        seed_window<D, K>(leaves, kind, hdr, pos, q, best, seed);
     }
     int cur = hdr.root;
     for (int iter = 0; iter <= n_nodes; ++iter) {
@@ -455,11 +501,11 @@ __device__ __forceinline__ void knn_search(const Node<D> *__restrict__ nodes, in
         const float d1 = box_d2<D>(q, nd.lo[1], nd.hi[1]);
         const int c0 = nd.child[0], c1 = nd.child[1];
         if (c0 < 0 && c0 != kEmptyRef)
-            knn_offer<K>(bd, bi, d0, ~c0);
+            best.offer(d0, ~c0);
         if (c1 < 0 && c1 != kEmptyRef)
-            knn_offer<K>(bd, bi, d1, ~c1);
-        const bool k0 = c0 >= 0 && !(d0 > bd[K - 1]);
-        const bool k1 = c1 >= 0 && !(d1 > bd[K - 1]);
+            best.offer(d1, ~c1);
+        const bool k0 = c0 >= 0 && !(d0 > best.bound());
+        const bool k1 = c1 >= 0 && !(d1 > best.bound());
         if (k0 && k1) {
             if (d1 < d0) {
                 st.push(KnnEntry{c0, d0});
@@ -476,7 +522,7 @@ __device__ __forceinline__ void knn_search(const Node<D> *__restrict__ nodes, in
             bool found = false;
             while (!st.empty()) {
                 const KnnEntry e = st.pop();
-                if (!(e.d2 > bd[K - 1])) {
+                if (!(e.d2 > best.bound())) {
                     cur = e.ref;
                     found = true;
                     break;
@@ -505,18 +551,14 @@ __device__ __forceinline__ float wave_min(float v)
 template <int D, int K>
 __device__ __forceinline__ void knn_search_wave(const Node<D> *__restrict__ nodes, int n_nodes,
                                                 const float *__restrict__ leaves, int kind, const TreeHeader &hdr,
-                                                const float *q, bool active, float (&bd)[K], int (&bi)[K],
+                                                const float *q, bool active, TopK<K> &best,
                                                 KnnEntry *wstack, int seed)
 {
     const int n = hdr.n;
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
-        bd[s] = INFINITY;
-        bi[s] = INT32_MAX;
-    }
+best.reset(INFINITY);
     if (n <= 0)
         return;
-    if (active && seed && n >= K) {
+    if (active && seed != 1 && n >= K) {
         int cur = hdr.root, pos = hdr.start;
         for (int iter = 0; iter <= n_nodes; ++iter) {
             if ((unsigned)cur >= (unsigned)n_nodes)
@@ -533,19 +575,7 @@ __device__ __forceinline__ void knn_search_wave(const Node<D> *__restrict__ node
             }
             cur = c;
         }
-        int w0 = pos - K;
-        const int lo_lim = hdr.start, hi_lim = hdr.start + n;
-        w0 = w0 > hi_lim - 2 * K ? hi_lim - 2 * K : w0;
-        w0 = w0 < lo_lim ? lo_lim : w0;
-        const int w1 = (w0 + 2 * K < hi_lim) ? w0 + 2 * K : hi_lim;
-        for (int p = w0; p < w1; ++p)
-            knn_offer<K>(bd, bi, leaf_d2<D>(leaves, kind, p, q), p);
-        const float bound = bd[K - 1];
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            bd[s] = bound;
-            bi[s] = INT32_MAX;
-        }
+        seed_window<D, K>(leaves, kind, hdr, pos, q, best, seed);
     }
     int sp = 0;
     int cur = hdr.root;
@@ -559,11 +589,11 @@ __device__ __forceinline__ void knn_search_wave(const Node<D> *__restrict__ node
         const float d1 = box_d2<D>(q, nd.lo[1], nd.hi[1]);
         const int c0 = nd.child[0], c1 = nd.child[1];
         if (active && c0 < 0 && c0 != kEmptyRef)
-            knn_offer<K>(bd, bi, d0, ~c0);
+            best.offer(d0, ~c0);
         if (active && c1 < 0 && c1 != kEmptyRef)
-            knn_offer<K>(bd, bi, d1, ~c1);
-        const bool k0 = active && c0 >= 0 && !(d0 > bd[K - 1]);
-        const bool k1 = active && c1 >= 0 && !(d1 > bd[K - 1]);
+            best.offer(d1, ~c1);
+        const bool k0 = active && c0 >= 0 && !(d0 > best.bound());
+        const bool k1 = active && c1 >= 0 && !(d1 > best.bound());
         const bool any0 = __ballot(k0) != 0, any1 = __ballot(k1) != 0;
         if (any0 && any1) {
             const bool want1 = (k0 || k1) && d1 < d0;
@@ -584,7 +614,7 @@ __device__ __forceinline__ void knn_search_wave(const Node<D> *__restrict__ node
             while (sp > 0) {
                 --sp;
                 const KnnEntry e = sp < kWaveStack ? wstack[sp] : KnnEntry{-1, INFINITY};
-                if (__ballot(active && !(e.d2 > bd[K - 1])) != 0) {
+                if (__ballot(active && !(e.d2 > best.bound())) != 0) {
                     cur = e.ref;
                     break;
                 }
@@ -600,15 +630,11 @@ __device__ __forceinline__ void knn_search_wave(const Node<D> *__restrict__ node
 template <int D, int K>
 __device__ __forceinline__ void knn_search_q(const QNode<D> *__restrict__ nodes, int n_nodes,
                                              const float *__restrict__ leaves, int kind, const TreeHeader &hdr,
-                                             const float *q, float (&bd)[K], int (&bi)[K], ShortStack<KnnEntry> &st,
+                                             const float *q, TopK<K> &best, ShortStack<KnnEntry> &st,
                                              int seed)
 {
     const int n = hdr.n;
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
-        bd[s] = INFINITY;
-        bi[s] = INT32_MAX;
-    }
+best.reset(INFINITY);
     if (n <= 0)
         return;
     float flo[D], fsc[D];
@@ -618,7 +644,7 @@ __device__ __forceinline__ void knn_search_q(const QNode<D> *__restrict__ nodes,
         fsc[d] = hdr.qscale[d];
     }
     const int lf = leaf_floats(D, kind);
-    if (seed && n >= K) {
+    if (seed != 1 && n >= K) {
         int cur = hdr.root, pos = hdr.start;
         for (int iter = 0; iter <= n_nodes; ++iter) {
             if ((unsigned)cur >= (unsigned)n_nodes)
@@ -637,19 +663,7 @@ __device__ __forceinline__ void knn_search_q(const QNode<D> *__restrict__ nodes,
             }
             cur = c;
         }
-        int w0 = pos - K;
-        const int lo_lim = hdr.start, hi_lim = hdr.start + n;
-        w0 = w0 > hi_lim - 2 * K ? hi_lim - 2 * K : w0;
-        w0 = w0 < lo_lim ? lo_lim : w0;
-        const int w1 = (w0 + 2 * K < hi_lim) ? w0 + 2 * K : hi_lim;
-        for (int p = w0; p < w1; ++p)
-            knn_offer<K>(bd, bi, leaf_d2<D>(leaves, kind, p, q), p);
-        const float bound = bd[K - 1];
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            bd[s] = bound;
-            bi[s] = INT32_MAX;
-        }
+        seed_window<D, K>(leaves, kind, hdr, pos, q, best, seed);
     }
     int cur = hdr.root;
     for (int iter = 0; iter <= n_nodes; ++iter) {
@@ -662,16 +676,16 @@ __device__ __forceinline__ void knn_search_q(const QNode<D> *__restrict__ nodes,
         const float d0 = box_d2<D>(q, lo[0], hi[0]);
         const float d1 = box_d2<D>(q, lo[1], hi[1]);
         const int c0 = nd.child[0], c1 = nd.child[1];
-        if (c0 < 0 && c0 != kEmptyRef && !(d0 > bd[K - 1])) {
+        if (c0 < 0 && c0 != kEmptyRef && !(d0 > best.bound())) {
             const float *r = leaves + (int64_t)(~c0) * lf;
-            knn_offer<K>(bd, bi, leaf_d2<D>(leaves, kind, ~c0, q), __float_as_int(r[kind == ARBORX_BOXES ? 2 * D : D]));
+            best.offer(leaf_d2<D>(leaves, kind, ~c0, q), __float_as_int(r[kind == ARBORX_BOXES ? 2 * D : D]));
         }
-        if (c1 < 0 && c1 != kEmptyRef && !(d1 > bd[K - 1])) {
+        if (c1 < 0 && c1 != kEmptyRef && !(d1 > best.bound())) {
             const float *r = leaves + (int64_t)(~c1) * lf;
-            knn_offer<K>(bd, bi, leaf_d2<D>(leaves, kind, ~c1, q), __float_as_int(r[kind == ARBORX_BOXES ? 2 * D : D]));
+            best.offer(leaf_d2<D>(leaves, kind, ~c1, q), __float_as_int(r[kind == ARBORX_BOXES ? 2 * D : D]));
         }
-        const bool k0 = c0 >= 0 && !(d0 > bd[K - 1]);
-        const bool k1 = c1 >= 0 && !(d1 > bd[K - 1]);
+        const bool k0 = c0 >= 0 && !(d0 > best.bound());
+        const bool k1 = c1 >= 0 && !(d1 > best.bound());
         if (k0 && k1) {
             if (d1 < d0) {
                 st.push(KnnEntry{c0, d0});
@@ -688,7 +702,7 @@ __device__ __forceinline__ void knn_search_q(const QNode<D> *__restrict__ nodes,
             bool found = false;
             while (!st.empty()) {
                 const KnnEntry e = st.pop();
-                if (!(e.d2 > bd[K - 1])) {
+                if (!(e.d2 > best.bound())) {
                     cur = e.ref;
                     found = true;
                     break;
@@ -696,20 +710,6 @@ __device__ __forceinline__ void knn_search_q(const QNode<D> *__restrict__ nodes,
             }
             if (!found)
                 break;
-        }
-    }
-}
-
-// Write the first k_out of the K best; empty slots become (+inf, -1).
-template <int K>
-__device__ __forceinline__ void knn_store(const float (&bd)[K], const int (&bi)[K], int k_out, float *d2, int32_t *idx)
-{
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
-        if (s < k_out) {
-            const bool empty = bi[s] == INT32_MAX;
-            d2[s] = empty ? INFINITY : bd[s];
-            idx[s] = empty ? -1 : bi[s];
         }
     }
 }

@@ -56,10 +56,11 @@ def run_forest(f, cfg, k):
     return fo, host(c), host(s), host(c0), host(d2), host(ix)
 
 
-@pytest.mark.parametrize("k,quantized_nodes", [(1, 0), (8, 0), (16, 0), (1, 1), (8, 1)])
-def test_forest_vs_oracle(k, quantized_nodes):
+@pytest.mark.parametrize("k,tuning", [(1, {}), (8, {}), (16, {}), (1, dict(quantized_nodes=1)),
+                                      (8, dict(quantized_nodes=1)), (8, dict(seed_mode=2)), (16, dict(seed_mode=1))])
+def test_forest_vs_oracle(k, tuning):
     cfg = small_forest(k)
-    ax.arborx_set_tuning(quantized_nodes=quantized_nodes)  # before the build: it decides what is stored
+    ax.arborx_set_tuning(**tuning)  # before the build: it decides what is stored
     try:
         fo, c, s, c0, d2, ix = run_forest(None, cfg, k)
     finally:

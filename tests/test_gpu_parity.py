@@ -424,8 +424,9 @@ def test_knn_seeding_off_identical(k):
     s = inputs.config_paper("shell", n=30_000, m=3000)
     t = ax.arborx_bvh_build(dev(s["data"]))
     check_knn(t, s["data"], s["queries"], k)
-    for kw in (dict(no_seed=1), dict(schedule=1), dict(schedule=1, no_seed=1), dict(schedule=2),
-               dict(quantized_nodes=1), dict(quantized_nodes=1, no_seed=1)):
+    for kw in (dict(seed_mode=1), dict(seed_mode=2), dict(schedule=1), dict(schedule=1, seed_mode=1),
+               dict(schedule=1, seed_mode=2), dict(schedule=2), dict(quantized_nodes=1),
+               dict(quantized_nodes=1, seed_mode=1), dict(quantized_nodes=1, seed_mode=2)):
         ax.arborx_set_tuning(**kw)
         try:
             if "quantized_nodes" in kw:
