@@ -10,14 +10,65 @@
 #include "internal.hpp"
 #include "profile.hpp"
 
+// Streams that have read a structure, each with an event recorded after its
+// latest use, so that destroying the structure can order the release of its
+// memory after every use without synchronising the device.
+struct StreamUses {
+    std::mutex mu;
+    std::vector<std::pair<hipStream_t, hipEvent_t>> ev;
+
+    void note(hipStream_t s)
+    {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+            return;  // a captured graph's lifetime is the caller's to order
+        std::lock_guard<std::mutex> lock(mu);
+        hipEvent_t e = nullptr;
+        for (auto &u : ev)
+            if (u.first == s)
+                e = u.second;
+        if (!e) {
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                (void)hipStreamSynchronize(s);  // cannot track: finish the use now
+                return;
+            }
+            ev.emplace_back(s, e);
+        }
+        if (hipEventRecord(e, s) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipStreamSynchronize(s);
+        }
+    }
+    // Make `to` wait for every recorded use, then drop the events.
+    void wait_all(hipStream_t to)
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        for (auto &u : ev) {
+            (void)hipStreamWaitEvent(to, u.second, 0);
+            (void)hipEventDestroy(u.second);
+        }
+        ev.clear();
+    }
+};
+
+// Records a use on scope exit, so that error paths after a launch are covered too.
+struct NoteUse {
+    StreamUses &u;
+    hipStream_t s;
+    ~NoteUse() { u.note(s); }
+};
+
 struct arborx_tree_s {
     ax::TreeDev dev;
     hipEvent_t ready = nullptr;
+    StreamUses uses;
 };
 
 struct arborx_forest_s {
     ax::ForestDev dev;
     hipEvent_t ready = nullptr;
+    StreamUses uses;
 };
 
 // State carried from the count call of a CSR query to its fill call.
@@ -40,12 +91,15 @@ namespace ax {
 
 static thread_local std::string g_error;
 // Defaults measured on MI355X at 10^7 points: 256-thread blocks for the radius
-// walks, 64-thread blocks for kNN (its 8-byte stack entries halve occupancy).
+// walks; 64-thread blocks and an 8-entry LDS ring for kNN (its 8-byte stack
+// entries and larger register set).
 static Tuning default_tuning(int op)
 {
     Tuning t;
-    if (op == OP_KNN)
+    if (op == OP_KNN) {
         t.block = 64;
+        t.stack = 8;
+    }
     return t;
 }
 static Tuning g_tuning[OP_KINDS] = {default_tuning(OP_SPATIAL), default_tuning(OP_REDUCE), default_tuning(OP_KNN)};
@@ -150,18 +204,37 @@ static arborx_status check_tree(arborx_tree t)
     return ARBORX_OK;
 }
 
+// Stream of the calling device on which destroyed structures release their
+// memory, after waiting for the build and every recorded use.
+static hipStream_t release_stream()
+{
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        streams[dev] = nullptr;
+    }
+    return streams[dev];
+}
+
 static void release_tree(arborx_tree t)
 {
     if (!t)
         return;
+    hipStream_t rs = release_stream();
     if (t->ready)
-        (void)hipEventSynchronize(t->ready);
-    (void)hipDeviceSynchronize();
-    dfree(t->dev.nodes, nullptr);
-    dfree(t->dev.qnodes, nullptr);
-    dfree(t->dev.leaves, nullptr);
-    dfree(t->dev.hdr, nullptr);
-    (void)hipStreamSynchronize(nullptr);
+        (void)hipStreamWaitEvent(rs, t->ready, 0);
+    t->uses.wait_all(rs);
+    if (!rs)
+        (void)hipDeviceSynchronize();
+    dfree(t->dev.nodes, rs);
+    dfree(t->dev.qnodes, rs);
+    dfree(t->dev.leaves, rs);
+    dfree(t->dev.hdr, rs);
     if (t->ready)
         (void)hipEventDestroy(t->ready);
     delete t;
@@ -366,6 +439,7 @@ static arborx_status csr_begin(arborx_tree t, Pred pred, const float *queries, i
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((st = wait_tree(t, s)) != ARBORX_OK)
         return st;
+    NoteUse note_use{t->uses, s};
     arborx_plan p = new arborx_plan_s(s);
     p->tree = t;
     p->pred = pred;
@@ -419,6 +493,7 @@ static arborx_status csr_finish(arborx_plan p, int32_t *indices, int64_t capacit
                                            std::to_string((long long)p->h.total));
     if (p->h.total == 0)
         return ARBORX_OK;
+    NoteUse note_use{p->tree->uses, p->stream};
     arborx_status st = spatial_fill(p->tree->dev, p->pred, p->queries, p->m, p->radius, p->perm, p->counts, p->stash,
                                     p->offsets, p->big_list, (int64_t)p->h.big_rows, p->huge_list,
                                     (int64_t)p->h.huge_rows, indices, p->stream);
@@ -498,6 +573,7 @@ arborx_status arborx_query_knn(arborx_tree t, const float *queries, int64_t m, i
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((st = wait_tree(t, s)) != ARBORX_OK)
         return st;
+    NoteUse note_use{t->uses, s};
     Temps tmp(s);
     uint32_t *perm = nullptr;
     if ((st = query_order(t->dev, queries, m, Pred::Sphere, OP_KNN, &perm, tmp, s)) != ARBORX_OK)
@@ -526,6 +602,7 @@ arborx_status arborx_query_spatial_reduce(arborx_tree t, const float *queries, i
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((st = wait_tree(t, s)) != ARBORX_OK)
         return st;
+    NoteUse note_use{t->uses, s};
     Temps tmp(s);
     uint32_t *perm = nullptr;
     if ((st = query_order(t->dev, queries, m, Pred::Sphere, OP_REDUCE, &perm, tmp, s)) != ARBORX_OK)
@@ -604,11 +681,13 @@ arborx_status arborx_forest_destroy(arborx_forest f)
 {
     if (!f)
         return ARBORX_OK;
+    hipStream_t rs = release_stream();
     if (f->ready)
-        (void)hipEventSynchronize(f->ready);
-    (void)hipDeviceSynchronize();
-    forest_release(f->dev, nullptr);
-    (void)hipStreamSynchronize(nullptr);
+        (void)hipStreamWaitEvent(rs, f->ready, 0);
+    f->uses.wait_all(rs);
+    if (!rs)
+        (void)hipDeviceSynchronize();
+    forest_release(f->dev, rs);
     if (f->ready)
         (void)hipEventDestroy(f->ready);
     delete f;
@@ -683,6 +762,7 @@ arborx_status arborx_forest_query_reduce(arborx_forest f, const float *queries, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((st = forest_wait(f, s)) != ARBORX_OK)
         return st;
+    NoteUse note_use{f->uses, s};
     return forest_query_reduce(f->dev, queries, m, batch_offsets, batch_tree, batch_radius, B, op, scale_bits, counts,
                                sum_fixed, s);
 }
@@ -701,6 +781,7 @@ arborx_status arborx_forest_query_knn(arborx_forest f, const float *queries, int
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((st = forest_wait(f, s)) != ARBORX_OK)
         return st;
+    NoteUse note_use{f->uses, s};
     return forest_query_knn(f->dev, queries, m, batch_offsets, batch_tree, B, k, dist2, indices, s);
 }
 

@@ -111,9 +111,11 @@ __device__ __forceinline__ void load_node(const Node<D> *__restrict__ nodes, int
 // gap to the nearer face (0 inside), each square and each sum rounded once,
 // dimensions summed from 0 upwards.  For a degenerate box [p, p] it equals the
 // point-to-point squared distance bit for bit, because |fl(p - q)| = |fl(q - p)|.
-// The gap is max(lo - q, q - hi, 0) without branches: when q < lo <= hi the
-// second difference is <= 0 and the first is the rounded gap itself, and
-// symmetrically above hi; inside both are <= 0.
+// The signed gap is q - med3(q, lo, hi): for lo <= hi the median is q
+// clamped to the box, so the difference is fl(q - lo) below the box (whose
+// square equals that of fl(lo - q)), fl(q - hi) above it and 0 inside, with
+// no branch.  The one box with lo > hi, the empty slot of a one-value tree,
+// is never tested for a match: its reference is checked first.
 template <int D>
 __device__ __forceinline__ float box_d2(const float *q, const float *lo, const float *hi)
 {
@@ -121,7 +123,7 @@ __device__ __forceinline__ float box_d2(const float *q, const float *lo, const f
     float acc = 0.0f;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        const float t = fmaxf(fmaxf(lo[d] - q[d], q[d] - hi[d]), 0.0f);
+        const float t = q[d] - __builtin_amdgcn_fmed3f(q[d], lo[d], hi[d]);
         float s = t * t;
         acc = acc + s;
     }

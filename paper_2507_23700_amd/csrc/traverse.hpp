@@ -18,22 +18,22 @@ constexpr int kSpill = 128;  // > any tree height: 63 code-bit levels + 32 posit
 // registers instead of reloading them from scratch on every push and pop.
 template <typename E>
 struct ShortStack {
-    E *lds;  // this thread's column: entry j at lds[j * stride]
+    E *lds;  // this thread's column: entry j at lds[j << shift] (the stride is the block size, a power of two)
     E *spill;
-    int stride, mask;
+    int shift, mask;
     int base = 0, cnt = 0, ns = 0;
-    __device__ ShortStack(E *col, int stride_, int cap, E *spill_) : lds(col), spill(spill_), stride(stride_),
-                                                                      mask(cap - 1) {}
+    __device__ ShortStack(E *col, int stride, int cap, E *spill_) : lds(col), spill(spill_), shift(__ffs(stride) - 1),
+                                                                     mask(cap - 1) {}
     __device__ __forceinline__ bool empty() const { return cnt == 0 && ns == 0; }
     __device__ __forceinline__ void push(E x)
     {
         if (cnt == mask + 1) {  // ring full: move the oldest LDS entry to the spill area
             if (ns < kSpill)
-                spill[ns++] = lds[(base & mask) * stride];
+                spill[ns++] = lds[(base & mask) << shift];
             ++base;
             --cnt;
         }
-        lds[((base + cnt) & mask) * stride] = x;
+        lds[((base + cnt) & mask) << shift] = x;
         ++cnt;
     }
     // The newest spilled entry sits just below the ring's oldest one: when the
@@ -42,11 +42,11 @@ struct ShortStack {
     {
         if (cnt == 0) {
             --base;
-            lds[(base & mask) * stride] = spill[--ns];
+            lds[(base & mask) << shift] = spill[--ns];
             cnt = 1;
         }
         --cnt;
-        return lds[((base + cnt) & mask) * stride];
+        return lds[((base + cnt) & mask) << shift];
     }
 };
 

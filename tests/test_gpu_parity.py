@@ -384,6 +384,30 @@ def test_stream_argument():
     assert np.array_equal(host(ix), o_ix)
 
 
+def test_destroy_with_queries_in_flight():
+    # destroying a tree orders the release of its memory after the work already
+    # queued on every stream that used it; a new build may then reuse the memory
+    cfg = inputs.config_small(n=50_000, m=20_000)
+    other = np.random.default_rng(9).random((50_000, 3)).astype(np.float32)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        d, q = dev(cfg["data"]), dev(cfg["queries"])
+        t = ax.arborx_bvh_build(d, stream=side)
+        c, s = ax.arborx_query_spatial_reduce(t, q, cfg["radius"], ax.COUNT_SUMDIST, stream=side)
+        d2, ix = ax.arborx_query_knn(t, q, 8, stream=side)
+    ax.arborx_bvh_destroy(t)
+    t2 = ax.arborx_bvh_build(dev(other))
+    c2, _ = ax.arborx_query_spatial_reduce(t2, dev(cfg["queries"]), cfg["radius"], ax.COUNT)
+    side.synchronize()
+    torch.cuda.synchronize()
+    oc, os_ = oracle.reduce(cfg["data"], cfg["queries"], cfg["radius"])
+    assert np.array_equal(host(c), oc) and np.array_equal(host(s), os_)
+    o_d2, o_ix = oracle.knn(cfg["data"], cfg["queries"], 8)
+    assert np.array_equal(host(ix), o_ix) and np.array_equal(host(d2), o_d2)
+    oc2, _ = oracle.reduce(other, cfg["queries"], cfg["radius"])
+    assert np.array_equal(host(c2), oc2)
+
+
 def test_plan_api_two_calls():
     import ctypes
     from paper_2507_23700_amd import _lib
