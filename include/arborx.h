@@ -65,7 +65,8 @@ typedef enum { ARBORX_COUNT = 0, ARBORX_COUNT_SUMDIST = 1 } arborx_reducer;
 /* Traversal schedule knobs; every schedule returns identical results. */
 typedef struct arborx_tuning {
     int32_t block;        /* threads per workgroup for traversal kernels: 64, 128, 256 (0 = default) */
-    int32_t order;        /* 1 = sort queries along the Morton curve before traversal, 0 = input order */
+    int32_t order;        /* sort queries along the Morton curve before traversal: 1 = on a 24-bit grid (three
+                             sort passes), 2 = on a 16-bit grid (two passes); 0 = input order */
     int32_t stack;        /* LDS short-stack entries per thread: 4..64 (0 = default); deeper trees spill */
     int32_t schedule;     /* 0 = thread per query with a short stack; 1 = wavefront packet (64 queries share
                              node fetches); 2 = thread per query, stackless with ropes (radius / intersects

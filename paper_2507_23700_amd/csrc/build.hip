@@ -126,18 +126,47 @@ __global__ __launch_bounds__(kBuildBlock) void bounds_partial(const float *__res
 }
 
 template <int D>
-__global__ void bounds_final(const float *__restrict__ partial, int blocks, int64_t n, TreeHeader *hdr)
+__global__ __launch_bounds__(kBuildBlock) void bounds_final(const float *__restrict__ partial, int blocks, int64_t n,
+                                                             TreeHeader *hdr)
 {
+    __shared__ float s_lo[kBuildBlock / kWave][D];
+    __shared__ float s_hi[kBuildBlock / kWave][D];
+    float a[D], b[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        a[d] = INFINITY;
+        b[d] = -INFINITY;
+    }
+    for (int k = threadIdx.x; k < blocks; k += kBuildBlock)
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            a[d] = fminf(a[d], partial[(int64_t)k * 2 * D + d]);
+            b[d] = fmaxf(b[d], partial[(int64_t)k * 2 * D + D + d]);
+        }
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            a[d] = fminf(a[d], __shfl_xor(a[d], o, kWave));
+            b[d] = fmaxf(b[d], __shfl_xor(b[d], o, kWave));
+        }
+    if (lane_id() == 0)
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            s_lo[wave_id()][d] = a[d];
+            s_hi[wave_id()][d] = b[d];
+        }
+    __syncthreads();
     const int d = threadIdx.x;
     if (d < D) {
-        float a = INFINITY, b = -INFINITY;
-        for (int k = 0; k < blocks; ++k) {
-            a = fminf(a, partial[(int64_t)k * 2 * D + d]);
-            b = fmaxf(b, partial[(int64_t)k * 2 * D + D + d]);
+        float lo = INFINITY, hi = -INFINITY;
+        for (int w = 0; w < kBuildBlock / kWave; ++w) {
+            lo = fminf(lo, s_lo[w][d]);
+            hi = fmaxf(hi, s_hi[w][d]);
         }
-        hdr->lo[d] = a;
-        hdr->hi[d] = b;
-        hdr->qscale[d] = quant_scale(a, b);
+        hdr->lo[d] = lo;
+        hdr->hi[d] = hi;
+        hdr->qscale[d] = quant_scale(lo, hi);
     }
     if (d == 0) {
         hdr->n = (int32_t)n;
@@ -699,7 +728,7 @@ arborx_status build_impl(const float *values, int64_t n, int kind, TreeDev &t, h
     {
         ProfScope ps("build_bounds", s);
         bounds_partial<D><<<pblocks, kBuildBlock, 0, s>>>(values, n, kind, partial);
-        bounds_final<D><<<1, 64, 0, s>>>(partial, pblocks, n, t.hdr);
+        bounds_final<D><<<1, kBuildBlock, 0, s>>>(partial, pblocks, n, t.hdr);
     }
     const float *blo = reinterpret_cast<const float *>(reinterpret_cast<const char *>(t.hdr) + offsetof(TreeHeader, lo));
     const float *bhi = reinterpret_cast<const float *>(reinterpret_cast<const char *>(t.hdr) + offsetof(TreeHeader, hi));

@@ -264,8 +264,8 @@ static arborx_status to_tuning(const arborx_tuning *t, const Tuning &base, Tunin
             return fail(ARBORX_E_INVALID, "block must be 64, 128 or 256");
         n.block = t->block;
     }
-    if (t->order != 0 && t->order != 1)
-        return fail(ARBORX_E_INVALID, "order must be 0 or 1");
+    if (t->order < 0 || t->order > 2)
+        return fail(ARBORX_E_INVALID, "order must be 0 (none), 1 (24-bit Morton) or 2 (16-bit Morton)");
     n.order = t->order;
     if (t->stack) {
         if (t->stack < 1 || t->stack > 64 || (t->stack & (t->stack - 1)))

@@ -309,16 +309,15 @@ __global__ void k_knn_empty(int64_t total, float *d2, int32_t *idx)
     }
 }
 
-// Morton codes of query centres on a coarse grid (kOrderBits bits in all),
-// normalised by the tree's bounds.  The order only affects speed: queries in
-// one cell of the grid are treated alike.
-constexpr int kOrderBits = 24;
+// Morton codes of query centres on a coarse grid (order_bits bits in all:
+// 24, or 16 for a two-pass sort), normalised by the tree's bounds.  The order
+// only affects speed: queries in one cell of the grid are treated alike.
+inline int order_bits(int order) { return order == 2 ? 16 : 24; }
 
 template <int D, bool BOXQ>
 __global__ void k_query_codes(const float *__restrict__ q, int64_t m, const TreeHeader *__restrict__ hdr,
-                              uint32_t *__restrict__ codes, uint32_t *__restrict__ ids)
+                              uint32_t *__restrict__ codes, uint32_t *__restrict__ ids, int bits)
 {
-    constexpr int bits = kOrderBits / D;
     float lo[D], inv[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -524,9 +523,10 @@ arborx_status knn_impl(const TreeDev &t, const float *q, int64_t m, int k, const
 }
 
 template <int D>
-arborx_status order_impl(const TreeDev &t, const float *q, int64_t m, Pred pred, uint32_t **perm, Temps &tmp,
-                         hipStream_t s)
+arborx_status order_impl(const TreeDev &t, const float *q, int64_t m, Pred pred, int order, uint32_t **perm,
+                         Temps &tmp, hipStream_t s)
 {
+    const int bits = order_bits(order) / D;
     uint32_t *codes, *codes2, *ids, *ids2;
     uint8_t *ws;
     arborx_status st;
@@ -536,11 +536,11 @@ arborx_status order_impl(const TreeDev &t, const float *q, int64_t m, Pred pred,
         return st;
     ProfScope ps("order", s);
     if (pred == Pred::Sphere)
-        k_query_codes<D, false><<<grid_for(m, 256, 65536), 256, 0, s>>>(q, m, t.hdr, codes, ids);
+        k_query_codes<D, false><<<grid_for(m, 256, 65536), 256, 0, s>>>(q, m, t.hdr, codes, ids, bits);
     else
-        k_query_codes<D, true><<<grid_for(m, 256, 65536), 256, 0, s>>>(q, m, t.hdr, codes, ids);
+        k_query_codes<D, true><<<grid_for(m, 256, 65536), 256, 0, s>>>(q, m, t.hdr, codes, ids, bits);
     bool alt = false;
-    AX_HIP(radix_sort_pairs<uint32_t>(codes, ids, codes2, ids2, m, 0, (kOrderBits / D) * D, ws, s, &alt));
+    AX_HIP(radix_sort_pairs<uint32_t>(codes, ids, codes2, ids2, m, 0, bits * D, ws, s, &alt));
     *perm = alt ? ids2 : ids;
     return ARBORX_OK;
 }
@@ -561,7 +561,7 @@ arborx_status query_order(const TreeDev &t, const float *queries, int64_t m, Pre
     *perm = nullptr;
     if (!tuning(op).order || t.n == 0 || m <= 1)
         return ARBORX_OK;
-    AX_DISPATCH_DIM(t.dim, (order_impl<D>(t, queries, m, pred, perm, tmp, s)));
+    AX_DISPATCH_DIM(t.dim, (order_impl<D>(t, queries, m, pred, tuning(op).order, perm, tmp, s)));
 }
 
 arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,

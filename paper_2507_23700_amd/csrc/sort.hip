@@ -1,9 +1,10 @@
 // Stable LSD radix sort of (key, uint32 value) pairs, 8-bit digits.
 //
-// One pass = three launches:
+// One pass = four launches:
 //   hist    : per 4096-key tile, a 256-bin digit histogram (LDS atomics),
 //             stored digit-major so that one scan over [digit][tile] yields
 //             every tile's global output offset per digit;
+//   totals  : one workgroup per digit sums its row of tile counts;
 //   scan    : one workgroup per digit scans its row of tile counts and adds
 //             the number of keys with smaller digits;
 //   scatter : per tile, keys are ranked stably inside each wavefront with
@@ -29,7 +30,7 @@ static_assert(kSortBlock == kRadix, "one thread per digit in the per-tile steps"
 template <typename K>
 __global__ __launch_bounds__(kSortBlock) void radix_hist(const K *__restrict__ keys, int64_t n, int shift,
                                                          uint32_t mask, uint32_t *__restrict__ tile_hist,
-                                                         uint32_t *__restrict__ digit_total, int num_tiles)
+                                                         int num_tiles)
 {
     __shared__ uint32_t h[kRadix];
     h[threadIdx.x] = 0;
@@ -42,10 +43,28 @@ __global__ __launch_bounds__(kSortBlock) void radix_hist(const K *__restrict__ k
             atomicAdd(&h[(uint32_t)(keys[i] >> shift) & mask], 1u);
     }
     __syncthreads();
-    uint32_t c = h[threadIdx.x];
-    tile_hist[(int64_t)threadIdx.x * num_tiles + blockIdx.x] = c;
-    if (c)
-        atomicAdd(&digit_total[threadIdx.x], c);
+    tile_hist[(int64_t)threadIdx.x * num_tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// digit_total[d] = sum over tiles of tile_hist[d][t]: one workgroup per digit.
+__global__ __launch_bounds__(kSortBlock) void radix_totals(const uint32_t *__restrict__ tile_hist, int num_tiles,
+                                                           uint32_t *__restrict__ digit_total)
+{
+    __shared__ uint32_t wsum[kSortBlock / kWave];
+    const uint32_t *row = tile_hist + (int64_t)blockIdx.x * num_tiles;
+    uint32_t s = 0;
+    for (int i = threadIdx.x; i < num_tiles; i += kSortBlock)
+        s += row[i];
+    s = wave_sum(s);
+    if (lane_id() == 0)
+        wsum[wave_id()] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kSortBlock / kWave; ++w)
+            t += wsum[w];
+        digit_total[blockIdx.x] = t;
+    }
 }
 
 // In place: tile_hist[d][t] <- (keys with digit < d) + sum_{t' < t} tile_hist[d][t'].
@@ -198,14 +217,14 @@ hipError_t radix_sort_pairs(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals
     const int passes = (end - begin + kRadixBits - 1) / kRadixBits;
     if (passes > 8)
         return hipErrorInvalidValue;
-    fill_kernel<uint32_t><<<grid_for((int64_t)passes * kRadix, 256), 256, 0, s>>>(totals, (int64_t)passes * kRadix, 0u);
     K *kin = keys, *kout = keys_alt;
     uint32_t *vin = vals, *vout = vals_alt;
     for (int p = 0; p < passes; ++p) {
         const int shift = begin + p * kRadixBits;
         const int bits = (end - shift) < kRadixBits ? (end - shift) : kRadixBits;
         const uint32_t mask = (1u << bits) - 1u;
-        radix_hist<K><<<tiles, kSortBlock, 0, s>>>(kin, n, shift, mask, tile_hist, totals + p * kRadix, tiles);
+        radix_hist<K><<<tiles, kSortBlock, 0, s>>>(kin, n, shift, mask, tile_hist, tiles);
+        radix_totals<<<kRadix, kSortBlock, 0, s>>>(tile_hist, tiles, totals + p * kRadix);
         radix_scan<<<kRadix, kSortBlock, 0, s>>>(tile_hist, totals + p * kRadix, tiles);
         radix_scatter<K><<<tiles, kSortBlock, 0, s>>>(kin, vin, kout, vout, n, shift, mask, tile_hist, tiles);
         K *tk = kin;

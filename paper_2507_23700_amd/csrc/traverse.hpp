@@ -377,18 +377,26 @@ struct TopK {
     }
     // distance of the K-th best: a box farther than this cannot contribute
     __device__ __forceinline__ float bound() const { return __uint_as_float((uint32_t)(key[K - 1] >> 32)); }
+    // Insertion from the back: the new key displaces the last slot and moves
+    // left past larger keys.  A candidate that gets in usually ranks near the
+    // end, so the walk stops as soon as no lane of the wavefront still moves.
     __device__ __forceinline__ void offer(float d, int id)
     {
-        uint64_t v = pack(d, id);
-        if (!(v < key[K - 1]))
+        const uint64_t v = pack(d, id);
+        bool moving = v < key[K - 1];
+        if (!moving)
             return;
 #pragma unroll
-        for (int s = 0; s < K; ++s) {
-            const uint64_t a = key[s];
-            const bool lt = v < a;
-            key[s] = lt ? v : a;
-            v = lt ? a : v;
+        for (int s = K - 1; s > 0; --s) {
+            const uint64_t prev = key[s - 1];
+            const bool shift = moving && v < prev;
+            key[s] = shift ? prev : (moving ? v : key[s]);
+            moving = shift;
+            if (__ballot(moving) == 0)
+                return;
         }
+        if (moving)
+            key[0] = v;
     }
     // Write the first k_out, indices relative to `base`; empty slots become (+inf, -1).
     __device__ __forceinline__ void store(int k_out, float *d2, int32_t *idx, int base) const
