@@ -165,12 +165,14 @@ def cpu_baseline(data, queries, radius, k, target_s=15.0, max_sample=20000):
     import oracle
     oracle.lib()
 
+    dim = data.shape[1]
+
     def run(sq):
         t0 = time.perf_counter()
-        off, idx = oracle.spatial(data, sq, radius)
-        c, _ = oracle.reduce(data, sq, radius, op=oracle.COUNT)
-        c2, s2 = oracle.reduce(data, sq, radius, op=oracle.COUNT_SUMDIST)
-        d2, ix = oracle.knn(data, sq, k)
+        off, idx = oracle.spatial(data, sq, radius, dim=dim)
+        c, _ = oracle.reduce(data, sq, radius, dim=dim, op=oracle.COUNT)
+        c2, s2 = oracle.reduce(data, sq, radius, dim=dim, op=oracle.COUNT_SUMDIST)
+        d2, ix = oracle.knn(data, sq, k, dim=dim)
         return time.perf_counter() - t0, (off, idx, c, c2, s2, d2, ix)
 
     g = np.random.default_rng(12345)
@@ -288,9 +290,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=10_000_000)
-    ap.add_argument("--dist", default="cube", choices=["cube", "shell"])
-    ap.add_argument("--k", type=int, default=16)
+    ap.add_argument("--n", type=int, default=None, help="points (= queries); default per workload")
+    ap.add_argument("--dist", default="cube", choices=["cube", "shell", "gmm6", "small"],
+                    help="cube / shell: 10^7 3D points; gmm6: 2*10^6 6D Gaussian mixture; small: 2*10^4 3D cube")
+    ap.add_argument("--k", type=int, default=None, help="kNN k; default per workload (16, 8 for gmm6, 10 for small)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-forest", action="store_true", help="skip the batched-vs-plain forest comparison")
     ap.add_argument("--no-chamfer", action="store_true", help="skip the Chamfer timing")
@@ -300,7 +303,9 @@ def main():
                     help="turn rocprofv3 counter CSVs into profiles/traffic.json and print a markdown table")
     args = ap.parse_args()
     if args.summarize_counters:
-        print(summarize_counters(*args.summarize_counters, workload=f"{args.dist}3d_n{args.n}_m{args.n}",
+        n0 = args.n or {"gmm6": 2_000_000, "small": 20_000}.get(args.dist, 10_000_000)
+        wl = f"gmm6d_n{n0}_m{n0}" if args.dist == "gmm6" else f"{'cube' if args.dist == 'small' else args.dist}3d_n{n0}_m{n0}"
+        print(summarize_counters(*args.summarize_counters, workload=wl,
                                  copy_bytes=2 ** 30))
         return
     if args.calibrate_copy > 0:
@@ -328,10 +333,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     L = _lib.lib()
-    log(f"generating {args.dist} workload n=m={args.n}")
-    cfg = inputs.config_paper(args.dist, n=args.n)
-    data, queries, radius, k = cfg["data"], cfg["queries"], float(cfg["radius"]), args.k
-    n = m = args.n
+    log(f"generating {args.dist} workload")
+    if args.dist == "gmm6":
+        cfg = inputs.config_gmm6(n=args.n or 2_000_000)
+    elif args.dist == "small":
+        cfg = inputs.config_small(n=args.n or 20_000, m=args.n or 20_000)
+    else:
+        cfg = inputs.config_paper(args.dist, n=args.n or 10_000_000)
+    data, queries, radius = cfg["data"], cfg["queries"], float(cfg["radius"])
+    k = args.k or cfg["k"]
+    n, m, dim = len(data), len(queries), data.shape[1]
     d = torch.from_numpy(data).cuda()
     q = torch.from_numpy(queries).cuda()
     torch.cuda.synchronize()
@@ -389,9 +400,9 @@ def main():
     }
 
     # dominant kernel by GPU time in the timed region
-    dom = max((kn for kn in prof if algorithmic_bytes(kn, n, m, 3, k, total)), key=lambda kn: prof[kn][0])
+    dom = max((kn for kn in prof if algorithmic_bytes(kn, n, m, dim, k, total)), key=lambda kn: prof[kn][0])
     avg_ms = prof[dom][0] / prof[dom][1]
-    alg = algorithmic_bytes(dom, n, m, 3, k, total)
+    alg = algorithmic_bytes(dom, n, m, dim, k, total)
     achieved = alg / (avg_ms * 1e-3) / 1e9
     roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom, cfg["workload"]),
@@ -423,9 +434,9 @@ def main():
         "value": value, "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic (seeded numpy generators)",
-        "config": {"workload": cfg["workload"], "n": n, "m": m, "dim": 3, "distribution": args.dist,
+        "config": {"workload": cfg["workload"], "n": n, "m": m, "dim": dim, "distribution": args.dist,
                    "radius": radius, "k": k,
-                   "step": "build + radius CSR + COUNT + COUNT_SUMDIST + kNN; value counts 4*M queries per step"},
+                   "step": f"build + radius CSR + COUNT + COUNT_SUMDIST + kNN k={k}; value counts 4*M queries per step"},
         "components": comps, "roofline": roofline, "cpu_baseline": cpu, "parity": parity,
         "batched_vs_plain": forest, "chamfer": chamfer,
     }

@@ -82,7 +82,7 @@ struct arborx_plan_s {
     hipStream_t stream;
     ax::Temps tmp;
     uint32_t *perm = nullptr;
-    int32_t *counts = nullptr, *stash = nullptr, *big_list = nullptr, *huge_list = nullptr;
+    int32_t *counts = nullptr, *ordered_counts = nullptr, *stash = nullptr, *big_list = nullptr, *huge_list = nullptr;
     ax::QueryHeader h{};
     arborx_plan_s(hipStream_t s) : tmp(s) {}
 };
@@ -458,17 +458,20 @@ static arborx_status csr_begin(arborx_tree t, Pred pred, const float *queries, i
     uint8_t *sws;
     const int64_t mm = m > 0 ? m : 1;
     if ((st = p->tmp.get(&qh, 1)) != ARBORX_OK || (st = p->tmp.get(&p->counts, mm)) != ARBORX_OK ||
+        (st = p->tmp.get(&p->ordered_counts, mm)) != ARBORX_OK ||
         (st = p->tmp.get(&p->stash, mm * kRowSortRegs)) != ARBORX_OK ||
         (st = p->tmp.get(&p->big_list, mm)) != ARBORX_OK || (st = p->tmp.get(&p->huge_list, mm)) != ARBORX_OK ||
         (st = p->tmp.get(&sws, scan_workspace_bytes(m))) != ARBORX_OK)
         return bail(st);
     if ((st = query_order(t->dev, queries, m, pred, OP_SPATIAL, &p->perm, p->tmp, s)) != ARBORX_OK)
         return bail(st);
-    if ((st = spatial_count(t->dev, pred, queries, m, radius, p->perm, p->counts, p->stash, s)) != ARBORX_OK)
+    if ((st = spatial_count(t->dev, pred, queries, m, radius, p->perm, p->counts, p->ordered_counts, p->stash, s)) !=
+        ARBORX_OK)
         return bail(st);
     {
         ProfScope ps("scan", s);
-        hipError_t e = csr_offsets_lists(p->counts, m, offsets, p->big_list, p->huge_list, qh, sws, s);
+        hipError_t e = csr_offsets_lists(p->counts, p->ordered_counts, p->perm, m, offsets, p->big_list, p->huge_list,
+                                         qh, sws, s);
         if (e != hipSuccess)
             return bail(hip_fail(e, "csr_offsets_lists"));
     }

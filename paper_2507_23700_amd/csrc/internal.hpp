@@ -119,11 +119,15 @@ size_t scan_workspace_bytes(int64_t n);
 // offsets[0..m] = exclusive scan of counts; also writes offsets[m] to *total_dev.
 hipError_t csr_offsets(const int32_t *counts, int64_t m, int64_t *offsets, int64_t *total_dev, void *workspace,
                        hipStream_t s);
-// As csr_offsets, and also lists (in row order) the rows longer than
-// kRowSortRegs (big_list, up to kRowSortBlock) and longer than kRowSortBlock
-// (huge_list); totals go to *qh.  Lists need room for m entries.
-hipError_t csr_offsets_lists(const int32_t *counts, int64_t m, int64_t *offsets, int32_t *big_list,
-                             int32_t *huge_list, QueryHeader *qh, void *workspace, hipStream_t s);
+// As csr_offsets, and also lists the rows longer than kRowSortRegs (big_list,
+// up to kRowSortBlock) and longer than kRowSortBlock (huge_list); totals go to
+// *qh.  With `order` (position -> row, e.g. the traversal order of the
+// queries) and ordered_counts[i] = counts[order[i]], the lists follow that
+// order, so a second walk over them stays coherent; else row order.  Lists
+// need room for m entries.
+hipError_t csr_offsets_lists(const int32_t *counts, const int32_t *ordered_counts, const uint32_t *order, int64_t m,
+                             int64_t *offsets, int32_t *big_list, int32_t *huge_list, QueryHeader *qh,
+                             void *workspace, hipStream_t s);
 
 // ---- build (build.hip) ----------------------------------------------------
 struct TreeDev {
@@ -178,9 +182,10 @@ enum class Pred { Sphere, Box };
 arborx_status query_order(const TreeDev &t, const float *queries, int64_t m, Pred pred, int op, uint32_t **perm,
                           Temps &tmp, hipStream_t s);
 // Count pass; also stores each query's first kRowSortRegs matches, sorted, in
-// stash[query][kRowSortRegs].
+// stash[query][kRowSortRegs], and (with perm) ordered_counts[t] = counts[perm[t]].
 arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
-                            const uint32_t *perm, int32_t *counts, int32_t *stash, hipStream_t s);
+                            const uint32_t *perm, int32_t *counts, int32_t *ordered_counts, int32_t *stash,
+                            hipStream_t s);
 // Fill pass: stash rows are copied; listed longer rows are walked again.
 arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
                            const uint32_t *perm, const int32_t *counts, const int32_t *stash,

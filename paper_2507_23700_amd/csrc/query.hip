@@ -25,16 +25,17 @@ namespace {
 __device__ __forceinline__ int node_count(const TreeHeader *hdr) { return hdr->n > 1 ? hdr->n - 1 : 1; }
 
 // Count pass of a CSR query.  With a stash, each query also keeps its first
-// kRowSortRegs matches sorted in registers and stores them in the stash row of
-// its input position (one aligned 64-byte segment per thread), so that the
-// copy into the CSR array later streams rows, counts and offsets in input
-// order; rows that fit need no second walk.
+// kRowSortRegs matches in registers, in the order found, and stores them in
+// the stash row of its input position (one aligned 64-byte segment per
+// thread), so that the copy into the CSR array later streams rows, counts and
+// offsets in input order and sorts each row there; rows that fit need no
+// second walk.
 template <int D, class P, bool STASH, int SCHED>
 __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
                                 const float *__restrict__ leaves, int kind, const TreeHeader *__restrict__ hdr,
                                 const float *__restrict__ queries, int64_t m, float r2,
                                 const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
-                                int32_t *__restrict__ stash, int stack_cap)
+                                int32_t *__restrict__ ordered_counts, int32_t *__restrict__ stash, int stack_cap)
 {
     extern __shared__ int s_stack[];
     const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
@@ -59,7 +60,7 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D
         buf[k] = 0;
     auto f = [&](int idx, float) {
         if (STASH && c < kRowSortRegs)
-            insert_sorted<kRowSortRegs>(buf, c, idx);
+            append_at<kRowSortRegs>(buf, c, idx);
         ++c;
     };
     if (SCHED == 1)
@@ -79,9 +80,12 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D
             row[k] = make_int4(buf[4 * k], buf[4 * k + 1], buf[4 * k + 2], buf[4 * k + 3]);
     }
     counts[qi] = c;
+    if (ordered_counts)
+        ordered_counts[t] = c;
 }
 
-// Rows of at most kRowSortRegs matches: copy the sorted stash row to the CSR
+// Rows of at most kRowSortRegs matches: sort the stash row in registers (a
+// bitonic network, empty slots padded to sort last) and copy it to the CSR
 // slot.  Thread i handles query i, so consecutive lanes fill adjacent rows.
 __global__ void k_copy_stash(const int32_t *__restrict__ stash, int64_t m, const int32_t *__restrict__ counts,
                              const int64_t *__restrict__ offsets, int32_t *__restrict__ indices)
@@ -103,6 +107,10 @@ __global__ void k_copy_stash(const int32_t *__restrict__ stash, int64_t m, const
         v[4 * k + 2] = x.z;
         v[4 * k + 3] = x.w;
     }
+#pragma unroll
+    for (int k = 0; k < kRowSortRegs; ++k)
+        v[k] = k < c ? v[k] : INT32_MAX;
+    sort_network<kRowSortRegs>(v);
 #pragma unroll
     for (int k = 0; k < kRowSortRegs; ++k)
         if (k < c)
@@ -143,7 +151,36 @@ __global__ void k_spatial_fill_rows(const Node<D> *__restrict__ nodes, const QNo
         traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
 }
 
-// One workgroup per listed row of at most kRowSortBlock entries: bitonic sort in LDS.
+// Listed rows of at most one wavefront (kWave entries): one wavefront per row,
+// a bitonic network across the lanes with shuffles, padding sorting last.
+__global__ __launch_bounds__(256) void k_sort_rows_wave(const int64_t *__restrict__ offsets,
+                                                        int32_t *__restrict__ indices,
+                                                        const int32_t *__restrict__ list, int64_t nb)
+{
+    const int lane = lane_id();
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); b < nb; b += waves) {
+        const int64_t row = list[b];
+        const int64_t o = offsets[row];
+        const int64_t len = offsets[row + 1] - o;
+        if (len > kWave)
+            continue;
+        int v = lane < len ? indices[o + lane] : INT32_MAX;
+#pragma unroll
+        for (int k = 2; k <= kWave; k <<= 1)
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const int other = __shfl_xor(v, j, kWave);
+                const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+                v = keep_min ? min(v, other) : max(v, other);
+            }
+        if (lane < len)
+            indices[o + lane] = v;
+    }
+}
+
+// One workgroup per listed row of kWave < len <= kRowSortBlock entries:
+// bitonic sort in LDS.
 __global__ __launch_bounds__(256) void k_sort_rows(const int64_t *__restrict__ offsets, int32_t *__restrict__ indices,
                                                    const int32_t *__restrict__ list, int64_t nb)
 {
@@ -152,7 +189,7 @@ __global__ __launch_bounds__(256) void k_sort_rows(const int64_t *__restrict__ o
         const int64_t row = list[b];
         const int64_t o = offsets[row];
         const int64_t len64 = offsets[row + 1] - o;
-        if (len64 > kRowSortBlock)
+        if (len64 <= kWave || len64 > kRowSortBlock)
             continue;
         const int len = (int)len64;
         int p2 = 1;
@@ -376,7 +413,7 @@ int effective_schedule(int op)
 
 template <int D>
 arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m, float r2, const uint32_t *perm,
-                         int32_t *counts, int32_t *stash, hipStream_t s)
+                         int32_t *counts, int32_t *ordered_counts, int32_t *stash, hipStream_t s)
 {
     const int sched = effective_schedule(OP_SPATIAL);
     const Launch L = traversal_launch(m, sizeof(int), OP_SPATIAL, sched == 1);
@@ -385,7 +422,8 @@ arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m,
     ProfScope ps("spatial_count", s);
 #define AX_COUNT(P, S)                                                                                     \
     k_spatial_count<D, P, true, S><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, t.leaves, t.kind, t.hdr, q, m, r2, \
-                                                                  perm, counts, stash, L.cap)
+                                                                  perm, counts, perm ? ordered_counts : nullptr,  \
+                                                                  stash, L.cap)
     if (pred == Pred::Sphere) {
         if (sched == 1)
             AX_COUNT(Sphere<D>, 1);
@@ -565,7 +603,8 @@ arborx_status query_order(const TreeDev &t, const float *queries, int64_t m, Pre
 }
 
 arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
-                            const uint32_t *perm, int32_t *counts, int32_t *stash, hipStream_t s)
+                            const uint32_t *perm, int32_t *counts, int32_t *ordered_counts, int32_t *stash,
+                            hipStream_t s)
 {
     if (m == 0)
         return ARBORX_OK;
@@ -575,7 +614,7 @@ arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, i
     if (st != ARBORX_OK)
         return st;
     const float r2 = radius * radius;
-    AX_DISPATCH_DIM(t.dim, (count_impl<D>(t, pred, queries, m, r2, perm, counts, stash, s)));
+    AX_DISPATCH_DIM(t.dim, (count_impl<D>(t, pred, queries, m, r2, perm, counts, ordered_counts, stash, s)));
 }
 
 arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
@@ -618,6 +657,7 @@ arborx_status sort_big_rows(const int64_t *offsets, int32_t *indices, const int3
     if (nbig <= 0)
         return ARBORX_OK;
     ProfScope ps("sort_rows", s);
+    k_sort_rows_wave<<<(unsigned)grid_for(nbig, 256 / kWave, 16384), 256, 0, s>>>(offsets, indices, big_list, nbig);
     k_sort_rows<<<(unsigned)(nbig < 8192 ? nbig : 8192), 256, 0, s>>>(offsets, indices, big_list, nbig);
     AX_HIP(hipGetLastError());
     return ARBORX_OK;

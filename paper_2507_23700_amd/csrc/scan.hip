@@ -84,7 +84,10 @@ __device__ __forceinline__ int64_t row_flags(int32_t c)
     return (c > kRowSortRegs && c <= kRowSortBlock) ? 1ll : (c > kRowSortBlock ? (1ll << 32) : 0ll);
 }
 
-__global__ __launch_bounds__(kScanBlock) void csr_tile_sums(const int32_t *__restrict__ counts, int64_t m,
+// counts[i] is row i's length; lcounts[i] is the length of the row listed at
+// position i (the same array, or the lengths in traversal order).
+__global__ __launch_bounds__(kScanBlock) void csr_tile_sums(const int32_t *__restrict__ counts,
+                                                            const int32_t *__restrict__ lcounts, int64_t m,
                                                             int64_t *__restrict__ tile_sums,
                                                             int64_t *__restrict__ tile_flags)
 {
@@ -95,9 +98,8 @@ __global__ __launch_bounds__(kScanBlock) void csr_tile_sums(const int32_t *__res
     for (int j = 0; j < kScanItems; ++j) {
         const int64_t i = base + (int64_t)j * kScanBlock + threadIdx.x;
         if (i < m) {
-            const int32_t c = counts[i];
-            s += c;
-            f += row_flags(c);
+            s += counts[i];
+            f += row_flags(lcounts[i]);
         }
     }
     int64_t tot = 0, ftot = 0;
@@ -136,7 +138,11 @@ __global__ __launch_bounds__(kScanBlock) void csr_tile_prefix(int64_t *__restric
     }
 }
 
-__global__ __launch_bounds__(kScanBlock) void csr_apply(const int32_t *__restrict__ counts, int64_t m,
+// Offsets in row order; long rows listed in the order of lcounts, as order[i]
+// (the row at position i) or i when order is NULL.
+__global__ __launch_bounds__(kScanBlock) void csr_apply(const int32_t *__restrict__ counts,
+                                                        const int32_t *__restrict__ lcounts,
+                                                        const uint32_t *__restrict__ order, int64_t m,
                                                         const int64_t *__restrict__ tile_prefix,
                                                         const int64_t *__restrict__ tile_flags,
                                                         int64_t *__restrict__ offsets, int32_t *__restrict__ big_list,
@@ -144,13 +150,27 @@ __global__ __launch_bounds__(kScanBlock) void csr_apply(const int32_t *__restric
 {
     __shared__ int64_t wsum[kScanBlock / kWave];
     const int64_t i0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    int32_t c[kScanItems];
+    int32_t c[kScanItems], lc[kScanItems];
+    if (i0 + kScanItems <= m) {  // whole chunk: 16-byte loads (i0 is a multiple of kScanItems)
+#pragma unroll
+        for (int j = 0; j < kScanItems; j += 4) {
+            const int4 a = *reinterpret_cast<const int4 *>(counts + i0 + j);
+            const int4 b = *reinterpret_cast<const int4 *>(lcounts + i0 + j);
+            c[j] = a.x, c[j + 1] = a.y, c[j + 2] = a.z, c[j + 3] = a.w;
+            lc[j] = b.x, lc[j + 1] = b.y, lc[j + 2] = b.z, lc[j + 3] = b.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) {
+            c[j] = (i0 + j < m) ? counts[i0 + j] : 0;
+            lc[j] = (i0 + j < m) ? lcounts[i0 + j] : 0;
+        }
+    }
     int64_t s = 0, f = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
-        c[j] = (i0 + j < m) ? counts[i0 + j] : 0;
         s += c[j];
-        f += row_flags(c[j]);
+        f += row_flags(lc[j]);
     }
     int64_t tot = 0, ftot = 0;
     int64_t run = tile_prefix[blockIdx.x] + block_exclusive_scan<kScanBlock>(s, wsum, &tot);
@@ -160,11 +180,14 @@ __global__ __launch_bounds__(kScanBlock) void csr_apply(const int32_t *__restric
         const int64_t i = i0 + j;
         if (i < m) {
             offsets[i] = run;
-            const int64_t fl = row_flags(c[j]);
-            if (fl == 1)
-                big_list[frun & 0xffffffffll] = (int32_t)i;
-            else if (fl != 0)
-                huge_list[frun >> 32] = (int32_t)i;
+            const int64_t fl = row_flags(lc[j]);
+            if (fl != 0) {
+                const int32_t row = order ? (int32_t)order[i] : (int32_t)i;
+                if (fl == 1)
+                    big_list[frun & 0xffffffffll] = row;
+                else
+                    huge_list[frun >> 32] = row;
+            }
             frun += fl;
         }
         run += c[j];
@@ -191,8 +214,9 @@ __global__ void scan_empty(int64_t *offsets, int64_t *total)
 
 size_t scan_workspace_bytes(int64_t m) { return (size_t)2 * ((m + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t); }
 
-hipError_t csr_offsets_lists(const int32_t *counts, int64_t m, int64_t *offsets, int32_t *big_list,
-                             int32_t *huge_list, QueryHeader *qh, void *workspace, hipStream_t s)
+hipError_t csr_offsets_lists(const int32_t *counts, const int32_t *ordered_counts, const uint32_t *order, int64_t m,
+                             int64_t *offsets, int32_t *big_list, int32_t *huge_list, QueryHeader *qh,
+                             void *workspace, hipStream_t s)
 {
     if (m == 0) {
         csr_empty<<<1, 1, 0, s>>>(offsets, qh);
@@ -201,9 +225,11 @@ hipError_t csr_offsets_lists(const int32_t *counts, int64_t m, int64_t *offsets,
     const int64_t tiles = (m + kScanTile - 1) / kScanTile;
     int64_t *tile_sums = static_cast<int64_t *>(workspace);
     int64_t *tile_flags = tile_sums + tiles + 1;
-    csr_tile_sums<<<(unsigned)tiles, kScanBlock, 0, s>>>(counts, m, tile_sums, tile_flags);
+    const int32_t *lc = order ? ordered_counts : counts;
+    csr_tile_sums<<<(unsigned)tiles, kScanBlock, 0, s>>>(counts, lc, m, tile_sums, tile_flags);
     csr_tile_prefix<<<1, kScanBlock, 0, s>>>(tile_sums, tile_flags, tiles, qh);
-    csr_apply<<<(unsigned)tiles, kScanBlock, 0, s>>>(counts, m, tile_sums, tile_flags, offsets, big_list, huge_list);
+    csr_apply<<<(unsigned)tiles, kScanBlock, 0, s>>>(counts, lc, order, m, tile_sums, tile_flags, offsets, big_list,
+                                                     huge_list);
     return hipGetLastError();
 }
 

@@ -337,18 +337,33 @@ __device__ __forceinline__ void traverse_spatial_q(const QNode<D> *__restrict__ 
     }
 }
 
-// Insert x into the ascending buffer buf[0..k) (k < C) using static indices only.
+// Store x in slot k of buf (k < C), with static indices only.
 template <int C>
-__device__ __forceinline__ void insert_sorted(int (&buf)[C], int k, int x)
+__device__ __forceinline__ void append_at(int (&buf)[C], int k, int x)
 {
-    int v = x;
 #pragma unroll
-    for (int s = 0; s < C; ++s) {
-        const int a = buf[s];
-        const bool in = s < k;
-        buf[s] = in ? min(a, v) : (s == k ? v : a);
-        v = in ? max(a, v) : v;
-    }
+    for (int s = 0; s < C; ++s)
+        buf[s] = s == k ? x : buf[s];
+}
+
+// Ascending bitonic sorting network over C (a power of two) registers.
+template <int C>
+__device__ __forceinline__ void sort_network(int (&v)[C])
+{
+#pragma unroll
+    for (int k = 2; k <= C; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const int a = v[i], b = v[l];
+                    const bool up = (i & k) == 0;
+                    v[i] = up ? min(a, b) : max(a, b);
+                    v[l] = up ? max(a, b) : min(a, b);
+                }
+            }
 }
 
 struct KnnEntry {
