@@ -76,8 +76,11 @@ typedef struct arborx_tuning {
     int32_t seed_mode;    /* kNN starting bound: 0 = the k-th smallest distance among the 2k leaves around the
                              query's Morton position (default), 1 = none (+inf), 2 = the largest distance
                              among the k leaves around it */
-    int32_t quantized_nodes; /* thread schedules: 0 = walk float child boxes (default), 1 = walk child boxes stored
-                                as 16-bit codes rounded outward, deciding leaves on their exact records */
+    int32_t node_format;  /* node layout walked by the thread schedule (schedule 0): 0 = binary nodes with float
+                             child boxes (default); 1 = binary nodes with child boxes as 16-bit codes rounded
+                             outward, leaves decided on their exact records; 2 = four-wide nodes (two levels
+                             per fetch).  Formats 1 and 2 are built only while some operation asks for them
+                             when the tree is built; asking later is ARBORX_E_INVALID */
 } arborx_tuning;
 
 /* Operation kinds that carry their own tuning. */

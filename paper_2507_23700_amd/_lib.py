@@ -54,7 +54,7 @@ _lib = None
 
 class Tuning(ctypes.Structure):
     _fields_ = [("block", I32), ("order", I32), ("stack", I32), ("schedule", I32), ("build", I32),
-                ("seed_mode", I32), ("quantized_nodes", I32)]
+                ("seed_mode", I32), ("node_format", I32)]
 
 
 def header_symbols() -> list[str]:

@@ -132,7 +132,7 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
             best->schedule = cached.schedule;
             best->build = cached.build;
             best->seed_mode = cached.seed;
-            best->quantized_nodes = cached.nodes;
+            best->node_format = cached.nodes;
         }
         if (best_ms)
             *best_ms = -1.0;
@@ -160,17 +160,18 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
         c.t.order = 1;
         cands.push_back(c);
     }
-    for (int block : {64, 256}) {  // quantized child boxes, when the tree holds them
-        if (!tree_has_qnodes(tree))
-            break;
-        Candidate c;
-        c.t = base;
-        c.t.block = block;
-        c.t.schedule = 0;
-        c.t.nodes = 1;
-        c.t.order = 1;
-        cands.push_back(c);
-    }
+    for (int format : {1, 2})  // other node formats, when the tree holds them
+        for (int block : {64, 256}) {
+            if (!tree_has_format(tree, format))
+                break;
+            Candidate c;
+            c.t = base;
+            c.t.block = block;
+            c.t.schedule = 0;
+            c.t.nodes = format;
+            c.t.order = 1;
+            cands.push_back(c);
+        }
     if (op != OP_KNN)
         for (int block : {64, 256}) {
             Candidate c;
@@ -299,7 +300,7 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
         best->schedule = b.schedule;
         best->build = b.build;
         best->seed_mode = b.seed;
-        best->quantized_nodes = b.nodes;
+        best->node_format = b.nodes;
     }
     if (best_ms)
         *best_ms = cands[besti].ms;

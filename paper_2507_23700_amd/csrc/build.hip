@@ -467,6 +467,64 @@ __global__ void quantize_nodes(const Node<D> *__restrict__ nodes, int n_nodes, c
 }
 
 
+// Four-wide node p from binary node p and its internal children (the tree
+// is final).  Slot order: p's left subtree first, so a leaf slot keeps the
+// sorted order of the leaves.
+template <int D>
+__global__ void widen_nodes(const Node<D> *__restrict__ nodes, int n_nodes, Node4<D> *__restrict__ wnodes)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_nodes)
+        return;
+    Node<D> nd;
+    load_node(nodes, p, nd);
+    Node4<D> w;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(w.pad) / sizeof(w.pad[0])); ++k)
+        w.pad[k] = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        w.child[s] = kEmptyRef;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            w.lo[s][d] = INFINITY;
+            w.hi[s][d] = -INFINITY;
+        }
+    }
+    int k = 0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int32_t ref = nd.child[c];
+        if (ref >= 0 && ref < n_nodes) {
+            Node<D> ch;
+            load_node(nodes, ref, ch);
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    w.lo[k][d] = ch.lo[g][d];
+                    w.hi[k][d] = ch.hi[g][d];
+                }
+                w.child[k] = ch.child[g];
+                ++k;
+            }
+        } else if (ref != kEmptyRef) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                w.lo[k][d] = nd.lo[c][d];
+                w.hi[k][d] = nd.hi[c][d];
+            }
+            w.child[k] = ref;
+            ++k;
+        }
+    }
+    float4 *dst = reinterpret_cast<float4 *>(wnodes + p);
+    const float4 *src = reinterpret_cast<const float4 *>(&w);
+#pragma unroll
+    for (int q = 0; q < (int)(sizeof(Node4<D>) / 16); ++q)
+        dst[q] = src[q];
+}
+
 template <int D>
 __global__ __launch_bounds__(kBuildBlock) void hierarchy_chunk_kernel(const uint64_t *__restrict__ codes,
                                                                       const uint32_t *__restrict__ ids,
@@ -708,8 +766,10 @@ arborx_status build_impl(const float *values, int64_t n, int kind, TreeDev &t, h
     st = dalloc((void **)&t.leaves, (size_t)n * leaf_floats(D, kind) * sizeof(float), s);
     if (st != ARBORX_OK)
         return st;
-    const bool quantized = quantized_requested();
+    const bool quantized = format_requested(1), wide = format_requested(2);
     if (quantized && (st = dalloc(&t.qnodes, (size_t)nn * sizeof(QNode<D>), s)) != ARBORX_OK)
+        return st;
+    if (wide && (st = dalloc(&t.wnodes, (size_t)nn * sizeof(Node4<D>), s)) != ARBORX_OK)
         return st;
 
     Temps tmp(s);
@@ -770,6 +830,11 @@ arborx_status build_impl(const float *values, int64_t n, int kind, TreeDev &t, h
         ProfScope ps("build_quantize", s);
         quantize_nodes<D><<<grid_for(nn, kBuildBlock), kBuildBlock, 0, s>>>(nodes, (int)nn, nullptr, 0, (int)n, t.hdr,
                                                                             static_cast<QNode<D> *>(t.qnodes));
+    }
+    if (wide) {
+        ProfScope ps("build_widen", s);
+        widen_nodes<D><<<grid_for(nn, kBuildBlock), kBuildBlock, 0, s>>>(nodes, (int)nn,
+                                                                         static_cast<Node4<D> *>(t.wnodes));
     }
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
@@ -939,8 +1004,10 @@ arborx_status forest_build_impl(const float *values, const int64_t *seg_host, in
         (st = dalloc((void **)&f.leaves, (size_t)(n > 0 ? n : 1) * leaf_floats(D, kind) * sizeof(float), s)) !=
             ARBORX_OK)
         return st;
-    const bool quantized = quantized_requested();
+    const bool quantized = format_requested(1), wide = format_requested(2);
     if (quantized && (st = dalloc(&f.qnodes, (size_t)(n > 0 ? n : 1) * sizeof(QNode<D>), s)) != ARBORX_OK)
+        return st;
+    if (wide && (st = dalloc(&f.wnodes, (size_t)(n > 0 ? n : 1) * sizeof(Node4<D>), s)) != ARBORX_OK)
         return st;
     AX_HIP(hipMemcpyAsync(f.seg, seg_host, sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, s));
     // tiles that never straddle a tree
@@ -1015,6 +1082,9 @@ arborx_status forest_build_impl(const float *values, const int64_t *seg_host, in
     if (quantized)
         quantize_nodes<D><<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(nodes, (int)n, f.seg, T, (int)n, f.hdrs,
                                                                            static_cast<QNode<D> *>(f.qnodes));
+    if (wide)
+        widen_nodes<D><<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(nodes, (int)n,
+                                                                        static_cast<Node4<D> *>(f.wnodes));
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
@@ -1046,6 +1116,8 @@ void forest_release(ForestDev &f, hipStream_t s)
     dfree(f.nodes, s);
     dfree(f.qnodes, s);
     f.qnodes = nullptr;
+    dfree(f.wnodes, s);
+    f.wnodes = nullptr;
     dfree(f.leaves, s);
     dfree(f.hdrs, s);
     dfree(f.seg, s);

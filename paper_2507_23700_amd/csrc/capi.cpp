@@ -108,21 +108,30 @@ static bool g_pool_ready[64] = {};
 
 const Tuning &tuning(int op) { return g_tuning[op >= 0 && op < OP_KINDS ? op : 0]; }
 
-bool quantized_requested()
+bool format_requested(int format)
 {
     for (int op = 0; op < OP_KINDS; ++op)
-        if (g_tuning[op].nodes == 1)
+        if (g_tuning[op].nodes == format)
             return true;
     return false;
 }
 
-bool tree_has_qnodes(arborx_tree tree) { return tree && tree->dev.qnodes; }
+bool tree_has_format(arborx_tree tree, int format)
+{
+    return tree && (format == 0 || (format == 1 && tree->dev.qnodes) || (format == 2 && tree->dev.wnodes));
+}
 
-arborx_status check_qnodes(const void *qnodes, int64_t n, int op)
+int walk_format(int op)
 {
     const Tuning &t = tuning(op);
-    if (n > 0 && t.nodes == 1 && t.schedule == 0 && !qnodes)
-        return fail(ARBORX_E_INVALID, "quantized_nodes is set but the structure was built without quantized nodes; "
+    const bool thread_walk = op == OP_KNN ? t.schedule != 1 : t.schedule == 0;  // kNN has no rope walk
+    return thread_walk ? t.nodes : 0;
+}
+
+arborx_status check_nodes(const void *qnodes, const void *wnodes, int64_t n, int fmt)
+{
+    if (n > 0 && ((fmt == 1 && !qnodes) || (fmt == 2 && !wnodes)))
+        return fail(ARBORX_E_INVALID, "node_format asks for nodes the structure was built without; "
                                       "set it before building");
     return ARBORX_OK;
 }
@@ -233,6 +242,7 @@ static void release_tree(arborx_tree t)
         (void)hipDeviceSynchronize();
     dfree(t->dev.nodes, rs);
     dfree(t->dev.qnodes, rs);
+    dfree(t->dev.wnodes, rs);
     dfree(t->dev.leaves, rs);
     dfree(t->dev.hdr, rs);
     if (t->ready)
@@ -281,9 +291,9 @@ static arborx_status to_tuning(const arborx_tuning *t, const Tuning &base, Tunin
     if (t->seed_mode < 0 || t->seed_mode > 2)
         return fail(ARBORX_E_INVALID, "seed_mode must be 0, 1 or 2");
     n.seed = t->seed_mode;
-    if (t->quantized_nodes != 0 && t->quantized_nodes != 1)
-        return fail(ARBORX_E_INVALID, "quantized_nodes must be 0 or 1");
-    n.nodes = t->quantized_nodes;
+    if (t->node_format < 0 || t->node_format > 2)
+        return fail(ARBORX_E_INVALID, "node_format must be 0 (binary), 1 (binary, 16-bit boxes) or 2 (four-wide)");
+    n.nodes = t->node_format;
     return ARBORX_OK;
 }
 
@@ -295,7 +305,7 @@ static void from_tuning(const Tuning &g, arborx_tuning *t)
     t->schedule = g.schedule;
     t->build = g.build;
     t->seed_mode = g.seed;
-    t->quantized_nodes = g.nodes;
+    t->node_format = g.nodes;
 }
 
 arborx_status arborx_set_tuning(const arborx_tuning *t)

@@ -79,9 +79,10 @@ __device__ __forceinline__ int64_t next_block(unsigned long long *counter, int64
     return start < m ? start : -1;
 }
 
-template <int D, bool SUMDIST, bool QN>
+template <int D, bool SUMDIST, int FMT>
 __global__ __launch_bounds__(kForestBlock) void k_forest_reduce(
-    const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes, const float *__restrict__ leaves, int kind,
+    const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes, const Node4<D> *__restrict__ wnodes,
+    const float *__restrict__ leaves, int kind,
     int n_nodes, const TreeHeader *__restrict__ hdrs, int T,
     const float *__restrict__ queries, int64_t m, const uint32_t *__restrict__ perm, const int64_t *__restrict__ boff,
     int B, const int32_t *__restrict__ btree, const float *__restrict__ bradius, float scale, int32_t *__restrict__ counts,
@@ -107,14 +108,13 @@ __global__ __launch_bounds__(kForestBlock) void k_forest_reduce(
             ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap, spill);
             auto f = [&](int, float d2) {
                 ++c;
-                if (SUMDIST) {
-                    const float dist = sqrtf(d2);
-                    const float scaled = dist * scale;
-                    s += (long long)scaled;
-                }
+                if (SUMDIST)
+                    s += fixed_term(d2, scale);
             };
-            if (QN)
+            if (FMT == 1)
                 traverse_spatial_q<D>(qnodes, hdrs[tr], n_nodes, leaves, kind, pred, st, f);
+            else if (FMT == 2)
+                traverse_spatial4<D>(wnodes, hdrs[tr].root, n_nodes, pred, st, f);
             else
                 traverse_spatial<D>(nodes, hdrs[tr].root, n_nodes, pred, st, f);
         }
@@ -124,9 +124,10 @@ __global__ __launch_bounds__(kForestBlock) void k_forest_reduce(
     }
 }
 
-template <int D, int K, bool QN>
+template <int D, int K, int FMT>
 __global__ __launch_bounds__(kForestBlock) void k_forest_knn(
-    const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes, int n_nodes,
+    const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes, const Node4<D> *__restrict__ wnodes,
+    int n_nodes,
     const float *__restrict__ leaves, int kind,
     const TreeHeader *__restrict__ hdrs, int T, const float *__restrict__ queries, int64_t m,
     const uint32_t *__restrict__ perm, const int64_t *__restrict__ boff, int B, const int32_t *__restrict__ btree,
@@ -158,8 +159,10 @@ __global__ __launch_bounds__(kForestBlock) void k_forest_knn(
         for (int d = 0; d < D; ++d)
             q[d] = queries[qi * D + d];
         ShortStack<KnnEntry> st(reinterpret_cast<KnnEntry *>(s_stack) + threadIdx.x, blockDim.x, stack_cap, spill);
-        if (QN)
+        if (FMT == 1)
             knn_search_q<D, K>(qnodes, n_nodes, leaves, kind, h, q, best, st, seed);
+        else if (FMT == 2)
+            knn_search4<D, K>(nodes, wnodes, n_nodes, leaves, kind, h, q, best, st, seed);
         else
             knn_search<D, K>(nodes, n_nodes, leaves, kind, h, q, best, st, seed);
         best.store(k_out, out_d2 + qi * k_out, out_idx + qi * k_out, h.start);  // indices local to the tree
@@ -258,25 +261,29 @@ arborx_status forest_reduce_impl(ForestDev &f, const float *q, int64_t m, const 
     ProfScope ps(op == ARBORX_COUNT_SUMDIST ? "forest_reduce_sumdist" : "forest_reduce_count", s);
     const Node<D> *nodes = static_cast<const Node<D> *>(f.nodes);
     const QNode<D> *qnodes = static_cast<const QNode<D> *>(f.qnodes);
+    const Node4<D> *wnodes = static_cast<const Node4<D> *>(f.wnodes);
     const int nn = (int)(f.n > 0 ? f.n : 1);
-    const bool qn = tu.nodes == 1;
-#define AX_FREDUCE(SD, Q)                                                                                        \
+#define AX_FREDUCE(SD, F)                                                                                        \
     do {                                                                                                         \
-        const int grid = persistent_grid((const void *)k_forest_reduce<D, SD, Q>, kForestBlock, lds);           \
-        k_forest_reduce<D, SD, Q><<<grid, kForestBlock, lds, s>>>(nodes, qnodes, f.leaves, f.kind, nn, f.hdrs, f.T, q, \
-                                                                  m, perm, boff, B, btree, brad, scale, counts, sums, \
-                                                                  counter, cap);                               \
+        const int grid = persistent_grid((const void *)k_forest_reduce<D, SD, F>, kForestBlock, lds);           \
+        k_forest_reduce<D, SD, F><<<grid, kForestBlock, lds, s>>>(nodes, qnodes, wnodes, f.leaves, f.kind, nn, f.hdrs, \
+                                                                  f.T, q, m, perm, boff, B, btree, brad, scale,  \
+                                                                  counts, sums, counter, cap);                 \
     } while (0)
     if (op == ARBORX_COUNT_SUMDIST) {
-        if (qn)
-            AX_FREDUCE(true, true);
+        if (tu.nodes == 1)
+            AX_FREDUCE(true, 1);
+        else if (tu.nodes == 2)
+            AX_FREDUCE(true, 2);
         else
-            AX_FREDUCE(true, false);
+            AX_FREDUCE(true, 0);
     } else {
-        if (qn)
-            AX_FREDUCE(false, true);
+        if (tu.nodes == 1)
+            AX_FREDUCE(false, 1);
+        else if (tu.nodes == 2)
+            AX_FREDUCE(false, 2);
         else
-            AX_FREDUCE(false, false);
+            AX_FREDUCE(false, 0);
     }
 #undef AX_FREDUCE
     AX_HIP(hipGetLastError());
@@ -303,17 +310,20 @@ arborx_status forest_knn_launch(ForestDev &f, const float *q, int64_t m, const i
         cap >>= 1;
     const size_t lds = (size_t)cap * kForestBlock * sizeof(KnnEntry);
     ProfScope ps("forest_knn", s);
-#define AX_FKNN(Q)                                                                                                 \
+#define AX_FKNN(F)                                                                                                 \
     do {                                                                                                           \
-        const int grid = persistent_grid((const void *)k_forest_knn<D, K, Q>, kForestBlock, lds);                 \
-        k_forest_knn<D, K, Q><<<grid, kForestBlock, lds, s>>>(                                                    \
-            static_cast<const Node<D> *>(f.nodes), static_cast<const QNode<D> *>(f.qnodes), (int)(f.n > 0 ? f.n : 1), \
-            f.leaves, f.kind, f.hdrs, f.T, q, m, perm, boff, B, btree, k, d2, idx, counter, cap, tu.seed);       \
+        const int grid = persistent_grid((const void *)k_forest_knn<D, K, F>, kForestBlock, lds);                 \
+        k_forest_knn<D, K, F><<<grid, kForestBlock, lds, s>>>(                                                    \
+            static_cast<const Node<D> *>(f.nodes), static_cast<const QNode<D> *>(f.qnodes),                        \
+            static_cast<const Node4<D> *>(f.wnodes), (int)(f.n > 0 ? f.n : 1), f.leaves, f.kind, f.hdrs, f.T, q, m, \
+            perm, boff, B, btree, k, d2, idx, counter, cap, tu.seed);                                              \
     } while (0)
     if (tu.nodes == 1)
-        AX_FKNN(true);
+        AX_FKNN(1);
+    else if (tu.nodes == 2)
+        AX_FKNN(2);
     else
-        AX_FKNN(false);
+        AX_FKNN(0);
 #undef AX_FKNN
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
@@ -346,7 +356,7 @@ arborx_status forest_query_reduce(ForestDev &f, const float *q, int64_t m, const
 {
     if (m == 0)
         return ARBORX_OK;
-    arborx_status st = check_qnodes(f.qnodes, f.n, OP_REDUCE);
+    arborx_status st = check_nodes(f.qnodes, f.wnodes, f.n, tuning(OP_REDUCE).nodes);
     if (st == ARBORX_OK)
         st = reserve_ws(f, m, s);
     if (st != ARBORX_OK)
@@ -364,7 +374,7 @@ arborx_status forest_query_knn(ForestDev &f, const float *q, int64_t m, const in
 {
     if (m == 0)
         return ARBORX_OK;
-    arborx_status st = check_qnodes(f.qnodes, f.n, OP_KNN);
+    arborx_status st = check_nodes(f.qnodes, f.wnodes, f.n, tuning(OP_KNN).nodes);
     if (st == ARBORX_OK)
         st = reserve_ws(f, m, s);
     if (st != ARBORX_OK)

@@ -85,6 +85,30 @@ static_assert(sizeof(QNode<3>) == 32, "3D quantized node is 32 bytes");
 
 constexpr int kQMax = 65535;
 
+// Four-wide node: binary node p with its two levels collapsed.  The slots are
+// p's children, each internal child replaced by its own two children, so one
+// fetch decides up to four subtrees.  A slot reference >= 0 names a binary
+// node whose four-wide node is visited next, < 0 is a leaf holding value ~ref,
+// kEmptyRef an unused slot (box lo = +inf, hi = -inf).  128 bytes in 3D.
+template <int D>
+struct alignas(16) Node4 {
+    float lo[4][D];
+    float hi[4][D];
+    int32_t child[4];
+    int32_t pad[(16 - (32 * D + 16) % 16) % 16 / 4 + (D == 3 ? 4 : 0)];
+};
+static_assert(sizeof(Node4<3>) == 128, "3D four-wide node is 128 bytes");
+
+template <int D>
+__device__ __forceinline__ void load_node4(const Node4<D> *__restrict__ nodes, int32_t i, Node4<D> &out)
+{
+    const float4 *src = reinterpret_cast<const float4 *>(nodes + i);
+    float4 *dst = reinterpret_cast<float4 *>(&out);
+#pragma unroll
+    for (int k = 0; k < (int)((sizeof(Node4<D>) - (D == 3 ? 16 : 0)) / 16); ++k)
+        dst[k] = src[k];
+}
+
 __device__ __forceinline__ float qdecode(uint32_t code, float lo, float scale) { return fmaf((float)code, scale, lo); }
 
 template <int D>

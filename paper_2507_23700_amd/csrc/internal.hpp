@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -41,17 +42,22 @@ struct Tuning {
     int schedule = 0;
     int build = 0;
     int seed = 0;   // kNN starting bound: 0 k-th of 2k nearby leaves, 1 none, 2 farthest of k nearby leaves
-    int nodes = 0;  // 0: float child boxes, 1: quantized 16-bit child boxes (exact leaf tests)
+    int nodes = 0;  // 0: binary float, 1: binary with quantized 16-bit child boxes (exact leaf tests), 2: four-wide
 };
 // Tuning is kept per operation kind so the autotuner can pick each separately.
 enum Op { OP_SPATIAL = 0, OP_REDUCE = 1, OP_KNN = 2, OP_KINDS = 3 };
 const Tuning &tuning(int op = OP_SPATIAL);
 void set_tuning_op(int op, const Tuning &t);
-// Quantized nodes are built only while some operation asks for them.
-bool quantized_requested();
-// ARBORX_E_INVALID unless the structure holds quantized nodes or `op` does not use them.
-arborx_status check_qnodes(const void *qnodes, int64_t n, int op);
-bool tree_has_qnodes(arborx_tree tree);
+// Quantized (1) and four-wide (2) nodes are built only while some operation
+// asks for that format.
+bool format_requested(int format);
+// Node format a single-tree walk of `op` uses: the tuning's format for the
+// thread schedule (kNN: any schedule but the wavefront packet), else binary.
+int walk_format(int op);
+// ARBORX_E_INVALID unless the structure holds the nodes of format `fmt`.
+arborx_status check_nodes(const void *qnodes, const void *wnodes, int64_t n, int fmt);
+bool tree_has_format(arborx_tree tree, int format);
+
 
 // Error reporting: thread-local last message.
 void set_error(const std::string &msg);
@@ -136,6 +142,7 @@ struct TreeDev {
     int kind = 0;
     void *nodes = nullptr;  // Node<dim>[max(n-1, 1)]
     void *qnodes = nullptr; // QNode<dim>[max(n-1, 1)]: the same tree with 16-bit child boxes
+    void *wnodes = nullptr; // Node4<dim>[max(n-1, 1)]: the same tree two levels per node
     float *leaves = nullptr; // n leaf records in sorted order (see leaf_floats)
     TreeHeader *hdr = nullptr;
 };
@@ -152,6 +159,7 @@ struct ForestDev {
     int dim = 0, kind = 0, T = 0;
     void *nodes = nullptr;     // Node<dim>[n]: one slot per split plus a spare for a last one-value tree
     void *qnodes = nullptr;    // QNode<dim>[n]
+    void *wnodes = nullptr;    // Node4<dim>[n]
     float *leaves = nullptr;   // n leaf records, sorted inside each tree
     TreeHeader *hdrs = nullptr;  // [T]
     int64_t *seg = nullptr;    // [T+1] device copy of the tree offsets

@@ -32,6 +32,7 @@ __device__ __forceinline__ int node_count(const TreeHeader *hdr) { return hdr->n
 // second walk.
 template <int D, class P, bool STASH, int SCHED>
 __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
+                                const Node4<D> *__restrict__ wnodes,
                                 const float *__restrict__ leaves, int kind, const TreeHeader *__restrict__ hdr,
                                 const float *__restrict__ queries, int64_t m, float r2,
                                 const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
@@ -69,6 +70,8 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D
         traverse_spatial_rope<D>(nodes, hdr->root, node_count(hdr), hdr->start + hdr->n - 1, pred, f);
     else if (SCHED == 3)
         traverse_spatial_q<D>(qnodes, *hdr, node_count(hdr), leaves, kind, pred, st, f);
+    else if (SCHED == 4)
+        traverse_spatial4<D>(wnodes, hdr->root, node_count(hdr), pred, st, f);
     else
         traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
     if (!active)
@@ -119,8 +122,9 @@ __global__ void k_copy_stash(const int32_t *__restrict__ stash, int64_t m, const
 
 // Second walk for listed rows (longer than the stash): matches written in
 // traversal order, sorted afterwards.
-template <int D, class P, bool QN>
+template <int D, class P, int FMT>
 __global__ void k_spatial_fill_rows(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
+                                    const Node4<D> *__restrict__ wnodes,
                                     const float *__restrict__ leaves, int kind, const TreeHeader *__restrict__ hdr,
                                     const float *__restrict__ queries, int64_t m, float r2,
                                     const int32_t *__restrict__ rows, int64_t nrows,
@@ -145,8 +149,10 @@ __global__ void k_spatial_fill_rows(const Node<D> *__restrict__ nodes, const QNo
             indices[o + k] = idx;
         ++k;
     };
-    if (QN)
+    if (FMT == 1)
         traverse_spatial_q<D>(qnodes, *hdr, node_count(hdr), leaves, kind, pred, st, f);
+    else if (FMT == 2)
+        traverse_spatial4<D>(wnodes, hdr->root, node_count(hdr), pred, st, f);
     else
         traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
 }
@@ -257,6 +263,7 @@ __global__ void k_huge_scatter(const uint64_t *__restrict__ keys, int64_t total,
 
 template <int D, bool SUMDIST, int SCHED>
 __global__ void k_spatial_reduce(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
+                                 const Node4<D> *__restrict__ wnodes,
                                  const float *__restrict__ leaves, int kind, const TreeHeader *__restrict__ hdr,
                                  const float *__restrict__ queries, int64_t m, float r2, float scale,
                                  const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
@@ -282,11 +289,8 @@ __global__ void k_spatial_reduce(const Node<D> *__restrict__ nodes, const QNode<
     long long s = 0;
     auto f = [&](int, float d2) {
         ++c;
-        if (SUMDIST) {
-            const float dist = sqrtf(d2);  // correctly rounded
-            const float scaled = dist * scale;  // exact: scale is a power of two
-            s += (long long)scaled;
-        }
+        if (SUMDIST)
+            s += fixed_term(d2, scale);
     };
     if (SCHED == 1)
         traverse_spatial_wave<D>(nodes, hdr->root, node_count(hdr), pred, wstack, f);
@@ -294,6 +298,8 @@ __global__ void k_spatial_reduce(const Node<D> *__restrict__ nodes, const QNode<
         traverse_spatial_rope<D>(nodes, hdr->root, node_count(hdr), hdr->start + hdr->n - 1, pred, f);
     else if (SCHED == 3)
         traverse_spatial_q<D>(qnodes, *hdr, node_count(hdr), leaves, kind, pred, st, f);
+    else if (SCHED == 4)
+        traverse_spatial4<D>(wnodes, hdr->root, node_count(hdr), pred, st, f);
     else
         traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
     if (!active)
@@ -303,8 +309,9 @@ __global__ void k_spatial_reduce(const Node<D> *__restrict__ nodes, const QNode<
         sums[qi] = s;
 }
 
-template <int D, int K, bool WAVE, bool QN>
-__global__ void k_knn(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes, int n_nodes,
+template <int D, int K, bool WAVE, int FMT>
+__global__ void k_knn(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
+                      const Node4<D> *__restrict__ wnodes, int n_nodes,
                       const float *__restrict__ leaves, int kind,
                       const TreeHeader *__restrict__ hdr, const float *__restrict__ queries, int64_t m, int k_out,
                       const uint32_t *__restrict__ perm, float *__restrict__ out_d2, int32_t *__restrict__ out_idx,
@@ -329,8 +336,10 @@ __global__ void k_knn(const Node<D> *__restrict__ nodes, const QNode<D> *__restr
     } else {
         KnnEntry spill[kSpill];
         ShortStack<KnnEntry> st(reinterpret_cast<KnnEntry *>(s_stack) + threadIdx.x, blockDim.x, stack_cap, spill);
-        if (QN)
+        if (FMT == 1)
             knn_search_q<D, K>(qnodes, n_nodes, leaves, kind, *hdr, q, best, st, seed);
+        else if (FMT == 2)
+            knn_search4<D, K>(nodes, wnodes, n_nodes, leaves, kind, *hdr, q, best, st, seed);
         else
             knn_search<D, K>(nodes, n_nodes, leaves, kind, *hdr, q, best, st, seed);
     }
@@ -404,11 +413,12 @@ Launch traversal_launch(int64_t m, size_t entry_bytes, int op, bool wave = false
     return L;
 }
 
-// Schedule 0 over quantized nodes runs as internal schedule 3.
+// Schedule 0 over quantized nodes runs as internal schedule 3, over four-wide
+// nodes as internal schedule 4.
 int effective_schedule(int op)
 {
     const Tuning &tu = tuning(op);
-    return tu.schedule == 0 && tu.nodes == 1 ? 3 : tu.schedule;
+    return tu.schedule != 0 ? tu.schedule : (tu.nodes == 1 ? 3 : (tu.nodes == 2 ? 4 : 0));
 }
 
 template <int D>
@@ -419,9 +429,10 @@ arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m,
     const Launch L = traversal_launch(m, sizeof(int), OP_SPATIAL, sched == 1);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
+    const Node4<D> *wnodes = static_cast<const Node4<D> *>(t.wnodes);
     ProfScope ps("spatial_count", s);
 #define AX_COUNT(P, S)                                                                                     \
-    k_spatial_count<D, P, true, S><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, t.leaves, t.kind, t.hdr, q, m, r2, \
+    k_spatial_count<D, P, true, S><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, wnodes, t.leaves, t.kind, t.hdr, q, m, r2, \
                                                                   perm, counts, perm ? ordered_counts : nullptr,  \
                                                                   stash, L.cap)
     if (pred == Pred::Sphere) {
@@ -431,6 +442,8 @@ arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m,
             AX_COUNT(Sphere<D>, 2);
         else if (sched == 3)
             AX_COUNT(Sphere<D>, 3);
+        else if (sched == 4)
+            AX_COUNT(Sphere<D>, 4);
         else
             AX_COUNT(Sphere<D>, 0);
     } else {
@@ -440,6 +453,8 @@ arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m,
             AX_COUNT(BoxQuery<D>, 2);
         else if (sched == 3)
             AX_COUNT(BoxQuery<D>, 3);
+        else if (sched == 4)
+            AX_COUNT(BoxQuery<D>, 4);
         else
             AX_COUNT(BoxQuery<D>, 0);
     }
@@ -457,21 +472,26 @@ arborx_status fill_rows_impl(const TreeDev &t, Pred pred, const float *q, int64_
     Launch L = traversal_launch(nrows, sizeof(int), OP_SPATIAL);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
-    const bool qn = tuning(OP_SPATIAL).nodes == 1;
+    const Node4<D> *wnodes = static_cast<const Node4<D> *>(t.wnodes);
+    const int fmt = walk_format(OP_SPATIAL);
     ProfScope ps("spatial_fill", s);
-#define AX_FILL(P, Q)                                                                                              \
-    k_spatial_fill_rows<D, P, Q><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, t.leaves, t.kind, t.hdr, q, m, r2, rows, \
-                                                                nrows, offsets, indices, L.cap)
+#define AX_FILL(P, F)                                                                                              \
+    k_spatial_fill_rows<D, P, F><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, wnodes, t.leaves, t.kind, t.hdr, q, m, r2, \
+                                                                rows, nrows, offsets, indices, L.cap)
     if (pred == Pred::Sphere) {
-        if (qn)
-            AX_FILL(Sphere<D>, true);
+        if (fmt == 1)
+            AX_FILL(Sphere<D>, 1);
+        else if (fmt == 2)
+            AX_FILL(Sphere<D>, 2);
         else
-            AX_FILL(Sphere<D>, false);
+            AX_FILL(Sphere<D>, 0);
     } else {
-        if (qn)
-            AX_FILL(BoxQuery<D>, true);
+        if (fmt == 1)
+            AX_FILL(BoxQuery<D>, 1);
+        else if (fmt == 2)
+            AX_FILL(BoxQuery<D>, 2);
         else
-            AX_FILL(BoxQuery<D>, false);
+            AX_FILL(BoxQuery<D>, 0);
     }
 #undef AX_FILL
     AX_HIP(hipGetLastError());
@@ -486,29 +506,29 @@ arborx_status reduce_impl(const TreeDev &t, const float *q, int64_t m, float r2,
     const Launch L = traversal_launch(m, sizeof(int), OP_REDUCE, sched == 1);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
+    const Node4<D> *wnodes = static_cast<const Node4<D> *>(t.wnodes);
     ProfScope ps(op == ARBORX_COUNT_SUMDIST ? "reduce_sumdist" : "reduce_count", s);
 #define AX_REDUCE(SD, S)                                                                                      \
-    k_spatial_reduce<D, SD, S><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, t.leaves, t.kind, t.hdr, q, m, r2, scale, \
+    k_spatial_reduce<D, SD, S><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, wnodes, t.leaves, t.kind, t.hdr, q, m, r2, scale, \
                                                               perm, counts, sums, L.cap)
-    if (op == ARBORX_COUNT_SUMDIST) {
-        if (sched == 1)
-            AX_REDUCE(true, 1);
-        else if (sched == 2)
-            AX_REDUCE(true, 2);
-        else if (sched == 3)
-            AX_REDUCE(true, 3);
-        else
-            AX_REDUCE(true, 0);
-    } else {
-        if (sched == 1)
-            AX_REDUCE(false, 1);
-        else if (sched == 2)
-            AX_REDUCE(false, 2);
-        else if (sched == 3)
-            AX_REDUCE(false, 3);
-        else
-            AX_REDUCE(false, 0);
-    }
+#define AX_REDUCE_MODE(MD)                 \
+    do {                                   \
+        if (sched == 1)                    \
+            AX_REDUCE(MD, 1);              \
+        else if (sched == 2)               \
+            AX_REDUCE(MD, 2);              \
+        else if (sched == 3)               \
+            AX_REDUCE(MD, 3);              \
+        else if (sched == 4)               \
+            AX_REDUCE(MD, 4);              \
+        else                               \
+            AX_REDUCE(MD, 0);              \
+    } while (0)
+    if (op == ARBORX_COUNT_SUMDIST)
+        AX_REDUCE_MODE(true);
+    else
+        AX_REDUCE_MODE(false);
+#undef AX_REDUCE_MODE
 #undef AX_REDUCE
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
@@ -519,21 +539,24 @@ arborx_status knn_launch(const TreeDev &t, const float *q, int64_t m, int k, con
                          int32_t *idx, hipStream_t s)
 {
     const bool wave = tuning(OP_KNN).schedule == 1;  // kNN has no rope form: schedule 2 walks with the stack
-    const bool qn = !wave && tuning(OP_KNN).nodes == 1;
+    const int fmt = walk_format(OP_KNN);
     const Launch L = traversal_launch(m, sizeof(KnnEntry), OP_KNN, wave);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
+    const Node4<D> *wnodes = static_cast<const Node4<D> *>(t.wnodes);
     const int seed = tuning(OP_KNN).seed;
     ProfScope ps("knn", s);
-#define AX_KNN(W, Q)                                                                                              \
-    k_knn<D, K, W, Q><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, tree_nodes(t), t.leaves, t.kind, t.hdr, q, m, k, \
-                                                     perm, d2, idx, L.cap, seed)
+#define AX_KNN(W, F)                                                                                              \
+    k_knn<D, K, W, F><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, wnodes, tree_nodes(t), t.leaves, t.kind, t.hdr, q, m, \
+                                                     k, perm, d2, idx, L.cap, seed)
     if (wave)
-        AX_KNN(true, false);
-    else if (qn)
-        AX_KNN(false, true);
+        AX_KNN(true, 0);
+    else if (fmt == 1)
+        AX_KNN(false, 1);
+    else if (fmt == 2)
+        AX_KNN(false, 2);
     else
-        AX_KNN(false, false);
+        AX_KNN(false, 0);
 #undef AX_KNN
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
@@ -610,7 +633,7 @@ arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, i
         return ARBORX_OK;
     if (t.n == 0)
         return fill_async<int32_t>(counts, m, 0, s);
-    arborx_status st = check_qnodes(t.qnodes, t.n, OP_SPATIAL);
+    arborx_status st = check_nodes(t.qnodes, t.wnodes, t.n, walk_format(OP_SPATIAL));
     if (st != ARBORX_OK)
         return st;
     const float r2 = radius * radius;
@@ -624,7 +647,7 @@ arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, in
 {
     if (m == 0 || t.n == 0)
         return ARBORX_OK;
-    arborx_status st = check_qnodes(t.qnodes, t.n, OP_SPATIAL);
+    arborx_status st = check_nodes(t.qnodes, t.wnodes, t.n, walk_format(OP_SPATIAL));
     if (st != ARBORX_OK)
         return st;
     {
@@ -714,7 +737,7 @@ arborx_status spatial_reduce(const TreeDev &t, const float *queries, int64_t m, 
             st = fill_async<int64_t>(sums, m, 0, s);
         return st;
     }
-    arborx_status st = check_qnodes(t.qnodes, t.n, OP_REDUCE);
+    arborx_status st = check_nodes(t.qnodes, t.wnodes, t.n, walk_format(OP_REDUCE));
     if (st != ARBORX_OK)
         return st;
     const float r2 = radius * radius;
@@ -732,7 +755,7 @@ arborx_status knn_query(const TreeDev &t, const float *queries, int64_t m, int k
         AX_HIP(hipGetLastError());
         return ARBORX_OK;
     }
-    arborx_status st = check_qnodes(t.qnodes, t.n, OP_KNN);
+    arborx_status st = check_nodes(t.qnodes, t.wnodes, t.n, walk_format(OP_KNN));
     if (st != ARBORX_OK)
         return st;
     AX_DISPATCH_DIM(t.dim, (knn_impl<D>(t, queries, m, k, perm, dist2, indices, s)));

@@ -170,6 +170,37 @@ __device__ __forceinline__ void traverse_spatial(const Node<D> *__restrict__ nod
     }
 }
 
+// The depth-first walk over four-wide nodes: one fetch tests up to four
+// subtrees; matching leaf slots are reported, the first matching internal slot
+// is entered and the others are deferred on the stack.
+template <int D, class P, class F>
+__device__ __forceinline__ void traverse_spatial4(const Node4<D> *__restrict__ nodes, int root, int n_nodes,
+                                                  const P &pred, ShortStack<int> &st, F &f)
+{
+    int cur = root;
+    for (int iter = 0; iter <= n_nodes; ++iter) {
+        if ((unsigned)cur >= (unsigned)n_nodes)
+            break;
+        Node4<D> nd;
+        load_node4(nodes, cur, nd);
+        int next = -1;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            float d;
+            const bool h = pred.hit(nd.lo[s], nd.hi[s], d);
+            const int c = nd.child[s];
+            if (h && c < 0 && c != kEmptyRef)
+                f(~c, d);
+            if (h && c >= 0) {
+                if (next >= 0)
+                    st.push(next);
+                next = c;
+            }
+        }
+        cur = next >= 0 ? next : (st.empty() ? -1 : st.pop());
+    }
+}
+
 // Wavefront-packet form of the walk: the 64 lanes (64 Morton-neighbouring
 // queries) visit the union of their paths together.  The node index is the
 // same in every lane, so each node is fetched once per wavefront through the
@@ -335,6 +366,15 @@ __device__ __forceinline__ void traverse_spatial_q(const QNode<D> *__restrict__ 
             cur = st.pop();
         }
     }
+}
+
+// One term of the fixed-point distance sum: trunc(sqrtf(d2) * scale), scale
+// a power of two.
+__device__ __forceinline__ long long fixed_term(float d2, float scale)
+{
+    const float dist = sqrtf(d2);       // correctly rounded
+    const float scaled = dist * scale;  // exact: scale is a power of two
+    return (long long)scaled;
 }
 
 // Store x in slot k of buf (k < C), with static indices only.
@@ -554,6 +594,102 @@ best.reset(INFINITY);
             if (!found)
                 break;
         }
+    }
+}
+
+// Order two (distance, reference, admitted) candidates so that the first is
+// the farther admitted one; candidates not admitted go last.
+__device__ __forceinline__ void far_first(float &da, int &ra, bool &ka, float &db, int &rb, bool &kb)
+{
+    const bool swap = (kb && !ka) || (ka && kb && db > da);
+    const float td = da;
+    const int tr = ra;
+    const bool tk = ka;
+    da = swap ? db : da;
+    ra = swap ? rb : ra;
+    ka = swap ? kb : ka;
+    db = swap ? td : db;
+    rb = swap ? tr : rb;
+    kb = swap ? tk : kb;
+}
+
+// kNN over four-wide nodes: leaf slots are offered; admitted internal slots
+// are sorted farthest first, the nearest is entered and the others are pushed
+// with their distances (the nearest of them on top).  Seeding as knn_search,
+// on the binary nodes.
+template <int D, int K>
+__device__ __forceinline__ void knn_search4(const Node<D> *__restrict__ nodes, const Node4<D> *__restrict__ wnodes,
+                                            int n_nodes, const float *__restrict__ leaves, int kind,
+                                            const TreeHeader &hdr, const float *q, TopK<K> &best,
+                                            ShortStack<KnnEntry> &st, int seed)
+{
+    const int n = hdr.n;
+    best.reset(INFINITY);
+    if (n <= 0)
+        return;
+    if (seed != 1 && n >= K) {
+        int cur = hdr.root, pos = hdr.start;
+        for (int iter = 0; iter <= n_nodes; ++iter) {
+            if ((unsigned)cur >= (unsigned)n_nodes)
+                break;
+            Node<D> nd;
+            load_node(nodes, cur, nd);
+            const float d0 = box_d2<D>(q, nd.lo[0], nd.hi[0]);
+            const float d1 = box_d2<D>(q, nd.lo[1], nd.hi[1]);
+            const int go = d1 < d0 ? 1 : 0;
+            const int c = go ? nd.child[1] : nd.child[0];
+            if (c < 0) {
+                pos = cur + go;
+                break;
+            }
+            cur = c;
+        }
+        seed_window<D, K>(leaves, kind, hdr, pos, q, best, seed);
+    }
+    int cur = hdr.root;
+    for (int iter = 0; iter <= n_nodes; ++iter) {
+        if ((unsigned)cur >= (unsigned)n_nodes)
+            break;
+        Node4<D> nd;
+        load_node4(wnodes, cur, nd);
+        float d[4];
+        int r[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            d[s] = box_d2<D>(q, nd.lo[s], nd.hi[s]);
+            r[s] = nd.child[s];
+            if (r[s] < 0 && r[s] != kEmptyRef)
+                best.offer(d[s], ~r[s]);
+        }
+        const float bound = best.bound();
+        bool k[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            k[s] = r[s] >= 0 && !(d[s] > bound);
+        // sorting network on four: farthest admitted first, not admitted last
+        far_first(d[0], r[0], k[0], d[1], r[1], k[1]);
+        far_first(d[2], r[2], k[2], d[3], r[3], k[3]);
+        far_first(d[0], r[0], k[0], d[2], r[2], k[2]);
+        far_first(d[1], r[1], k[1], d[3], r[3], k[3]);
+        far_first(d[1], r[1], k[1], d[2], r[2], k[2]);
+        int next = -1;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            if (k[s]) {
+                if (next >= 0)
+                    st.push(KnnEntry{next, d[s - 1 >= 0 ? s - 1 : 0]});
+                next = r[s];
+            }
+        if (next < 0) {
+            while (!st.empty()) {
+                const KnnEntry e = st.pop();
+                if (!(e.d2 > best.bound())) {
+                    next = e.ref;
+                    break;
+                }
+            }
+        }
+        cur = next;
     }
 }
 

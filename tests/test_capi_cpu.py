@@ -83,16 +83,17 @@ def test_tuning_validation_and_roundtrip():
     assert L.arborx_set_tuning(ctypes.byref(t)) == 0
     g = _lib.Tuning()
     assert L.arborx_get_tuning(ctypes.byref(g)) == 0
-    assert (g.block, g.order, g.stack, g.schedule, g.build, g.seed_mode, g.quantized_nodes) == (128, 0, 8, 0, 1, 1, 1)
+    assert (g.block, g.order, g.stack, g.schedule, g.build, g.seed_mode, g.node_format) == (128, 0, 8, 0, 1, 1, 1)
     assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(100, 1, 0, 0, 0, 0, 0))) == 1
     assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 0, 0, 2, 0, 0))) == 1
-    assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 0, 0, 0, 0, 2))) == 1
+    assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 0, 0, 0, 0, 3))) == 1
+    assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 0, 0, 0, 0, 2))) == 0
     assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 0, 0, 0, 3, 0))) == 1
     assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 0, 0, 0, -1, 0))) == 1
     assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 12, 0, 0, 0, 0))) == 1
     assert L.arborx_set_tuning(None) == 0
     assert L.arborx_get_tuning(ctypes.byref(g)) == 0
-    assert (g.block, g.order, g.stack, g.build, g.seed_mode, g.quantized_nodes) == (256, 1, 16, 0, 0, 0)
+    assert (g.block, g.order, g.stack, g.build, g.seed_mode, g.node_format) == (256, 1, 16, 0, 0, 0)
 
 
 def test_debug_entry_validation():
@@ -109,12 +110,12 @@ def test_valid_call_without_gpu_reports_device_error():
 
 
 def test_python_tuning_roundtrip():
-    ax.arborx_set_tuning(block=64, stack=8, quantized_nodes=1)
+    ax.arborx_set_tuning(block=64, stack=8, node_format=1)
     try:
-        assert ax.arborx_get_tuning() == dict(block=64, order=1, stack=8, schedule=0, build=0, seed_mode=0, quantized_nodes=1)
+        assert ax.arborx_get_tuning() == dict(block=64, order=1, stack=8, schedule=0, build=0, seed_mode=0, node_format=1)
         ax.arborx_set_tuning_op(ax.OP_KNN, block=128, seed_mode=1)
         assert ax.arborx_get_tuning_op(ax.OP_KNN)["seed_mode"] == 1
-        assert ax.arborx_get_tuning_op(ax.OP_KNN)["quantized_nodes"] == 0
-        assert ax.arborx_get_tuning_op(ax.OP_REDUCE)["quantized_nodes"] == 1
+        assert ax.arborx_get_tuning_op(ax.OP_KNN)["node_format"] == 0
+        assert ax.arborx_get_tuning_op(ax.OP_REDUCE)["node_format"] == 1
     finally:
         ax.arborx_reset_tuning()

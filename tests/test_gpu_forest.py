@@ -56,8 +56,10 @@ def run_forest(f, cfg, k):
     return fo, host(c), host(s), host(c0), host(d2), host(ix)
 
 
-@pytest.mark.parametrize("k,tuning", [(1, {}), (8, {}), (16, {}), (1, dict(quantized_nodes=1)),
-                                      (8, dict(quantized_nodes=1)), (8, dict(seed_mode=2)), (16, dict(seed_mode=1))])
+@pytest.mark.parametrize("k,tuning", [(1, {}), (8, {}), (16, {}), (1, dict(node_format=1)),
+                                      (8, dict(node_format=1)), (8, dict(seed_mode=2)), (16, dict(seed_mode=1)),
+                                      (1, dict(node_format=2)), (8, dict(node_format=2)),
+                                      (16, dict(node_format=2, seed_mode=2))])
 def test_forest_vs_oracle(k, tuning):
     cfg = small_forest(k)
     ax.arborx_set_tuning(**tuning)  # before the build: it decides what is stored

@@ -353,15 +353,16 @@ def test_capacity_protocol():
     assert total.value == o_off[-1] and np.array_equal(host(off), o_off)
 
 
-@pytest.mark.parametrize("block,order,stack,schedule,quantized_nodes",
+@pytest.mark.parametrize("block,order,stack,schedule,node_format",
                          [(64, 1, 1, 0, 0), (128, 0, 2, 0, 0), (256, 1, 4, 0, 0), (256, 0, 64, 0, 0), (64, 0, 16, 0, 0),
                           (64, 1, 1, 0, 1), (256, 0, 64, 0, 1), (128, 1, 16, 0, 1),
+                          (64, 1, 1, 0, 2), (256, 0, 64, 0, 2), (128, 1, 16, 0, 2), (256, 1, 4, 1, 2), (64, 1, 8, 2, 2),
                           (256, 1, 16, 1, 0), (64, 0, 16, 1, 0), (128, 1, 4, 1, 0),
                           (256, 1, 16, 2, 0), (64, 0, 16, 2, 0)])
-def test_schedules_identical(block, order, stack, schedule, quantized_nodes):
+def test_schedules_identical(block, order, stack, schedule, node_format):
     cfg = inputs.config_small(n=20_000, m=4000)
     data, q, r = cfg["data"], cfg["queries"], cfg["radius"]
-    ax.arborx_set_tuning(block=block, order=order, stack=stack, schedule=schedule, quantized_nodes=quantized_nodes)
+    ax.arborx_set_tuning(block=block, order=order, stack=stack, schedule=schedule, node_format=node_format)
     try:
         t = ax.arborx_bvh_build(dev(data))
         check_spatial(t, data, q, r)
@@ -449,11 +450,12 @@ def test_knn_seeding_off_identical(k):
     t = ax.arborx_bvh_build(dev(s["data"]))
     check_knn(t, s["data"], s["queries"], k)
     for kw in (dict(seed_mode=1), dict(seed_mode=2), dict(schedule=1), dict(schedule=1, seed_mode=1),
-               dict(schedule=1, seed_mode=2), dict(schedule=2), dict(quantized_nodes=1),
-               dict(quantized_nodes=1, seed_mode=1), dict(quantized_nodes=1, seed_mode=2)):
+               dict(schedule=1, seed_mode=2), dict(schedule=2), dict(node_format=1),
+               dict(node_format=1, seed_mode=1), dict(node_format=1, seed_mode=2), dict(node_format=2),
+               dict(node_format=2, seed_mode=1), dict(node_format=2, seed_mode=2)):
         ax.arborx_set_tuning(**kw)
         try:
-            if "quantized_nodes" in kw:
+            if "node_format" in kw:  # the format is stored when the tree is built
                 t = ax.arborx_bvh_build(dev(s["data"]))
             check_knn(t, s["data"], s["queries"], k)
             check_spatial(t, s["data"], s["queries"], 0.01)
@@ -462,8 +464,8 @@ def test_knn_seeding_off_identical(k):
 
 
 def _both_node_forms(build, fn):
-    for qn in (0, 1):
-        ax.arborx_set_tuning(quantized_nodes=qn)
+    for fmt in (0, 1, 2):
+        ax.arborx_set_tuning(node_format=fmt)
         try:
             fn(build())
         finally:
@@ -515,17 +517,36 @@ def test_quantized_boxes_and_dims():
     _both_node_forms(lambda: ax.arborx_bvh_build(dev(boxes), kind=ax.BOXES), run_boxes)
 
 
-def test_quantized_request_needs_quantized_build():
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_node_format_request_needs_that_build(fmt):
     cfg = inputs.config_small(n=3000, m=200)
     t = ax.arborx_bvh_build(dev(cfg["data"]))
-    ax.arborx_set_tuning(quantized_nodes=1)
+    ax.arborx_set_tuning(node_format=fmt)
     try:
-        with pytest.raises(ax.ArborXError, match="built without quantized nodes"):
+        with pytest.raises(ax.ArborXError, match="built without"):
             ax.arborx_query_knn(t, dev(cfg["queries"]), 4)
-        with pytest.raises(ax.ArborXError, match="built without quantized nodes"):
+        with pytest.raises(ax.ArborXError, match="built without"):
             ax.arborx_query_spatial_reduce(t, dev(cfg["queries"]), 0.05, ax.COUNT)
         t2 = ax.arborx_bvh_build(dev(cfg["data"]))
         check_knn(t2, cfg["data"], cfg["queries"], 4)
     finally:
         ax.arborx_reset_tuning()
     check_knn(t2, cfg["data"], cfg["queries"], 4)  # float nodes are always there
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7, 64, 65, 1000])
+def test_four_wide_small_trees_and_duplicates(n):
+    g = np.random.default_rng(100 + n)
+    data = g.random((n, 3)).astype(np.float32)
+    data[n // 2:] = data[0]  # duplicates
+    q = np.concatenate([data[:3], g.random((200, 3)).astype(np.float32)])
+    ax.arborx_set_tuning(node_format=2)
+    try:
+        t = ax.arborx_bvh_build(dev(data))
+        for r in (0.0, 0.3, float("inf")):
+            check_spatial(t, data, q, r)
+        check_knn(t, data, q, min(5, n))
+        check_knn(t, data, q, 9)
+        check_reduce(t, data, q, 0.3)
+    finally:
+        ax.arborx_reset_tuning()
