@@ -40,6 +40,13 @@ struct StreamUses {
             (void)hipStreamSynchronize(s);
         }
     }
+    // Make `to` wait for every recorded use so far.
+    void wait(hipStream_t to)
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        for (auto &u : ev)
+            (void)hipStreamWaitEvent(to, u.second, 0);
+    }
     // Make `to` wait for every recorded use, then drop the events.
     void wait_all(hipStream_t to)
     {
@@ -59,10 +66,25 @@ struct NoteUse {
     ~NoteUse() { u.note(s); }
 };
 
+// The traversal order of the last query array a tree was asked about,
+// identified by its address, length, predicate kind and order mode.  A
+// repeated call reuses it; a changed array under the same address only makes
+// the reused order less coherent, never the results different, because any
+// permutation of the queries is a valid traversal order.
+struct OrderCache {
+    std::mutex mu;
+    const float *queries = nullptr;
+    int64_t m = -1;
+    int pred = -1, mode = 0;
+    uint32_t *perm = nullptr;
+    hipEvent_t ready = nullptr;
+};
+
 struct arborx_tree_s {
     ax::TreeDev dev;
     hipEvent_t ready = nullptr;
     StreamUses uses;
+    OrderCache order;
 };
 
 struct arborx_forest_s {
@@ -245,9 +267,55 @@ static void release_tree(arborx_tree t)
     dfree(t->dev.wnodes, rs);
     dfree(t->dev.leaves, rs);
     dfree(t->dev.hdr, rs);
+    if (t->order.ready)
+        (void)hipStreamWaitEvent(rs, t->order.ready, 0);
+    dfree(t->order.perm, rs);
+    if (t->order.ready)
+        (void)hipEventDestroy(t->order.ready);
     if (t->ready)
         (void)hipEventDestroy(t->ready);
     delete t;
+}
+
+// Traversal order for a query call on tree t: the cached one when the call
+// repeats the last query array, else a new one that replaces it.
+static arborx_status tree_order(arborx_tree t, const float *queries, int64_t m, Pred pred, int op, uint32_t **perm,
+                                Temps &tmp, hipStream_t s)
+{
+    *perm = nullptr;
+    const int mode = tuning(op).order;
+    if (!mode || t->dev.n == 0 || m <= 1)
+        return ARBORX_OK;
+    OrderCache &oc = t->order;
+    std::lock_guard<std::mutex> lock(oc.mu);
+    if (oc.perm && oc.queries == queries && oc.m == m && oc.pred == (int)pred && oc.mode == mode) {
+        AX_HIP(hipStreamWaitEvent(s, oc.ready, 0));
+        *perm = oc.perm;
+        return ARBORX_OK;
+    }
+    uint32_t *fresh = nullptr, *keep = nullptr;
+    arborx_status st = query_order(t->dev, queries, m, pred, op, &fresh, tmp, s);
+    if (st != ARBORX_OK || !fresh)
+        return st;
+    if ((st = dalloc((void **)&keep, (size_t)m * sizeof(uint32_t), s)) != ARBORX_OK)
+        return st;
+    AX_HIP(hipMemcpyAsync(keep, fresh, (size_t)m * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    if (!oc.ready)
+        AX_HIP(hipEventCreateWithFlags(&oc.ready, hipEventDisableTiming));
+    if (oc.perm) {  // release the old order after every use of the tree so far
+        hipStream_t rs = release_stream();
+        (void)hipStreamWaitEvent(rs, oc.ready, 0);
+        t->uses.wait(rs);
+        dfree(oc.perm, rs);
+    }
+    AX_HIP(hipEventRecord(oc.ready, s));
+    oc.queries = queries;
+    oc.m = m;
+    oc.pred = (int)pred;
+    oc.mode = mode;
+    oc.perm = keep;
+    *perm = keep;
+    return ARBORX_OK;
 }
 
 static arborx_status wait_tree(arborx_tree t, hipStream_t s)
@@ -473,7 +541,7 @@ static arborx_status csr_begin(arborx_tree t, Pred pred, const float *queries, i
         (st = p->tmp.get(&p->big_list, mm)) != ARBORX_OK || (st = p->tmp.get(&p->huge_list, mm)) != ARBORX_OK ||
         (st = p->tmp.get(&sws, scan_workspace_bytes(m))) != ARBORX_OK)
         return bail(st);
-    if ((st = query_order(t->dev, queries, m, pred, OP_SPATIAL, &p->perm, p->tmp, s)) != ARBORX_OK)
+    if ((st = tree_order(t, queries, m, pred, OP_SPATIAL, &p->perm, p->tmp, s)) != ARBORX_OK)
         return bail(st);
     if ((st = spatial_count(t->dev, pred, queries, m, radius, p->perm, p->counts, p->ordered_counts, p->stash, s)) !=
         ARBORX_OK)
@@ -491,6 +559,7 @@ static arborx_status csr_begin(arborx_tree t, Pred pred, const float *queries, i
     if (e != hipSuccess)
         return bail(hip_fail(e, "reading the match total"));
     *total = (int64_t)p->h.total;
+    p->perm = nullptr;  // the tree's cached order may be replaced once this call returns
     *out = p;
     return ARBORX_OK;
 }
@@ -507,7 +576,7 @@ static arborx_status csr_finish(arborx_plan p, int32_t *indices, int64_t capacit
     if (p->h.total == 0)
         return ARBORX_OK;
     NoteUse note_use{p->tree->uses, p->stream};
-    arborx_status st = spatial_fill(p->tree->dev, p->pred, p->queries, p->m, p->radius, p->perm, p->counts, p->stash,
+    arborx_status st = spatial_fill(p->tree->dev, p->pred, p->queries, p->m, p->radius, p->counts, p->stash,
                                     p->offsets, p->big_list, (int64_t)p->h.big_rows, p->huge_list,
                                     (int64_t)p->h.huge_rows, indices, p->stream);
     if (st != ARBORX_OK)
@@ -589,7 +658,7 @@ arborx_status arborx_query_knn(arborx_tree t, const float *queries, int64_t m, i
     NoteUse note_use{t->uses, s};
     Temps tmp(s);
     uint32_t *perm = nullptr;
-    if ((st = query_order(t->dev, queries, m, Pred::Sphere, OP_KNN, &perm, tmp, s)) != ARBORX_OK)
+    if ((st = tree_order(t, queries, m, Pred::Sphere, OP_KNN, &perm, tmp, s)) != ARBORX_OK)
         return st;
     return knn_query(t->dev, queries, m, k, perm, dist2, indices, s);
 }
@@ -618,7 +687,7 @@ arborx_status arborx_query_spatial_reduce(arborx_tree t, const float *queries, i
     NoteUse note_use{t->uses, s};
     Temps tmp(s);
     uint32_t *perm = nullptr;
-    if ((st = query_order(t->dev, queries, m, Pred::Sphere, OP_REDUCE, &perm, tmp, s)) != ARBORX_OK)
+    if ((st = tree_order(t, queries, m, Pred::Sphere, OP_REDUCE, &perm, tmp, s)) != ARBORX_OK)
         return st;
     return spatial_reduce(t->dev, queries, m, radius, op, scale_bits, perm, counts, sum_fixed, s);
 }

@@ -641,7 +641,7 @@ arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, i
 }
 
 arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
-                           const uint32_t *perm, const int32_t *counts, const int32_t *stash,
+                           const int32_t *counts, const int32_t *stash,
                            const int64_t *offsets, const int32_t *big_list, int64_t nbig, const int32_t *huge_list,
                            int64_t nhuge, int32_t *indices, hipStream_t s)
 {

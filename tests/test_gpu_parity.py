@@ -409,6 +409,39 @@ def test_destroy_with_queries_in_flight():
     assert np.array_equal(host(c2), oc2)
 
 
+def test_query_order_cache():
+    # the tree reuses the traversal order of a repeated query array; results
+    # never depend on it, also when the array changes in place
+    cfg = inputs.config_small(n=30_000, m=8000)
+    data, r = cfg["data"], cfg["radius"]
+    t = ax.arborx_bvh_build(dev(data))
+    qa = cfg["queries"]
+    qb = np.random.default_rng(21).random((8000, 3)).astype(np.float32)
+    q = dev(qa)
+    check_reduce(t, data, qa, r)
+    c, _ = ax.arborx_query_spatial_reduce(t, q, r, ax.COUNT)            # same array: reused order
+    assert np.array_equal(host(c), oracle.reduce(data, qa, r)[0])
+    q.copy_(dev(qb))                                                    # same address, new contents
+    c, s = ax.arborx_query_spatial_reduce(t, q, r, ax.COUNT_SUMDIST)
+    oc, os_ = oracle.reduce(data, qb, r)
+    assert np.array_equal(host(c), oc) and np.array_equal(host(s), os_)
+    d2, ix = ax.arborx_query_knn(t, q, 6)
+    o_d2, o_ix = oracle.knn(data, qb, 6)
+    assert np.array_equal(host(ix), o_ix) and np.array_equal(host(d2), o_d2)
+    off, idx = ax.arborx_query_spatial(t, q, r)
+    o_off, o_idx = oracle.spatial(data, qb, r)
+    assert np.array_equal(host(off), o_off) and np.array_equal(host(idx), o_idx)
+    side = torch.cuda.Stream()                                          # another stream, alternating arrays
+    q2 = dev(qa)
+    with torch.cuda.stream(side):
+        for qq, ref in ((q2, qa), (q, qb), (q2, qa)):
+            c, _ = ax.arborx_query_spatial_reduce(t, qq, r, ax.COUNT, stream=side)
+            side.synchronize()
+            assert np.array_equal(host(c), oracle.reduce(data, ref, r)[0])
+    ax.arborx_bvh_destroy(t)
+    torch.cuda.synchronize()
+
+
 def test_plan_api_two_calls():
     import ctypes
     from paper_2507_23700_amd import _lib
