@@ -526,7 +526,7 @@ __global__ void widen_nodes(const Node<D> *__restrict__ nodes, int n_nodes, Node
 }
 
 template <int D>
-__global__ __launch_bounds__(kBuildBlock) void hierarchy_chunk_kernel(const uint64_t *__restrict__ codes,
+__global__ __launch_bounds__(chunk_leaves<D>()) void hierarchy_chunk_kernel(const uint64_t *__restrict__ codes,
                                                                       const uint32_t *__restrict__ ids,
                                                                       const float *__restrict__ values, int kind,
                                                                       int n, Node<D> *__restrict__ nodes,
@@ -542,22 +542,23 @@ __global__ __launch_bounds__(kBuildBlock) void hierarchy_chunk_kernel(const uint
     __shared__ float s_lo[C][2][D], s_hi[C][2][D];  // both child slots of each local split
     __shared__ int32_t s_ref[C][2];
 
+    // one thread per leaf of the chunk, so every climb of the chunk runs at once
     const int cs = blockIdx.x * C;
     const int ce = min(n, cs + C);
     const int tid = threadIdx.x;
-    for (int j = tid; j < C; j += kBuildBlock)
+    for (int j = tid; j < C; j += C)
         s_flag[j] = 0;
-    for (int j = tid; j <= C; j += kBuildBlock) {
+    for (int j = tid; j <= C; j += C) {
         const int g = cs - 1 + j;
         s_key[j] = (g >= 0 && g <= ce - 1 && g <= n - 2) ? split_key(codes, g) : 0ull;
     }
-    for (int j = cs + tid; j < ce && j <= n - 2; j += kBuildBlock)
+    for (int j = cs + tid; j < ce && j <= n - 2; j += C)
         gflags[j] = 0;
     if (tid < 2)
         escapes[2 * blockIdx.x + tid].valid = 0;
     __syncthreads();
 
-    for (int i = cs + tid; i < ce; i += kBuildBlock) {
+    for (int i = cs + tid; i < ce; i += C) {
         const uint32_t id = ids[i];
         if (id >= (uint32_t)n)
             continue;
@@ -644,7 +645,7 @@ __global__ __launch_bounds__(kBuildBlock) void hierarchy_chunk_kernel(const uint
     }
     __syncthreads();
     // splits with a single arrival: publish that child's slot for phase 2
-    for (int lp = tid; lp <= ce - 2 - cs; lp += kBuildBlock) {
+    for (int lp = tid; lp <= ce - 2 - cs; lp += C) {
         const unsigned long long w = s_flag[lp];
         if (w != 0 && w != kDone) {
             const int side = (int)(w >> 48);
@@ -820,7 +821,7 @@ arborx_status build_impl(const float *values, int64_t n, int kind, TreeDev &t, h
         if ((st = tmp.get(&esc, (size_t)2 * chunks)) != ARBORX_OK)
             return st;
         ProfScope ps("build_hierarchy", s);
-        hierarchy_chunk_kernel<D><<<chunks, kBuildBlock, 0, s>>>(codes, ids, values, kind, (int)n, nodes, t.leaves,
+        hierarchy_chunk_kernel<D><<<chunks, C, 0, s>>>(codes, ids, values, kind, (int)n, nodes, t.leaves,
                                                                  flags, esc, nullptr, 0, t.hdr);
         if (chunks > 1)
             hierarchy_top_kernel<D><<<grid_for(2 * chunks, kBuildBlock), kBuildBlock, 0, s>>>(
@@ -1074,7 +1075,7 @@ arborx_status forest_build_impl(const float *values, const int64_t *seg_host, in
         return st;
     Node<D> *nodes = static_cast<Node<D> *>(f.nodes);
     ProfScope ps("build_hierarchy", s);
-    hierarchy_chunk_kernel<D><<<chunks, kBuildBlock, 0, s>>>(codes, ids, values, kind, (int)n, nodes, f.leaves, flags,
+    hierarchy_chunk_kernel<D><<<chunks, C, 0, s>>>(codes, ids, values, kind, (int)n, nodes, f.leaves, flags,
                                                              esc, f.seg, T, f.hdrs);
     if (chunks > 1)
         hierarchy_top_kernel<D><<<grid_for(2 * chunks, kBuildBlock), kBuildBlock, 0, s>>>(
