@@ -73,8 +73,8 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel, workload):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they match this source."""
+def profiled(kernel, workload, field):
+    """A per-launch figure from committed rocprofv3 counter runs, if they match this source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -83,7 +83,12 @@ def traffic_for(kernel, workload):
     e = t.get(workload, {}).get(kernel)
     if not e or e.get("source_hash") != source_hash():
         return None
-    return e.get("bytes_per_launch")
+    return e.get(field)
+
+
+def traffic_for(kernel, workload):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    return profiled(kernel, workload, "bytes_per_launch")
 
 
 KERNEL_PHASE = [  # rocprofv3 kernel name fragment -> phase name used by the in-library profiler
@@ -94,10 +99,14 @@ KERNEL_PHASE = [  # rocprofv3 kernel name fragment -> phase name used by the in-
 ]
 
 
-def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, stats_csv, workload, copy_bytes):
+def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, stats_csv, workload, copy_bytes,
+                       sq_csv=None):
     """Per-phase HBM bytes per launch from rocprofv3 --pmc runs, scaled by what the same
-    counters read for a plain device copy of copy_bytes bytes.  Writes profiles/traffic.json
-    and returns a markdown table."""
+    counters read for a plain device copy of copy_bytes bytes; with sq_csv (SQ_INSTS_VALU and
+    SQ_BUSY_CYCLES), the fraction of vector-ALU issue slots used: each shader engine's 32
+    SIMDs issue one wave64 VALU instruction per 4 cycles, 8 per SE-cycle, and SQ_BUSY_CYCLES
+    sums the busy cycles over the SEs.  Writes profiles/traffic.json and returns a markdown
+    table."""
     import collections
     import csv
 
@@ -127,6 +136,10 @@ def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, sta
     write, wl = per_dispatch(write_csv, "WRITE_SIZE")
     hit, _ = per_dispatch(write_csv, "TCC_HIT_sum")
     miss, _ = per_dispatch(write_csv, "TCC_MISS_sum")
+    valu, busy = {}, {}
+    if sq_csv:
+        valu, _ = per_dispatch(sq_csv, "SQ_INSTS_VALU")
+        busy, _ = per_dispatch(sq_csv, "SQ_BUSY_CYCLES")
     dur = collections.defaultdict(list)
     for r in csv.DictReader(open(stats_csv)):
         ph = phase(r["Name"])
@@ -134,8 +147,8 @@ def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, sta
             dur[ph].append((float(r["AverageNs"]), int(r["Calls"])))
     src = source_hash()
     table = {}
-    lines = [f"| phase | launches | avg ms (kernel trace) | HBM read MB/launch | HBM write MB/launch | L2 hit |",
-             "|---|---|---|---|---|---|"]
+    lines = [f"| phase | launches | avg ms (kernel trace) | HBM read MB/launch | HBM write MB/launch | L2 hit |"
+             f" VALU busy |", "|---|---|---|---|---|---|---|"]
     for ph in sorted(fetch, key=lambda k: -fetch[k]):
         if ph not in dict(KERNEL_PHASE).values():
             continue
@@ -144,9 +157,11 @@ def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, sta
         wr = write.get(ph, 0.0) * wscale / max(len(wl.get(ph, ())), 1)
         h = hit.get(ph, 0.0) / max(hit.get(ph, 0.0) + miss.get(ph, 0.0), 1e-9)
         ms = sum(a * c for a, c in dur[ph]) / max(sum(c for _, c in dur[ph]), 1) / 1e6 if dur[ph] else float("nan")
+        vb = valu[ph] / (busy[ph] * 8.0) if busy.get(ph) else None  # both summed over the phase's launches
         table[ph] = {"bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr, "l2_hit": h,
-                     "source_hash": src}
-        lines.append(f"| {ph} | {nl} | {ms:.3f} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | {h:.3f} |")
+                     "valu_busy": vb, "source_hash": src}
+        lines.append(f"| {ph} | {nl} | {ms:.3f} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | {h:.3f} | "
+                     f"{'%.2f' % vb if vb is not None else '-'} |")
     path = os.path.join(ROOT, "profiles", "traffic.json")
     allw = json.load(open(path)) if os.path.exists(path) else {}
     allw[workload] = table
@@ -299,14 +314,18 @@ def main():
     ap.add_argument("--no-chamfer", action="store_true", help="skip the Chamfer timing")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of GIB gibibytes (counter calibration) and exit")
-    ap.add_argument("--summarize-counters", nargs=5, metavar=("FETCH", "WRITE", "COPYFETCH", "COPYWRITE", "STATS"),
-                    help="turn rocprofv3 counter CSVs into profiles/traffic.json and print a markdown table")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="CSV",
+                    help="FETCH WRITE COPYFETCH COPYWRITE STATS [SQ]: turn rocprofv3 counter CSVs into "
+                         "profiles/traffic.json and print a markdown table")
     args = ap.parse_args()
     if args.summarize_counters:
         n0 = args.n or {"gmm6": 2_000_000, "small": 20_000}.get(args.dist, 10_000_000)
         wl = f"gmm6d_n{n0}_m{n0}" if args.dist == "gmm6" else f"{'cube' if args.dist == 'small' else args.dist}3d_n{n0}_m{n0}"
-        print(summarize_counters(*args.summarize_counters, workload=wl,
-                                 copy_bytes=2 ** 30))
+        if len(args.summarize_counters) not in (5, 6):
+            ap.error("--summarize-counters takes FETCH WRITE COPYFETCH COPYWRITE STATS [SQ]")
+        csvs = args.summarize_counters
+        print(summarize_counters(*csvs[:5], workload=wl, copy_bytes=2 ** 30,
+                                 sq_csv=csvs[5] if len(csvs) == 6 else None))
         return
     if args.calibrate_copy > 0:
         import torch
@@ -406,6 +425,7 @@ def main():
     achieved = alg / (avg_ms * 1e-3) / 1e9
     roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom, cfg["workload"]),
+                "valu_busy": profiled(dom, cfg["workload"], "valu_busy"),
                 "algorithmic_bytes_per_launch": alg, "avg_launch_ms": avg_ms}
 
     cpu = None

@@ -780,7 +780,11 @@ arborx_status build_impl(const float *values, int64_t n, int kind, TreeDev &t, h
     uint32_t *ids, *ids2;
     unsigned long long *flags;
     uint8_t *ws;
-    if ((st = tmp.get(&partial, (size_t)pblocks * 2 * D)) != ARBORX_OK || (st = tmp.get(&codes, n)) != ARBORX_OK ||
+    // the sorted codes stay with the tree: kNN finds a query's leaf position by binary search
+    if ((st = dalloc((void **)&t.codes, (size_t)n * sizeof(uint64_t), s)) != ARBORX_OK)
+        return st;
+    codes = t.codes;
+    if ((st = tmp.get(&partial, (size_t)pblocks * 2 * D)) != ARBORX_OK ||
         (st = tmp.get(&codes2, n)) != ARBORX_OK || (st = tmp.get(&ids, n)) != ARBORX_OK ||
         (st = tmp.get(&ids2, n)) != ARBORX_OK || (st = tmp.get(&flags, nn)) != ARBORX_OK ||
         (st = tmp.get(&ws, radix_workspace_bytes(n))) != ARBORX_OK)
@@ -803,8 +807,8 @@ arborx_status build_impl(const float *values, int64_t n, int kind, TreeDev &t, h
         ProfScope ps("build_sort", s);
         AX_HIP(radix_sort_pairs<uint64_t>(codes, ids, codes2, ids2, n, 0, (63 / D) * D, ws, s, &alt));
     }
-    if (alt) {
-        codes = codes2;
+    if (alt) {  // an odd number of passes (none for the dimensions compiled in): keep the result in t.codes
+        AX_HIP(hipMemcpyAsync(t.codes, codes2, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
         ids = ids2;
     }
     Node<D> *nodes = static_cast<Node<D> *>(t.nodes);

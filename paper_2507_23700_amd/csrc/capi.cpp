@@ -265,6 +265,7 @@ static void release_tree(arborx_tree t)
     dfree(t->dev.nodes, rs);
     dfree(t->dev.qnodes, rs);
     dfree(t->dev.wnodes, rs);
+    dfree(t->dev.codes, rs);
     dfree(t->dev.leaves, rs);
     dfree(t->dev.hdr, rs);
     if (t->order.ready)

@@ -162,9 +162,9 @@ __global__ __launch_bounds__(kForestBlock) void k_forest_knn(
         if (FMT == 1)
             knn_search_q<D, K>(qnodes, n_nodes, leaves, kind, h, q, best, st, seed);
         else if (FMT == 2)
-            knn_search4<D, K>(nodes, wnodes, n_nodes, leaves, kind, h, q, best, st, seed);
+            knn_search4<D, K>(nodes, wnodes, n_nodes, leaves, kind, h, q, best, st, seed, nullptr);
         else
-            knn_search<D, K>(nodes, n_nodes, leaves, kind, h, q, best, st, seed);
+            knn_search<D, K>(nodes, n_nodes, leaves, kind, h, q, best, st, seed, nullptr);
         best.store(k_out, out_d2 + qi * k_out, out_idx + qi * k_out, h.start);  // indices local to the tree
     }
 }

@@ -143,6 +143,7 @@ struct TreeDev {
     void *nodes = nullptr;  // Node<dim>[max(n-1, 1)]
     void *qnodes = nullptr; // QNode<dim>[max(n-1, 1)]: the same tree with 16-bit child boxes
     void *wnodes = nullptr; // Node4<dim>[max(n-1, 1)]: the same tree two levels per node
+    uint64_t *codes = nullptr;  // [n] sorted Morton codes of the leaves (the build's sort keys)
     float *leaves = nullptr; // n leaf records in sorted order (see leaf_floats)
     TreeHeader *hdr = nullptr;
 };

@@ -311,7 +311,7 @@ __global__ void k_spatial_reduce(const Node<D> *__restrict__ nodes, const QNode<
 
 template <int D, int K, bool WAVE, int FMT>
 __global__ void k_knn(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
-                      const Node4<D> *__restrict__ wnodes, int n_nodes,
+                      const Node4<D> *__restrict__ wnodes, const uint64_t *__restrict__ codes, int n_nodes,
                       const float *__restrict__ leaves, int kind,
                       const TreeHeader *__restrict__ hdr, const float *__restrict__ queries, int64_t m, int k_out,
                       const uint32_t *__restrict__ perm, float *__restrict__ out_d2, int32_t *__restrict__ out_idx,
@@ -339,9 +339,9 @@ __global__ void k_knn(const Node<D> *__restrict__ nodes, const QNode<D> *__restr
         if (FMT == 1)
             knn_search_q<D, K>(qnodes, n_nodes, leaves, kind, *hdr, q, best, st, seed);
         else if (FMT == 2)
-            knn_search4<D, K>(nodes, wnodes, n_nodes, leaves, kind, *hdr, q, best, st, seed);
+            knn_search4<D, K>(nodes, wnodes, n_nodes, leaves, kind, *hdr, q, best, st, seed, codes);
         else
-            knn_search<D, K>(nodes, n_nodes, leaves, kind, *hdr, q, best, st, seed);
+            knn_search<D, K>(nodes, n_nodes, leaves, kind, *hdr, q, best, st, seed, codes);
     }
     if (active)
         best.store(k_out, out_d2 + qi * k_out, out_idx + qi * k_out, 0);
@@ -547,8 +547,8 @@ arborx_status knn_launch(const TreeDev &t, const float *q, int64_t m, int k, con
     const int seed = tuning(OP_KNN).seed;
     ProfScope ps("knn", s);
 #define AX_KNN(W, F)                                                                                              \
-    k_knn<D, K, W, F><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, wnodes, tree_nodes(t), t.leaves, t.kind, t.hdr, q, m, \
-                                                     k, perm, d2, idx, L.cap, seed)
+    k_knn<D, K, W, F><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, wnodes, t.codes, tree_nodes(t), t.leaves, t.kind,  \
+                                                     t.hdr, q, m, k, perm, d2, idx, L.cap, seed)
     if (wave)
         AX_KNN(true, 0);
     else if (fmt == 1)

@@ -482,6 +482,31 @@ __device__ __forceinline__ float leaf_d2(const float *__restrict__ leaves, int k
     return box_d2<D>(q, lo, hi);
 }
 
+// Position of q among the sorted leaves of the tree of hdr: the first leaf
+// whose Morton code (the build's, on the tree's bounds) is not below q's,
+// found by binary search over the kept codes, clamped to the tree.
+template <int D>
+__device__ __forceinline__ int leaf_position(const uint64_t *__restrict__ codes, const TreeHeader &hdr, const float *q)
+{
+    constexpr int bits = 63 / D;
+    uint32_t c[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const float ext = hdr.hi[d] - hdr.lo[d];
+        c[d] = quantise(q[d], hdr.lo[d], ext > 0.0f ? 1.0f / ext : 0.0f, bits);
+    }
+    const uint64_t key = interleave<D>(c, bits);
+    int lo = hdr.start, hi = hdr.start + hdr.n;  // first code >= key in [lo, hi)
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (codes[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo < hdr.start + hdr.n ? lo : hdr.start + hdr.n - 1;
+}
+
 // Starting bound for the kNN walk from the sorted leaves around position pos
 // (where a greedy descent towards q ends).  mode 0: the k-th smallest distance
 // among the 2k leaves around pos; mode 2: the largest distance among the k
@@ -528,14 +553,14 @@ template <int D, int K>
 __device__ __forceinline__ void knn_search(const Node<D> *__restrict__ nodes, int n_nodes,
                                            const float *__restrict__ leaves, int kind, const TreeHeader &hdr,
                                            const float *q, TopK<K> &best, ShortStack<KnnEntry> &st,
-                                           int seed)
+                                           int seed, const uint64_t *__restrict__ codes)
 {
     const int n = hdr.n;
 best.reset(INFINITY);
     if (n <= 0)
         return;
     if (seed != 1 && n >= K) {
-        int cur = hdr.root, pos = hdr.start;
+        int cur = codes ? -1 : hdr.root, pos = codes ? leaf_position<D>(codes, hdr, q) : hdr.start;
         for (int iter = 0; iter <= n_nodes; ++iter) {
             if ((unsigned)cur >= (unsigned)n_nodes)
                 break;
@@ -621,14 +646,14 @@ template <int D, int K>
 __device__ __forceinline__ void knn_search4(const Node<D> *__restrict__ nodes, const Node4<D> *__restrict__ wnodes,
                                             int n_nodes, const float *__restrict__ leaves, int kind,
                                             const TreeHeader &hdr, const float *q, TopK<K> &best,
-                                            ShortStack<KnnEntry> &st, int seed)
+                                            ShortStack<KnnEntry> &st, int seed, const uint64_t *__restrict__ codes)
 {
     const int n = hdr.n;
     best.reset(INFINITY);
     if (n <= 0)
         return;
     if (seed != 1 && n >= K) {
-        int cur = hdr.root, pos = hdr.start;
+        int cur = codes ? -1 : hdr.root, pos = codes ? leaf_position<D>(codes, hdr, q) : hdr.start;
         for (int iter = 0; iter <= n_nodes; ++iter) {
             if ((unsigned)cur >= (unsigned)n_nodes)
                 break;
