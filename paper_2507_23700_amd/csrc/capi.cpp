@@ -538,7 +538,7 @@ static arborx_status csr_begin(arborx_tree t, Pred pred, const float *queries, i
     const int64_t mm = m > 0 ? m : 1;
     if ((st = p->tmp.get(&qh, 1)) != ARBORX_OK || (st = p->tmp.get(&p->counts, mm)) != ARBORX_OK ||
         (st = p->tmp.get(&p->ordered_counts, mm)) != ARBORX_OK ||
-        (st = p->tmp.get(&p->stash, mm * kRowSortRegs)) != ARBORX_OK ||
+        (st = p->tmp.get(&p->stash, mm * stash_regs(t->dev.dim))) != ARBORX_OK ||
         (st = p->tmp.get(&p->big_list, mm)) != ARBORX_OK || (st = p->tmp.get(&p->huge_list, mm)) != ARBORX_OK ||
         (st = p->tmp.get(&sws, scan_workspace_bytes(m))) != ARBORX_OK)
         return bail(st);
@@ -549,7 +549,8 @@ static arborx_status csr_begin(arborx_tree t, Pred pred, const float *queries, i
         return bail(st);
     {
         ProfScope ps("scan", s);
-        hipError_t e = csr_offsets_lists(p->counts, p->ordered_counts, p->perm, m, offsets, p->big_list, p->huge_list,
+        hipError_t e = csr_offsets_lists(p->counts, p->ordered_counts, p->perm, m, stash_regs(t->dev.dim), offsets,
+                                         p->big_list, p->huge_list,
                                          qh, sws, s);
         if (e != hipSuccess)
             return bail(hip_fail(e, "csr_offsets_lists"));

@@ -30,7 +30,7 @@ struct TreeHeader {
 // Device-resident per-call header of a CSR query, written by the scan.
 struct QueryHeader {
     unsigned long long total;      // offsets[m]
-    unsigned long long big_rows;   // rows with kRowSortRegs < len <= kRowSortBlock
+    unsigned long long big_rows;   // rows with stash_regs(dim) < len <= kRowSortBlock
     unsigned long long huge_rows;  // rows with len > kRowSortBlock
     unsigned long long pad;
 };
@@ -125,14 +125,14 @@ size_t scan_workspace_bytes(int64_t n);
 // offsets[0..m] = exclusive scan of counts; also writes offsets[m] to *total_dev.
 hipError_t csr_offsets(const int32_t *counts, int64_t m, int64_t *offsets, int64_t *total_dev, void *workspace,
                        hipStream_t s);
-// As csr_offsets, and also lists the rows longer than kRowSortRegs (big_list,
+// As csr_offsets, and also lists the rows longer than `regs` (big_list,
 // up to kRowSortBlock) and longer than kRowSortBlock (huge_list); totals go to
 // *qh.  With `order` (position -> row, e.g. the traversal order of the
 // queries) and ordered_counts[i] = counts[order[i]], the lists follow that
 // order, so a second walk over them stays coherent; else row order.  Lists
 // need room for m entries.
 hipError_t csr_offsets_lists(const int32_t *counts, const int32_t *ordered_counts, const uint32_t *order, int64_t m,
-                             int64_t *offsets, int32_t *big_list, int32_t *huge_list, QueryHeader *qh,
+                             int regs, int64_t *offsets, int32_t *big_list, int32_t *huge_list, QueryHeader *qh,
                              void *workspace, hipStream_t s);
 
 // ---- build (build.hip) ----------------------------------------------------
@@ -190,8 +190,8 @@ arborx_status chamfer_backward(const float *a, const int64_t *a_off, const float
 enum class Pred { Sphere, Box };
 arborx_status query_order(const TreeDev &t, const float *queries, int64_t m, Pred pred, int op, uint32_t **perm,
                           Temps &tmp, hipStream_t s);
-// Count pass; also stores each query's first kRowSortRegs matches, sorted, in
-// stash[query][kRowSortRegs], and (with perm) ordered_counts[t] = counts[perm[t]].
+// Count pass; also stores each query's first stash_regs(dim) matches in
+// stash[query][stash_regs(dim)], and (with perm) ordered_counts[t] = counts[perm[t]].
 arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
                             const uint32_t *perm, int32_t *counts, int32_t *ordered_counts, int32_t *stash,
                             hipStream_t s);
@@ -209,7 +209,11 @@ arborx_status spatial_reduce(const TreeDev &t, const float *queries, int64_t m, 
 arborx_status knn_query(const TreeDev &t, const float *queries, int64_t m, int k, const uint32_t *perm,
                         float *dist2, int32_t *indices, hipStream_t s);
 
-constexpr int kRowSortRegs = 16;      // rows up to this length are sorted in registers
+// Matches a CSR count walk keeps per query (its stash row), sorted in
+// registers when copied out; longer rows are walked again.  32 in 6D, where
+// radius rows run longer for the same selectivity.
+__host__ __device__ constexpr int stash_regs(int dim) { return dim >= 6 ? 32 : 16; }
+constexpr int kMaxStashRegs = 32;
 constexpr int kRowSortBlock = 4096;   // rows up to this length are sorted by one workgroup
 
 }  // namespace ax

@@ -25,7 +25,7 @@ namespace {
 __device__ __forceinline__ int node_count(const TreeHeader *hdr) { return hdr->n > 1 ? hdr->n - 1 : 1; }
 
 // Count pass of a CSR query.  With a stash, each query also keeps its first
-// kRowSortRegs matches in registers, in the order found, and stores them in
+// stash_regs(D) matches in registers, in the order found, and stores them in
 // the stash row of its input position (one aligned 64-byte segment per
 // thread), so that the copy into the CSR array later streams rows, counts and
 // offsets in input order and sorts each row there; rows that fit need no
@@ -54,14 +54,15 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D
     int spill[kSpill];
     ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap, spill);
     int *wstack = s_stack + wave_id() * kWaveStack;
+    constexpr int R = stash_regs(D);
     int c = 0;
-    int buf[kRowSortRegs];
+    int buf[R];
 #pragma unroll
-    for (int k = 0; k < kRowSortRegs; ++k)
+    for (int k = 0; k < R; ++k)
         buf[k] = 0;
     auto f = [&](int idx, float) {
-        if (STASH && c < kRowSortRegs)
-            append_at<kRowSortRegs>(buf, c, idx);
+        if (STASH && c < R)
+            append_at<R>(buf, c, idx);
         ++c;
     };
     if (SCHED == 1)
@@ -77,9 +78,9 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D
     if (!active)
         return;
     if (STASH) {
-        int4 *row = reinterpret_cast<int4 *>(stash + qi * kRowSortRegs);
+        int4 *row = reinterpret_cast<int4 *>(stash + qi * R);
 #pragma unroll
-        for (int k = 0; k < kRowSortRegs / 4; ++k)
+        for (int k = 0; k < R / 4; ++k)
             row[k] = make_int4(buf[4 * k], buf[4 * k + 1], buf[4 * k + 2], buf[4 * k + 3]);
     }
     counts[qi] = c;
@@ -87,9 +88,10 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D
         ordered_counts[t] = c;
 }
 
-// Rows of at most kRowSortRegs matches: sort the stash row in registers (a
-// bitonic network, empty slots padded to sort last) and copy it to the CSR
-// slot.  Thread i handles query i, so consecutive lanes fill adjacent rows.
+// Rows of at most R matches: sort the stash row in registers (a bitonic
+// network, empty slots padded to sort last) and copy it to the CSR slot.
+// Thread i handles query i, so consecutive lanes fill adjacent rows.
+template <int R>
 __global__ void k_copy_stash(const int32_t *__restrict__ stash, int64_t m, const int32_t *__restrict__ counts,
                              const int64_t *__restrict__ offsets, int32_t *__restrict__ indices)
 {
@@ -97,13 +99,13 @@ __global__ void k_copy_stash(const int32_t *__restrict__ stash, int64_t m, const
     if (qi >= m)
         return;
     const int c = counts[qi];
-    if (c > kRowSortRegs)
+    if (c > R)
         return;
-    const int4 *row = reinterpret_cast<const int4 *>(stash + qi * kRowSortRegs);
+    const int4 *row = reinterpret_cast<const int4 *>(stash + qi * R);
     const int64_t o = offsets[qi];
-    int v[kRowSortRegs];
+    int v[R];
 #pragma unroll
-    for (int k = 0; k < kRowSortRegs / 4; ++k) {
+    for (int k = 0; k < R / 4; ++k) {
         const int4 x = row[k];
         v[4 * k] = x.x;
         v[4 * k + 1] = x.y;
@@ -111,11 +113,11 @@ __global__ void k_copy_stash(const int32_t *__restrict__ stash, int64_t m, const
         v[4 * k + 3] = x.w;
     }
 #pragma unroll
-    for (int k = 0; k < kRowSortRegs; ++k)
+    for (int k = 0; k < R; ++k)
         v[k] = k < c ? v[k] : INT32_MAX;
-    sort_network<kRowSortRegs>(v);
+    sort_network<R>(v);
 #pragma unroll
-    for (int k = 0; k < kRowSortRegs; ++k)
+    for (int k = 0; k < R; ++k)
         if (k < c)
             indices[o + k] = v[k];
 }
@@ -652,7 +654,10 @@ arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, in
         return st;
     {
         ProfScope ps("copy_stash", s);
-        k_copy_stash<<<grid_for(m, 256, INT32_MAX), 256, 0, s>>>(stash, m, counts, offsets, indices);
+        if (stash_regs(t.dim) == 32)
+            k_copy_stash<32><<<grid_for(m, 256, INT32_MAX), 256, 0, s>>>(stash, m, counts, offsets, indices);
+        else
+            k_copy_stash<16><<<grid_for(m, 256, INT32_MAX), 256, 0, s>>>(stash, m, counts, offsets, indices);
         AX_HIP(hipGetLastError());
     }
     const float r2 = radius * radius;

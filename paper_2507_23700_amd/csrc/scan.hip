@@ -77,17 +77,17 @@ __global__ __launch_bounds__(kScanBlock) void scan_apply(const int32_t *__restri
 
 // CSR offsets plus ordered lists of long rows.  Per tile the scan carries the
 // count sum and a packed pair of flag counts (low 32 bits: rows longer than
-// kRowSortRegs but at most kRowSortBlock; high 32 bits: longer rows), so the
+// `regs` but at most kRowSortBlock; high 32 bits: longer rows), so the
 // row ids of both kinds are compacted in row order without atomics.
-__device__ __forceinline__ int64_t row_flags(int32_t c)
+__device__ __forceinline__ int64_t row_flags(int32_t c, int regs)
 {
-    return (c > kRowSortRegs && c <= kRowSortBlock) ? 1ll : (c > kRowSortBlock ? (1ll << 32) : 0ll);
+    return (c > regs && c <= kRowSortBlock) ? 1ll : (c > kRowSortBlock ? (1ll << 32) : 0ll);
 }
 
 // counts[i] is row i's length; lcounts[i] is the length of the row listed at
 // position i (the same array, or the lengths in traversal order).
 __global__ __launch_bounds__(kScanBlock) void csr_tile_sums(const int32_t *__restrict__ counts,
-                                                            const int32_t *__restrict__ lcounts, int64_t m,
+                                                            const int32_t *__restrict__ lcounts, int64_t m, int regs,
                                                             int64_t *__restrict__ tile_sums,
                                                             int64_t *__restrict__ tile_flags)
 {
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kScanBlock) void csr_tile_sums(const int32_t *__res
         const int64_t i = base + (int64_t)j * kScanBlock + threadIdx.x;
         if (i < m) {
             s += counts[i];
-            f += row_flags(lcounts[i]);
+            f += row_flags(lcounts[i], regs);
         }
     }
     int64_t tot = 0, ftot = 0;
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kScanBlock) void csr_tile_prefix(int64_t *__restric
 // (the row at position i) or i when order is NULL.
 __global__ __launch_bounds__(kScanBlock) void csr_apply(const int32_t *__restrict__ counts,
                                                         const int32_t *__restrict__ lcounts,
-                                                        const uint32_t *__restrict__ order, int64_t m,
+                                                        const uint32_t *__restrict__ order, int64_t m, int regs,
                                                         const int64_t *__restrict__ tile_prefix,
                                                         const int64_t *__restrict__ tile_flags,
                                                         int64_t *__restrict__ offsets, int32_t *__restrict__ big_list,
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(kScanBlock) void csr_apply(const int32_t *__restric
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
         s += c[j];
-        f += row_flags(lc[j]);
+        f += row_flags(lc[j], regs);
     }
     int64_t tot = 0, ftot = 0;
     int64_t run = tile_prefix[blockIdx.x] + block_exclusive_scan<kScanBlock>(s, wsum, &tot);
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(kScanBlock) void csr_apply(const int32_t *__restric
         const int64_t i = i0 + j;
         if (i < m) {
             offsets[i] = run;
-            const int64_t fl = row_flags(lc[j]);
+            const int64_t fl = row_flags(lc[j], regs);
             if (fl != 0) {
                 const int32_t row = order ? (int32_t)order[i] : (int32_t)i;
                 if (fl == 1)
@@ -215,7 +215,7 @@ __global__ void scan_empty(int64_t *offsets, int64_t *total)
 size_t scan_workspace_bytes(int64_t m) { return (size_t)2 * ((m + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t); }
 
 hipError_t csr_offsets_lists(const int32_t *counts, const int32_t *ordered_counts, const uint32_t *order, int64_t m,
-                             int64_t *offsets, int32_t *big_list, int32_t *huge_list, QueryHeader *qh,
+                             int regs, int64_t *offsets, int32_t *big_list, int32_t *huge_list, QueryHeader *qh,
                              void *workspace, hipStream_t s)
 {
     if (m == 0) {
@@ -226,9 +226,9 @@ hipError_t csr_offsets_lists(const int32_t *counts, const int32_t *ordered_count
     int64_t *tile_sums = static_cast<int64_t *>(workspace);
     int64_t *tile_flags = tile_sums + tiles + 1;
     const int32_t *lc = order ? ordered_counts : counts;
-    csr_tile_sums<<<(unsigned)tiles, kScanBlock, 0, s>>>(counts, lc, m, tile_sums, tile_flags);
+    csr_tile_sums<<<(unsigned)tiles, kScanBlock, 0, s>>>(counts, lc, m, regs, tile_sums, tile_flags);
     csr_tile_prefix<<<1, kScanBlock, 0, s>>>(tile_sums, tile_flags, tiles, qh);
-    csr_apply<<<(unsigned)tiles, kScanBlock, 0, s>>>(counts, lc, order, m, tile_sums, tile_flags, offsets, big_list,
+    csr_apply<<<(unsigned)tiles, kScanBlock, 0, s>>>(counts, lc, order, m, regs, tile_sums, tile_flags, offsets, big_list,
                                                      huge_list);
     return hipGetLastError();
 }
