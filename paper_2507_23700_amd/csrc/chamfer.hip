@@ -8,9 +8,10 @@
 // float32 squared distances summed in float64.  With the assignment held fixed
 // the gradient is
 //   dL/da_i = 2 (a_i - b_nn(i)) + sum_{j : nn(j) = i} 2 (a_i - b_j),
-// and symmetrically for b; the backward kernel evaluates it in float64 from
-// the float32 coordinates, one thread per point, scattering the reverse terms
-// with float64 atomics, then rounds once to float32.
+// and symmetrically for b; the backward pass evaluates it in float64 from the
+// float32 coordinates, one thread per point: a first pass stores each point's
+// own term, a second scatters the reverse terms with float64 atomics, and the
+// result is rounded once to float32.
 #include <vector>
 
 #include "device_util.hpp"
@@ -58,29 +59,57 @@ __global__ __launch_bounds__(256) void k_pair_loss(const float *__restrict__ d2,
     }
 }
 
-// Gradient contributions of the points of one side (src, offsets soff) whose
-// nearest neighbours are in the other side (dst, doff):
-//   g_src[i] += 2 g (x_i - y_nn(i));  g_dst[nn(i)] -= 2 g (x_i - y_nn(i)).
-__global__ void k_chamfer_grad(const float *__restrict__ src, const int64_t *__restrict__ soff, int64_t ns,
-                               const float *__restrict__ dst, const int64_t *__restrict__ doff,
-                               const int32_t *__restrict__ nn, const float *__restrict__ grad_loss, int P,
-                               double *__restrict__ gsrc, double *__restrict__ gdst)
+// The term of point i of one side (src, offsets soff) with its nearest
+// neighbour in the other side (dst, doff): 2 g (x_i - y_nn(i)), or 0.
+__device__ __forceinline__ bool own_term(const float *__restrict__ src, const int64_t *__restrict__ soff,
+                                         const float *__restrict__ dst, const int64_t *__restrict__ doff,
+                                         const int32_t *__restrict__ nn, const float *__restrict__ grad_loss, int P,
+                                         int64_t i, double (&t)[3], int64_t &jj)
+{
+    t[0] = t[1] = t[2] = 0.0;
+    const int32_t j = nn[i];
+    if (j < 0)
+        return false;
+    const int p = pair_of(soff, P, i);
+    jj = doff[p] + j;
+    if (jj >= doff[p + 1])
+        return false;
+    const double g2 = 2.0 * (double)grad_loss[p];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        t[d] = g2 * ((double)src[i * 3 + d] - (double)dst[jj * 3 + d]);
+    return true;
+}
+
+// First pass: g_src[i] = 2 g (x_i - y_nn(i)), a plain store per point.
+__global__ void k_chamfer_own(const float *__restrict__ src, const int64_t *__restrict__ soff, int64_t ns,
+                              const float *__restrict__ dst, const int64_t *__restrict__ doff,
+                              const int32_t *__restrict__ nn, const float *__restrict__ grad_loss, int P,
+                              double *__restrict__ gsrc)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t j = nn[i];
-        if (j < 0)
-            continue;
-        const int p = pair_of(soff, P, i);
-        const int64_t jj = doff[p] + j;
-        if (jj >= doff[p + 1])
-            continue;
-        const double g2 = 2.0 * (double)grad_loss[p];
+        double t[3];
+        int64_t jj = 0;
+        own_term(src, soff, dst, doff, nn, grad_loss, P, i, t, jj);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const double diff = (double)src[i * 3 + d] - (double)dst[jj * 3 + d];
-            atomicAdd(&gsrc[i * 3 + d], g2 * diff);
-            atomicAdd(&gdst[jj * 3 + d], -g2 * diff);
-        }
+        for (int d = 0; d < 3; ++d)
+            gsrc[i * 3 + d] = t[d];
+    }
+}
+
+// Second pass, after both first passes: g_dst[nn(i)] -= 2 g (x_i - y_nn(i)).
+__global__ void k_chamfer_reverse(const float *__restrict__ src, const int64_t *__restrict__ soff, int64_t ns,
+                                  const float *__restrict__ dst, const int64_t *__restrict__ doff,
+                                  const int32_t *__restrict__ nn, const float *__restrict__ grad_loss, int P,
+                                  double *__restrict__ gdst)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x) {
+        double t[3];
+        int64_t jj = 0;
+        if (own_term(src, soff, dst, doff, nn, grad_loss, P, i, t, jj))
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                atomicAdd(&gdst[jj * 3 + d], -t[d]);
     }
 }
 
@@ -159,12 +188,14 @@ arborx_status chamfer_backward(const float *a, const int64_t *a_off, const float
     AX_HIP(hipMemcpyAsync(aoff, a_off, 8 * (P + 1), hipMemcpyHostToDevice, s));
     AX_HIP(hipMemcpyAsync(boff, b_off, 8 * (P + 1), hipMemcpyHostToDevice, s));
     ProfScope ps("chamfer_backward", s);
-    fill_kernel<double><<<grid_for(3 * na, 256, 65536), 256, 0, s>>>(ga, 3 * na, 0.0);
-    fill_kernel<double><<<grid_for(3 * nb, 256, 65536), 256, 0, s>>>(gb, 3 * nb, 0.0);
     if (na > 0)
-        k_chamfer_grad<<<grid_for(na, 256, 65536), 256, 0, s>>>(a, aoff, na, b, boff, nn_ab, grad_loss, P, ga, gb);
+        k_chamfer_own<<<grid_for(na, 256, 65536), 256, 0, s>>>(a, aoff, na, b, boff, nn_ab, grad_loss, P, ga);
     if (nb > 0)
-        k_chamfer_grad<<<grid_for(nb, 256, 65536), 256, 0, s>>>(b, boff, nb, a, aoff, nn_ba, grad_loss, P, gb, ga);
+        k_chamfer_own<<<grid_for(nb, 256, 65536), 256, 0, s>>>(b, boff, nb, a, aoff, nn_ba, grad_loss, P, gb);
+    if (na > 0)
+        k_chamfer_reverse<<<grid_for(na, 256, 65536), 256, 0, s>>>(a, aoff, na, b, boff, nn_ab, grad_loss, P, gb);
+    if (nb > 0)
+        k_chamfer_reverse<<<grid_for(nb, 256, 65536), 256, 0, s>>>(b, boff, nb, a, aoff, nn_ba, grad_loss, P, ga);
     if (na > 0)
         k_to_float<<<grid_for(3 * na, 256, 65536), 256, 0, s>>>(ga, 3 * na, grad_a);
     if (nb > 0)
