@@ -81,6 +81,10 @@ typedef struct arborx_tuning {
                              outward, leaves decided on their exact records; 2 = four-wide nodes (two levels
                              per fetch).  Formats 1 and 2 are built only while some operation asks for them
                              when the tree is built; asking later is ARBORX_E_INVALID */
+    int32_t queries_per_thread; /* radius searches (CSR count pass of sphere queries, fused reductions) with
+                                   the thread schedule on binary nodes: 1, 2 or 4 Morton-neighbouring queries
+                                   answered by one thread in one walk over the union of their paths; 0 = by
+                                   operation and dimension (up to 3D: 2 for CSR, 4 for reductions; 1 in 6D) */
 } arborx_tuning;
 
 /* Operation kinds that carry their own tuning. */

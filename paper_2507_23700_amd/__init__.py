@@ -62,8 +62,9 @@ def version() -> str:
     return _lib.lib().arborx_version().decode()
 
 
-def arborx_set_tuning(block=0, order=1, stack=0, schedule=0, build=0, seed_mode=0, node_format=0) -> None:
-    t = _lib.Tuning(block, order, stack, schedule, build, seed_mode, node_format)
+def arborx_set_tuning(block=0, order=1, stack=0, schedule=0, build=0, seed_mode=0, node_format=0,
+                      queries_per_thread=0) -> None:
+    t = _lib.Tuning(block, order, stack, schedule, build, seed_mode, node_format, queries_per_thread)
     _check(_lib.lib().arborx_set_tuning(ctypes.byref(t)))
 
 
@@ -82,11 +83,12 @@ OP_SPATIAL, OP_REDUCE, OP_KNN = 0, 1, 2
 
 def _tuning_dict(t):
     return dict(block=t.block, order=t.order, stack=t.stack, schedule=t.schedule, build=t.build, seed_mode=t.seed_mode,
-                node_format=t.node_format)
+                node_format=t.node_format, queries_per_thread=t.queries_per_thread)
 
 
-def arborx_set_tuning_op(op, block=0, order=1, stack=0, schedule=0, build=0, seed_mode=0, node_format=0) -> None:
-    t = _lib.Tuning(block, order, stack, schedule, build, seed_mode, node_format)
+def arborx_set_tuning_op(op, block=0, order=1, stack=0, schedule=0, build=0, seed_mode=0, node_format=0,
+                         queries_per_thread=0) -> None:
+    t = _lib.Tuning(block, order, stack, schedule, build, seed_mode, node_format, queries_per_thread)
     _check(_lib.lib().arborx_set_tuning_op(op, ctypes.byref(t)))
 
 

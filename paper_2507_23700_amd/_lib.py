@@ -54,7 +54,8 @@ _lib = None
 
 class Tuning(ctypes.Structure):
     _fields_ = [("block", I32), ("order", I32), ("stack", I32), ("schedule", I32), ("build", I32),
-                ("seed_mode", I32), ("node_format", I32)]
+                ("seed_mode", I32), ("node_format", I32),
+                ("queries_per_thread", I32)]
 
 
 def header_symbols() -> list[str]:

@@ -64,10 +64,10 @@ bool cache_lookup(const std::string &key, Tuning &t)
     bool found = false;
     while (std::fgets(line, sizeof(line), f)) {
         char k[200];
-        int block, order, stack, schedule, seed, nodes;
+        int block, order, stack, schedule, seed, nodes, packet;
         if (std::sscanf(line, "{\"key\": \"%199[^\"]\", \"block\": %d, \"order\": %d, \"stack\": %d, \"schedule\": %d, "
-                              "\"seed\": %d, \"nodes\": %d",
-                        k, &block, &order, &stack, &schedule, &seed, &nodes) == 7 &&
+                              "\"seed\": %d, \"nodes\": %d, \"packet\": %d",
+                        k, &block, &order, &stack, &schedule, &seed, &nodes, &packet) == 8 &&
             key == k) {
             t.block = block;
             t.order = order;
@@ -75,6 +75,7 @@ bool cache_lookup(const std::string &key, Tuning &t)
             t.schedule = schedule;
             t.seed = seed;
             t.nodes = nodes;
+            t.packet = packet;
             found = true;
         }
     }
@@ -92,8 +93,8 @@ void cache_store(const std::string &key, const Tuning &t, double ms)
         return;
     std::fprintf(f,
                  "{\"key\": \"%s\", \"block\": %d, \"order\": %d, \"stack\": %d, \"schedule\": %d, \"seed\": %d, "
-                 "\"nodes\": %d, \"ms\": %.4f}\n",
-                 key.c_str(), t.block, t.order, t.stack, t.schedule, t.seed, t.nodes, ms);
+                 "\"nodes\": %d, \"packet\": %d, \"ms\": %.4f}\n",
+                 key.c_str(), t.block, t.order, t.stack, t.schedule, t.seed, t.nodes, t.packet, ms);
     std::fclose(f);
 }
 
@@ -132,6 +133,7 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
             best->schedule = cached.schedule;
             best->build = cached.build;
             best->seed_mode = cached.seed;
+            best->queries_per_thread = cached.packet;
             best->node_format = cached.nodes;
         }
         if (best_ms)
@@ -170,6 +172,15 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
             c.t.schedule = 0;
             c.t.nodes = format;
             c.t.order = 1;
+            cands.push_back(c);
+        }
+    if (op != OP_KNN)
+        for (int nq : {1, 2, 4}) {  // queries per thread of the radius walks
+            Candidate c;
+            c.t = base;
+            c.t.schedule = 0;
+            c.t.nodes = 0;
+            c.t.packet = nq;
             cands.push_back(c);
         }
     if (op != OP_KNN)
@@ -300,6 +311,7 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
         best->schedule = b.schedule;
         best->build = b.build;
         best->seed_mode = b.seed;
+        best->queries_per_thread = b.packet;
         best->node_format = b.nodes;
     }
     if (best_ms)

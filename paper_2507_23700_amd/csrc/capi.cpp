@@ -363,6 +363,10 @@ static arborx_status to_tuning(const arborx_tuning *t, const Tuning &base, Tunin
     if (t->node_format < 0 || t->node_format > 2)
         return fail(ARBORX_E_INVALID, "node_format must be 0 (binary), 1 (binary, 16-bit boxes) or 2 (four-wide)");
     n.nodes = t->node_format;
+    if (t->queries_per_thread != 0 && t->queries_per_thread != 1 && t->queries_per_thread != 2 &&
+        t->queries_per_thread != 4)
+        return fail(ARBORX_E_INVALID, "queries_per_thread must be 0 (default), 1, 2 or 4");
+    n.packet = t->queries_per_thread;
     return ARBORX_OK;
 }
 
@@ -375,6 +379,7 @@ static void from_tuning(const Tuning &g, arborx_tuning *t)
     t->build = g.build;
     t->seed_mode = g.seed;
     t->node_format = g.nodes;
+    t->queries_per_thread = g.packet;
 }
 
 arborx_status arborx_set_tuning(const arborx_tuning *t)

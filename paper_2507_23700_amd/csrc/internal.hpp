@@ -43,6 +43,9 @@ struct Tuning {
     int build = 0;
     int seed = 0;   // kNN starting bound: 0 k-th of 2k nearby leaves, 1 none, 2 farthest of k nearby leaves
     int nodes = 0;  // 0: binary float, 1: binary with quantized 16-bit child boxes (exact leaf tests), 2: four-wide
+    int packet = 0; // radius walks on binary nodes: queries per thread (1, 2 or 4) walked together; 0 = by
+                    // operation and dimension (up to 3D, where neighbouring paths overlap most: 4 for the
+                    // fused reductions, 2 for the CSR count with its register rows; 1 in 6D)
 };
 // Tuning is kept per operation kind so the autotuner can pick each separately.
 enum Op { OP_SPATIAL = 0, OP_REDUCE = 1, OP_KNN = 2, OP_KINDS = 3 };

@@ -88,6 +88,66 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D
         ordered_counts[t] = c;
 }
 
+// Packet form of the CSR count walk (sphere queries, binary nodes): thread t
+// answers the NQ queries at sorted positions NQ*t .. NQ*t + NQ - 1 in one walk,
+// each with its own register stash row.
+template <int D, int NQ>
+__global__ void k_spatial_count_packet(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+                                       const float *__restrict__ queries, int64_t m, float r2,
+                                       const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
+                                       int32_t *__restrict__ ordered_counts, int32_t *__restrict__ stash,
+                                       int stack_cap)
+{
+    extern __shared__ int s_stack[];
+    constexpr int R = stash_regs(D);
+    const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
+    if (t * NQ >= m)
+        return;
+    Sphere<D> pred[NQ];
+    int64_t qi[NQ];
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+        const int64_t p = t * NQ + j;
+        qi[j] = p < m ? (perm ? (int64_t)perm[p] : p) : m;
+        if (qi[j] < m)
+            pred[j].load(queries, qi[j], r2);
+        else
+            pred[j].dead();
+    }
+    int spill[kSpill];
+    ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap, spill);
+    int c[NQ];
+    int buf[NQ][R];
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+        c[j] = 0;
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            buf[j][k] = 0;
+    }
+    auto f = [&](int j, int idx, float) {
+#pragma unroll
+        for (int jj = 0; jj < NQ; ++jj)
+            if (jj == j) {
+                if (c[jj] < R)
+                    append_at<R>(buf[jj], c[jj], idx);
+                ++c[jj];
+            }
+    };
+    traverse_spatial_packet<D, NQ>(nodes, hdr->root, node_count(hdr), pred, st, f);
+#pragma unroll
+    for (int j = 0; j < NQ; ++j)
+        if (qi[j] < m) {
+            int4 *row = reinterpret_cast<int4 *>(stash + qi[j] * R);
+#pragma unroll
+            for (int k = 0; k < R / 4; ++k)
+                row[k] = make_int4(buf[j][4 * k], buf[j][4 * k + 1], buf[j][4 * k + 2], buf[j][4 * k + 3]);
+            counts[qi[j]] = c[j];
+            if (ordered_counts)
+                ordered_counts[t * NQ + j] = c[j];
+        }
+}
+
 // Rows of at most R matches: sort the stash row in registers (a bitonic
 // network, empty slots padded to sort last) and copy it to the CSR slot.
 // Thread i handles query i, so consecutive lanes fill adjacent rows.
@@ -311,6 +371,57 @@ __global__ void k_spatial_reduce(const Node<D> *__restrict__ nodes, const QNode<
         sums[qi] = s;
 }
 
+// Packet form of the fused reduction: thread t answers the NQ queries at
+// sorted positions NQ*t .. NQ*t + NQ - 1 in one walk over binary nodes.
+template <int D, bool SUMDIST, int NQ>
+__global__ void k_spatial_reduce_packet(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+                                        const float *__restrict__ queries, int64_t m, float r2, float scale,
+                                        const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
+                                        int64_t *__restrict__ sums, int stack_cap)
+{
+    extern __shared__ int s_stack[];
+    const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
+    if (t * NQ >= m)
+        return;
+    Sphere<D> pred[NQ];
+    int64_t qi[NQ];
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+        const int64_t p = t * NQ + j;
+        qi[j] = p < m ? (perm ? (int64_t)perm[p] : p) : m;
+        if (qi[j] < m)
+            pred[j].load(queries, qi[j], r2);
+        else
+            pred[j].dead();
+    }
+    int spill[kSpill];
+    ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap, spill);
+    int c[NQ];
+    long long s[NQ];
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+        c[j] = 0;
+        s[j] = 0;
+    }
+    auto f = [&](int j, int, float d2) {
+#pragma unroll
+        for (int jj = 0; jj < NQ; ++jj)
+            if (jj == j) {
+                ++c[jj];
+                if (SUMDIST)
+                    s[jj] += fixed_term(d2, scale);
+            }
+    };
+    traverse_spatial_packet<D, NQ>(nodes, hdr->root, node_count(hdr), pred, st, f);
+#pragma unroll
+    for (int j = 0; j < NQ; ++j)
+        if (qi[j] < m) {
+            counts[qi[j]] = c[j];
+            if (SUMDIST)
+                sums[qi[j]] = s[j];
+        }
+}
+
 template <int D, int K, bool WAVE, int FMT>
 __global__ void k_knn(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
                       const Node4<D> *__restrict__ wnodes, const uint64_t *__restrict__ codes, int n_nodes,
@@ -428,6 +539,20 @@ arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m,
                          int32_t *counts, int32_t *ordered_counts, int32_t *stash, hipStream_t s)
 {
     const int sched = effective_schedule(OP_SPATIAL);
+    const int nq = tuning(OP_SPATIAL).packet ? tuning(OP_SPATIAL).packet : (D <= 3 ? 2 : 1);
+    if (sched == 0 && nq > 1 && pred == Pred::Sphere) {  // NQ queries per thread over binary nodes
+        const Launch L = traversal_launch((m + nq - 1) / nq, sizeof(int), OP_SPATIAL);
+        const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
+        ProfScope ps("spatial_count", s);
+        if (nq == 2)
+            k_spatial_count_packet<D, 2><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, counts,
+                                                                        perm ? ordered_counts : nullptr, stash, L.cap);
+        else
+            k_spatial_count_packet<D, 4><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, counts,
+                                                                        perm ? ordered_counts : nullptr, stash, L.cap);
+        AX_HIP(hipGetLastError());
+        return ARBORX_OK;
+    }
     const Launch L = traversal_launch(m, sizeof(int), OP_SPATIAL, sched == 1);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
@@ -505,6 +630,28 @@ arborx_status reduce_impl(const TreeDev &t, const float *q, int64_t m, float r2,
                           const uint32_t *perm, int32_t *counts, int64_t *sums, hipStream_t s)
 {
     const int sched = effective_schedule(OP_REDUCE);
+    const int nq = tuning(OP_REDUCE).packet ? tuning(OP_REDUCE).packet : (D <= 3 ? 4 : 1);
+    if (sched == 0 && nq > 1) {  // NQ queries per thread over binary nodes
+        const Launch L = traversal_launch((m + nq - 1) / nq, sizeof(int), OP_REDUCE);
+        const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
+        ProfScope ps(op == ARBORX_COUNT_SUMDIST ? "reduce_sumdist" : "reduce_count", s);
+#define AX_RP(SD, N) k_spatial_reduce_packet<D, SD, N><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, scale, \
+                                                                                   perm, counts, sums, L.cap)
+        if (op == ARBORX_COUNT_SUMDIST) {
+            if (nq == 2)
+                AX_RP(true, 2);
+            else
+                AX_RP(true, 4);
+        } else {
+            if (nq == 2)
+                AX_RP(false, 2);
+            else
+                AX_RP(false, 4);
+        }
+#undef AX_RP
+        AX_HIP(hipGetLastError());
+        return ARBORX_OK;
+    }
     const Launch L = traversal_launch(m, sizeof(int), OP_REDUCE, sched == 1);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);

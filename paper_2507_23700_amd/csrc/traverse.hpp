@@ -201,6 +201,51 @@ __device__ __forceinline__ void traverse_spatial4(const Node4<D> *__restrict__ n
     }
 }
 
+// Packet walk: one thread answers NQ queries (Morton neighbours) in a single
+// depth-first walk over the union of their paths.  A child is entered when
+// any query's predicate admits it; leaves are tested per query, calling
+// f(j, index, d2) for query j.  Neighbouring queries share most of their
+// paths, so a thread makes fewer dependent node fetches per query.
+template <int D, int NQ, class P, class F>
+__device__ __forceinline__ void traverse_spatial_packet(const Node<D> *__restrict__ nodes, int root, int n_nodes,
+                                                        const P (&pred)[NQ], ShortStack<int> &st, F &f)
+{
+    int cur = root;
+    for (int iter = 0; iter <= n_nodes; ++iter) {
+        if ((unsigned)cur >= (unsigned)n_nodes)
+            break;
+        Node<D> nd;
+        load_node(nodes, cur, nd);
+        const int c0 = nd.child[0], c1 = nd.child[1];
+        bool g0 = false, g1 = false;
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) {
+            float d0, d1;
+            const bool h0 = pred[j].hit(nd.lo[0], nd.hi[0], d0);
+            const bool h1 = pred[j].hit(nd.lo[1], nd.hi[1], d1);
+            if (h0 && c0 < 0 && c0 != kEmptyRef)
+                f(j, ~c0, d0);
+            if (h1 && c1 < 0 && c1 != kEmptyRef)
+                f(j, ~c1, d1);
+            g0 = g0 | h0;
+            g1 = g1 | h1;
+        }
+        g0 = g0 && c0 >= 0;
+        g1 = g1 && c1 >= 0;
+        if (g0) {
+            if (g1)
+                st.push(c1);
+            cur = c0;
+        } else if (g1) {
+            cur = c1;
+        } else {
+            if (st.empty())
+                break;
+            cur = st.pop();
+        }
+    }
+}
+
 // Wavefront-packet form of the walk: the 64 lanes (64 Morton-neighbouring
 // queries) visit the union of their paths together.  The node index is the
 // same in every lane, so each node is fetched once per wavefront through the

@@ -90,6 +90,7 @@ def test_tuning_validation_and_roundtrip():
     assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 0, 0, 0, 0, 2))) == 0
     assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 0, 0, 0, 3, 0))) == 1
     assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 0, 0, 0, -1, 0))) == 1
+    assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 0, 0, 0, 0, 0, 3))) == 1
     assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 12, 0, 0, 0, 0))) == 1
     assert L.arborx_set_tuning(None) == 0
     assert L.arborx_get_tuning(ctypes.byref(g)) == 0
@@ -112,7 +113,8 @@ def test_valid_call_without_gpu_reports_device_error():
 def test_python_tuning_roundtrip():
     ax.arborx_set_tuning(block=64, stack=8, node_format=1)
     try:
-        assert ax.arborx_get_tuning() == dict(block=64, order=1, stack=8, schedule=0, build=0, seed_mode=0, node_format=1)
+        assert ax.arborx_get_tuning() == dict(block=64, order=1, stack=8, schedule=0, build=0, seed_mode=0, node_format=1,
+                                              queries_per_thread=0)
         ax.arborx_set_tuning_op(ax.OP_KNN, block=128, seed_mode=1)
         assert ax.arborx_get_tuning_op(ax.OP_KNN)["seed_mode"] == 1
         assert ax.arborx_get_tuning_op(ax.OP_KNN)["node_format"] == 0

@@ -372,6 +372,34 @@ def test_schedules_identical(block, order, stack, schedule, node_format):
         ax.arborx_reset_tuning()
 
 
+@pytest.mark.parametrize("nq", [1, 2, 4])
+def test_query_packets_identical(nq):
+    cfg = inputs.config_small(n=20_000, m=4001)  # a ragged last packet
+    data, q, r = cfg["data"], cfg["queries"], cfg["radius"]
+    t = ax.arborx_bvh_build(dev(data))
+    for kw in (dict(queries_per_thread=nq), dict(queries_per_thread=nq, block=64, stack=2),
+               dict(queries_per_thread=nq, order=0)):
+        ax.arborx_set_tuning(**kw)
+        try:
+            check_reduce(t, data, q, r)
+            check_reduce(t, data, q, 0.0)
+            check_reduce(t, data, q[:3], float("inf"))
+            check_spatial(t, data, q, r)
+            check_spatial(t, data, q[:5], 0.3)  # rows longer than the register stash
+        finally:
+            ax.arborx_reset_tuning()
+    g = np.random.default_rng(nq)
+    for n in (1, 2, 5):
+        small = g.random((n, 3)).astype(np.float32)
+        ts = ax.arborx_bvh_build(dev(small))
+        ax.arborx_set_tuning(queries_per_thread=nq)
+        try:
+            check_reduce(ts, small, q[:7], 0.4)
+            check_spatial(ts, small, q[:7], 0.4)
+        finally:
+            ax.arborx_reset_tuning()
+
+
 def test_stream_argument():
     cfg = inputs.config_small(n=3000, m=700)
     s = torch.cuda.Stream()
