@@ -92,6 +92,8 @@ def traffic_for(kernel, workload):
 
 
 KERNEL_PHASE = [  # rocprofv3 kernel name fragment -> phase name used by the in-library profiler
+    ("k_spatial_count_packet<", "spatial_count"), ("k_spatial_reduce_packet<3, false", "reduce_count"),
+    ("k_spatial_reduce_packet<3, true", "reduce_sumdist"), ("k_valu_probe", "valu_probe"),
     ("k_knn<", "knn"), ("k_spatial_count<", "spatial_count"), ("k_spatial_reduce<3, false", "reduce_count"),
     ("k_spatial_reduce<3, true", "reduce_sumdist"), ("k_spatial_fill_rows<", "spatial_fill"),
     ("hierarchy_chunk_kernel<", "build_hierarchy"), ("hierarchy_top_kernel<", "build_hierarchy"),
@@ -100,12 +102,12 @@ KERNEL_PHASE = [  # rocprofv3 kernel name fragment -> phase name used by the in-
 
 
 def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, stats_csv, workload, copy_bytes,
-                       sq_csv=None):
+                       sq_csv=None, sq_probe_csv=None):
     """Per-phase HBM bytes per launch from rocprofv3 --pmc runs, scaled by what the same
-    counters read for a plain device copy of copy_bytes bytes; with sq_csv (SQ_INSTS_VALU and
-    SQ_BUSY_CYCLES), the fraction of vector-ALU issue slots used: each shader engine's 32
-    SIMDs issue one wave64 VALU instruction per 4 cycles, 8 per SE-cycle, and SQ_BUSY_CYCLES
-    sums the busy cycles over the SEs.  Writes profiles/traffic.json and returns a markdown
+    counters read for a plain device copy of copy_bytes bytes; with sq_csv and sq_probe_csv
+    (SQ_INSTS_VALU and SQ_BUSY_CYCLES of the kernels and of the library's VALU issue probe),
+    each kernel's VALU instructions per busy cycle as a fraction of the probe's, the issue
+    rate independent FMA chains reach.  Writes profiles/traffic.json and returns a markdown
     table."""
     import collections
     import csv
@@ -136,10 +138,13 @@ def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, sta
     write, wl = per_dispatch(write_csv, "WRITE_SIZE")
     hit, _ = per_dispatch(write_csv, "TCC_HIT_sum")
     miss, _ = per_dispatch(write_csv, "TCC_MISS_sum")
-    valu, busy = {}, {}
-    if sq_csv:
+    valu, busy, peak = {}, {}, None
+    if sq_csv and sq_probe_csv:
         valu, _ = per_dispatch(sq_csv, "SQ_INSTS_VALU")
         busy, _ = per_dispatch(sq_csv, "SQ_BUSY_CYCLES")
+        pv, _ = per_dispatch(sq_probe_csv, "SQ_INSTS_VALU")
+        pb, _ = per_dispatch(sq_probe_csv, "SQ_BUSY_CYCLES")
+        peak = pv["valu_probe"] / pb["valu_probe"]
     dur = collections.defaultdict(list)
     for r in csv.DictReader(open(stats_csv)):
         ph = phase(r["Name"])
@@ -157,7 +162,7 @@ def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, sta
         wr = write.get(ph, 0.0) * wscale / max(len(wl.get(ph, ())), 1)
         h = hit.get(ph, 0.0) / max(hit.get(ph, 0.0) + miss.get(ph, 0.0), 1e-9)
         ms = sum(a * c for a, c in dur[ph]) / max(sum(c for _, c in dur[ph]), 1) / 1e6 if dur[ph] else float("nan")
-        vb = valu[ph] / (busy[ph] * 8.0) if busy.get(ph) else None  # both summed over the phase's launches
+        vb = valu[ph] / busy[ph] / peak if peak and busy.get(ph) else None  # sums over the phase's launches
         table[ph] = {"bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr, "l2_hit": h,
                      "valu_busy": vb, "source_hash": src}
         lines.append(f"| {ph} | {nl} | {ms:.3f} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | {h:.3f} | "
@@ -171,6 +176,8 @@ def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, sta
     lines.append("")
     lines.append(f"Counter scale from a {copy_bytes / 2 ** 30:.0f} GiB device copy: FETCH_SIZE x {fscale:.3f}, "
                  f"WRITE_SIZE x {wscale:.3f}.  Kernel sources hash {src}.")
+    if peak:
+        lines.append(f"VALU issue probe: {peak:.2f} VALU instructions per SQ busy cycle (the busy column's 1.0).")
     return "\n".join(lines)
 
 
@@ -314,18 +321,33 @@ def main():
     ap.add_argument("--no-chamfer", action="store_true", help="skip the Chamfer timing")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of GIB gibibytes (counter calibration) and exit")
+    ap.add_argument("--calibrate-valu", action="store_true",
+                    help="only run the library's VALU issue probe (counter calibration) and exit")
     ap.add_argument("--summarize-counters", nargs="+", metavar="CSV",
-                    help="FETCH WRITE COPYFETCH COPYWRITE STATS [SQ]: turn rocprofv3 counter CSVs into "
+                    help="FETCH WRITE COPYFETCH COPYWRITE STATS [SQ SQPROBE]: turn rocprofv3 counter CSVs into "
                          "profiles/traffic.json and print a markdown table")
     args = ap.parse_args()
     if args.summarize_counters:
         n0 = args.n or {"gmm6": 2_000_000, "small": 20_000}.get(args.dist, 10_000_000)
         wl = f"gmm6d_n{n0}_m{n0}" if args.dist == "gmm6" else f"{'cube' if args.dist == 'small' else args.dist}3d_n{n0}_m{n0}"
-        if len(args.summarize_counters) not in (5, 6):
-            ap.error("--summarize-counters takes FETCH WRITE COPYFETCH COPYWRITE STATS [SQ]")
+        if len(args.summarize_counters) not in (5, 7):
+            ap.error("--summarize-counters takes FETCH WRITE COPYFETCH COPYWRITE STATS [SQ SQPROBE]")
         csvs = args.summarize_counters
         print(summarize_counters(*csvs[:5], workload=wl, copy_bytes=2 ** 30,
-                                 sq_csv=csvs[5] if len(csvs) == 6 else None))
+                                 sq_csv=csvs[5] if len(csvs) == 7 else None,
+                                 sq_probe_csv=csvs[6] if len(csvs) == 7 else None))
+        return
+    if args.calibrate_valu:
+        import torch
+        from paper_2507_23700_amd import _lib
+        blocks, iters = 8192, 4096
+        out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            st = _lib.lib().arborx_debug_valu_probe(ctypes.c_void_p(out.data_ptr()), blocks, iters, None)
+            if st != 0:
+                sys.exit(f"valu probe failed: {_lib.lib().arborx_last_error().decode()}")
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_valu_blocks": blocks, "iters": iters, "launches": 3}))
         return
     if args.calibrate_copy > 0:
         import torch

@@ -315,6 +315,17 @@ arborx_status arborx_debug_morton64(const float *points, int64_t n, int32_t dim,
  */
 arborx_status arborx_debug_tree_nodes(arborx_tree tree, int32_t *child, float *lo, float *hi, int32_t *root);
 
+/*
+ * Vector-ALU issue probe for counter calibration: `blocks` workgroups of 256
+ * threads each run `iters` rounds of eight independent float32 FMA chains
+ * (8 * iters VALU instructions per wavefront in the loop) and write one float
+ * per thread to out [device, blocks * 256 floats] so the work is kept.  Its
+ * SQ_INSTS_VALU / SQ_BUSY_CYCLES is the achievable issue rate that kernel
+ * counter readings are compared with.  blocks in 1..2^20, iters in 1..2^20.
+ * Does not synchronise.
+ */
+arborx_status arborx_debug_valu_probe(float *out, int32_t blocks, int32_t iters, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Profiling: per-phase GPU time measured with events on the launch stream.  */
 /* ------------------------------------------------------------------------ */

@@ -983,6 +983,43 @@ arborx_status arborx_debug_morton64(const float *points, int64_t n, int32_t dim,
     return ARBORX_OK;
 }
 
+namespace ax {
+namespace {
+// Eight independent FMA chains per thread: the loop body is VALU work only.
+__global__ __launch_bounds__(256) void k_valu_probe(float *__restrict__ out, int iters)
+{
+    const float x = (float)threadIdx.x * 0x1p-10f;
+    float a0 = x, a1 = x + 1.0f, a2 = x + 2.0f, a3 = x + 3.0f, a4 = x + 4.0f, a5 = x + 5.0f, a6 = x + 6.0f,
+          a7 = x + 7.0f;
+    for (int i = 0; i < iters; ++i) {
+        a0 = fmaf(a0, 0.999f, 0.25f);
+        a1 = fmaf(a1, 0.999f, 0.25f);
+        a2 = fmaf(a2, 0.999f, 0.25f);
+        a3 = fmaf(a3, 0.999f, 0.25f);
+        a4 = fmaf(a4, 0.999f, 0.25f);
+        a5 = fmaf(a5, 0.999f, 0.25f);
+        a6 = fmaf(a6, 0.999f, 0.25f);
+        a7 = fmaf(a7, 0.999f, 0.25f);
+    }
+    out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
+}
+}  // namespace
+}  // namespace ax
+
+arborx_status arborx_debug_valu_probe(float *out, int32_t blocks, int32_t iters, void *stream)
+{
+    if (!out)
+        return fail(ARBORX_E_INVALID, "out is NULL");
+    if (blocks < 1 || blocks > (1 << 20) || iters < 1 || iters > (1 << 20))
+        return fail(ARBORX_E_INVALID, "blocks and iters must be in 1..2^20");
+    arborx_status st = check_device();
+    if (st != ARBORX_OK)
+        return st;
+    k_valu_probe<<<blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(out, iters);
+    AX_HIP(hipGetLastError());
+    return ARBORX_OK;
+}
+
 arborx_status arborx_debug_tree_nodes(arborx_tree t, int32_t *child, float *lo, float *hi, int32_t *root)
 {
     arborx_status st = check_tree(t);
