@@ -65,13 +65,14 @@ __global__ void k_forest_codes(const float *__restrict__ q, int64_t m, const int
     }
 }
 
-// Next block of sorted positions for this workgroup, or -1 when all are taken.
-__device__ __forceinline__ int64_t next_block(unsigned long long *counter, int64_t m)
+// Next block of `span` sorted positions for this workgroup (one per thread by
+// default), or -1 when all are taken.
+__device__ __forceinline__ int64_t next_block(unsigned long long *counter, int64_t m, int64_t span = 0)
 {
     __shared__ int64_t s_start;
     if (threadIdx.x == 0) {
         const unsigned long long c = atomicAdd(counter, 1ull);
-        s_start = (int64_t)c * blockDim.x;
+        s_start = (int64_t)c * (span > 0 ? span : (int64_t)blockDim.x);
     }
     __syncthreads();
     const int64_t start = s_start;
@@ -121,6 +122,83 @@ __global__ __launch_bounds__(kForestBlock) void k_forest_reduce(
         counts[qi] = c;
         if (SUMDIST)
             sums[qi] = s;
+    }
+}
+
+// Packet form of the forest reduction (binary nodes): thread t of a block
+// takes NQ consecutive sorted positions.  Sorting is by (batch, Morton code),
+// so they usually share a batch and tree and are walked together; a packet
+// that straddles trees is walked one query at a time.
+template <int D, bool SUMDIST, int NQ>
+__global__ __launch_bounds__(kForestBlock) void k_forest_reduce_packet(
+    const Node<D> *__restrict__ nodes, int n_nodes, const TreeHeader *__restrict__ hdrs, int T,
+    const float *__restrict__ queries, int64_t m, const uint32_t *__restrict__ perm, const int64_t *__restrict__ boff,
+    int B, const int32_t *__restrict__ btree, const float *__restrict__ bradius, float scale, int32_t *__restrict__ counts,
+    int64_t *__restrict__ sums, unsigned long long *counter, int stack_cap)
+{
+    extern __shared__ int s_stack[];
+    int spill[kSpill];
+    for (int64_t start; (start = next_block(counter, m, (int64_t)kForestBlock * NQ)) >= 0;) {
+        int64_t qi[NQ];
+        int tr[NQ];
+        Sphere<D> pred[NQ];
+        bool same = true;
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) {
+            const int64_t p = start + (int64_t)threadIdx.x * NQ + j;
+            qi[j] = p < m ? (int64_t)perm[p] : -1;
+            tr[j] = -1;
+            if (qi[j] >= 0 && qi[j] < m) {
+                const int b = batch_of(boff, B, qi[j]);
+                tr[j] = btree[b] >= 0 && btree[b] < T ? btree[b] : -1;
+                const float r = bradius[b];
+                pred[j].load(queries, qi[j], r * r);
+            } else {
+                qi[j] = -1;
+                pred[j].dead();
+            }
+            if (qi[j] >= 0 && tr[j] != tr[0])
+                same = false;
+        }
+        int c[NQ];
+        long long s[NQ];
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) {
+            c[j] = 0;
+            s[j] = 0;
+        }
+        ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap, spill);
+        if (same && tr[0] >= 0) {
+            auto f = [&](int j, int, float d2) {
+#pragma unroll
+                for (int jj = 0; jj < NQ; ++jj)
+                    if (jj == j) {
+                        ++c[jj];
+                        if (SUMDIST)
+                            s[jj] += fixed_term(d2, scale);
+                    }
+            };
+            traverse_spatial_packet<D, NQ>(nodes, hdrs[tr[0]].root, n_nodes, pred, st, f);
+        } else {
+#pragma unroll
+            for (int j = 0; j < NQ; ++j)
+                if (qi[j] >= 0 && tr[j] >= 0) {
+                    st.clear();
+                    auto f = [&](int, float d2) {
+                        ++c[j];
+                        if (SUMDIST)
+                            s[j] += fixed_term(d2, scale);
+                    };
+                    traverse_spatial<D>(nodes, hdrs[tr[j]].root, n_nodes, pred[j], st, f);
+                }
+        }
+#pragma unroll
+        for (int j = 0; j < NQ; ++j)
+            if (qi[j] >= 0) {
+                counts[qi[j]] = c[j];
+                if (SUMDIST)
+                    sums[qi[j]] = s[j];
+            }
     }
 }
 
@@ -263,6 +341,29 @@ arborx_status forest_reduce_impl(ForestDev &f, const float *q, int64_t m, const 
     const QNode<D> *qnodes = static_cast<const QNode<D> *>(f.qnodes);
     const Node4<D> *wnodes = static_cast<const Node4<D> *>(f.wnodes);
     const int nn = (int)(f.n > 0 ? f.n : 1);
+    const int nq = tu.packet ? tu.packet : (D <= 3 ? 4 : 1);
+    if (tu.nodes == 0 && nq > 1) {
+#define AX_FRP(SD, N)                                                                                            \
+    do {                                                                                                         \
+        const int grid = persistent_grid((const void *)k_forest_reduce_packet<D, SD, N>, kForestBlock, lds);    \
+        k_forest_reduce_packet<D, SD, N><<<grid, kForestBlock, lds, s>>>(nodes, nn, f.hdrs, f.T, q, m, perm, boff, B, \
+                                                                         btree, brad, scale, counts, sums, counter, cap); \
+    } while (0)
+        if (op == ARBORX_COUNT_SUMDIST) {
+            if (nq == 2)
+                AX_FRP(true, 2);
+            else
+                AX_FRP(true, 4);
+        } else {
+            if (nq == 2)
+                AX_FRP(false, 2);
+            else
+                AX_FRP(false, 4);
+        }
+#undef AX_FRP
+        AX_HIP(hipGetLastError());
+        return ARBORX_OK;
+    }
 #define AX_FREDUCE(SD, F)                                                                                        \
     do {                                                                                                         \
         const int grid = persistent_grid((const void *)k_forest_reduce<D, SD, F>, kForestBlock, lds);           \

@@ -25,6 +25,7 @@ struct ShortStack {
     __device__ ShortStack(E *col, int stride, int cap, E *spill_) : lds(col), spill(spill_), shift(__ffs(stride) - 1),
                                                                      mask(cap - 1) {}
     __device__ __forceinline__ bool empty() const { return cnt == 0 && ns == 0; }
+    __device__ __forceinline__ void clear() { base = cnt = ns = 0; }
     __device__ __forceinline__ void push(E x)
     {
         if (cnt == mask + 1) {  // ring full: move the oldest LDS entry to the spill area

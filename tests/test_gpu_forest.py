@@ -59,7 +59,8 @@ def run_forest(f, cfg, k):
 @pytest.mark.parametrize("k,tuning", [(1, {}), (8, {}), (16, {}), (1, dict(node_format=1)),
                                       (8, dict(node_format=1)), (8, dict(seed_mode=2)), (16, dict(seed_mode=1)),
                                       (1, dict(node_format=2)), (8, dict(node_format=2)),
-                                      (16, dict(node_format=2, seed_mode=2))])
+                                      (16, dict(node_format=2, seed_mode=2)), (8, dict(queries_per_thread=1)),
+                                      (1, dict(queries_per_thread=2)), (16, dict(queries_per_thread=4))])
 def test_forest_vs_oracle(k, tuning):
     cfg = small_forest(k)
     ax.arborx_set_tuning(**tuning)  # before the build: it decides what is stored
