@@ -553,12 +553,54 @@ __device__ __forceinline__ int leaf_position(const uint64_t *__restrict__ codes,
     return lo < hdr.start + hdr.n ? lo : hdr.start + hdr.n - 1;
 }
 
+// Width of the register window that selects the mode-0 seed bound: the
+// smallest power of two holding 2K distances.
+template <int K>
+constexpr int seed_width()
+{
+    int w = 1;
+    while (w < 2 * K)
+        w <<= 1;
+    return w;
+}
+
+// Bitonic compare-exchange network on register words, fully unrolled so
+// that every index is a compile-time constant: sorts v[LO .. LO + N) (N a
+// power of two) ascending if UP, else descending.  The words are the bit
+// patterns of distances >= 0 (or NaN), which order as unsigned integers like
+// the distances, NaN after +inf.
+template <int W, int LO, int N, bool UP>
+__device__ __forceinline__ void bitonic_sort_range(uint32_t (&v)[W])
+{
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool asc = ((i & k) == 0) == UP;
+                    const uint32_t a = v[LO + i], b = v[LO + l];
+                    const uint32_t mn = a < b ? a : b, mx = a < b ? b : a;
+                    v[LO + i] = asc ? mn : mx;
+                    v[LO + l] = asc ? mx : mn;
+                }
+            }
+}
+
 // Starting bound for the kNN walk from the sorted leaves around position pos
 // (where a greedy descent towards q ends).  mode 0: the k-th smallest distance
 // among the 2k leaves around pos; mode 2: the largest distance among the k
-// leaves around pos (no insertion work, a looser bound).  Either is at least
-// the true k-th neighbour distance, so the slots start as k copies of
-// (bound, INT32_MAX), which admit every true result.  Needs n >= k.
+// leaves around pos (a looser bound).  Either is at least the true k-th
+// neighbour distance, so the slots start as k copies of (bound, INT32_MAX),
+// which admit every true result.  Needs n >= k.
+//
+// For k <= 16 the k-th smallest of the window is selected in registers with a
+// sorting network (the distances' bit patterns sorted as unsigned words);
+// when the window is exactly 2k wide only its two halves are sorted, one up
+// and one down: the elementwise minima of the halves are then the k smallest
+// of the window, so their maximum is the k-th smallest.
 template <int D, int K>
 __device__ __forceinline__ void seed_window(const float *__restrict__ leaves, int kind, const TreeHeader &hdr, int pos,
                                             const float *q, TopK<K> &best, int mode)
@@ -579,6 +621,32 @@ __device__ __forceinline__ void seed_window(const float *__restrict__ leaves, in
     w0 = w0 > hi_lim - 2 * K ? hi_lim - 2 * K : w0;
     w0 = w0 < lo_lim ? lo_lim : w0;
     const int w1 = (w0 + 2 * K < hi_lim) ? w0 + 2 * K : hi_lim;
+    if constexpr (K <= 16) {
+        constexpr int W = seed_width<K>();
+        constexpr uint32_t kInfBits = 0x7f800000u;
+        uint32_t v[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            const int p = w0 + i;
+            v[i] = (i < 2 * K && p < w1) ? __float_as_uint(leaf_d2<D>(leaves, kind, p, q)) : kInfBits;
+        }
+        uint32_t kth;
+        if constexpr (W == 2 * K && K > 1) {
+            bitonic_sort_range<W, 0, K, true>(v);
+            bitonic_sort_range<W, K, K, false>(v);
+            kth = 0;
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                const uint32_t mn = v[i] < v[K + i] ? v[i] : v[K + i];
+                kth = mn > kth ? mn : kth;
+            }
+        } else {
+            bitonic_sort_range<W, 0, W, true>(v);
+            kth = v[K - 1];
+        }
+        best.reset(__uint_as_float(kth < kInfBits ? kth : kInfBits));
+        return;
+    }
     for (int p = w0; p < w1; ++p)
         best.offer(leaf_d2<D>(leaves, kind, p, q), p);  // distinct keys; only distances matter
     best.reset(best.bound());
