@@ -96,6 +96,32 @@ const char *arborx_version(void);
 /* Thread-local message describing the last error of this thread ("" if none). [host] */
 const char *arborx_last_error(void);
 
+/*
+ * Device memory hook.  The library takes all of its device memory (tree and
+ * forest storage, per-call temporaries, CSR plans) from alloc_fn and returns it
+ * to free_fn, for example to share a framework's caching allocator; by
+ * default it uses stream-ordered allocations from the device's pool.
+ *   alloc_fn(bytes, stream, ctx) returns device memory for work queued on
+ *     `stream`, or NULL (the call then fails with ARBORX_E_NOMEM).
+ *   free_fn(ptr, stream, ctx) hands a block back.  `stream` is the stream the
+ *     block was allocated for, and every use of the block by the library was
+ *     queued on that stream before the call or has already completed: the
+ *     block may be given at once to later work on that stream, and to other
+ *     streams once that stream has passed this point (the contract of a
+ *     per-stream caching allocator).  Blocks that work on other streams used
+ *     (a destroyed tree that queries on several streams read, a replaced
+ *     query order) are handed back only after that work has completed; the
+ *     library checks for that at its later allocations and in this call.
+ *   ctx is passed through unchanged.
+ * Both NULL restores the default.  Allowed only while the library holds no
+ * device memory of the previous allocator (no live tree, forest or plan);
+ * blocks still waiting for other streams are waited for here.  Otherwise
+ * ARBORX_E_INVALID.  Not to be called concurrently with other library calls.  [host]
+ */
+typedef void *(*arborx_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*arborx_free_fn)(void *ptr, void *stream, void *ctx);
+arborx_status arborx_set_allocator(arborx_alloc_fn alloc_fn, arborx_free_fn free_fn, void *ctx);
+
 /* Set the traversal schedule used by later queries; NULL restores the defaults.  [host] */
 arborx_status arborx_set_tuning(const arborx_tuning *tuning);
 

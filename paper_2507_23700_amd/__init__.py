@@ -62,6 +62,47 @@ def version() -> str:
     return _lib.lib().arborx_version().decode()
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_allocator = None  # the installed ctypes callbacks, kept alive while the library may call them
+
+
+def arborx_set_allocator(alloc=None, free=None) -> None:
+    """Take the library's device memory from ``alloc(nbytes, stream) -> int`` and return it to
+    ``free(ptr, stream)`` (``stream`` is the raw stream handle as an int, 0 for the default
+    stream); with no arguments the library's own stream-ordered pool is used again."""
+    global _allocator
+    if (alloc is None) != (free is None):
+        raise ValueError("give both alloc and free, or neither")
+    if alloc is None:
+        _check(_lib.lib().arborx_set_allocator(None, None, None))
+        _allocator = None
+        return
+
+    def a(nbytes, stream, ctx):
+        try:
+            return alloc(int(nbytes), stream or 0) or None
+        except Exception:  # reported to the caller as ARBORX_E_NOMEM
+            return None
+
+    def f(ptr, stream, ctx):
+        free(ptr, stream or 0)
+
+    cbs = (_ALLOC_FN(a), _FREE_FN(f))
+    _check(_lib.lib().arborx_set_allocator(ctypes.cast(cbs[0], ctypes.c_void_p), ctypes.cast(cbs[1], ctypes.c_void_p),
+                                           None))
+    _allocator = cbs
+
+
+def use_torch_allocator(device=None) -> None:
+    """Serve the library's device memory from PyTorch's caching allocator, so that trees, forests
+    and per-call temporaries share torch's memory pool (and show in torch.cuda.memory_allocated)."""
+    torch = _torch()
+    dev = torch.cuda.current_device() if device is None else device
+    arborx_set_allocator(lambda n, s: torch.cuda.caching_allocator_alloc(n, dev, s),
+                         lambda p, s: torch.cuda.caching_allocator_delete(p))
+
+
 def arborx_set_tuning(block=0, order=1, stack=0, schedule=0, build=0, seed_mode=0, node_format=0,
                       queries_per_thread=0) -> None:
     t = _lib.Tuning(block, order, stack, schedule, build, seed_mode, node_format, queries_per_thread)

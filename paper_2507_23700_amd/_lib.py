@@ -18,6 +18,7 @@ P, I32, I64, F32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_flo
 SIGNATURES = {
     "arborx_version": (ctypes.c_char_p, []),
     "arborx_last_error": (ctypes.c_char_p, []),
+    "arborx_set_allocator": (I32, [P, P, P]),
     "arborx_set_tuning": (I32, [P]),
     "arborx_get_tuning": (I32, [P]),
     "arborx_set_tuning_op": (I32, [I32, P]),

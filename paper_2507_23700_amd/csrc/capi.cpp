@@ -2,8 +2,10 @@
 // stream handling, temporaries, and dispatch to the kernels.
 #include <cmath>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "device_util.hpp"
@@ -195,23 +197,127 @@ static void ensure_pool()
     g_pool_ready[dev] = true;
 }
 
+// Caller-supplied allocator (arborx_set_allocator).  Each block taken from
+// it is remembered with the stream it was allocated for; a block released on
+// another stream (after work there that may still be running) waits in
+// `pending` with an event until that work has completed.  The user's
+// functions are never called with the mutex held: they may run arbitrary code.
+struct UserAllocator {
+    arborx_alloc_fn alloc = nullptr;
+    arborx_free_fn free_ = nullptr;
+    void *ctx = nullptr;
+};
+struct PendingFree {
+    void *p;
+    hipStream_t owner;
+    hipEvent_t done;
+};
+static std::mutex g_alloc_mu;
+static UserAllocator g_user;
+static std::unordered_map<void *, hipStream_t> g_user_blocks;
+static std::vector<PendingFree> g_pending;
+static std::atomic<int64_t> g_default_live{0};
+
+// Hand back the pending blocks whose event has completed (all of them, after
+// waiting, if `wait`).
+static void drain_pending(bool wait)
+{
+    std::vector<PendingFree> ready;
+    UserAllocator u;
+    {
+        std::lock_guard<std::mutex> lock(g_alloc_mu);
+        u = g_user;
+        for (size_t i = 0; i < g_pending.size();) {
+            if (wait)
+                (void)hipEventSynchronize(g_pending[i].done);
+            const hipError_t q = hipEventQuery(g_pending[i].done);
+            if (q == hipSuccess || wait) {
+                ready.push_back(g_pending[i]);
+                g_pending[i] = g_pending.back();
+                g_pending.pop_back();
+            } else {
+                (void)hipGetLastError();  // "not ready" must not surface as a later call's error
+                ++i;
+            }
+        }
+    }
+    for (const PendingFree &f : ready) {
+        (void)hipEventDestroy(f.done);
+        if (u.free_)
+            u.free_(f.p, f.owner, u.ctx);
+    }
+}
+
 arborx_status dalloc(void **p, size_t bytes, hipStream_t s)
 {
-    ensure_pool();
     *p = nullptr;
+    UserAllocator u;
+    bool pending = false;
+    {
+        std::lock_guard<std::mutex> lock(g_alloc_mu);
+        u = g_user;
+        pending = !g_pending.empty();
+    }
+    if (u.alloc) {
+        if (pending)
+            drain_pending(false);
+        void *q = u.alloc(bytes ? bytes : 1, static_cast<void *>(s), u.ctx);
+        if (!q)
+            return fail(ARBORX_E_NOMEM, "the caller's allocator returned no memory for " + std::to_string(bytes) +
+                                            " bytes");
+        std::lock_guard<std::mutex> lock(g_alloc_mu);
+        g_user_blocks[q] = s;
+        *p = q;
+        return ARBORX_OK;
+    }
+    ensure_pool();
     hipError_t e = hipMallocAsync(p, bytes ? bytes : 1, s);
     if (e != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
         return fail(ARBORX_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
     }
+    ++g_default_live;
     return ARBORX_OK;
 }
 
+// Release p after the work queued on s so far.
 void dfree(void *p, hipStream_t s)
 {
-    if (p)
+    if (!p)
+        return;
+    UserAllocator u;
+    hipStream_t owner = nullptr;
+    bool user = false;
+    {
+        std::lock_guard<std::mutex> lock(g_alloc_mu);
+        auto it = g_user_blocks.find(p);
+        if (it != g_user_blocks.end()) {
+            user = true;
+            owner = it->second;
+            g_user_blocks.erase(it);
+            u = g_user;
+        }
+    }
+    if (!user) {
         (void)hipFreeAsync(p, s);
+        --g_default_live;
+        return;
+    }
+    if (s != owner) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess && hipEventRecord(e, s) == hipSuccess) {
+            std::lock_guard<std::mutex> lock(g_alloc_mu);
+            g_pending.push_back(PendingFree{p, owner, e});
+            return;
+        }
+        (void)hipGetLastError();
+        if (e)
+            (void)hipEventDestroy(e);
+        (void)hipStreamSynchronize(s);
+    }
+    if (u.free_)
+        u.free_(p, static_cast<void *>(owner), u.ctx);
 }
 
 static arborx_status check_device()
@@ -380,6 +486,20 @@ static void from_tuning(const Tuning &g, arborx_tuning *t)
     t->seed_mode = g.seed;
     t->node_format = g.nodes;
     t->queries_per_thread = g.packet;
+}
+
+arborx_status arborx_set_allocator(arborx_alloc_fn alloc_fn, arborx_free_fn free_fn, void *ctx)
+{
+    if (!alloc_fn != !free_fn)
+        return fail(ARBORX_E_INVALID, "alloc_fn and free_fn must both be given or both be NULL");
+    drain_pending(true);
+    std::lock_guard<std::mutex> lock(g_alloc_mu);
+    if (!g_user_blocks.empty() || !g_pending.empty() || g_default_live.load() != 0)
+        return fail(ARBORX_E_INVALID, "the library still holds device memory (a live tree, forest or plan)");
+    g_user.alloc = alloc_fn;
+    g_user.free_ = free_fn;
+    g_user.ctx = alloc_fn ? ctx : nullptr;
+    return ARBORX_OK;
 }
 
 arborx_status arborx_set_tuning(const arborx_tuning *t)

@@ -121,3 +121,16 @@ def test_python_tuning_roundtrip():
         assert ax.arborx_get_tuning_op(ax.OP_REDUCE)["node_format"] == 1
     finally:
         ax.arborx_reset_tuning()
+
+
+def test_allocator_hook_validation():
+    alloc = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)(lambda n, s, c: None)
+    free = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)(lambda p, s, c: None)
+    a, f = ctypes.cast(alloc, ctypes.c_void_p), ctypes.cast(free, ctypes.c_void_p)
+    assert L.arborx_set_allocator(a, None, None) == 1
+    assert L.arborx_set_allocator(None, f, None) == 1
+    assert "both" in _err()
+    assert L.arborx_set_allocator(a, f, None) == 0  # nothing is held: the hook may change
+    assert L.arborx_set_allocator(None, None, None) == 0
+    with pytest.raises(ValueError):
+        ax.arborx_set_allocator(lambda n, s: 0)
