@@ -299,11 +299,24 @@ def arborx_debug_tree_nodes(tree: Tree):
 # ---------------------------------------------------------------------------
 
 class Forest:
-    """Owns an arborx_forest handle; destroyed with the object."""
+    """Owns an arborx_forest handle; destroyed with the object.  Built by arborx_forest_build;
+    .reduce / .knn / .reserve / .info call the forest entry points on it."""
 
     def __init__(self, handle, T, n, dim, kind, values):
         self.handle, self.T, self.n, self.dim, self.kind = handle, T, n, dim, kind
         self._values = values
+
+    def info(self):
+        return arborx_forest_info(self)
+
+    def reserve(self, m, **kw):
+        arborx_forest_reserve(self, m, **kw)
+
+    def reduce(self, queries, batch_offsets, batch_tree, batch_radius, op=COUNT_SUMDIST, **kw):
+        return arborx_forest_query_reduce(self, queries, batch_offsets, batch_tree, batch_radius, op, **kw)
+
+    def knn(self, queries, batch_offsets, batch_tree, k, **kw):
+        return arborx_forest_query_knn(self, queries, batch_offsets, batch_tree, k, **kw)
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -652,27 +652,21 @@ __device__ __forceinline__ void seed_window(const float *__restrict__ leaves, in
     best.reset(best.bound());
 }
 
-// Nearest-first walk keeping the K best (d2, index) pairs sorted in
-// registers; a subtree is skipped only if its box is strictly farther than the
-// current K-th pair, so equal-distance values with smaller indices are found.
-//
-// Seeding: a greedy descent (nearer child first) finds the query's position in
-// the tree's sorted leaves; the K-th smallest distance among the 2K leaves
-// around it bounds the K-th nearest distance from above, so the walk starts
-// with that bound instead of +inf.  The heap then starts as K copies of
+// Seeding of a kNN walk: the query's position in the tree's sorted leaves
+// (binary search over the kept leaf codes, or a greedy nearer-child descent
+// when there are none); the K-th smallest distance among the 2K leaves around
+// it bounds the K-th nearest distance from above, so the walk starts with that
+// bound instead of +inf.  The heap then starts as K copies of
 // (bound, INT32_MAX): every value at distance < bound, or == bound, orders
 // before them, so all true results are still admitted, and none of the
 // placeholders survive when the tree has at least K values.
 template <int D, int K>
-__device__ __forceinline__ void knn_search(const Node<D> *__restrict__ nodes, int n_nodes,
-                                           const float *__restrict__ leaves, int kind, const TreeHeader &hdr,
-                                           const float *q, TopK<K> &best, ShortStack<KnnEntry> &st,
-                                           int seed, const uint64_t *__restrict__ codes)
+__device__ __forceinline__ void knn_seed(const Node<D> *__restrict__ nodes, int n_nodes,
+                                         const float *__restrict__ leaves, int kind, const TreeHeader &hdr,
+                                         const float *q, TopK<K> &best, int seed, const uint64_t *__restrict__ codes)
 {
     const int n = hdr.n;
-best.reset(INFINITY);
-    if (n <= 0)
-        return;
+    best.reset(INFINITY);
     if (seed != 1 && n >= K) {
         int cur = codes ? -1 : hdr.root, pos = codes ? leaf_position<D>(codes, hdr, q) : hdr.start;
         for (int iter = 0; iter <= n_nodes; ++iter) {
@@ -693,6 +687,20 @@ best.reset(INFINITY);
         // window of 2K leaves around pos inside [start, start + n)
         seed_window<D, K>(leaves, kind, hdr, pos, q, best, seed);
     }
+}
+
+// Nearest-first walk keeping the K best (d2, index) pairs sorted in
+// registers; a subtree is skipped only if its box is strictly farther than the
+// current K-th pair, so equal-distance values with smaller indices are found.
+template <int D, int K>
+__device__ __forceinline__ void knn_search(const Node<D> *__restrict__ nodes, int n_nodes,
+                                           const float *__restrict__ leaves, int kind, const TreeHeader &hdr,
+                                           const float *q, TopK<K> &best, ShortStack<KnnEntry> &st,
+                                           int seed, const uint64_t *__restrict__ codes)
+{
+    knn_seed<D, K>(nodes, n_nodes, leaves, kind, hdr, q, best, seed, codes);
+    if (hdr.n <= 0)
+        return;
     int cur = hdr.root;
     for (int iter = 0; iter <= n_nodes; ++iter) {
         if ((unsigned)cur >= (unsigned)n_nodes)

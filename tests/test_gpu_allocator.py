@@ -140,6 +140,10 @@ def test_torch_allocator_forest_and_chamfer():
     d2, ix = ax.arborx_forest_query_knn(f, dev(qs), dev(boff), dev(btree), 4)
     assert np.array_equal(host(c), oc) and np.array_equal(host(s), os_)
     assert np.array_equal(host(d2), od2) and np.array_equal(host(ix), oix)
+    c2, s2 = f.reduce(dev(qs), dev(boff), dev(btree), dev(brad))  # the handle's convenience methods
+    d22, ix2 = f.knn(dev(qs), dev(boff), dev(btree), 4)
+    assert np.array_equal(host(c2), oc) and np.array_equal(host(s2), os_) and np.array_equal(host(ix2), oix)
+    assert f.info()["T"] == 4
     a = dev(inputs.cube(900, 3, g))
     b = dev(inputs.cube(1100, 3, g))
     a_off = np.array([0, 400, 900], dtype=np.int64)
