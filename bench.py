@@ -307,6 +307,25 @@ def chamfer_bench(reps=3):
             "pairs_per_s": P / ((t_f + t_b) * 1e-3), "points_per_s": pts / ((t_f + t_b) * 1e-3)}
 
 
+def copy_bandwidth(torch, gib=1.0, reps=5):
+    """Measured device-to-device copy rate (bytes read + written per second, GB/s): the practical
+    HBM ceiling the roofline fraction is also reported against."""
+    n = int(gib * 2 ** 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 2 * 4 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -445,10 +464,12 @@ def main():
     avg_ms = prof[dom][0] / prof[dom][1]
     alg = algorithmic_bytes(dom, n, m, dim, k, total)
     achieved = alg / (avg_ms * 1e-3) / 1e9
+    copy_gbs = copy_bandwidth(torch)
     roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom, cfg["workload"]),
                 "valu_busy": profiled(dom, cfg["workload"], "valu_busy"),
-                "algorithmic_bytes_per_launch": alg, "avg_launch_ms": avg_ms}
+                "algorithmic_bytes_per_launch": alg, "avg_launch_ms": avg_ms,
+                "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs}
 
     cpu = None
     parity = None

@@ -1,0 +1,91 @@
+"""Parity at the benchmark's full sizes, with the default launch configuration
+the benchmark times: 10^7 uniform-cube and hollow-shell points in 3D (radius
+for ~10 neighbours, k = 16) and 2*10^6 Gaussian-mixture points in 6D (radius
+for ~20 neighbours, k = 8).  Seeded samples of queries are checked element by
+element against the oracle; every query is checked through properties that
+hold at any size (CSR offsets and ascending rows, counts equal across the
+three query forms, kNN rows ordered by (distance, index))."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2507_23700_amd as ax
+from paper_2507_23700_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SAMPLE = 192
+
+
+@pytest.fixture(autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ax.arborx_reset_tuning()
+    yield
+    torch.cuda.empty_cache()
+
+
+def workload(name):
+    if name == "gmm6":
+        return inputs.config_gmm6()
+    return inputs.config_paper(name, n=10_000_000)
+
+
+def check_rows_ascending(off, idx):
+    """Within every CSR row the indices increase strictly."""
+    inc = np.diff(idx.astype(np.int64)) > 0
+    row_start = np.zeros(len(idx), dtype=bool)
+    starts = off[:-1][np.diff(off) > 0]
+    row_start[starts] = True
+    # position i+1 starts a new row, or idx[i] < idx[i+1]
+    assert np.all(inc | row_start[1:])
+
+
+def check_knn_rows(d2, ix, n):
+    assert np.all(np.isfinite(d2)) and np.all((ix >= 0) & (ix < n))
+    dd = np.diff(d2, axis=1)
+    assert np.all(dd >= 0)
+    assert np.all((dd > 0) | (np.diff(ix.astype(np.int64), axis=1) > 0))
+
+
+@pytest.mark.parametrize("name", ["cube", "shell", "gmm6"])
+def test_full_size_sampled_parity_and_properties(name):
+    cfg = workload(name)
+    data, q, r, k = cfg["data"], cfg["queries"], float(cfg["radius"]), cfg["k"]
+    n, m, dim = len(data), len(q), data.shape[1]
+    print(f"full-size parity: {cfg['workload']} r={r} k={k}", flush=True)
+    d, qd = torch.from_numpy(data).cuda(), torch.from_numpy(q).cuda()
+    t = ax.arborx_bvh_build(d)
+    off_t, idx_t = ax.arborx_query_spatial(t, qd, r)
+    c_t, _ = ax.arborx_query_spatial_reduce(t, qd, r, ax.COUNT)
+    c2_t, s2_t = ax.arborx_query_spatial_reduce(t, qd, r, ax.COUNT_SUMDIST)
+    d2_t, ix_t = ax.arborx_query_knn(t, qd, k)
+    torch.cuda.synchronize()
+    off, idx = off_t.cpu().numpy(), idx_t.cpu().numpy()
+    c, c2, s2 = c_t.cpu().numpy(), c2_t.cpu().numpy(), s2_t.cpu().numpy()
+    d2, ix = d2_t.cpu().numpy(), ix_t.cpu().numpy()
+    del off_t, idx_t, c_t, c2_t, s2_t, d2_t, ix_t, t
+
+    # every query: properties
+    assert off[0] == 0 and off[-1] == len(idx) and np.all(np.diff(off) >= 0)
+    assert np.array_equal(np.diff(off), c) and np.array_equal(c, c2)
+    assert np.all((idx >= 0) & (idx < n))
+    check_rows_ascending(off, idx)
+    assert np.all(s2[c2 == 0] == 0) and np.all(s2 >= 0)
+    check_knn_rows(d2, ix, n)
+    mean = len(idx) / m
+    assert 5.0 < mean < 40.0  # the radius closed forms aim at ~10 (3D) and ~20 (6D) neighbours
+
+    # a seeded sample: element by element against the oracle
+    sel = np.sort(np.random.default_rng(2507).choice(m, SAMPLE, replace=False))
+    sq = np.ascontiguousarray(q[sel])
+    o_off, o_idx = oracle.spatial(data, sq, r, dim=dim)
+    o_c, o_s = oracle.reduce(data, sq, r, dim=dim)
+    o_d2, o_ix = oracle.knn(data, sq, k, dim=dim)
+    for j, i in enumerate(sel):
+        assert np.array_equal(idx[off[i]:off[i + 1]], o_idx[o_off[j]:o_off[j + 1]])
+    assert np.array_equal(c2[sel], o_c) and np.array_equal(s2[sel], o_s)
+    assert np.array_equal(ix[sel], o_ix) and np.array_equal(d2[sel], o_d2)
