@@ -97,7 +97,7 @@ KERNEL_PHASE = [  # rocprofv3 kernel name fragment -> phase name used by the in-
     ("k_knn<", "knn"), ("k_spatial_count<", "spatial_count"), ("k_spatial_reduce<3, false", "reduce_count"),
     ("k_spatial_reduce<3, true", "reduce_sumdist"), ("k_spatial_fill_rows<", "spatial_fill"),
     ("hierarchy_chunk_kernel<", "build_hierarchy"), ("hierarchy_top_kernel<", "build_hierarchy"),
-    ("k_copy_stash", "copy_stash"), ("radix_scatter<", "radix_scatter"), ("radix_hist<", "radix_hist"),
+    ("k_copy_stash", "copy_stash"), ("k_copy_overflow", "copy_overflow"), ("radix_scatter<", "radix_scatter"), ("radix_hist<", "radix_hist"),
 ]
 
 

@@ -107,6 +107,7 @@ struct arborx_plan_s {
     ax::Temps tmp;
     uint32_t *perm = nullptr;
     int32_t *counts = nullptr, *ordered_counts = nullptr, *stash = nullptr, *big_list = nullptr, *huge_list = nullptr;
+    ax::OverflowPool ovf{};
     ax::QueryHeader h{};
     arborx_plan_s(hipStream_t s) : tmp(s) {}
 };
@@ -664,13 +665,17 @@ static arborx_status csr_begin(arborx_tree t, Pred pred, const float *queries, i
     if ((st = p->tmp.get(&qh, 1)) != ARBORX_OK || (st = p->tmp.get(&p->counts, mm)) != ARBORX_OK ||
         (st = p->tmp.get(&p->ordered_counts, mm)) != ARBORX_OK ||
         (st = p->tmp.get(&p->stash, mm * stash_regs(t->dev.dim))) != ARBORX_OK ||
+        (st = p->tmp.get(&p->ovf.head, mm)) != ARBORX_OK ||
+        (st = p->tmp.get(&p->ovf.pool, overflow_pool_ints(mm, t->dev.dim))) != ARBORX_OK ||
+        (st = p->tmp.get(&p->ovf.ctr, (size_t)kOvfPools * 8)) != ARBORX_OK ||
         (st = p->tmp.get(&p->big_list, mm)) != ARBORX_OK || (st = p->tmp.get(&p->huge_list, mm)) != ARBORX_OK ||
         (st = p->tmp.get(&sws, scan_workspace_bytes(m))) != ARBORX_OK)
         return bail(st);
     if ((st = tree_order(t, queries, m, pred, OP_SPATIAL, &p->perm, p->tmp, s)) != ARBORX_OK)
         return bail(st);
-    if ((st = spatial_count(t->dev, pred, queries, m, radius, p->perm, p->counts, p->ordered_counts, p->stash, s)) !=
-        ARBORX_OK)
+    p->ovf.per = (int32_t)(overflow_pool_ints(mm, t->dev.dim) / kOvfPools);
+    if ((st = spatial_count(t->dev, pred, queries, m, radius, p->perm, p->counts, p->ordered_counts, p->stash, p->ovf,
+                            s)) != ARBORX_OK)
         return bail(st);
     {
         ProfScope ps("scan", s);
@@ -703,7 +708,7 @@ static arborx_status csr_finish(arborx_plan p, int32_t *indices, int64_t capacit
     if (p->h.total == 0)
         return ARBORX_OK;
     NoteUse note_use{p->tree->uses, p->stream};
-    arborx_status st = spatial_fill(p->tree->dev, p->pred, p->queries, p->m, p->radius, p->counts, p->stash,
+    arborx_status st = spatial_fill(p->tree->dev, p->pred, p->queries, p->m, p->radius, p->counts, p->stash, p->ovf,
                                     p->offsets, p->big_list, (int64_t)p->h.big_rows, p->huge_list,
                                     (int64_t)p->h.huge_rows, indices, p->stream);
     if (st != ARBORX_OK)

@@ -193,14 +193,34 @@ arborx_status chamfer_backward(const float *a, const int64_t *a_off, const float
 enum class Pred { Sphere, Box };
 arborx_status query_order(const TreeDev &t, const float *queries, int64_t m, Pred pred, int op, uint32_t **perm,
                           Temps &tmp, hipStream_t s);
+// Matches of a CSR count walk beyond a query's stash row, kept in chained
+// chunks of kChunk ints (the last int of a full chunk is the index of the
+// next chunk) taken from kOvfPools sub-pools, each with its own allocation
+// counter, chosen by workgroup so that allocations rarely contend.  A row
+// whose chunks would not fit, or that grows past kRowSortBlock, is marked for
+// a second walk instead.
+constexpr int kChunk = 32;
+constexpr int kOvfPools = 256;
+struct OverflowPool {
+    int32_t *head;                 // [m] first chunk of each row longer than the stash; -2: walk it again
+    int32_t *pool;                 // kOvfPools sub-pools of `per` ints each
+    unsigned long long *ctr;       // kOvfPools counters, one per 64 bytes (stride 8), zero before the walk
+    int32_t per;                   // ints per sub-pool, a multiple of kChunk
+};
+// Ints of the overflow pool for m queries (as many as the stash rows, at most
+// 2^31 - 1 in all, at least one chunk per sub-pool).
+int64_t overflow_pool_ints(int64_t m, int dim);
 // Count pass; also stores each query's first stash_regs(dim) matches in
-// stash[query][stash_regs(dim)], and (with perm) ordered_counts[t] = counts[perm[t]].
+// stash[query][stash_regs(dim)], further matches in ovf, and (with perm)
+// ordered_counts[t] = counts[perm[t]].
 arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
                             const uint32_t *perm, int32_t *counts, int32_t *ordered_counts, int32_t *stash,
-                            hipStream_t s);
-// Fill pass: stash rows are copied; listed longer rows are walked again.
+                            const OverflowPool &ovf, hipStream_t s);
+// Fill pass: stash rows are copied, listed longer rows are copied from the
+// stash and their overflow chunks, and the rest (huge rows, rows whose chunks
+// did not fit) are walked again.
 arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
-                           const int32_t *counts, const int32_t *stash,
+                           const int32_t *counts, const int32_t *stash, const OverflowPool &ovf,
                            const int64_t *offsets, const int32_t *big_list, int64_t nbig, const int32_t *huge_list,
                            int64_t nhuge, int32_t *indices, hipStream_t s);
 arborx_status sort_big_rows(const int64_t *offsets, int32_t *indices, const int32_t *big_list, int64_t nbig,

@@ -24,6 +24,41 @@ namespace {
 // Node slots of a single tree (one-value trees still have one node).
 __device__ __forceinline__ int node_count(const TreeHeader *hdr) { return hdr->n > 1 ? hdr->n - 1 : 1; }
 
+// Match number c (c >= R, counted from 0) of query qi, past its stash row of
+// R: stored in the query's overflow chain, whose current chunk is `cur` (one
+// register per query; -2 once the row is given up).  Chunks come from the
+// sub-pool of this workgroup as the row grows; the first one is recorded as
+// the row's head, each later one in the last slot of its predecessor.
+template <int R>
+__device__ __forceinline__ void overflow_add(const OverflowPool &o, int64_t qi, int c, int idx, int32_t &cur)
+{
+    if (cur == -2)
+        return;
+    const int k = c - R;
+    const int pos = k % (kChunk - 1);
+    if (c >= kRowSortBlock) {  // a huge row: walked again and sorted apart
+        cur = -2;
+        o.head[qi] = -2;
+        return;
+    }
+    if (pos == 0) {
+        const int sub = (int)(blockIdx.x % kOvfPools);
+        const unsigned long long b = atomicAdd(&o.ctr[sub * 8], (unsigned long long)kChunk);
+        if (b + kChunk > (unsigned long long)o.per) {  // pool exhausted: walk this row again
+            cur = -2;
+            o.head[qi] = -2;
+            return;
+        }
+        const int32_t next = sub * o.per + (int32_t)b;
+        if (k == 0)
+            o.head[qi] = next;
+        else
+            o.pool[cur + kChunk - 1] = next;
+        cur = next;
+    }
+    o.pool[cur + pos] = idx;
+}
+
 // Count pass of a CSR query.  With a stash, each query also keeps its first
 // stash_regs(D) matches in registers, in the order found, and stores them in
 // the stash row of its input position (one aligned 64-byte segment per
@@ -36,7 +71,8 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D
                                 const float *__restrict__ leaves, int kind, const TreeHeader *__restrict__ hdr,
                                 const float *__restrict__ queries, int64_t m, float r2,
                                 const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
-                                int32_t *__restrict__ ordered_counts, int32_t *__restrict__ stash, int stack_cap)
+                                int32_t *__restrict__ ordered_counts, int32_t *__restrict__ stash,
+                                OverflowPool ovf, int stack_cap)
 {
     extern __shared__ int s_stack[];
     const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
@@ -60,9 +96,14 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D
 #pragma unroll
     for (int k = 0; k < R; ++k)
         buf[k] = 0;
+    int32_t ov = -1;
     auto f = [&](int idx, float) {
-        if (STASH && c < R)
-            append_at<R>(buf, c, idx);
+        if (STASH) {
+            if (c < R)
+                append_at<R>(buf, c, idx);
+            else
+                overflow_add<R>(ovf, qi, c, idx, ov);
+        }
         ++c;
     };
     if (SCHED == 1)
@@ -92,11 +133,11 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D
 // answers the NQ queries at sorted positions NQ*t .. NQ*t + NQ - 1 in one walk,
 // each with its own register stash row.
 template <int D, int NQ>
-__global__ void k_spatial_count_packet(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+__global__ __attribute__((amdgpu_waves_per_eu(NQ == 2 && D <= 3 ? 6 : 1))) void k_spatial_count_packet(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
                                        const float *__restrict__ queries, int64_t m, float r2,
                                        const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
                                        int32_t *__restrict__ ordered_counts, int32_t *__restrict__ stash,
-                                       int stack_cap)
+                                       OverflowPool ovf, int stack_cap)
 {
     extern __shared__ int s_stack[];
     constexpr int R = stash_regs(D);
@@ -125,12 +166,18 @@ __global__ void k_spatial_count_packet(const Node<D> *__restrict__ nodes, const 
         for (int k = 0; k < R; ++k)
             buf[j][k] = 0;
     }
+    int32_t ov[NQ];
+#pragma unroll
+    for (int j = 0; j < NQ; ++j)
+        ov[j] = -1;
     auto f = [&](int j, int idx, float) {
 #pragma unroll
         for (int jj = 0; jj < NQ; ++jj)
             if (jj == j) {
                 if (c[jj] < R)
                     append_at<R>(buf[jj], c[jj], idx);
+                else
+                    overflow_add<R>(ovf, qi[jj], c[jj], idx, ov[jj]);
                 ++c[jj];
             }
     };
@@ -182,14 +229,47 @@ __global__ void k_copy_stash(const int32_t *__restrict__ stash, int64_t m, const
             indices[o + k] = v[k];
 }
 
-// Second walk for listed rows (longer than the stash): matches written in
-// traversal order, sorted afterwards.
+// Listed rows (longer than the stash, at most kRowSortBlock) whose overflow
+// chunks all fit: one wavefront per row copies the stash row, then the chunks
+// in chain order, into the row's CSR slot, in the order found; the rows are
+// sorted afterwards like walked ones.
+__global__ __launch_bounds__(256) void k_copy_overflow(const int32_t *__restrict__ stash, int R, OverflowPool ovf,
+                                                       const int32_t *__restrict__ counts,
+                                                       const int64_t *__restrict__ offsets,
+                                                       const int32_t *__restrict__ list, int64_t nb,
+                                                       int32_t *__restrict__ indices)
+{
+    const int lane = lane_id();
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); b < nb; b += waves) {
+        const int64_t row = list[b];
+        const int c = counts[row];
+        if (c <= R || c > kRowSortBlock)
+            continue;
+        int32_t cur = ovf.head[row];
+        if (cur < 0)
+            continue;
+        const int64_t o = offsets[row];
+        if (lane < R)
+            indices[o + lane] = stash[row * R + lane];
+        for (int done = R; done < c; done += kChunk - 1) {
+            const int n = c - done < kChunk - 1 ? c - done : kChunk - 1;
+            if (lane < n)
+                indices[o + done + lane] = ovf.pool[cur + lane];
+            if (done + n < c)
+                cur = ovf.pool[cur + kChunk - 1];
+        }
+    }
+}
+
+// Second walk for listed rows (longer than the stash) that were not kept in
+// overflow chunks: matches written in traversal order, sorted afterwards.
 template <int D, class P, int FMT>
 __global__ void k_spatial_fill_rows(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
                                     const Node4<D> *__restrict__ wnodes,
                                     const float *__restrict__ leaves, int kind, const TreeHeader *__restrict__ hdr,
                                     const float *__restrict__ queries, int64_t m, float r2,
-                                    const int32_t *__restrict__ rows, int64_t nrows,
+                                    const int32_t *__restrict__ rows, int64_t nrows, const int32_t *__restrict__ head,
                                     const int64_t *__restrict__ offsets, int32_t *__restrict__ indices, int stack_cap)
 {
     extern __shared__ int s_stack[];
@@ -198,6 +278,8 @@ __global__ void k_spatial_fill_rows(const Node<D> *__restrict__ nodes, const QNo
         return;
     const int64_t qi = rows[j];
     if (qi < 0 || qi >= m)
+        return;
+    if (head && head[qi] >= 0)  // copied from its overflow chunks
         return;
     P pred;
     pred.load(queries, qi, r2);
@@ -536,7 +618,8 @@ int effective_schedule(int op)
 
 template <int D>
 arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m, float r2, const uint32_t *perm,
-                         int32_t *counts, int32_t *ordered_counts, int32_t *stash, hipStream_t s)
+                         int32_t *counts, int32_t *ordered_counts, int32_t *stash, const OverflowPool &ovf,
+                         hipStream_t s)
 {
     const int sched = effective_schedule(OP_SPATIAL);
     const int nq = tuning(OP_SPATIAL).packet ? tuning(OP_SPATIAL).packet : (D <= 3 ? 2 : 1);
@@ -546,10 +629,12 @@ arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m,
         ProfScope ps("spatial_count", s);
         if (nq == 2)
             k_spatial_count_packet<D, 2><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, counts,
-                                                                        perm ? ordered_counts : nullptr, stash, L.cap);
+                                                                        perm ? ordered_counts : nullptr, stash, ovf,
+                                                                        L.cap);
         else
             k_spatial_count_packet<D, 4><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, counts,
-                                                                        perm ? ordered_counts : nullptr, stash, L.cap);
+                                                                        perm ? ordered_counts : nullptr, stash, ovf,
+                                                                        L.cap);
         AX_HIP(hipGetLastError());
         return ARBORX_OK;
     }
@@ -561,7 +646,7 @@ arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m,
 #define AX_COUNT(P, S)                                                                                     \
     k_spatial_count<D, P, true, S><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, wnodes, t.leaves, t.kind, t.hdr, q, m, r2, \
                                                                   perm, counts, perm ? ordered_counts : nullptr,  \
-                                                                  stash, L.cap)
+                                                                  stash, ovf, L.cap)
     if (pred == Pred::Sphere) {
         if (sched == 1)
             AX_COUNT(Sphere<D>, 1);
@@ -592,7 +677,8 @@ arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m,
 
 template <int D>
 arborx_status fill_rows_impl(const TreeDev &t, Pred pred, const float *q, int64_t m, float r2, const int32_t *rows,
-                             int64_t nrows, const int64_t *offsets, int32_t *indices, hipStream_t s)
+                             int64_t nrows, const int32_t *head, const int64_t *offsets, int32_t *indices,
+                             hipStream_t s)
 {
     if (nrows <= 0)
         return ARBORX_OK;
@@ -604,7 +690,7 @@ arborx_status fill_rows_impl(const TreeDev &t, Pred pred, const float *q, int64_
     ProfScope ps("spatial_fill", s);
 #define AX_FILL(P, F)                                                                                              \
     k_spatial_fill_rows<D, P, F><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, wnodes, t.leaves, t.kind, t.hdr, q, m, r2, \
-                                                                rows, nrows, offsets, indices, L.cap)
+                                                                rows, nrows, head, offsets, indices, L.cap)
     if (pred == Pred::Sphere) {
         if (fmt == 1)
             AX_FILL(Sphere<D>, 1);
@@ -776,7 +862,7 @@ arborx_status query_order(const TreeDev &t, const float *queries, int64_t m, Pre
 
 arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
                             const uint32_t *perm, int32_t *counts, int32_t *ordered_counts, int32_t *stash,
-                            hipStream_t s)
+                            const OverflowPool &ovf, hipStream_t s)
 {
     if (m == 0)
         return ARBORX_OK;
@@ -785,12 +871,23 @@ arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, i
     arborx_status st = check_nodes(t.qnodes, t.wnodes, t.n, walk_format(OP_SPATIAL));
     if (st != ARBORX_OK)
         return st;
+    if ((st = fill_async<unsigned long long>(ovf.ctr, (int64_t)kOvfPools * 8, 0ull, s)) != ARBORX_OK)
+        return st;
     const float r2 = radius * radius;
-    AX_DISPATCH_DIM(t.dim, (count_impl<D>(t, pred, queries, m, r2, perm, counts, ordered_counts, stash, s)));
+    AX_DISPATCH_DIM(t.dim, (count_impl<D>(t, pred, queries, m, r2, perm, counts, ordered_counts, stash, ovf, s)));
+}
+
+int64_t overflow_pool_ints(int64_t m, int dim)
+{
+    int64_t per = (m * stash_regs(dim) + kOvfPools - 1) / kOvfPools;
+    per = (per + kChunk - 1) / kChunk * kChunk;
+    const int64_t max_per = (int64_t)INT32_MAX / kOvfPools / kChunk * kChunk;
+    per = per < kChunk ? kChunk : (per > max_per ? max_per : per);
+    return per * kOvfPools;
 }
 
 arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
-                           const int32_t *counts, const int32_t *stash,
+                           const int32_t *counts, const int32_t *stash, const OverflowPool &ovf,
                            const int64_t *offsets, const int32_t *big_list, int64_t nbig, const int32_t *huge_list,
                            int64_t nhuge, int32_t *indices, hipStream_t s)
 {
@@ -807,19 +904,25 @@ arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, in
             k_copy_stash<16><<<grid_for(m, 256, INT32_MAX), 256, 0, s>>>(stash, m, counts, offsets, indices);
         AX_HIP(hipGetLastError());
     }
+    if (nbig > 0) {
+        ProfScope ps("copy_overflow", s);
+        k_copy_overflow<<<grid_for(nbig, 256 / kWave, 16384), 256, 0, s>>>(stash, stash_regs(t.dim), ovf, counts,
+                                                                            offsets, big_list, nbig, indices);
+        AX_HIP(hipGetLastError());
+    }
     const float r2 = radius * radius;
     switch (t.dim) {
     case 2:
-        if ((st = fill_rows_impl<2>(t, pred, queries, m, r2, big_list, nbig, offsets, indices, s)) == ARBORX_OK)
-            st = fill_rows_impl<2>(t, pred, queries, m, r2, huge_list, nhuge, offsets, indices, s);
+        if ((st = fill_rows_impl<2>(t, pred, queries, m, r2, big_list, nbig, ovf.head, offsets, indices, s)) == ARBORX_OK)
+            st = fill_rows_impl<2>(t, pred, queries, m, r2, huge_list, nhuge, nullptr, offsets, indices, s);
         return st;
     case 3:
-        if ((st = fill_rows_impl<3>(t, pred, queries, m, r2, big_list, nbig, offsets, indices, s)) == ARBORX_OK)
-            st = fill_rows_impl<3>(t, pred, queries, m, r2, huge_list, nhuge, offsets, indices, s);
+        if ((st = fill_rows_impl<3>(t, pred, queries, m, r2, big_list, nbig, ovf.head, offsets, indices, s)) == ARBORX_OK)
+            st = fill_rows_impl<3>(t, pred, queries, m, r2, huge_list, nhuge, nullptr, offsets, indices, s);
         return st;
     case 6:
-        if ((st = fill_rows_impl<6>(t, pred, queries, m, r2, big_list, nbig, offsets, indices, s)) == ARBORX_OK)
-            st = fill_rows_impl<6>(t, pred, queries, m, r2, huge_list, nhuge, offsets, indices, s);
+        if ((st = fill_rows_impl<6>(t, pred, queries, m, r2, big_list, nbig, ovf.head, offsets, indices, s)) == ARBORX_OK)
+            st = fill_rows_impl<6>(t, pred, queries, m, r2, huge_list, nhuge, nullptr, offsets, indices, s);
         return st;
     default:
         return fail(ARBORX_E_UNSUPPORTED, "dimension not compiled in");

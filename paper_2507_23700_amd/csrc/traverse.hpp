@@ -420,7 +420,7 @@ __device__ __forceinline__ long long fixed_term(float d2, float scale)
 {
     const float dist = sqrtf(d2);       // correctly rounded
     const float scaled = dist * scale;  // exact: scale is a power of two
-    return (long long)scaled;
+    return (long long)(unsigned long long)scaled;  // scaled >= 0: the unsigned conversion is shorter
 }
 
 // Store x in slot k of buf (k < C), with static indices only.
