@@ -505,6 +505,30 @@ def test_rows_around_stash_size():
     assert (lens == 16).any() and (lens == 17).any() and (lens > 40).any() and (lens < 16).any()
 
 
+@pytest.mark.parametrize("case", ["chains", "pool_runs_out", "wave", "rope", "quantized", "four_wide", "one_per_thread"])
+def test_overflow_chains(case):
+    # uniform points plus 20 dense blobs: queries near a blob centre have rows of several hundred matches,
+    # kept in chains of many overflow chunks; with few queries the pool is small and runs out, and those
+    # rows are walked a second time instead
+    g = np.random.default_rng(11)
+    hot = g.random((20, 3))
+    blob = hot[g.integers(0, 20, 12000)] + 0.003 * g.standard_normal((12000, 3))
+    data = np.concatenate([g.random((30000, 3)), blob]).astype(np.float32)
+    near = lambda n: hot[g.integers(0, 20, n)] + 0.001 * g.standard_normal((n, 3))
+    q = (near(60) if case == "pool_runs_out" else np.concatenate([g.random((20000, 3)), near(40)])).astype(np.float32)
+    tuning = dict(wave=dict(schedule=1), rope=dict(schedule=2), quantized=dict(node_format=1),
+                  four_wide=dict(node_format=2), one_per_thread=dict(queries_per_thread=1)).get(case, {})
+    ax.arborx_set_tuning(**tuning)
+    try:
+        t = ax.arborx_bvh_build(dev(data))
+        off = check_spatial(t, data, q, 0.01)
+    finally:
+        ax.arborx_reset_tuning()
+    lens = np.diff(off)
+    assert lens.max() > 16 + 5 * 31  # chains of several chunks
+    assert (lens == 0).any() or case == "pool_runs_out"
+
+
 @pytest.mark.parametrize("k", [1, 16, 64])
 def test_knn_seeding_off_identical(k):
     s = inputs.config_paper("shell", n=30_000, m=3000)
