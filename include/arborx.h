@@ -184,6 +184,9 @@ arborx_status arborx_bvh_info(arborx_tree tree, int64_t *n, int32_t *dim, int32_
  * Two-phase protocol: if indices is NULL or capacity < total, offsets and
  * *total are filled and ARBORX_E_CAPACITY is returned; call again with a
  * large enough buffer.  Synchronises `stream` (to read the total).
+ * Temporary device memory: about 4*(2*S + 5)*m bytes plus the query order,
+ * where S is the per-query register stash (16 matches; 32 in 6D): the stash
+ * rows and an overflow pool of the same size that keeps longer rows.
  */
 arborx_status arborx_query_spatial(arborx_tree tree, const float *queries, int64_t m, float radius, int64_t *offsets,
                                    int32_t *indices, int64_t capacity, int64_t *total, void *stream);

@@ -527,6 +527,12 @@ def test_overflow_chains(case):
     lens = np.diff(off)
     assert lens.max() > 16 + 5 * 31  # chains of several chunks
     assert (lens == 0).any() or case == "pool_runs_out"
+    if case == "chains":  # box queries take the same path
+        qb = np.ascontiguousarray(np.stack([q - 0.008, q + 0.008], axis=1))
+        off_b, idx_b = ax.arborx_query_intersects(t, dev(qb))
+        o_off, o_idx = oracle.intersects(data, qb)
+        assert np.array_equal(host(off_b), o_off) and np.array_equal(host(idx_b), o_idx)
+        assert np.diff(o_off).max() > 16 + 5 * 31
 
 
 @pytest.mark.parametrize("k", [1, 16, 64])
