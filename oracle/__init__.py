@@ -68,11 +68,12 @@ def lib():
         L.oracle_intersects_count.argtypes = [P, I64, I32, I32, P, I64, P]
         L.oracle_intersects_fill.argtypes = [P, I64, I32, I32, P, I64, P, P]
         L.oracle_reduce.argtypes = [P, I64, I32, I32, P, I64, F32, I32, I32, P, P]
+        L.oracle_count_up_to.argtypes = [P, I64, I32, I32, P, I64, F32, I32, P]
         L.oracle_knn.argtypes = [P, I64, I32, I32, P, I64, I32, P, P]
         L.oracle_chamfer_forward.argtypes = [P, P, P, P, I32, P, P, P]
         L.oracle_chamfer_backward.argtypes = [P, P, P, P, I32, P, P, P, P, P]
         for f in ("oracle_spatial_count", "oracle_spatial_fill", "oracle_intersects_count", "oracle_intersects_fill",
-                  "oracle_reduce", "oracle_knn", "oracle_chamfer_forward", "oracle_chamfer_backward",
+                  "oracle_reduce", "oracle_count_up_to", "oracle_knn", "oracle_chamfer_forward", "oracle_chamfer_backward",
                   "oracle_threads"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -151,6 +152,15 @@ def reduce(values, queries, radius, op=COUNT_SUMDIST, scale_bits=32, dim=3, kind
     sums = np.zeros(m, dtype=np.int64)
     lib().oracle_reduce(_p(v), n, dim, kind, _p(q), m, np.float32(radius), op, scale_bits, _p(counts), _p(sums))
     return counts, (sums if op == COUNT_SUMDIST else None)
+
+
+def count_up_to(values, queries, radius, n_max, dim=3, kind=POINTS):
+    """Early-terminating count (Section 2.2): each query stops at n_max matches; int32[m]."""
+    v, n = _values(values, dim, kind)
+    q, m = _queries(queries, dim, 1)
+    counts = np.zeros(m, dtype=np.int32)
+    lib().oracle_count_up_to(_p(v), n, dim, kind, _p(q), m, np.float32(radius), np.int32(n_max), _p(counts))
+    return counts
 
 
 def knn(values, queries, k, dim=3, kind=POINTS):

@@ -19,6 +19,8 @@
  *     (squared distance, index), padded with (+inf, -1) when k > n;
  *   - pure-callback queries (Section 2.2, query form (1)): per-query COUNT, and
  *     COUNT plus a fixed-point sum of distances, nothing stored per match;
+ *   - the early-terminating count of Section 2.2: a query stops once it has
+ *     counted n_max matches, so its result is min(count, n_max);
  *   - Chamfer loss of nearest-neighbour pairs and its gradient, in float64.
  *
  * Floating-point contract (the paper fixes none; this follows the exactness
@@ -198,6 +200,27 @@ int oracle_reduce(const float *values, int64_t n, int dim, int kind, const float
         counts[i] = c;
         if (op == RED_COUNT_SUMDIST)
             sum_fixed[i] = s;
+    }
+    return 0;
+}
+
+/* Early-terminating count (Section 2.2, the callback that stops a query's
+ * search once it has seen n_max matches): values are tested in index order
+ * and the count stops growing, and the scan ends, at n_max.  The paper's
+ * listing compares after a post-increment, which would let the count reach
+ * n_max + 1; the intended result, and this one, is min(count, n_max). */
+int oracle_count_up_to(const float *values, int64_t n, int dim, int kind, const float *queries, int64_t m,
+                       float radius, int32_t n_max, int32_t *counts)
+{
+    const float r2 = radius * radius;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < m; ++i) {
+        const float *q = queries + i * dim;
+        int32_t c = 0;
+        for (int64_t j = 0; j < n && c < n_max; ++j)
+            if (dist2_value(values, j, dim, kind, q) <= r2)
+                ++c;
+        counts[i] = c;
     }
     return 0;
 }

@@ -453,3 +453,27 @@ def test_forest_is_per_tree():
     d2, ix = oracle.forest_knn(values, toff, q, boff, bt, 4)
     assert np.all(ix[60:] == -1)
     assert ix[:30].max() < 400  # local indices
+
+
+def test_count_up_to_hand_worked_and_kdtree():
+    # the four collinear points of the line4 fixture, query x = 1.5: d2 = 2.25, 0.25, 0.25, 2.25
+    vals = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0], [3, 0, 0]], dtype=np.float32)
+    q = np.array([[1.5, 0, 0]], dtype=np.float32)
+    for r, n_max, want in [(0.5, 0, 0), (0.5, 1, 1), (0.5, 2, 2), (0.5, 5, 2), (1.6, 3, 3), (1.6, 9, 4),
+                           (0.49999997, 4, 0)]:
+        assert oracle.count_up_to(vals, q, r, n_max)[0] == want, (r, n_max)
+    # on random data: the count of a float64 k-d tree ball (radius bracketed away from ties), capped
+    g = np.random.default_rng(21)
+    data = g.random((3000, 3)).astype(np.float32)
+    qs = g.random((400, 3)).astype(np.float32)
+    r = 0.08
+    tree = cKDTree(data.astype(np.float64))
+    lo = np.array([len(x) for x in tree.query_ball_point(qs.astype(np.float64), r * (1 - 1e-5))])
+    hi = np.array([len(x) for x in tree.query_ball_point(qs.astype(np.float64), r * (1 + 1e-5))])
+    for n_max in (0, 1, 3, 7, 12, 10_000):
+        c = oracle.count_up_to(data, qs, r, n_max)
+        assert np.all(c >= np.minimum(lo, n_max)) and np.all(c <= np.minimum(hi, n_max))
+        # the paper's listing compares after a post-increment: that reading would reach n_max + 1
+        post = np.minimum(hi, n_max + 1)
+        if n_max < hi.max():
+            assert not np.array_equal(c, post)
