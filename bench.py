@@ -97,7 +97,7 @@ KERNEL_PHASE = [  # rocprofv3 kernel name fragment -> phase name used by the in-
     ("k_knn<", "knn"), ("k_spatial_count<", "spatial_count"), ("k_spatial_reduce<3, false", "reduce_count"),
     ("k_spatial_reduce<3, true", "reduce_sumdist"), ("k_spatial_fill_rows<", "spatial_fill"),
     ("hierarchy_chunk_kernel<", "build_hierarchy"), ("hierarchy_top_kernel<", "build_hierarchy"),
-    ("k_copy_stash", "copy_stash"), ("k_copy_overflow", "copy_overflow"), ("radix_scatter<", "radix_scatter"), ("radix_hist<", "radix_hist"),
+    ("k_copy_stash", "copy_stash"), ("k_copy_overflow", "copy_overflow"), ("k_count_up_to", "count_up_to"), ("radix_scatter<", "radix_scatter"), ("radix_hist<", "radix_hist"),
 ]
 
 
@@ -458,6 +458,11 @@ def main():
         "mean_neighbours": total / m,
         "kernel_ms_per_step": {kname: v[0] / args.steps for kname, v in sorted(prof.items())},
     }
+    # outside the step: the early-terminating count at limits below and above the mean row length
+    tree = state["tree"]
+    for n_max in (1, 5):
+        ms = timed(lambda: ax.arborx_query_spatial_count_up_to(tree, q, radius, n_max), 5)
+        comps[f"count_up_to{n_max}_qps"] = m / ms * 1e3
 
     # dominant kernel by GPU time in the timed region
     dom = max((kn for kn in prof if algorithmic_bytes(kn, n, m, dim, k, total)), key=lambda kn: prof[kn][0])

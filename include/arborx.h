@@ -245,6 +245,21 @@ arborx_status arborx_query_spatial_reduce(arborx_tree tree, const float *queries
                                           int32_t op, int32_t *counts, int64_t *sum_fixed, int32_t scale_bits,
                                           void *stream);
 
+/*
+ * Early-terminating count (Section 2.2: a callback may end a query's search
+ * once it has what it needs, here after n_max matches; the paper's example
+ * counts up to a limit).  counts[i] = min(number of values within radius of
+ * query i, n_max), exactly.  The walk of each query stops at its n_max-th
+ * match, so small limits are cheaper than a full COUNT.
+ *   queries  [m][dim] query points;  radius >= 0 (may be +inf), NaN is ARBORX_E_INVALID
+ *   n_max    >= 0 (0 gives all zeros without a walk)
+ *   counts   [m] int32 output
+ * Uses the thread walk over binary nodes with the block size, stack depth and
+ * query order of ARBORX_OP_REDUCE.  Asynchronous.
+ */
+arborx_status arborx_query_spatial_count_up_to(arborx_tree tree, const float *queries, int64_t m, float radius,
+                                               int32_t n_max, int32_t *counts, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Forest: many independent trees in one structure, queried in one launch.  */
 /* ------------------------------------------------------------------------ */

@@ -256,6 +256,17 @@ def arborx_query_spatial_reduce(tree: Tree, queries, radius: float, op=COUNT_SUM
     return counts, sums
 
 
+def arborx_query_spatial_count_up_to(tree: Tree, queries, radius: float, n_max: int, stream=None):
+    """Early-terminating count: int32[m] = min(matches within radius, n_max)."""
+    torch = _torch()
+    q = _queries(tree, queries, False)
+    m = q.shape[0]
+    counts = torch.empty(m, dtype=torch.int32, device=q.device)
+    _check(_lib.lib().arborx_query_spatial_count_up_to(tree.handle, _ptr(q), m, ctypes.c_float(radius), int(n_max),
+                                                       _ptr(counts), _stream(stream)))
+    return counts
+
+
 def arborx_debug_radix_sort(keys, values, begin_bit=0, end_bit=None, stream=None):
     """In-place stable sort of (keys int64/int32 viewed as unsigned, values int32) by key bits."""
     torch = _torch()
@@ -498,6 +509,9 @@ class BVH:
 
     def count(self, queries, radius, **kw):
         return arborx_query_spatial_reduce(self.tree, queries, radius, COUNT, **kw)[0]
+
+    def count_up_to(self, queries, radius, n_max, **kw):
+        return arborx_query_spatial_count_up_to(self.tree, queries, radius, n_max, **kw)
 
     def count_sumdist(self, queries, radius, scale_bits=32, **kw):
         return arborx_query_spatial_reduce(self.tree, queries, radius, COUNT_SUMDIST, scale_bits, **kw)

@@ -824,6 +824,33 @@ arborx_status arborx_query_spatial_reduce(arborx_tree t, const float *queries, i
     return spatial_reduce(t->dev, queries, m, radius, op, scale_bits, perm, counts, sum_fixed, s);
 }
 
+arborx_status arborx_query_spatial_count_up_to(arborx_tree t, const float *queries, int64_t m, float radius,
+                                               int32_t n_max, int32_t *counts, void *stream)
+{
+    arborx_status st = check_tree(t);
+    if (st != ARBORX_OK)
+        return st;
+    if (m < 0)
+        return fail(ARBORX_E_INVALID, "m must be >= 0");
+    if (std::isnan(radius) || radius < 0.0f)
+        return fail(ARBORX_E_INVALID, "radius must be >= 0 and not NaN");
+    if (n_max < 0)
+        return fail(ARBORX_E_INVALID, "n_max must be >= 0");
+    if (m > 0 && (!queries || !counts))
+        return fail(ARBORX_E_INVALID, "queries and counts must not be NULL");
+    if ((st = check_device()) != ARBORX_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = wait_tree(t, s)) != ARBORX_OK)
+        return st;
+    NoteUse note_use{t->uses, s};
+    Temps tmp(s);
+    uint32_t *perm = nullptr;
+    if (n_max > 0 && (st = tree_order(t, queries, m, Pred::Sphere, OP_REDUCE, &perm, tmp, s)) != ARBORX_OK)
+        return st;
+    return spatial_count_up_to(t->dev, queries, m, radius, n_max, perm, counts, s);
+}
+
 // ---------------------------------------------------------------------------
 // forest
 // ---------------------------------------------------------------------------

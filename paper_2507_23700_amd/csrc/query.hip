@@ -542,6 +542,32 @@ __global__ void k_knn(const Node<D> *__restrict__ nodes, const QNode<D> *__restr
         best.store(k_out, out_d2 + qi * k_out, out_idx + qi * k_out, 0);
 }
 
+// Early-terminating count (Section 2.2): a query's walk over binary nodes ends
+// once it has counted n_max matches; the result is min(count, n_max).
+template <int D>
+__global__ void k_count_up_to(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+                              const float *__restrict__ queries, int64_t m, float r2, int n_max,
+                              const uint32_t *__restrict__ perm, int32_t *__restrict__ counts, int stack_cap)
+{
+    extern __shared__ int s_stack[];
+    const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
+    if (t >= m)
+        return;
+    const int64_t qi = perm ? (int64_t)perm[t] : t;
+    if (qi < 0 || qi >= m)
+        return;
+    Sphere<D> pred;
+    pred.load(queries, qi, r2);
+    int spill[kSpill];
+    ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap, spill);
+    int c = 0;
+    auto f = [&](int, float) { ++c; };
+    auto stop = [&]() { return c >= n_max; };
+    if (n_max > 0)
+        traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f, stop);
+    counts[qi] = c < n_max ? c : n_max;
+}
+
 __global__ void k_knn_empty(int64_t total, float *d2, int32_t *idx)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
@@ -998,6 +1024,29 @@ arborx_status spatial_reduce(const TreeDev &t, const float *queries, int64_t m, 
     const float r2 = radius * radius;
     const float scale = ldexpf(1.0f, scale_bits);
     AX_DISPATCH_DIM(t.dim, (reduce_impl<D>(t, queries, m, r2, op, scale, perm, counts, sums, s)));
+}
+
+template <int D>
+arborx_status count_up_to_impl(const TreeDev &t, const float *q, int64_t m, float r2, int n_max,
+                               const uint32_t *perm, int32_t *counts, hipStream_t s)
+{
+    const Launch L = traversal_launch(m, sizeof(int), OP_REDUCE);
+    ProfScope ps("count_up_to", s);
+    k_count_up_to<D><<<L.grid, L.block, L.lds, s>>>(static_cast<const Node<D> *>(t.nodes), t.hdr, q, m, r2, n_max,
+                                                      perm, counts, L.cap);
+    AX_HIP(hipGetLastError());
+    return ARBORX_OK;
+}
+
+arborx_status spatial_count_up_to(const TreeDev &t, const float *queries, int64_t m, float radius, int n_max,
+                                  const uint32_t *perm, int32_t *counts, hipStream_t s)
+{
+    if (m == 0)
+        return ARBORX_OK;
+    if (t.n == 0 || n_max == 0)
+        return fill_async<int32_t>(counts, m, 0, s);
+    const float r2 = radius * radius;
+    AX_DISPATCH_DIM(t.dim, (count_up_to_impl<D>(t, queries, m, r2, n_max, perm, counts, s)));
 }
 
 arborx_status knn_query(const TreeDev &t, const float *queries, int64_t m, int k, const uint32_t *perm,

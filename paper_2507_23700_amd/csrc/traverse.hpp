@@ -129,13 +129,19 @@ __device__ __forceinline__ void leaf_exact(const float *__restrict__ leaves, int
         f(__float_as_int(lf[kind == ARBORX_BOXES ? 2 * D : D]), d2);
 }
 
-// Depth-first walk calling f(index, d2) on every matching value.
+struct NeverStop {
+    __device__ __forceinline__ constexpr bool operator()() const { return false; }
+};
+
+// Depth-first walk calling f(index, d2) on every matching value; with a stop
+// functor, the walk ends as soon as stop() holds after a node's matches were
+// reported (the early termination of Section 2.2).
 // A depth-first walk enters each internal node at most once, so `limit`
 // iterations (more than the node count) bound every walk even on a corrupt
 // tree, and node indices are range-checked before use.
-template <int D, class P, class F>
+template <int D, class P, class F, class S = NeverStop>
 __device__ __forceinline__ void traverse_spatial(const Node<D> *__restrict__ nodes, int root, int n_nodes,
-                                                 const P &pred, ShortStack<int> &st, F &f)
+                                                 const P &pred, ShortStack<int> &st, F &f, const S &stop = S())
 {
     int cur = root;
     for (int iter = 0; iter <= n_nodes; ++iter) {
@@ -157,6 +163,8 @@ __device__ __forceinline__ void traverse_spatial(const Node<D> *__restrict__ nod
                 f(~c1, d1);
             h1 = false;
         }
+        if (stop())
+            break;
         if (h0) {
             if (h1)
                 st.push(c1);

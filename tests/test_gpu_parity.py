@@ -641,3 +641,41 @@ def test_four_wide_small_trees_and_duplicates(n):
         check_reduce(t, data, q, 0.3)
     finally:
         ax.arborx_reset_tuning()
+
+
+@pytest.mark.parametrize("case", ["cube", "clusters", "boxes_tree", "dim6", "tuned"])
+def test_count_up_to(case):
+    g = np.random.default_rng(31)
+    kind, dim = oracle.POINTS, 3
+    if case == "clusters":  # rows from 0 to several hundred matches
+        hot = g.random((20, 3))
+        data = np.concatenate([g.random((20000, 3)), hot[g.integers(0, 20, 8000)] + 0.003 * g.standard_normal((8000, 3))])
+        data = data.astype(np.float32)
+        q = np.concatenate([g.random((3000, 3)), hot[g.integers(0, 20, 200)]]).astype(np.float32)
+        r = 0.01
+    elif case == "boxes_tree":
+        c = g.random((6000, 3)).astype(np.float32)
+        h = (g.random((6000, 3)) * 0.01).astype(np.float32)
+        data = np.ascontiguousarray(np.stack([c - h, c + h], axis=1))
+        q, r, kind = g.random((2001, 3)).astype(np.float32), 0.03, oracle.BOXES
+    elif case == "dim6":
+        cfg = inputs.config_gmm6(n=20_000, m=2001)
+        data, q, r, dim = cfg["data"], cfg["queries"], float(cfg["radius"]), 6
+    else:
+        cfg = inputs.config_small(n=20_000, m=4001)
+        data, q, r = cfg["data"], cfg["queries"], float(cfg["radius"])
+    if case == "tuned":
+        ax.arborx_set_tuning(block=64, stack=2, order=0)
+    try:
+        t = ax.arborx_bvh_build(dev(data), ax.BOXES if kind == oracle.BOXES else ax.POINTS)
+        full, _ = oracle.reduce(data, q, r, op=oracle.COUNT, dim=dim, kind=kind)
+        for n_max in (0, 1, 2, 7, 16, 100, 2 ** 31 - 1):
+            got = host(ax.arborx_query_spatial_count_up_to(t, dev(q), r, n_max))
+            assert np.array_equal(got, oracle.count_up_to(data, q, r, n_max, dim=dim, kind=kind)), n_max
+            assert np.array_equal(got, np.minimum(full, n_max))
+        got = host(ax.arborx_query_spatial_count_up_to(t, dev(q), float("inf"), 50))
+        assert np.all(got == min(50, len(data)))
+    finally:
+        ax.arborx_reset_tuning()
+    e = ax.arborx_bvh_build(dev(np.zeros((0, dim), dtype=np.float32)))
+    assert np.all(host(ax.arborx_query_spatial_count_up_to(e, dev(q[:, :dim] if q.ndim == 2 else q), 1.0, 3)) == 0)
