@@ -69,6 +69,7 @@ def lib():
         L.oracle_intersects_fill.argtypes = [P, I64, I32, I32, P, I64, P, P]
         L.oracle_reduce.argtypes = [P, I64, I32, I32, P, I64, F32, I32, I32, P, P]
         L.oracle_count_up_to.argtypes = [P, I64, I32, I32, P, I64, F32, I32, P]
+        L.oracle_match_distances.argtypes = [P, I64, I32, I32, P, I64, P, P, P]
         L.oracle_knn.argtypes = [P, I64, I32, I32, P, I64, I32, P, P]
         L.oracle_chamfer_forward.argtypes = [P, P, P, P, I32, P, P, P]
         L.oracle_chamfer_backward.argtypes = [P, P, P, P, I32, P, P, P, P, P]
@@ -152,6 +153,17 @@ def reduce(values, queries, radius, op=COUNT_SUMDIST, scale_bits=32, dim=3, kind
     sums = np.zeros(m, dtype=np.int64)
     lib().oracle_reduce(_p(v), n, dim, kind, _p(q), m, np.float32(radius), op, scale_bits, _p(counts), _p(sums))
     return counts, (sums if op == COUNT_SUMDIST else None)
+
+
+def match_distances(values, queries, offsets, indices, dim=3, kind=POINTS):
+    """Callback with output (Section 2.1, query call (2)): float32 squared distance of every CSR match."""
+    v, n = _values(values, dim, kind)
+    q, m = _queries(queries, dim, 1)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    idx = np.ascontiguousarray(indices, dtype=np.int32)
+    out = np.zeros(len(idx), dtype=np.float32)
+    lib().oracle_match_distances(_p(v), n, dim, kind, _p(q), m, _p(off), _p(idx), _p(out))
+    return out
 
 
 def count_up_to(values, queries, radius, n_max, dim=3, kind=POINTS):

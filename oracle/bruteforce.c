@@ -21,6 +21,8 @@
  *     COUNT plus a fixed-point sum of distances, nothing stored per match;
  *   - the early-terminating count of Section 2.2: a query stops once it has
  *     counted n_max matches, so its result is min(count, n_max);
+ *   - the callback-with-output form (Section 2.1, query call (2)) as the
+ *     squared distance of each match of a CSR result;
  *   - Chamfer loss of nearest-neighbour pairs and its gradient, in float64.
  *
  * Floating-point contract (the paper fixes none; this follows the exactness
@@ -201,6 +203,20 @@ int oracle_reduce(const float *values, int64_t n, int dim, int kind, const float
         if (op == RED_COUNT_SUMDIST)
             sum_fixed[i] = s;
     }
+    return 0;
+}
+
+/* Callback with output (Section 2.1, query call (2)): for every match of a
+ * CSR result (row i of offsets/indices belongs to query i), the squared
+ * distance between query i and the matched value, as in the search itself. */
+int oracle_match_distances(const float *values, int64_t n, int dim, int kind, const float *queries, int64_t m,
+                           const int64_t *offsets, const int32_t *indices, float *out)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t p = offsets[i]; p < offsets[i + 1]; ++p)
+            out[p] = (indices[p] >= 0 && indices[p] < n) ? dist2_value(values, indices[p], dim, kind, queries + i * dim)
+                                                         : NAN;
     return 0;
 }
 

@@ -477,3 +477,27 @@ def test_count_up_to_hand_worked_and_kdtree():
         post = np.minimum(hi, n_max + 1)
         if n_max < hi.max():
             assert not np.array_equal(c, post)
+
+
+def test_match_distances_hand_worked_and_kdtree():
+    vals = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0], [3, 0, 0]], dtype=np.float32)
+    q = np.array([[1.5, 0, 0]], dtype=np.float32)
+    off, idx = oracle.spatial(vals, q, 0.5)
+    assert list(idx) == [1, 2] and list(oracle.match_distances(vals, q, off, idx)) == [0.25, 0.25]
+    off, idx = oracle.spatial(vals, q, float("inf"))
+    assert list(oracle.match_distances(vals, q, off, idx)) == [2.25, 0.25, 0.25, 2.25]
+    # random data: float64 k-d tree distances agree to float32 rounding, and every distance is within r
+    g = np.random.default_rng(22)
+    data = g.random((2000, 3)).astype(np.float32)
+    qs = g.random((300, 3)).astype(np.float32)
+    r = 0.09
+    off, idx = oracle.spatial(data, qs, r)
+    d2 = oracle.match_distances(data, qs, off, idx)
+    rows = np.repeat(np.arange(len(qs)), np.diff(off))
+    ref = np.sum((qs[rows].astype(np.float64) - data[idx].astype(np.float64)) ** 2, axis=1)
+    assert np.allclose(d2, ref, rtol=1e-6, atol=1e-12) and np.all(d2 <= np.float32(r) * np.float32(r))
+    # box values: zero inside the box, the face distance outside
+    boxes = np.array([[[0, 0, 0], [1, 1, 1]]], dtype=np.float32)
+    qb = np.array([[0.5, 0.5, 0.5], [2.0, 0.5, 0.5]], dtype=np.float32)
+    off, idx = oracle.spatial(boxes, qb, 2.0, kind=oracle.BOXES)
+    assert list(oracle.match_distances(boxes, qb, off, idx, kind=oracle.BOXES)) == [0.0, 1.0]
