@@ -260,6 +260,19 @@ arborx_status arborx_query_spatial_reduce(arborx_tree tree, const float *queries
 arborx_status arborx_query_spatial_count_up_to(arborx_tree tree, const float *queries, int64_t m, float radius,
                                                int32_t n_max, int32_t *counts, void *stream);
 
+/*
+ * Callback with output (Section 2.1, query call (2), e.g. returning each
+ * match's distance): the float32 squared distance of every match of a radius
+ * search's CSR result, evaluated exactly as in the search.
+ *   values    the array the tree was built from (unchanged since the build)
+ *   queries   [m][dim] the radius query's points;  offsets [m+1], indices [total] its result
+ *   distances [total] float32 output aligned with indices (NaN for an index outside the tree)
+ * Asynchronous; stream-ordered after the search when issued on its stream.
+ */
+arborx_status arborx_query_match_distances(arborx_tree tree, const float *values, const float *queries, int64_t m,
+                                           const int64_t *offsets, const int32_t *indices, float *distances,
+                                           void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Forest: many independent trees in one structure, queried in one launch.  */
 /* ------------------------------------------------------------------------ */

@@ -256,6 +256,30 @@ def arborx_query_spatial_reduce(tree: Tree, queries, radius: float, op=COUNT_SUM
     return counts, sums
 
 
+def arborx_query_match_distances(tree: Tree, values, queries, offsets, indices, stream=None):
+    """Callback with output: float32 squared distance of every match of a radius CSR result."""
+    torch = _torch()
+    v = _dev(values, torch.float32, "values")
+    want = (tree.n, 2, tree.dim) if tree.kind == BOXES else (tree.n, tree.dim)
+    if tuple(v.shape) != want:
+        raise ValueError(f"values must be the build input, shape {list(want)}")
+    q = _queries(tree, queries, False)
+    off = _dev(offsets, torch.int64, "offsets")
+    if off.shape[0] != q.shape[0] + 1:
+        raise ValueError("offsets must have m + 1 entries")
+    idx = _dev(indices, torch.int32, "indices")
+    out = torch.empty(idx.shape[0], dtype=torch.float32, device=q.device)
+    _check(_lib.lib().arborx_query_match_distances(tree.handle, _ptr(v), _ptr(q), q.shape[0], _ptr(off), _ptr(idx),
+                                                   _ptr(out), _stream(stream)))
+    return out
+
+
+def arborx_query_spatial_with_distances(tree: Tree, values, queries, radius: float, stream=None):
+    """Radius search returning (offsets, indices, squared distances) in CSR form."""
+    off, idx = arborx_query_spatial(tree, queries, radius, stream=stream)
+    return off, idx, arborx_query_match_distances(tree, values, queries, off, idx, stream=stream)
+
+
 def arborx_query_spatial_count_up_to(tree: Tree, queries, radius: float, n_max: int, stream=None):
     """Early-terminating count: int32[m] = min(matches within radius, n_max)."""
     torch = _torch()
@@ -484,6 +508,7 @@ class BVH:
 
     def __init__(self, values, kind=POINTS, stream=None):
         self.tree = arborx_bvh_build(values, kind, stream)
+        self.values = values
 
     def info(self):
         return arborx_bvh_info(self.tree)
@@ -509,6 +534,9 @@ class BVH:
 
     def count(self, queries, radius, **kw):
         return arborx_query_spatial_reduce(self.tree, queries, radius, COUNT, **kw)[0]
+
+    def spatial_with_distances(self, queries, radius, **kw):
+        return arborx_query_spatial_with_distances(self.tree, self.values, queries, radius, **kw)
 
     def count_up_to(self, queries, radius, n_max, **kw):
         return arborx_query_spatial_count_up_to(self.tree, queries, radius, n_max, **kw)

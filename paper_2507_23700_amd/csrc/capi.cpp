@@ -824,6 +824,25 @@ arborx_status arborx_query_spatial_reduce(arborx_tree t, const float *queries, i
     return spatial_reduce(t->dev, queries, m, radius, op, scale_bits, perm, counts, sum_fixed, s);
 }
 
+arborx_status arborx_query_match_distances(arborx_tree t, const float *values, const float *queries, int64_t m,
+                                           const int64_t *offsets, const int32_t *indices, float *distances,
+                                           void *stream)
+{
+    arborx_status st = check_tree(t);
+    if (st != ARBORX_OK)
+        return st;
+    if (m < 0)
+        return fail(ARBORX_E_INVALID, "m must be >= 0");
+    if (m > 0 && (!queries || !offsets || (t->dev.n > 0 && (!values || !indices || !distances))))
+        return fail(ARBORX_E_INVALID, "values, queries, offsets, indices and distances must not be NULL");
+    if ((st = check_device()) != ARBORX_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = wait_tree(t, s)) != ARBORX_OK)
+        return st;
+    return match_distances(t->dev, values, queries, m, offsets, indices, distances, s);
+}
+
 arborx_status arborx_query_spatial_count_up_to(arborx_tree t, const float *queries, int64_t m, float radius,
                                                int32_t n_max, int32_t *counts, void *stream)
 {

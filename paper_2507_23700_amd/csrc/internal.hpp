@@ -229,6 +229,9 @@ arborx_status sort_huge_rows(int64_t n_values, const int64_t *offsets, int32_t *
                              int64_t h, Temps &tmp, hipStream_t s);
 arborx_status spatial_reduce(const TreeDev &t, const float *queries, int64_t m, float radius, int op,
                              int scale_bits, const uint32_t *perm, int32_t *counts, int64_t *sums, hipStream_t s);
+// out[p] = squared distance of match p (CSR row i = query i) from the build input.
+arborx_status match_distances(const TreeDev &t, const float *values, const float *queries, int64_t m,
+                              const int64_t *offsets, const int32_t *indices, float *out, hipStream_t s);
 // Early-terminating count: counts[i] = min(matches of query i, n_max).
 arborx_status spatial_count_up_to(const TreeDev &t, const float *queries, int64_t m, float radius, int n_max,
                                   const uint32_t *perm, int32_t *counts, hipStream_t s);

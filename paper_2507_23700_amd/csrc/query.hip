@@ -542,6 +542,39 @@ __global__ void k_knn(const Node<D> *__restrict__ nodes, const QNode<D> *__restr
         best.store(k_out, out_d2 + qi * k_out, out_idx + qi * k_out, 0);
 }
 
+// Callback with output (Section 2.1, query call (2)): the squared distance of
+// every match of a radius search's CSR result, evaluated as in the walk (the
+// box distance with lo = hi for points) from the build input.  One thread per
+// query row, so the row's outputs are contiguous.
+template <int D>
+__global__ void k_match_distances(const float *__restrict__ values, int64_t n, int kind,
+                                  const float *__restrict__ queries, int64_t m, const int64_t *__restrict__ offsets,
+                                  const int32_t *__restrict__ indices, float *__restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        float q[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            q[d] = queries[i * D + d];
+        const int64_t end = offsets[i + 1];
+        for (int64_t p = offsets[i]; p < end; ++p) {
+            const int64_t j = indices[p];
+            if (j < 0 || j >= n) {
+                out[p] = NAN;
+                continue;
+            }
+            const float *v = values + j * (kind == ARBORX_BOXES ? 2 * D : D);
+            float lo[D], hi[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                lo[d] = v[d];
+                hi[d] = kind == ARBORX_BOXES ? v[D + d] : v[d];
+            }
+            out[p] = box_d2<D>(q, lo, hi);
+        }
+    }
+}
+
 // Early-terminating count (Section 2.2): a query's walk over binary nodes ends
 // once it has counted n_max matches; the result is min(count, n_max).
 template <int D>
@@ -1047,6 +1080,25 @@ arborx_status spatial_count_up_to(const TreeDev &t, const float *queries, int64_
         return fill_async<int32_t>(counts, m, 0, s);
     const float r2 = radius * radius;
     AX_DISPATCH_DIM(t.dim, (count_up_to_impl<D>(t, queries, m, r2, n_max, perm, counts, s)));
+}
+
+arborx_status match_distances(const TreeDev &t, const float *values, const float *queries, int64_t m,
+                              const int64_t *offsets, const int32_t *indices, float *out, hipStream_t s)
+{
+    if (m == 0 || t.n == 0)
+        return ARBORX_OK;
+    ProfScope ps("match_distances", s);
+#define AX_MD(DD) k_match_distances<DD><<<grid_for(m, 256, 65536), 256, 0, s>>>(values, t.n, t.kind, queries, m, \
+                                                                                offsets, indices, out)
+    switch (t.dim) {
+    case 2: AX_MD(2); break;
+    case 3: AX_MD(3); break;
+    case 6: AX_MD(6); break;
+    default: return fail(ARBORX_E_UNSUPPORTED, "dimension not compiled in");
+    }
+#undef AX_MD
+    AX_HIP(hipGetLastError());
+    return ARBORX_OK;
 }
 
 arborx_status knn_query(const TreeDev &t, const float *queries, int64_t m, int k, const uint32_t *perm,

@@ -64,12 +64,14 @@ def test_full_size_sampled_parity_and_properties(name):
     c2_t, s2_t = ax.arborx_query_spatial_reduce(t, qd, r, ax.COUNT_SUMDIST)
     d2_t, ix_t = ax.arborx_query_knn(t, qd, k)
     u5_t = ax.arborx_query_spatial_count_up_to(t, qd, r, 5)
+    md_t = ax.arborx_query_match_distances(t, d, qd, off_t, idx_t)
     torch.cuda.synchronize()
     off, idx = off_t.cpu().numpy(), idx_t.cpu().numpy()
     c, c2, s2 = c_t.cpu().numpy(), c2_t.cpu().numpy(), s2_t.cpu().numpy()
     d2, ix = d2_t.cpu().numpy(), ix_t.cpu().numpy()
     u5 = u5_t.cpu().numpy()
-    del off_t, idx_t, c_t, c2_t, s2_t, d2_t, ix_t, u5_t, t
+    md = md_t.cpu().numpy()
+    del off_t, idx_t, c_t, c2_t, s2_t, d2_t, ix_t, u5_t, md_t, t
 
     # every query: properties
     assert off[0] == 0 and off[-1] == len(idx) and np.all(np.diff(off) >= 0)
@@ -79,6 +81,7 @@ def test_full_size_sampled_parity_and_properties(name):
     assert np.all(s2[c2 == 0] == 0) and np.all(s2 >= 0)
     check_knn_rows(d2, ix, n)
     assert np.array_equal(u5, np.minimum(c, 5))
+    assert np.all(md <= np.float32(r) * np.float32(r)) and np.all(md >= 0)
     mean = len(idx) / m
     assert 5.0 < mean < 40.0  # the radius closed forms aim at ~10 (3D) and ~20 (6D) neighbours
 
@@ -93,3 +96,6 @@ def test_full_size_sampled_parity_and_properties(name):
     assert np.array_equal(c2[sel], o_c) and np.array_equal(s2[sel], o_s)
     assert np.array_equal(ix[sel], o_ix) and np.array_equal(d2[sel], o_d2)
     assert np.array_equal(u5[sel], oracle.count_up_to(data, sq, r, 5, dim=dim))
+    o_md = oracle.match_distances(data, sq, o_off, o_idx, dim=dim)
+    for j, i in enumerate(sel):
+        assert np.array_equal(md[off[i]:off[i + 1]], o_md[o_off[j]:o_off[j + 1]])

@@ -679,3 +679,29 @@ def test_count_up_to(case):
         ax.arborx_reset_tuning()
     e = ax.arborx_bvh_build(dev(np.zeros((0, dim), dtype=np.float32)))
     assert np.all(host(ax.arborx_query_spatial_count_up_to(e, dev(q[:, :dim] if q.ndim == 2 else q), 1.0, 3)) == 0)
+
+
+@pytest.mark.parametrize("case", ["cube", "boxes", "dim6", "long_rows"])
+def test_match_distances(case):
+    g = np.random.default_rng(41)
+    kind, dim = oracle.POINTS, 3
+    if case == "boxes":
+        c = g.random((6000, 3)).astype(np.float32)
+        h = (g.random((6000, 3)) * 0.01).astype(np.float32)
+        data = np.ascontiguousarray(np.stack([c - h, c + h], axis=1))
+        q, r, kind = g.random((2001, 3)).astype(np.float32), 0.03, oracle.BOXES
+    elif case == "dim6":
+        cfg = inputs.config_gmm6(n=20_000, m=2001)
+        data, q, r, dim = cfg["data"], cfg["queries"], float(cfg["radius"]), 6
+    elif case == "long_rows":
+        data, q, r = g.random((9000, 3)).astype(np.float32), g.random((50, 3)).astype(np.float32), 0.4
+    else:
+        cfg = inputs.config_small(n=20_000, m=4001)
+        data, q, r = cfg["data"], cfg["queries"], float(cfg["radius"])
+    bvh = ax.BVH(dev(data), ax.BOXES if kind == oracle.BOXES else ax.POINTS)
+    off, idx, d2 = bvh.spatial_with_distances(dev(q), r)
+    o_off, o_idx = oracle.spatial(data, q, r, dim=dim, kind=kind)
+    assert np.array_equal(host(off), o_off) and np.array_equal(host(idx), o_idx)
+    want = oracle.match_distances(data, q, o_off, o_idx, dim=dim, kind=kind)
+    assert np.array_equal(host(d2), want)
+    assert np.all(host(d2) <= np.float32(r) * np.float32(r))
