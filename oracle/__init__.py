@@ -70,6 +70,7 @@ def lib():
         L.oracle_reduce.argtypes = [P, I64, I32, I32, P, I64, F32, I32, I32, P, P]
         L.oracle_count_up_to.argtypes = [P, I64, I32, I32, P, I64, F32, I32, P]
         L.oracle_match_distances.argtypes = [P, I64, I32, I32, P, I64, P, P, P]
+        L.oracle_dbscan.argtypes = [P, I64, I32, F32, I32, P]
         L.oracle_knn.argtypes = [P, I64, I32, I32, P, I64, I32, P, P]
         L.oracle_chamfer_forward.argtypes = [P, P, P, P, I32, P, P, P]
         L.oracle_chamfer_backward.argtypes = [P, P, P, P, I32, P, P, P, P, P]
@@ -153,6 +154,16 @@ def reduce(values, queries, radius, op=COUNT_SUMDIST, scale_bits=32, dim=3, kind
     sums = np.zeros(m, dtype=np.int64)
     lib().oracle_reduce(_p(v), n, dim, kind, _p(q), m, np.float32(radius), op, scale_bits, _p(counts), _p(sums))
     return counts, (sums if op == COUNT_SUMDIST else None)
+
+
+def dbscan(points, eps, min_pts, dim=3):
+    """DBSCAN (Section 2.4) by definition: int32 labels; a cluster is labelled by its smallest core
+    index, a border point by its smallest-index core neighbour's cluster, noise by -1.  O(n^2)."""
+    v, n = _values(points, dim, POINTS)
+    labels = np.zeros(n, dtype=np.int32)
+    if lib().oracle_dbscan(_p(v), n, dim, np.float32(eps), np.int32(min_pts), _p(labels)) != 0:
+        raise MemoryError("oracle_dbscan")
+    return labels
 
 
 def match_distances(values, queries, offsets, indices, dim=3, kind=POINTS):

@@ -23,6 +23,8 @@
  *     counted n_max matches, so its result is min(count, n_max);
  *   - the callback-with-output form (Section 2.1, query call (2)) as the
  *     squared distance of each match of a CSR result;
+ *   - density-based clustering over the radius search (Section 2.4, DBSCAN):
+ *     core points, their eps-connected components and border points;
  *   - Chamfer loss of nearest-neighbour pairs and its gradient, in float64.
  *
  * Floating-point contract (the paper fixes none; this follows the exactness
@@ -203,6 +205,62 @@ int oracle_reduce(const float *values, int64_t n, int dim, int kind, const float
         if (op == RED_COUNT_SUMDIST)
             sum_fixed[i] = s;
     }
+    return 0;
+}
+
+/* DBSCAN (Section 2.4) by its definition, brute force: a point is core when
+ * at least min_pts points (itself included) lie within eps (d2 <= fl(eps^2));
+ * core points within eps of each other are connected, and each connected
+ * component of core points is a cluster labelled by its smallest index; a
+ * non-core point with a core point within eps is a border point and takes the
+ * label of its smallest-index core neighbour; every other point is noise (-1).
+ * Labelling by smallest indices makes the answer unique.  O(n^2). */
+int oracle_dbscan(const float *points, int64_t n, int dim, float eps, int32_t min_pts, int32_t *labels)
+{
+    const float r2 = eps * eps;
+    unsigned char *core = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!core || !queue) {
+        free(core);
+        free(queue);
+        return -1;
+    }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = 0;
+        for (int64_t j = 0; j < n; ++j)
+            if (dist2_point(points + i * dim, points + j * dim, dim) <= r2)
+                ++c;
+        core[i] = c >= min_pts;
+        labels[i] = -1;
+    }
+    for (int64_t i = 0; i < n; ++i) {  /* components of core points, in index order */
+        if (!core[i] || labels[i] >= 0)
+            continue;
+        int64_t head = 0, tail = 0;
+        queue[tail++] = i;
+        labels[i] = (int32_t)i;
+        while (head < tail) {
+            const int64_t a = queue[head++];
+            for (int64_t b = 0; b < n; ++b)
+                if (core[b] && labels[b] < 0 && dist2_point(points + a * dim, points + b * dim, dim) <= r2) {
+                    labels[b] = (int32_t)i;
+                    queue[tail++] = b;
+                }
+        }
+    }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < n; ++j) {  /* border points: the smallest-index core neighbour */
+        if (core[j])
+            continue;
+        for (int64_t b = 0; b < n; ++b)
+            if (core[b] && dist2_point(points + j * dim, points + b * dim, dim) <= r2) {
+                labels[j] = labels[b];
+                break;
+            }
+    }
+    free(core);
+    free(queue);
     return 0;
 }
 

@@ -501,3 +501,43 @@ def test_match_distances_hand_worked_and_kdtree():
     qb = np.array([[0.5, 0.5, 0.5], [2.0, 0.5, 0.5]], dtype=np.float32)
     off, idx = oracle.spatial(boxes, qb, 2.0, kind=oracle.BOXES)
     assert list(oracle.match_distances(boxes, qb, off, idx, kind=oracle.BOXES)) == [0.0, 1.0]
+
+
+def test_dbscan_hand_worked():
+    # points on a line x = 0, 1, 2, 10, 11, 20; eps = 1.5
+    pts = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0], [10, 0, 0], [11, 0, 0], [20, 0, 0]], dtype=np.float32)
+    # min_pts 2 (a point counts itself): {0,1,2} and {10,11} are clusters of core points, 20 is noise
+    assert list(oracle.dbscan(pts, 1.5, 2)) == [0, 0, 0, 3, 3, -1]
+    # min_pts 3: only x = 1 is core; 0 and 2 are its border points; 10 and 11 are noise
+    assert list(oracle.dbscan(pts, 1.5, 3)) == [1, 1, 1, -1, -1, -1]
+    # min_pts 1: every point is core; singletons label themselves
+    assert list(oracle.dbscan(pts, 1.5, 1)) == [0, 0, 0, 3, 3, 5]
+    # closed ball: eps exactly 1 still links neighbours 1 apart
+    assert list(oracle.dbscan(pts, 1.0, 2)) == [0, 0, 0, 3, 3, -1]
+
+
+def test_dbscan_vs_sklearn():
+    from sklearn.cluster import DBSCAN
+    g = np.random.default_rng(23)
+    centres = g.random((12, 3)) * 10
+    pts = np.concatenate([centres[g.integers(0, 12, 1500)] + 0.25 * g.standard_normal((1500, 3)),
+                          g.random((300, 3)) * 10]).astype(np.float32)
+    eps, min_pts = 0.3, 6
+    lab = oracle.dbscan(pts, eps, min_pts)
+    # float64 scikit-learn just inside and just outside eps: equal core sets mean no distance lies
+    # within rounding of eps, so the float32 decisions are the same
+    inner, outer = (DBSCAN(eps=eps * f, min_samples=min_pts).fit(pts.astype(np.float64)) for f in (1 - 1e-5, 1 + 1e-5))
+    assert np.array_equal(np.sort(inner.core_sample_indices_), np.sort(outer.core_sample_indices_))
+    core = np.zeros(len(pts), dtype=bool)
+    core[inner.core_sample_indices_] = True
+    assert 0 < core.sum() < len(pts)
+    # same partition of the core points (up to relabelling) and the same noise
+    a, b = lab[core], inner.labels_[core]
+    assert len(set(zip(a.tolist(), b.tolist()))) == len(set(a.tolist())) == len(set(b.tolist()))
+    assert np.array_equal(lab == -1, inner.labels_ == -1)
+    # each cluster is labelled by its smallest core index; border points by their smallest core neighbour
+    for c in set(a.tolist()):
+        assert c == np.nonzero(core & (lab == c))[0].min()
+    d2 = ((pts[:, None, :].astype(np.float64) - pts[None, :, :]) ** 2).sum(-1)
+    for j in np.nonzero((lab >= 0) & ~core)[0]:
+        assert lab[j] == lab[np.nonzero((d2[j] <= eps * eps) & core)[0].min()]
