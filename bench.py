@@ -97,7 +97,7 @@ KERNEL_PHASE = [  # rocprofv3 kernel name fragment -> phase name used by the in-
     ("k_knn<", "knn"), ("k_spatial_count<", "spatial_count"), ("k_spatial_reduce<3, false", "reduce_count"),
     ("k_spatial_reduce<3, true", "reduce_sumdist"), ("k_spatial_fill_rows<", "spatial_fill"),
     ("hierarchy_chunk_kernel<", "build_hierarchy"), ("hierarchy_top_kernel<", "build_hierarchy"),
-    ("k_copy_stash", "copy_stash"), ("k_copy_overflow", "copy_overflow"), ("k_count_up_to", "count_up_to"), ("k_match_distances", "match_distances"), ("radix_scatter<", "radix_scatter"), ("radix_hist<", "radix_hist"),
+    ("k_copy_stash", "copy_stash"), ("k_copy_overflow", "copy_overflow"), ("k_count_up_to", "count_up_to"), ("k_match_distances", "match_distances"), ("k_dbscan_", "dbscan"), ("radix_scatter<", "radix_scatter"), ("radix_hist<", "radix_hist"),
 ]
 
 
@@ -466,6 +466,9 @@ def main():
     # the callback-with-output form: squared distance of each match of the step's CSR result
     ms = timed(lambda: ax.arborx_query_match_distances(tree, d, q, state["off"], state["idx"]), 5)
     comps["match_distances_per_s"] = total / ms * 1e3
+    # DBSCAN over the tree's points (eps = the step's radius, min_pts = 10)
+    ms = timed(lambda: ax.arborx_dbscan(tree, d, radius, 10), 3)
+    comps["dbscan_mpts_s"] = n / ms / 1e3
 
     # dominant kernel by GPU time in the timed region
     dom = max((kn for kn in prof if algorithmic_bytes(kn, n, m, dim, k, total)), key=lambda kn: prof[kn][0])

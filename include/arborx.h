@@ -273,6 +273,24 @@ arborx_status arborx_query_match_distances(arborx_tree tree, const float *values
                                            const int64_t *offsets, const int32_t *indices, float *distances,
                                            void *stream);
 
+/*
+ * DBSCAN over the tree's own points (Section 2.4: density-based clustering
+ * built on the index's radius search).  A point is core when at least min_pts
+ * points, itself included, lie within eps (closed ball, d2 <= fl(eps*eps)); core
+ * points within eps of each other share a cluster.  labels[i]:
+ *   core point    the smallest index among the core points of its cluster;
+ *   border point  (not core, some core point within eps) the label of its
+ *                 smallest-index core neighbour;
+ *   noise         -1.
+ * These tie rules make the result unique.
+ *   points  the [n][dim] array the tree was built from (a tree of points)
+ *   eps >= 0 (NaN is ARBORX_E_INVALID);  min_pts >= 0 (0 or 1: every point is core)
+ *   labels  [n] int32 output
+ * Asynchronous; temporary memory about 12 bytes per point plus the query order.
+ */
+arborx_status arborx_dbscan(arborx_tree tree, const float *points, float eps, int32_t min_pts, int32_t *labels,
+                            void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Forest: many independent trees in one structure, queried in one launch.  */
 /* ------------------------------------------------------------------------ */

@@ -280,6 +280,19 @@ def arborx_query_spatial_with_distances(tree: Tree, values, queries, radius: flo
     return off, idx, arborx_query_match_distances(tree, values, queries, off, idx, stream=stream)
 
 
+def arborx_dbscan(tree: Tree, points, eps: float, min_pts: int, stream=None):
+    """DBSCAN over the tree's points: int32 labels (cluster = smallest core index, border = its
+    smallest-index core neighbour's cluster, noise = -1)."""
+    torch = _torch()
+    v = _dev(points, torch.float32, "points")
+    if tree.kind != POINTS or tuple(v.shape) != (tree.n, tree.dim):
+        raise ValueError(f"points must be the build input of a tree of points, shape [{tree.n}, {tree.dim}]")
+    labels = torch.empty(tree.n, dtype=torch.int32, device=v.device)
+    _check(_lib.lib().arborx_dbscan(tree.handle, _ptr(v), ctypes.c_float(eps), int(min_pts), _ptr(labels),
+                                    _stream(stream)))
+    return labels
+
+
 def arborx_query_spatial_count_up_to(tree: Tree, queries, radius: float, n_max: int, stream=None):
     """Early-terminating count: int32[m] = min(matches within radius, n_max)."""
     torch = _torch()
@@ -537,6 +550,9 @@ class BVH:
 
     def spatial_with_distances(self, queries, radius, **kw):
         return arborx_query_spatial_with_distances(self.tree, self.values, queries, radius, **kw)
+
+    def dbscan(self, eps, min_pts, **kw):
+        return arborx_dbscan(self.tree, self.values, eps, min_pts, **kw)
 
     def count_up_to(self, queries, radius, n_max, **kw):
         return arborx_query_spatial_count_up_to(self.tree, queries, radius, n_max, **kw)

@@ -824,6 +824,40 @@ arborx_status arborx_query_spatial_reduce(arborx_tree t, const float *queries, i
     return spatial_reduce(t->dev, queries, m, radius, op, scale_bits, perm, counts, sum_fixed, s);
 }
 
+arborx_status arborx_dbscan(arborx_tree t, const float *points, float eps, int32_t min_pts, int32_t *labels,
+                            void *stream)
+{
+    arborx_status st = check_tree(t);
+    if (st != ARBORX_OK)
+        return st;
+    if (t->dev.kind != ARBORX_POINTS)
+        return fail(ARBORX_E_INVALID, "DBSCAN clusters a tree built from points");
+    if (std::isnan(eps) || eps < 0.0f)
+        return fail(ARBORX_E_INVALID, "eps must be >= 0 and not NaN");
+    if (min_pts < 0)
+        return fail(ARBORX_E_INVALID, "min_pts must be >= 0");
+    const int64_t n = t->dev.n;
+    if (n > 0 && (!points || !labels))
+        return fail(ARBORX_E_INVALID, "points and labels must not be NULL");
+    if ((st = check_device()) != ARBORX_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = wait_tree(t, s)) != ARBORX_OK)
+        return st;
+    if (n == 0)
+        return ARBORX_OK;
+    NoteUse note_use{t->uses, s};
+    Temps tmp(s);
+    uint32_t *perm = nullptr;
+    int32_t *counts = nullptr, *parent = nullptr;
+    if ((st = tree_order(t, points, n, Pred::Sphere, OP_REDUCE, &perm, tmp, s)) != ARBORX_OK ||
+        (st = tmp.get(&counts, n)) != ARBORX_OK || (st = tmp.get(&parent, n)) != ARBORX_OK)
+        return st;
+    if ((st = spatial_reduce(t->dev, points, n, eps, ARBORX_COUNT, 0, perm, counts, nullptr, s)) != ARBORX_OK)
+        return st;
+    return dbscan(t->dev, points, eps, min_pts, perm, counts, parent, labels, s);
+}
+
 arborx_status arborx_query_match_distances(arborx_tree t, const float *values, const float *queries, int64_t m,
                                            const int64_t *offsets, const int32_t *indices, float *distances,
                                            void *stream)

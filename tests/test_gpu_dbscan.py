@@ -1,0 +1,85 @@
+"""DBSCAN on the index (core points by a fused COUNT, clusters by a lock-free
+union-find, border points to their smallest-index core neighbour) against the
+brute-force definition in the oracle, label for label."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2507_23700_amd as ax
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ax.arborx_reset_tuning()
+    yield
+    ax.arborx_reset_tuning()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def clustered(n, dim, seed, noise=0.15):
+    g = np.random.default_rng(seed)
+    k = max(2, n // 150)
+    centres = g.random((k, dim)) * 10
+    m = int(n * (1 - noise))
+    pts = np.concatenate([centres[g.integers(0, k, m)] + 0.25 * g.standard_normal((m, dim)),
+                          g.random((n - m, dim)) * 10])
+    return np.ascontiguousarray(pts.astype(np.float32))
+
+
+def check(pts, eps, min_pts):
+    bvh = ax.BVH(dev(pts))
+    got = bvh.dbscan(eps, min_pts).cpu().numpy()
+    want = oracle.dbscan(pts, eps, min_pts, dim=pts.shape[1])
+    assert np.array_equal(got, want), (eps, min_pts)
+    return got
+
+
+def test_hand_worked_line():
+    pts = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0], [10, 0, 0], [11, 0, 0], [20, 0, 0]], dtype=np.float32)
+    assert list(check(pts, 1.5, 2)) == [0, 0, 0, 3, 3, -1]
+    assert list(check(pts, 1.5, 3)) == [1, 1, 1, -1, -1, -1]
+    assert list(check(pts, 1.5, 1)) == [0, 0, 0, 3, 3, 5]
+
+
+@pytest.mark.parametrize("eps,min_pts", [(0.3, 6), (0.3, 1), (0.2, 10), (0.6, 4), (100.0, 5), (0.0, 2)])
+def test_clustered_3d(eps, min_pts):
+    pts = clustered(6000, 3, 1)
+    pts[::97] = pts[1::97][: len(pts[::97])]  # exact duplicates: eps = 0 still links them
+    lab = check(pts, eps, min_pts)
+    if eps == 100.0:
+        assert np.all(lab == 0)
+
+
+@pytest.mark.parametrize("dim", [2, 6])
+def test_other_dims(dim):
+    check(clustered(5000, dim, 2 + dim), 0.35 if dim == 2 else 0.6, 5)
+
+
+def test_large_and_tuned():
+    pts = clustered(40_000, 3, 7)
+    check(pts, 0.15, 8)
+    ax.arborx_set_tuning(block=64, stack=2, order=0)
+    check(pts, 0.15, 8)
+
+
+def test_empty_and_tiny():
+    e = ax.BVH(dev(np.zeros((0, 3), dtype=np.float32)))
+    assert e.dbscan(1.0, 2).numel() == 0
+    one = np.array([[0.5, 0.5, 0.5]], dtype=np.float32)
+    assert list(check(one, 1.0, 1)) == [0] and list(check(one, 1.0, 2)) == [-1]
+
+
+def test_rejects_box_trees():
+    boxes = np.zeros((4, 2, 3), dtype=np.float32)
+    t = ax.arborx_bvh_build(dev(boxes), ax.BOXES)
+    with pytest.raises(ValueError):
+        ax.arborx_dbscan(t, dev(np.zeros((4, 3), dtype=np.float32)), 1.0, 2)

@@ -51,6 +51,30 @@ def check_knn_rows(d2, ix, n):
     assert np.all((dd > 0) | (np.diff(ix.astype(np.int64), axis=1) > 0))
 
 
+def check_dbscan(data, eps, min_pts, lab, counts):
+    """Properties of DBSCAN labels at any size, with the point counts from the (tested) COUNT query:
+    every cluster is labelled by a core point that labels itself and has the smallest index of
+    the cluster's core points met here; a sample of points is checked against its oracle
+    neighbourhood (core neighbours share its label; a border point carries its smallest-index core
+    neighbour's label; noise has no core neighbour)."""
+    core = counts >= min_pts
+    ci = np.nonzero(core)[0]
+    assert np.all(lab[ci] >= 0) and np.all(lab[ci] <= ci) and np.all(core[lab[ci]])
+    assert np.all(lab[lab[ci]] == lab[ci])
+    nc = np.nonzero(~core & (lab >= 0))[0]
+    assert np.all(core[lab[nc]]) and np.all(lab[lab[nc]] == lab[nc])
+    g = np.random.default_rng(99)
+    sel = np.concatenate([g.choice(ci, 24, replace=False), g.choice(np.nonzero(~core)[0], 24, replace=False)])
+    off, idx = oracle.spatial(data, np.ascontiguousarray(data[sel]), eps)
+    for j, i in enumerate(sel):
+        nb = idx[off[j]:off[j + 1]]
+        cn = nb[core[nb]]
+        if core[i]:
+            assert np.all(lab[cn] == lab[i])
+        else:
+            assert lab[i] == (lab[cn.min()] if len(cn) else -1)
+
+
 @pytest.mark.parametrize("name", ["cube", "shell", "gmm6"])
 def test_full_size_sampled_parity_and_properties(name):
     cfg = workload(name)
@@ -64,6 +88,8 @@ def test_full_size_sampled_parity_and_properties(name):
     c2_t, s2_t = ax.arborx_query_spatial_reduce(t, qd, r, ax.COUNT_SUMDIST)
     d2_t, ix_t = ax.arborx_query_knn(t, qd, k)
     u5_t = ax.arborx_query_spatial_count_up_to(t, qd, r, 5)
+    db_t = ax.arborx_dbscan(t, d, r, 10) if dim == 3 else None
+    dbc_t = ax.arborx_query_spatial_reduce(t, d, r, ax.COUNT)[0] if dim == 3 else None
     md_t = ax.arborx_query_match_distances(t, d, qd, off_t, idx_t)
     torch.cuda.synchronize()
     off, idx = off_t.cpu().numpy(), idx_t.cpu().numpy()
@@ -71,6 +97,9 @@ def test_full_size_sampled_parity_and_properties(name):
     d2, ix = d2_t.cpu().numpy(), ix_t.cpu().numpy()
     u5 = u5_t.cpu().numpy()
     md = md_t.cpu().numpy()
+    db = db_t.cpu().numpy() if db_t is not None else None
+    dbc = dbc_t.cpu().numpy() if dbc_t is not None else None
+    del db_t, dbc_t
     del off_t, idx_t, c_t, c2_t, s2_t, d2_t, ix_t, u5_t, md_t, t
 
     # every query: properties
@@ -96,6 +125,8 @@ def test_full_size_sampled_parity_and_properties(name):
     assert np.array_equal(c2[sel], o_c) and np.array_equal(s2[sel], o_s)
     assert np.array_equal(ix[sel], o_ix) and np.array_equal(d2[sel], o_d2)
     assert np.array_equal(u5[sel], oracle.count_up_to(data, sq, r, 5, dim=dim))
+    if db is not None:
+        check_dbscan(data, r, 10, db, dbc)
     o_md = oracle.match_distances(data, sq, o_off, o_idx, dim=dim)
     for j, i in enumerate(sel):
         assert np.array_equal(md[off[i]:off[i + 1]], o_md[o_off[j]:o_off[j + 1]])
