@@ -71,6 +71,8 @@ def lib():
         L.oracle_count_up_to.argtypes = [P, I64, I32, I32, P, I64, F32, I32, P]
         L.oracle_match_distances.argtypes = [P, I64, I32, I32, P, I64, P, P, P]
         L.oracle_dbscan.argtypes = [P, I64, I32, F32, I32, P]
+        L.oracle_ray_count.argtypes = [P, I64, I32, I32, P, I64, P]
+        L.oracle_ray_nearest.argtypes = [P, I64, I32, I32, P, I64, I32, P, P]
         L.oracle_knn.argtypes = [P, I64, I32, I32, P, I64, I32, P, P]
         L.oracle_chamfer_forward.argtypes = [P, P, P, P, I32, P, P, P]
         L.oracle_chamfer_backward.argtypes = [P, P, P, P, I32, P, P, P, P, P]
@@ -154,6 +156,25 @@ def reduce(values, queries, radius, op=COUNT_SUMDIST, scale_bits=32, dim=3, kind
     sums = np.zeros(m, dtype=np.int64)
     lib().oracle_reduce(_p(v), n, dim, kind, _p(q), m, np.float32(radius), op, scale_bits, _p(counts), _p(sums))
     return counts, (sums if op == COUNT_SUMDIST else None)
+
+
+def ray_count(values, rays, dim=3, kind=POINTS):
+    """Ray predicate (Section 2.5): number of values each ray o + t*d (t >= 0) meets; rays [m][2][dim]."""
+    v, n = _values(values, dim, kind)
+    r, m = _queries(rays, dim, 2)
+    counts = np.zeros(m, dtype=np.int32)
+    lib().oracle_ray_count(_p(v), n, dim, kind, _p(r), m, _p(counts))
+    return counts
+
+
+def ray_nearest(values, rays, k, dim=3, kind=POINTS):
+    """The k values each ray meets first: (t float32[m][k], idx int32[m][k]) by (entry t, index)."""
+    v, n = _values(values, dim, kind)
+    r, m = _queries(rays, dim, 2)
+    t = np.zeros((m, k), dtype=np.float32)
+    idx = np.zeros((m, k), dtype=np.int32)
+    lib().oracle_ray_nearest(_p(v), n, dim, kind, _p(r), m, k, _p(t), _p(idx))
+    return t, idx
 
 
 def dbscan(points, eps, min_pts, dim=3):

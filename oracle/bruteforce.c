@@ -25,6 +25,8 @@
  *     squared distance of each match of a CSR result;
  *   - density-based clustering over the radius search (Section 2.4, DBSCAN):
  *     core points, their eps-connected components and border points;
+ *   - ray predicates (Section 2.5): the values a ray meets, counted, and the k
+ *     met first, ordered by (entry parameter, index);
  *   - Chamfer loss of nearest-neighbour pairs and its gradient, in float64.
  *
  * Floating-point contract (the paper fixes none; this follows the exactness
@@ -204,6 +206,90 @@ int oracle_reduce(const float *values, int64_t n, int dim, int kind, const float
         counts[i] = c;
         if (op == RED_COUNT_SUMDIST)
             sum_fixed[i] = s;
+    }
+    return 0;
+}
+
+/* A ray o + t*dir (t >= 0) against the closed box [lo, hi] (Section 2.5, ray
+ * predicates), by slabs: in each dimension with dir != 0 the parameters
+ * t1 = (lo - o) / dir and t2 = (hi - o) / dir (float32, correctly rounded
+ * division); a dimension with dir == 0 admits every t when lo <= o <= hi and
+ * none otherwise.  Starting from tmin = 0 and tmax = +inf and taking the
+ * dimensions in order, tmin = max(tmin, min(t1, t2)) and
+ * tmax = min(tmax, max(t1, t2)); the ray meets the box iff tmin <= tmax, and
+ * tmin is then its entry parameter. */
+static int ray_box(const float *o, const float *dir, const float *lo, const float *hi, int dim, float *t_entry)
+{
+    float tmin = 0.0f, tmax = INFINITY;
+    for (int k = 0; k < dim; ++k) {
+        if (dir[k] == 0.0f) {
+            if (o[k] < lo[k] || o[k] > hi[k])
+                return 0;
+            continue;
+        }
+        const float t1 = (lo[k] - o[k]) / dir[k];
+        const float t2 = (hi[k] - o[k]) / dir[k];
+        const float tn = t1 < t2 ? t1 : t2, tf = t1 < t2 ? t2 : t1;
+        if (tn > tmin)
+            tmin = tn;
+        if (tf < tmax)
+            tmax = tf;
+    }
+    if (tmin > tmax)
+        return 0;
+    *t_entry = tmin;
+    return 1;
+}
+
+static int ray_value(const float *values, int64_t j, int dim, int kind, const float *ray, float *t)
+{
+    const float *lo = values + j * (kind == KIND_BOXES ? 2 * dim : dim);
+    const float *hi = kind == KIND_BOXES ? lo + dim : lo;
+    return ray_box(ray, ray + dim, lo, hi, dim, t);
+}
+
+/* Rays are [m][2][dim]: the origin row, then the direction row. */
+int oracle_ray_count(const float *values, int64_t n, int dim, int kind, const float *rays, int64_t m, int32_t *counts)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < m; ++i) {
+        int32_t c = 0;
+        float t;
+        for (int64_t j = 0; j < n; ++j)
+            c += ray_value(values, j, dim, kind, rays + i * 2 * dim, &t);
+        counts[i] = c;
+    }
+    return 0;
+}
+
+/* The k values a ray meets first, in the order (entry parameter, index),
+ * padded with (+inf, -1). */
+int oracle_ray_nearest(const float *values, int64_t n, int dim, int kind, const float *rays, int64_t m, int k,
+                       float *t_out, int32_t *idx_out)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < m; ++i) {
+        float *bt = t_out + i * k;
+        int32_t *bi = idx_out + i * k;
+        for (int s = 0; s < k; ++s) {
+            bt[s] = INFINITY;
+            bi[s] = -1;
+        }
+        for (int64_t j = 0; j < n; ++j) {
+            float t;
+            if (!ray_value(values, j, dim, kind, rays + i * 2 * dim, &t))
+                continue;
+            if (bi[k - 1] >= 0 && !(t < bt[k - 1]))  /* equal t: the earlier (smaller) index stays */
+                continue;
+            int s = k - 1;
+            while (s > 0 && (bi[s - 1] < 0 || t < bt[s - 1])) {
+                bt[s] = bt[s - 1];
+                bi[s] = bi[s - 1];
+                --s;
+            }
+            bt[s] = t;
+            bi[s] = (int32_t)j;
+        }
     }
     return 0;
 }

@@ -541,3 +541,66 @@ def test_dbscan_vs_sklearn():
     d2 = ((pts[:, None, :].astype(np.float64) - pts[None, :, :]) ** 2).sum(-1)
     for j in np.nonzero((lab >= 0) & ~core)[0]:
         assert lab[j] == lab[np.nonzero((d2[j] <= eps * eps) & core)[0].min()]
+
+
+def _ray(o, d):
+    return np.array([[o, d]], dtype=np.float32)
+
+
+def test_ray_hand_worked():
+    # five unit boxes [i, i+1] x [0, 1] x [0, 1] along x
+    boxes = np.array([[[i, 0, 0], [i + 1, 1, 1]] for i in range(5)], dtype=np.float32)
+    B = oracle.BOXES
+    r = _ray((-1, 0.5, 0.5), (1, 0, 0))  # enters box i at t = i + 1
+    assert oracle.ray_count(boxes, r, kind=B)[0] == 5
+    t, ix = oracle.ray_nearest(boxes, r, 3, kind=B)
+    assert list(t[0]) == [1, 2, 3] and list(ix[0]) == [0, 1, 2]
+    assert oracle.ray_count(boxes, _ray((-1, 0.5, 0.5), (-1, 0, 0)), kind=B)[0] == 0  # pointing away
+    t, ix = oracle.ray_nearest(boxes, _ray((2.5, 0.5, 0.5), (2, 0, 0)), 3, kind=B)  # starts inside box 2
+    assert list(t[0]) == [0, 0.25, 0.75] and list(ix[0]) == [2, 3, 4]
+    t, ix = oracle.ray_nearest(boxes, _ray((0.5, 0.5, -1), (0, 0, 1)), 2, kind=B)  # d_x = d_y = 0
+    assert list(t[0]) == [1, np.inf] and list(ix[0]) == [0, -1]
+    assert oracle.ray_count(boxes, _ray((0.5, 2, -1), (0, 0, 1)), kind=B)[0] == 0  # outside the y slab
+    # a shared face: boxes 0 and 1 touch at x = 1; a ray along that face meets both at the same t
+    t, ix = oracle.ray_nearest(boxes, _ray((1, 0.5, -1), (0, 0, 1)), 3, kind=B)
+    assert list(t[0][:2]) == [1, 1] and list(ix[0][:2]) == [0, 1] and ix[0][2] == -1
+    # points are degenerate boxes: met only exactly
+    pts = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0]], dtype=np.float32)
+    t, ix = oracle.ray_nearest(pts, _ray((-2, 0, 0), (0.5, 0, 0)), 3)
+    assert list(t[0]) == [4, 6, np.inf] and list(ix[0]) == [0, 1, -1]
+
+
+def test_ray_vs_exact_rationals():
+    # the slab test in exact rational arithmetic decides the same hits wherever the decision is not
+    # within float32 rounding of a tangency
+    g = np.random.default_rng(24)
+    c = g.random((300, 3)).astype(np.float32)
+    h = (g.random((300, 3)) * 0.08 + 0.01).astype(np.float32)
+    boxes = np.ascontiguousarray(np.stack([c - h, c + h], axis=1))
+    rays = np.ascontiguousarray(np.stack([g.random((60, 3)) * 2 - 0.5, g.standard_normal((60, 3))], axis=1)
+                                .astype(np.float32))
+    t, ix = oracle.ray_nearest(boxes, rays, 300, kind=oracle.BOXES)
+    cnt = oracle.ray_count(boxes, rays, kind=oracle.BOXES)
+    checked = 0
+    for i in range(len(rays)):
+        o = [Fraction(float(x)) for x in rays[i, 0]]
+        d = [Fraction(float(x)) for x in rays[i, 1]]
+        hits = {}
+        for j in range(len(boxes)):
+            tmin, tmax, ok, margin = Fraction(0), None, True, None
+            for k in range(3):
+                t1 = (Fraction(float(boxes[j, 0, k])) - o[k]) / d[k]
+                t2 = (Fraction(float(boxes[j, 1, k])) - o[k]) / d[k]
+                tmin, tmax = max(tmin, min(t1, t2)), (max(t1, t2) if tmax is None else min(tmax, max(t1, t2)))
+            gap = tmax - tmin
+            if abs(gap) < Fraction(1, 10 ** 4) * (1 + abs(tmax)):
+                break  # too close to tangency for an exact comparison: skip this ray
+            if gap >= 0:
+                hits[j] = tmin
+        else:
+            got = {int(j): float(tt) for j, tt in zip(ix[i], t[i]) if j >= 0}
+            assert set(got) == set(hits) and cnt[i] == len(hits)
+            for j, tt in hits.items():
+                assert abs(got[j] - float(tt)) <= 1e-5 * (1 + abs(float(tt)))
+            checked += 1
+    assert checked > 40
