@@ -97,7 +97,7 @@ KERNEL_PHASE = [  # rocprofv3 kernel name fragment -> phase name used by the in-
     ("k_knn<", "knn"), ("k_spatial_count<", "spatial_count"), ("k_spatial_reduce<3, false", "reduce_count"),
     ("k_spatial_reduce<3, true", "reduce_sumdist"), ("k_spatial_fill_rows<", "spatial_fill"),
     ("hierarchy_chunk_kernel<", "build_hierarchy"), ("hierarchy_top_kernel<", "build_hierarchy"),
-    ("k_copy_stash", "copy_stash"), ("k_copy_overflow", "copy_overflow"), ("k_count_up_to", "count_up_to"), ("k_match_distances", "match_distances"), ("k_dbscan_", "dbscan"), ("radix_scatter<", "radix_scatter"), ("radix_hist<", "radix_hist"),
+    ("k_copy_stash", "copy_stash"), ("k_copy_overflow", "copy_overflow"), ("k_count_up_to", "count_up_to"), ("k_match_distances", "match_distances"), ("k_dbscan_", "dbscan"), ("k_ray_count", "ray_count"), ("k_ray_nearest", "ray_nearest"), ("radix_scatter<", "radix_scatter"), ("radix_hist<", "radix_hist"),
 ]
 
 
@@ -466,6 +466,19 @@ def main():
     # the callback-with-output form: squared distance of each match of the step's CSR result
     ms = timed(lambda: ax.arborx_query_match_distances(tree, d, q, state["off"], state["idx"]), 5)
     comps["match_distances_per_s"] = total / ms * 1e3
+    # rays against 2*10^6 small random boxes: hit counts and the first hit of 10^6 rays
+    g = np.random.default_rng(2507)
+    bc = g.random((2_000_000, 3)).astype(np.float32)
+    bh = (g.random((2_000_000, 3)) * 0.004 + 0.001).astype(np.float32)
+    boxes = torch.from_numpy(np.ascontiguousarray(np.stack([bc - bh, bc + bh], axis=1))).cuda()
+    rays = torch.from_numpy(np.ascontiguousarray(np.stack([g.random((1_000_000, 3)), g.standard_normal((1_000_000, 3))],
+                                                          axis=1).astype(np.float32))).cuda()
+    btree = ax.arborx_bvh_build(boxes, ax.BOXES)
+    ms = timed(lambda: ax.arborx_query_ray_count(btree, rays), 3)
+    comps["ray_count_rays_s"] = rays.shape[0] / ms * 1e3
+    ms = timed(lambda: ax.arborx_query_ray_nearest(btree, rays, 1), 3)
+    comps["ray_first_hit_rays_s"] = rays.shape[0] / ms * 1e3
+    del btree, boxes, rays
     # DBSCAN over the tree's points (eps = the step's radius, min_pts = 10)
     ms = timed(lambda: ax.arborx_dbscan(tree, d, radius, 10), 3)
     comps["dbscan_mpts_s"] = n / ms / 1e3

@@ -291,6 +291,25 @@ arborx_status arborx_query_match_distances(arborx_tree tree, const float *values
 arborx_status arborx_dbscan(arborx_tree tree, const float *points, float eps, int32_t min_pts, int32_t *labels,
                             void *stream);
 
+/*
+ * Ray predicates (Section 2.5: rays traced against the index's values).  Ray i
+ * is rays[i] = {origin[dim], direction[dim]} ([m][2][dim]) and covers
+ * o + t*dir for t >= 0.  It meets a value's closed box (a point is a degenerate
+ * box) when, taking the dimensions in order from tmin = 0, tmax = +inf, with
+ * t1 = (lo - o) / dir and t2 = (hi - o) / dir in float32 for dir != 0,
+ * tmin = max(tmin, min(t1, t2)) and tmax = min(tmax, max(t1, t2)) end with
+ * tmin <= tmax (a dimension with dir == 0 needs lo <= o <= hi); tmin is the
+ * entry parameter.
+ *   arborx_query_ray_count    counts[m]: number of values each ray meets;
+ *   arborx_query_ray_nearest  the k values met first: t_entry[m][k] and
+ *                             indices[m][k] ordered by (entry t, index),
+ *                             padded with (+inf, -1); 1 <= k <= 64.
+ * Asynchronous.
+ */
+arborx_status arborx_query_ray_count(arborx_tree tree, const float *rays, int64_t m, int32_t *counts, void *stream);
+arborx_status arborx_query_ray_nearest(arborx_tree tree, const float *rays, int64_t m, int32_t k, float *t_entry,
+                                       int32_t *indices, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Forest: many independent trees in one structure, queried in one launch.  */
 /* ------------------------------------------------------------------------ */

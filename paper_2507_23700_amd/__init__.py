@@ -280,6 +280,26 @@ def arborx_query_spatial_with_distances(tree: Tree, values, queries, radius: flo
     return off, idx, arborx_query_match_distances(tree, values, queries, off, idx, stream=stream)
 
 
+def arborx_query_ray_count(tree: Tree, rays, stream=None):
+    """Number of values each ray meets; rays [m, 2, dim] = (origin, direction)."""
+    torch = _torch()
+    r = _queries(tree, rays, True)
+    counts = torch.empty(r.shape[0], dtype=torch.int32, device=r.device)
+    _check(_lib.lib().arborx_query_ray_count(tree.handle, _ptr(r), r.shape[0], _ptr(counts), _stream(stream)))
+    return counts
+
+
+def arborx_query_ray_nearest(tree: Tree, rays, k: int, stream=None):
+    """The k values each ray meets first: (t_entry float32[m, k], indices int32[m, k]) by (t, index)."""
+    torch = _torch()
+    r = _queries(tree, rays, True)
+    m = r.shape[0]
+    t = torch.empty((m, k), dtype=torch.float32, device=r.device)
+    idx = torch.empty((m, k), dtype=torch.int32, device=r.device)
+    _check(_lib.lib().arborx_query_ray_nearest(tree.handle, _ptr(r), m, int(k), _ptr(t), _ptr(idx), _stream(stream)))
+    return t, idx
+
+
 def arborx_dbscan(tree: Tree, points, eps: float, min_pts: int, stream=None):
     """DBSCAN over the tree's points: int32 labels (cluster = smallest core index, border = its
     smallest-index core neighbour's cluster, noise = -1)."""
@@ -550,6 +570,12 @@ class BVH:
 
     def spatial_with_distances(self, queries, radius, **kw):
         return arborx_query_spatial_with_distances(self.tree, self.values, queries, radius, **kw)
+
+    def ray_count(self, rays, **kw):
+        return arborx_query_ray_count(self.tree, rays, **kw)
+
+    def ray_nearest(self, rays, k, **kw):
+        return arborx_query_ray_nearest(self.tree, rays, k, **kw)
 
     def dbscan(self, eps, min_pts, **kw):
         return arborx_dbscan(self.tree, self.values, eps, min_pts, **kw)

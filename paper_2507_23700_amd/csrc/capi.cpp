@@ -824,6 +824,45 @@ arborx_status arborx_query_spatial_reduce(arborx_tree t, const float *queries, i
     return spatial_reduce(t->dev, queries, m, radius, op, scale_bits, perm, counts, sum_fixed, s);
 }
 
+static arborx_status ray_args(arborx_tree t, const float *rays, int64_t m, const void *out1, const void *out2)
+{
+    arborx_status st = check_tree(t);
+    if (st != ARBORX_OK)
+        return st;
+    if (m < 0 || m >= INT32_MAX)
+        return fail(ARBORX_E_INVALID, "m must be in [0, 2^31-1)");
+    if (m > 0 && (!rays || !out1 || !out2))
+        return fail(ARBORX_E_INVALID, "rays and outputs must not be NULL");
+    return check_device();
+}
+
+arborx_status arborx_query_ray_count(arborx_tree t, const float *rays, int64_t m, int32_t *counts, void *stream)
+{
+    arborx_status st = ray_args(t, rays, m, counts, counts);
+    if (st != ARBORX_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = wait_tree(t, s)) != ARBORX_OK)
+        return st;
+    NoteUse note_use{t->uses, s};
+    return ray_count(t->dev, rays, m, counts, s);
+}
+
+arborx_status arborx_query_ray_nearest(arborx_tree t, const float *rays, int64_t m, int32_t k, float *t_entry,
+                                       int32_t *indices, void *stream)
+{
+    if (k < 1 || k > 64)
+        return fail(ARBORX_E_INVALID, "k must be in 1..64");
+    arborx_status st = ray_args(t, rays, m, t_entry, indices);
+    if (st != ARBORX_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = wait_tree(t, s)) != ARBORX_OK)
+        return st;
+    NoteUse note_use{t->uses, s};
+    return ray_nearest(t->dev, rays, m, k, t_entry, indices, s);
+}
+
 arborx_status arborx_dbscan(arborx_tree t, const float *points, float eps, int32_t min_pts, int32_t *labels,
                             void *stream)
 {

@@ -232,6 +232,10 @@ arborx_status spatial_reduce(const TreeDev &t, const float *queries, int64_t m, 
 // out[p] = squared distance of match p (CSR row i = query i) from the build input.
 arborx_status match_distances(const TreeDev &t, const float *values, const float *queries, int64_t m,
                               const int64_t *offsets, const int32_t *indices, float *out, hipStream_t s);
+// Ray predicates (ray.hip); rays are [m][2][dim] (origin row, direction row).
+arborx_status ray_count(const TreeDev &t, const float *rays, int64_t m, int32_t *counts, hipStream_t s);
+arborx_status ray_nearest(const TreeDev &t, const float *rays, int64_t m, int k, float *t_out, int32_t *idx_out,
+                          hipStream_t s);
 // DBSCAN over the tree's own points (dbscan.hip): counts[i] holds the points
 // within eps of point i; parent is scratch of n ints; labels[n] the result.
 arborx_status dbscan(const TreeDev &t, const float *points, float eps, int min_pts, const uint32_t *perm,

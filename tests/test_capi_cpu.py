@@ -70,6 +70,8 @@ def test_query_argument_validation():
     assert L.arborx_query_spatial_count_up_to(None, FAKE, 1, f(1), 5, FAKE, None) == 1
     assert L.arborx_query_match_distances(None, FAKE, FAKE, 1, FAKE, FAKE, FAKE, None) == 1
     assert L.arborx_dbscan(None, FAKE, f(1), 2, FAKE, None) == 1
+    assert L.arborx_query_ray_count(None, FAKE, 1, FAKE, None) == 1
+    assert L.arborx_query_ray_nearest(None, FAKE, 1, 3, FAKE, FAKE, None) == 1
     assert L.arborx_query_intersects(None, FAKE, 1, FAKE, FAKE, 1, ctypes.byref(tot), None) == 1
     assert L.arborx_bvh_info(None, None, None, None, None, None) == 1
     assert L.arborx_debug_tree_nodes(None, FAKE, FAKE, FAKE, FAKE) == 1
