@@ -9,10 +9,16 @@ float32 points uniform in the unit cube, radius for ~10 neighbours.
 Prints ONE JSON line on stdout (progress goes to stderr):
   value      = queries answered per second over the timed steps, build included
                (4 query passes of M queries per step);
-  components = per-phase rates from events recorded on the launch stream;
+  components = per-phase rates from events recorded on the launch stream, and,
+               timed after the steps and outside them, the early-terminating
+               count, per-match distances, DBSCAN on the step's tree, and rays
+               against a tree of 2*10^6 boxes;
   roofline   = the dominant kernel's algorithmic bytes / its average duration
-               against MI355X HBM peak (8 TB/s);
-  cpu_baseline = the CPU oracle on a bounded sample of the same queries.
+               against MI355X HBM peak (8 TB/s), with the measured HBM traffic
+               while profiles/traffic.json matches the kernel sources, and the
+               measured device-copy rate;
+  cpu_baseline = the CPU oracle on a bounded sample of the same queries;
+  batched_vs_plain / chamfer = the forest and Chamfer workloads.
 """
 from __future__ import annotations
 
