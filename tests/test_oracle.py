@@ -604,3 +604,51 @@ def test_ray_vs_exact_rationals():
                 assert abs(got[j] - float(tt)) <= 1e-5 * (1 + abs(float(tt)))
             checked += 1
     assert checked > 40
+
+
+# ---------------------------------------------------------------------------
+# hand-worked box geometry: each face of the closed box, and touching faces
+# ---------------------------------------------------------------------------
+
+def test_box_distance_hand_worked_faces():
+    # value box [1,2] x [2,4] x [3,5]; every gap below is exact in binary32
+    box = np.array([[[1, 2, 3], [2, 4, 5]]], dtype=np.float32)
+    cases = [
+        ((0.5, 6.0, 4.0), 0.25 + 4.0),   # below lo in x (gap 0.5), above hi in y (gap 2), inside in z
+        ((1.5, 3.0, 1.0), 4.0),          # inside in x and y, below lo in z (gap 2)
+        ((-1.0, 1.5, 5.0), 4.0 + 0.25),  # below in x (gap 2), below in y (gap 0.5), on the hi face in z
+        ((2.0, 4.0, 8.0), 9.0),          # on the hi corner edge in x and y, above in z (gap 3)
+        ((1.25, 2.5, 3.5), 0.0),         # inside
+        ((1.0, 2.0, 3.0), 0.0),          # the lo corner itself belongs to the closed box
+    ]
+    for q, want in cases:
+        qa = np.array([q], dtype=np.float32)
+        d2, ix = oracle.knn(box, qa, 1, kind=oracle.BOXES)
+        assert ix[0, 0] == 0 and d2[0, 0] == np.float32(want), (q, d2[0, 0], want)
+        off, idx = oracle.spatial(box, qa, np.float32(0), kind=oracle.BOXES)
+        assert list(idx) == ([0] if want == 0.0 else [])
+    # a face mix-up (the far face's gap for a query below lo) would give 1.5^2 here, not 0.5^2
+    d2, _ = oracle.knn(box, np.array([[0.5, 3.0, 4.0]], dtype=np.float32), 1, kind=oracle.BOXES)
+    assert d2[0, 0] == np.float32(0.25)
+
+
+def test_intersects_touching_faces_are_closed():
+    unit = np.array([[[0, 0, 0], [1, 1, 1]]], dtype=np.float32)
+    up = np.nextafter(np.float32(1), np.float32(2))
+    down = np.nextafter(np.float32(0), np.float32(-1))
+    qb = np.array([
+        [[1, 0, 0], [2, 1, 1]],             # shares the x = 1 face: overlaps
+        [[-1, 0, 0], [0, 1, 1]],            # shares the x = 0 face from below: overlaps
+        [[1, 1, 1], [2, 2, 2]],             # touches only at the corner (1,1,1): overlaps
+        [[0.25, -1, 0.25], [0.5, 0, 0.5]],  # touches the y = 0 face: overlaps
+        [[up, 0, 0], [2, 1, 1]],            # one ulp past the x = 1 face: no overlap
+        [[-1, 0, 0], [down, 1, 1]],         # one ulp short of the x = 0 face: no overlap
+    ], dtype=np.float32)
+    off, idx = oracle.intersects(unit, qb, kind=oracle.BOXES)
+    assert np.diff(off).tolist() == [1, 1, 1, 1, 0, 0]
+    # point values on a query box's faces and corners belong to it
+    pts = np.array([[1, 0.5, 0.5], [2, 1, 1], [0, 0, 0], [up, 0.5, 0.5], [0.5, 0.5, down]], dtype=np.float32)
+    off, idx = oracle.intersects(pts, np.ascontiguousarray(unit), kind=oracle.POINTS)
+    assert idx.tolist() == [0, 2]
+    off, idx = oracle.intersects(pts, np.array([[[1, 0, 0], [2, 1, 1]]], dtype=np.float32), kind=oracle.POINTS)
+    assert idx.tolist() == [0, 1, 3]
