@@ -232,6 +232,28 @@ arborx_status arborx_query_knn(arborx_tree tree, const float *queries, int64_t m
                                int32_t *indices, void *stream);
 
 /*
+ * Allocation-free k-nearest search, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments and the same results, bit for bit, as
+ * arborx_query_knn, but the call allocates nothing: the Morton ordering of the
+ * queries runs in a static scratch area that the library holds once per GPU
+ * (ARBORX_NOALLOC_MAX_QUERIES x 16 bytes + 1 MiB, about 33 MiB, reserved with
+ * the library's code on that GPU until the process ends), and the order is not
+ * cached on the tree.
+ *   m       0..ARBORX_NOALLOC_MAX_QUERIES; larger m returns ARBORX_E_CAPACITY
+ *           before any device work.
+ * Every call on one GPU uses that GPU's one scratch area: calls that overlap
+ * in time on the same GPU (on different streams, or from different threads
+ * without ordering) race and give undefined results.  Calls ordered on one
+ * stream are safe; nothing has to be cleared between them.  While `stream` is
+ * being captured the call does not wait on the tree's build event (the
+ * caller orders the build before the capture).  Does not synchronise.
+ */
+#define ARBORX_NOALLOC_MAX_QUERIES 2097152
+arborx_status arborx_query_knn_noalloc(arborx_tree tree, const float *queries, int64_t m, int32_t k, float *dist2,
+                                       int32_t *indices, void *stream);
+
+/*
  * Radius search fused with a per-query reduction; nothing is stored per match
  * (Section 2.2, pure callback).
  *   op          ARBORX_COUNT or ARBORX_COUNT_SUMDIST

@@ -244,6 +244,30 @@ def arborx_query_knn(tree: Tree, queries, k: int, stream=None):
     return d2, idx
 
 
+def arborx_query_knn_noalloc(tree: Tree, queries, k: int, dist2=None, indices=None, stream=None):
+    """As arborx_query_knn, but the library allocates no device memory for the call (its query
+    ordering runs in a static per-GPU scratch area; m <= ARBORX_NOALLOC_MAX_QUERIES).  Pass
+    preallocated ``dist2`` float32[m, k] and ``indices`` int32[m, k] to keep the call free of
+    torch allocations too."""
+    torch = _torch()
+    q = _queries(tree, queries, False)
+    m = q.shape[0]
+    if dist2 is None:
+        dist2 = torch.empty((m, k), dtype=torch.float32, device=q.device)
+    if indices is None:
+        indices = torch.empty((m, k), dtype=torch.int32, device=q.device)
+    _dev(dist2, torch.float32, "dist2")
+    _dev(indices, torch.int32, "indices")
+    if tuple(dist2.shape) != (m, k) or tuple(indices.shape) != (m, k):
+        raise ValueError(f"dist2 and indices must be [{m}, {k}]")
+    _check(_lib.lib().arborx_query_knn_noalloc(tree.handle, _ptr(q), m, k, _ptr(dist2), _ptr(indices),
+                                               _stream(stream)))
+    return dist2, indices
+
+
+NOALLOC_MAX_QUERIES = 2097152  # ARBORX_NOALLOC_MAX_QUERIES in include/arborx.h
+
+
 def arborx_query_spatial_reduce(tree: Tree, queries, radius: float, op=COUNT_SUMDIST, scale_bits=32, stream=None):
     """Fused radius reduce: counts int32[m] and (COUNT_SUMDIST) sum_fixed int64[m]."""
     torch = _torch()

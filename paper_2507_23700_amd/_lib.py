@@ -30,6 +30,7 @@ SIGNATURES = {
     "arborx_query_spatial": (I32, [P, P, I64, F32, P, P, I64, P, P]),
     "arborx_query_intersects": (I32, [P, P, I64, P, P, I64, P, P]),
     "arborx_query_knn": (I32, [P, P, I64, I32, P, P, P]),
+    "arborx_query_knn_noalloc": (I32, [P, P, I64, I32, P, P, P]),
     "arborx_query_spatial_reduce": (I32, [P, P, I64, F32, I32, P, P, I32, P]),
     "arborx_query_spatial_count_up_to": (I32, [P, P, I64, F32, I32, P, P]),
     "arborx_query_match_distances": (I32, [P, P, P, I64, P, P, P, P]),

@@ -795,6 +795,33 @@ arborx_status arborx_query_knn(arborx_tree t, const float *queries, int64_t m, i
     return knn_query(t->dev, queries, m, k, perm, dist2, indices, s);
 }
 
+arborx_status arborx_query_knn_noalloc(arborx_tree t, const float *queries, int64_t m, int32_t k, float *dist2,
+                                       int32_t *indices, void *stream)
+{
+    arborx_status st = check_tree(t);
+    if (st != ARBORX_OK)
+        return st;
+    if (m < 0)
+        return fail(ARBORX_E_INVALID, "m must be >= 0");
+    if (k < 1 || k > 64)
+        return fail(ARBORX_E_INVALID, "k must be in 1..64");
+    if (m > 0 && (!queries || !dist2 || !indices))
+        return fail(ARBORX_E_INVALID, "queries, dist2 and indices must not be NULL");
+    if (m > ARBORX_NOALLOC_MAX_QUERIES)
+        return fail(ARBORX_E_CAPACITY, "m = " + std::to_string((long long)m) +
+                                           " exceeds ARBORX_NOALLOC_MAX_QUERIES = " +
+                                           std::to_string(ARBORX_NOALLOC_MAX_QUERIES));
+    if ((st = check_device()) != ARBORX_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    AX_HIP(hipStreamIsCapturing(s, &cs));
+    if (cs == hipStreamCaptureStatusNone && (st = wait_tree(t, s)) != ARBORX_OK)
+        return st;
+    NoteUse note_use{t->uses, s};
+    return knn_query_noalloc(t->dev, queries, m, k, dist2, indices, s);
+}
+
 arborx_status arborx_query_spatial_reduce(arborx_tree t, const float *queries, int64_t m, float radius, int32_t op,
                                           int32_t *counts, int64_t *sum_fixed, int32_t scale_bits, void *stream)
 {

@@ -245,6 +245,10 @@ arborx_status spatial_count_up_to(const TreeDev &t, const float *queries, int64_
                                   const uint32_t *perm, int32_t *counts, hipStream_t s);
 arborx_status knn_query(const TreeDev &t, const float *queries, int64_t m, int k, const uint32_t *perm,
                         float *dist2, int32_t *indices, hipStream_t s);
+// kNN whose query ordering runs in the library's static per-device scratch
+// (at most ARBORX_NOALLOC_MAX_QUERIES queries): no device allocation.
+arborx_status knn_query_noalloc(const TreeDev &t, const float *queries, int64_t m, int k, float *dist2,
+                                int32_t *indices, hipStream_t s);
 
 // Matches a CSR count walk keeps per query (its stash row), sorted in
 // registers when copied out; longer rows are walked again.  32 in 6D, where

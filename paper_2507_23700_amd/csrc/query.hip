@@ -12,6 +12,9 @@
 // children.  A child that is a leaf is decided from the slot box alone: for
 // point values the box is the point, and the box distance equals the point
 // distance bit for bit.
+#include <mutex>
+#include <string>
+
 #include "device_util.hpp"
 #include "geometry.hpp"
 #include "internal.hpp"
@@ -877,18 +880,14 @@ arborx_status knn_impl(const TreeDev &t, const float *q, int64_t m, int k, const
     return knn_launch<D, 64>(t, q, m, k, perm, d2, idx, s);
 }
 
+// Query order into caller-given buffers: codes/codes2/ids/ids2 of m entries
+// each and a radix workspace of radix_workspace_bytes(m); *perm points into
+// ids or ids2.
 template <int D>
-arborx_status order_impl(const TreeDev &t, const float *q, int64_t m, Pred pred, int order, uint32_t **perm,
-                         Temps &tmp, hipStream_t s)
+arborx_status order_into(const TreeDev &t, const float *q, int64_t m, Pred pred, int order, uint32_t *codes,
+                         uint32_t *codes2, uint32_t *ids, uint32_t *ids2, void *ws, uint32_t **perm, hipStream_t s)
 {
     const int bits = order_bits(order) / D;
-    uint32_t *codes, *codes2, *ids, *ids2;
-    uint8_t *ws;
-    arborx_status st;
-    if ((st = tmp.get(&codes, m)) != ARBORX_OK || (st = tmp.get(&codes2, m)) != ARBORX_OK ||
-        (st = tmp.get(&ids, m)) != ARBORX_OK || (st = tmp.get(&ids2, m)) != ARBORX_OK ||
-        (st = tmp.get(&ws, radix_workspace_bytes(m))) != ARBORX_OK)
-        return st;
     ProfScope ps("order", s);
     if (pred == Pred::Sphere)
         k_query_codes<D, false><<<grid_for(m, 256, 65536), 256, 0, s>>>(q, m, t.hdr, codes, ids, bits);
@@ -898,6 +897,20 @@ arborx_status order_impl(const TreeDev &t, const float *q, int64_t m, Pred pred,
     AX_HIP(radix_sort_pairs<uint32_t>(codes, ids, codes2, ids2, m, 0, bits * D, ws, s, &alt));
     *perm = alt ? ids2 : ids;
     return ARBORX_OK;
+}
+
+template <int D>
+arborx_status order_impl(const TreeDev &t, const float *q, int64_t m, Pred pred, int order, uint32_t **perm,
+                         Temps &tmp, hipStream_t s)
+{
+    uint32_t *codes, *codes2, *ids, *ids2;
+    uint8_t *ws;
+    arborx_status st;
+    if ((st = tmp.get(&codes, m)) != ARBORX_OK || (st = tmp.get(&codes2, m)) != ARBORX_OK ||
+        (st = tmp.get(&ids, m)) != ARBORX_OK || (st = tmp.get(&ids2, m)) != ARBORX_OK ||
+        (st = tmp.get(&ws, radix_workspace_bytes(m))) != ARBORX_OK)
+        return st;
+    return order_into<D>(t, q, m, pred, order, codes, codes2, ids, ids2, ws, perm, s);
 }
 
 #define AX_DISPATCH_DIM(dim, CALL)                                              \
@@ -1115,6 +1128,78 @@ arborx_status knn_query(const TreeDev &t, const float *queries, int64_t m, int k
     if (st != ARBORX_OK)
         return st;
     AX_DISPATCH_DIM(t.dim, (knn_impl<D>(t, queries, m, k, perm, dist2, indices, s)));
+}
+
+
+// ---- allocation-free kNN ---------------------------------------------------
+// Scratch of arborx_query_knn_noalloc: the query-ordering buffers (two code
+// and two id arrays of kNoAllocMaxQueries entries, then the radix sort's tile
+// histograms).  One copy per GPU, loaded with the code object and kept until
+// the process ends.  In host code `scratch` names a host-side stand-in, so
+// only the device address from hipGetSymbolAddress is ever passed to kernels.
+constexpr int64_t kNoAllocMaxQueries = ARBORX_NOALLOC_MAX_QUERIES;
+constexpr size_t kNoAllocArrayBytes = (size_t)kNoAllocMaxQueries * sizeof(uint32_t);
+constexpr size_t kNoAllocWsBytes = size_t(1) << 20;
+constexpr size_t kNoAllocScratchBytes = 4 * kNoAllocArrayBytes + kNoAllocWsBytes;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[64] = {};
+
+// Device address of this GPU's scratch, looked up once per device with that
+// device current.
+static arborx_status scratch_address(void **out)
+{
+    int dev = -1;
+    AX_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64)
+        return fail(ARBORX_E_DEVICE, "device index out of range for the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return ARBORX_OK;
+}
+
+arborx_status knn_query_noalloc(const TreeDev &t, const float *queries, int64_t m, int k, float *dist2,
+                                int32_t *indices, hipStream_t s)
+{
+    if (m > kNoAllocMaxQueries)
+        return fail(ARBORX_E_CAPACITY, "m = " + std::to_string((long long)m) +
+                                           " exceeds the allocation-free limit of " +
+                                           std::to_string((long long)kNoAllocMaxQueries) + " queries");
+    if (m == 0)
+        return ARBORX_OK;
+    uint32_t *perm = nullptr;
+    const int order = tuning(OP_KNN).order;
+    if (order && t.n > 0 && m > 1) {
+        if (radix_workspace_bytes(m) > kNoAllocWsBytes)
+            return fail(ARBORX_E_CAPACITY, "radix workspace exceeds the allocation-free scratch");
+        void *base = nullptr;
+        arborx_status st = scratch_address(&base);
+        if (st != ARBORX_OK)
+            return st;
+        unsigned char *b = static_cast<unsigned char *>(base);
+        uint32_t *codes = reinterpret_cast<uint32_t *>(b);
+        uint32_t *codes2 = reinterpret_cast<uint32_t *>(b + kNoAllocArrayBytes);
+        uint32_t *ids = reinterpret_cast<uint32_t *>(b + 2 * kNoAllocArrayBytes);
+        uint32_t *ids2 = reinterpret_cast<uint32_t *>(b + 3 * kNoAllocArrayBytes);
+        void *ws = b + 4 * kNoAllocArrayBytes;
+        switch (t.dim) {
+        case 2: st = order_into<2>(t, queries, m, Pred::Sphere, order, codes, codes2, ids, ids2, ws, &perm, s); break;
+        case 3: st = order_into<3>(t, queries, m, Pred::Sphere, order, codes, codes2, ids, ids2, ws, &perm, s); break;
+        case 6: st = order_into<6>(t, queries, m, Pred::Sphere, order, codes, codes2, ids, ids2, ws, &perm, s); break;
+        default: return fail(ARBORX_E_UNSUPPORTED, "dimension not compiled in");
+        }
+        if (st != ARBORX_OK)
+            return st;
+    }
+    return knn_query(t, queries, m, k, perm, dist2, indices, s);
 }
 
 }  // namespace ax
