@@ -10,7 +10,18 @@
 namespace ax {
 namespace {
 
-constexpr int kSpill = 128;  // > any tree height: 63 code-bit levels + 32 position levels
+// Deepest tree the build can make.  Along a root-to-leaf path the split keys
+// (code XOR of neighbouring leaves, or position XOR for equal codes) strictly
+// decrease, and two splits with the same highest bit always have a larger
+// split between them in sorted order, so no path repeats a highest bit: at
+// most 63 code bits + 31 position bits + the leaf edge.
+constexpr int kMaxTreeHeight = 95;
+// Spill entries behind the LDS ring.  A binary walk pushes at most one entry
+// per level, a four-wide walk at most three per four-wide level (two binary
+// levels), so no walk ever holds more than 3 * ceil(95 / 2) = 144 deferred
+// entries, even with a one-entry ring: the spill area never overflows.
+constexpr int kSpill = 160;
+static_assert(kSpill >= 3 * ((kMaxTreeHeight + 1) / 2), "spill area below the four-wide walk's bound");
 
 // The ring indices live in registers; only the rarely used spill area (a
 // separate private array owned by the caller) sits in scratch memory.  Keeping
@@ -29,7 +40,7 @@ struct ShortStack {
     __device__ __forceinline__ void push(E x)
     {
         if (cnt == mask + 1) {  // ring full: move the oldest LDS entry to the spill area
-            if (ns < kSpill)
+            if (ns < kSpill)    // always true (see kSpill); the check only keeps the store in bounds
                 spill[ns++] = lds[(base & mask) << shift];
             ++base;
             --cnt;
@@ -260,10 +271,11 @@ __device__ __forceinline__ void traverse_spatial_packet(const Node<D> *__restric
 // same in every lane, so each node is fetched once per wavefront through the
 // scalar cache, and the stack of deferred nodes is one per wavefront in LDS.
 // A stack entry is pushed only at a level where some lane needs both
-// children, so its depth never exceeds the tree height (at most 63 code-bit
-// levels plus 32 position levels), below kWaveStack.  Lanes without a query
+// children, so its depth never exceeds the tree height (kMaxTreeHeight),
+// below kWaveStack.  Lanes without a query
 // (`active` false) carry a predicate that matches nothing.
 constexpr int kWaveStack = 128;
+static_assert(kWaveStack > kMaxTreeHeight, "wavefront stack below the tree height bound");
 
 template <int D, class P, class F>
 __device__ __forceinline__ void traverse_spatial_wave(const Node<D> *__restrict__ nodes, int root, int n_nodes,

@@ -705,3 +705,38 @@ def test_match_distances(case):
     want = oracle.match_distances(data, q, o_off, o_idx, dim=dim, kind=kind)
     assert np.array_equal(host(d2), want)
     assert np.all(host(d2) <= np.float32(r) * np.float32(r))
+
+
+def _deepest_tree_points():
+    """A comb with one split at every Morton code bit (cell coordinate 2^j in one
+    dimension, 0 in the others, j = 0..20, bounds [0, 1]) above 2^14 copies of the
+    origin (a position subtree of depth 14): about 78 levels, close to the deepest
+    tree the build can make, where walks defer the most subtrees."""
+    pts = [np.zeros(3)] * (1 << 14) + [np.ones(3)]
+    for d in range(3):
+        for j in range(21):
+            p = np.zeros(3)
+            p[d] = 2.0 ** (j - 21)
+            pts.append(p)
+    return np.array(pts, dtype=np.float32)
+
+
+@pytest.mark.parametrize("tuning", [dict(stack=1), dict(stack=1, node_format=2), dict(stack=1, node_format=1),
+                                    dict(stack=1, schedule=1), dict(stack=1, schedule=2),
+                                    dict(stack=1, queries_per_thread=4)])
+def test_deepest_tree_one_entry_ring(tuning):
+    data = _deepest_tree_points()
+    g = np.random.default_rng(77)
+    q = np.concatenate([data[-70:], g.random((30, 3))]).astype(np.float32)
+    ax.arborx_set_tuning(**tuning)
+    try:
+        t = ax.arborx_bvh_build(dev(data))
+        h = ax.arborx_bvh_info(t)["height"]
+        assert 70 <= h <= 95
+        for r in (float("inf"), 2.0 ** -20, 0.0):  # every value deferred and found again at r = inf
+            check_spatial(t, data, q, r)
+            check_reduce(t, data, q, r)
+        check_knn(t, data, q, 64)
+        check_knn(t, data, q, 3)
+    finally:
+        ax.arborx_reset_tuning()
