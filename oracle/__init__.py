@@ -71,13 +71,15 @@ def lib():
         L.oracle_count_up_to.argtypes = [P, I64, I32, I32, P, I64, F32, I32, P]
         L.oracle_match_distances.argtypes = [P, I64, I32, I32, P, I64, P, P, P]
         L.oracle_dbscan.argtypes = [P, I64, I32, F32, I32, P]
+        L.oracle_self_join_degree.argtypes = [P, I64, I32, F32, P]
+        L.oracle_self_join_pairs.argtypes = [P, I64, I32, F32, P, P]
         L.oracle_ray_count.argtypes = [P, I64, I32, I32, P, I64, P]
         L.oracle_ray_nearest.argtypes = [P, I64, I32, I32, P, I64, I32, P, P]
         L.oracle_knn.argtypes = [P, I64, I32, I32, P, I64, I32, P, P]
         L.oracle_chamfer_forward.argtypes = [P, P, P, P, I32, P, P, P]
         L.oracle_chamfer_backward.argtypes = [P, P, P, P, I32, P, P, P, P, P]
         for f in ("oracle_spatial_count", "oracle_spatial_fill", "oracle_intersects_count", "oracle_intersects_fill",
-                  "oracle_reduce", "oracle_count_up_to", "oracle_knn", "oracle_chamfer_forward", "oracle_chamfer_backward",
+                  "oracle_reduce", "oracle_count_up_to", "oracle_self_join_degree", "oracle_self_join_pairs", "oracle_knn", "oracle_chamfer_forward", "oracle_chamfer_backward",
                   "oracle_threads"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -185,6 +187,25 @@ def dbscan(points, eps, min_pts, dim=3):
     if lib().oracle_dbscan(_p(v), n, dim, np.float32(eps), np.int32(min_pts), _p(labels)) != 0:
         raise MemoryError("oracle_dbscan")
     return labels
+
+
+def self_join_degree(points, radius, dim=3):
+    """Pair search (Section 2.6) as a self-join: int32 degree[i] = number of j != i with
+    d2(p_i, p_j) <= fl(r*r)."""
+    v, n = _values(points, dim, POINTS)
+    deg = np.zeros(n, dtype=np.int32)
+    lib().oracle_self_join_degree(_p(v), n, dim, np.float32(radius), _p(deg))
+    return deg
+
+
+def self_join_pairs(points, radius, dim=3):
+    """The self-join's unordered pairs as upper-triangle CSR: row i = ascending j > i within r."""
+    v, n = _values(points, dim, POINTS)
+    off = np.zeros(n + 1, dtype=np.int64)
+    lib().oracle_self_join_pairs(_p(v), n, dim, np.float32(radius), _p(off), None)
+    idx = np.zeros(int(off[-1]), dtype=np.int32)
+    lib().oracle_self_join_pairs(_p(v), n, dim, np.float32(radius), _p(off), _p(idx))
+    return off, idx
 
 
 def match_distances(values, queries, offsets, indices, dim=3, kind=POINTS):

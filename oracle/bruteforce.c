@@ -23,6 +23,8 @@
  *     counted n_max matches, so its result is min(count, n_max);
  *   - the callback-with-output form (Section 2.1, query call (2)) as the
  *     squared distance of each match of a CSR result;
+ *   - search for pairs of objects (Section 2.6): the self-join of a point set
+ *     with a radius, as per-point pair counts and upper-triangle CSR rows;
  *   - density-based clustering over the radius search (Section 2.4, DBSCAN):
  *     core points, their eps-connected components and border points;
  *   - ray predicates (Section 2.5): the values a ray meets, counted, and the k
@@ -381,6 +383,48 @@ int oracle_count_up_to(const float *values, int64_t n, int dim, int kind, const 
             if (dist2_value(values, j, dim, kind, q) <= r2)
                 ++c;
         counts[i] = c;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* pair search (self-join)                                              */
+/* ------------------------------------------------------------------ */
+
+/* Search for pairs of objects (Section 2.6 names a dedicated traversal for
+ * it; DBSCAN of Section 2.4 is built on it), read as the self-join of a point
+ * set with a radius: the unordered pairs {i, j}, i != j, whose squared distance
+ * is at most fl(r*r).  degree[i] = the number of j != i paired with i. */
+int oracle_self_join_degree(const float *points, int64_t n, int dim, float radius, int32_t *degree)
+{
+    const float r2 = radius * radius;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t c = 0;
+        for (int64_t j = 0; j < n; ++j)
+            if (j != i && dist2_point(points + i * dim, points + j * dim, dim) <= r2)
+                ++c;
+        degree[i] = c;
+    }
+    return 0;
+}
+
+/* The same pairs as CSR rows of the upper triangle: row i lists the j > i
+ * paired with i, ascending; offsets[n] is the number of pairs.  Call with
+ * indices == NULL to get the offsets only. */
+int oracle_self_join_pairs(const float *points, int64_t n, int dim, float radius, int64_t *offsets, int32_t *indices)
+{
+    const float r2 = radius * radius;
+    offsets[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = 0;
+        for (int64_t j = i + 1; j < n; ++j)
+            if (dist2_point(points + i * dim, points + j * dim, dim) <= r2) {
+                if (indices)
+                    indices[offsets[i] + c] = (int32_t)j;
+                ++c;
+            }
+        offsets[i + 1] = offsets[i] + c;
     }
     return 0;
 }

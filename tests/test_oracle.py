@@ -652,3 +652,59 @@ def test_intersects_touching_faces_are_closed():
     assert idx.tolist() == [0, 2]
     off, idx = oracle.intersects(pts, np.array([[[1, 0, 0], [2, 1, 1]]], dtype=np.float32), kind=oracle.POINTS)
     assert idx.tolist() == [0, 1, 3]
+
+
+# ---------------------------------------------------------------------------
+# pair search (self-join)
+# ---------------------------------------------------------------------------
+
+def test_self_join_hand_worked():
+    # points on a line x = 0, 1, 2, 10, 11, 20
+    pts = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0], [10, 0, 0], [11, 0, 0], [20, 0, 0]], dtype=np.float32)
+    for r in (1.5, 1.0):  # closed ball: neighbours exactly 1 apart pair at r = 1
+        assert list(oracle.self_join_degree(pts, r)) == [1, 2, 1, 1, 1, 0]
+        off, idx = oracle.self_join_pairs(pts, r)
+        assert list(off) == [0, 1, 2, 2, 3, 3, 3] and list(idx) == [1, 2, 4]
+    assert list(oracle.self_join_degree(pts, np.nextafter(np.float32(1), np.float32(0)))) == [0] * 6
+    assert list(oracle.self_join_degree(pts, 2.0)) == [2, 2, 2, 1, 1, 0]
+    off, idx = oracle.self_join_pairs(pts, 2.0)
+    assert list(off) == [0, 2, 3, 3, 4, 4, 4] and list(idx) == [1, 2, 2, 4]
+    # duplicates pair at r = 0, and a point never pairs with itself
+    dup = np.zeros((3, 3), dtype=np.float32)
+    assert list(oracle.self_join_degree(dup, 0.0)) == [2, 2, 2]
+    off, idx = oracle.self_join_pairs(dup, 0.0)
+    assert list(off) == [0, 2, 3, 3] and list(idx) == [1, 2, 2]
+    assert list(oracle.self_join_degree(pts[:1], 100.0)) == [0]
+    assert len(oracle.self_join_degree(pts[:0], 1.0)) == 0
+
+
+@pytest.mark.parametrize("k", [2, 5])
+def test_self_join_grid_closed_forms(k):
+    # integer lattice k^3 (exact in float32): r = 1 pairs the axis neighbours, 3 k^2 (k-1) pairs;
+    # r = 1.5 adds the face diagonals (d2 = 2), 6 k (k-1)^2 more
+    ax_ = np.arange(k, dtype=np.float32)
+    pts = np.stack(np.meshgrid(ax_, ax_, ax_, indexing="ij"), axis=-1).reshape(-1, 3)
+    deg = oracle.self_join_degree(pts, 1.0)
+    inner = lambda x: (x > 0).astype(int) + (x < k - 1).astype(int)  # noqa: E731
+    assert np.array_equal(deg, inner(pts[:, 0]) + inner(pts[:, 1]) + inner(pts[:, 2]))
+    off, _ = oracle.self_join_pairs(pts, 1.0)
+    assert off[-1] == 3 * k * k * (k - 1) and deg.sum() == 2 * off[-1]
+    off, _ = oracle.self_join_pairs(pts, 1.5)
+    assert off[-1] == 3 * k * k * (k - 1) + 6 * k * (k - 1) ** 2
+
+
+@pytest.mark.parametrize("dim", [3, 6])
+def test_self_join_vs_kdtree_pairs(dim):
+    g = np.random.default_rng(40 + dim)
+    pts = g.random((2500, dim)).astype(np.float32)
+    r = 0.06 if dim == 3 else 0.3
+    off, idx = oracle.self_join_pairs(pts, r, dim=dim)
+    got = set(zip(np.repeat(np.arange(len(pts)), np.diff(off)).tolist(), idx.tolist()))
+    tree = cKDTree(pts.astype(np.float64))
+    inner = tree.query_pairs(r * (1 - 1e-5))  # float64 pairs, radius bracketed away from ties
+    outer = tree.query_pairs(r * (1 + 1e-5))
+    assert inner <= got <= outer and len(got) > 1000
+    deg = oracle.self_join_degree(pts, r, dim=dim)
+    assert np.array_equal(deg, np.bincount(np.array(sorted(got)).ravel(), minlength=len(pts)))
+    # a point's partners are its radius-search matches without itself
+    assert np.array_equal(deg, oracle.spatial_count(pts, pts, r, dim=dim) - 1)
