@@ -103,7 +103,7 @@ KERNEL_PHASE = [  # rocprofv3 kernel name fragment -> phase name used by the in-
     ("k_knn<", "knn"), ("k_spatial_count<", "spatial_count"), ("k_spatial_reduce<3, false", "reduce_count"),
     ("k_spatial_reduce<3, true", "reduce_sumdist"), ("k_spatial_fill_rows<", "spatial_fill"),
     ("hierarchy_chunk_kernel<", "build_hierarchy"), ("hierarchy_top_kernel<", "build_hierarchy"),
-    ("k_copy_stash", "copy_stash"), ("k_copy_overflow", "copy_overflow"), ("k_count_up_to", "count_up_to"), ("k_match_distances", "match_distances"), ("k_dbscan_", "dbscan"), ("k_ray_count", "ray_count"), ("k_ray_nearest", "ray_nearest"), ("radix_scatter<", "radix_scatter"), ("radix_hist<", "radix_hist"),
+    ("k_copy_stash", "copy_stash"), ("k_copy_overflow", "copy_overflow"), ("k_count_up_to", "count_up_to"), ("k_match_distances", "match_distances"), ("k_dbscan_", "dbscan"), ("k_pair_degree", "pair_degree"), ("k_ray_count", "ray_count"), ("k_ray_nearest", "ray_nearest"), ("radix_scatter<", "radix_scatter"), ("radix_hist<", "radix_hist"),
 ]
 
 
@@ -210,9 +210,26 @@ def cpu_baseline(data, queries, radius, k, target_s=15.0, max_sample=20000):
     s = int(min(max_sample, max(probe, probe * target_s / max(dt, 1e-6))))
     sel = np.sort(g.choice(len(queries), s, replace=False))
     dt, res = run(queries[sel])
-    return dict(value=4 * s / dt, unit="queries/s", cores=oracle.threads(), kind="oracle",
+    return dict(value=4 * s / dt, unit="queries/s", cores=oracle.threads(), kind="oracle", **host_cpu(),
                 sample=f"{s} seeded queries of the same workload (CSR radius, COUNT, COUNT_SUMDIST, kNN k={k}) "
                        f"against all {len(data)} points; {dt:.1f} s"), sel, res
+
+
+def host_cpu():
+    """Model name and vector extensions of the host CPU the oracle ran on."""
+    model, flags = "unknown", set()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name") and model == "unknown":
+                    model = line.split(":", 1)[1].strip()
+                elif line.startswith("flags") and not flags:
+                    flags = set(line.split(":", 1)[1].split())
+    except OSError:
+        pass
+    simd = [x for x in ("sse4_2", "avx", "avx2", "fma", "avx512f", "avx512bw", "avx512vl", "avx512_bf16")
+            if x in flags]
+    return {"cpu_model": model, "simd": " ".join(simd), "host_threads": os.cpu_count()}
 
 
 def timed(fn, reps=3):
@@ -485,9 +502,27 @@ def main():
     ms = timed(lambda: ax.arborx_query_ray_nearest(btree, rays, 1), 3)
     comps["ray_first_hit_rays_s"] = rays.shape[0] / ms * 1e3
     del btree, boxes, rays
-    # DBSCAN over the tree's points (eps = the step's radius, min_pts = 10)
+    # DBSCAN over the tree's points (eps = the step's radius, min_pts = 10), and the pair search it is
+    # built on (the self-join of the tree's points at the same radius)
     ms = timed(lambda: ax.arborx_dbscan(tree, d, radius, 10), 3)
     comps["dbscan_mpts_s"] = n / ms / 1e3
+    ms = timed(lambda: ax.arborx_self_join_degree(tree, radius), 3)
+    comps["self_join_mpts_s"] = n / ms / 1e3
+    # standalone calls: inside the step the reductions and kNN reuse the query order that the CSR call
+    # computed and cached on the tree; alternating two copies of the queries makes every call order
+    # its queries again, as a call on fresh queries does
+    q_alt = q.clone()
+    qs = [q, q_alt]
+    for name, fn in (("reduce_count", lambda qq: ax.arborx_query_spatial_reduce(tree, qq, radius, ax.COUNT)),
+                     (f"knn{k}", lambda qq: ax.arborx_query_knn(tree, qq, k))):
+        ctr = [0]
+
+        def call(fn=fn, ctr=ctr):
+            ctr[0] += 1
+            fn(qs[ctr[0] % 2])
+        ms = timed(call, 5)
+        comps[f"{name}_standalone_qps"] = m / ms * 1e3
+    del q_alt, qs
 
     # dominant kernel by GPU time in the timed region
     dom = max((kn for kn in prof if algorithmic_bytes(kn, n, m, dim, k, total)), key=lambda kn: prof[kn][0])

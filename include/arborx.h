@@ -304,14 +304,30 @@ arborx_status arborx_query_match_distances(arborx_tree tree, const float *values
  *   border point  (not core, some core point within eps) the label of its
  *                 smallest-index core neighbour;
  *   noise         -1.
- * These tie rules make the result unique.
- *   points  the [n][dim] array the tree was built from (a tree of points)
+ * These tie rules make the result unique.  Built on the pair search of
+ * arborx_self_join_degree: every pair of points within eps is met once.
+ *   points  the [n][dim] array the tree was built from (a tree of points); the
+ *           walks read the same coordinates from the tree's leaf records
  *   eps >= 0 (NaN is ARBORX_E_INVALID);  min_pts >= 0 (0 or 1: every point is core)
  *   labels  [n] int32 output
- * Asynchronous; temporary memory about 12 bytes per point plus the query order.
+ * Asynchronous; temporary memory 16 bytes per point.
  */
 arborx_status arborx_dbscan(arborx_tree tree, const float *points, float eps, int32_t min_pts, int32_t *labels,
                             void *stream);
+
+/*
+ * Search for pairs of objects (Section 2.6: a dedicated traversal for it), as
+ * the self-join of the tree's own points with a radius: the unordered pairs
+ * {i, j}, i != j, with d2(p_i, p_j) <= fl(radius*radius) (closed ball).  Each
+ * leaf walks only the part of the tree after its own sorted position, so every
+ * pair is found exactly once.
+ *   radius >= 0 (NaN is ARBORX_E_INVALID); +inf pairs everything
+ *   degree [n] int32 output, input order: degree[i] = number of j != i paired
+ *          with i (the number of pairs is half the sum)
+ * A tree of boxes is ARBORX_E_INVALID.  Asynchronous; temporary memory 4 bytes
+ * per point.
+ */
+arborx_status arborx_self_join_degree(arborx_tree tree, float radius, int32_t *degree, void *stream);
 
 /*
  * Ray predicates (Section 2.5: rays traced against the index's values).  Ray i

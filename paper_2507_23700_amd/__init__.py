@@ -337,6 +337,17 @@ def arborx_dbscan(tree: Tree, points, eps: float, min_pts: int, stream=None):
     return labels
 
 
+def arborx_self_join_degree(tree: Tree, radius: float, stream=None):
+    """Pair search over the tree's own points: int32 degree[i] = number of values j != i within
+    radius of value i (every unordered pair is found once, by a walk over the later leaves)."""
+    torch = _torch()
+    if tree.kind != POINTS:
+        raise ValueError("the self-join pairs the points of a tree built from points")
+    deg = torch.empty(tree.n, dtype=torch.int32, device="cuda")
+    _check(_lib.lib().arborx_self_join_degree(tree.handle, ctypes.c_float(radius), _ptr(deg), _stream(stream)))
+    return deg
+
+
 def arborx_query_spatial_count_up_to(tree: Tree, queries, radius: float, n_max: int, stream=None):
     """Early-terminating count: int32[m] = min(matches within radius, n_max)."""
     torch = _torch()

@@ -35,6 +35,7 @@ SIGNATURES = {
     "arborx_query_spatial_count_up_to": (I32, [P, P, I64, F32, I32, P, P]),
     "arborx_query_match_distances": (I32, [P, P, P, I64, P, P, P, P]),
     "arborx_dbscan": (I32, [P, P, F32, I32, P, P]),
+    "arborx_self_join_degree": (I32, [P, F32, P, P]),
     "arborx_query_ray_count": (I32, [P, P, I64, P, P]),
     "arborx_query_ray_nearest": (I32, [P, P, I64, I32, P, P, P]),
     "arborx_debug_radix_sort": (I32, [P, P, I64, I32, I32, I32, P]),

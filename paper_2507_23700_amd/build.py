@@ -22,7 +22,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
-SOURCES = ["sort.hip", "scan.hip", "build.hip", "query.hip", "forest.hip", "chamfer.hip", "dbscan.hip", "ray.hip", "autotune.hip", "capi.cpp", "profile.cpp"]
+SOURCES = ["sort.hip", "scan.hip", "build.hip", "query.hip", "forest.hip", "chamfer.hip", "pairs.hip", "ray.hip", "autotune.hip", "capi.cpp", "profile.cpp"]
 
 
 def _compile(src: str) -> str:

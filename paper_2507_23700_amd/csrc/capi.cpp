@@ -913,15 +913,29 @@ arborx_status arborx_dbscan(arborx_tree t, const float *points, float eps, int32
     if (n == 0)
         return ARBORX_OK;
     NoteUse note_use{t->uses, s};
-    Temps tmp(s);
-    uint32_t *perm = nullptr;
-    int32_t *counts = nullptr, *parent = nullptr;
-    if ((st = tree_order(t, points, n, Pred::Sphere, OP_REDUCE, &perm, tmp, s)) != ARBORX_OK ||
-        (st = tmp.get(&counts, n)) != ARBORX_OK || (st = tmp.get(&parent, n)) != ARBORX_OK)
+    return dbscan(t->dev, eps, min_pts, labels, s);
+}
+
+arborx_status arborx_self_join_degree(arborx_tree t, float radius, int32_t *degree, void *stream)
+{
+    arborx_status st = check_tree(t);
+    if (st != ARBORX_OK)
         return st;
-    if ((st = spatial_reduce(t->dev, points, n, eps, ARBORX_COUNT, 0, perm, counts, nullptr, s)) != ARBORX_OK)
+    if (t->dev.kind != ARBORX_POINTS)
+        return fail(ARBORX_E_INVALID, "the self-join pairs the points of a tree built from points");
+    if (std::isnan(radius) || radius < 0.0f)
+        return fail(ARBORX_E_INVALID, "radius must be >= 0 and not NaN");
+    if (t->dev.n > 0 && !degree)
+        return fail(ARBORX_E_INVALID, "degree must not be NULL");
+    if ((st = check_device()) != ARBORX_OK)
         return st;
-    return dbscan(t->dev, points, eps, min_pts, perm, counts, parent, labels, s);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = wait_tree(t, s)) != ARBORX_OK)
+        return st;
+    if (t->dev.n == 0)
+        return ARBORX_OK;
+    NoteUse note_use{t->uses, s};
+    return self_join_degree(t->dev, radius, degree, s);
 }
 
 arborx_status arborx_query_match_distances(arborx_tree t, const float *values, const float *queries, int64_t m,

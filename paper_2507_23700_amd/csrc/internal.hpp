@@ -236,10 +236,11 @@ arborx_status match_distances(const TreeDev &t, const float *values, const float
 arborx_status ray_count(const TreeDev &t, const float *rays, int64_t m, int32_t *counts, hipStream_t s);
 arborx_status ray_nearest(const TreeDev &t, const float *rays, int64_t m, int k, float *t_out, int32_t *idx_out,
                           hipStream_t s);
-// DBSCAN over the tree's own points (dbscan.hip): counts[i] holds the points
-// within eps of point i; parent is scratch of n ints; labels[n] the result.
-arborx_status dbscan(const TreeDev &t, const float *points, float eps, int min_pts, const uint32_t *perm,
-                     int32_t *counts, int32_t *parent, int32_t *labels, hipStream_t s);
+// Pair search over the tree's own points (pairs.hip): degree[i] = number of
+// values j != i within radius of value i (input order).
+arborx_status self_join_degree(const TreeDev &t, float radius, int32_t *degree, hipStream_t s);
+// DBSCAN over the tree's own points (pairs.hip), labels[n] in input order.
+arborx_status dbscan(const TreeDev &t, float eps, int min_pts, int32_t *labels, hipStream_t s);
 // Early-terminating count: counts[i] = min(matches of query i, n_max).
 arborx_status spatial_count_up_to(const TreeDev &t, const float *queries, int64_t m, float radius, int n_max,
                                   const uint32_t *perm, int32_t *counts, hipStream_t s);

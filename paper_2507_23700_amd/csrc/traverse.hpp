@@ -370,6 +370,58 @@ __device__ __forceinline__ void traverse_spatial_rope(const Node<D> *__restrict_
     }
 }
 
+// Pair-search walk (Section 2.6 names a dedicated traversal for searching
+// pairs of objects) for the value at sorted position p of a single tree: the
+// rope walk started at p's own rope.  In depth-first order the slot after leaf
+// p is (node p, right side) -- node p separates leaves p and p + 1, whichever
+// of nodes p - 1 and p holds the leaf -- and the ropes from there reach
+// exactly the subtrees of positions p + 1 .. last_leaf.  So each unordered
+// pair of values is met once, from its earlier position, and no walk touches
+// the part of the tree before its own leaf.  f(q, index, d2) gets the
+// partner's sorted position (a leaf in slot (node, side) sits at position
+// node + side), its value index and its distance.
+template <int D, class P, class F>
+__device__ __forceinline__ void traverse_pairs_after(const Node<D> *__restrict__ nodes, int n_nodes, int p,
+                                                     int last_leaf, const P &pred, F &f)
+{
+    if (p >= last_leaf)
+        return;
+    int cur = p, side = 1;
+    Node<D> nd;
+    int loaded = -1;
+    for (int iter = 0; iter <= 2 * n_nodes; ++iter) {
+        if ((unsigned)cur >= (unsigned)n_nodes)
+            break;
+        if (cur != loaded) {
+            load_node(nodes, cur, nd);
+            loaded = cur;
+        }
+        float lo[D], hi[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            lo[d] = side ? nd.lo[1][d] : nd.lo[0][d];
+            hi[d] = side ? nd.hi[1][d] : nd.hi[0][d];
+        }
+        const int c = side ? nd.child[1] : nd.child[0];
+        float d2;
+        if (c != kEmptyRef && pred.hit(lo, hi, d2)) {
+            if (c >= 0) {
+                cur = c;
+                side = 0;
+                continue;
+            }
+            f(cur + side, ~c, d2);
+        }
+        if (side == 0) {
+            side = 1;
+        } else {
+            if (nd.range_r >= last_leaf)
+                break;
+            cur = nd.range_r;
+        }
+    }
+}
+
 // Decode both child boxes of a quantized node in the tree's frame.
 template <int D>
 __device__ __forceinline__ void qboxes(const QNode<D> &nd, const float *flo, const float *fsc, float (&lo)[2][D],

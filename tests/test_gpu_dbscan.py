@@ -1,6 +1,8 @@
-"""DBSCAN on the index (core points by a fused COUNT, clusters by a lock-free
-union-find, border points to their smallest-index core neighbour) against the
-brute-force definition in the oracle, label for label."""
+"""Pair search (the self-join of a tree's points, each pair met once by a walk
+over the later leaves) and DBSCAN built on it (core points from the pair
+counts, clusters by a lock-free union-find, border points to their
+smallest-index core neighbour), against the brute-force definitions in the
+oracle, element by element."""
 import numpy as np
 import pytest
 
@@ -83,3 +85,63 @@ def test_rejects_box_trees():
     t = ax.arborx_bvh_build(dev(boxes), ax.BOXES)
     with pytest.raises(ValueError):
         ax.arborx_dbscan(t, dev(np.zeros((4, 3), dtype=np.float32)), 1.0, 2)
+
+
+def check_degree(pts, r):
+    bvh = ax.BVH(dev(pts))
+    got = ax.arborx_self_join_degree(bvh.tree, r).cpu().numpy()
+    want = oracle.self_join_degree(pts, r, dim=pts.shape[1])
+    assert np.array_equal(got, want), r
+    return got
+
+
+def test_self_join_hand_worked():
+    pts = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0], [10, 0, 0], [11, 0, 0], [20, 0, 0]], dtype=np.float32)
+    assert list(check_degree(pts, 1.5)) == [1, 2, 1, 1, 1, 0]
+    assert list(check_degree(pts, 1.0)) == [1, 2, 1, 1, 1, 0]
+    assert list(check_degree(pts, float(np.nextafter(np.float32(1), np.float32(0))))) == [0] * 6
+    assert list(check_degree(pts, float("inf"))) == [5] * 6
+
+
+@pytest.mark.parametrize("dim,r", [(2, 0.3), (3, 0.25), (3, 0.0), (3, 3.0), (6, 0.5)])
+def test_self_join_clustered(dim, r):
+    pts = clustered(7000, dim, 30 + dim)
+    pts[::89] = pts[1::89][: len(pts[::89])]  # exact duplicates pair at r = 0
+    deg = check_degree(pts, r)
+    assert deg.sum() % 2 == 0
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 64, 65, 1000])
+def test_self_join_small_trees(n):
+    g = np.random.default_rng(n)
+    pts = g.random((n, 3)).astype(np.float32)
+    pts[n // 2:] = pts[:n - n // 2]
+    if n == 0:
+        bvh = ax.BVH(dev(pts))
+        assert ax.arborx_self_join_degree(bvh.tree, 1.0).numel() == 0
+        return
+    for r in (0.0, 0.2, float("inf")):
+        check_degree(pts, r)
+
+
+def test_self_join_uniform_cube_matches_count():
+    g = np.random.default_rng(5)
+    pts = g.random((60_000, 3)).astype(np.float32)
+    r = 0.02
+    bvh = ax.BVH(dev(pts))
+    deg = ax.arborx_self_join_degree(bvh.tree, r)
+    c, _ = ax.arborx_query_spatial_reduce(bvh.tree, dev(pts), r, ax.COUNT)
+    assert torch.equal(deg + 1, c)  # a point's partners are its radius matches without itself
+    sample = g.choice(len(pts), 3000, replace=False)
+    want = oracle.spatial_count(pts, pts[sample], r) - 1
+    assert np.array_equal(deg.cpu().numpy()[sample], want)
+
+
+def test_self_join_rejects_boxes_and_bad_radius():
+    boxes = np.zeros((4, 2, 3), dtype=np.float32)
+    t = ax.arborx_bvh_build(dev(boxes), ax.BOXES)
+    with pytest.raises(ValueError):
+        ax.arborx_self_join_degree(t, 1.0)
+    p = ax.arborx_bvh_build(dev(np.zeros((4, 3), dtype=np.float32)))
+    with pytest.raises(ax.ArborXError):
+        ax.arborx_self_join_degree(p, float("nan"))

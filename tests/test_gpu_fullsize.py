@@ -89,7 +89,8 @@ def test_full_size_sampled_parity_and_properties(name):
     d2_t, ix_t = ax.arborx_query_knn(t, qd, k)
     u5_t = ax.arborx_query_spatial_count_up_to(t, qd, r, 5)
     db_t = ax.arborx_dbscan(t, d, r, 10) if dim == 3 else None
-    dbc_t = ax.arborx_query_spatial_reduce(t, d, r, ax.COUNT)[0] if dim == 3 else None
+    dbc_t = ax.arborx_query_spatial_reduce(t, d, r, ax.COUNT)[0]
+    sj_t = ax.arborx_self_join_degree(t, r)
     md_t = ax.arborx_query_match_distances(t, d, qd, off_t, idx_t)
     torch.cuda.synchronize()
     off, idx = off_t.cpu().numpy(), idx_t.cpu().numpy()
@@ -98,8 +99,9 @@ def test_full_size_sampled_parity_and_properties(name):
     u5 = u5_t.cpu().numpy()
     md = md_t.cpu().numpy()
     db = db_t.cpu().numpy() if db_t is not None else None
-    dbc = dbc_t.cpu().numpy() if dbc_t is not None else None
-    del db_t, dbc_t
+    dbc = dbc_t.cpu().numpy()
+    sj = sj_t.cpu().numpy()
+    del db_t, dbc_t, sj_t
     del off_t, idx_t, c_t, c2_t, s2_t, d2_t, ix_t, u5_t, md_t, t
 
     # every query: properties
@@ -127,6 +129,10 @@ def test_full_size_sampled_parity_and_properties(name):
     assert np.array_equal(u5[sel], oracle.count_up_to(data, sq, r, 5, dim=dim))
     if db is not None:
         check_dbscan(data, r, 10, db, dbc)
+    # pair search over the data points: each point's partners are its radius matches without itself
+    assert np.array_equal(sj + 1, dbc) and sj.sum() % 2 == 0
+    psel = np.sort(np.random.default_rng(2508).choice(n, SAMPLE, replace=False))
+    assert np.array_equal(sj[psel], oracle.spatial_count(data, np.ascontiguousarray(data[psel]), r, dim=dim) - 1)
     o_md = oracle.match_distances(data, sq, o_off, o_idx, dim=dim)
     for j, i in enumerate(sel):
         assert np.array_equal(md[off[i]:off[i + 1]], o_md[o_off[j]:o_off[j + 1]])
