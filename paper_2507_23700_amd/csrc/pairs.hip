@@ -1,26 +1,30 @@
 // Search for pairs of objects (Section 2.6: a dedicated traversal for it) and
 // density-based clustering on top of it (Section 2.4: DBSCAN on the index).
 //
-// The self-join of a tree's own points: thread p takes the leaf at sorted
-// position p (its coordinates and value index come from the leaf record, so
+// The self-join of a tree's own points: a thread takes consecutive leaves in
+// sorted order (coordinates and value indices come from the leaf records, so
 // the threads of a wavefront hold Morton neighbours without any query
-// ordering) and walks only the subtrees after its own leaf, so every
-// unordered pair within the radius is met exactly once.  Per-pair results go
-// to arrays indexed by sorted position: a pair's two positions are close in
-// Morton order most of the time, so the atomics of one wavefront land in a
-// few cache lines; a last pass moves them to input order.
+// ordering) and visits only the subtrees after its own leaves, so every
+// unordered pair within the radius is met exactly once.  Two walks give the
+// same pairs: a top-down packet walk over several leaves per thread (the
+// default) and the stackless walk from each leaf's own rope (schedule 2).
+// Pair counts go to an array indexed by sorted position: a pair's two
+// positions are close in Morton order most of the time, so the atomics of one
+// wavefront land in a few cache lines; a last pass moves them to input order.
 //
-// DBSCAN, three passes over the pairs, all in sorted-position space:
+// DBSCAN, two passes over the pairs:
 //   1. pair counts: a point is core when its pairs plus itself reach min_pts;
 //   2. one pair walk: core-core pairs are united in a lock-free union-find
-//      whose links always go from the larger root to the smaller, and each
+//      over value indices whose links always go from the larger root to the
+//      smaller, so each cluster's root ends as its smallest core index (over
+//      sorted positions instead, the lanes of a wavefront, Morton neighbours,
+//      contend for the same few roots: eight times slower at 10^7 points); each
 //      non-core point keeps the smallest index among its core partners
 //      (atomic minimum, from whichever side of the pair meets it);
-//   3. labels: a cluster takes the smallest value index among its core
-//      points, a non-core point the label of its smallest-index core partner,
-//      or -1 (noise).
-// Labelling by smallest indices makes the result unique, so it is compared
-// with a brute-force definition element by element.
+// then labels: a core point takes its root, a non-core point the label of its
+// smallest-index core partner, or -1 (noise).  Labelling by smallest indices
+// makes the result unique, so it is compared with a brute-force definition
+// element by element.
 #include "device_util.hpp"
 #include "geometry.hpp"
 #include "internal.hpp"
@@ -57,25 +61,52 @@ __device__ __forceinline__ int leaf_index(const float *__restrict__ leaves, int6
     return __float_as_int(leaves[p * leaf_floats(D, ARBORX_POINTS) + D]);
 }
 
-// Pass 1: deg[q] = partners of the point at sorted position q.
-template <int D>
-__global__ void k_pair_degree(const Node<D> *__restrict__ nodes, const float *__restrict__ leaves, int64_t n,
-                              float r2, int32_t *__restrict__ deg)
+// Pass 1: deg[q] = partners of the point at sorted position q.  NQ leaves per
+// thread over the packet walk, or (NQ = 0) one leaf per thread over its rope.
+template <int D, int NQ>
+__global__ void k_pair_degree(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+                              const float *__restrict__ leaves, int64_t n, float r2, int32_t *__restrict__ deg,
+                              int stack_cap)
 {
-    const int64_t p = xcd_block() * blockDim.x + threadIdx.x;
-    if (p >= n - 1)  // the last position has no later partner
+    extern __shared__ int s_stack[];
+    constexpr int W = NQ ? NQ : 1;
+    const int64_t p0 = (xcd_block() * blockDim.x + threadIdx.x) * W;
+    if (p0 >= n - 1)  // the last position has no later partner
         return;
-    Sphere<D> pred;
-    load_point_leaf<D>(leaves, p, pred.c);
-    pred.r2 = r2;
-    int c = 0;
-    auto f = [&](int q, int, float) {
-        ++c;
-        atomicAdd(deg + q, 1);
-    };
-    traverse_pairs_after<D>(nodes, (int)(n - 1), (int)p, (int)(n - 1), pred, f);
-    if (c)
-        atomicAdd(deg + p, c);
+    Sphere<D> pred[W];
+    int c[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        c[j] = 0;
+        if (p0 + j < n - 1) {
+            load_point_leaf<D>(leaves, p0 + j, pred[j].c);
+            pred[j].r2 = r2;
+        } else {
+            pred[j].dead();
+        }
+    }
+    if constexpr (NQ == 0) {
+        auto f = [&](int q, int, float) {
+            ++c[0];
+            atomicAdd(deg + q, 1);
+        };
+        traverse_pairs_after<D>(nodes, (int)(n - 1), (int)p0, (int)(n - 1), pred[0], f);
+    } else {
+        int spill[kSpill];
+        ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap, spill);
+        auto f = [&](int j, int q, int, float) {
+#pragma unroll
+            for (int jj = 0; jj < W; ++jj)
+                if (jj == j)
+                    ++c[jj];
+            atomicAdd(deg + q, 1);
+        };
+        traverse_pairs_packet<D, W>(nodes, hdr->root, (int)(n - 1), (int)p0, pred, st, f);
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+        if (c[j])
+            atomicAdd(deg + p0 + j, c[j]);
 }
 
 // out[index of the leaf at q] = by_pos[q].
@@ -90,12 +121,18 @@ __global__ void k_to_input_order(const int32_t *__restrict__ by_pos, const float
     }
 }
 
+// Parent links are read and shortened with workgroup-scope accesses, which
+// the per-XCD L2 serves, so another XCD's recent link may not be visible yet.
+// That is safe: links only ever go from a value to a smaller value of the same
+// component and are never undone, so a stale parent is still an ancestor, and
+// a stale root is caught by the exchange in unite, which is device-wide and
+// returns the true parent.
 __device__ __forceinline__ int32_t load_parent(const int32_t *parent, int32_t x)
 {
-    return __hip_atomic_load(parent + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(parent + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Root of x.  Every link points to a smaller position (unions link the larger
+// Root of x.  Every link points to a smaller index (unions link the larger
 // root to the smaller; shortcuts below point a node at a smaller member of its
 // own chain), so a chain strictly decreases and ends at a root.  The nodes
 // above the root found are then pointed at it: they are not roots (and never
@@ -113,20 +150,22 @@ __device__ __forceinline__ int32_t find_root(int32_t *parent, int32_t x)
     while (x > r) {
         const int32_t next = load_parent(parent, x);
         if (next != r)
-            __hip_atomic_store(parent + x, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(parent + x, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         x = next;
     }
     return r;
 }
 
-// Link the components of a and b: the larger root is pointed at the smaller.
-// A failed exchange means another thread linked that root meanwhile, which can
-// happen at most n - 1 times in all, so the bounded loop always finishes.
+// Link the components of a and b: the larger root is pointed at the smaller
+// by a device-wide exchange.  When it fails, the value it returns is that
+// root's true parent, smaller than it, and the walk goes on from there; so
+// every failure moves one of the two ends to a smaller index, and at most 2n
+// rounds finish.
 __device__ __forceinline__ void unite(int32_t *parent, int32_t a, int32_t b, int64_t n)
 {
-    for (int64_t iter = 0; iter <= n; ++iter) {
-        a = find_root(parent, a);
-        b = find_root(parent, b);
+    a = find_root(parent, a);
+    b = find_root(parent, b);
+    for (int64_t iter = 0; iter <= 2 * n + 1; ++iter) {
         if (a == b)
             return;
         if (a < b) {
@@ -134,75 +173,95 @@ __device__ __forceinline__ void unite(int32_t *parent, int32_t a, int32_t b, int
             a = b;
             b = t;
         }
-        if (atomicCAS(parent + a, a, b) == a)
+        const int32_t old = atomicCAS(parent + a, a, b);
+        if (old == a)
             return;
+        a = find_root(parent, old);
+        b = find_root(parent, b);
     }
 }
 
-__global__ void k_dbscan_init(int32_t *__restrict__ parent, int32_t *__restrict__ border,
-                              int32_t *__restrict__ cmin, int64_t n)
+__global__ void k_dbscan_init(int32_t *__restrict__ parent, int32_t *__restrict__ border, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         parent[i] = (int32_t)i;
         border[i] = INT32_MAX;
-        cmin[i] = INT32_MAX;
     }
 }
 
-// Pass 2: one pair walk per position.
-template <int D>
-__global__ void k_dbscan_pairs(const Node<D> *__restrict__ nodes, const float *__restrict__ leaves, int64_t n,
-                               float r2, int min_pts, const int32_t *__restrict__ deg, int32_t *__restrict__ parent,
-                               int32_t *__restrict__ border)
+// Pass 2: one pair walk, NQ leaves per thread (NQ = 0: the rope walk).
+// parent is indexed by value index, deg and border by sorted position.
+template <int D, int NQ>
+__global__ void k_dbscan_pairs(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+                               const float *__restrict__ leaves, int64_t n, float r2, int min_pts,
+                               const int32_t *__restrict__ deg, int32_t *__restrict__ parent,
+                               int32_t *__restrict__ border, int stack_cap)
 {
-    const int64_t p = xcd_block() * blockDim.x + threadIdx.x;
-    if (p >= n - 1)
+    extern __shared__ int s_stack[];
+    constexpr int W = NQ ? NQ : 1;
+    const int64_t p0 = (xcd_block() * blockDim.x + threadIdx.x) * W;
+    if (p0 >= n - 1)
         return;
-    Sphere<D> pred;
-    const int id = load_point_leaf<D>(leaves, p, pred.c);
-    pred.r2 = r2;
-    const bool core_p = deg[p] + 1 >= min_pts;
-    int best = INT32_MAX;
-    auto f = [&](int q, int qid, float) {
+    Sphere<D> pred[W];
+    int id[W], best[W];
+    bool core[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        best[j] = INT32_MAX;
+        core[j] = false;
+        id[j] = -1;
+        if (p0 + j < n - 1) {
+            id[j] = load_point_leaf<D>(leaves, p0 + j, pred[j].c);
+            pred[j].r2 = r2;
+            core[j] = deg[p0 + j] + 1 >= min_pts;
+        } else {
+            pred[j].dead();
+        }
+    }
+    auto pair = [&](int j, int q, int qid) {
         const bool core_q = deg[q] + 1 >= min_pts;
-        if (core_p && core_q)
-            unite(parent, (int32_t)p, q, n);
-        else if (core_p)
-            atomicMin(border + q, id);
-        else if (core_q)
-            best = qid < best ? qid : best;
+#pragma unroll
+        for (int jj = 0; jj < W; ++jj)
+            if (jj == j) {
+                if (core[jj] && core_q)
+                    unite(parent, id[jj], qid, n);
+                else if (core[jj])
+                    atomicMin(border + q, id[jj]);
+                else if (core_q)
+                    best[jj] = qid < best[jj] ? qid : best[jj];
+            }
     };
-    traverse_pairs_after<D>(nodes, (int)(n - 1), (int)p, (int)(n - 1), pred, f);
-    if (best != INT32_MAX)
-        atomicMin(border + p, best);
+    if constexpr (NQ == 0) {
+        auto f = [&](int q, int qid, float) { pair(0, q, qid); };
+        traverse_pairs_after<D>(nodes, (int)(n - 1), (int)p0, (int)(n - 1), pred[0], f);
+    } else {
+        int spill[kSpill];
+        ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap, spill);
+        auto f = [&](int j, int q, int qid, float) { pair(j, q, qid); };
+        traverse_pairs_packet<D, W>(nodes, hdr->root, (int)(n - 1), (int)p0, pred, st, f);
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+        if (best[j] != INT32_MAX)
+            atomicMin(border + p0 + j, best[j]);
 }
 
-// Pass 3a: the smallest value index of each cluster, kept at its root.
-template <int D>
-__global__ void k_dbscan_cluster_min(int32_t *__restrict__ parent, const int32_t *__restrict__ deg, int64_t n,
-                                     int min_pts, const float *__restrict__ leaves, int32_t *__restrict__ cmin)
-{
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
-        if (deg[q] + 1 >= min_pts)
-            atomicMin(cmin + find_root(parent, (int32_t)q), leaf_index<D>(leaves, q));
-}
-
-// Pass 3b: labels of core points.
+// Labels of core points: the root of their value index, the cluster's
+// smallest core index.
 template <int D>
 __global__ void k_dbscan_core_labels(int32_t *__restrict__ parent, const int32_t *__restrict__ deg, int64_t n,
-                                     int min_pts, const float *__restrict__ leaves,
-                                     const int32_t *__restrict__ cmin, int32_t *__restrict__ labels)
+                                     int min_pts, const float *__restrict__ leaves, int32_t *__restrict__ labels)
 {
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
         if (deg[q] + 1 >= min_pts) {
             const int id = leaf_index<D>(leaves, q);
             if (id >= 0 && id < n)
-                labels[id] = cmin[find_root(parent, (int32_t)q)];
+                labels[id] = find_root(parent, id);
         }
 }
 
-// Pass 3c: labels of the other points, from their smallest-index core
-// partner (labelled in pass 3b), else noise.
+// Labels of the other points, from their smallest-index core partner
+// (labelled by the previous pass), else noise.
 template <int D>
 __global__ void k_dbscan_border_labels(const int32_t *__restrict__ deg, const int32_t *__restrict__ border, int64_t n,
                                        int min_pts, const float *__restrict__ leaves, int32_t *__restrict__ labels)
@@ -216,7 +275,31 @@ __global__ void k_dbscan_border_labels(const int32_t *__restrict__ deg, const in
         }
 }
 
-constexpr int kPairBlock = 256;
+// Launch shape of the pair walks: the reductions' tuning (block, stack; the
+// rope walk for schedule 2), with NQ leaves per thread over the packet walk
+// (queries_per_thread, else 2 up to 3D and 1 in 6D: at 10^7 points in 3D, two
+// leaves per thread ran DBSCAN's pair pass fastest and the pair count as fast
+// as four).
+struct PairLaunch {
+    int nq, block, cap;
+    unsigned grid;
+    size_t lds;
+};
+
+PairLaunch pair_launch(int64_t n, int dim)
+{
+    const Tuning &tu = tuning(OP_REDUCE);
+    PairLaunch L;
+    L.nq = tu.schedule == 2 ? 0 : (tu.packet ? tu.packet : (dim <= 3 ? 2 : 1));
+    L.block = tu.block;
+    L.cap = tu.stack;
+    while (L.cap > 1 && (size_t)L.cap * L.block * sizeof(int) > 65536)
+        L.cap >>= 1;
+    L.lds = L.nq ? (size_t)L.cap * L.block * sizeof(int) : 0;
+    const int64_t per = L.nq ? L.nq : 1;
+    L.grid = grid_for((n - 1 + per - 1) / per, L.block, INT32_MAX);
+    return L;
+}
 
 template <int D>
 arborx_status degree_by_position(const TreeDev &t, float r2, int32_t *deg, hipStream_t s)
@@ -224,9 +307,19 @@ arborx_status degree_by_position(const TreeDev &t, float r2, int32_t *deg, hipSt
     const int64_t n = t.n;
     fill_kernel<int32_t><<<grid_for(n, 256, 65536), 256, 0, s>>>(deg, n, 0);
     if (n > 1) {
+        const PairLaunch L = pair_launch(n, D);
+        const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
         ProfScope ps("pair_degree", s);
-        k_pair_degree<D><<<grid_for(n - 1, kPairBlock, INT32_MAX), kPairBlock, 0, s>>>(
-            static_cast<const Node<D> *>(t.nodes), t.leaves, n, r2, deg);
+#define AX_PD(NQ) k_pair_degree<D, NQ><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, t.leaves, n, r2, deg, L.cap)
+        if (L.nq == 0)
+            AX_PD(0);
+        else if (L.nq == 1)
+            AX_PD(1);
+        else if (L.nq == 2)
+            AX_PD(2);
+        else
+            AX_PD(4);
+#undef AX_PD
     }
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
@@ -249,21 +342,32 @@ arborx_status dbscan_impl(const TreeDev &t, float eps, int min_pts, int32_t *lab
 {
     const int64_t n = t.n;
     const float r2 = eps * eps;
-    int32_t *deg, *parent, *border, *cmin;
+    int32_t *deg, *parent, *border;
     arborx_status st;
     if ((st = tmp.get(&deg, n)) != ARBORX_OK || (st = tmp.get(&parent, n)) != ARBORX_OK ||
-        (st = tmp.get(&border, n)) != ARBORX_OK || (st = tmp.get(&cmin, n)) != ARBORX_OK)
+        (st = tmp.get(&border, n)) != ARBORX_OK)
         return st;
     if ((st = degree_by_position<D>(t, r2, deg, s)) != ARBORX_OK)
         return st;
     ProfScope ps("dbscan", s);
     const unsigned g = grid_for(n, 256, 65536);
-    k_dbscan_init<<<g, 256, 0, s>>>(parent, border, cmin, n);
-    if (n > 1)
-        k_dbscan_pairs<D><<<grid_for(n - 1, kPairBlock, INT32_MAX), kPairBlock, 0, s>>>(
-            static_cast<const Node<D> *>(t.nodes), t.leaves, n, r2, min_pts, deg, parent, border);
-    k_dbscan_cluster_min<D><<<g, 256, 0, s>>>(parent, deg, n, min_pts, t.leaves, cmin);
-    k_dbscan_core_labels<D><<<g, 256, 0, s>>>(parent, deg, n, min_pts, t.leaves, cmin, labels);
+    k_dbscan_init<<<g, 256, 0, s>>>(parent, border, n);
+    if (n > 1) {
+        const PairLaunch L = pair_launch(n, D);
+        const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
+#define AX_DP(NQ) k_dbscan_pairs<D, NQ><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, t.leaves, n, r2, min_pts, deg, \
+                                                                       parent, border, L.cap)
+        if (L.nq == 0)
+            AX_DP(0);
+        else if (L.nq == 1)
+            AX_DP(1);
+        else if (L.nq == 2)
+            AX_DP(2);
+        else
+            AX_DP(4);
+#undef AX_DP
+    }
+    k_dbscan_core_labels<D><<<g, 256, 0, s>>>(parent, deg, n, min_pts, t.leaves, labels);
     k_dbscan_border_labels<D><<<g, 256, 0, s>>>(deg, border, n, min_pts, t.leaves, labels);
     AX_HIP(hipGetLastError());
     return ARBORX_OK;

@@ -422,6 +422,56 @@ __device__ __forceinline__ void traverse_pairs_after(const Node<D> *__restrict__
     }
 }
 
+// Top-down packet form of the pair-search walk: one thread takes the NQ
+// consecutive sorted positions p0 .. p0 + NQ - 1 of a single tree and walks
+// from the root over the union of their paths.  Node c separates leaves c and
+// c + 1, so its left child holds positions [range_l, c] and its right child
+// [c + 1, range_r]; query j enters a child only if the child's box admits it
+// and the child holds a position after p0 + j.  Each unordered pair is thus
+// reported once, to the query at its earlier position, as
+// f(j, partner position, partner index, d2); the walk over the shared upper
+// levels is paid once per NQ queries.  Queries past the tree carry a
+// predicate that matches nothing.
+template <int D, int NQ, class P, class F>
+__device__ __forceinline__ void traverse_pairs_packet(const Node<D> *__restrict__ nodes, int root, int n_nodes, int p0,
+                                                      const P (&pred)[NQ], ShortStack<int> &st, F &f)
+{
+    int cur = root;
+    for (int iter = 0; iter <= n_nodes; ++iter) {
+        if ((unsigned)cur >= (unsigned)n_nodes)
+            break;
+        Node<D> nd;
+        load_node(nodes, cur, nd);
+        const int c0 = nd.child[0], c1 = nd.child[1];
+        bool g0 = false, g1 = false;
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) {
+            float d0, d1;
+            const bool h0 = cur > p0 + j && pred[j].hit(nd.lo[0], nd.hi[0], d0);
+            const bool h1 = nd.range_r > p0 + j && pred[j].hit(nd.lo[1], nd.hi[1], d1);
+            if (h0 && c0 < 0 && c0 != kEmptyRef)
+                f(j, cur, ~c0, d0);
+            if (h1 && c1 < 0 && c1 != kEmptyRef)
+                f(j, cur + 1, ~c1, d1);
+            g0 = g0 | h0;
+            g1 = g1 | h1;
+        }
+        g0 = g0 && c0 >= 0;
+        g1 = g1 && c1 >= 0;
+        if (g0) {
+            if (g1)
+                st.push(c1);
+            cur = c0;
+        } else if (g1) {
+            cur = c1;
+        } else {
+            if (st.empty())
+                break;
+            cur = st.pop();
+        }
+    }
+}
+
 // Decode both child boxes of a quantized node in the tree's frame.
 template <int D>
 __device__ __forceinline__ void qboxes(const QNode<D> &nd, const float *flo, const float *fsc, float (&lo)[2][D],

@@ -145,3 +145,17 @@ def test_self_join_rejects_boxes_and_bad_radius():
     p = ax.arborx_bvh_build(dev(np.zeros((4, 3), dtype=np.float32)))
     with pytest.raises(ax.ArborXError):
         ax.arborx_self_join_degree(p, float("nan"))
+
+
+@pytest.mark.parametrize("tuning", [dict(schedule=2), dict(queries_per_thread=1), dict(queries_per_thread=2),
+                                    dict(queries_per_thread=4), dict(block=64, stack=1)])
+def test_pair_walk_forms_identical(tuning):
+    pts = clustered(9000, 3, 61)
+    pts[::53] = pts[1::53][: len(pts[::53])]
+    ax.arborx_set_tuning(**tuning)
+    check_degree(pts, 0.2)
+    check(pts, 0.2, 6)
+    check(pts, 0.35, 1)
+    p6 = clustered(4000, 6, 62)
+    check_degree(p6, 0.6)
+    check(p6, 0.6, 5)
