@@ -11,8 +11,10 @@ Prints ONE JSON line on stdout (progress goes to stderr):
                (4 query passes of M queries per step);
   components = per-phase rates from events recorded on the launch stream, and,
                timed after the steps and outside them, the early-terminating
-               count, per-match distances, DBSCAN on the step's tree, and rays
-               against a tree of 2*10^6 boxes;
+               count, the radius search with per-match distances (callback
+               with output), DBSCAN and the pair search on the step's tree,
+               standalone reduce and kNN calls that order their queries, and
+               rays against a tree of 2*10^6 boxes;
   roofline   = the dominant kernel's algorithmic bytes / its average duration
                against MI355X HBM peak (8 TB/s), with the measured HBM traffic
                while profiles/traffic.json matches the kernel sources, and the
@@ -486,7 +488,11 @@ def main():
     for n_max in (1, 5):
         ms = timed(lambda: ax.arborx_query_spatial_count_up_to(tree, q, radius, n_max), 5)
         comps[f"count_up_to{n_max}_qps"] = m / ms * 1e3
-    # the callback-with-output form: squared distance of each match of the step's CSR result
+    # the callback-with-output form: one radius search whose walk writes each match's squared distance
+    # beside its index (compare spatial_csr_qps, the same search without the output), and the gather
+    # of the same distances over the step's finished CSR result
+    ms = timed(lambda: ax.arborx_query_spatial_with_distances(tree, q, radius), 5)
+    comps["spatial_with_distances_qps"] = m / ms * 1e3
     ms = timed(lambda: ax.arborx_query_match_distances(tree, d, q, state["off"], state["idx"]), 5)
     comps["match_distances_per_s"] = total / ms * 1e3
     # rays against 2*10^6 small random boxes: hit counts and the first hit of 10^6 rays

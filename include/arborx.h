@@ -283,9 +283,35 @@ arborx_status arborx_query_spatial_count_up_to(arborx_tree tree, const float *qu
                                                int32_t n_max, int32_t *counts, void *stream);
 
 /*
- * Callback with output (Section 2.1, query call (2), e.g. returning each
- * match's distance): the float32 squared distance of every match of a radius
- * search's CSR result, evaluated exactly as in the search.
+ * Callback with output (Section 2.1, query call (2); Section 2.2): a radius
+ * search whose callback emits one output per match, here the match's float32
+ * squared distance as the walk computed it, stored in CSR form beside the
+ * indices.  The walk keeps each distance with its index (in the register
+ * stash, the overflow chunks, and a second walk for rows that need one), and
+ * the row sorts move it along, so no pass after the search reads the values
+ * again.  Same arguments, protocol and results as arborx_query_spatial, plus
+ *   distances [capacity] float32 output: distances[p] is the squared distance
+ *             between query i and value indices[p], for p in row i
+ * If indices or distances is NULL, or capacity < total, offsets and *total are
+ * filled and ARBORX_E_CAPACITY is returned.  Temporary device memory twice
+ * that of arborx_query_spatial.  Synchronises `stream` (to read the total).
+ * The plan form: arborx_query_spatial_with_distances_begin, then
+ * arborx_query_finish_with_distances (distances must not be NULL when the
+ * total is not 0; arborx_query_finish on such a plan writes indices only).
+ */
+arborx_status arborx_query_spatial_with_distances(arborx_tree tree, const float *queries, int64_t m, float radius,
+                                                  int64_t *offsets, int32_t *indices, float *distances,
+                                                  int64_t capacity, int64_t *total, void *stream);
+arborx_status arborx_query_spatial_with_distances_begin(arborx_tree tree, const float *queries, int64_t m, float radius,
+                                                        int64_t *offsets, int64_t *total, arborx_plan *plan,
+                                                        void *stream);
+arborx_status arborx_query_finish_with_distances(arborx_plan plan, int32_t *indices, float *distances,
+                                                 int64_t capacity);
+
+/*
+ * The same per-match output computed after a search instead: the float32
+ * squared distance of every match of any radius CSR result (for example one
+ * produced earlier by arborx_query_spatial), evaluated exactly as in the search.
  *   values    the array the tree was built from (unchanged since the build)
  *   queries   [m][dim] the radius query's points;  offsets [m+1], indices [total] its result
  *   distances [total] float32 output aligned with indices (NaN for an index outside the tree)

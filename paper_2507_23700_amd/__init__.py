@@ -298,10 +298,25 @@ def arborx_query_match_distances(tree: Tree, values, queries, offsets, indices, 
     return out
 
 
-def arborx_query_spatial_with_distances(tree: Tree, values, queries, radius: float, stream=None):
-    """Radius search returning (offsets, indices, squared distances) in CSR form."""
-    off, idx = arborx_query_spatial(tree, queries, radius, stream=stream)
-    return off, idx, arborx_query_match_distances(tree, values, queries, off, idx, stream=stream)
+def arborx_query_spatial_with_distances(tree: Tree, queries, radius: float, stream=None):
+    """Callback with output: radius search returning (offsets, indices, squared distances) in CSR
+    form, each distance written by the search's own walk beside its index."""
+    torch = _torch()
+    q = _queries(tree, queries, False)
+    m = q.shape[0]
+    offsets = torch.empty(m + 1, dtype=torch.int64, device=q.device)
+    total = ctypes.c_int64()
+    plan = ctypes.c_void_p()
+    L = _lib.lib()
+    _check(L.arborx_query_spatial_with_distances_begin(tree.handle, _ptr(q), m, ctypes.c_float(radius), _ptr(offsets),
+                                                       ctypes.byref(total), ctypes.byref(plan), _stream(stream)))
+    try:
+        indices = torch.empty(max(total.value, 1), dtype=torch.int32, device=q.device)
+        dist = torch.empty(max(total.value, 1), dtype=torch.float32, device=q.device)
+        _check(L.arborx_query_finish_with_distances(plan, _ptr(indices), _ptr(dist), indices.numel()))
+    finally:
+        L.arborx_plan_destroy(plan)
+    return offsets, indices[:total.value], dist[:total.value]
 
 
 def arborx_query_ray_count(tree: Tree, rays, stream=None):
@@ -604,7 +619,7 @@ class BVH:
         return arborx_query_spatial_reduce(self.tree, queries, radius, COUNT, **kw)[0]
 
     def spatial_with_distances(self, queries, radius, **kw):
-        return arborx_query_spatial_with_distances(self.tree, self.values, queries, radius, **kw)
+        return arborx_query_spatial_with_distances(self.tree, queries, radius, **kw)
 
     def ray_count(self, rays, **kw):
         return arborx_query_ray_count(self.tree, rays, **kw)

@@ -45,6 +45,9 @@ SIGNATURES = {
     "arborx_query_spatial_begin": (I32, [P, P, I64, F32, P, P, P, P]),
     "arborx_query_intersects_begin": (I32, [P, P, I64, P, P, P, P]),
     "arborx_query_finish": (I32, [P, P, I64]),
+    "arborx_query_spatial_with_distances": (I32, [P, P, I64, F32, P, P, P, I64, P, P]),
+    "arborx_query_spatial_with_distances_begin": (I32, [P, P, I64, F32, P, P, P, P]),
+    "arborx_query_finish_with_distances": (I32, [P, P, P, I64]),
     "arborx_plan_destroy": (I32, [P]),
     "arborx_forest_build": (I32, [P, P, I32, I32, I32, P, P]),
     "arborx_forest_destroy": (I32, [P]),

@@ -107,6 +107,7 @@ struct arborx_plan_s {
     ax::Temps tmp;
     uint32_t *perm = nullptr;
     int32_t *counts = nullptr, *ordered_counts = nullptr, *stash = nullptr, *big_list = nullptr, *huge_list = nullptr;
+    float *stash_d2 = nullptr;  // with distances (the callback-with-output form)
     ax::OverflowPool ovf{};
     ax::QueryHeader h{};
     arborx_plan_s(hipStream_t s) : tmp(s) {}
@@ -622,7 +623,8 @@ arborx_status arborx_bvh_info(arborx_tree t, int64_t *n, int32_t *dim, int32_t *
 }
 
 static arborx_status csr_begin(arborx_tree t, Pred pred, const float *queries, int64_t m, float radius,
-                               int64_t *offsets, int64_t *total, arborx_plan *out, void *stream)
+                               int64_t *offsets, int64_t *total, arborx_plan *out, void *stream,
+                               bool with_dist = false)
 {
     arborx_status st = check_tree(t);
     if (st != ARBORX_OK)
@@ -671,11 +673,15 @@ static arborx_status csr_begin(arborx_tree t, Pred pred, const float *queries, i
         (st = p->tmp.get(&p->big_list, mm)) != ARBORX_OK || (st = p->tmp.get(&p->huge_list, mm)) != ARBORX_OK ||
         (st = p->tmp.get(&sws, scan_workspace_bytes(m))) != ARBORX_OK)
         return bail(st);
+    p->ovf.dpool = nullptr;
+    if (with_dist && ((st = p->tmp.get(&p->stash_d2, mm * stash_regs(t->dev.dim))) != ARBORX_OK ||
+                      (st = p->tmp.get(&p->ovf.dpool, overflow_pool_ints(mm, t->dev.dim))) != ARBORX_OK))
+        return bail(st);
     if ((st = tree_order(t, queries, m, pred, OP_SPATIAL, &p->perm, p->tmp, s)) != ARBORX_OK)
         return bail(st);
     p->ovf.per = (int32_t)(overflow_pool_ints(mm, t->dev.dim) / kOvfPools);
-    if ((st = spatial_count(t->dev, pred, queries, m, radius, p->perm, p->counts, p->ordered_counts, p->stash, p->ovf,
-                            s)) != ARBORX_OK)
+    if ((st = spatial_count(t->dev, pred, queries, m, radius, p->perm, p->counts, p->ordered_counts, p->stash,
+                            p->stash_d2, p->ovf, s)) != ARBORX_OK)
         return bail(st);
     {
         ProfScope ps("scan", s);
@@ -696,39 +702,43 @@ static arborx_status csr_begin(arborx_tree t, Pred pred, const float *queries, i
     return ARBORX_OK;
 }
 
-static arborx_status csr_finish(arborx_plan p, int32_t *indices, int64_t capacity)
+static arborx_status csr_finish(arborx_plan p, int32_t *indices, int64_t capacity, float *dist = nullptr)
 {
     if (!p)
         return fail(ARBORX_E_INVALID, "plan is NULL");
     if (capacity < 0)
         return fail(ARBORX_E_INVALID, "capacity must be >= 0");
+    if (dist && !p->stash_d2)
+        return fail(ARBORX_E_INVALID, "distances asked of a plan begun without them");
     if (!indices || capacity < (int64_t)p->h.total)
         return fail(ARBORX_E_CAPACITY, "indices capacity " + std::to_string(capacity) + " < total " +
                                            std::to_string((long long)p->h.total));
     if (p->h.total == 0)
         return ARBORX_OK;
     NoteUse note_use{p->tree->uses, p->stream};
-    arborx_status st = spatial_fill(p->tree->dev, p->pred, p->queries, p->m, p->radius, p->counts, p->stash, p->ovf,
-                                    p->offsets, p->big_list, (int64_t)p->h.big_rows, p->huge_list,
-                                    (int64_t)p->h.huge_rows, indices, p->stream);
+    arborx_status st = spatial_fill(p->tree->dev, p->pred, p->queries, p->m, p->radius, p->counts, p->stash,
+                                    p->stash_d2, p->ovf, p->offsets, p->big_list, (int64_t)p->h.big_rows,
+                                    p->huge_list, (int64_t)p->h.huge_rows, indices, dist, p->stream);
     if (st != ARBORX_OK)
         return st;
-    if ((st = sort_big_rows(p->offsets, indices, p->big_list, (int64_t)p->h.big_rows, p->stream)) != ARBORX_OK)
+    if ((st = sort_big_rows(p->offsets, indices, dist, p->big_list, (int64_t)p->h.big_rows, p->stream)) != ARBORX_OK)
         return st;
-    return sort_huge_rows(p->tree->dev.n, p->offsets, indices, p->huge_list, (int64_t)p->h.huge_rows, p->tmp,
+    return sort_huge_rows(p->tree->dev.n, p->offsets, indices, dist, p->huge_list, (int64_t)p->h.huge_rows, p->tmp,
                           p->stream);
 }
 
 static arborx_status csr_query(arborx_tree t, Pred pred, const float *queries, int64_t m, float radius,
-                               int64_t *offsets, int32_t *indices, int64_t capacity, int64_t *total, void *stream)
+                               int64_t *offsets, int32_t *indices, int64_t capacity, int64_t *total, void *stream,
+                               bool with_dist = false, float *dist = nullptr)
 {
     if (capacity < 0)
         return fail(ARBORX_E_INVALID, "capacity must be >= 0");
     arborx_plan p = nullptr;
-    arborx_status st = csr_begin(t, pred, queries, m, radius, offsets, total, &p, stream);
+    arborx_status st = csr_begin(t, pred, queries, m, radius, offsets, total, &p, stream, with_dist);
     if (st != ARBORX_OK)
         return st;
-    st = csr_finish(p, indices, capacity);
+    st = (with_dist && p->h.total > 0 && !dist) ? fail(ARBORX_E_CAPACITY, "distances is NULL")
+                                                 : csr_finish(p, indices, capacity, p->h.total > 0 ? dist : nullptr);
     std::string msg = g_error;
     delete p;
     set_error(msg);
@@ -750,6 +760,31 @@ arborx_status arborx_query_intersects_begin(arborx_tree t, const float *qboxes, 
 arborx_status arborx_query_finish(arborx_plan plan, int32_t *indices, int64_t capacity)
 {
     return csr_finish(plan, indices, capacity);
+}
+
+arborx_status arborx_query_spatial_with_distances_begin(arborx_tree t, const float *queries, int64_t m, float radius,
+                                                        int64_t *offsets, int64_t *total, arborx_plan *plan,
+                                                        void *stream)
+{
+    return csr_begin(t, Pred::Sphere, queries, m, radius, offsets, total, plan, stream, true);
+}
+
+arborx_status arborx_query_finish_with_distances(arborx_plan plan, int32_t *indices, float *distances,
+                                                 int64_t capacity)
+{
+    if (plan && plan->h.total > 0 && !distances)
+        return fail(ARBORX_E_INVALID, "distances is NULL");
+    if (plan && plan->h.total == 0)
+        return csr_finish(plan, indices, capacity);
+    return csr_finish(plan, indices, capacity, distances);
+}
+
+arborx_status arborx_query_spatial_with_distances(arborx_tree t, const float *queries, int64_t m, float radius,
+                                                  int64_t *offsets, int32_t *indices, float *distances,
+                                                  int64_t capacity, int64_t *total, void *stream)
+{
+    return csr_query(t, Pred::Sphere, queries, m, radius, offsets, indices, capacity, total, stream, true,
+                     distances);
 }
 
 arborx_status arborx_plan_destroy(arborx_plan plan)

@@ -204,6 +204,7 @@ constexpr int kOvfPools = 256;
 struct OverflowPool {
     int32_t *head;                 // [m] first chunk of each row longer than the stash; -2: walk it again
     int32_t *pool;                 // kOvfPools sub-pools of `per` ints each
+    float *dpool;                  // NULL, or the match distances, slot for slot beside pool
     unsigned long long *ctr;       // kOvfPools counters, one per 64 bytes (stride 8), zero before the walk
     int32_t per;                   // ints per sub-pool, a multiple of kChunk
 };
@@ -213,20 +214,23 @@ int64_t overflow_pool_ints(int64_t m, int dim);
 // Count pass; also stores each query's first stash_regs(dim) matches in
 // stash[query][stash_regs(dim)], further matches in ovf, and (with perm)
 // ordered_counts[t] = counts[perm[t]].
+// With stash_d2 (and ovf.dpool), each match's squared distance is kept beside
+// its index: stash_d2[query][stash_regs(dim)] and the parallel pool.
 arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
                             const uint32_t *perm, int32_t *counts, int32_t *ordered_counts, int32_t *stash,
-                            const OverflowPool &ovf, hipStream_t s);
+                            float *stash_d2, const OverflowPool &ovf, hipStream_t s);
 // Fill pass: stash rows are copied, listed longer rows are copied from the
 // stash and their overflow chunks, and the rest (huge rows, rows whose chunks
 // did not fit) are walked again.
 arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
-                           const int32_t *counts, const int32_t *stash, const OverflowPool &ovf,
-                           const int64_t *offsets, const int32_t *big_list, int64_t nbig, const int32_t *huge_list,
-                           int64_t nhuge, int32_t *indices, hipStream_t s);
-arborx_status sort_big_rows(const int64_t *offsets, int32_t *indices, const int32_t *big_list, int64_t nbig,
-                            hipStream_t s);
-arborx_status sort_huge_rows(int64_t n_values, const int64_t *offsets, int32_t *indices, const int32_t *huge_list,
-                             int64_t h, Temps &tmp, hipStream_t s);
+                           const int32_t *counts, const int32_t *stash, const float *stash_d2,
+                           const OverflowPool &ovf, const int64_t *offsets, const int32_t *big_list, int64_t nbig,
+                           const int32_t *huge_list, int64_t nhuge, int32_t *indices, float *dist, hipStream_t s);
+// Row sorts; with dist, each distance moves with its index.
+arborx_status sort_big_rows(const int64_t *offsets, int32_t *indices, float *dist, const int32_t *big_list,
+                            int64_t nbig, hipStream_t s);
+arborx_status sort_huge_rows(int64_t n_values, const int64_t *offsets, int32_t *indices, float *dist,
+                             const int32_t *huge_list, int64_t h, Temps &tmp, hipStream_t s);
 arborx_status spatial_reduce(const TreeDev &t, const float *queries, int64_t m, float radius, int op,
                              int scale_bits, const uint32_t *perm, int32_t *counts, int64_t *sums, hipStream_t s);
 // out[p] = squared distance of match p (CSR row i = query i) from the build input.

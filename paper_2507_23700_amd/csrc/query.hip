@@ -32,8 +32,9 @@ __device__ __forceinline__ int node_count(const TreeHeader *hdr) { return hdr->n
 // register per query; -2 once the row is given up).  Chunks come from the
 // sub-pool of this workgroup as the row grows; the first one is recorded as
 // the row's head, each later one in the last slot of its predecessor.
-template <int R>
-__device__ __forceinline__ void overflow_add(const OverflowPool &o, int64_t qi, int c, int idx, int32_t &cur)
+template <int R, bool OUT>
+__device__ __forceinline__ void overflow_add(const OverflowPool &o, int64_t qi, int c, int idx, float d2,
+                                             int32_t &cur)
 {
     if (cur == -2)
         return;
@@ -60,6 +61,8 @@ __device__ __forceinline__ void overflow_add(const OverflowPool &o, int64_t qi, 
         cur = next;
     }
     o.pool[cur + pos] = idx;
+    if (OUT)
+        o.dpool[cur + pos] = d2;  // the callback's output, in the parallel pool
 }
 
 // Count pass of a CSR query.  With a stash, each query also keeps its first
@@ -67,15 +70,17 @@ __device__ __forceinline__ void overflow_add(const OverflowPool &o, int64_t qi, 
 // the stash row of its input position (one aligned 64-byte segment per
 // thread), so that the copy into the CSR array later streams rows, counts and
 // offsets in input order and sorts each row there; rows that fit need no
-// second walk.
-template <int D, class P, bool STASH, int SCHED>
+// second walk.  With OUT (the callback-with-output form), each match's
+// squared distance, as the walk computed it, travels beside its index in a
+// parallel register row, stash row and overflow pool.
+template <int D, class P, bool STASH, int SCHED, bool OUT = false>
 __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
                                 const Node4<D> *__restrict__ wnodes,
                                 const float *__restrict__ leaves, int kind, const TreeHeader *__restrict__ hdr,
                                 const float *__restrict__ queries, int64_t m, float r2,
                                 const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
                                 int32_t *__restrict__ ordered_counts, int32_t *__restrict__ stash,
-                                OverflowPool ovf, int stack_cap)
+                                float *__restrict__ stash_d2, OverflowPool ovf, int stack_cap)
 {
     extern __shared__ int s_stack[];
     const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
@@ -96,16 +101,23 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D
     constexpr int R = stash_regs(D);
     int c = 0;
     int buf[R];
+    float dbuf[OUT ? R : 1];
 #pragma unroll
     for (int k = 0; k < R; ++k)
         buf[k] = 0;
+#pragma unroll
+    for (int k = 0; k < (OUT ? R : 1); ++k)
+        dbuf[k] = 0.0f;
     int32_t ov = -1;
-    auto f = [&](int idx, float) {
+    auto f = [&](int idx, float d2) {
         if (STASH) {
-            if (c < R)
+            if (c < R) {
                 append_at<R>(buf, c, idx);
-            else
-                overflow_add<R>(ovf, qi, c, idx, ov);
+                if constexpr (OUT)
+                    append_at<R>(dbuf, c, d2);
+            } else {
+                overflow_add<R, OUT>(ovf, qi, c, idx, d2, ov);
+            }
         }
         ++c;
     };
@@ -126,6 +138,12 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D
 #pragma unroll
         for (int k = 0; k < R / 4; ++k)
             row[k] = make_int4(buf[4 * k], buf[4 * k + 1], buf[4 * k + 2], buf[4 * k + 3]);
+        if constexpr (OUT) {
+            float4 *drow = reinterpret_cast<float4 *>(stash_d2 + qi * R);
+#pragma unroll
+            for (int k = 0; k < R / 4; ++k)
+                drow[k] = make_float4(dbuf[4 * k], dbuf[4 * k + 1], dbuf[4 * k + 2], dbuf[4 * k + 3]);
+        }
     }
     counts[qi] = c;
     if (ordered_counts)
@@ -135,12 +153,12 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D
 // Packet form of the CSR count walk (sphere queries, binary nodes): thread t
 // answers the NQ queries at sorted positions NQ*t .. NQ*t + NQ - 1 in one walk,
 // each with its own register stash row.
-template <int D, int NQ>
-__global__ __attribute__((amdgpu_waves_per_eu(NQ == 2 && D <= 3 ? 6 : 1))) void k_spatial_count_packet(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
-                                       const float *__restrict__ queries, int64_t m, float r2,
-                                       const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
-                                       int32_t *__restrict__ ordered_counts, int32_t *__restrict__ stash,
-                                       OverflowPool ovf, int stack_cap)
+template <int D, int NQ, bool OUT = false>
+__global__ __attribute__((amdgpu_waves_per_eu(NQ == 2 && D <= 3 && !OUT ? 6 : 1))) void k_spatial_count_packet(
+    const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr, const float *__restrict__ queries,
+    int64_t m, float r2, const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
+    int32_t *__restrict__ ordered_counts, int32_t *__restrict__ stash, float *__restrict__ stash_d2,
+    OverflowPool ovf, int stack_cap)
 {
     extern __shared__ int s_stack[];
     constexpr int R = stash_regs(D);
@@ -162,25 +180,32 @@ __global__ __attribute__((amdgpu_waves_per_eu(NQ == 2 && D <= 3 ? 6 : 1))) void 
     ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap, spill);
     int c[NQ];
     int buf[NQ][R];
+    float dbuf[NQ][OUT ? R : 1];
 #pragma unroll
     for (int j = 0; j < NQ; ++j) {
         c[j] = 0;
 #pragma unroll
         for (int k = 0; k < R; ++k)
             buf[j][k] = 0;
+#pragma unroll
+        for (int k = 0; k < (OUT ? R : 1); ++k)
+            dbuf[j][k] = 0.0f;
     }
     int32_t ov[NQ];
 #pragma unroll
     for (int j = 0; j < NQ; ++j)
         ov[j] = -1;
-    auto f = [&](int j, int idx, float) {
+    auto f = [&](int j, int idx, float d2) {
 #pragma unroll
         for (int jj = 0; jj < NQ; ++jj)
             if (jj == j) {
-                if (c[jj] < R)
+                if (c[jj] < R) {
                     append_at<R>(buf[jj], c[jj], idx);
-                else
-                    overflow_add<R>(ovf, qi[jj], c[jj], idx, ov[jj]);
+                    if constexpr (OUT)
+                        append_at<R>(dbuf[jj], c[jj], d2);
+                } else {
+                    overflow_add<R, OUT>(ovf, qi[jj], c[jj], idx, d2, ov[jj]);
+                }
                 ++c[jj];
             }
     };
@@ -192,18 +217,34 @@ __global__ __attribute__((amdgpu_waves_per_eu(NQ == 2 && D <= 3 ? 6 : 1))) void 
 #pragma unroll
             for (int k = 0; k < R / 4; ++k)
                 row[k] = make_int4(buf[j][4 * k], buf[j][4 * k + 1], buf[j][4 * k + 2], buf[j][4 * k + 3]);
+            if constexpr (OUT) {
+                float4 *drow = reinterpret_cast<float4 *>(stash_d2 + qi[j] * R);
+#pragma unroll
+                for (int k = 0; k < R / 4; ++k)
+                    drow[k] = make_float4(dbuf[j][4 * k], dbuf[j][4 * k + 1], dbuf[j][4 * k + 2], dbuf[j][4 * k + 3]);
+            }
             counts[qi[j]] = c[j];
             if (ordered_counts)
                 ordered_counts[t * NQ + j] = c[j];
         }
 }
 
+// An index and its float32 squared distance (>= 0) as one word that orders
+// like the index: rows sort by index and the distance travels along.
+__device__ __forceinline__ uint64_t pack_match(int idx, float d2)
+{
+    return ((uint64_t)(uint32_t)idx << 32) | __float_as_uint(d2);
+}
+
 // Rows of at most R matches: sort the stash row in registers (a bitonic
 // network, empty slots padded to sort last) and copy it to the CSR slot.
-// Thread i handles query i, so consecutive lanes fill adjacent rows.
-template <int R>
-__global__ void k_copy_stash(const int32_t *__restrict__ stash, int64_t m, const int32_t *__restrict__ counts,
-                             const int64_t *__restrict__ offsets, int32_t *__restrict__ indices)
+// Thread i handles query i, so consecutive lanes fill adjacent rows.  With
+// dist, the stashed distances are sorted along with the indices (packed with
+// them into one word) and copied to the same slots of dist.
+template <int R, bool OUT>
+__global__ void k_copy_stash(const int32_t *__restrict__ stash, const float *__restrict__ stash_d2, int64_t m,
+                             const int32_t *__restrict__ counts, const int64_t *__restrict__ offsets,
+                             int32_t *__restrict__ indices, float *__restrict__ dist)
 {
     const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (qi >= m)
@@ -222,25 +263,49 @@ __global__ void k_copy_stash(const int32_t *__restrict__ stash, int64_t m, const
         v[4 * k + 2] = x.z;
         v[4 * k + 3] = x.w;
     }
+    if constexpr (OUT) {
+        const float4 *drow = reinterpret_cast<const float4 *>(stash_d2 + qi * R);
+        uint64_t w[R];
 #pragma unroll
-    for (int k = 0; k < R; ++k)
-        v[k] = k < c ? v[k] : INT32_MAX;
-    sort_network<R>(v);
+        for (int k = 0; k < R / 4; ++k) {
+            const float4 x = drow[k];
+            w[4 * k] = pack_match(v[4 * k], x.x);
+            w[4 * k + 1] = pack_match(v[4 * k + 1], x.y);
+            w[4 * k + 2] = pack_match(v[4 * k + 2], x.z);
+            w[4 * k + 3] = pack_match(v[4 * k + 3], x.w);
+        }
 #pragma unroll
-    for (int k = 0; k < R; ++k)
-        if (k < c)
-            indices[o + k] = v[k];
+        for (int k = 0; k < R; ++k)
+            w[k] = k < c ? w[k] : ~0ull;
+        sort_network<R>(w);
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (k < c) {
+                indices[o + k] = (int32_t)(w[k] >> 32);
+                dist[o + k] = __uint_as_float((uint32_t)w[k]);
+            }
+    } else {
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            v[k] = k < c ? v[k] : INT32_MAX;
+        sort_network<R>(v);
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (k < c)
+                indices[o + k] = v[k];
+    }
 }
 
 // Listed rows (longer than the stash, at most kRowSortBlock) whose overflow
 // chunks all fit: one wavefront per row copies the stash row, then the chunks
 // in chain order, into the row's CSR slot, in the order found; the rows are
 // sorted afterwards like walked ones.
-__global__ __launch_bounds__(256) void k_copy_overflow(const int32_t *__restrict__ stash, int R, OverflowPool ovf,
+__global__ __launch_bounds__(256) void k_copy_overflow(const int32_t *__restrict__ stash,
+                                                       const float *__restrict__ stash_d2, int R, OverflowPool ovf,
                                                        const int32_t *__restrict__ counts,
                                                        const int64_t *__restrict__ offsets,
                                                        const int32_t *__restrict__ list, int64_t nb,
-                                                       int32_t *__restrict__ indices)
+                                                       int32_t *__restrict__ indices, float *__restrict__ dist)
 {
     const int lane = lane_id();
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
@@ -253,12 +318,18 @@ __global__ __launch_bounds__(256) void k_copy_overflow(const int32_t *__restrict
         if (cur < 0)
             continue;
         const int64_t o = offsets[row];
-        if (lane < R)
+        if (lane < R) {
             indices[o + lane] = stash[row * R + lane];
+            if (dist)
+                dist[o + lane] = stash_d2[row * R + lane];
+        }
         for (int done = R; done < c; done += kChunk - 1) {
             const int n = c - done < kChunk - 1 ? c - done : kChunk - 1;
-            if (lane < n)
+            if (lane < n) {
                 indices[o + done + lane] = ovf.pool[cur + lane];
+                if (dist)
+                    dist[o + done + lane] = ovf.dpool[cur + lane];
+            }
             if (done + n < c)
                 cur = ovf.pool[cur + kChunk - 1];
         }
@@ -273,7 +344,8 @@ __global__ void k_spatial_fill_rows(const Node<D> *__restrict__ nodes, const QNo
                                     const float *__restrict__ leaves, int kind, const TreeHeader *__restrict__ hdr,
                                     const float *__restrict__ queries, int64_t m, float r2,
                                     const int32_t *__restrict__ rows, int64_t nrows, const int32_t *__restrict__ head,
-                                    const int64_t *__restrict__ offsets, int32_t *__restrict__ indices, int stack_cap)
+                                    const int64_t *__restrict__ offsets, int32_t *__restrict__ indices,
+                                    float *__restrict__ dist, int stack_cap)
 {
     extern __shared__ int s_stack[];
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -291,9 +363,12 @@ __global__ void k_spatial_fill_rows(const Node<D> *__restrict__ nodes, const QNo
     const int64_t o = offsets[qi];
     const int64_t len = offsets[qi + 1] - o;
     int64_t k = 0;
-    auto f = [&](int idx, float) {
-        if (k < len)
+    auto f = [&](int idx, float d2) {
+        if (k < len) {
             indices[o + k] = idx;
+            if (dist)
+                dist[o + k] = d2;
+        }
         ++k;
     };
     if (FMT == 1)
@@ -306,8 +381,10 @@ __global__ void k_spatial_fill_rows(const Node<D> *__restrict__ nodes, const QNo
 
 // Listed rows of at most one wavefront (kWave entries): one wavefront per row,
 // a bitonic network across the lanes with shuffles, padding sorting last.
+// With dist, each index travels with its distance (packed into one word).
+template <bool OUT>
 __global__ __launch_bounds__(256) void k_sort_rows_wave(const int64_t *__restrict__ offsets,
-                                                        int32_t *__restrict__ indices,
+                                                        int32_t *__restrict__ indices, float *__restrict__ dist,
                                                         const int32_t *__restrict__ list, int64_t nb)
 {
     const int lane = lane_id();
@@ -318,26 +395,36 @@ __global__ __launch_bounds__(256) void k_sort_rows_wave(const int64_t *__restric
         const int64_t len = offsets[row + 1] - o;
         if (len > kWave)
             continue;
-        int v = lane < len ? indices[o + lane] : INT32_MAX;
+        uint64_t v = OUT ? ~0ull : (0xffffffffull << 32);
+        if (lane < len)
+            v = OUT ? pack_match(indices[o + lane], dist[o + lane]) : ((uint64_t)(uint32_t)indices[o + lane] << 32);
 #pragma unroll
         for (int k = 2; k <= kWave; k <<= 1)
 #pragma unroll
             for (int j = k >> 1; j > 0; j >>= 1) {
-                const int other = __shfl_xor(v, j, kWave);
+                const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), j, kWave);
+                const uint32_t lo = OUT ? __shfl_xor((uint32_t)v, j, kWave) : 0u;
+                const uint64_t other = ((uint64_t)hi << 32) | lo;
                 const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
-                v = keep_min ? min(v, other) : max(v, other);
+                v = keep_min ? (v < other ? v : other) : (v < other ? other : v);
             }
-        if (lane < len)
-            indices[o + lane] = v;
+        if (lane < len) {
+            indices[o + lane] = (int32_t)(v >> 32);
+            if (OUT)
+                dist[o + lane] = __uint_as_float((uint32_t)v);
+        }
     }
 }
 
 // One workgroup per listed row of kWave < len <= kRowSortBlock entries:
-// bitonic sort in LDS.
+// bitonic sort in LDS (with dist: the distances move with their indices).
+template <bool OUT>
 __global__ __launch_bounds__(256) void k_sort_rows(const int64_t *__restrict__ offsets, int32_t *__restrict__ indices,
-                                                   const int32_t *__restrict__ list, int64_t nb)
+                                                   float *__restrict__ dist, const int32_t *__restrict__ list,
+                                                   int64_t nb)
 {
     __shared__ int32_t s[kRowSortBlock];
+    __shared__ float sd[OUT ? kRowSortBlock : 1];
     for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
         const int64_t row = list[b];
         const int64_t o = offsets[row];
@@ -348,8 +435,11 @@ __global__ __launch_bounds__(256) void k_sort_rows(const int64_t *__restrict__ o
         int p2 = 1;
         while (p2 < len)
             p2 <<= 1;
-        for (int i = threadIdx.x; i < p2; i += blockDim.x)
+        for (int i = threadIdx.x; i < p2; i += blockDim.x) {
             s[i] = i < len ? indices[o + i] : INT32_MAX;
+            if (OUT)
+                sd[i] = i < len ? dist[o + i] : 0.0f;
+        }
         __syncthreads();
         for (int kk = 2; kk <= p2; kk <<= 1) {
             for (int j = kk >> 1; j > 0; j >>= 1) {
@@ -361,14 +451,22 @@ __global__ __launch_bounds__(256) void k_sort_rows(const int64_t *__restrict__ o
                         if ((a > c) == up) {
                             s[i] = c;
                             s[ixj] = a;
+                            if (OUT) {
+                                const float t = sd[i];
+                                sd[i] = sd[ixj];
+                                sd[ixj] = t;
+                            }
                         }
                     }
                 }
                 __syncthreads();
             }
         }
-        for (int i = threadIdx.x; i < len; i += blockDim.x)
+        for (int i = threadIdx.x; i < len; i += blockDim.x) {
             indices[o + i] = s[i];
+            if (OUT)
+                dist[o + i] = sd[i];
+        }
         __syncthreads();
     }
 }
@@ -383,28 +481,34 @@ __global__ void k_huge_lengths(const int64_t *__restrict__ offsets, const int32_
 }
 
 __global__ void k_huge_gather(const int64_t *__restrict__ offsets, const int32_t *__restrict__ indices,
-                              const int32_t *__restrict__ list, int64_t h, const int64_t *__restrict__ starts,
-                              int ib, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals)
+                              const float *__restrict__ dist, const int32_t *__restrict__ list, int64_t h,
+                              const int64_t *__restrict__ starts, int ib, uint64_t *__restrict__ keys,
+                              uint32_t *__restrict__ vals)
 {
     for (int64_t b = blockIdx.x; b < h; b += gridDim.x) {
         const int64_t o = offsets[list[b]], len = offsets[list[b] + 1] - o, st = starts[b];
         for (int64_t j = threadIdx.x; j < len; j += blockDim.x) {
             keys[st + j] = ((uint64_t)b << ib) | (uint32_t)indices[o + j];
-            vals[st + j] = 0;
+            vals[st + j] = dist ? __float_as_uint(dist[o + j]) : 0u;
         }
     }
 }
 
-__global__ void k_huge_scatter(const uint64_t *__restrict__ keys, int64_t total, int ib, int64_t h,
-                               const int64_t *__restrict__ offsets, const int32_t *__restrict__ list,
-                               const int64_t *__restrict__ starts, int32_t *__restrict__ indices)
+__global__ void k_huge_scatter(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals, int64_t total,
+                               int ib, int64_t h, const int64_t *__restrict__ offsets,
+                               const int32_t *__restrict__ list, const int64_t *__restrict__ starts,
+                               int32_t *__restrict__ indices, float *__restrict__ dist)
 {
     const uint64_t lowmask = (1ull << ib) - 1ull;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t key = keys[p];
         const int64_t b = (int64_t)(key >> ib);
-        if (b < h)
-            indices[offsets[list[b]] + (p - starts[b])] = (int32_t)(key & lowmask);
+        if (b < h) {
+            const int64_t at = offsets[list[b]] + (p - starts[b]);
+            indices[at] = (int32_t)(key & lowmask);
+            if (dist)
+                dist[at] = __uint_as_float(vals[p]);
+        }
     }
 }
 
@@ -680,23 +784,31 @@ int effective_schedule(int op)
 
 template <int D>
 arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m, float r2, const uint32_t *perm,
-                         int32_t *counts, int32_t *ordered_counts, int32_t *stash, const OverflowPool &ovf,
-                         hipStream_t s)
+                         int32_t *counts, int32_t *ordered_counts, int32_t *stash, float *stash_d2,
+                         const OverflowPool &ovf, hipStream_t s)
 {
     const int sched = effective_schedule(OP_SPATIAL);
     const int nq = tuning(OP_SPATIAL).packet ? tuning(OP_SPATIAL).packet : (D <= 3 ? 2 : 1);
+    const bool out = stash_d2 != nullptr;  // the callback-with-output form (sphere queries only)
     if (sched == 0 && nq > 1 && pred == Pred::Sphere) {  // NQ queries per thread over binary nodes
         const Launch L = traversal_launch((m + nq - 1) / nq, sizeof(int), OP_SPATIAL);
         const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
         ProfScope ps("spatial_count", s);
-        if (nq == 2)
-            k_spatial_count_packet<D, 2><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, counts,
-                                                                        perm ? ordered_counts : nullptr, stash, ovf,
-                                                                        L.cap);
-        else
-            k_spatial_count_packet<D, 4><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, counts,
-                                                                        perm ? ordered_counts : nullptr, stash, ovf,
-                                                                        L.cap);
+#define AX_CP(N, O) k_spatial_count_packet<D, N, O><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, counts, \
+                                                                                  perm ? ordered_counts : nullptr,    \
+                                                                                  stash, stash_d2, ovf, L.cap)
+        if (nq == 2) {
+            if (out)
+                AX_CP(2, true);
+            else
+                AX_CP(2, false);
+        } else {
+            if (out)
+                AX_CP(4, true);
+            else
+                AX_CP(4, false);
+        }
+#undef AX_CP
         AX_HIP(hipGetLastError());
         return ARBORX_OK;
     }
@@ -705,11 +817,24 @@ arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m,
     const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
     const Node4<D> *wnodes = static_cast<const Node4<D> *>(t.wnodes);
     ProfScope ps("spatial_count", s);
-#define AX_COUNT(P, S)                                                                                     \
-    k_spatial_count<D, P, true, S><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, wnodes, t.leaves, t.kind, t.hdr, q, m, r2, \
-                                                                  perm, counts, perm ? ordered_counts : nullptr,  \
-                                                                  stash, ovf, L.cap)
-    if (pred == Pred::Sphere) {
+#define AX_COUNT_O(P, S, O)                                                                                           \
+    k_spatial_count<D, P, true, S, O><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, wnodes, t.leaves, t.kind, t.hdr, q, \
+                                                                     m, r2, perm, counts,                             \
+                                                                     perm ? ordered_counts : nullptr, stash, stash_d2, \
+                                                                     ovf, L.cap)
+#define AX_COUNT(P, S) AX_COUNT_O(P, S, false)
+    if (pred == Pred::Sphere && out) {
+        if (sched == 1)
+            AX_COUNT_O(Sphere<D>, 1, true);
+        else if (sched == 2)
+            AX_COUNT_O(Sphere<D>, 2, true);
+        else if (sched == 3)
+            AX_COUNT_O(Sphere<D>, 3, true);
+        else if (sched == 4)
+            AX_COUNT_O(Sphere<D>, 4, true);
+        else
+            AX_COUNT_O(Sphere<D>, 0, true);
+    } else if (pred == Pred::Sphere) {
         if (sched == 1)
             AX_COUNT(Sphere<D>, 1);
         else if (sched == 2)
@@ -733,6 +858,7 @@ arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m,
             AX_COUNT(BoxQuery<D>, 0);
     }
 #undef AX_COUNT
+#undef AX_COUNT_O
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
@@ -740,7 +866,7 @@ arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m,
 template <int D>
 arborx_status fill_rows_impl(const TreeDev &t, Pred pred, const float *q, int64_t m, float r2, const int32_t *rows,
                              int64_t nrows, const int32_t *head, const int64_t *offsets, int32_t *indices,
-                             hipStream_t s)
+                             float *dist, hipStream_t s)
 {
     if (nrows <= 0)
         return ARBORX_OK;
@@ -752,7 +878,7 @@ arborx_status fill_rows_impl(const TreeDev &t, Pred pred, const float *q, int64_
     ProfScope ps("spatial_fill", s);
 #define AX_FILL(P, F)                                                                                              \
     k_spatial_fill_rows<D, P, F><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, wnodes, t.leaves, t.kind, t.hdr, q, m, r2, \
-                                                                rows, nrows, head, offsets, indices, L.cap)
+                                                                rows, nrows, head, offsets, indices, dist, L.cap)
     if (pred == Pred::Sphere) {
         if (fmt == 1)
             AX_FILL(Sphere<D>, 1);
@@ -934,7 +1060,7 @@ arborx_status query_order(const TreeDev &t, const float *queries, int64_t m, Pre
 
 arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
                             const uint32_t *perm, int32_t *counts, int32_t *ordered_counts, int32_t *stash,
-                            const OverflowPool &ovf, hipStream_t s)
+                            float *stash_d2, const OverflowPool &ovf, hipStream_t s)
 {
     if (m == 0)
         return ARBORX_OK;
@@ -946,7 +1072,8 @@ arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, i
     if ((st = fill_async<unsigned long long>(ovf.ctr, (int64_t)kOvfPools * 8, 0ull, s)) != ARBORX_OK)
         return st;
     const float r2 = radius * radius;
-    AX_DISPATCH_DIM(t.dim, (count_impl<D>(t, pred, queries, m, r2, perm, counts, ordered_counts, stash, ovf, s)));
+    AX_DISPATCH_DIM(t.dim,
+                    (count_impl<D>(t, pred, queries, m, r2, perm, counts, ordered_counts, stash, stash_d2, ovf, s)));
 }
 
 int64_t overflow_pool_ints(int64_t m, int dim)
@@ -959,9 +1086,9 @@ int64_t overflow_pool_ints(int64_t m, int dim)
 }
 
 arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
-                           const int32_t *counts, const int32_t *stash, const OverflowPool &ovf,
-                           const int64_t *offsets, const int32_t *big_list, int64_t nbig, const int32_t *huge_list,
-                           int64_t nhuge, int32_t *indices, hipStream_t s)
+                           const int32_t *counts, const int32_t *stash, const float *stash_d2,
+                           const OverflowPool &ovf, const int64_t *offsets, const int32_t *big_list, int64_t nbig,
+                           const int32_t *huge_list, int64_t nhuge, int32_t *indices, float *dist, hipStream_t s)
 {
     if (m == 0 || t.n == 0)
         return ARBORX_OK;
@@ -970,51 +1097,69 @@ arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, in
         return st;
     {
         ProfScope ps("copy_stash", s);
-        if (stash_regs(t.dim) == 32)
-            k_copy_stash<32><<<grid_for(m, 256, INT32_MAX), 256, 0, s>>>(stash, m, counts, offsets, indices);
-        else
-            k_copy_stash<16><<<grid_for(m, 256, INT32_MAX), 256, 0, s>>>(stash, m, counts, offsets, indices);
+        const unsigned g = grid_for(m, 256, INT32_MAX);
+        if (stash_regs(t.dim) == 32) {
+            if (dist)
+                k_copy_stash<32, true><<<g, 256, 0, s>>>(stash, stash_d2, m, counts, offsets, indices, dist);
+            else
+                k_copy_stash<32, false><<<g, 256, 0, s>>>(stash, stash_d2, m, counts, offsets, indices, dist);
+        } else {
+            if (dist)
+                k_copy_stash<16, true><<<g, 256, 0, s>>>(stash, stash_d2, m, counts, offsets, indices, dist);
+            else
+                k_copy_stash<16, false><<<g, 256, 0, s>>>(stash, stash_d2, m, counts, offsets, indices, dist);
+        }
         AX_HIP(hipGetLastError());
     }
     if (nbig > 0) {
         ProfScope ps("copy_overflow", s);
-        k_copy_overflow<<<grid_for(nbig, 256 / kWave, 16384), 256, 0, s>>>(stash, stash_regs(t.dim), ovf, counts,
-                                                                            offsets, big_list, nbig, indices);
+        k_copy_overflow<<<grid_for(nbig, 256 / kWave, 16384), 256, 0, s>>>(stash, stash_d2, stash_regs(t.dim), ovf,
+                                                                            counts, offsets, big_list, nbig, indices,
+                                                                            dist);
         AX_HIP(hipGetLastError());
     }
     const float r2 = radius * radius;
     switch (t.dim) {
     case 2:
-        if ((st = fill_rows_impl<2>(t, pred, queries, m, r2, big_list, nbig, ovf.head, offsets, indices, s)) == ARBORX_OK)
-            st = fill_rows_impl<2>(t, pred, queries, m, r2, huge_list, nhuge, nullptr, offsets, indices, s);
+        if ((st = fill_rows_impl<2>(t, pred, queries, m, r2, big_list, nbig, ovf.head, offsets, indices, dist, s)) ==
+            ARBORX_OK)
+            st = fill_rows_impl<2>(t, pred, queries, m, r2, huge_list, nhuge, nullptr, offsets, indices, dist, s);
         return st;
     case 3:
-        if ((st = fill_rows_impl<3>(t, pred, queries, m, r2, big_list, nbig, ovf.head, offsets, indices, s)) == ARBORX_OK)
-            st = fill_rows_impl<3>(t, pred, queries, m, r2, huge_list, nhuge, nullptr, offsets, indices, s);
+        if ((st = fill_rows_impl<3>(t, pred, queries, m, r2, big_list, nbig, ovf.head, offsets, indices, dist, s)) ==
+            ARBORX_OK)
+            st = fill_rows_impl<3>(t, pred, queries, m, r2, huge_list, nhuge, nullptr, offsets, indices, dist, s);
         return st;
     case 6:
-        if ((st = fill_rows_impl<6>(t, pred, queries, m, r2, big_list, nbig, ovf.head, offsets, indices, s)) == ARBORX_OK)
-            st = fill_rows_impl<6>(t, pred, queries, m, r2, huge_list, nhuge, nullptr, offsets, indices, s);
+        if ((st = fill_rows_impl<6>(t, pred, queries, m, r2, big_list, nbig, ovf.head, offsets, indices, dist, s)) ==
+            ARBORX_OK)
+            st = fill_rows_impl<6>(t, pred, queries, m, r2, huge_list, nhuge, nullptr, offsets, indices, dist, s);
         return st;
     default:
         return fail(ARBORX_E_UNSUPPORTED, "dimension not compiled in");
     }
 }
 
-arborx_status sort_big_rows(const int64_t *offsets, int32_t *indices, const int32_t *big_list, int64_t nbig,
-                            hipStream_t s)
+arborx_status sort_big_rows(const int64_t *offsets, int32_t *indices, float *dist, const int32_t *big_list,
+                            int64_t nbig, hipStream_t s)
 {
     if (nbig <= 0)
         return ARBORX_OK;
     ProfScope ps("sort_rows", s);
-    k_sort_rows_wave<<<(unsigned)grid_for(nbig, 256 / kWave, 16384), 256, 0, s>>>(offsets, indices, big_list, nbig);
-    k_sort_rows<<<(unsigned)(nbig < 8192 ? nbig : 8192), 256, 0, s>>>(offsets, indices, big_list, nbig);
+    const unsigned gw = grid_for(nbig, 256 / kWave, 16384), gb = (unsigned)(nbig < 8192 ? nbig : 8192);
+    if (dist) {
+        k_sort_rows_wave<true><<<gw, 256, 0, s>>>(offsets, indices, dist, big_list, nbig);
+        k_sort_rows<true><<<gb, 256, 0, s>>>(offsets, indices, dist, big_list, nbig);
+    } else {
+        k_sort_rows_wave<false><<<gw, 256, 0, s>>>(offsets, indices, dist, big_list, nbig);
+        k_sort_rows<false><<<gb, 256, 0, s>>>(offsets, indices, dist, big_list, nbig);
+    }
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
 
-arborx_status sort_huge_rows(int64_t n_values, const int64_t *offsets, int32_t *indices, const int32_t *huge_list,
-                             int64_t h, Temps &tmp, hipStream_t s)
+arborx_status sort_huge_rows(int64_t n_values, const int64_t *offsets, int32_t *indices, float *dist,
+                             const int32_t *huge_list, int64_t h, Temps &tmp, hipStream_t s)
 {
     if (h <= 0)
         return ARBORX_OK;
@@ -1044,11 +1189,12 @@ arborx_status sort_huge_rows(int64_t n_values, const int64_t *offsets, int32_t *
         (st = tmp.get(&v1, total)) != ARBORX_OK || (st = tmp.get(&v2, total)) != ARBORX_OK ||
         (st = tmp.get(&rws, radix_workspace_bytes(total))) != ARBORX_OK)
         return st;
-    k_huge_gather<<<(unsigned)(h < 4096 ? h : 4096), 256, 0, s>>>(offsets, indices, huge_list, h, starts, ib, k1, v1);
+    k_huge_gather<<<(unsigned)(h < 4096 ? h : 4096), 256, 0, s>>>(offsets, indices, dist, huge_list, h, starts, ib, k1,
+                                                                  v1);
     bool alt = false;
     AX_HIP(radix_sort_pairs<uint64_t>(k1, v1, k2, v2, total, 0, ib + hb, rws, s, &alt));
-    k_huge_scatter<<<grid_for(total, 256, 65536), 256, 0, s>>>(alt ? k2 : k1, total, ib, h, offsets, huge_list, starts,
-                                                              indices);
+    k_huge_scatter<<<grid_for(total, 256, 65536), 256, 0, s>>>(alt ? k2 : k1, alt ? v2 : v1, total, ib, h, offsets,
+                                                              huge_list, starts, indices, dist);
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }

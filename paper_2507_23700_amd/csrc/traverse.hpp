@@ -546,8 +546,8 @@ __device__ __forceinline__ long long fixed_term(float d2, float scale)
 }
 
 // Store x in slot k of buf (k < C), with static indices only.
-template <int C>
-__device__ __forceinline__ void append_at(int (&buf)[C], int k, int x)
+template <int C, typename T>
+__device__ __forceinline__ void append_at(T (&buf)[C], int k, T x)
 {
 #pragma unroll
     for (int s = 0; s < C; ++s)
@@ -555,8 +555,8 @@ __device__ __forceinline__ void append_at(int (&buf)[C], int k, int x)
 }
 
 // Ascending bitonic sorting network over C (a power of two) registers.
-template <int C>
-__device__ __forceinline__ void sort_network(int (&v)[C])
+template <int C, typename T>
+__device__ __forceinline__ void sort_network(T (&v)[C])
 {
 #pragma unroll
     for (int k = 2; k <= C; k <<= 1)
@@ -566,10 +566,11 @@ __device__ __forceinline__ void sort_network(int (&v)[C])
             for (int i = 0; i < C; ++i) {
                 const int l = i ^ j;
                 if (l > i) {
-                    const int a = v[i], b = v[l];
+                    const T a = v[i], b = v[l];
                     const bool up = (i & k) == 0;
-                    v[i] = up ? min(a, b) : max(a, b);
-                    v[l] = up ? max(a, b) : min(a, b);
+                    const T lo = a < b ? a : b, hi = a < b ? b : a;
+                    v[i] = up ? lo : hi;
+                    v[l] = up ? hi : lo;
                 }
             }
 }

@@ -92,6 +92,10 @@ def test_full_size_sampled_parity_and_properties(name):
     dbc_t = ax.arborx_query_spatial_reduce(t, d, r, ax.COUNT)[0]
     sj_t = ax.arborx_self_join_degree(t, r)
     md_t = ax.arborx_query_match_distances(t, d, qd, off_t, idx_t)
+    # the callback-with-output form: the walk's own distances equal the gather over the CSR result
+    _, idw_t, dw_t = ax.arborx_query_spatial_with_distances(t, qd, r)
+    same_w = bool(torch.equal(idw_t, idx_t)) and bool(torch.equal(dw_t.view(torch.int32), md_t.view(torch.int32)))
+    del idw_t, dw_t
     torch.cuda.synchronize()
     off, idx = off_t.cpu().numpy(), idx_t.cpu().numpy()
     c, c2, s2 = c_t.cpu().numpy(), c2_t.cpu().numpy(), s2_t.cpu().numpy()
@@ -105,6 +109,7 @@ def test_full_size_sampled_parity_and_properties(name):
     del off_t, idx_t, c_t, c2_t, s2_t, d2_t, ix_t, u5_t, md_t, t
 
     # every query: properties
+    assert same_w
     assert off[0] == 0 and off[-1] == len(idx) and np.all(np.diff(off) >= 0)
     assert np.array_equal(np.diff(off), c) and np.array_equal(c, c2)
     assert np.all((idx >= 0) & (idx < n))

@@ -42,6 +42,15 @@ def check_spatial(tree, data, q, r, dim=3, kind=oracle.POINTS):
     return o_off
 
 
+def check_spatial_dist(tree, data, q, r, dim=3, kind=oracle.POINTS):
+    """The callback-with-output form: (offsets, indices, distances) from one search, exact."""
+    off, idx, d2 = ax.arborx_query_spatial_with_distances(tree, dev(q), float(r))
+    o_off, o_idx = oracle.spatial(data, q, r, dim=dim, kind=kind)
+    assert np.array_equal(host(off), o_off) and np.array_equal(host(idx), o_idx)
+    assert np.array_equal(host(d2), oracle.match_distances(data, q, o_off, o_idx, dim=dim, kind=kind))
+    return o_off
+
+
 def check_knn(tree, data, q, k, dim=3, kind=oracle.POINTS):
     d2, ix = ax.arborx_query_knn(tree, dev(q), k)
     o_d2, o_ix = oracle.knn(data, q, k, dim=dim, kind=kind)
@@ -327,6 +336,8 @@ def test_infinite_radius_long_rows():
     off = check_spatial(t, data, q, float("inf"))
     assert off[-1] == 9000 * 40
     check_spatial(t, data, q, 0.35)  # rows of a few thousand: workgroup sort
+    check_spatial_dist(t, data, q, float("inf"))  # rows past the workgroup sort: radix path carries distances
+    check_spatial_dist(t, data, q, 0.35)
 
 
 def test_denormal_distances():
@@ -349,8 +360,31 @@ def test_capacity_protocol():
     st = _lib.lib().arborx_query_spatial(t.handle, ctypes.c_void_p(q.data_ptr()), 500, ctypes.c_float(cfg["radius"]),
                                          ctypes.c_void_p(off.data_ptr()), None, 0, ctypes.byref(total), None)
     assert st == ax.E_CAPACITY
-    o_off, _ = oracle.spatial(cfg["data"], cfg["queries"], cfg["radius"])
+    o_off, o_idx = oracle.spatial(cfg["data"], cfg["queries"], cfg["radius"])
     assert total.value == o_off[-1] and np.array_equal(host(off), o_off)
+    # the distance form follows the same protocol, and a missing distances buffer counts as too small
+    L = _lib.lib()
+    idx = torch.empty(int(o_off[-1]), dtype=torch.int32, device="cuda")
+    d2 = torch.empty(int(o_off[-1]), dtype=torch.float32, device="cuda")
+    args = (t.handle, ctypes.c_void_p(q.data_ptr()), 500, ctypes.c_float(cfg["radius"]), ctypes.c_void_p(off.data_ptr()))
+    st = L.arborx_query_spatial_with_distances(*args, ctypes.c_void_p(idx.data_ptr()), None, idx.numel(),
+                                               ctypes.byref(total), None)
+    assert st == ax.E_CAPACITY and total.value == o_off[-1]
+    st = L.arborx_query_spatial_with_distances(*args, ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),
+                                               idx.numel() - 1, ctypes.byref(total), None)
+    assert st == ax.E_CAPACITY
+    st = L.arborx_query_spatial_with_distances(*args, ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),
+                                               idx.numel(), ctypes.byref(total), None)
+    assert st == ax.OK and np.array_equal(host(idx), o_idx)
+    assert np.array_equal(host(d2), oracle.match_distances(cfg["data"], cfg["queries"], o_off, o_idx))
+    # a plan begun without distances cannot give them
+    plan = ctypes.c_void_p()
+    assert L.arborx_query_spatial_begin(*args, ctypes.byref(total), ctypes.byref(plan), None) == ax.OK
+    try:
+        assert L.arborx_query_finish_with_distances(plan, ctypes.c_void_p(idx.data_ptr()),
+                                                    ctypes.c_void_p(d2.data_ptr()), idx.numel()) == ax.E_INVALID
+    finally:
+        L.arborx_plan_destroy(plan)
 
 
 @pytest.mark.parametrize("block,order,stack,schedule,node_format",
@@ -366,6 +400,7 @@ def test_schedules_identical(block, order, stack, schedule, node_format):
     try:
         t = ax.arborx_bvh_build(dev(data))
         check_spatial(t, data, q, r)
+        check_spatial_dist(t, data, q, r)
         check_knn(t, data, q, 10)
         check_reduce(t, data, q, r)
     finally:
@@ -522,6 +557,7 @@ def test_overflow_chains(case):
     try:
         t = ax.arborx_bvh_build(dev(data))
         off = check_spatial(t, data, q, 0.01)
+        check_spatial_dist(t, data, q, 0.01)  # distances through the stash, chunks and second walks
     finally:
         ax.arborx_reset_tuning()
     lens = np.diff(off)
@@ -705,6 +741,16 @@ def test_match_distances(case):
     want = oracle.match_distances(data, q, o_off, o_idx, dim=dim, kind=kind)
     assert np.array_equal(host(d2), want)
     assert np.all(host(d2) <= np.float32(r) * np.float32(r))
+    # the gather form over the same CSR result agrees with the walk's own output
+    v = dev(data)
+    assert np.array_equal(host(ax.arborx_query_match_distances(bvh.tree, v, dev(q), off, idx)), want)
+    # every schedule and packet width of the count walk gives the same output
+    for kw in (dict(schedule=1), dict(schedule=2), dict(queries_per_thread=1), dict(queries_per_thread=4)):
+        ax.arborx_set_tuning(**kw)
+        try:
+            check_spatial_dist(bvh.tree, data, q, r, dim=dim, kind=kind)
+        finally:
+            ax.arborx_reset_tuning()
 
 
 def _deepest_tree_points():
