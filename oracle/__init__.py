@@ -75,11 +75,14 @@ def lib():
         L.oracle_self_join_pairs.argtypes = [P, I64, I32, F32, P, P]
         L.oracle_ray_count.argtypes = [P, I64, I32, I32, P, I64, P]
         L.oracle_ray_nearest.argtypes = [P, I64, I32, I32, P, I64, I32, P, P]
+        L.oracle_ray_intersect.argtypes = [P, I64, I32, I32, P, I64, P, P]
+        L.oracle_ray_ordered_intersect.argtypes = [P, I64, I32, I32, P, I64, P, P, P]
         L.oracle_knn.argtypes = [P, I64, I32, I32, P, I64, I32, P, P]
         L.oracle_chamfer_forward.argtypes = [P, P, P, P, I32, P, P, P]
         L.oracle_chamfer_backward.argtypes = [P, P, P, P, I32, P, P, P, P, P]
         for f in ("oracle_spatial_count", "oracle_spatial_fill", "oracle_intersects_count", "oracle_intersects_fill",
-                  "oracle_reduce", "oracle_count_up_to", "oracle_self_join_degree", "oracle_self_join_pairs", "oracle_knn", "oracle_chamfer_forward", "oracle_chamfer_backward",
+                  "oracle_reduce", "oracle_count_up_to", "oracle_self_join_degree", "oracle_self_join_pairs",
+                  "oracle_ray_intersect", "oracle_ray_ordered_intersect", "oracle_knn", "oracle_chamfer_forward", "oracle_chamfer_backward",
                   "oracle_threads"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -177,6 +180,30 @@ def ray_nearest(values, rays, k, dim=3, kind=POINTS):
     idx = np.zeros((m, k), dtype=np.int32)
     lib().oracle_ray_nearest(_p(v), n, dim, kind, _p(r), m, k, _p(t), _p(idx))
     return t, idx
+
+
+def ray_intersect(values, rays, dim=3, kind=POINTS):
+    """Ray intersect (Section 2.5): every value each ray meets, CSR (offsets, indices) with ascending rows."""
+    v, n = _values(values, dim, kind)
+    r, m = _queries(rays, dim, 2)
+    off = np.zeros(m + 1, dtype=np.int64)
+    if lib().oracle_ray_intersect(_p(v), n, dim, kind, _p(r), m, _p(off), None) != 0:
+        raise MemoryError("oracle_ray_intersect")
+    idx = np.zeros(int(off[-1]), dtype=np.int32)
+    lib().oracle_ray_intersect(_p(v), n, dim, kind, _p(r), m, _p(off), _p(idx))
+    return off, idx
+
+
+def ray_ordered_intersect(values, rays, dim=3, kind=POINTS):
+    """Ray ordered intersect (Section 2.5): CSR rows in the order (entry t, index), with the entry
+    parameters: (offsets, indices, t)."""
+    v, n = _values(values, dim, kind)
+    r, m = _queries(rays, dim, 2)
+    off, _ = ray_intersect(values, rays, dim=dim, kind=kind)
+    idx = np.zeros(int(off[-1]), dtype=np.int32)
+    t = np.zeros(int(off[-1]), dtype=np.float32)
+    lib().oracle_ray_ordered_intersect(_p(v), n, dim, kind, _p(r), m, _p(off), _p(idx), _p(t))
+    return off, idx, t
 
 
 def dbscan(points, eps, min_pts, dim=3):

@@ -27,8 +27,9 @@
  *     with a radius, as per-point pair counts and upper-triangle CSR rows;
  *   - density-based clustering over the radius search (Section 2.4, DBSCAN):
  *     core points, their eps-connected components and border points;
- *   - ray predicates (Section 2.5): the values a ray meets, counted, and the k
- *     met first, ordered by (entry parameter, index);
+ *   - ray predicates (Section 2.5): the values a ray meets, counted, listed
+ *     (intersect), listed in the order met (ordered intersect), and the k met
+ *     first, ordered by (entry parameter, index);
  *   - Chamfer loss of nearest-neighbour pairs and its gradient, in float64.
  *
  * Floating-point contract (the paper fixes none; this follows the exactness
@@ -291,6 +292,62 @@ int oracle_ray_nearest(const float *values, int64_t n, int dim, int kind, const 
             }
             bt[s] = t;
             bi[s] = (int32_t)j;
+        }
+    }
+    return 0;
+}
+
+/* Ray intersect (Section 2.5): every value the ray meets, as CSR rows with
+ * ascending indices (offsets[m+1] from the counts; indices == NULL fills the
+ * offsets only). */
+int oracle_ray_intersect(const float *values, int64_t n, int dim, int kind, const float *rays, int64_t m,
+                         int64_t *offsets, int32_t *indices)
+{
+    int32_t *counts = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    if (!counts)
+        return -1;
+    oracle_ray_count(values, n, dim, kind, rays, m, counts);
+    offsets[0] = 0;
+    for (int64_t i = 0; i < m; ++i)
+        offsets[i + 1] = offsets[i] + counts[i];
+    free(counts);
+    if (!indices)
+        return 0;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t at = offsets[i];
+        float t;
+        for (int64_t j = 0; j < n; ++j)
+            if (ray_value(values, j, dim, kind, rays + i * 2 * dim, &t))
+                indices[at++] = (int32_t)j;
+    }
+    return 0;
+}
+
+/* Ray ordered intersect (Section 2.5: the hits in the order a physical ray
+ * meets them): each CSR row of oracle_ray_intersect reordered by (entry
+ * parameter, index), with the entry parameters in t_out.  Insertion sort: a
+ * hit moves before every earlier hit with a larger entry parameter, so equal
+ * parameters keep ascending indices. */
+int oracle_ray_ordered_intersect(const float *values, int64_t n, int dim, int kind, const float *rays, int64_t m,
+                                 const int64_t *offsets, int32_t *indices, float *t_out)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < m; ++i) {
+        const int64_t o = offsets[i];
+        int64_t len = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            float t;
+            if (!ray_value(values, j, dim, kind, rays + i * 2 * dim, &t))
+                continue;
+            int64_t s = len++;
+            while (s > 0 && t_out[o + s - 1] > t) {
+                t_out[o + s] = t_out[o + s - 1];
+                indices[o + s] = indices[o + s - 1];
+                --s;
+            }
+            t_out[o + s] = t;
+            indices[o + s] = (int32_t)j;
         }
     }
     return 0;

@@ -708,3 +708,77 @@ def test_self_join_vs_kdtree_pairs(dim):
     assert np.array_equal(deg, np.bincount(np.array(sorted(got)).ravel(), minlength=len(pts)))
     # a point's partners are its radius-search matches without itself
     assert np.array_equal(deg, oracle.spatial_count(pts, pts, r, dim=dim) - 1)
+
+
+# ---------------------------------------------------------------------------
+# ray intersect and ordered intersect (all hits)
+# ---------------------------------------------------------------------------
+
+def test_ray_intersect_hand_worked():
+    boxes = np.array([[[i, 0, 0], [i + 1, 1, 1]] for i in range(5)], dtype=np.float32)
+    B = oracle.BOXES
+    rays = np.concatenate([_ray((-1, 0.5, 0.5), (1, 0, 0)),     # enters box i at t = i + 1
+                           _ray((6, 0.5, 0.5), (-1, 0, 0)),     # backwards: box 4 first, at t = 1
+                           _ray((2.5, 0.5, 0.5), (2, 0, 0)),    # starts inside box 2
+                           _ray((-1, 0.5, 0.5), (-1, 0, 0)),    # pointing away: no hit
+                           _ray((1, 0.5, -1), (0, 0, 1))])      # along the face shared by boxes 0 and 1
+    off, idx = oracle.ray_intersect(boxes, rays, kind=B)
+    assert list(off) == [0, 5, 10, 13, 13, 15]
+    assert list(idx) == [0, 1, 2, 3, 4, 0, 1, 2, 3, 4, 2, 3, 4, 0, 1]
+    off2, idx2, t = oracle.ray_ordered_intersect(boxes, rays, kind=B)
+    assert list(off2) == list(off)
+    assert list(idx2) == [0, 1, 2, 3, 4, 4, 3, 2, 1, 0, 2, 3, 4, 0, 1]
+    assert list(t) == [1, 2, 3, 4, 5, 1, 2, 3, 4, 5, 0, 0.25, 0.75, 1, 1]  # equal t: smaller index first
+    # points are degenerate boxes, met only exactly
+    pts = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0]], dtype=np.float32)
+    pr = np.concatenate([_ray((-2, 0, 0), (0.5, 0, 0)), _ray((3, 0, 0), (-0.5, 0, 0))])
+    off, idx, t = oracle.ray_ordered_intersect(pts, pr)
+    assert list(off) == [0, 2, 4] and list(idx) == [0, 1, 1, 0] and list(t) == [4, 6, 4, 6]
+    assert list(oracle.ray_intersect(pts, pr)[1]) == [0, 1, 0, 1]
+
+
+def test_ray_intersect_vs_exact_rationals_and_nearest():
+    g = np.random.default_rng(25)
+    c = g.random((250, 3)).astype(np.float32)
+    h = (g.random((250, 3)) * 0.08 + 0.01).astype(np.float32)
+    boxes = np.ascontiguousarray(np.stack([c - h, c + h], axis=1))
+    rays = np.ascontiguousarray(np.stack([g.random((50, 3)) * 2 - 0.5, g.standard_normal((50, 3))], axis=1)
+                                .astype(np.float32))
+    B = oracle.BOXES
+    off, idx = oracle.ray_intersect(boxes, rays, kind=B)
+    off2, idx2, t = oracle.ray_ordered_intersect(boxes, rays, kind=B)
+    assert np.array_equal(off, off2) and np.array_equal(np.diff(off), oracle.ray_count(boxes, rays, kind=B))
+    checked = 0
+    for i in range(len(rays)):
+        row, orow, trow = idx[off[i]:off[i + 1]], idx2[off[i]:off[i + 1]], t[off[i]:off[i + 1]]
+        assert np.all(np.diff(row) > 0) and np.array_equal(np.sort(orow), row)
+        o = [Fraction(float(x)) for x in rays[i, 0]]
+        d = [Fraction(float(x)) for x in rays[i, 1]]
+        hits, near_tangent = {}, False
+        for j in range(len(boxes)):
+            tmin, tmax = Fraction(0), None
+            for k in range(3):
+                t1 = (Fraction(float(boxes[j, 0, k])) - o[k]) / d[k]
+                t2 = (Fraction(float(boxes[j, 1, k])) - o[k]) / d[k]
+                tmin, tmax = max(tmin, min(t1, t2)), (max(t1, t2) if tmax is None else min(tmax, max(t1, t2)))
+            if abs(tmax - tmin) < Fraction(1, 10 ** 4) * (1 + abs(tmax)):
+                near_tangent = True
+                break
+            if tmax >= tmin:
+                hits[j] = tmin
+        if near_tangent:
+            continue
+        assert set(row.tolist()) == set(hits)
+        exact = [hits[int(j)] for j in orow]
+        for a, b in zip(exact, exact[1:]):  # met in order, up to float32 rounding of the entry parameter
+            assert a <= b + Fraction(1, 10 ** 5) * (1 + abs(b))
+        for j, tt in zip(orow, trow):
+            assert abs(float(tt) - float(hits[int(j)])) <= 1e-5 * (1 + abs(float(hits[int(j)])))
+        checked += 1
+    assert checked > 30
+    # the first k hits in order are the k-nearest ray query (an insertion into a bounded list)
+    tn, ixn = oracle.ray_nearest(boxes, rays, 6, kind=B)
+    for i in range(len(rays)):
+        kk = min(6, off[i + 1] - off[i])
+        assert np.array_equal(ixn[i, :kk], idx2[off[i]:off[i] + kk])
+        assert np.array_equal(tn[i, :kk], t[off[i]:off[i] + kk])
