@@ -14,7 +14,8 @@ Prints ONE JSON line on stdout (progress goes to stderr):
                count, the radius search with per-match distances (callback
                with output), DBSCAN and the pair search on the step's tree,
                standalone reduce and kNN calls that order their queries, and
-               rays against a tree of 2*10^6 boxes;
+               rays against a tree of 2*10^6 boxes (hit counts, first hit, all
+               hits, all hits in the order met);
   roofline   = the dominant kernel's algorithmic bytes / its average duration
                against MI355X HBM peak (8 TB/s), with the measured HBM traffic
                while profiles/traffic.json matches the kernel sources, and the
@@ -507,6 +508,12 @@ def main():
     comps["ray_count_rays_s"] = rays.shape[0] / ms * 1e3
     ms = timed(lambda: ax.arborx_query_ray_nearest(btree, rays, 1), 3)
     comps["ray_first_hit_rays_s"] = rays.shape[0] / ms * 1e3
+    hits = ax.arborx_query_ray_intersect(btree, rays)[0][-1].item()
+    ms = timed(lambda: ax.arborx_query_ray_intersect(btree, rays), 3)
+    comps["ray_intersect_rays_s"] = rays.shape[0] / ms * 1e3
+    ms = timed(lambda: ax.arborx_query_ray_ordered_intersect(btree, rays), 3)
+    comps["ray_ordered_intersect_rays_s"] = rays.shape[0] / ms * 1e3
+    comps["ray_mean_hits"] = hits / rays.shape[0]
     del btree, boxes, rays
     # DBSCAN over the tree's points (eps = the step's radius, min_pts = 10), and the pair search it is
     # built on (the self-join of the tree's points at the same radius)

@@ -356,6 +356,41 @@ arborx_status arborx_dbscan(arborx_tree tree, const float *points, float eps, in
 arborx_status arborx_self_join_degree(arborx_tree tree, float radius, int32_t *degree, void *stream);
 
 /*
+ * Ray intersect (Section 2.5, the intersect predicate: every value a ray
+ * meets, as if the objects were transparent), with CSR output.
+ *   rays      [m][2][dim]: origin row, then direction row (any length, zero
+ *             components allowed); hits as in arborx_query_ray_count
+ *   offsets, indices, capacity, total: as arborx_query_spatial; rows ascending
+ * Rays are ordered by the Morton code of their origins before the walk.
+ * Synchronises `stream` (to read the total).  Plan form:
+ * arborx_query_ray_intersect_begin, then arborx_query_finish.
+ */
+arborx_status arborx_query_ray_intersect(arborx_tree tree, const float *rays, int64_t m, int64_t *offsets,
+                                        int32_t *indices, int64_t capacity, int64_t *total, void *stream);
+arborx_status arborx_query_ray_intersect_begin(arborx_tree tree, const float *rays, int64_t m, int64_t *offsets,
+                                              int64_t *total, arborx_plan *plan, void *stream);
+
+/*
+ * Ray ordered intersect (Section 2.5, ordered_intersect: the values a ray
+ * meets, in the order a physical ray meets them), with CSR output: each row
+ * ordered by (entry parameter, index), and the entry parameters beside the
+ * indices.  The first k entries of a row are arborx_query_ray_nearest's.
+ *   t_entry   [capacity] float32 output: the ray parameter t >= 0 at which it
+ *             enters the value's box (0 when the origin is inside)
+ * If indices or t_entry is NULL, or capacity < total, offsets and *total are
+ * filled and ARBORX_E_CAPACITY is returned.  Synchronises `stream`.  Plan form:
+ * arborx_query_ray_ordered_intersect_begin, then
+ * arborx_query_finish_with_distances (its `distances` receive the entry
+ * parameters) or arborx_query_finish (indices only, still in order).
+ */
+arborx_status arborx_query_ray_ordered_intersect(arborx_tree tree, const float *rays, int64_t m, int64_t *offsets,
+                                                int32_t *indices, float *t_entry, int64_t capacity, int64_t *total,
+                                                void *stream);
+arborx_status arborx_query_ray_ordered_intersect_begin(arborx_tree tree, const float *rays, int64_t m,
+                                                      int64_t *offsets, int64_t *total, arborx_plan *plan,
+                                                      void *stream);
+
+/*
  * Ray predicates (Section 2.5: rays traced against the index's values).  Ray i
  * is rays[i] = {origin[dim], direction[dim]} ([m][2][dim]) and covers
  * o + t*dir for t >= 0.  It meets a value's closed box (a point is a degenerate

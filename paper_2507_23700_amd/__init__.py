@@ -328,6 +328,32 @@ def arborx_query_ray_count(tree: Tree, rays, stream=None):
     return counts
 
 
+def arborx_query_ray_intersect(tree: Tree, rays, stream=None):
+    """Every value each ray meets (rays [m, 2, dim] = origin, direction): CSR (offsets, indices), rows ascending."""
+    r = _queries(tree, rays, True)
+    return _csr(_lib.lib().arborx_query_ray_intersect_begin, tree, r, [], stream)
+
+
+def arborx_query_ray_ordered_intersect(tree: Tree, rays, stream=None):
+    """The values each ray meets in the order met: CSR (offsets, indices, t_entry), rows by (t, index)."""
+    torch = _torch()
+    r = _queries(tree, rays, True)
+    m = r.shape[0]
+    offsets = torch.empty(m + 1, dtype=torch.int64, device=r.device)
+    total = ctypes.c_int64()
+    plan = ctypes.c_void_p()
+    L = _lib.lib()
+    _check(L.arborx_query_ray_ordered_intersect_begin(tree.handle, _ptr(r), m, _ptr(offsets), ctypes.byref(total),
+                                                      ctypes.byref(plan), _stream(stream)))
+    try:
+        indices = torch.empty(max(total.value, 1), dtype=torch.int32, device=r.device)
+        t = torch.empty(max(total.value, 1), dtype=torch.float32, device=r.device)
+        _check(L.arborx_query_finish_with_distances(plan, _ptr(indices), _ptr(t), indices.numel()))
+    finally:
+        L.arborx_plan_destroy(plan)
+    return offsets, indices[:total.value], t[:total.value]
+
+
 def arborx_query_ray_nearest(tree: Tree, rays, k: int, stream=None):
     """The k values each ray meets first: (t_entry float32[m, k], indices int32[m, k]) by (t, index)."""
     torch = _torch()

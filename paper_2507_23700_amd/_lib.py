@@ -37,6 +37,10 @@ SIGNATURES = {
     "arborx_dbscan": (I32, [P, P, F32, I32, P, P]),
     "arborx_self_join_degree": (I32, [P, F32, P, P]),
     "arborx_query_ray_count": (I32, [P, P, I64, P, P]),
+    "arborx_query_ray_intersect": (I32, [P, P, I64, P, P, I64, P, P]),
+    "arborx_query_ray_intersect_begin": (I32, [P, P, I64, P, P, P, P]),
+    "arborx_query_ray_ordered_intersect": (I32, [P, P, I64, P, P, P, I64, P, P]),
+    "arborx_query_ray_ordered_intersect_begin": (I32, [P, P, I64, P, P, P, P]),
     "arborx_query_ray_nearest": (I32, [P, P, I64, I32, P, P, P]),
     "arborx_debug_radix_sort": (I32, [P, P, I64, I32, I32, I32, P]),
     "arborx_debug_morton64": (I32, [P, I64, I32, P, P, P]),

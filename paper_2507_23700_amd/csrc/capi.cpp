@@ -107,7 +107,8 @@ struct arborx_plan_s {
     ax::Temps tmp;
     uint32_t *perm = nullptr;
     int32_t *counts = nullptr, *ordered_counts = nullptr, *stash = nullptr, *big_list = nullptr, *huge_list = nullptr;
-    float *stash_d2 = nullptr;  // with distances (the callback-with-output form)
+    float *stash_d2 = nullptr;  // with per-match values (distances, or a ray's entry parameters)
+    int mode = ax::VALUES_NONE; // how rows are sorted and whether values are kept
     ax::OverflowPool ovf{};
     ax::QueryHeader h{};
     arborx_plan_s(hipStream_t s) : tmp(s) {}
@@ -624,8 +625,9 @@ arborx_status arborx_bvh_info(arborx_tree t, int64_t *n, int32_t *dim, int32_t *
 
 static arborx_status csr_begin(arborx_tree t, Pred pred, const float *queries, int64_t m, float radius,
                                int64_t *offsets, int64_t *total, arborx_plan *out, void *stream,
-                               bool with_dist = false)
+                               int mode = VALUES_NONE)
 {
+    const bool with_dist = mode != VALUES_NONE;
     arborx_status st = check_tree(t);
     if (st != ARBORX_OK)
         return st;
@@ -655,6 +657,7 @@ static arborx_status csr_begin(arborx_tree t, Pred pred, const float *queries, i
     p->radius = radius;
     p->offsets = offsets;
     p->stream = s;
+    p->mode = mode;
     auto bail = [&](arborx_status e) {
         std::string msg = g_error;
         delete p;
@@ -715,29 +718,35 @@ static arborx_status csr_finish(arborx_plan p, int32_t *indices, int64_t capacit
                                            std::to_string((long long)p->h.total));
     if (p->h.total == 0)
         return ARBORX_OK;
+    arborx_status st;
+    if (!dist && p->mode == VALUES_ORDERED &&  // rows ordered by value need the values even when not returned
+        (st = p->tmp.get(&dist, (size_t)p->h.total)) != ARBORX_OK)
+        return st;
     NoteUse note_use{p->tree->uses, p->stream};
-    arborx_status st = spatial_fill(p->tree->dev, p->pred, p->queries, p->m, p->radius, p->counts, p->stash,
-                                    p->stash_d2, p->ovf, p->offsets, p->big_list, (int64_t)p->h.big_rows,
-                                    p->huge_list, (int64_t)p->h.huge_rows, indices, dist, p->stream);
+    st = spatial_fill(p->tree->dev, p->pred, p->queries, p->m, p->radius, p->counts, p->stash, p->stash_d2, p->ovf,
+                      p->offsets, p->big_list, (int64_t)p->h.big_rows, p->huge_list, (int64_t)p->h.huge_rows,
+                      indices, dist, p->mode, p->stream);
     if (st != ARBORX_OK)
         return st;
-    if ((st = sort_big_rows(p->offsets, indices, dist, p->big_list, (int64_t)p->h.big_rows, p->stream)) != ARBORX_OK)
+    if ((st = sort_big_rows(p->offsets, indices, dist, p->mode, p->big_list, (int64_t)p->h.big_rows, p->stream)) !=
+        ARBORX_OK)
         return st;
-    return sort_huge_rows(p->tree->dev.n, p->offsets, indices, dist, p->huge_list, (int64_t)p->h.huge_rows, p->tmp,
-                          p->stream);
+    return sort_huge_rows(p->tree->dev.n, p->offsets, indices, dist, p->mode, p->huge_list, (int64_t)p->h.huge_rows,
+                          p->tmp, p->stream);
 }
 
 static arborx_status csr_query(arborx_tree t, Pred pred, const float *queries, int64_t m, float radius,
                                int64_t *offsets, int32_t *indices, int64_t capacity, int64_t *total, void *stream,
-                               bool with_dist = false, float *dist = nullptr)
+                               int mode = VALUES_NONE, float *dist = nullptr)
 {
     if (capacity < 0)
         return fail(ARBORX_E_INVALID, "capacity must be >= 0");
+    const bool with_dist = mode != VALUES_NONE;
     arborx_plan p = nullptr;
-    arborx_status st = csr_begin(t, pred, queries, m, radius, offsets, total, &p, stream, with_dist);
+    arborx_status st = csr_begin(t, pred, queries, m, radius, offsets, total, &p, stream, mode);
     if (st != ARBORX_OK)
         return st;
-    st = (with_dist && p->h.total > 0 && !dist) ? fail(ARBORX_E_CAPACITY, "distances is NULL")
+    st = (with_dist && p->h.total > 0 && !dist) ? fail(ARBORX_E_CAPACITY, "the per-match value output is NULL")
                                                  : csr_finish(p, indices, capacity, p->h.total > 0 ? dist : nullptr);
     std::string msg = g_error;
     delete p;
@@ -766,7 +775,7 @@ arborx_status arborx_query_spatial_with_distances_begin(arborx_tree t, const flo
                                                         int64_t *offsets, int64_t *total, arborx_plan *plan,
                                                         void *stream)
 {
-    return csr_begin(t, Pred::Sphere, queries, m, radius, offsets, total, plan, stream, true);
+    return csr_begin(t, Pred::Sphere, queries, m, radius, offsets, total, plan, stream, VALUES_BY_INDEX);
 }
 
 arborx_status arborx_query_finish_with_distances(arborx_plan plan, int32_t *indices, float *distances,
@@ -783,7 +792,7 @@ arborx_status arborx_query_spatial_with_distances(arborx_tree t, const float *qu
                                                   int64_t *offsets, int32_t *indices, float *distances,
                                                   int64_t capacity, int64_t *total, void *stream)
 {
-    return csr_query(t, Pred::Sphere, queries, m, radius, offsets, indices, capacity, total, stream, true,
+    return csr_query(t, Pred::Sphere, queries, m, radius, offsets, indices, capacity, total, stream, VALUES_BY_INDEX,
                      distances);
 }
 
@@ -896,6 +905,33 @@ static arborx_status ray_args(arborx_tree t, const float *rays, int64_t m, const
     if (m > 0 && (!rays || !out1 || !out2))
         return fail(ARBORX_E_INVALID, "rays and outputs must not be NULL");
     return check_device();
+}
+
+arborx_status arborx_query_ray_intersect_begin(arborx_tree t, const float *rays, int64_t m, int64_t *offsets,
+                                              int64_t *total, arborx_plan *plan, void *stream)
+{
+    return csr_begin(t, Pred::Ray, rays, m, 0.0f, offsets, total, plan, stream, VALUES_NONE);
+}
+
+arborx_status arborx_query_ray_intersect(arborx_tree t, const float *rays, int64_t m, int64_t *offsets,
+                                        int32_t *indices, int64_t capacity, int64_t *total, void *stream)
+{
+    return csr_query(t, Pred::Ray, rays, m, 0.0f, offsets, indices, capacity, total, stream);
+}
+
+arborx_status arborx_query_ray_ordered_intersect_begin(arborx_tree t, const float *rays, int64_t m,
+                                                      int64_t *offsets, int64_t *total, arborx_plan *plan,
+                                                      void *stream)
+{
+    return csr_begin(t, Pred::Ray, rays, m, 0.0f, offsets, total, plan, stream, VALUES_ORDERED);
+}
+
+arborx_status arborx_query_ray_ordered_intersect(arborx_tree t, const float *rays, int64_t m, int64_t *offsets,
+                                                int32_t *indices, float *t_entry, int64_t capacity, int64_t *total,
+                                                void *stream)
+{
+    return csr_query(t, Pred::Ray, rays, m, 0.0f, offsets, indices, capacity, total, stream, VALUES_ORDERED,
+                     t_entry);
 }
 
 arborx_status arborx_query_ray_count(arborx_tree t, const float *rays, int64_t m, int32_t *counts, void *stream)

@@ -190,7 +190,11 @@ arborx_status chamfer_backward(const float *a, const int64_t *a_off, const float
                                float *grad_b, hipStream_t s);
 
 // ---- queries (query.hip) --------------------------------------------------
-enum class Pred { Sphere, Box };
+enum class Pred { Sphere, Box, Ray };
+// Per-match value kept by a CSR query: none; the walk's float (squared
+// distance, or a ray's entry parameter) with rows sorted by index; or that
+// float with rows sorted by (value, index) (a ray's hits in the order met).
+enum ValueMode { VALUES_NONE = 0, VALUES_BY_INDEX = 1, VALUES_ORDERED = 2 };
 arborx_status query_order(const TreeDev &t, const float *queries, int64_t m, Pred pred, int op, uint32_t **perm,
                           Temps &tmp, hipStream_t s);
 // Matches of a CSR count walk beyond a query's stash row, kept in chained
@@ -222,14 +226,18 @@ arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, i
 // Fill pass: stash rows are copied, listed longer rows are copied from the
 // stash and their overflow chunks, and the rest (huge rows, rows whose chunks
 // did not fit) are walked again.
+// With dist, each match's value is written beside its index, rows sorted as
+// `mode` says (VALUES_BY_INDEX or VALUES_ORDERED).
 arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
                            const int32_t *counts, const int32_t *stash, const float *stash_d2,
                            const OverflowPool &ovf, const int64_t *offsets, const int32_t *big_list, int64_t nbig,
-                           const int32_t *huge_list, int64_t nhuge, int32_t *indices, float *dist, hipStream_t s);
-// Row sorts; with dist, each distance moves with its index.
-arborx_status sort_big_rows(const int64_t *offsets, int32_t *indices, float *dist, const int32_t *big_list,
+                           const int32_t *huge_list, int64_t nhuge, int32_t *indices, float *dist, int mode,
+                           hipStream_t s);
+// Row sorts; with dist, each value moves with its index, rows sorted by
+// index or (mode VALUES_ORDERED) by (value, index).
+arborx_status sort_big_rows(const int64_t *offsets, int32_t *indices, float *dist, int mode, const int32_t *big_list,
                             int64_t nbig, hipStream_t s);
-arborx_status sort_huge_rows(int64_t n_values, const int64_t *offsets, int32_t *indices, float *dist,
+arborx_status sort_huge_rows(int64_t n_values, const int64_t *offsets, int32_t *indices, float *dist, int mode,
                              const int32_t *huge_list, int64_t h, Temps &tmp, hipStream_t s);
 arborx_status spatial_reduce(const TreeDev &t, const float *queries, int64_t m, float radius, int op,
                              int scale_bits, const uint32_t *perm, int32_t *counts, int64_t *sums, hipStream_t s);

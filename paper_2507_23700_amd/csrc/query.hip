@@ -229,19 +229,33 @@ __global__ __attribute__((amdgpu_waves_per_eu(NQ == 2 && D <= 3 && !OUT ? 6 : 1)
         }
 }
 
-// An index and its float32 squared distance (>= 0) as one word that orders
-// like the index: rows sort by index and the distance travels along.
-__device__ __forceinline__ uint64_t pack_match(int idx, float d2)
+// An index and its float value (>= 0: a squared distance or a ray's entry
+// parameter) as one word.  MODE 1 orders the word like the index, so rows
+// sort by index with the value travelling along; MODE 2 orders it by (value,
+// index): the bits of a float >= 0 order like the float.
+template <int MODE>
+__device__ __forceinline__ uint64_t pack_match(int idx, float v)
 {
-    return ((uint64_t)(uint32_t)idx << 32) | __float_as_uint(d2);
+    return MODE == 2 ? (((uint64_t)__float_as_uint(v) << 32) | (uint32_t)idx)
+                     : (((uint64_t)(uint32_t)idx << 32) | __float_as_uint(v));
+}
+template <int MODE>
+__device__ __forceinline__ int match_index(uint64_t w)
+{
+    return (int)(uint32_t)(MODE == 2 ? w : w >> 32);
+}
+template <int MODE>
+__device__ __forceinline__ float match_value(uint64_t w)
+{
+    return __uint_as_float((uint32_t)(MODE == 2 ? w >> 32 : w));
 }
 
 // Rows of at most R matches: sort the stash row in registers (a bitonic
 // network, empty slots padded to sort last) and copy it to the CSR slot.
-// Thread i handles query i, so consecutive lanes fill adjacent rows.  With
-// dist, the stashed distances are sorted along with the indices (packed with
-// them into one word) and copied to the same slots of dist.
-template <int R, bool OUT>
+// Thread i handles query i, so consecutive lanes fill adjacent rows.  With a
+// value mode, the stashed values are sorted along with the indices (packed
+// with them into one word) and copied to the same slots of dist.
+template <int R, int MODE>
 __global__ void k_copy_stash(const int32_t *__restrict__ stash, const float *__restrict__ stash_d2, int64_t m,
                              const int32_t *__restrict__ counts, const int64_t *__restrict__ offsets,
                              int32_t *__restrict__ indices, float *__restrict__ dist)
@@ -263,16 +277,16 @@ __global__ void k_copy_stash(const int32_t *__restrict__ stash, const float *__r
         v[4 * k + 2] = x.z;
         v[4 * k + 3] = x.w;
     }
-    if constexpr (OUT) {
+    if constexpr (MODE != 0) {
         const float4 *drow = reinterpret_cast<const float4 *>(stash_d2 + qi * R);
         uint64_t w[R];
 #pragma unroll
         for (int k = 0; k < R / 4; ++k) {
             const float4 x = drow[k];
-            w[4 * k] = pack_match(v[4 * k], x.x);
-            w[4 * k + 1] = pack_match(v[4 * k + 1], x.y);
-            w[4 * k + 2] = pack_match(v[4 * k + 2], x.z);
-            w[4 * k + 3] = pack_match(v[4 * k + 3], x.w);
+            w[4 * k] = pack_match<MODE>(v[4 * k], x.x);
+            w[4 * k + 1] = pack_match<MODE>(v[4 * k + 1], x.y);
+            w[4 * k + 2] = pack_match<MODE>(v[4 * k + 2], x.z);
+            w[4 * k + 3] = pack_match<MODE>(v[4 * k + 3], x.w);
         }
 #pragma unroll
         for (int k = 0; k < R; ++k)
@@ -281,8 +295,8 @@ __global__ void k_copy_stash(const int32_t *__restrict__ stash, const float *__r
 #pragma unroll
         for (int k = 0; k < R; ++k)
             if (k < c) {
-                indices[o + k] = (int32_t)(w[k] >> 32);
-                dist[o + k] = __uint_as_float((uint32_t)w[k]);
+                indices[o + k] = match_index<MODE>(w[k]);
+                dist[o + k] = match_value<MODE>(w[k]);
             }
     } else {
 #pragma unroll
@@ -381,8 +395,8 @@ __global__ void k_spatial_fill_rows(const Node<D> *__restrict__ nodes, const QNo
 
 // Listed rows of at most one wavefront (kWave entries): one wavefront per row,
 // a bitonic network across the lanes with shuffles, padding sorting last.
-// With dist, each index travels with its distance (packed into one word).
-template <bool OUT>
+// With a value mode, each index travels with its value (packed into one word).
+template <int MODE>
 __global__ __launch_bounds__(256) void k_sort_rows_wave(const int64_t *__restrict__ offsets,
                                                         int32_t *__restrict__ indices, float *__restrict__ dist,
                                                         const int32_t *__restrict__ list, int64_t nb)
@@ -395,34 +409,40 @@ __global__ __launch_bounds__(256) void k_sort_rows_wave(const int64_t *__restric
         const int64_t len = offsets[row + 1] - o;
         if (len > kWave)
             continue;
-        uint64_t v = OUT ? ~0ull : (0xffffffffull << 32);
+        uint64_t v = MODE ? ~0ull : (0xffffffffull << 32);
         if (lane < len)
-            v = OUT ? pack_match(indices[o + lane], dist[o + lane]) : ((uint64_t)(uint32_t)indices[o + lane] << 32);
+            v = MODE ? pack_match<MODE>(indices[o + lane], dist[o + lane])
+                     : ((uint64_t)(uint32_t)indices[o + lane] << 32);
 #pragma unroll
         for (int k = 2; k <= kWave; k <<= 1)
 #pragma unroll
             for (int j = k >> 1; j > 0; j >>= 1) {
                 const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), j, kWave);
-                const uint32_t lo = OUT ? __shfl_xor((uint32_t)v, j, kWave) : 0u;
+                const uint32_t lo = MODE ? __shfl_xor((uint32_t)v, j, kWave) : 0u;
                 const uint64_t other = ((uint64_t)hi << 32) | lo;
                 const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
                 v = keep_min ? (v < other ? v : other) : (v < other ? other : v);
             }
         if (lane < len) {
-            indices[o + lane] = (int32_t)(v >> 32);
-            if (OUT)
-                dist[o + lane] = __uint_as_float((uint32_t)v);
+            if (MODE) {
+                indices[o + lane] = match_index<MODE>(v);
+                dist[o + lane] = match_value<MODE>(v);
+            } else {
+                indices[o + lane] = (int32_t)(v >> 32);
+            }
         }
     }
 }
 
 // One workgroup per listed row of kWave < len <= kRowSortBlock entries:
-// bitonic sort in LDS (with dist: the distances move with their indices).
-template <bool OUT>
+// bitonic sort in LDS (with a value mode the values move with their indices;
+// mode 2 sorts by (value, index)).
+template <int MODE>
 __global__ __launch_bounds__(256) void k_sort_rows(const int64_t *__restrict__ offsets, int32_t *__restrict__ indices,
                                                    float *__restrict__ dist, const int32_t *__restrict__ list,
                                                    int64_t nb)
 {
+    constexpr bool OUT = MODE != 0;
     __shared__ int32_t s[kRowSortBlock];
     __shared__ float sd[OUT ? kRowSortBlock : 1];
     for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
@@ -438,7 +458,7 @@ __global__ __launch_bounds__(256) void k_sort_rows(const int64_t *__restrict__ o
         for (int i = threadIdx.x; i < p2; i += blockDim.x) {
             s[i] = i < len ? indices[o + i] : INT32_MAX;
             if (OUT)
-                sd[i] = i < len ? dist[o + i] : 0.0f;
+                sd[i] = i < len ? dist[o + i] : INFINITY;
         }
         __syncthreads();
         for (int kk = 2; kk <= p2; kk <<= 1) {
@@ -448,7 +468,12 @@ __global__ __launch_bounds__(256) void k_sort_rows(const int64_t *__restrict__ o
                     if (ixj > i) {
                         const int a = s[i], c = s[ixj];
                         const bool up = (i & kk) == 0;
-                        if ((a > c) == up) {
+                        bool greater = a > c;
+                        if (MODE == 2) {
+                            const float va = sd[i], vc = sd[ixj];
+                            greater = va > vc || (va == vc && a > c);
+                        }
+                        if (greater == up) {
                             s[i] = c;
                             s[ixj] = a;
                             if (OUT) {
@@ -508,6 +533,36 @@ __global__ void k_huge_scatter(const uint64_t *__restrict__ keys, const uint32_t
             indices[at] = (int32_t)(key & lowmask);
             if (dist)
                 dist[at] = __uint_as_float(vals[p]);
+        }
+    }
+}
+
+// Mode 2 for huge rows: after the sort by (row rank, index), re-key every
+// entry as (row rank, value bits) with its index as payload; a stable sort by
+// that key then orders each row by (value, index).
+__global__ void k_huge_by_value(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals, int64_t total,
+                                int ib, uint64_t *__restrict__ keys2, uint32_t *__restrict__ vals2)
+{
+    const uint64_t lowmask = (1ull << ib) - 1ull;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = keys[p];
+        keys2[p] = ((key >> ib) << 32) | vals[p];
+        vals2[p] = (uint32_t)(key & lowmask);
+    }
+}
+
+__global__ void k_huge_scatter_by_value(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+                                        int64_t total, int64_t h, const int64_t *__restrict__ offsets,
+                                        const int32_t *__restrict__ list, const int64_t *__restrict__ starts,
+                                        int32_t *__restrict__ indices, float *__restrict__ dist)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = keys[p];
+        const int64_t b = (int64_t)(key >> 32);
+        if (b < h) {
+            const int64_t at = offsets[list[b]] + (p - starts[b]);
+            indices[at] = (int32_t)vals[p];
+            dist[at] = __uint_as_float((uint32_t)key);
         }
     }
 }
@@ -721,7 +776,9 @@ __global__ void k_knn_empty(int64_t total, float *d2, int32_t *idx)
 // only affects speed: queries in one cell of the grid are treated alike.
 inline int order_bits(int order) { return order == 2 ? 16 : 24; }
 
-template <int D, bool BOXQ>
+// BOXQ: queries are [m][2][D] rows; the code is of the box centre, or (RAY)
+// of the ray's origin row.
+template <int D, bool BOXQ, bool RAY = false>
 __global__ void k_query_codes(const float *__restrict__ q, int64_t m, const TreeHeader *__restrict__ hdr,
                               uint32_t *__restrict__ codes, uint32_t *__restrict__ ids, int bits)
 {
@@ -736,7 +793,9 @@ __global__ void k_query_codes(const float *__restrict__ q, int64_t m, const Tree
         uint32_t c[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            const float x = BOXQ ? q[i * 2 * D + d] + 0.5f * (q[i * 2 * D + D + d] - q[i * 2 * D + d]) : q[i * D + d];
+            const float x = RAY ? q[i * 2 * D + d]
+                                : (BOXQ ? q[i * 2 * D + d] + 0.5f * (q[i * 2 * D + D + d] - q[i * 2 * D + d])
+                                        : q[i * D + d]);
             c[d] = quantise(x, lo[d], inv[d], bits);
         }
         codes[i] = (uint32_t)interleave<D>(c, bits);
@@ -834,6 +893,28 @@ arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m,
             AX_COUNT_O(Sphere<D>, 4, true);
         else
             AX_COUNT_O(Sphere<D>, 0, true);
+    } else if (pred == Pred::Ray && out) {  // the value slot carries the entry parameter
+        if (sched == 1)
+            AX_COUNT_O(RayPred<D>, 1, true);
+        else if (sched == 2)
+            AX_COUNT_O(RayPred<D>, 2, true);
+        else if (sched == 3)
+            AX_COUNT_O(RayPred<D>, 3, true);
+        else if (sched == 4)
+            AX_COUNT_O(RayPred<D>, 4, true);
+        else
+            AX_COUNT_O(RayPred<D>, 0, true);
+    } else if (pred == Pred::Ray) {
+        if (sched == 1)
+            AX_COUNT(RayPred<D>, 1);
+        else if (sched == 2)
+            AX_COUNT(RayPred<D>, 2);
+        else if (sched == 3)
+            AX_COUNT(RayPred<D>, 3);
+        else if (sched == 4)
+            AX_COUNT(RayPred<D>, 4);
+        else
+            AX_COUNT(RayPred<D>, 0);
     } else if (pred == Pred::Sphere) {
         if (sched == 1)
             AX_COUNT(Sphere<D>, 1);
@@ -886,6 +967,13 @@ arborx_status fill_rows_impl(const TreeDev &t, Pred pred, const float *q, int64_
             AX_FILL(Sphere<D>, 2);
         else
             AX_FILL(Sphere<D>, 0);
+    } else if (pred == Pred::Ray) {
+        if (fmt == 1)
+            AX_FILL(RayPred<D>, 1);
+        else if (fmt == 2)
+            AX_FILL(RayPred<D>, 2);
+        else
+            AX_FILL(RayPred<D>, 0);
     } else {
         if (fmt == 1)
             AX_FILL(BoxQuery<D>, 1);
@@ -1017,6 +1105,8 @@ arborx_status order_into(const TreeDev &t, const float *q, int64_t m, Pred pred,
     ProfScope ps("order", s);
     if (pred == Pred::Sphere)
         k_query_codes<D, false><<<grid_for(m, 256, 65536), 256, 0, s>>>(q, m, t.hdr, codes, ids, bits);
+    else if (pred == Pred::Ray)
+        k_query_codes<D, true, true><<<grid_for(m, 256, 65536), 256, 0, s>>>(q, m, t.hdr, codes, ids, bits);
     else
         k_query_codes<D, true><<<grid_for(m, 256, 65536), 256, 0, s>>>(q, m, t.hdr, codes, ids, bits);
     bool alt = false;
@@ -1088,7 +1178,8 @@ int64_t overflow_pool_ints(int64_t m, int dim)
 arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
                            const int32_t *counts, const int32_t *stash, const float *stash_d2,
                            const OverflowPool &ovf, const int64_t *offsets, const int32_t *big_list, int64_t nbig,
-                           const int32_t *huge_list, int64_t nhuge, int32_t *indices, float *dist, hipStream_t s)
+                           const int32_t *huge_list, int64_t nhuge, int32_t *indices, float *dist, int mode,
+                           hipStream_t s)
 {
     if (m == 0 || t.n == 0)
         return ARBORX_OK;
@@ -1098,17 +1189,24 @@ arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, in
     {
         ProfScope ps("copy_stash", s);
         const unsigned g = grid_for(m, 256, INT32_MAX);
+        const int md = dist ? (mode == VALUES_ORDERED ? 2 : 1) : 0;
+#define AX_CS(R, M) k_copy_stash<R, M><<<g, 256, 0, s>>>(stash, stash_d2, m, counts, offsets, indices, dist)
         if (stash_regs(t.dim) == 32) {
-            if (dist)
-                k_copy_stash<32, true><<<g, 256, 0, s>>>(stash, stash_d2, m, counts, offsets, indices, dist);
+            if (md == 2)
+                AX_CS(32, 2);
+            else if (md == 1)
+                AX_CS(32, 1);
             else
-                k_copy_stash<32, false><<<g, 256, 0, s>>>(stash, stash_d2, m, counts, offsets, indices, dist);
+                AX_CS(32, 0);
         } else {
-            if (dist)
-                k_copy_stash<16, true><<<g, 256, 0, s>>>(stash, stash_d2, m, counts, offsets, indices, dist);
+            if (md == 2)
+                AX_CS(16, 2);
+            else if (md == 1)
+                AX_CS(16, 1);
             else
-                k_copy_stash<16, false><<<g, 256, 0, s>>>(stash, stash_d2, m, counts, offsets, indices, dist);
+                AX_CS(16, 0);
         }
+#undef AX_CS
         AX_HIP(hipGetLastError());
     }
     if (nbig > 0) {
@@ -1140,25 +1238,28 @@ arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, in
     }
 }
 
-arborx_status sort_big_rows(const int64_t *offsets, int32_t *indices, float *dist, const int32_t *big_list,
+arborx_status sort_big_rows(const int64_t *offsets, int32_t *indices, float *dist, int mode, const int32_t *big_list,
                             int64_t nbig, hipStream_t s)
 {
     if (nbig <= 0)
         return ARBORX_OK;
     ProfScope ps("sort_rows", s);
     const unsigned gw = grid_for(nbig, 256 / kWave, 16384), gb = (unsigned)(nbig < 8192 ? nbig : 8192);
-    if (dist) {
-        k_sort_rows_wave<true><<<gw, 256, 0, s>>>(offsets, indices, dist, big_list, nbig);
-        k_sort_rows<true><<<gb, 256, 0, s>>>(offsets, indices, dist, big_list, nbig);
+    if (dist && mode == VALUES_ORDERED) {
+        k_sort_rows_wave<2><<<gw, 256, 0, s>>>(offsets, indices, dist, big_list, nbig);
+        k_sort_rows<2><<<gb, 256, 0, s>>>(offsets, indices, dist, big_list, nbig);
+    } else if (dist) {
+        k_sort_rows_wave<1><<<gw, 256, 0, s>>>(offsets, indices, dist, big_list, nbig);
+        k_sort_rows<1><<<gb, 256, 0, s>>>(offsets, indices, dist, big_list, nbig);
     } else {
-        k_sort_rows_wave<false><<<gw, 256, 0, s>>>(offsets, indices, dist, big_list, nbig);
-        k_sort_rows<false><<<gb, 256, 0, s>>>(offsets, indices, dist, big_list, nbig);
+        k_sort_rows_wave<0><<<gw, 256, 0, s>>>(offsets, indices, dist, big_list, nbig);
+        k_sort_rows<0><<<gb, 256, 0, s>>>(offsets, indices, dist, big_list, nbig);
     }
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
 
-arborx_status sort_huge_rows(int64_t n_values, const int64_t *offsets, int32_t *indices, float *dist,
+arborx_status sort_huge_rows(int64_t n_values, const int64_t *offsets, int32_t *indices, float *dist, int mode,
                              const int32_t *huge_list, int64_t h, Temps &tmp, hipStream_t s)
 {
     if (h <= 0)
@@ -1180,7 +1281,7 @@ arborx_status sort_huge_rows(int64_t n_values, const int64_t *offsets, int32_t *
         ++ib;
     while ((1ll << hb) < h)
         ++hb;
-    if (ib + hb > 64)
+    if (ib + hb > 64 || (mode == VALUES_ORDERED && hb > 32))
         return fail(ARBORX_E_UNSUPPORTED, "too many long rows to sort");
     uint64_t *k1, *k2;
     uint32_t *v1, *v2;
@@ -1193,8 +1294,17 @@ arborx_status sort_huge_rows(int64_t n_values, const int64_t *offsets, int32_t *
                                                                   v1);
     bool alt = false;
     AX_HIP(radix_sort_pairs<uint64_t>(k1, v1, k2, v2, total, 0, ib + hb, rws, s, &alt));
-    k_huge_scatter<<<grid_for(total, 256, 65536), 256, 0, s>>>(alt ? k2 : k1, alt ? v2 : v1, total, ib, h, offsets,
-                                                              huge_list, starts, indices, dist);
+    uint64_t *ks = alt ? k2 : k1, *ko = alt ? k1 : k2;
+    uint32_t *vs = alt ? v2 : v1, *vo = alt ? v1 : v2;
+    if (mode == VALUES_ORDERED && dist) {
+        k_huge_by_value<<<grid_for(total, 256, 65536), 256, 0, s>>>(ks, vs, total, ib, ko, vo);
+        AX_HIP(radix_sort_pairs<uint64_t>(ko, vo, ks, vs, total, 0, 32 + hb, rws, s, &alt));
+        k_huge_scatter_by_value<<<grid_for(total, 256, 65536), 256, 0, s>>>(alt ? ks : ko, alt ? vs : vo, total, h,
+                                                                           offsets, huge_list, starts, indices, dist);
+    } else {
+        k_huge_scatter<<<grid_for(total, 256, 65536), 256, 0, s>>>(ks, vs, total, ib, h, offsets, huge_list, starts,
+                                                                  indices, dist);
+    }
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }

@@ -15,39 +15,6 @@
 namespace ax {
 namespace {
 
-template <int D>
-struct RayPred {
-    float o[D], dir[D];
-    __device__ __forceinline__ void load(const float *rays, int64_t i)
-    {
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            o[d] = rays[i * 2 * D + d];
-            dir[d] = rays[i * 2 * D + D + d];
-        }
-    }
-    // Slabs taken in dimension order from tmin = 0, tmax = +inf; t = entry parameter.
-    __device__ __forceinline__ bool hit(const float *lo, const float *hi, float &t) const
-    {
-        float tmin = 0.0f, tmax = INFINITY;
-        bool inside = true;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            if (dir[k] == 0.0f) {
-                inside = inside && !(o[k] < lo[k] || o[k] > hi[k]);
-                continue;
-            }
-            const float t1 = (lo[k] - o[k]) / dir[k];
-            const float t2 = (hi[k] - o[k]) / dir[k];
-            const float tn = t1 < t2 ? t1 : t2, tf = t1 < t2 ? t2 : t1;
-            tmin = tn > tmin ? tn : tmin;
-            tmax = tf < tmax ? tf : tmax;
-        }
-        t = tmin;
-        return inside && !(tmin > tmax);
-    }
-};
-
 __device__ __forceinline__ int ray_nodes(const TreeHeader *hdr) { return hdr->n > 1 ? hdr->n - 1 : 1; }
 
 template <int D>
@@ -59,7 +26,7 @@ __global__ void k_ray_count(const Node<D> *__restrict__ nodes, const TreeHeader 
     if (i >= m)
         return;
     RayPred<D> p;
-    p.load(rays, i);
+    p.load(rays, i, 0.0f);
     int spill[kSpill];
     ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap, spill);
     int c = 0;
@@ -79,7 +46,7 @@ __global__ void k_ray_nearest(const Node<D> *__restrict__ nodes, const TreeHeade
     if (i >= m)
         return;
     RayPred<D> p;
-    p.load(rays, i);
+    p.load(rays, i, 0.0f);
     KnnEntry spill[kSpill];
     ShortStack<KnnEntry> st(reinterpret_cast<KnnEntry *>(s_stack) + threadIdx.x, blockDim.x, stack_cap, spill);
     TopK<K> best;

@@ -123,6 +123,53 @@ struct BoxQuery {
     }
 };
 
+// A ray o + t*dir, t >= 0 (Section 2.5).  It meets a closed box when its slab
+// intervals overlap: slabs taken in dimension order from tmin = 0, tmax =
+// +inf, t1 = (lo - o)/dir and t2 = (hi - o)/dir with correctly rounded
+// division, a zero direction component requiring lo <= o <= hi.  The entry
+// parameter tmin is reported in the distance slot.  Subtraction and division
+// are monotone, so a box inside another is met no earlier: pruning by a
+// parent's box is exact.
+template <int D>
+struct RayPred {
+    float o[D], dir[D];
+    __device__ __forceinline__ void load(const float *rays, int64_t i, float)
+    {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            o[d] = rays[i * 2 * D + d];
+            dir[d] = rays[i * 2 * D + D + d];
+        }
+    }
+    __device__ __forceinline__ void dead()  // origin at +inf, no direction: outside every finite box
+    {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            o[d] = INFINITY;
+            dir[d] = 0.0f;
+        }
+    }
+    __device__ __forceinline__ bool hit(const float *lo, const float *hi, float &t) const
+    {
+        float tmin = 0.0f, tmax = INFINITY;
+        bool inside = true;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            if (dir[k] == 0.0f) {
+                inside = inside && !(o[k] < lo[k] || o[k] > hi[k]);
+                continue;
+            }
+            const float t1 = (lo[k] - o[k]) / dir[k];
+            const float t2 = (hi[k] - o[k]) / dir[k];
+            const float tn = t1 < t2 ? t1 : t2, tf = t1 < t2 ? t2 : t1;
+            tmin = tn > tmin ? tn : tmin;
+            tmax = tf < tmax ? tf : tmax;
+        }
+        t = tmin;
+        return inside && !(tmin > tmax);
+    }
+};
+
 // Exact test of the sorted leaf record `pos` (the value's own box) against
 // the predicate, calling f(index, d2) on a match.
 template <int D, class P, class F>
