@@ -293,11 +293,29 @@ def forest_bench(reps=3):
     t_p = timed(plain, reps)
     same = all(torch.equal(a, b) for a, b in zip(out["batched"], out["plain"]))
     log(f"forest: batched {t_b:.1f} ms, per-tree loop {t_p:.1f} ms, identical={same}")
+    # the same batched work captured once in a hipGraph: rebuild in place, reduce, kNN; nothing allocates
+    fo = ax.arborx_forest_create(int(toff[-1]), len(toff) - 1, 3)
+    off_d = torch.from_numpy(toff.astype("int64")).cuda()
+    ax.arborx_forest_reserve(fo, m)
+    torch.cuda.synchronize()
+    gs = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(gs):
+        with torch.cuda.graph(graph, stream=gs):
+            ax.arborx_forest_rebuild(fo, v, off_d, stream=gs)
+            gc_, gsum = ax.arborx_forest_query_reduce(fo, q, dbo, dbt, dbr, ax.COUNT_SUMDIST, stream=gs)
+            gd2, gix = ax.arborx_forest_query_knn(fo, q, dbo, dbt, k, stream=gs)
+    graph.replay()
+    torch.cuda.synchronize()
+    t_g = timed(graph.replay, reps)
+    same_g = all(torch.equal(a, b) for a, b in zip((gc_, gsum, gd2, gix), out["batched"]))
+    log(f"forest: one hipGraph replay {t_g:.1f} ms, identical={same_g}")
     res = {"workload": "forest_t64_b4096", "trees": len(toff) - 1, "points": int(toff[-1]), "batches": len(bt),
            "queries": int(m), "ops": f"build + COUNT_SUMDIST + kNN k={k}", "batched_ms": t_b, "plain_ms": t_p,
            "speedup": t_p / t_b, "identical": bool(same),
-           "batched_queries_per_s": 2 * m / (t_b * 1e-3)}
-    del out
+           "batched_queries_per_s": 2 * m / (t_b * 1e-3),
+           "graph_ms": t_g, "graph_speedup": t_p / t_g, "graph_identical": bool(same_g)}
+    del out, graph, gc_, gsum, gd2, gix, fo
     torch.cuda.empty_cache()
     return res
 

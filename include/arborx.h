@@ -137,7 +137,8 @@ arborx_status arborx_get_tuning_op(int32_t op, arborx_tuning *tuning);
  * every candidate (block size, short-stack depth, thread or wavefront-packet
  * schedule, query ordering, kNN seeding) runs on `queries`; all must produce
  * identical outputs (checked with a device hash, else ARBORX_E_DEVICE); the
- * fastest by event timing on `stream` becomes the tuning of `op`.  radius is
+ * fastest by event timing on `stream` (median of three runs) becomes the
+ * tuning of `op`, unless the tuning in force is within 3% of it.  radius is
  * used for ARBORX_OP_SPATIAL / ARBORX_OP_REDUCE, k for ARBORX_OP_KNN.  If the
  * environment variable ARBORX_TUNING_CACHE names a file, a choice recorded
  * there for the same operation, dimension, kind, k and size classes is reused
@@ -146,6 +147,19 @@ arborx_status arborx_get_tuning_op(int32_t op, arborx_tuning *tuning);
  */
 arborx_status arborx_autotune(arborx_tree tree, int32_t op, const float *queries, int64_t m, float radius, int32_t k,
                               arborx_tuning *best, double *best_ms, void *stream);
+
+/*
+ * The same for forest queries (op ARBORX_OP_REDUCE, timed with COUNT_SUMDIST,
+ * or ARBORX_OP_KNN with k): the candidates are what a forest walk honours
+ * (stack depth, queries per thread of the reduction, node formats the forest
+ * holds, kNN seeding); every candidate must give the same outputs; the one in
+ * force is kept unless another is at least 3% faster (median of three timed
+ * runs).  Arguments as arborx_forest_query_reduce / _knn.  Synchronises.
+ */
+arborx_status arborx_autotune_forest(arborx_forest forest, int32_t op, const float *queries, int64_t m,
+                                     const int64_t *batch_offsets, const int32_t *batch_tree,
+                                     const float *batch_radius, int32_t B, int32_t k, arborx_tuning *best,
+                                     double *best_ms, void *stream);
 
 /*
  * Build a BVH over n values (Section 2.1, index constructor; Section 2.6: 64-bit
@@ -422,6 +436,32 @@ arborx_status arborx_query_ray_nearest(arborx_tree tree, const float *rays, int6
 arborx_status arborx_forest_build(const float *values, const int64_t *tree_offsets, int32_t T, int32_t dim,
                                   int32_t kind, void *stream, arborx_forest *out);
 arborx_status arborx_forest_destroy(arborx_forest forest);
+/*
+ * A forest that can be rebuilt inside a captured graph (Section 2.1: an index
+ * built from arrays of values; here many trees, refilled in place).
+ * arborx_forest_create makes every device allocation for n values in T trees
+ * of dimension dim (the structure and the build's workspace) and builds
+ * nothing; its trees are empty until the first rebuild.
+ * arborx_forest_rebuild builds the trees from device arrays:
+ *   values        [n][dim] points or [n][2][dim] boxes (device)
+ *   tree_offsets  [T+1] int64 (DEVICE): tree t holds values
+ *                 [tree_offsets[t], tree_offsets[t+1]); expected nondecreasing
+ *                 from 0 to n.  Not read on the host: an array that is not
+ *                 is made so on the device (offsets clamped to [0, n], each at
+ *                 least the one before, the last n), never read out of range.
+ * The rebuild launches kernels only: no allocation, no host read, no copy, no
+ * synchronisation, so it can be captured in a hipGraph together with forest
+ * queries (after arborx_forest_reserve) and replayed with new values, offsets
+ * and queries of the same sizes; the result equals arborx_forest_build's.
+ * While `stream` is being captured the rebuild neither waits for earlier uses
+ * of the forest nor records its completion: the caller orders them.
+ * arborx_forest_build is create + a copy of host offsets + rebuild.
+ */
+arborx_status arborx_forest_create(int64_t n, int32_t T, int32_t dim, int32_t kind, void *stream,
+                                   arborx_forest *out);
+arborx_status arborx_forest_rebuild(arborx_forest forest, const float *values, const int64_t *tree_offsets,
+                                    void *stream);
+
 
 /* Forest metadata [host]: T, total values, dim, and per-tree root and height
  * arrays of T entries (roots/heights may be NULL; -1 root = empty tree). */

@@ -150,6 +150,20 @@ def arborx_autotune(tree, op, queries, radius=0.0, k=1, stream=None):
     return _tuning_dict(best), ms.value
 
 
+def arborx_autotune_forest(forest, op, queries, batch_offsets, batch_tree, batch_radius=None, k=1, stream=None):
+    """Tune the forest queries of `op` (OP_REDUCE or OP_KNN) on these batches: (tuning dict, ms)."""
+    torch = _torch()
+    q = _dev(queries, torch.float32, "queries")
+    bo = _dev(batch_offsets, torch.int64, "batch_offsets")
+    bt = _dev(batch_tree, torch.int32, "batch_tree")
+    br = _dev(batch_radius, torch.float32, "batch_radius") if batch_radius is not None else None
+    best = _lib.Tuning()
+    ms = ctypes.c_double()
+    _check(_lib.lib().arborx_autotune_forest(forest.handle, op, _ptr(q), q.shape[0], _ptr(bo), _ptr(bt), _ptr(br),
+                                             bt.shape[0], k, ctypes.byref(best), ctypes.byref(ms), _stream(stream)))
+    return _tuning_dict(best), ms.value
+
+
 class Tree:
     """Owns an arborx_tree handle; destroyed with the object."""
 
@@ -487,6 +501,26 @@ def arborx_forest_build(values, tree_offsets, kind=POINTS, stream=None) -> Fores
     _check(_lib.lib().arborx_forest_build(_ptr(values), off.ctypes.data_as(ctypes.c_void_p), T, dim, kind,
                                           _stream(stream), ctypes.byref(h)))
     return Forest(h, T, n, dim, kind, values)
+
+
+def arborx_forest_create(n: int, T: int, dim: int, kind=POINTS, stream=None) -> Forest:
+    """Allocate a forest for n values in T trees of dimension dim, built later (and in a captured
+    graph, if wanted) by arborx_forest_rebuild."""
+    h = ctypes.c_void_p()
+    _check(_lib.lib().arborx_forest_create(int(n), int(T), int(dim), kind, _stream(stream), ctypes.byref(h)))
+    return Forest(h, int(T), int(n), int(dim), kind, None)
+
+
+def arborx_forest_rebuild(forest: Forest, values, tree_offsets, stream=None) -> None:
+    """Build the forest's trees from device values [n, dim] (or [n, 2, dim]) and device int64
+    tree_offsets [T+1]; kernels only, so it can be captured in a graph."""
+    torch = _torch()
+    values = _dev(values, torch.float32, "values")
+    off = _dev(tree_offsets, torch.int64, "tree_offsets")
+    if values.shape[0] != forest.n or values.shape[-1] != forest.dim or off.shape[0] != forest.T + 1:
+        raise ValueError(f"values must be [{forest.n}, ..., {forest.dim}] and tree_offsets [{forest.T + 1}]")
+    _check(_lib.lib().arborx_forest_rebuild(forest.handle, _ptr(values), _ptr(off), _stream(stream)))
+    forest._values = values
 
 
 def arborx_forest_info(forest: Forest) -> dict:

@@ -24,6 +24,7 @@ SIGNATURES = {
     "arborx_set_tuning_op": (I32, [I32, P]),
     "arborx_get_tuning_op": (I32, [I32, P]),
     "arborx_autotune": (I32, [P, I32, P, I64, F32, I32, P, P, P]),
+    "arborx_autotune_forest": (I32, [P, I32, P, I64, P, P, P, I32, I32, P, P, P]),
     "arborx_bvh_build": (I32, [P, I64, I32, I32, P, P]),
     "arborx_bvh_destroy": (I32, [P]),
     "arborx_bvh_info": (I32, [P, P, P, P, P, P]),
@@ -55,6 +56,8 @@ SIGNATURES = {
     "arborx_plan_destroy": (I32, [P]),
     "arborx_forest_build": (I32, [P, P, I32, I32, I32, P, P]),
     "arborx_forest_destroy": (I32, [P]),
+    "arborx_forest_create": (I32, [I64, I32, I32, I32, P, P]),
+    "arborx_forest_rebuild": (I32, [P, P, P, P]),
     "arborx_forest_info": (I32, [P, P, P, P, P, P]),
     "arborx_forest_reserve": (I32, [P, I64, P]),
     "arborx_forest_query_reduce": (I32, [P, P, I64, P, P, P, I32, I32, P, P, I32, P]),

@@ -991,17 +991,158 @@ __global__ __launch_bounds__(kBuildBlock) void forest_tile_morton(const float *_
     }
 }
 
-template <int D>
-arborx_status forest_build_impl(const float *values, const int64_t *seg_host, int T, int kind, ForestDev &f,
-                                hipStream_t s)
+// The segmentation the build uses, made valid whatever the caller's device
+// array holds: seg[0] = 0, seg[T] = n, and in between the running maximum of
+// the offsets clamped to [0, n], so segments never overlap or leave the value
+// array (a valid array is copied unchanged).  One workgroup: an inclusive
+// max-scan over chunks of its width.
+constexpr int kSegBlock = 1024;
+
+__global__ __launch_bounds__(kSegBlock) void forest_segments(const int64_t *__restrict__ off, int T, int64_t n,
+                                                             int64_t *__restrict__ seg)
 {
-    AX_HIP(hipGetLastError());
-    const int64_t n = seg_host[T];
+    __shared__ int64_t s_wmax[kSegBlock / kWave];
+    __shared__ int64_t s_carry;
+    if (threadIdx.x == 0)
+        s_carry = 0;
+    __syncthreads();
+    for (int base = 0; base <= T; base += kSegBlock) {
+        const int i = base + (int)threadIdx.x;
+        int64_t v = 0;
+        if (i == T)
+            v = n;
+        else if (i > 0 && i < T)
+            v = off[i] < 0 ? 0 : (off[i] > n ? n : off[i]);
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {  // inclusive max-scan across the wavefront
+            const int64_t u = __shfl_up(v, o, kWave);
+            if (lane_id() >= o)
+                v = u > v ? u : v;
+        }
+        if (lane_id() == kWave - 1)
+            s_wmax[wave_id()] = v;
+        __syncthreads();
+        int64_t before = s_carry;
+        for (int w = 0; w < wave_id(); ++w)
+            before = s_wmax[w] > before ? s_wmax[w] : before;
+        v = v > before ? v : before;
+        if (i <= T)
+            seg[i] = v;
+        __syncthreads();
+        if (threadIdx.x == kSegBlock - 1)
+            s_carry = v;
+        __syncthreads();
+    }
+}
+
+// Tiles that never straddle a tree, from the device segmentation: tree t
+// gets ceil(n_t / kForestTile) tiles, placed by an exclusive scan over the
+// trees; entries up to max_tiles past the last are empty tiles (no values).
+__global__ __launch_bounds__(kSegBlock) void forest_tiles(const int64_t *__restrict__ seg, int T, int max_tiles,
+                                                          int32_t *__restrict__ tile_tree,
+                                                          int32_t *__restrict__ tile_start,
+                                                          int32_t *__restrict__ tile_end)
+{
+    __shared__ int32_t s_wsum[kSegBlock / kWave];
+    __shared__ int32_t s_carry;
+    if (threadIdx.x == 0)
+        s_carry = 0;
+    __syncthreads();
+    for (int base = 0; base < T; base += kSegBlock) {
+        const int t = base + (int)threadIdx.x;
+        const int64_t a = t < T ? seg[t] : 0, e = t < T ? seg[t + 1] : 0;
+        const int cnt = (int)((e - a + kForestTile - 1) / kForestTile);
+        int incl = cnt;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int u = __shfl_up(incl, o, kWave);
+            if (lane_id() >= o)
+                incl += u;
+        }
+        if (lane_id() == kWave - 1)
+            s_wsum[wave_id()] = incl;
+        __syncthreads();
+        int before = s_carry;
+        for (int w = 0; w < wave_id(); ++w)
+            before += s_wsum[w];
+        const int first = before + incl - cnt;
+        for (int j = 0; j < cnt && first + j < max_tiles; ++j) {
+            const int64_t ts = a + (int64_t)j * kForestTile;
+            tile_tree[first + j] = t;
+            tile_start[first + j] = (int32_t)ts;
+            tile_end[first + j] = (int32_t)(e < ts + kForestTile ? e : ts + kForestTile);
+        }
+        __syncthreads();
+        if (threadIdx.x == kSegBlock - 1)
+            s_carry = before + incl;
+        __syncthreads();
+    }
+    for (int j = s_carry + (int)threadIdx.x; j < max_tiles; j += kSegBlock) {
+        tile_tree[j] = 0;
+        tile_start[j] = 0;
+        tile_end[j] = 0;
+    }
+}
+
+// The build workspace of a forest of n values in T trees, carved from one
+// block: tree bounds, tile tables, keys and ids (two each, for the sort),
+// arrival flags, the sort's tile histograms, the climb's escapes, and the
+// caller's offsets copied in by the build from host offsets.
+struct ForestBuildWs {
+    uint32_t *tmin, *tmax;
+    int32_t *tiles;
+    uint64_t *codes, *codes2;
+    uint32_t *ids, *ids2;
+    unsigned long long *flags;
+    uint8_t *rws;
+    void *esc;
+    int64_t *offs;
+};
+
+template <int D>
+size_t forest_build_ws(int64_t n, int T, int max_tiles, uint8_t *base, ForestBuildWs *w)
+{
+    const int64_t nn = n > 0 ? n : 1;
+    const int chunks = (int)((nn + chunk_leaves<D>() - 1) / chunk_leaves<D>());
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        uint8_t *p = base ? base + at : nullptr;
+        at += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    uint8_t *tmin = take(sizeof(uint32_t) * T * D), *tmax = take(sizeof(uint32_t) * T * D);
+    uint8_t *tiles = take(sizeof(int32_t) * 3 * (size_t)max_tiles);
+    uint8_t *codes = take(8 * nn), *codes2 = take(8 * nn), *ids = take(4 * nn), *ids2 = take(4 * nn);
+    uint8_t *flags = take(8 * nn), *rws = take(radix_workspace_bytes(nn));
+    uint8_t *esc = take(sizeof(Escape<D>) * 2 * (size_t)chunks), *offs = take(sizeof(int64_t) * (T + 1));
+    if (w) {
+        w->tmin = reinterpret_cast<uint32_t *>(tmin);
+        w->tmax = reinterpret_cast<uint32_t *>(tmax);
+        w->tiles = reinterpret_cast<int32_t *>(tiles);
+        w->codes = reinterpret_cast<uint64_t *>(codes);
+        w->codes2 = reinterpret_cast<uint64_t *>(codes2);
+        w->ids = reinterpret_cast<uint32_t *>(ids);
+        w->ids2 = reinterpret_cast<uint32_t *>(ids2);
+        w->flags = reinterpret_cast<unsigned long long *>(flags);
+        w->rws = rws;
+        w->esc = esc;
+        w->offs = reinterpret_cast<int64_t *>(offs);
+    }
+    return at;
+}
+
+inline int forest_max_tiles(int64_t n, int T) { return (int)(n / kForestTile) + T + 1; }
+
+// Every device allocation of a forest of n values in T trees: the structure
+// and the build workspace.
+template <int D>
+arborx_status forest_alloc_impl(int64_t n, int T, int kind, ForestDev &f, hipStream_t s)
+{
     f.n = n;
     f.dim = D;
     f.kind = kind;
     f.T = T;
-    f.seg_host.assign(seg_host, seg_host + T + 1);
+    f.max_tiles = forest_max_tiles(n, T);
     arborx_status st;
     if ((st = dalloc((void **)&f.hdrs, sizeof(TreeHeader) * T, s)) != ARBORX_OK ||
         (st = dalloc((void **)&f.seg, sizeof(int64_t) * (T + 1), s)) != ARBORX_OK ||
@@ -1009,47 +1150,35 @@ arborx_status forest_build_impl(const float *values, const int64_t *seg_host, in
         (st = dalloc((void **)&f.leaves, (size_t)(n > 0 ? n : 1) * leaf_floats(D, kind) * sizeof(float), s)) !=
             ARBORX_OK)
         return st;
-    const bool quantized = format_requested(1), wide = format_requested(2);
-    if (quantized && (st = dalloc(&f.qnodes, (size_t)(n > 0 ? n : 1) * sizeof(QNode<D>), s)) != ARBORX_OK)
+    if (format_requested(1) && (st = dalloc(&f.qnodes, (size_t)(n > 0 ? n : 1) * sizeof(QNode<D>), s)) != ARBORX_OK)
         return st;
-    if (wide && (st = dalloc(&f.wnodes, (size_t)(n > 0 ? n : 1) * sizeof(Node4<D>), s)) != ARBORX_OK)
+    if (format_requested(2) && (st = dalloc(&f.wnodes, (size_t)(n > 0 ? n : 1) * sizeof(Node4<D>), s)) != ARBORX_OK)
         return st;
-    AX_HIP(hipMemcpyAsync(f.seg, seg_host, sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, s));
-    // tiles that never straddle a tree
-    std::vector<int32_t> tt, ts, te;
-    for (int t = 0; t < T; ++t)
-        for (int64_t a = seg_host[t]; a < seg_host[t + 1]; a += kForestTile) {
-            tt.push_back(t);
-            ts.push_back((int32_t)a);
-            te.push_back((int32_t)std::min<int64_t>(a + kForestTile, seg_host[t + 1]));
-        }
-    const int tiles = (int)tt.size();
-    Temps tmp(s);
-    uint32_t *tmin, *tmax, *ids, *ids2;
-    int32_t *dtiles;
-    uint64_t *codes, *codes2;
-    unsigned long long *flags;
-    uint8_t *ws;
-    const int64_t nn = n > 0 ? n : 1;
-    if ((st = tmp.get(&tmin, (size_t)T * D)) != ARBORX_OK || (st = tmp.get(&tmax, (size_t)T * D)) != ARBORX_OK ||
-        (st = tmp.get(&dtiles, (size_t)3 * (tiles > 0 ? tiles : 1))) != ARBORX_OK ||
-        (st = tmp.get(&codes, nn)) != ARBORX_OK || (st = tmp.get(&codes2, nn)) != ARBORX_OK ||
-        (st = tmp.get(&ids, nn)) != ARBORX_OK || (st = tmp.get(&ids2, nn)) != ARBORX_OK ||
-        (st = tmp.get(&flags, nn)) != ARBORX_OK || (st = tmp.get(&ws, radix_workspace_bytes(nn))) != ARBORX_OK)
-        return st;
-    if (tiles > 0) {
-        AX_HIP(hipMemcpyAsync(dtiles, tt.data(), 4 * tiles, hipMemcpyHostToDevice, s));
-        AX_HIP(hipMemcpyAsync(dtiles + tiles, ts.data(), 4 * tiles, hipMemcpyHostToDevice, s));
-        AX_HIP(hipMemcpyAsync(dtiles + 2 * tiles, te.data(), 4 * tiles, hipMemcpyHostToDevice, s));
-    }
-    fill_kernel<uint32_t><<<grid_for((int64_t)T * D, 256), 256, 0, s>>>(tmin, (int64_t)T * D, 0xffffffffu);
-    fill_kernel<uint32_t><<<grid_for((int64_t)T * D, 256), 256, 0, s>>>(tmax, (int64_t)T * D, 0u);
+    f.bws_bytes = forest_build_ws<D>(n, T, f.max_tiles, nullptr, nullptr);
+    return dalloc(&f.bws, f.bws_bytes, s);
+}
+
+// Build the forest's trees in place from device-resident values and offsets:
+// kernels only (no allocation, no host read, no copy), so the call can be
+// captured in a graph and replayed with new contents of the same sizes.
+template <int D>
+arborx_status forest_rebuild_impl(const float *values, const int64_t *offs, ForestDev &f, hipStream_t s)
+{
+    AX_HIP(hipGetLastError());
+    const int64_t n = f.n;
+    const int T = f.T, kind = f.kind, tiles = f.max_tiles;
+    ForestBuildWs w;
+    forest_build_ws<D>(n, T, tiles, static_cast<uint8_t *>(f.bws), &w);
+    int32_t *dtiles = w.tiles;
+    forest_segments<<<1, kSegBlock, 0, s>>>(offs, T, n, f.seg);
+    forest_tiles<<<1, kSegBlock, 0, s>>>(f.seg, T, tiles, dtiles, dtiles + tiles, dtiles + 2 * tiles);
+    fill_kernel<uint32_t><<<grid_for((int64_t)T * D, 256), 256, 0, s>>>(w.tmin, (int64_t)T * D, 0xffffffffu);
+    fill_kernel<uint32_t><<<grid_for((int64_t)T * D, 256), 256, 0, s>>>(w.tmax, (int64_t)T * D, 0u);
     {
         ProfScope ps("build_bounds", s);
-        if (tiles > 0)
-            forest_tile_bounds<D><<<tiles, kBuildBlock, 0, s>>>(values, kind, dtiles, dtiles + tiles,
-                                                                dtiles + 2 * tiles, tmin, tmax);
-        forest_headers<D><<<grid_for(T, 256), 256, 0, s>>>(f.seg, T, tmin, tmax, f.hdrs);
+        forest_tile_bounds<D><<<tiles, kBuildBlock, 0, s>>>(values, kind, dtiles, dtiles + tiles, dtiles + 2 * tiles,
+                                                            w.tmin, w.tmax);
+        forest_headers<D><<<grid_for(T, 256), 256, 0, s>>>(f.seg, T, w.tmin, w.tmax, f.hdrs);
     }
     AX_HIP(hipGetLastError());
     if (n == 0)
@@ -1058,6 +1187,8 @@ arborx_status forest_build_impl(const float *values, const int64_t *seg_host, in
     while ((1 << tb) < T)
         ++tb;
     const int mbits = (63 - tb) / D * D;
+    uint64_t *codes = w.codes, *codes2 = w.codes2;
+    uint32_t *ids = w.ids, *ids2 = w.ids2;
     {
         ProfScope ps("build_morton", s);
         forest_tile_morton<D><<<tiles, kBuildBlock, 0, s>>>(values, kind, dtiles, dtiles + tiles, dtiles + 2 * tiles,
@@ -1066,7 +1197,7 @@ arborx_status forest_build_impl(const float *values, const int64_t *seg_host, in
     bool alt = false;
     {
         ProfScope ps("build_sort", s);
-        AX_HIP(radix_sort_pairs<uint64_t>(codes, ids, codes2, ids2, n, 0, mbits + tb, ws, s, &alt));
+        AX_HIP(radix_sort_pairs<uint64_t>(codes, ids, codes2, ids2, n, 0, mbits + tb, w.rws, s, &alt));
     }
     if (alt) {
         codes = codes2;
@@ -1074,24 +1205,35 @@ arborx_status forest_build_impl(const float *values, const int64_t *seg_host, in
     }
     constexpr int C = chunk_leaves<D>();
     const int chunks = (int)((n + C - 1) / C);
-    Escape<D> *esc;
-    if ((st = tmp.get(&esc, (size_t)2 * chunks)) != ARBORX_OK)
-        return st;
+    Escape<D> *esc = static_cast<Escape<D> *>(w.esc);
     Node<D> *nodes = static_cast<Node<D> *>(f.nodes);
     ProfScope ps("build_hierarchy", s);
-    hierarchy_chunk_kernel<D><<<chunks, C, 0, s>>>(codes, ids, values, kind, (int)n, nodes, f.leaves, flags,
-                                                             esc, f.seg, T, f.hdrs);
+    hierarchy_chunk_kernel<D><<<chunks, C, 0, s>>>(codes, ids, values, kind, (int)n, nodes, f.leaves, w.flags, esc,
+                                                   f.seg, T, f.hdrs);
     if (chunks > 1)
         hierarchy_top_kernel<D><<<grid_for(2 * chunks, kBuildBlock), kBuildBlock, 0, s>>>(
-            codes, (int)n, nodes, flags, esc, 2 * chunks, f.seg, T, f.hdrs);
-    if (quantized)
+            codes, (int)n, nodes, w.flags, esc, 2 * chunks, f.seg, T, f.hdrs);
+    if (f.qnodes)
         quantize_nodes<D><<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(nodes, (int)n, f.seg, T, (int)n, f.hdrs,
                                                                            static_cast<QNode<D> *>(f.qnodes));
-    if (wide)
+    if (f.wnodes)
         widen_nodes<D><<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(nodes, (int)n,
                                                                         static_cast<Node4<D> *>(f.wnodes));
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
+}
+
+template <int D>
+arborx_status forest_build_impl(const float *values, const int64_t *seg_host, int T, int kind, ForestDev &f,
+                                hipStream_t s)
+{
+    arborx_status st = forest_alloc_impl<D>(seg_host[T], T, kind, f, s);
+    if (st != ARBORX_OK)
+        return st;
+    ForestBuildWs w;
+    forest_build_ws<D>(f.n, T, f.max_tiles, static_cast<uint8_t *>(f.bws), &w);
+    AX_HIP(hipMemcpyAsync(w.offs, seg_host, sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, s));
+    return forest_rebuild_impl<D>(values, w.offs, f, s);
 }
 
 }  // namespace
@@ -1127,12 +1269,35 @@ void forest_release(ForestDev &f, hipStream_t s)
     dfree(f.hdrs, s);
     dfree(f.seg, s);
     dfree(f.ws, s);
+    dfree(f.bws, s);
+    f.bws = nullptr;
+    f.bws_bytes = 0;
     f.nodes = nullptr;
     f.leaves = nullptr;
     f.hdrs = nullptr;
     f.seg = nullptr;
     f.ws = nullptr;
     f.ws_bytes = 0;
+}
+
+arborx_status forest_alloc(int64_t n, int T, int dim, int kind, ForestDev &f, hipStream_t s)
+{
+    switch (dim) {
+    case 2: return forest_alloc_impl<2>(n, T, kind, f, s);
+    case 3: return forest_alloc_impl<3>(n, T, kind, f, s);
+    case 6: return forest_alloc_impl<6>(n, T, kind, f, s);
+    default: return fail(ARBORX_E_UNSUPPORTED, "dimension not compiled in");
+    }
+}
+
+arborx_status forest_rebuild(const float *values, const int64_t *tree_offsets, ForestDev &f, hipStream_t s)
+{
+    switch (f.dim) {
+    case 2: return forest_rebuild_impl<2>(values, tree_offsets, f, s);
+    case 3: return forest_rebuild_impl<3>(values, tree_offsets, f, s);
+    case 6: return forest_rebuild_impl<6>(values, tree_offsets, f, s);
+    default: return fail(ARBORX_E_UNSUPPORTED, "dimension not compiled in");
+    }
 }
 
 arborx_status build_forest(const float *values, const int64_t *seg_host, int T, int dim, int kind, ForestDev &f,

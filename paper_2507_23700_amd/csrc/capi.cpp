@@ -148,6 +148,11 @@ bool tree_has_format(arborx_tree tree, int format)
     return tree && (format == 0 || (format == 1 && tree->dev.qnodes) || (format == 2 && tree->dev.wnodes));
 }
 
+bool forest_has_format(arborx_forest forest, int format)
+{
+    return forest && (format == 0 || (format == 1 && forest->dev.qnodes) || (format == 2 && forest->dev.wnodes));
+}
+
 int walk_format(int op)
 {
     const Tuning &t = tuning(op);
@@ -1119,6 +1124,74 @@ arborx_status arborx_forest_build(const float *values, const int64_t *tree_offse
         return st;
     }
     *out = f;
+    return ARBORX_OK;
+}
+
+arborx_status arborx_forest_create(int64_t n, int32_t T, int32_t dim, int32_t kind, void *stream, arborx_forest *out)
+{
+    if (!out)
+        return fail(ARBORX_E_INVALID, "out is NULL");
+    if (T < 1)
+        return fail(ARBORX_E_INVALID, "T must be >= 1");
+    if (n < 0 || n >= INT32_MAX)
+        return fail(ARBORX_E_INVALID, "n must be in [0, 2^31-1)");
+    if (!dim_valid(dim))
+        return fail(ARBORX_E_INVALID, "dim must be in 1..10");
+    if (kind != ARBORX_POINTS && kind != ARBORX_BOXES)
+        return fail(ARBORX_E_INVALID, "kind must be ARBORX_POINTS or ARBORX_BOXES");
+    if (!dim_compiled(dim))
+        return fail(ARBORX_E_UNSUPPORTED, "dimension not compiled in (2, 3 and 6 are)");
+    arborx_status st = check_device();
+    if (st != ARBORX_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    arborx_forest f = new arborx_forest_s();
+    st = forest_alloc(n, T, dim, kind, f->dev, s);
+    if (st == ARBORX_OK) {
+        hipError_t e = hipEventCreateWithFlags(&f->ready, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventRecord(f->ready, s);
+        if (e != hipSuccess)
+            st = hip_fail(e, "hipEventRecord");
+    }
+    if (st != ARBORX_OK) {
+        std::string msg = g_error;
+        (void)hipStreamSynchronize(s);
+        forest_release(f->dev, s);
+        (void)hipStreamSynchronize(s);
+        if (f->ready)
+            (void)hipEventDestroy(f->ready);
+        delete f;
+        set_error(msg);
+        return st;
+    }
+    *out = f;
+    return ARBORX_OK;
+}
+
+arborx_status arborx_forest_rebuild(arborx_forest f, const float *values, const int64_t *tree_offsets, void *stream)
+{
+    if (!f)
+        return fail(ARBORX_E_INVALID, "forest is NULL");
+    if (!tree_offsets)
+        return fail(ARBORX_E_INVALID, "tree_offsets is NULL");
+    if (f->dev.n > 0 && !values)
+        return fail(ARBORX_E_INVALID, "values is NULL");
+    arborx_status st = check_device();
+    if (st != ARBORX_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    AX_HIP(hipStreamIsCapturing(s, &cs));
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    if (!capturing) {  // queries of the old contents on other streams finish first
+        AX_HIP(hipStreamWaitEvent(s, f->ready, 0));
+        f->uses.wait(s);
+    }
+    if ((st = forest_rebuild(values, tree_offsets, f->dev, s)) != ARBORX_OK)
+        return st;
+    if (!capturing)
+        AX_HIP(hipEventRecord(f->ready, s));
     return ARBORX_OK;
 }
 

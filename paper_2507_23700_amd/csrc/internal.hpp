@@ -60,6 +60,7 @@ int walk_format(int op);
 // ARBORX_E_INVALID unless the structure holds the nodes of format `fmt`.
 arborx_status check_nodes(const void *qnodes, const void *wnodes, int64_t n, int fmt);
 bool tree_has_format(arborx_tree tree, int format);
+bool forest_has_format(arborx_forest forest, int format);
 
 
 // Error reporting: thread-local last message.
@@ -167,12 +168,19 @@ struct ForestDev {
     float *leaves = nullptr;   // n leaf records, sorted inside each tree
     TreeHeader *hdrs = nullptr;  // [T]
     int64_t *seg = nullptr;    // [T+1] device copy of the tree offsets
-    std::vector<int64_t> seg_host;
     void *ws = nullptr;        // query workspace, grown on demand (reserve before graph capture)
     size_t ws_bytes = 0;
+    void *bws = nullptr;       // build workspace, sized at allocation for n values in T trees
+    size_t bws_bytes = 0;
+    int max_tiles = 0;         // upper bound of the build's per-tree tiles: n / tile + T + 1
 };
 arborx_status build_forest(const float *values, const int64_t *seg_host, int T, int dim, int kind, ForestDev &f,
                            hipStream_t s);
+// Every allocation of a forest of n values in T trees (structure and build
+// workspace), then rebuilds from device values and device offsets [T+1] that
+// launch kernels only: capturable in a graph.
+arborx_status forest_alloc(int64_t n, int T, int dim, int kind, ForestDev &f, hipStream_t s);
+arborx_status forest_rebuild(const float *values, const int64_t *tree_offsets, ForestDev &f, hipStream_t s);
 void forest_release(ForestDev &f, hipStream_t s);
 // Grow the query workspace to serve m queries without allocating.
 arborx_status forest_reserve(ForestDev &f, int64_t m, hipStream_t s);

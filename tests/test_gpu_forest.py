@@ -129,6 +129,86 @@ def test_forest_query_in_hip_graph():
         torch.cuda.synchronize()
 
 
+def _forest_contents(rep, n, T, m):
+    """New contents of the same sizes for a replay: n values split anew into T trees (some empty,
+    some of one value), and m new queries with the fixed batch layout."""
+    g = np.random.default_rng(500 + rep)
+    cuts = np.sort(g.integers(0, n + 1, T - 1))
+    cuts[: rep % 3] = 0  # leading empty trees on some replays
+    toff = np.concatenate([[0], cuts, [n]]).astype(np.int64)
+    vals = inputs.cube(n, 3, g) if rep % 2 == 0 else inputs.shell(n, g)
+    return np.ascontiguousarray(vals), toff, np.ascontiguousarray(inputs.cube(m, 3, g))
+
+
+@pytest.mark.parametrize("tuning", [{}, dict(node_format=1), dict(node_format=2)])
+def test_forest_build_and_queries_in_one_hip_graph(tuning):
+    cfg = small_forest(4)
+    n, T, m = len(cfg["values"]), len(cfg["tree_offsets"]) - 1, len(cfg["queries"])
+    ax.arborx_set_tuning(**tuning)
+    try:
+        fo = ax.arborx_forest_create(n, T, 3)
+        v, off = dev(cfg["values"]), dev(cfg["tree_offsets"])
+        q, bo, bt, br = dev(cfg["queries"]), dev(cfg["batch_offsets"]), dev(cfg["batch_tree"]), dev(cfg["batch_radius"])
+        ax.arborx_forest_reserve(fo, m)
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):  # build, reduce and kNN: one graph, nothing allocated
+                ax.arborx_forest_rebuild(fo, v, off, stream=s)
+                out = ax.arborx_forest_query_reduce(fo, q, bo, bt, br, ax.COUNT_SUMDIST, stream=s)
+                outk = ax.arborx_forest_query_knn(fo, q, bo, bt, 8, stream=s)
+        for rep in range(4):
+            vals, toff, qs = _forest_contents(rep, n, T, m)
+            v.copy_(dev(vals))
+            off.copy_(dev(toff))
+            q.copy_(dev(qs))
+            out[0].fill_(-7)
+            outk[1].fill_(-7)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            # the eager build of the same contents gives the same answers, bit for bit
+            ref = ax.arborx_forest_build(dev(vals), toff)
+            rc, rs = ax.arborx_forest_query_reduce(ref, dev(qs), bo, bt, br, ax.COUNT_SUMDIST)
+            rd, ri = ax.arborx_forest_query_knn(ref, dev(qs), bo, bt, 8)
+            torch.cuda.synchronize()
+            assert np.array_equal(host(out[0]), host(rc)) and np.array_equal(host(out[1]), host(rs)), rep
+            assert np.array_equal(host(outk[1]), host(ri)) and np.array_equal(host(outk[0]), host(rd)), rep
+            sel = list(range(0, len(cfg["batch_tree"]), 2))
+            oc, os_ = oracle.forest_reduce(vals, toff, qs, cfg["batch_offsets"], cfg["batch_tree"],
+                                           cfg["batch_radius"], batches=sel)
+            od2, oix = oracle.forest_knn(vals, toff, qs, cfg["batch_offsets"], cfg["batch_tree"], 8, batches=sel)
+            for b in sel:
+                sl = slice(cfg["batch_offsets"][b], cfg["batch_offsets"][b + 1])
+                assert np.array_equal(host(out[0])[sl], oc[sl]) and np.array_equal(host(out[1])[sl], os_[sl])
+                assert np.array_equal(host(outk[1])[sl], oix[sl]) and np.array_equal(host(outk[0])[sl], od2[sl])
+            ax.arborx_forest_query_knn(ref, dev(qs), bo, bt, 4)  # eager work between replays
+            del ref
+            torch.cuda.synchronize()
+        del g
+    finally:
+        ax.arborx_reset_tuning()
+
+
+def test_forest_rebuild_sanitizes_offsets():
+    # offsets that are not a valid split are made one on the device: never out of range
+    cfg = small_forest(5)
+    n, T = len(cfg["values"]), len(cfg["tree_offsets"]) - 1
+    fo = ax.arborx_forest_create(n, T, 3)
+    bad = np.array([5, -3, 2000, 1500, n + 100, 7000, 9000, 3], dtype=np.int64)
+    ax.arborx_forest_rebuild(fo, dev(cfg["values"]), dev(bad))
+    fixed = np.concatenate([[0], np.maximum.accumulate(np.clip(bad[1:T], 0, n)), [n]]).astype(np.int64)
+    fixed[1:T] = np.maximum.accumulate(fixed[1:T])
+    ref = ax.arborx_forest_build(dev(cfg["values"]), fixed)
+    q, bo, bt, br = dev(cfg["queries"]), dev(cfg["batch_offsets"]), dev(cfg["batch_tree"]), dev(cfg["batch_radius"])
+    a = ax.arborx_forest_query_reduce(fo, q, bo, bt, br, ax.COUNT_SUMDIST)
+    b = ax.arborx_forest_query_reduce(ref, q, bo, bt, br, ax.COUNT_SUMDIST)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    info = ax.arborx_forest_info(fo)
+    assert info["n"] == n and info["T"] == T
+
+
 def test_chamfer_forward_backward_vs_oracle():
     cfg = inputs.chamfer_pairs(pairs=12, lo=50, hi=3000, cfg=60)
     a, ao, b, bo = cfg["a"], cfg["a_off"], cfg["b"], cfg["b_off"]
@@ -223,5 +303,35 @@ def test_autotune_keeps_results(tmp_path, monkeypatch):
         off, idx = ax.arborx_query_spatial(t, dq, float(r))
         o_off, o_idx = oracle.spatial(data, q, r)
         assert np.array_equal(host(off), o_off) and np.array_equal(host(idx), o_idx)
+    finally:
+        ax.arborx_reset_tuning()
+
+
+def test_autotune_forest_keeps_results(tmp_path, monkeypatch):
+    cfg = small_forest(6)
+    ax.arborx_set_tuning(node_format=2)  # build the four-wide nodes too, so that format is a candidate
+    try:
+        fo = ax.arborx_forest_build(dev(cfg["values"]), cfg["tree_offsets"])
+    finally:
+        ax.arborx_reset_tuning()
+    q, bo, bt, br = dev(cfg["queries"]), dev(cfg["batch_offsets"]), dev(cfg["batch_tree"]), dev(cfg["batch_radius"])
+    monkeypatch.setenv("ARBORX_TUNING_CACHE", str(tmp_path / "forest_tuning.jsonl"))
+    try:
+        for op in (ax.OP_REDUCE, ax.OP_KNN):
+            base = ax.arborx_get_tuning_op(op)
+            best, ms = ax.arborx_autotune_forest(fo, op, q, bo, bt, br, k=8)
+            assert ms > 0 and best["stack"] in (4, 8, 16, 32, base["stack"])
+            assert best["node_format"] in (0, 2) and best["queries_per_thread"] in (0, 1, 2, 4)
+            assert best["seed_mode"] in (0, 1, 2) and ax.arborx_get_tuning_op(op) == best
+        best2, ms2 = ax.arborx_autotune_forest(fo, ax.OP_KNN, q, bo, bt, br, k=8)
+        assert ms2 == -1.0 and best2 == ax.arborx_get_tuning_op(ax.OP_KNN)
+        c, s = ax.arborx_forest_query_reduce(fo, q, bo, bt, br, ax.COUNT_SUMDIST)
+        d2, ix = ax.arborx_forest_query_knn(fo, q, bo, bt, 8)
+        oc, os_ = oracle.forest_reduce(cfg["values"], cfg["tree_offsets"], cfg["queries"], cfg["batch_offsets"],
+                                       cfg["batch_tree"], cfg["batch_radius"])
+        od2, oix = oracle.forest_knn(cfg["values"], cfg["tree_offsets"], cfg["queries"], cfg["batch_offsets"],
+                                     cfg["batch_tree"], 8)
+        assert np.array_equal(host(c), oc) and np.array_equal(host(s), os_)
+        assert np.array_equal(host(ix), oix) and np.array_equal(host(d2), od2)
     finally:
         ax.arborx_reset_tuning()
