@@ -539,6 +539,13 @@ arborx_status arborx_debug_radix_sort(void *keys, uint32_t *values, int64_t n, i
 arborx_status arborx_debug_morton64(const float *points, int64_t n, int32_t dim, const float *bounds, uint64_t *codes,
                                     void *stream);
 
+/* Walk statistics for the touched-bytes measurement: visits[i] = node fetches
+ * of query i in the one-query-per-thread depth-first radius walk over binary
+ * nodes (op 0, radius) or in the kNN walk after its seeding (op 1, k 1..64).
+ * Touched bytes = fetches x the node size (64 B in 3D).  Asynchronous. */
+arborx_status arborx_debug_node_visits(arborx_tree tree, const float *queries, int64_t m, float radius, int32_t op,
+                                       int32_t k, int32_t *visits, void *stream);
+
 /*
  * Copy the tree's nodes to host memory for invariant checks.  Synchronises.
  *   child   [host] [n-1][2] int32: >= 0 internal node, < 0 leaf holding value ~child

@@ -427,6 +427,17 @@ def arborx_debug_radix_sort(keys, values, begin_bit=0, end_bit=None, stream=None
                                               _stream(stream)))
 
 
+def arborx_debug_node_visits(tree: Tree, queries, radius=0.0, k=0, stream=None):
+    """Node fetches per query: of the one-query-per-thread radius walk (k = 0) or of the kNN walk
+    after its seeding (k >= 1).  int32[m]."""
+    torch = _torch()
+    q = _queries(tree, queries, False)
+    v = torch.empty(q.shape[0], dtype=torch.int32, device=q.device)
+    _check(_lib.lib().arborx_debug_node_visits(tree.handle, _ptr(q), q.shape[0], ctypes.c_float(radius),
+                                               1 if k else 0, int(k), _ptr(v), _stream(stream)))
+    return v
+
+
 def arborx_debug_morton64(points, bounds, stream=None):
     """Morton-64 codes (as int64 bit patterns) of [n, dim] points under bounds [2, dim]."""
     torch = _torch()

@@ -46,6 +46,7 @@ SIGNATURES = {
     "arborx_debug_radix_sort": (I32, [P, P, I64, I32, I32, I32, P]),
     "arborx_debug_morton64": (I32, [P, I64, I32, P, P, P]),
     "arborx_debug_tree_nodes": (I32, [P, P, P, P, P]),
+    "arborx_debug_node_visits": (I32, [P, P, I64, F32, I32, I32, P, P]),
     "arborx_debug_valu_probe": (I32, [P, I32, I32, P]),
     "arborx_query_spatial_begin": (I32, [P, P, I64, F32, P, P, P, P]),
     "arborx_query_intersects_begin": (I32, [P, P, I64, P, P, P, P]),

@@ -236,6 +236,8 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
                 }
     }
 
+    for (size_t i = 1; i < cands.size(); ++i)  // candidates are used exactly as listed
+        cands[i].t.by_dim = false;
     Temps tmp(s);
     unsigned long long *hash;
     int32_t *o1 = nullptr;
@@ -410,6 +412,8 @@ extern "C" arborx_status arborx_autotune_forest(arborx_forest forest, int32_t op
                 cands.push_back(c);
             }
 
+    for (size_t i = 1; i < cands.size(); ++i)
+        cands[i].t.by_dim = false;
     Temps tmp(s);
     unsigned long long *hash;
     int32_t *o1 = nullptr;

@@ -127,7 +127,23 @@ static Tuning default_tuning(int op)
         t.block = 64;
         t.stack = 8;
     }
+    t.by_dim = true;
     return t;
+}
+
+void launch_shape(int op, int dim, int &block, int &stack)
+{
+    const Tuning &t = tuning(op);
+    block = t.block;
+    stack = t.stack;
+    if (t.by_dim && dim >= 6) {
+        if (op == OP_KNN) {
+            block = 256;
+            stack = 16;
+        } else if (op == OP_REDUCE) {
+            stack = 32;
+        }
+    }
 }
 static Tuning g_tuning[OP_KINDS] = {default_tuning(OP_SPATIAL), default_tuning(OP_REDUCE), default_tuning(OP_KNN)};
 static std::mutex g_pool_mutex;
@@ -452,6 +468,7 @@ const char *arborx_last_error(void) { return g_error.c_str(); }
 static arborx_status to_tuning(const arborx_tuning *t, const Tuning &base, Tuning &n)
 {
     n = base;
+    n.by_dim = false;  // a caller's tuning is used as given
     if (t->block) {
         if (t->block != 64 && t->block != 128 && t->block != 256)
             return fail(ARBORX_E_INVALID, "block must be 64, 128 or 256");
@@ -1447,6 +1464,31 @@ arborx_status arborx_debug_valu_probe(float *out, int32_t blocks, int32_t iters,
     k_valu_probe<<<blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(out, iters);
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
+}
+
+arborx_status arborx_debug_node_visits(arborx_tree t, const float *queries, int64_t m, float radius, int32_t op,
+                                       int32_t k, int32_t *visits, void *stream)
+{
+    arborx_status st = check_tree(t);
+    if (st != ARBORX_OK)
+        return st;
+    if (m < 0 || m >= INT32_MAX)
+        return fail(ARBORX_E_INVALID, "m must be in [0, 2^31-1)");
+    if (op != 0 && op != 1)
+        return fail(ARBORX_E_INVALID, "op must be 0 (radius walk) or 1 (kNN walk)");
+    if (op == 1 && (k < 1 || k > 64))
+        return fail(ARBORX_E_INVALID, "k must be in 1..64");
+    if (op == 0 && (std::isnan(radius) || radius < 0.0f))
+        return fail(ARBORX_E_INVALID, "radius must be >= 0 and not NaN");
+    if (m > 0 && (!queries || !visits))
+        return fail(ARBORX_E_INVALID, "queries and visits must not be NULL");
+    if ((st = check_device()) != ARBORX_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = wait_tree(t, s)) != ARBORX_OK)
+        return st;
+    NoteUse note_use{t->uses, s};
+    return debug_node_visits(t->dev, queries, m, radius, op, k, visits, s);
 }
 
 arborx_status arborx_debug_tree_nodes(arborx_tree t, int32_t *child, float *lo, float *hi, int32_t *root)

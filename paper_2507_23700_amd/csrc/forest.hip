@@ -331,7 +331,8 @@ arborx_status forest_reduce_impl(ForestDev &f, const float *q, int64_t m, const 
         return st;
     fill_kernel<unsigned long long><<<1, 64, 0, s>>>(counter, 1, 0ull);
     const Tuning &tu = tuning(OP_REDUCE);
-    int cap = tu.stack;
+    int block_unused = 0, cap = 0;
+    launch_shape(OP_REDUCE, D, block_unused, cap);
     while (cap > 1 && (size_t)cap * kForestBlock * sizeof(int) > 65536)
         cap >>= 1;
     const size_t lds = (size_t)cap * kForestBlock * sizeof(int);
@@ -406,7 +407,8 @@ arborx_status forest_knn_launch(ForestDev &f, const float *q, int64_t m, const i
         return st;
     fill_kernel<unsigned long long><<<1, 64, 0, s>>>(counter, 1, 0ull);
     const Tuning &tu = tuning(OP_KNN);
-    int cap = tu.stack;
+    int block_unused = 0, cap = 0;
+    launch_shape(OP_KNN, D, block_unused, cap);
     while (cap > 1 && (size_t)cap * kForestBlock * sizeof(KnnEntry) > 65536)
         cap >>= 1;
     const size_t lds = (size_t)cap * kForestBlock * sizeof(KnnEntry);

@@ -46,7 +46,14 @@ struct Tuning {
     int packet = 0; // radius walks on binary nodes: queries per thread (1, 2 or 4) walked together; 0 = by
                     // operation and dimension (up to 3D, where neighbouring paths overlap most: 4 for the
                     // fused reductions, 2 for the CSR count with its register rows; 1 in 6D)
+    bool by_dim = false;  // the library's defaults: block and stack also follow the dimension (launch_shape)
 };
+// Block size and short-stack depth a launch of `op` in dimension `dim` uses:
+// the tuning's, except that the library's defaults in 6D take the shapes the
+// autotuner picked on the 6D Gaussian mixture at 2*10^6 points (kNN: 256-thread
+// blocks, 16-entry ring, 10.2 -> 9.1 ms; reductions: 32-entry ring, 12.4 ->
+// 11.7 ms).
+void launch_shape(int op, int dim, int &block, int &stack);
 // Tuning is kept per operation kind so the autotuner can pick each separately.
 enum Op { OP_SPATIAL = 0, OP_REDUCE = 1, OP_KNN = 2, OP_KINDS = 3 };
 const Tuning &tuning(int op = OP_SPATIAL);
@@ -266,6 +273,10 @@ arborx_status spatial_count_up_to(const TreeDev &t, const float *queries, int64_
                                   const uint32_t *perm, int32_t *counts, hipStream_t s);
 arborx_status knn_query(const TreeDev &t, const float *queries, int64_t m, int k, const uint32_t *perm,
                         float *dist2, int32_t *indices, hipStream_t s);
+// Node fetches per query of the one-query-per-thread radius walk (op 0) or
+// kNN walk (op 1, k = 1..64, after seeding).
+arborx_status debug_node_visits(const TreeDev &t, const float *queries, int64_t m, float radius, int op, int k,
+                                int32_t *visits, hipStream_t s);
 // kNN whose query ordering runs in the library's static per-device scratch
 // (at most ARBORX_NOALLOC_MAX_QUERIES queries): no device allocation.
 arborx_status knn_query_noalloc(const TreeDev &t, const float *queries, int64_t m, int k, float *dist2,

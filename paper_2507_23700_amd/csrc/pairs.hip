@@ -291,8 +291,7 @@ PairLaunch pair_launch(int64_t n, int dim)
     const Tuning &tu = tuning(OP_REDUCE);
     PairLaunch L;
     L.nq = tu.schedule == 2 ? 0 : (tu.packet ? tu.packet : (dim <= 3 ? 2 : 1));
-    L.block = tu.block;
-    L.cap = tu.stack;
+    launch_shape(OP_REDUCE, dim, L.block, L.cap);
     while (L.cap > 1 && (size_t)L.cap * L.block * sizeof(int) > 65536)
         L.cap >>= 1;
     L.lds = L.nq ? (size_t)L.cap * L.block * sizeof(int) : 0;

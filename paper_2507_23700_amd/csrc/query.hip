@@ -763,6 +763,44 @@ __global__ void k_count_up_to(const Node<D> *__restrict__ nodes, const TreeHeade
     counts[qi] = c < n_max ? c : n_max;
 }
 
+// Walk statistics: node fetches per query of the one-query-per-thread radius
+// walk (op 0) or kNN walk (op 1, after its seeding), for the touched-bytes
+// figure (fetches x node bytes).
+template <int D, int K>
+__global__ void k_debug_visits(const Node<D> *__restrict__ nodes, const uint64_t *__restrict__ codes, int n_nodes,
+                               const float *__restrict__ leaves, int kind, const TreeHeader *__restrict__ hdr,
+                               const float *__restrict__ queries, int64_t m, float r2, int op,
+                               int32_t *__restrict__ visits, int stack_cap)
+{
+    extern __shared__ int s_stack[];
+    const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (qi >= m)
+        return;
+    int v = 0;
+    if (op == 0) {
+        Sphere<D> pred;
+        pred.load(queries, qi, r2);
+        int spill[kSpill];
+        ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap, spill);
+        auto f = [](int, float) {};
+        auto count = [&]() {
+            ++v;
+            return false;
+        };
+        traverse_spatial<D>(nodes, hdr->root, n_nodes, pred, st, f, count);
+    } else {
+        float q[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            q[d] = queries[qi * D + d];
+        TopK<K> best;
+        KnnEntry spill[kSpill];
+        ShortStack<KnnEntry> st(reinterpret_cast<KnnEntry *>(s_stack) + threadIdx.x, blockDim.x, stack_cap, spill);
+        knn_search<D, K>(nodes, n_nodes, leaves, kind, *hdr, q, best, st, 0, codes, &v);
+    }
+    visits[qi] = v;
+}
+
 __global__ void k_knn_empty(int64_t total, float *d2, int32_t *idx)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
@@ -820,12 +858,10 @@ struct Launch {
     size_t lds;
 };
 
-Launch traversal_launch(int64_t m, size_t entry_bytes, int op, bool wave = false)
+Launch traversal_launch(int64_t m, size_t entry_bytes, int op, int dim, bool wave = false)
 {
-    const Tuning &tu = tuning(op);
     Launch L;
-    L.block = tu.block;
-    L.cap = tu.stack;
+    launch_shape(op, dim, L.block, L.cap);
     L.grid = (unsigned)((m + L.block - 1) / L.block);
     while (L.cap > 1 && (size_t)L.cap * L.block * entry_bytes > 65536)
         L.cap >>= 1;
@@ -850,7 +886,7 @@ arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m,
     const int nq = tuning(OP_SPATIAL).packet ? tuning(OP_SPATIAL).packet : (D <= 3 ? 2 : 1);
     const bool out = stash_d2 != nullptr;  // the callback-with-output form (sphere queries only)
     if (sched == 0 && nq > 1 && pred == Pred::Sphere) {  // NQ queries per thread over binary nodes
-        const Launch L = traversal_launch((m + nq - 1) / nq, sizeof(int), OP_SPATIAL);
+        const Launch L = traversal_launch((m + nq - 1) / nq, sizeof(int), OP_SPATIAL, D);
         const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
         ProfScope ps("spatial_count", s);
 #define AX_CP(N, O) k_spatial_count_packet<D, N, O><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, counts, \
@@ -871,7 +907,7 @@ arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m,
         AX_HIP(hipGetLastError());
         return ARBORX_OK;
     }
-    const Launch L = traversal_launch(m, sizeof(int), OP_SPATIAL, sched == 1);
+    const Launch L = traversal_launch(m, sizeof(int), OP_SPATIAL, D, sched == 1);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
     const Node4<D> *wnodes = static_cast<const Node4<D> *>(t.wnodes);
@@ -951,7 +987,7 @@ arborx_status fill_rows_impl(const TreeDev &t, Pred pred, const float *q, int64_
 {
     if (nrows <= 0)
         return ARBORX_OK;
-    Launch L = traversal_launch(nrows, sizeof(int), OP_SPATIAL);
+    Launch L = traversal_launch(nrows, sizeof(int), OP_SPATIAL, D);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
     const Node4<D> *wnodes = static_cast<const Node4<D> *>(t.wnodes);
@@ -994,7 +1030,7 @@ arborx_status reduce_impl(const TreeDev &t, const float *q, int64_t m, float r2,
     const int sched = effective_schedule(OP_REDUCE);
     const int nq = tuning(OP_REDUCE).packet ? tuning(OP_REDUCE).packet : (D <= 3 ? 4 : 1);
     if (sched == 0 && nq > 1) {  // NQ queries per thread over binary nodes
-        const Launch L = traversal_launch((m + nq - 1) / nq, sizeof(int), OP_REDUCE);
+        const Launch L = traversal_launch((m + nq - 1) / nq, sizeof(int), OP_REDUCE, D);
         const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
         ProfScope ps(op == ARBORX_COUNT_SUMDIST ? "reduce_sumdist" : "reduce_count", s);
 #define AX_RP(SD, N) k_spatial_reduce_packet<D, SD, N><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, scale, \
@@ -1014,7 +1050,7 @@ arborx_status reduce_impl(const TreeDev &t, const float *q, int64_t m, float r2,
         AX_HIP(hipGetLastError());
         return ARBORX_OK;
     }
-    const Launch L = traversal_launch(m, sizeof(int), OP_REDUCE, sched == 1);
+    const Launch L = traversal_launch(m, sizeof(int), OP_REDUCE, D, sched == 1);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
     const Node4<D> *wnodes = static_cast<const Node4<D> *>(t.wnodes);
@@ -1051,7 +1087,7 @@ arborx_status knn_launch(const TreeDev &t, const float *q, int64_t m, int k, con
 {
     const bool wave = tuning(OP_KNN).schedule == 1;  // kNN has no rope form: schedule 2 walks with the stack
     const int fmt = walk_format(OP_KNN);
-    const Launch L = traversal_launch(m, sizeof(KnnEntry), OP_KNN, wave);
+    const Launch L = traversal_launch(m, sizeof(KnnEntry), OP_KNN, D, wave);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
     const Node4<D> *wnodes = static_cast<const Node4<D> *>(t.wnodes);
@@ -1332,7 +1368,7 @@ template <int D>
 arborx_status count_up_to_impl(const TreeDev &t, const float *q, int64_t m, float r2, int n_max,
                                const uint32_t *perm, int32_t *counts, hipStream_t s)
 {
-    const Launch L = traversal_launch(m, sizeof(int), OP_REDUCE);
+    const Launch L = traversal_launch(m, sizeof(int), OP_REDUCE, D);
     ProfScope ps("count_up_to", s);
     k_count_up_to<D><<<L.grid, L.block, L.lds, s>>>(static_cast<const Node<D> *>(t.nodes), t.hdr, q, m, r2, n_max,
                                                       perm, counts, L.cap);
@@ -1456,6 +1492,43 @@ arborx_status knn_query_noalloc(const TreeDev &t, const float *queries, int64_t 
             return st;
     }
     return knn_query(t, queries, m, k, perm, dist2, indices, s);
+}
+
+arborx_status debug_node_visits(const TreeDev &t, const float *queries, int64_t m, float radius, int op, int k,
+                                int32_t *visits, hipStream_t s)
+{
+    if (m == 0)
+        return ARBORX_OK;
+    if (t.n == 0)
+        return fill_async<int32_t>(visits, m, 0, s);
+    const int block = op == 0 ? 256 : 64, cap = 8;
+    const size_t lds = (size_t)cap * block * (op == 0 ? sizeof(int) : sizeof(KnnEntry));
+    const float r2 = radius * radius;
+#define AX_DV(DD, KK)                                                                                                  \
+    k_debug_visits<DD, KK><<<grid_for(m, block, INT32_MAX), block, lds, s>>>(                                           \
+        static_cast<const Node<DD> *>(t.nodes), t.codes, tree_nodes(t), t.leaves, t.kind, t.hdr, queries, m, r2, op, \
+        visits, cap)
+#define AX_DV_K(DD)                 \
+    do {                            \
+        if (op == 0 || k <= 1)      \
+            AX_DV(DD, 1);           \
+        else if (k <= 8)            \
+            AX_DV(DD, 8);           \
+        else if (k <= 16)           \
+            AX_DV(DD, 16);          \
+        else                        \
+            AX_DV(DD, 64);          \
+    } while (0)
+    switch (t.dim) {
+    case 2: AX_DV_K(2); break;
+    case 3: AX_DV_K(3); break;
+    case 6: AX_DV_K(6); break;
+    default: return fail(ARBORX_E_UNSUPPORTED, "dimension not compiled in");
+    }
+#undef AX_DV_K
+#undef AX_DV
+    AX_HIP(hipGetLastError());
+    return ARBORX_OK;
 }
 
 }  // namespace ax

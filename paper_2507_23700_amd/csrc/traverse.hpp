@@ -866,7 +866,7 @@ template <int D, int K>
 __device__ __forceinline__ void knn_search(const Node<D> *__restrict__ nodes, int n_nodes,
                                            const float *__restrict__ leaves, int kind, const TreeHeader &hdr,
                                            const float *q, TopK<K> &best, ShortStack<KnnEntry> &st,
-                                           int seed, const uint64_t *__restrict__ codes)
+                                           int seed, const uint64_t *__restrict__ codes, int *visits = nullptr)
 {
     knn_seed<D, K>(nodes, n_nodes, leaves, kind, hdr, q, best, seed, codes);
     if (hdr.n <= 0)
@@ -875,6 +875,8 @@ __device__ __forceinline__ void knn_search(const Node<D> *__restrict__ nodes, in
     for (int iter = 0; iter <= n_nodes; ++iter) {
         if ((unsigned)cur >= (unsigned)n_nodes)
             break;
+        if (visits)  // node fetches, for the walk statistics of the debug entry point
+            ++*visits;
         Node<D> nd;
         load_node(nodes, cur, nd);
         const float d0 = box_d2<D>(q, nd.lo[0], nd.hi[0]);

@@ -786,3 +786,15 @@ def test_deepest_tree_one_entry_ring(tuning):
         check_knn(t, data, q, 3)
     finally:
         ax.arborx_reset_tuning()
+
+
+def test_node_visit_statistics():
+    # an infinite radius visits every internal node exactly once; kNN visits at least the root
+    cfg = inputs.config_small(n=5000, m=300)
+    t = ax.arborx_bvh_build(dev(cfg["data"]))
+    v = host(ax.arborx_debug_node_visits(t, dev(cfg["queries"]), radius=float("inf")))
+    assert np.all(v == 4999)
+    v = host(ax.arborx_debug_node_visits(t, dev(cfg["queries"]), radius=float(cfg["radius"])))
+    assert np.all(v >= 1) and v.mean() < 200
+    vk = host(ax.arborx_debug_node_visits(t, dev(cfg["queries"]), k=10))
+    assert np.all(vk >= 1) and np.all(vk <= 4999)
