@@ -862,57 +862,59 @@ __device__ __forceinline__ void knn_seed(const Node<D> *__restrict__ nodes, int 
 // Nearest-first walk keeping the K best (d2, index) pairs sorted in
 // registers; a subtree is skipped only if its box is strictly farther than the
 // current K-th pair, so equal-distance values with smaller indices are found.
+// Software-pipelined: the next node is chosen from the current node's box
+// distances and the bound before this node's leaves are offered (a bound that
+// can only be looser, so nothing is lost), its fetch is issued, and the leaf
+// insertions and the stack push run while it is in flight.
 template <int D, int K>
 __device__ __forceinline__ void knn_search(const Node<D> *__restrict__ nodes, int n_nodes,
                                            const float *__restrict__ leaves, int kind, const TreeHeader &hdr,
-                                           const float *q, TopK<K> &best, ShortStack<KnnEntry> &st,
-                                           int seed, const uint64_t *__restrict__ codes, int *visits = nullptr)
+                                           const float *q, TopK<K> &best, ShortStack<KnnEntry> &st, int seed,
+                                           const uint64_t *__restrict__ codes, int *visits = nullptr)
 {
     knn_seed<D, K>(nodes, n_nodes, leaves, kind, hdr, q, best, seed, codes);
     if (hdr.n <= 0)
         return;
     int cur = hdr.root;
+    Node<D> nd;
+    if ((unsigned)cur < (unsigned)n_nodes)
+        load_node(nodes, cur, nd);
     for (int iter = 0; iter <= n_nodes; ++iter) {
         if ((unsigned)cur >= (unsigned)n_nodes)
             break;
         if (visits)  // node fetches, for the walk statistics of the debug entry point
             ++*visits;
-        Node<D> nd;
-        load_node(nodes, cur, nd);
         const float d0 = box_d2<D>(q, nd.lo[0], nd.hi[0]);
         const float d1 = box_d2<D>(q, nd.lo[1], nd.hi[1]);
         const int c0 = nd.child[0], c1 = nd.child[1];
+        const float bound = best.bound();
+        const bool k0 = c0 >= 0 && !(d0 > bound);
+        const bool k1 = c1 >= 0 && !(d1 > bound);
+        int next = -1;
+        if (k0 && k1) {
+            const bool near1 = d1 < d0;
+            st.push(near1 ? KnnEntry{c0, d0} : KnnEntry{c1, d1});
+            next = near1 ? c1 : c0;
+        } else if (k0) {
+            next = c0;
+        } else if (k1) {
+            next = c1;
+        } else {
+            while (!st.empty()) {
+                const KnnEntry e = st.pop();
+                if (!(e.d2 > bound)) {
+                    next = e.ref;
+                    break;
+                }
+            }
+        }
+        if ((unsigned)next < (unsigned)n_nodes)
+            load_node(nodes, next, nd);  // in flight during the insertions below
         if (c0 < 0 && c0 != kEmptyRef)
             best.offer(d0, ~c0);
         if (c1 < 0 && c1 != kEmptyRef)
             best.offer(d1, ~c1);
-        const bool k0 = c0 >= 0 && !(d0 > best.bound());
-        const bool k1 = c1 >= 0 && !(d1 > best.bound());
-        if (k0 && k1) {
-            if (d1 < d0) {
-                st.push(KnnEntry{c0, d0});
-                cur = c1;
-            } else {
-                st.push(KnnEntry{c1, d1});
-                cur = c0;
-            }
-        } else if (k0) {
-            cur = c0;
-        } else if (k1) {
-            cur = c1;
-        } else {
-            bool found = false;
-            while (!st.empty()) {
-                const KnnEntry e = st.pop();
-                if (!(e.d2 > best.bound())) {
-                    cur = e.ref;
-                    found = true;
-                    break;
-                }
-            }
-            if (!found)
-                break;
-        }
+        cur = next;
     }
 }
 
