@@ -965,7 +965,11 @@ arborx_status arborx_query_ray_count(arborx_tree t, const float *rays, int64_t m
     if ((st = wait_tree(t, s)) != ARBORX_OK)
         return st;
     NoteUse note_use{t->uses, s};
-    return ray_count(t->dev, rays, m, counts, s);
+    Temps tmp(s);
+    uint32_t *perm = nullptr;
+    if ((st = tree_order(t, rays, m, Pred::Ray, OP_REDUCE, &perm, tmp, s)) != ARBORX_OK)
+        return st;
+    return ray_count(t->dev, rays, m, perm, counts, s);
 }
 
 arborx_status arborx_query_ray_nearest(arborx_tree t, const float *rays, int64_t m, int32_t k, float *t_entry,
@@ -980,7 +984,11 @@ arborx_status arborx_query_ray_nearest(arborx_tree t, const float *rays, int64_t
     if ((st = wait_tree(t, s)) != ARBORX_OK)
         return st;
     NoteUse note_use{t->uses, s};
-    return ray_nearest(t->dev, rays, m, k, t_entry, indices, s);
+    Temps tmp(s);
+    uint32_t *perm = nullptr;
+    if ((st = tree_order(t, rays, m, Pred::Ray, OP_KNN, &perm, tmp, s)) != ARBORX_OK)
+        return st;
+    return ray_nearest(t->dev, rays, m, perm, k, t_entry, indices, s);
 }
 
 arborx_status arborx_dbscan(arborx_tree t, const float *points, float eps, int32_t min_pts, int32_t *labels,

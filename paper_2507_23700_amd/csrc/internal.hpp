@@ -260,8 +260,11 @@ arborx_status spatial_reduce(const TreeDev &t, const float *queries, int64_t m, 
 arborx_status match_distances(const TreeDev &t, const float *values, const float *queries, int64_t m,
                               const int64_t *offsets, const int32_t *indices, float *out, hipStream_t s);
 // Ray predicates (ray.hip); rays are [m][2][dim] (origin row, direction row).
-arborx_status ray_count(const TreeDev &t, const float *rays, int64_t m, int32_t *counts, hipStream_t s);
-arborx_status ray_nearest(const TreeDev &t, const float *rays, int64_t m, int k, float *t_out, int32_t *idx_out,
+// perm: traversal order of the rays (may be NULL).
+arborx_status ray_count(const TreeDev &t, const float *rays, int64_t m, const uint32_t *perm, int32_t *counts,
+                        hipStream_t s);
+arborx_status ray_nearest(const TreeDev &t, const float *rays, int64_t m, const uint32_t *perm, int k, float *t_out,
+                          int32_t *idx_out,
                           hipStream_t s);
 // Pair search over the tree's own points (pairs.hip): degree[i] = number of
 // values j != i within radius of value i (input order).

@@ -17,12 +17,18 @@ namespace {
 
 __device__ __forceinline__ int ray_nodes(const TreeHeader *hdr) { return hdr->n > 1 ? hdr->n - 1 : 1; }
 
+// Thread t answers ray perm[t] (origins in Morton order: neighbouring rays
+// start in the same part of the tree), or ray t without an order.
 template <int D>
 __global__ void k_ray_count(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
-                            const float *__restrict__ rays, int64_t m, int32_t *__restrict__ counts, int stack_cap)
+                            const float *__restrict__ rays, int64_t m, const uint32_t *__restrict__ perm,
+                            int32_t *__restrict__ counts, int stack_cap)
 {
     extern __shared__ int s_stack[];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
+    if (t >= m)
+        return;
+    const int64_t i = perm ? (int64_t)perm[t] : t;
     if (i >= m)
         return;
     RayPred<D> p;
@@ -38,11 +44,14 @@ __global__ void k_ray_count(const Node<D> *__restrict__ nodes, const TreeHeader 
 
 template <int D, int K>
 __global__ void k_ray_nearest(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
-                              const float *__restrict__ rays, int64_t m, int k_out, float *__restrict__ t_out,
-                              int32_t *__restrict__ idx_out, int stack_cap)
+                              const float *__restrict__ rays, int64_t m, const uint32_t *__restrict__ perm, int k_out,
+                              float *__restrict__ t_out, int32_t *__restrict__ idx_out, int stack_cap)
 {
     extern __shared__ int s_stack[];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t0 = xcd_block() * blockDim.x + threadIdx.x;
+    if (t0 >= m)
+        return;
+    const int64_t i = perm ? (int64_t)perm[t0] : t0;
     if (i >= m)
         return;
     RayPred<D> p;
@@ -100,65 +109,68 @@ __global__ void k_ray_nearest(const Node<D> *__restrict__ nodes, const TreeHeade
 constexpr int kRayBlock = 64;
 
 template <int D>
-arborx_status ray_count_impl(const TreeDev &t, const float *rays, int64_t m, int32_t *counts, hipStream_t s)
+arborx_status ray_count_impl(const TreeDev &t, const float *rays, int64_t m, const uint32_t *perm, int32_t *counts,
+                             hipStream_t s)
 {
     const int cap = 8;
     ProfScope ps("ray_count", s);
     k_ray_count<D><<<(unsigned)((m + kRayBlock - 1) / kRayBlock), kRayBlock, (size_t)cap * kRayBlock * sizeof(int),
-                     s>>>(static_cast<const Node<D> *>(t.nodes), t.hdr, rays, m, counts, cap);
+                     s>>>(static_cast<const Node<D> *>(t.nodes), t.hdr, rays, m, perm, counts, cap);
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
 
 template <int D, int K>
-arborx_status ray_nearest_launch(const TreeDev &t, const float *rays, int64_t m, int k, float *t_out,
-                                 int32_t *idx_out, hipStream_t s)
+arborx_status ray_nearest_launch(const TreeDev &t, const float *rays, int64_t m, const uint32_t *perm, int k,
+                                 float *t_out, int32_t *idx_out, hipStream_t s)
 {
     const int cap = 8;
     ProfScope ps("ray_nearest", s);
     k_ray_nearest<D, K><<<(unsigned)((m + kRayBlock - 1) / kRayBlock), kRayBlock,
                           (size_t)cap * kRayBlock * sizeof(KnnEntry), s>>>(static_cast<const Node<D> *>(t.nodes),
-                                                                           t.hdr, rays, m, k, t_out, idx_out, cap);
+                                                                           t.hdr, rays, m, perm, k, t_out, idx_out,
+                                                                           cap);
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }
 
 template <int D>
-arborx_status ray_nearest_impl(const TreeDev &t, const float *rays, int64_t m, int k, float *t_out,
-                               int32_t *idx_out, hipStream_t s)
+arborx_status ray_nearest_impl(const TreeDev &t, const float *rays, int64_t m, const uint32_t *perm, int k,
+                               float *t_out, int32_t *idx_out, hipStream_t s)
 {
     if (k <= 1)
-        return ray_nearest_launch<D, 1>(t, rays, m, k, t_out, idx_out, s);
+        return ray_nearest_launch<D, 1>(t, rays, m, perm, k, t_out, idx_out, s);
     if (k <= 4)
-        return ray_nearest_launch<D, 4>(t, rays, m, k, t_out, idx_out, s);
+        return ray_nearest_launch<D, 4>(t, rays, m, perm, k, t_out, idx_out, s);
     if (k <= 16)
-        return ray_nearest_launch<D, 16>(t, rays, m, k, t_out, idx_out, s);
-    return ray_nearest_launch<D, 64>(t, rays, m, k, t_out, idx_out, s);
+        return ray_nearest_launch<D, 16>(t, rays, m, perm, k, t_out, idx_out, s);
+    return ray_nearest_launch<D, 64>(t, rays, m, perm, k, t_out, idx_out, s);
 }
 
 }  // namespace
 
-arborx_status ray_count(const TreeDev &t, const float *rays, int64_t m, int32_t *counts, hipStream_t s)
+arborx_status ray_count(const TreeDev &t, const float *rays, int64_t m, const uint32_t *perm, int32_t *counts,
+                        hipStream_t s)
 {
     if (m == 0)
         return ARBORX_OK;
     switch (t.dim) {
-    case 2: return ray_count_impl<2>(t, rays, m, counts, s);
-    case 3: return ray_count_impl<3>(t, rays, m, counts, s);
-    case 6: return ray_count_impl<6>(t, rays, m, counts, s);
+    case 2: return ray_count_impl<2>(t, rays, m, perm, counts, s);
+    case 3: return ray_count_impl<3>(t, rays, m, perm, counts, s);
+    case 6: return ray_count_impl<6>(t, rays, m, perm, counts, s);
     default: return fail(ARBORX_E_UNSUPPORTED, "dimension not compiled in");
     }
 }
 
-arborx_status ray_nearest(const TreeDev &t, const float *rays, int64_t m, int k, float *t_out, int32_t *idx_out,
-                          hipStream_t s)
+arborx_status ray_nearest(const TreeDev &t, const float *rays, int64_t m, const uint32_t *perm, int k, float *t_out,
+                          int32_t *idx_out, hipStream_t s)
 {
     if (m == 0)
         return ARBORX_OK;
     switch (t.dim) {
-    case 2: return ray_nearest_impl<2>(t, rays, m, k, t_out, idx_out, s);
-    case 3: return ray_nearest_impl<3>(t, rays, m, k, t_out, idx_out, s);
-    case 6: return ray_nearest_impl<6>(t, rays, m, k, t_out, idx_out, s);
+    case 2: return ray_nearest_impl<2>(t, rays, m, perm, k, t_out, idx_out, s);
+    case 3: return ray_nearest_impl<3>(t, rays, m, perm, k, t_out, idx_out, s);
+    case 6: return ray_nearest_impl<6>(t, rays, m, perm, k, t_out, idx_out, s);
     default: return fail(ARBORX_E_UNSUPPORTED, "dimension not compiled in");
     }
 }
