@@ -100,13 +100,16 @@ def traffic_for(kernel, workload):
     return profiled(kernel, workload, "bytes_per_launch")
 
 
-KERNEL_PHASE = [  # rocprofv3 kernel name fragment -> phase name used by the in-library profiler
-    ("k_spatial_count_packet<", "spatial_count"), ("k_spatial_reduce_packet<3, false", "reduce_count"),
-    ("k_spatial_reduce_packet<3, true", "reduce_sumdist"), ("k_valu_probe", "valu_probe"),
-    ("k_knn<", "knn"), ("k_spatial_count<", "spatial_count"), ("k_spatial_reduce<3, false", "reduce_count"),
-    ("k_spatial_reduce<3, true", "reduce_sumdist"), ("k_spatial_fill_rows<", "spatial_fill"),
-    ("hierarchy_chunk_kernel<", "build_hierarchy"), ("hierarchy_top_kernel<", "build_hierarchy"),
-    ("k_copy_stash", "copy_stash"), ("k_copy_overflow", "copy_overflow"), ("k_count_up_to", "count_up_to"), ("k_match_distances", "match_distances"), ("k_dbscan_", "dbscan"), ("k_pair_degree", "pair_degree"), ("k_ray_count", "ray_count"), ("k_ray_nearest", "ray_nearest"), ("radix_scatter<", "radix_scatter"), ("radix_hist<", "radix_hist"),
+KERNEL_PHASE = [  # rocprofv3 kernel name pattern -> phase name used by the in-library profiler
+    (r"k_spatial_count(_packet)?<\d+, ax::RayPred", "ray_all_hits"), (r"k_spatial_count(_packet)?<", "spatial_count"),
+    (r"k_spatial_reduce(_packet)?<\d+, false", "reduce_count"), (r"k_spatial_reduce(_packet)?<\d+, true", "reduce_sumdist"),
+    (r"k_valu_probe", "valu_probe"), (r"k_knn<", "knn"), (r"k_spatial_fill_rows<", "spatial_fill"),
+    (r"hierarchy_(chunk|top)_kernel<", "build_hierarchy"), (r"k_copy_stash", "copy_stash"),
+    (r"k_copy_overflow", "copy_overflow"), (r"k_sort_rows", "sort_rows"), (r"k_count_up_to", "count_up_to"),
+    (r"k_match_distances", "match_distances"), (r"k_pair_degree", "pair_degree"), (r"k_dbscan_", "dbscan"),
+    (r"k_ray_count", "ray_count"), (r"k_ray_nearest", "ray_nearest"), (r"radix_scatter<", "radix_scatter"),
+    (r"radix_hist<", "radix_hist"), (r"k_query_codes<", "order"), (r"morton_kernel<", "build_morton"),
+    (r"k_forest_reduce", "forest_reduce"), (r"k_forest_knn", "forest_knn"), (r"k_chamfer|k_pair_loss", "chamfer"),
 ]
 
 
@@ -121,10 +124,12 @@ def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, sta
     import collections
     import csv
 
+    import re
+
     def phase(name):
         nm = name.replace("(anonymous namespace)::", "")
-        for frag, ph in KERNEL_PHASE:
-            if frag in nm:
+        for pat, ph in KERNEL_PHASE:
+            if re.search(pat, nm):
                 return ph
         return None
 
@@ -164,7 +169,7 @@ def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, sta
     lines = [f"| phase | launches | avg ms (kernel trace) | HBM read MB/launch | HBM write MB/launch | L2 hit |"
              f" VALU busy |", "|---|---|---|---|---|---|---|"]
     for ph in sorted(fetch, key=lambda k: -fetch[k]):
-        if ph not in dict(KERNEL_PHASE).values():
+        if ph not in {p for _, p in KERNEL_PHASE}:
             continue
         nl = max(len(fl[ph]), 1)
         rd = fetch[ph] * fscale / nl

@@ -376,6 +376,8 @@ arborx_status arborx_self_join_degree(arborx_tree tree, float radius, int32_t *d
  *             components allowed); hits as in arborx_query_ray_count
  *   offsets, indices, capacity, total: as arborx_query_spatial; rows ascending
  * Rays are ordered by the Morton code of their origins before the walk.
+ * Temporary device memory: as arborx_query_spatial, with an overflow pool four
+ * times larger (rays meet many more values than a radius query).
  * Synchronises `stream` (to read the total).  Plan form:
  * arborx_query_ray_intersect_begin, then arborx_query_finish.
  */

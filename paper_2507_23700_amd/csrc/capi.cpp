@@ -693,18 +693,19 @@ static arborx_status csr_begin(arborx_tree t, Pred pred, const float *queries, i
         (st = p->tmp.get(&p->ordered_counts, mm)) != ARBORX_OK ||
         (st = p->tmp.get(&p->stash, mm * stash_regs(t->dev.dim))) != ARBORX_OK ||
         (st = p->tmp.get(&p->ovf.head, mm)) != ARBORX_OK ||
-        (st = p->tmp.get(&p->ovf.pool, overflow_pool_ints(mm, t->dev.dim))) != ARBORX_OK ||
+        (st = p->tmp.get(&p->ovf.pool, overflow_pool_ints(mm, t->dev.dim, overflow_factor(pred)))) != ARBORX_OK ||
         (st = p->tmp.get(&p->ovf.ctr, (size_t)kOvfPools * 8)) != ARBORX_OK ||
         (st = p->tmp.get(&p->big_list, mm)) != ARBORX_OK || (st = p->tmp.get(&p->huge_list, mm)) != ARBORX_OK ||
         (st = p->tmp.get(&sws, scan_workspace_bytes(m))) != ARBORX_OK)
         return bail(st);
     p->ovf.dpool = nullptr;
     if (with_dist && ((st = p->tmp.get(&p->stash_d2, mm * stash_regs(t->dev.dim))) != ARBORX_OK ||
-                      (st = p->tmp.get(&p->ovf.dpool, overflow_pool_ints(mm, t->dev.dim))) != ARBORX_OK))
+                      (st = p->tmp.get(&p->ovf.dpool, overflow_pool_ints(mm, t->dev.dim, overflow_factor(pred)))) !=
+                          ARBORX_OK))
         return bail(st);
     if ((st = tree_order(t, queries, m, pred, OP_SPATIAL, &p->perm, p->tmp, s)) != ARBORX_OK)
         return bail(st);
-    p->ovf.per = (int32_t)(overflow_pool_ints(mm, t->dev.dim) / kOvfPools);
+    p->ovf.per = (int32_t)(overflow_pool_ints(mm, t->dev.dim, overflow_factor(pred)) / kOvfPools);
     if ((st = spatial_count(t->dev, pred, queries, m, radius, p->perm, p->counts, p->ordered_counts, p->stash,
                             p->stash_d2, p->ovf, s)) != ARBORX_OK)
         return bail(st);
@@ -1116,6 +1117,8 @@ arborx_status arborx_forest_build(const float *values, const int64_t *tree_offse
             return fail(ARBORX_E_INVALID, "tree_offsets must be nondecreasing");
     if (tree_offsets[T] >= INT32_MAX)
         return fail(ARBORX_E_INVALID, "too many values");
+    if ((int64_t)T + tree_offsets[T] / 4096 + 1 >= INT32_MAX)
+        return fail(ARBORX_E_INVALID, "too many trees");
     if (!dim_valid(dim))
         return fail(ARBORX_E_INVALID, "dim must be in 1..10");
     if (kind != ARBORX_POINTS && kind != ARBORX_BOXES)
@@ -1160,6 +1163,8 @@ arborx_status arborx_forest_create(int64_t n, int32_t T, int32_t dim, int32_t ki
         return fail(ARBORX_E_INVALID, "T must be >= 1");
     if (n < 0 || n >= INT32_MAX)
         return fail(ARBORX_E_INVALID, "n must be in [0, 2^31-1)");
+    if ((int64_t)T + n / 4096 + 1 >= INT32_MAX)
+        return fail(ARBORX_E_INVALID, "too many trees");
     if (!dim_valid(dim))
         return fail(ARBORX_E_INVALID, "dim must be in 1..10");
     if (kind != ARBORX_POINTS && kind != ARBORX_BOXES)

@@ -227,9 +227,13 @@ struct OverflowPool {
     unsigned long long *ctr;       // kOvfPools counters, one per 64 bytes (stride 8), zero before the walk
     int32_t per;                   // ints per sub-pool, a multiple of kChunk
 };
-// Ints of the overflow pool for m queries (as many as the stash rows, at most
-// 2^31 - 1 in all, at least one chunk per sub-pool).
-int64_t overflow_pool_ints(int64_t m, int dim);
+// Ints of the overflow pool for m queries (factor times as many as the stash
+// rows, at most 2^31 - 1 in all, at least one chunk per sub-pool).
+int64_t overflow_pool_ints(int64_t m, int dim, int factor = 1);
+// Pool factor by predicate: rays meet far more values than a radius query
+// aimed at about ten (48 on average against 2*10^6 small boxes), and a row
+// whose chunks do not fit is walked a second time.
+inline int overflow_factor(Pred pred) { return pred == Pred::Ray ? 4 : 1; }
 // Count pass; also stores each query's first stash_regs(dim) matches in
 // stash[query][stash_regs(dim)], further matches in ovf, and (with perm)
 // ordered_counts[t] = counts[perm[t]].

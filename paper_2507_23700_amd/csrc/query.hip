@@ -1202,9 +1202,9 @@ arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, i
                     (count_impl<D>(t, pred, queries, m, r2, perm, counts, ordered_counts, stash, stash_d2, ovf, s)));
 }
 
-int64_t overflow_pool_ints(int64_t m, int dim)
+int64_t overflow_pool_ints(int64_t m, int dim, int factor)
 {
-    int64_t per = (m * stash_regs(dim) + kOvfPools - 1) / kOvfPools;
+    int64_t per = (m * stash_regs(dim) * factor + kOvfPools - 1) / kOvfPools;
     per = (per + kChunk - 1) / kChunk * kChunk;
     const int64_t max_per = (int64_t)INT32_MAX / kOvfPools / kChunk * kChunk;
     per = per < kChunk ? kChunk : (per > max_per ? max_per : per);

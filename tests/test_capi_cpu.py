@@ -139,3 +139,35 @@ def test_allocator_hook_validation():
     assert L.arborx_set_allocator(None, None, None) == 0
     with pytest.raises(ValueError):
         ax.arborx_set_allocator(lambda n, s: 0)
+
+
+def test_new_entry_point_validation():
+    """Arguments of the pair search, per-match output, ray CSR, forest create/rebuild, forest
+    autotuner, walk statistics and allocation-free kNN entry points fail on the host, before any
+    device work."""
+    f = ctypes.c_float
+    tot = ctypes.c_int64()
+    plan = P()
+    out = P()
+    assert L.arborx_self_join_degree(None, f(1), FAKE, None) == 1
+    assert L.arborx_query_spatial_with_distances(None, FAKE, 1, f(1), FAKE, FAKE, FAKE, 1, ctypes.byref(tot), None) == 1
+    assert L.arborx_query_spatial_with_distances_begin(None, FAKE, 1, f(1), FAKE, ctypes.byref(tot),
+                                                       ctypes.byref(plan), None) == 1
+    assert L.arborx_query_finish_with_distances(None, FAKE, FAKE, 1) == 1
+    assert L.arborx_query_ray_intersect(None, FAKE, 1, FAKE, FAKE, 1, ctypes.byref(tot), None) == 1
+    assert L.arborx_query_ray_intersect_begin(None, FAKE, 1, FAKE, ctypes.byref(tot), ctypes.byref(plan), None) == 1
+    assert L.arborx_query_ray_ordered_intersect(None, FAKE, 1, FAKE, FAKE, FAKE, 1, ctypes.byref(tot), None) == 1
+    assert L.arborx_query_ray_ordered_intersect_begin(None, FAKE, 1, FAKE, ctypes.byref(tot), ctypes.byref(plan),
+                                                      None) == 1
+    assert L.arborx_forest_create(10, 0, 3, 0, None, ctypes.byref(out)) == 1
+    assert L.arborx_forest_create(-1, 2, 3, 0, None, ctypes.byref(out)) == 1
+    assert L.arborx_forest_create(10, 2, 11, 0, None, ctypes.byref(out)) == 1
+    assert L.arborx_forest_create(10, 2, 3, 5, None, ctypes.byref(out)) == 1
+    assert L.arborx_forest_create(10, 2, 4, 0, None, ctypes.byref(out)) == 2
+    assert L.arborx_forest_create(10, 2 ** 31 - 2, 3, 0, None, ctypes.byref(out)) == 1 and "trees" in _err()
+    assert L.arborx_forest_create(10, 2, 3, 0, None, None) == 1
+    assert L.arborx_forest_rebuild(None, FAKE, FAKE, None) == 1
+    assert L.arborx_autotune_forest(None, 1, FAKE, 1, FAKE, FAKE, FAKE, 1, 1, None, None, None) == 1
+    assert L.arborx_debug_node_visits(None, FAKE, 1, f(1), 0, 1, FAKE, None) == 1
+    assert L.arborx_query_knn_noalloc(None, FAKE, 1, 3, FAKE, FAKE, None) == 1
+    assert out.value is None
