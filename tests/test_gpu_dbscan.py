@@ -159,3 +159,14 @@ def test_pair_walk_forms_identical(tuning):
     p6 = clustered(4000, 6, 62)
     check_degree(p6, 0.6)
     check(p6, 0.6, 5)
+
+
+def test_self_join_line_closed_form():
+    # n points spaced 1 apart on a line: at r = 1.5 the ends pair once and every other point twice
+    n = 5000
+    pts = np.zeros((n, 3), dtype=np.float32)
+    pts[:, 0] = np.arange(n, dtype=np.float32)
+    deg = check_degree(pts, 1.5)
+    assert deg[0] == 1 and deg[-1] == 1 and np.all(deg[1:-1] == 2)
+    lab = check(pts, 1.5, 3)  # interior points are core, the two ends border: one cluster, smallest core index 1
+    assert np.all(lab == 1)

@@ -335,3 +335,26 @@ def test_autotune_forest_keeps_results(tmp_path, monkeypatch):
         assert np.array_equal(host(ix), oix) and np.array_equal(host(d2), od2)
     finally:
         ax.arborx_reset_tuning()
+
+
+def test_forest_create_edge_cases():
+    # no values at all: every tree empty, reductions zero, kNN padded
+    fo = ax.arborx_forest_create(0, 3, 3)
+    ax.arborx_forest_rebuild(fo, torch.zeros((0, 3), dtype=torch.float32, device="cuda"),
+                             dev(np.zeros(4, dtype=np.int64)))
+    q = dev(np.random.default_rng(1).random((10, 3)).astype(np.float32))
+    bo, bt = dev(np.array([0, 4, 10], dtype=np.int64)), dev(np.array([2, 0], dtype=np.int32))
+    c, s = ax.arborx_forest_query_reduce(fo, q, bo, bt, dev(np.array([1.0, 1.0], dtype=np.float32)), ax.COUNT_SUMDIST)
+    d2, ix = ax.arborx_forest_query_knn(fo, q, bo, bt, 3)
+    assert np.all(host(c) == 0) and np.all(host(s) == 0) and np.all(host(ix) == -1) and np.all(np.isinf(host(d2)))
+    # one tree holding everything, then rebuilt as two: same forest object
+    g = np.random.default_rng(2)
+    vals = g.random((3000, 3)).astype(np.float32)
+    fo = ax.arborx_forest_create(3000, 2, 3)
+    v = dev(vals)
+    for toff in (np.array([0, 3000, 3000]), np.array([0, 1234, 3000]), np.array([0, 0, 3000])):
+        ax.arborx_forest_rebuild(fo, v, dev(toff.astype(np.int64)))
+        bo2, bt2 = np.array([0, 5, 10], dtype=np.int64), np.array([0, 1], dtype=np.int32)
+        d2, ix = ax.arborx_forest_query_knn(fo, q, dev(bo2), dev(bt2), 4)
+        od2, oix = oracle.forest_knn(vals, toff, host(q), bo2, bt2, 4)
+        assert np.array_equal(host(ix), oix) and np.array_equal(host(d2), od2)

@@ -798,3 +798,15 @@ def test_node_visit_statistics():
     assert np.all(v >= 1) and v.mean() < 200
     vk = host(ax.arborx_debug_node_visits(t, dev(cfg["queries"]), k=10))
     assert np.all(vk >= 1) and np.all(vk <= 4999)
+
+
+def test_with_distances_edge_cases():
+    empty = ax.arborx_bvh_build(dev(np.zeros((0, 3), dtype=np.float32)))
+    q = np.random.default_rng(3).random((20, 3)).astype(np.float32)
+    off, idx, d2 = ax.arborx_query_spatial_with_distances(empty, dev(q), 0.5)
+    assert np.all(host(off) == 0) and idx.numel() == 0 and d2.numel() == 0
+    data = np.concatenate([q[:5], q[:5], np.random.default_rng(4).random((200, 3))]).astype(np.float32)
+    t = ax.arborx_bvh_build(dev(data))
+    check_spatial_dist(t, data, q, 0.0)  # exact duplicates only, at distance 0
+    off, idx, d2 = ax.arborx_query_spatial_with_distances(t, dev(q[:0]), 0.1)
+    assert off.numel() == 1 and idx.numel() == 0
