@@ -159,7 +159,7 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
             best->build = cached.build;
             best->seed_mode = cached.seed;
             best->queries_per_thread = cached.packet;
-            best->node_format = cached.nodes;
+            best->node_format = node_format_of(cached, op, dim, false);
         }
         if (best_ms)
             *best_ms = -1.0;
@@ -201,14 +201,17 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
             cands.push_back(c);
         }
     if (op != OP_KNN)
-        for (int nq : {1, 2, 4}) {  // queries per thread of the radius walks
-            Candidate c;
-            c.t = base;
-            c.t.schedule = 0;
-            c.t.nodes = 0;
-            c.t.packet = nq;
-            cands.push_back(c);
-        }
+        for (int format : {0, 1})
+            for (int nq : {1, 2, 4}) {  // queries per thread of the radius walks
+                if (!tree_has_format(tree, format))
+                    break;
+                Candidate c;
+                c.t = base;
+                c.t.schedule = 0;
+                c.t.nodes = format;
+                c.t.packet = nq;
+                cands.push_back(c);
+            }
     if (op != OP_KNN)
         for (int block : {64, 256}) {
             Candidate c;
@@ -331,7 +334,7 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
         best->build = b.build;
         best->seed_mode = b.seed;
         best->queries_per_thread = b.packet;
-        best->node_format = b.nodes;
+        best->node_format = node_format_of(b, op, dim, false);
     }
     if (best_ms)
         *best_ms = cands[besti].ms;
@@ -375,7 +378,7 @@ extern "C" arborx_status arborx_autotune_forest(arborx_forest forest, int32_t op
             best->build = cached.build;
             best->seed_mode = cached.seed;
             best->queries_per_thread = cached.packet;
-            best->node_format = cached.nodes;
+            best->node_format = node_format_of(cached, op, dim, true);
         }
         if (best_ms)
             *best_ms = -1.0;
@@ -383,8 +386,10 @@ extern "C" arborx_status arborx_autotune_forest(arborx_forest forest, int32_t op
     }
     std::vector<Candidate> cands;
     cands.push_back(Candidate{base, 0});
+    Tuning fbase = base;  // the others start from the node format the forest walks under the tuning in force
+    fbase.nodes = node_format_of(base, op, dim, true);
     for (int stack : {4, 8, 16, 32}) {
-        Candidate c{base, 0};
+        Candidate c{fbase, 0};
         c.t.stack = stack;
         c.t.nodes = 0;
         cands.push_back(c);
@@ -392,7 +397,7 @@ extern "C" arborx_status arborx_autotune_forest(arborx_forest forest, int32_t op
     if (op == OP_REDUCE)
         for (int nq : {1, 2, 4})
             for (int stack : {8, 16}) {
-                Candidate c{base, 0};
+                Candidate c{fbase, 0};
                 c.t.nodes = 0;
                 c.t.packet = nq;
                 c.t.stack = stack;
@@ -400,14 +405,14 @@ extern "C" arborx_status arborx_autotune_forest(arborx_forest forest, int32_t op
             }
     for (int format : {1, 2})
         if (forest_has_format(forest, format)) {
-            Candidate c{base, 0};
+            Candidate c{fbase, 0};
             c.t.nodes = format;
             cands.push_back(c);
         }
     if (op == OP_KNN)
         for (int mode = 0; mode < 3; ++mode)
             if (mode != base.seed) {
-                Candidate c{base, 0};
+                Candidate c{fbase, 0};
                 c.t.seed = mode;
                 cands.push_back(c);
             }
@@ -492,7 +497,7 @@ extern "C" arborx_status arborx_autotune_forest(arborx_forest forest, int32_t op
         best->build = b.build;
         best->seed_mode = b.seed;
         best->queries_per_thread = b.packet;
-        best->node_format = b.nodes;
+        best->node_format = node_format_of(b, op, dim, true);
     }
     if (best_ms)
         *best_ms = cands[besti].ms;

@@ -49,28 +49,34 @@ __device__ __forceinline__ float quant_scale(float lo, float hi)
     return s;
 }
 
-// Largest code whose decoded value is <= x, and smallest whose decoded value is >= x.
-__device__ __forceinline__ uint32_t qcode_down(float x, float lo, float scale)
+// Largest code whose decoded value is <= x, and smallest whose decoded value
+// is >= x.  The estimate from the reciprocal step `inv` is corrected both ways
+// against the decode itself, so the result does not depend on its rounding.
+__device__ __forceinline__ uint32_t qcode_down(float x, float lo, float scale, float inv)
 {
     if (!(scale > 0.0f) || !(x > lo))
         return 0u;
-    float u = floorf((x - lo) / scale);
-    uint32_t c = u >= (float)kQMax ? (uint32_t)kQMax : (uint32_t)u;
+    const float u = floorf((x - lo) * inv);
+    uint32_t c = u >= (float)kQMax ? (uint32_t)kQMax : (u > 0.0f ? (uint32_t)u : 0u);
     while (c > 0 && qdecode(c, lo, scale) > x)
         --c;
+    while (c < (uint32_t)kQMax && qdecode(c + 1, lo, scale) <= x)
+        ++c;
     return c;
 }
 
-__device__ __forceinline__ uint32_t qcode_up(float x, float lo, float scale)
+__device__ __forceinline__ uint32_t qcode_up(float x, float lo, float scale, float inv)
 {
     if (!(scale > 0.0f))
         return 0u;
     if (!(x > lo))
         return 0u;
-    float u = ceilf((x - lo) / scale);
-    uint32_t c = u >= (float)kQMax ? (uint32_t)kQMax : (uint32_t)u;
+    const float u = ceilf((x - lo) * inv);
+    uint32_t c = u >= (float)kQMax ? (uint32_t)kQMax : (u > 0.0f ? (uint32_t)u : 0u);
     while (c < (uint32_t)kQMax && qdecode(c, lo, scale) < x)
         ++c;
+    while (c > 0 && qdecode(c - 1, lo, scale) >= x)
+        --c;
     return c;
 }
 
@@ -372,6 +378,57 @@ __device__ __forceinline__ void load_value_box(const float *values, int kind, ui
     }
 }
 
+// Quantized form of float node p of a tree with header h.  A point tree's
+// leaf child keeps its point and reference unchanged (the point's float words
+// fill that child's code bytes); a box tree's leaf child becomes its sorted
+// leaf position: the left child of node p is leaf p, the right child leaf
+// p + 1.
+template <int D>
+__device__ __forceinline__ void store_qnode(QNode<D> *__restrict__ dst, const Node<D> &nd, int p, int kind,
+                                            const TreeHeader &h)
+{
+    QNode<D> qn;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(qn.pad) / sizeof(qn.pad[0])); ++k)
+        qn.pad[k] = 0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int32_t ref = nd.child[c];
+        if (ref == kEmptyRef) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                qn.q[c][0][d] = (uint16_t)kQMax;
+                qn.q[c][1][d] = 0;
+            }
+            qn.child[c] = kEmptyRef;
+            continue;
+        }
+        if (ref < 0 && kind != ARBORX_BOXES) {
+            uint16_t *qc = &qn.q[c][0][0];
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const uint32_t bits = __float_as_uint(nd.lo[c][d]);
+                qc[2 * d] = (uint16_t)(bits & 0xffffu);
+                qc[2 * d + 1] = (uint16_t)(bits >> 16);
+            }
+            qn.child[c] = ref;
+            continue;
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const float inv = h.qscale[d] > 0.0f ? 1.0f / h.qscale[d] : 0.0f;
+            qn.q[c][0][d] = (uint16_t)qcode_down(nd.lo[c][d], h.lo[d], h.qscale[d], inv);
+            qn.q[c][1][d] = (uint16_t)qcode_up(nd.hi[c][d], h.lo[d], h.qscale[d], inv);
+        }
+        qn.child[c] = ref >= 0 ? ref : ~(p + c);
+    }
+    float4 *d4 = reinterpret_cast<float4 *>(dst);
+    const float4 *s4 = reinterpret_cast<const float4 *>(&qn);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(QNode<D>) / 16); ++k)
+        d4[k] = s4[k];
+}
+
 template <int D>
 __device__ void write_single_leaf_tree(Node<D> *node, TreeHeader *hdr, const float *lo, const float *hi, int32_t ref,
                                        int index)
@@ -420,50 +477,23 @@ __device__ __forceinline__ void segment_of(int i, const int64_t *__restrict__ se
     te = (int)seg[lo + 1] - 1;
 }
 
-// Float nodes -> quantized nodes.  Node p belongs to the tree holding sorted
-// leaf p (a one-value tree's node sits at its own leaf position).  Leaf child
-// references become sorted leaf positions: the left child of node p is leaf p,
-// the right child leaf p + 1.
+// Float nodes -> quantized nodes, a pass over the finished tree (a pass of
+// its own measured faster than writing both forms during the climb, whose
+// levels run one after another).  Node p belongs to the tree holding sorted
+// leaf p (a one-value tree's node sits at its own leaf position).
 template <int D>
 __global__ void quantize_nodes(const Node<D> *__restrict__ nodes, int n_nodes, const int64_t *__restrict__ seg,
-                               int nseg, int n, const TreeHeader *__restrict__ hdrs, QNode<D> *__restrict__ qnodes)
+                               int nseg, int n, int kind, const TreeHeader *__restrict__ hdrs,
+                               QNode<D> *__restrict__ qnodes)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n_nodes)
         return;
     int sg, ts, te;
     segment_of(p < n ? p : n - 1, seg, nseg, n, sg, ts, te);
-    const TreeHeader &h = hdrs[sg];
     Node<D> nd;
     load_node(nodes, p, nd);
-    QNode<D> qn;
-#pragma unroll
-    for (int k = 0; k < (int)(sizeof(qn.pad) / sizeof(qn.pad[0])); ++k)
-        qn.pad[k] = 0;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const int32_t ref = nd.child[c];
-        if (ref == kEmptyRef) {
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                qn.q[c][0][d] = (uint16_t)kQMax;
-                qn.q[c][1][d] = 0;
-            }
-            qn.child[c] = kEmptyRef;
-            continue;
-        }
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            qn.q[c][0][d] = (uint16_t)qcode_down(nd.lo[c][d], h.lo[d], h.qscale[d]);
-            qn.q[c][1][d] = (uint16_t)qcode_up(nd.hi[c][d], h.lo[d], h.qscale[d]);
-        }
-        qn.child[c] = ref >= 0 ? ref : ~(p + c);
-    }
-    float4 *dst = reinterpret_cast<float4 *>(qnodes + p);
-    const float4 *src = reinterpret_cast<const float4 *>(&qn);
-#pragma unroll
-    for (int k = 0; k < (int)(sizeof(QNode<D>) / 16); ++k)
-        dst[k] = src[k];
+    store_qnode<D>(qnodes + p, nd, p, kind, hdrs[sg]);
 }
 
 
@@ -767,7 +797,7 @@ arborx_status build_impl(const float *values, int64_t n, int kind, TreeDev &t, h
     st = dalloc((void **)&t.leaves, (size_t)n * leaf_floats(D, kind) * sizeof(float), s);
     if (st != ARBORX_OK)
         return st;
-    const bool quantized = format_requested(1), wide = format_requested(2);
+    const bool quantized = format_requested(1, D, false), wide = format_requested(2, D, false);
     if (quantized && (st = dalloc(&t.qnodes, (size_t)nn * sizeof(QNode<D>), s)) != ARBORX_OK)
         return st;
     if (wide && (st = dalloc(&t.wnodes, (size_t)nn * sizeof(Node4<D>), s)) != ARBORX_OK)
@@ -833,8 +863,8 @@ arborx_status build_impl(const float *values, int64_t n, int kind, TreeDev &t, h
     }
     if (quantized) {
         ProfScope ps("build_quantize", s);
-        quantize_nodes<D><<<grid_for(nn, kBuildBlock), kBuildBlock, 0, s>>>(nodes, (int)nn, nullptr, 0, (int)n, t.hdr,
-                                                                            static_cast<QNode<D> *>(t.qnodes));
+        quantize_nodes<D><<<grid_for(nn, kBuildBlock), kBuildBlock, 0, s>>>(nodes, (int)nn, nullptr, 0, (int)n, t.kind,
+                                                                            t.hdr, static_cast<QNode<D> *>(t.qnodes));
     }
     if (wide) {
         ProfScope ps("build_widen", s);
@@ -1150,9 +1180,9 @@ arborx_status forest_alloc_impl(int64_t n, int T, int kind, ForestDev &f, hipStr
         (st = dalloc((void **)&f.leaves, (size_t)(n > 0 ? n : 1) * leaf_floats(D, kind) * sizeof(float), s)) !=
             ARBORX_OK)
         return st;
-    if (format_requested(1) && (st = dalloc(&f.qnodes, (size_t)(n > 0 ? n : 1) * sizeof(QNode<D>), s)) != ARBORX_OK)
+    if (format_requested(1, D, true) && (st = dalloc(&f.qnodes, (size_t)(n > 0 ? n : 1) * sizeof(QNode<D>), s)) != ARBORX_OK)
         return st;
-    if (format_requested(2) && (st = dalloc(&f.wnodes, (size_t)(n > 0 ? n : 1) * sizeof(Node4<D>), s)) != ARBORX_OK)
+    if (format_requested(2, D, true) && (st = dalloc(&f.wnodes, (size_t)(n > 0 ? n : 1) * sizeof(Node4<D>), s)) != ARBORX_OK)
         return st;
     f.bws_bytes = forest_build_ws<D>(n, T, f.max_tiles, nullptr, nullptr);
     return dalloc(&f.bws, f.bws_bytes, s);
@@ -1214,8 +1244,8 @@ arborx_status forest_rebuild_impl(const float *values, const int64_t *offs, Fore
         hierarchy_top_kernel<D><<<grid_for(2 * chunks, kBuildBlock), kBuildBlock, 0, s>>>(
             codes, (int)n, nodes, w.flags, esc, 2 * chunks, f.seg, T, f.hdrs);
     if (f.qnodes)
-        quantize_nodes<D><<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(nodes, (int)n, f.seg, T, (int)n, f.hdrs,
-                                                                           static_cast<QNode<D> *>(f.qnodes));
+        quantize_nodes<D><<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(nodes, (int)n, f.seg, T, (int)n, f.kind,
+                                                                           f.hdrs, static_cast<QNode<D> *>(f.qnodes));
     if (f.wnodes)
         widen_nodes<D><<<grid_for(n, kBuildBlock), kBuildBlock, 0, s>>>(nodes, (int)n,
                                                                         static_cast<Node4<D> *>(f.wnodes));

@@ -119,14 +119,21 @@ namespace ax {
 static thread_local std::string g_error;
 // Defaults measured on MI355X at 10^7 points: 256-thread blocks for the radius
 // walks; 64-thread blocks and an 8-entry LDS ring for kNN (its 8-byte stack
-// entries and larger register set).
+// entries and larger register set).  The radius walks run over quantized nodes
+// (half the node loads; a point's leaf is exact in its parent), the CSR count
+// one query per thread; kNN over float nodes up to 3D, where its top-k
+// insertions rather than node loads bound it (node_format below).
 static Tuning default_tuning(int op)
 {
     Tuning t;
     if (op == OP_KNN) {
         t.block = 64;
         t.stack = 8;
+    } else {
+        t.nodes = 1;
     }
+    if (op == OP_SPATIAL)
+        t.packet = 1;
     t.by_dim = true;
     return t;
 }
@@ -138,10 +145,10 @@ void launch_shape(int op, int dim, int &block, int &stack)
     stack = t.stack;
     if (t.by_dim && dim >= 6) {
         if (op == OP_KNN) {
-            block = 256;
+            block = 64;
             stack = 16;
-        } else if (op == OP_REDUCE) {
-            stack = 32;
+        } else if (op == OP_SPATIAL) {
+            block = 64;
         }
     }
 }
@@ -151,10 +158,21 @@ static bool g_pool_ready[64] = {};
 
 const Tuning &tuning(int op) { return g_tuning[op >= 0 && op < OP_KINDS ? op : 0]; }
 
-bool format_requested(int format)
+int node_format_of(const Tuning &t, int op, int dim, bool forest)
+{
+    if (!t.by_dim)
+        return t.nodes;
+    if (forest)
+        return 0;
+    return op == OP_KNN && dim >= 6 ? 1 : t.nodes;
+}
+
+int node_format(int op, int dim, bool forest) { return node_format_of(tuning(op), op, dim, forest); }
+
+bool format_requested(int format, int dim, bool forest)
 {
     for (int op = 0; op < OP_KINDS; ++op)
-        if (g_tuning[op].nodes == format)
+        if (node_format(op, dim, forest) == format)
             return true;
     return false;
 }
@@ -169,11 +187,11 @@ bool forest_has_format(arborx_forest forest, int format)
     return forest && (format == 0 || (format == 1 && forest->dev.qnodes) || (format == 2 && forest->dev.wnodes));
 }
 
-int walk_format(int op)
+int walk_format(int op, int dim)
 {
     const Tuning &t = tuning(op);
     const bool thread_walk = op == OP_KNN ? t.schedule != 1 : t.schedule == 0;  // kNN has no rope walk
-    return thread_walk ? t.nodes : 0;
+    return thread_walk ? node_format(op, dim, false) : 0;
 }
 
 arborx_status check_nodes(const void *qnodes, const void *wnodes, int64_t n, int fmt)

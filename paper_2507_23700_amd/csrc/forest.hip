@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kForestBlock) void k_forest_knn(
             q[d] = queries[qi * D + d];
         ShortStack<KnnEntry> st(reinterpret_cast<KnnEntry *>(s_stack) + threadIdx.x, blockDim.x, stack_cap, spill);
         if (FMT == 1)
-            knn_search_q<D, K>(qnodes, n_nodes, leaves, kind, h, q, best, st, seed);
+            knn_search_q<D, K>(qnodes, n_nodes, leaves, kind, h, q, best, st, seed, nullptr);
         else if (FMT == 2)
             knn_search4<D, K>(nodes, wnodes, n_nodes, leaves, kind, h, q, best, st, seed, nullptr);
         else
@@ -342,8 +342,9 @@ arborx_status forest_reduce_impl(ForestDev &f, const float *q, int64_t m, const 
     const QNode<D> *qnodes = static_cast<const QNode<D> *>(f.qnodes);
     const Node4<D> *wnodes = static_cast<const Node4<D> *>(f.wnodes);
     const int nn = (int)(f.n > 0 ? f.n : 1);
+    const int fmt = node_format(OP_REDUCE, D, true);
     const int nq = tu.packet ? tu.packet : (D <= 3 ? 4 : 1);
-    if (tu.nodes == 0 && nq > 1) {
+    if (fmt == 0 && nq > 1) {
 #define AX_FRP(SD, N)                                                                                            \
     do {                                                                                                         \
         const int grid = persistent_grid((const void *)k_forest_reduce_packet<D, SD, N>, kForestBlock, lds);    \
@@ -373,16 +374,16 @@ arborx_status forest_reduce_impl(ForestDev &f, const float *q, int64_t m, const 
                                                                   counts, sums, counter, cap);                 \
     } while (0)
     if (op == ARBORX_COUNT_SUMDIST) {
-        if (tu.nodes == 1)
+        if (fmt == 1)
             AX_FREDUCE(true, 1);
-        else if (tu.nodes == 2)
+        else if (fmt == 2)
             AX_FREDUCE(true, 2);
         else
             AX_FREDUCE(true, 0);
     } else {
-        if (tu.nodes == 1)
+        if (fmt == 1)
             AX_FREDUCE(false, 1);
-        else if (tu.nodes == 2)
+        else if (fmt == 2)
             AX_FREDUCE(false, 2);
         else
             AX_FREDUCE(false, 0);
@@ -407,6 +408,7 @@ arborx_status forest_knn_launch(ForestDev &f, const float *q, int64_t m, const i
         return st;
     fill_kernel<unsigned long long><<<1, 64, 0, s>>>(counter, 1, 0ull);
     const Tuning &tu = tuning(OP_KNN);
+    const int fmt = node_format(OP_KNN, D, true);
     int block_unused = 0, cap = 0;
     launch_shape(OP_KNN, D, block_unused, cap);
     while (cap > 1 && (size_t)cap * kForestBlock * sizeof(KnnEntry) > 65536)
@@ -421,9 +423,9 @@ arborx_status forest_knn_launch(ForestDev &f, const float *q, int64_t m, const i
             static_cast<const Node4<D> *>(f.wnodes), (int)(f.n > 0 ? f.n : 1), f.leaves, f.kind, f.hdrs, f.T, q, m, \
             perm, boff, B, btree, k, d2, idx, counter, cap, tu.seed);                                              \
     } while (0)
-    if (tu.nodes == 1)
+    if (fmt == 1)
         AX_FKNN(1);
-    else if (tu.nodes == 2)
+    else if (fmt == 2)
         AX_FKNN(2);
     else
         AX_FKNN(0);
@@ -459,7 +461,7 @@ arborx_status forest_query_reduce(ForestDev &f, const float *q, int64_t m, const
 {
     if (m == 0)
         return ARBORX_OK;
-    arborx_status st = check_nodes(f.qnodes, f.wnodes, f.n, tuning(OP_REDUCE).nodes);
+    arborx_status st = check_nodes(f.qnodes, f.wnodes, f.n, node_format(OP_REDUCE, f.dim, true));
     if (st == ARBORX_OK)
         st = reserve_ws(f, m, s);
     if (st != ARBORX_OK)
@@ -477,7 +479,7 @@ arborx_status forest_query_knn(ForestDev &f, const float *q, int64_t m, const in
 {
     if (m == 0)
         return ARBORX_OK;
-    arborx_status st = check_nodes(f.qnodes, f.wnodes, f.n, tuning(OP_KNN).nodes);
+    arborx_status st = check_nodes(f.qnodes, f.wnodes, f.n, node_format(OP_KNN, f.dim, true));
     if (st == ARBORX_OK)
         st = reserve_ws(f, m, s);
     if (st != ARBORX_OK)

@@ -73,8 +73,12 @@ __device__ __forceinline__ void store_leaf(float *leaves, int64_t pos, int kind,
 // The same node with each child box stored as 16-bit codes in the tree's
 // frame (lo + code * qscale per dimension), rounded outward so that the
 // decoded box always contains the true one: tests on it are conservative.
-// A leaf child refers to its sorted leaf record (~position), whose exact
-// coordinates decide the match.  32 bytes in 3D, half the float node.
+// In a tree of points a leaf child is stored exactly instead: the point's D
+// float32 words take the 4*D bytes of that child's codes, and the reference
+// is ~value index as in the float node, so leaf tests need no second fetch
+// and give the float node's results bit for bit.  In a tree of boxes a leaf
+// child refers to its sorted leaf record (~position), whose exact box decides
+// the match.  32 bytes in 3D, half the float node; 64 bytes in 6D.
 template <int D>
 struct alignas(16) QNode {
     uint16_t q[2][2][D];  // [child][lo, hi][dim]
@@ -119,6 +123,24 @@ __device__ __forceinline__ void load_qnode(const QNode<D> *__restrict__ nodes, i
 #pragma unroll
     for (int k = 0; k < (int)(sizeof(QNode<D>) / 16); ++k)
         dst[k] = src[k];
+}
+
+// Child c of a quantized node as a box.  `exact` (a point tree's leaf child)
+// reads the stored point; otherwise the codes decode outward-rounded.  Both
+// forms are evaluated and selected, so the choice costs no branch.
+template <int D>
+__device__ __forceinline__ void qchild(const QNode<D> &nd, int c, bool exact, const float *flo, const float *fsc,
+                                       float (&lo)[D], float (&hi)[D])
+{
+    const uint16_t *qc = &nd.q[c][0][0];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const float p = __uint_as_float((uint32_t)qc[2 * d] | ((uint32_t)qc[2 * d + 1] << 16));
+        const float l = qdecode(qc[d], flo[d], fsc[d]);
+        const float h = qdecode(qc[D + d], flo[d], fsc[d]);
+        lo[d] = exact ? p : l;
+        hi[d] = exact ? p : h;
+    }
 }
 
 template <int D>

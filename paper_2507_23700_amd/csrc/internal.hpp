@@ -44,26 +44,32 @@ struct Tuning {
     int seed = 0;   // kNN starting bound: 0 k-th of 2k nearby leaves, 1 none, 2 farthest of k nearby leaves
     int nodes = 0;  // 0: binary float, 1: binary with quantized 16-bit child boxes (exact leaf tests), 2: four-wide
     int packet = 0; // radius walks on binary nodes: queries per thread (1, 2 or 4) walked together; 0 = by
-                    // operation and dimension (up to 3D, where neighbouring paths overlap most: 4 for the
-                    // fused reductions, 2 for the CSR count with its register rows; 1 in 6D)
+                    // operation, dimension and format (up to 3D, where neighbouring paths overlap most: for
+                    // the fused reductions 4 on float nodes, 2 on quantized ones; 2 for the CSR count; 1 in
+                    // 6D)
     bool by_dim = false;  // the library's defaults: block and stack also follow the dimension (launch_shape)
 };
 // Block size and short-stack depth a launch of `op` in dimension `dim` uses:
-// the tuning's, except that the library's defaults in 6D take the shapes the
-// autotuner picked on the 6D Gaussian mixture at 2*10^6 points (kNN: 256-thread
-// blocks, 16-entry ring, 10.2 -> 9.1 ms; reductions: 32-entry ring, 12.4 ->
-// 11.7 ms).
+// the tuning's, except that the library's defaults in 6D take the shapes
+// measured best on the 6D Gaussian mixture at 2*10^6 points over quantized
+// nodes (kNN: 64-thread blocks, 16-entry ring, 7.4 -> 6.7 ms; CSR count:
+// 64-thread blocks, 10.8 -> 10.2 ms; reductions keep the 3D shape).
 void launch_shape(int op, int dim, int &block, int &stack);
 // Tuning is kept per operation kind so the autotuner can pick each separately.
 enum Op { OP_SPATIAL = 0, OP_REDUCE = 1, OP_KNN = 2, OP_KINDS = 3 };
 const Tuning &tuning(int op = OP_SPATIAL);
 void set_tuning_op(int op, const Tuning &t);
+// Node format the thread schedule of `op` walks on a tree (or forest) of
+// dimension `dim`: the tuning's; under the library's defaults, also 1 for kNN
+// in 6D, and 0 for every forest walk.
+int node_format(int op, int dim, bool forest);
+int node_format_of(const Tuning &t, int op, int dim, bool forest);
 // Quantized (1) and four-wide (2) nodes are built only while some operation
-// asks for that format.
-bool format_requested(int format);
-// Node format a single-tree walk of `op` uses: the tuning's format for the
-// thread schedule (kNN: any schedule but the wavefront packet), else binary.
-int walk_format(int op);
+// asks for that format on a structure of this dimension and kind.
+bool format_requested(int format, int dim, bool forest);
+// Node format a single-tree walk of `op` uses: node_format for the thread
+// schedule (kNN: any schedule but the wavefront packet), else binary.
+int walk_format(int op, int dim);
 // ARBORX_E_INVALID unless the structure holds the nodes of format `fmt`.
 arborx_status check_nodes(const void *qnodes, const void *wnodes, int64_t n, int fmt);
 bool tree_has_format(arborx_tree tree, int format);

@@ -14,6 +14,7 @@
 // distance bit for bit.
 #include <mutex>
 #include <string>
+#include <type_traits>
 
 #include "device_util.hpp"
 #include "geometry.hpp"
@@ -65,6 +66,75 @@ __device__ __forceinline__ void overflow_add(const OverflowPool &o, int64_t qi, 
         o.dpool[cur + pos] = d2;  // the callback's output, in the parallel pool
 }
 
+// Stash row writer of the count walks.  Matches gather in a four-entry
+// register group that is stored into the query's stash row (one 16-byte
+// store, and one for the values) each time it fills, and once more for a
+// partial last group, so a match costs a four-way select instead of one over
+// the whole row.  Row entries past the count stay unwritten: every reader
+// masks the row by its count.
+template <bool OUT>
+struct StashGroup {
+    int g[4];
+    float dg[OUT ? 4 : 1];
+    __device__ __forceinline__ void add(int c, int idx, float d2, int32_t *row, float *drow)
+    {
+        const int k = c & 3;
+        append_at<4>(g, k, idx);
+        if constexpr (OUT)
+            append_at<4>(dg, k, d2);
+        if (k == 3)
+            flush(c - 3, row, drow);
+    }
+    __device__ __forceinline__ void flush(int base, int32_t *row, float *drow) const
+    {
+        *reinterpret_cast<int4 *>(row + base) = make_int4(g[0], g[1], g[2], g[3]);
+        if constexpr (OUT)
+            *reinterpret_cast<float4 *>(drow + base) = make_float4(dg[0], dg[1], dg[2], dg[3]);
+    }
+    // after the walk, for a row of c matches with a stash row of R
+    __device__ __forceinline__ void finish(int c, int R, int32_t *row, float *drow) const
+    {
+        if (c < R && (c & 3) != 0)
+            flush(c & ~3, row, drow);
+    }
+};
+
+// The other row writer, with the interface of StashGroup: the whole stash row
+// of R in registers, stored once after the walk.  The packet walk over float
+// nodes measured faster with it; the walks over quantized nodes and the
+// one-query walks, with the groups.
+template <int R, bool OUT>
+struct StashRegs {
+    int g[R];
+    float dg[OUT ? R : 1];
+    __device__ __forceinline__ StashRegs()
+    {
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            g[k] = 0;
+#pragma unroll
+        for (int k = 0; k < (OUT ? R : 1); ++k)
+            dg[k] = 0.0f;
+    }
+    __device__ __forceinline__ void add(int c, int idx, float d2, int32_t *, float *)
+    {
+        append_at<R>(g, c, idx);
+        if constexpr (OUT)
+            append_at<R>(dg, c, d2);
+    }
+    __device__ __forceinline__ void finish(int, int, int32_t *row, float *drow) const
+    {
+#pragma unroll
+        for (int k = 0; k < R / 4; ++k)
+            reinterpret_cast<int4 *>(row)[k] = make_int4(g[4 * k], g[4 * k + 1], g[4 * k + 2], g[4 * k + 3]);
+        if constexpr (OUT) {
+#pragma unroll
+            for (int k = 0; k < R / 4; ++k)
+                reinterpret_cast<float4 *>(drow)[k] = make_float4(dg[4 * k], dg[4 * k + 1], dg[4 * k + 2], dg[4 * k + 3]);
+        }
+    }
+};
+
 // Count pass of a CSR query.  With a stash, each query also keeps its first
 // stash_regs(D) matches in registers, in the order found, and stores them in
 // the stash row of its input position (one aligned 64-byte segment per
@@ -100,24 +170,16 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D
     int *wstack = s_stack + wave_id() * kWaveStack;
     constexpr int R = stash_regs(D);
     int c = 0;
-    int buf[R];
-    float dbuf[OUT ? R : 1];
-#pragma unroll
-    for (int k = 0; k < R; ++k)
-        buf[k] = 0;
-#pragma unroll
-    for (int k = 0; k < (OUT ? R : 1); ++k)
-        dbuf[k] = 0.0f;
+    StashGroup<OUT> grp;
+    int32_t *row = STASH ? stash + qi * R : nullptr;
+    float *drow = OUT ? stash_d2 + qi * R : nullptr;
     int32_t ov = -1;
     auto f = [&](int idx, float d2) {
         if (STASH) {
-            if (c < R) {
-                append_at<R>(buf, c, idx);
-                if constexpr (OUT)
-                    append_at<R>(dbuf, c, d2);
-            } else {
+            if (c < R)
+                grp.add(c, idx, d2, row, drow);
+            else
                 overflow_add<R, OUT>(ovf, qi, c, idx, d2, ov);
-            }
         }
         ++c;
     };
@@ -133,29 +195,20 @@ __global__ void k_spatial_count(const Node<D> *__restrict__ nodes, const QNode<D
         traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f);
     if (!active)
         return;
-    if (STASH) {
-        int4 *row = reinterpret_cast<int4 *>(stash + qi * R);
-#pragma unroll
-        for (int k = 0; k < R / 4; ++k)
-            row[k] = make_int4(buf[4 * k], buf[4 * k + 1], buf[4 * k + 2], buf[4 * k + 3]);
-        if constexpr (OUT) {
-            float4 *drow = reinterpret_cast<float4 *>(stash_d2 + qi * R);
-#pragma unroll
-            for (int k = 0; k < R / 4; ++k)
-                drow[k] = make_float4(dbuf[4 * k], dbuf[4 * k + 1], dbuf[4 * k + 2], dbuf[4 * k + 3]);
-        }
-    }
+    if (STASH)
+        grp.finish(c, R, row, drow);
     counts[qi] = c;
     if (ordered_counts)
         ordered_counts[t] = c;
 }
 
-// Packet form of the CSR count walk (sphere queries, binary nodes): thread t
-// answers the NQ queries at sorted positions NQ*t .. NQ*t + NQ - 1 in one walk,
-// each with its own register stash row.
-template <int D, int NQ, bool OUT = false>
+// Packet form of the CSR count walk (sphere queries, binary nodes, float or
+// quantized): thread t answers the NQ queries at sorted positions
+// NQ*t .. NQ*t + NQ - 1 in one walk, each with its own register stash row.
+template <int D, int NQ, bool OUT = false, bool Q = false>
 __global__ __attribute__((amdgpu_waves_per_eu(NQ == 2 && D <= 3 && !OUT ? 6 : 1))) void k_spatial_count_packet(
-    const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr, const float *__restrict__ queries,
+    const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes, const float *__restrict__ leaves,
+    int kind, const TreeHeader *__restrict__ hdr, const float *__restrict__ queries,
     int64_t m, float r2, const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
     int32_t *__restrict__ ordered_counts, int32_t *__restrict__ stash, float *__restrict__ stash_d2,
     OverflowPool ovf, int stack_cap)
@@ -179,17 +232,15 @@ __global__ __attribute__((amdgpu_waves_per_eu(NQ == 2 && D <= 3 && !OUT ? 6 : 1)
     int spill[kSpill];
     ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap, spill);
     int c[NQ];
-    int buf[NQ][R];
-    float dbuf[NQ][OUT ? R : 1];
+    using Row = typename std::conditional<Q, StashGroup<OUT>, StashRegs<R, OUT>>::type;
+    Row grp[NQ];
+    int32_t *row[NQ];
+    float *drow[NQ];
 #pragma unroll
     for (int j = 0; j < NQ; ++j) {
         c[j] = 0;
-#pragma unroll
-        for (int k = 0; k < R; ++k)
-            buf[j][k] = 0;
-#pragma unroll
-        for (int k = 0; k < (OUT ? R : 1); ++k)
-            dbuf[j][k] = 0.0f;
+        row[j] = stash + qi[j] * R;
+        drow[j] = OUT ? stash_d2 + qi[j] * R : nullptr;
     }
     int32_t ov[NQ];
 #pragma unroll
@@ -199,30 +250,21 @@ __global__ __attribute__((amdgpu_waves_per_eu(NQ == 2 && D <= 3 && !OUT ? 6 : 1)
 #pragma unroll
         for (int jj = 0; jj < NQ; ++jj)
             if (jj == j) {
-                if (c[jj] < R) {
-                    append_at<R>(buf[jj], c[jj], idx);
-                    if constexpr (OUT)
-                        append_at<R>(dbuf[jj], c[jj], d2);
-                } else {
+                if (c[jj] < R)
+                    grp[jj].add(c[jj], idx, d2, row[jj], drow[jj]);
+                else
                     overflow_add<R, OUT>(ovf, qi[jj], c[jj], idx, d2, ov[jj]);
-                }
                 ++c[jj];
             }
     };
-    traverse_spatial_packet<D, NQ>(nodes, hdr->root, node_count(hdr), pred, st, f);
+    if (Q)
+        traverse_spatial_packet_q<D, NQ>(qnodes, *hdr, node_count(hdr), leaves, kind, pred, st, f);
+    else
+        traverse_spatial_packet<D, NQ>(nodes, hdr->root, node_count(hdr), pred, st, f);
 #pragma unroll
     for (int j = 0; j < NQ; ++j)
         if (qi[j] < m) {
-            int4 *row = reinterpret_cast<int4 *>(stash + qi[j] * R);
-#pragma unroll
-            for (int k = 0; k < R / 4; ++k)
-                row[k] = make_int4(buf[j][4 * k], buf[j][4 * k + 1], buf[j][4 * k + 2], buf[j][4 * k + 3]);
-            if constexpr (OUT) {
-                float4 *drow = reinterpret_cast<float4 *>(stash_d2 + qi[j] * R);
-#pragma unroll
-                for (int k = 0; k < R / 4; ++k)
-                    drow[k] = make_float4(dbuf[j][4 * k], dbuf[j][4 * k + 1], dbuf[j][4 * k + 2], dbuf[j][4 * k + 3]);
-            }
+            grp[j].finish(c[j], R, row[j], drow[j]);
             counts[qi[j]] = c[j];
             if (ordered_counts)
                 ordered_counts[t * NQ + j] = c[j];
@@ -616,9 +658,12 @@ __global__ void k_spatial_reduce(const Node<D> *__restrict__ nodes, const QNode<
 }
 
 // Packet form of the fused reduction: thread t answers the NQ queries at
-// sorted positions NQ*t .. NQ*t + NQ - 1 in one walk over binary nodes.
-template <int D, bool SUMDIST, int NQ>
-__global__ void k_spatial_reduce_packet(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+// sorted positions NQ*t .. NQ*t + NQ - 1 in one walk over binary nodes
+// (float or quantized).
+template <int D, bool SUMDIST, int NQ, bool Q = false>
+__global__ void k_spatial_reduce_packet(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
+                                        const float *__restrict__ leaves, int kind,
+                                        const TreeHeader *__restrict__ hdr,
                                         const float *__restrict__ queries, int64_t m, float r2, float scale,
                                         const uint32_t *__restrict__ perm, int32_t *__restrict__ counts,
                                         int64_t *__restrict__ sums, int stack_cap)
@@ -656,7 +701,10 @@ __global__ void k_spatial_reduce_packet(const Node<D> *__restrict__ nodes, const
                     s[jj] += fixed_term(d2, scale);
             }
     };
-    traverse_spatial_packet<D, NQ>(nodes, hdr->root, node_count(hdr), pred, st, f);
+    if (Q)
+        traverse_spatial_packet_q<D, NQ>(qnodes, *hdr, node_count(hdr), leaves, kind, pred, st, f);
+    else
+        traverse_spatial_packet<D, NQ>(nodes, hdr->root, node_count(hdr), pred, st, f);
 #pragma unroll
     for (int j = 0; j < NQ; ++j)
         if (qi[j] < m) {
@@ -694,7 +742,7 @@ __global__ void k_knn(const Node<D> *__restrict__ nodes, const QNode<D> *__restr
         KnnEntry spill[kSpill];
         ShortStack<KnnEntry> st(reinterpret_cast<KnnEntry *>(s_stack) + threadIdx.x, blockDim.x, stack_cap, spill);
         if (FMT == 1)
-            knn_search_q<D, K>(qnodes, n_nodes, leaves, kind, *hdr, q, best, st, seed);
+            knn_search_q<D, K>(qnodes, n_nodes, leaves, kind, *hdr, q, best, st, seed, codes);
         else if (FMT == 2)
             knn_search4<D, K>(nodes, wnodes, n_nodes, leaves, kind, *hdr, q, best, st, seed, codes);
         else
@@ -871,10 +919,20 @@ Launch traversal_launch(int64_t m, size_t entry_bytes, int op, int dim, bool wav
 
 // Schedule 0 over quantized nodes runs as internal schedule 3, over four-wide
 // nodes as internal schedule 4.
-int effective_schedule(int op)
+// Node format a walk of `op` takes on tree t: walk_format's, except that the
+// library's defaults fall back to float nodes on a tree built without the
+// quantized ones (a request the caller made for a missing format is an error).
+int tree_format(int op, const TreeDev &t)
+{
+    const int f = walk_format(op, t.dim);
+    return (f == 1 && !t.qnodes && tuning(op).by_dim) ? 0 : f;
+}
+
+int effective_schedule(int op, const TreeDev &t)
 {
     const Tuning &tu = tuning(op);
-    return tu.schedule != 0 ? tu.schedule : (tu.nodes == 1 ? 3 : (tu.nodes == 2 ? 4 : 0));
+    const int fmt = tree_format(op, t);
+    return tu.schedule != 0 ? tu.schedule : (fmt == 1 ? 3 : (fmt == 2 ? 4 : 0));
 }
 
 template <int D>
@@ -882,27 +940,38 @@ arborx_status count_impl(const TreeDev &t, Pred pred, const float *q, int64_t m,
                          int32_t *counts, int32_t *ordered_counts, int32_t *stash, float *stash_d2,
                          const OverflowPool &ovf, hipStream_t s)
 {
-    const int sched = effective_schedule(OP_SPATIAL);
+    const int sched = effective_schedule(OP_SPATIAL, t);
     const int nq = tuning(OP_SPATIAL).packet ? tuning(OP_SPATIAL).packet : (D <= 3 ? 2 : 1);
     const bool out = stash_d2 != nullptr;  // the callback-with-output form (sphere queries only)
-    if (sched == 0 && nq > 1 && pred == Pred::Sphere) {  // NQ queries per thread over binary nodes
+    if ((sched == 0 || sched == 3) && nq > 1 && pred == Pred::Sphere) {  // NQ queries per thread, binary nodes
         const Launch L = traversal_launch((m + nq - 1) / nq, sizeof(int), OP_SPATIAL, D);
         const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
+        const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
         ProfScope ps("spatial_count", s);
-#define AX_CP(N, O) k_spatial_count_packet<D, N, O><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, perm, counts, \
-                                                                                  perm ? ordered_counts : nullptr,    \
-                                                                                  stash, stash_d2, ovf, L.cap)
+#define AX_CP(N, O, QF)                                                                                           \
+    k_spatial_count_packet<D, N, O, QF><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, t.leaves, t.kind, t.hdr, q, m, \
+                                                                       r2, perm, counts,                            \
+                                                                       perm ? ordered_counts : nullptr, stash,      \
+                                                                       stash_d2, ovf, L.cap)
+#define AX_CPQ(N, O)         \
+    do {                     \
+        if (sched == 3)      \
+            AX_CP(N, O, true); \
+        else                 \
+            AX_CP(N, O, false); \
+    } while (0)
         if (nq == 2) {
             if (out)
-                AX_CP(2, true);
+                AX_CPQ(2, true);
             else
-                AX_CP(2, false);
+                AX_CPQ(2, false);
         } else {
             if (out)
-                AX_CP(4, true);
+                AX_CPQ(4, true);
             else
-                AX_CP(4, false);
+                AX_CPQ(4, false);
         }
+#undef AX_CPQ
 #undef AX_CP
         AX_HIP(hipGetLastError());
         return ARBORX_OK;
@@ -991,7 +1060,7 @@ arborx_status fill_rows_impl(const TreeDev &t, Pred pred, const float *q, int64_
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
     const Node4<D> *wnodes = static_cast<const Node4<D> *>(t.wnodes);
-    const int fmt = walk_format(OP_SPATIAL);
+    const int fmt = tree_format(OP_SPATIAL, t);
     ProfScope ps("spatial_fill", s);
 #define AX_FILL(P, F)                                                                                              \
     k_spatial_fill_rows<D, P, F><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, wnodes, t.leaves, t.kind, t.hdr, q, m, r2, \
@@ -1027,25 +1096,35 @@ template <int D>
 arborx_status reduce_impl(const TreeDev &t, const float *q, int64_t m, float r2, int op, float scale,
                           const uint32_t *perm, int32_t *counts, int64_t *sums, hipStream_t s)
 {
-    const int sched = effective_schedule(OP_REDUCE);
-    const int nq = tuning(OP_REDUCE).packet ? tuning(OP_REDUCE).packet : (D <= 3 ? 4 : 1);
-    if (sched == 0 && nq > 1) {  // NQ queries per thread over binary nodes
+    const int sched = effective_schedule(OP_REDUCE, t);
+    const int nq = tuning(OP_REDUCE).packet ? tuning(OP_REDUCE).packet : (D <= 3 ? (sched == 3 ? 2 : 4) : 1);
+    if ((sched == 0 || sched == 3) && nq > 1) {  // NQ queries per thread over binary nodes
         const Launch L = traversal_launch((m + nq - 1) / nq, sizeof(int), OP_REDUCE, D);
         const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
+        const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
         ProfScope ps(op == ARBORX_COUNT_SUMDIST ? "reduce_sumdist" : "reduce_count", s);
-#define AX_RP(SD, N) k_spatial_reduce_packet<D, SD, N><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, q, m, r2, scale, \
-                                                                                   perm, counts, sums, L.cap)
+#define AX_RP(SD, N, QF)                                                                                       \
+    k_spatial_reduce_packet<D, SD, N, QF><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, t.leaves, t.kind, t.hdr, q, \
+                                                                         m, r2, scale, perm, counts, sums, L.cap)
+#define AX_RPQ(SD, N)          \
+    do {                       \
+        if (sched == 3)        \
+            AX_RP(SD, N, true);  \
+        else                   \
+            AX_RP(SD, N, false); \
+    } while (0)
         if (op == ARBORX_COUNT_SUMDIST) {
             if (nq == 2)
-                AX_RP(true, 2);
+                AX_RPQ(true, 2);
             else
-                AX_RP(true, 4);
+                AX_RPQ(true, 4);
         } else {
             if (nq == 2)
-                AX_RP(false, 2);
+                AX_RPQ(false, 2);
             else
-                AX_RP(false, 4);
+                AX_RPQ(false, 4);
         }
+#undef AX_RPQ
 #undef AX_RP
         AX_HIP(hipGetLastError());
         return ARBORX_OK;
@@ -1086,7 +1165,7 @@ arborx_status knn_launch(const TreeDev &t, const float *q, int64_t m, int k, con
                          int32_t *idx, hipStream_t s)
 {
     const bool wave = tuning(OP_KNN).schedule == 1;  // kNN has no rope form: schedule 2 walks with the stack
-    const int fmt = walk_format(OP_KNN);
+    const int fmt = tree_format(OP_KNN, t);
     const Launch L = traversal_launch(m, sizeof(KnnEntry), OP_KNN, D, wave);
     const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
     const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
@@ -1192,7 +1271,7 @@ arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, i
         return ARBORX_OK;
     if (t.n == 0)
         return fill_async<int32_t>(counts, m, 0, s);
-    arborx_status st = check_nodes(t.qnodes, t.wnodes, t.n, walk_format(OP_SPATIAL));
+    arborx_status st = check_nodes(t.qnodes, t.wnodes, t.n, tree_format(OP_SPATIAL, t));
     if (st != ARBORX_OK)
         return st;
     if ((st = fill_async<unsigned long long>(ovf.ctr, (int64_t)kOvfPools * 8, 0ull, s)) != ARBORX_OK)
@@ -1219,7 +1298,7 @@ arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, in
 {
     if (m == 0 || t.n == 0)
         return ARBORX_OK;
-    arborx_status st = check_nodes(t.qnodes, t.wnodes, t.n, walk_format(OP_SPATIAL));
+    arborx_status st = check_nodes(t.qnodes, t.wnodes, t.n, tree_format(OP_SPATIAL, t));
     if (st != ARBORX_OK)
         return st;
     {
@@ -1356,7 +1435,7 @@ arborx_status spatial_reduce(const TreeDev &t, const float *queries, int64_t m, 
             st = fill_async<int64_t>(sums, m, 0, s);
         return st;
     }
-    arborx_status st = check_nodes(t.qnodes, t.wnodes, t.n, walk_format(OP_REDUCE));
+    arborx_status st = check_nodes(t.qnodes, t.wnodes, t.n, tree_format(OP_REDUCE, t));
     if (st != ARBORX_OK)
         return st;
     const float r2 = radius * radius;
@@ -1416,7 +1495,7 @@ arborx_status knn_query(const TreeDev &t, const float *queries, int64_t m, int k
         AX_HIP(hipGetLastError());
         return ARBORX_OK;
     }
-    arborx_status st = check_nodes(t.qnodes, t.wnodes, t.n, walk_format(OP_KNN));
+    arborx_status st = check_nodes(t.qnodes, t.wnodes, t.n, tree_format(OP_KNN, t));
     if (st != ARBORX_OK)
         return st;
     AX_DISPATCH_DIM(t.dim, (knn_impl<D>(t, queries, m, k, perm, dist2, indices, s)));

@@ -519,28 +519,27 @@ __device__ __forceinline__ void traverse_pairs_packet(const Node<D> *__restrict_
     }
 }
 
-// Decode both child boxes of a quantized node in the tree's frame.
+// Both child boxes of a quantized node in the tree's frame; `points` says the
+// tree holds points, whose leaf children are stored exactly.
 template <int D>
-__device__ __forceinline__ void qboxes(const QNode<D> &nd, const float *flo, const float *fsc, float (&lo)[2][D],
-                                       float (&hi)[2][D])
+__device__ __forceinline__ void qboxes(const QNode<D> &nd, bool points, const float *flo, const float *fsc,
+                                       float (&lo)[2][D], float (&hi)[2][D])
 {
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            lo[c][d] = qdecode(nd.q[c][0][d], flo[d], fsc[d]);
-            hi[c][d] = qdecode(nd.q[c][1][d], flo[d], fsc[d]);
-        }
+    qchild<D>(nd, 0, points && nd.child[0] < 0, flo, fsc, lo[0], hi[0]);
+    qchild<D>(nd, 1, points && nd.child[1] < 0, flo, fsc, lo[1], hi[1]);
 }
 
-// The short-stack walk over quantized nodes.  Child boxes decode to supersets
-// of the true boxes, so no matching subtree is skipped; a leaf whose decoded
-// box passes is then tested exactly on its leaf record.
+// The short-stack walk over quantized nodes.  Internal child boxes decode to
+// supersets of the true boxes, so no matching subtree is skipped.  A point
+// tree's leaf child is exact in the node and reported from it; a box tree's
+// leaf whose decoded box passes is tested exactly on its leaf record.  (An
+// empty slot's bytes are never reported: its reference is checked first.)
 template <int D, class P, class F>
 __device__ __forceinline__ void traverse_spatial_q(const QNode<D> *__restrict__ nodes, const TreeHeader &h,
                                                    int n_nodes, const float *__restrict__ leaves, int kind,
                                                    const P &pred, ShortStack<int> &st, F &f)
 {
+    const bool points = kind != ARBORX_BOXES;
     float flo[D], fsc[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -554,19 +553,27 @@ __device__ __forceinline__ void traverse_spatial_q(const QNode<D> *__restrict__ 
         QNode<D> nd;
         load_qnode(nodes, cur, nd);
         float lo[2][D], hi[2][D];
-        qboxes<D>(nd, flo, fsc, lo, hi);
+        qboxes<D>(nd, points, flo, fsc, lo, hi);
         float d0, d1;
         bool h0 = pred.hit(lo[0], hi[0], d0);
         bool h1 = pred.hit(lo[1], hi[1], d1);
         const int c0 = nd.child[0], c1 = nd.child[1];
         if (h0 && c0 < 0) {
-            if (c0 != kEmptyRef)
-                leaf_exact<D>(leaves, kind, ~c0, pred, f);
+            if (c0 != kEmptyRef) {
+                if (points)
+                    f(~c0, d0);
+                else
+                    leaf_exact<D>(leaves, kind, ~c0, pred, f);
+            }
             h0 = false;
         }
         if (h1 && c1 < 0) {
-            if (c1 != kEmptyRef)
-                leaf_exact<D>(leaves, kind, ~c1, pred, f);
+            if (c1 != kEmptyRef) {
+                if (points)
+                    f(~c1, d1);
+                else
+                    leaf_exact<D>(leaves, kind, ~c1, pred, f);
+            }
             h1 = false;
         }
         if (h0) {
@@ -574,6 +581,68 @@ __device__ __forceinline__ void traverse_spatial_q(const QNode<D> *__restrict__ 
                 st.push(c1);
             cur = c0;
         } else if (h1) {
+            cur = c1;
+        } else {
+            if (st.empty())
+                break;
+            cur = st.pop();
+        }
+    }
+}
+
+// Packet walk over quantized nodes: as traverse_spatial_packet, one decode
+// of the node's child boxes serving all NQ queries; leaves as in
+// traverse_spatial_q.
+template <int D, int NQ, class P, class F>
+__device__ __forceinline__ void traverse_spatial_packet_q(const QNode<D> *__restrict__ nodes, const TreeHeader &h,
+                                                          int n_nodes, const float *__restrict__ leaves, int kind,
+                                                          const P (&pred)[NQ], ShortStack<int> &st, F &f)
+{
+    const bool points = kind != ARBORX_BOXES;
+    float flo[D], fsc[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        flo[d] = h.lo[d];
+        fsc[d] = h.qscale[d];
+    }
+    int cur = h.root;
+    for (int iter = 0; iter <= n_nodes; ++iter) {
+        if ((unsigned)cur >= (unsigned)n_nodes)
+            break;
+        QNode<D> nd;
+        load_qnode(nodes, cur, nd);
+        float lo[2][D], hi[2][D];
+        qboxes<D>(nd, points, flo, fsc, lo, hi);
+        const int c0 = nd.child[0], c1 = nd.child[1];
+        bool g0 = false, g1 = false;
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) {
+            float d0, d1;
+            const bool h0 = pred[j].hit(lo[0], hi[0], d0);
+            const bool h1 = pred[j].hit(lo[1], hi[1], d1);
+            auto fj = [&](int idx, float d) { f(j, idx, d); };
+            if (h0 && c0 < 0 && c0 != kEmptyRef) {
+                if (points)
+                    f(j, ~c0, d0);
+                else
+                    leaf_exact<D>(leaves, kind, ~c0, pred[j], fj);
+            }
+            if (h1 && c1 < 0 && c1 != kEmptyRef) {
+                if (points)
+                    f(j, ~c1, d1);
+                else
+                    leaf_exact<D>(leaves, kind, ~c1, pred[j], fj);
+            }
+            g0 = g0 | h0;
+            g1 = g1 | h1;
+        }
+        g0 = g0 && c0 >= 0;
+        g1 = g1 && c1 >= 0;
+        if (g0) {
+            if (g1)
+                st.push(c1);
+            cur = c0;
+        } else if (g1) {
             cur = c1;
         } else {
             if (st.empty())
@@ -1105,40 +1174,42 @@ best.reset(INFINITY);
     }
 }
 
-// kNN over quantized nodes: as knn_search, pruning with the decoded (larger)
-// boxes and offering leaves with exact distances from their records.
+// kNN over quantized nodes: as knn_search (seeded, software-pipelined),
+// pruning with the decoded (larger) internal boxes.  A point tree's leaves are
+// offered with their exact distances from the node; a box tree's leaves that
+// pass the bound are offered from their records.
 template <int D, int K>
 __device__ __forceinline__ void knn_search_q(const QNode<D> *__restrict__ nodes, int n_nodes,
                                              const float *__restrict__ leaves, int kind, const TreeHeader &hdr,
                                              const float *q, TopK<K> &best, ShortStack<KnnEntry> &st,
-                                             int seed)
+                                             int seed, const uint64_t *__restrict__ codes)
 {
     const int n = hdr.n;
-best.reset(INFINITY);
+    best.reset(INFINITY);
     if (n <= 0)
         return;
+    const bool points = kind != ARBORX_BOXES;
     float flo[D], fsc[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         flo[d] = hdr.lo[d];
         fsc[d] = hdr.qscale[d];
     }
-    const int lf = leaf_floats(D, kind);
     if (seed != 1 && n >= K) {
-        int cur = hdr.root, pos = hdr.start;
+        int cur = codes ? -1 : hdr.root, pos = codes ? leaf_position<D>(codes, hdr, q) : hdr.start;
         for (int iter = 0; iter <= n_nodes; ++iter) {
             if ((unsigned)cur >= (unsigned)n_nodes)
                 break;
             QNode<D> nd;
             load_qnode(nodes, cur, nd);
             float lo[2][D], hi[2][D];
-            qboxes<D>(nd, flo, fsc, lo, hi);
+            qboxes<D>(nd, points, flo, fsc, lo, hi);
             const float d0 = box_d2<D>(q, lo[0], hi[0]);
             const float d1 = box_d2<D>(q, lo[1], hi[1]);
             const int go = (d1 < d0 && nd.child[1] != kEmptyRef) ? 1 : 0;
             const int c = go ? nd.child[1] : nd.child[0];
             if (c < 0) {
-                pos = ~c;
+                pos = cur + go;  // node cur separates sorted leaves cur and cur + 1
                 break;
             }
             cur = c;
@@ -1146,51 +1217,53 @@ best.reset(INFINITY);
         seed_window<D, K>(leaves, kind, hdr, pos, q, best, seed);
     }
     int cur = hdr.root;
+    QNode<D> nd;
+    if ((unsigned)cur < (unsigned)n_nodes)
+        load_qnode(nodes, cur, nd);
     for (int iter = 0; iter <= n_nodes; ++iter) {
         if ((unsigned)cur >= (unsigned)n_nodes)
             break;
-        QNode<D> nd;
-        load_qnode(nodes, cur, nd);
         float lo[2][D], hi[2][D];
-        qboxes<D>(nd, flo, fsc, lo, hi);
+        qboxes<D>(nd, points, flo, fsc, lo, hi);
         const float d0 = box_d2<D>(q, lo[0], hi[0]);
         const float d1 = box_d2<D>(q, lo[1], hi[1]);
         const int c0 = nd.child[0], c1 = nd.child[1];
-        if (c0 < 0 && c0 != kEmptyRef && !(d0 > best.bound())) {
-            const float *r = leaves + (int64_t)(~c0) * lf;
-            best.offer(leaf_d2<D>(leaves, kind, ~c0, q), __float_as_int(r[kind == ARBORX_BOXES ? 2 * D : D]));
-        }
-        if (c1 < 0 && c1 != kEmptyRef && !(d1 > best.bound())) {
-            const float *r = leaves + (int64_t)(~c1) * lf;
-            best.offer(leaf_d2<D>(leaves, kind, ~c1, q), __float_as_int(r[kind == ARBORX_BOXES ? 2 * D : D]));
-        }
-        const bool k0 = c0 >= 0 && !(d0 > best.bound());
-        const bool k1 = c1 >= 0 && !(d1 > best.bound());
+        const float bound = best.bound();
+        const bool k0 = c0 >= 0 && !(d0 > bound);
+        const bool k1 = c1 >= 0 && !(d1 > bound);
+        int next = -1;
         if (k0 && k1) {
-            if (d1 < d0) {
-                st.push(KnnEntry{c0, d0});
-                cur = c1;
-            } else {
-                st.push(KnnEntry{c1, d1});
-                cur = c0;
-            }
+            const bool near1 = d1 < d0;
+            st.push(near1 ? KnnEntry{c0, d0} : KnnEntry{c1, d1});
+            next = near1 ? c1 : c0;
         } else if (k0) {
-            cur = c0;
+            next = c0;
         } else if (k1) {
-            cur = c1;
+            next = c1;
         } else {
-            bool found = false;
             while (!st.empty()) {
                 const KnnEntry e = st.pop();
-                if (!(e.d2 > best.bound())) {
-                    cur = e.ref;
-                    found = true;
+                if (!(e.d2 > bound)) {
+                    next = e.ref;
                     break;
                 }
             }
-            if (!found)
-                break;
         }
+        if ((unsigned)next < (unsigned)n_nodes)
+            load_qnode(nodes, next, nd);  // in flight during the insertions below
+        if (points) {
+            if (c0 < 0 && c0 != kEmptyRef)
+                best.offer(d0, ~c0);
+            if (c1 < 0 && c1 != kEmptyRef)
+                best.offer(d1, ~c1);
+        } else {
+            const int lf = leaf_floats(D, kind);
+            if (c0 < 0 && c0 != kEmptyRef && !(d0 > best.bound()))
+                best.offer(leaf_d2<D>(leaves, kind, ~c0, q), __float_as_int(leaves[(int64_t)(~c0) * lf + 2 * D]));
+            if (c1 < 0 && c1 != kEmptyRef && !(d1 > best.bound()))
+                best.offer(leaf_d2<D>(leaves, kind, ~c1, q), __float_as_int(leaves[(int64_t)(~c1) * lf + 2 * D]));
+        }
+        cur = next;
     }
 }
 

@@ -99,7 +99,7 @@ def test_tuning_validation_and_roundtrip():
     assert L.arborx_set_tuning(ctypes.byref(_lib.Tuning(0, 1, 12, 0, 0, 0, 0))) == 1
     assert L.arborx_set_tuning(None) == 0
     assert L.arborx_get_tuning(ctypes.byref(g)) == 0
-    assert (g.block, g.order, g.stack, g.build, g.seed_mode, g.node_format) == (256, 1, 16, 0, 0, 0)
+    assert (g.block, g.order, g.stack, g.build, g.seed_mode, g.node_format, g.queries_per_thread) == (256, 1, 16, 0, 0, 1, 1)
 
 
 def test_debug_entry_validation():

@@ -206,6 +206,33 @@ def test_chunked_and_single_pass_builds_identical(n):
     _tree_invariants(t6, g6)
 
 
+@pytest.mark.parametrize("n,dim,boxes", [(1025, 3, False), (70_001, 3, False), (5000, 6, False), (4000, 3, True),
+                                         (1, 3, False)])
+def test_quantized_nodes_both_builds(n, dim, boxes):
+    # quantized nodes over trees from the single-pass and the chunked climb (equal codes across chunk borders,
+    # box leaves refetched, a one-value tree): walks over them give the oracle's results
+    g = np.random.default_rng(n + dim)
+    c = g.random((n, dim)).astype(np.float32)
+    c[n // 3:n // 3 + n // 5] = c[0]  # equal codes across chunk borders
+    if boxes:
+        h = (g.random((n, dim)) * 0.01).astype(np.float32)
+        data, kind = np.ascontiguousarray(np.stack([c - h, c + h], axis=1)), oracle.BOXES
+    else:
+        data, kind = c, oracle.POINTS
+    q = g.random((700, dim)).astype(np.float32)
+    r = 0.05 if dim == 3 else 0.4
+    for build in (1, 0):
+        ax.arborx_set_tuning(build=build, node_format=1)
+        try:
+            t = ax.arborx_bvh_build(dev(data), ax.BOXES if boxes else ax.POINTS)
+            check_spatial(t, data, q, r, dim=dim, kind=kind)
+            check_knn(t, data, q, min(n, 7), dim=dim, kind=kind)
+            if not boxes:
+                check_reduce(t, data, q, r, dim=dim)
+        finally:
+            ax.arborx_reset_tuning()
+
+
 def test_tree_invariants_duplicates_and_boxes():
     g = np.random.default_rng(1)
     data = g.random((3000, 3)).astype(np.float32)
@@ -647,7 +674,15 @@ def test_quantized_boxes_and_dims():
 @pytest.mark.parametrize("fmt", [1, 2])
 def test_node_format_request_needs_that_build(fmt):
     cfg = inputs.config_small(n=3000, m=200)
-    t = ax.arborx_bvh_build(dev(cfg["data"]))
+    ax.arborx_set_tuning(node_format=0)  # a tree with float nodes only
+    try:
+        t = ax.arborx_bvh_build(dev(cfg["data"]))
+    finally:
+        ax.arborx_reset_tuning()
+    # the library's defaults walk quantized nodes where a tree has them, float nodes where it has not
+    check_spatial(t, cfg["data"], cfg["queries"], 0.05)
+    check_reduce(t, cfg["data"], cfg["queries"], 0.05)
+    check_knn(t, cfg["data"], cfg["queries"], 4)
     ax.arborx_set_tuning(node_format=fmt)
     try:
         with pytest.raises(ax.ArborXError, match="built without"):
