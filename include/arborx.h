@@ -77,14 +77,21 @@ typedef struct arborx_tuning {
                              query's Morton position (default), 1 = none (+inf), 2 = the largest distance
                              among the k leaves around it */
     int32_t node_format;  /* node layout walked by the thread schedule (schedule 0): 0 = binary nodes with float
-                             child boxes (default); 1 = binary nodes with child boxes as 16-bit codes rounded
-                             outward, leaves decided on their exact records; 2 = four-wide nodes (two levels
-                             per fetch).  Formats 1 and 2 are built only while some operation asks for them
-                             when the tree is built; asking later is ARBORX_E_INVALID */
+                             child boxes; 1 = binary nodes with internal child boxes as 16-bit codes rounded
+                             outward (32 bytes in 3D), a point tree's leaf children stored exactly in the node
+                             and a box tree's decided on their exact records; 2 = four-wide nodes (two levels
+                             per fetch).  Every format gives identical results.  Formats 1 and 2 are built only
+                             while some operation asks for them when the tree is built; asking later is
+                             ARBORX_E_INVALID.  The defaults (arborx_set_tuning(NULL)): 1 for ARBORX_OP_SPATIAL
+                             and ARBORX_OP_REDUCE, 0 for ARBORX_OP_KNN, over trees of points; under them a 6D
+                             kNN over points also walks format 1, while trees of boxes, forests and a tree built
+                             without format 1 are walked on format 0 */
     int32_t queries_per_thread; /* radius searches (CSR count pass of sphere queries, fused reductions) with
                                    the thread schedule on binary nodes: 1, 2 or 4 Morton-neighbouring queries
                                    answered by one thread in one walk over the union of their paths; 0 = by
-                                   operation and dimension (up to 3D: 2 for CSR, 4 for reductions; 1 in 6D) */
+                                   operation, dimension and format (up to 3D: 2 for CSR; for reductions 4 on
+                                   format 0, 2 on format 1; 1 in 6D).  Defaults: 1 for ARBORX_OP_SPATIAL, 0
+                                   otherwise */
 } arborx_tuning;
 
 /* Operation kinds that carry their own tuning. */

@@ -159,7 +159,7 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
             best->build = cached.build;
             best->seed_mode = cached.seed;
             best->queries_per_thread = cached.packet;
-            best->node_format = node_format_of(cached, op, dim, false);
+            best->node_format = node_format_of(cached, op, dim, kind, false);
         }
         if (best_ms)
             *best_ms = -1.0;
@@ -334,7 +334,7 @@ extern "C" arborx_status arborx_autotune(arborx_tree tree, int32_t op, const flo
         best->build = b.build;
         best->seed_mode = b.seed;
         best->queries_per_thread = b.packet;
-        best->node_format = node_format_of(b, op, dim, false);
+        best->node_format = node_format_of(b, op, dim, kind, false);
     }
     if (best_ms)
         *best_ms = cands[besti].ms;
@@ -366,6 +366,7 @@ extern "C" arborx_status arborx_autotune_forest(arborx_forest forest, int32_t op
     if (st != ARBORX_OK)
         return st;
     const std::string key = "forest " + cache_key(op, dim, 0, k, n, m);
+    const int fkind = ARBORX_POINTS;  // under the defaults every forest walks format 0, whatever its values
     const Tuning base = tuning(op);
     Tuning cached = base;
     if (cache_lookup(key, cached)) {
@@ -378,7 +379,7 @@ extern "C" arborx_status arborx_autotune_forest(arborx_forest forest, int32_t op
             best->build = cached.build;
             best->seed_mode = cached.seed;
             best->queries_per_thread = cached.packet;
-            best->node_format = node_format_of(cached, op, dim, true);
+            best->node_format = node_format_of(cached, op, dim, fkind, true);
         }
         if (best_ms)
             *best_ms = -1.0;
@@ -387,7 +388,7 @@ extern "C" arborx_status arborx_autotune_forest(arborx_forest forest, int32_t op
     std::vector<Candidate> cands;
     cands.push_back(Candidate{base, 0});
     Tuning fbase = base;  // the others start from the node format the forest walks under the tuning in force
-    fbase.nodes = node_format_of(base, op, dim, true);
+    fbase.nodes = node_format_of(base, op, dim, fkind, true);
     for (int stack : {4, 8, 16, 32}) {
         Candidate c{fbase, 0};
         c.t.stack = stack;
@@ -497,7 +498,7 @@ extern "C" arborx_status arborx_autotune_forest(arborx_forest forest, int32_t op
         best->build = b.build;
         best->seed_mode = b.seed;
         best->queries_per_thread = b.packet;
-        best->node_format = node_format_of(b, op, dim, true);
+        best->node_format = node_format_of(b, op, dim, fkind, true);
     }
     if (best_ms)
         *best_ms = cands[besti].ms;

@@ -797,7 +797,7 @@ arborx_status build_impl(const float *values, int64_t n, int kind, TreeDev &t, h
     st = dalloc((void **)&t.leaves, (size_t)n * leaf_floats(D, kind) * sizeof(float), s);
     if (st != ARBORX_OK)
         return st;
-    const bool quantized = format_requested(1, D, false), wide = format_requested(2, D, false);
+    const bool quantized = format_requested(1, D, kind, false), wide = format_requested(2, D, kind, false);
     if (quantized && (st = dalloc(&t.qnodes, (size_t)nn * sizeof(QNode<D>), s)) != ARBORX_OK)
         return st;
     if (wide && (st = dalloc(&t.wnodes, (size_t)nn * sizeof(Node4<D>), s)) != ARBORX_OK)
@@ -1180,9 +1180,10 @@ arborx_status forest_alloc_impl(int64_t n, int T, int kind, ForestDev &f, hipStr
         (st = dalloc((void **)&f.leaves, (size_t)(n > 0 ? n : 1) * leaf_floats(D, kind) * sizeof(float), s)) !=
             ARBORX_OK)
         return st;
-    if (format_requested(1, D, true) && (st = dalloc(&f.qnodes, (size_t)(n > 0 ? n : 1) * sizeof(QNode<D>), s)) != ARBORX_OK)
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    if (format_requested(1, D, kind, true) && (st = dalloc(&f.qnodes, nn * sizeof(QNode<D>), s)) != ARBORX_OK)
         return st;
-    if (format_requested(2, D, true) && (st = dalloc(&f.wnodes, (size_t)(n > 0 ? n : 1) * sizeof(Node4<D>), s)) != ARBORX_OK)
+    if (format_requested(2, D, kind, true) && (st = dalloc(&f.wnodes, nn * sizeof(Node4<D>), s)) != ARBORX_OK)
         return st;
     f.bws_bytes = forest_build_ws<D>(n, T, f.max_tiles, nullptr, nullptr);
     return dalloc(&f.bws, f.bws_bytes, s);

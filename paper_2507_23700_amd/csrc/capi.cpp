@@ -119,10 +119,11 @@ namespace ax {
 static thread_local std::string g_error;
 // Defaults measured on MI355X at 10^7 points: 256-thread blocks for the radius
 // walks; 64-thread blocks and an 8-entry LDS ring for kNN (its 8-byte stack
-// entries and larger register set).  The radius walks run over quantized nodes
-// (half the node loads; a point's leaf is exact in its parent), the CSR count
-// one query per thread; kNN over float nodes up to 3D, where its top-k
-// insertions rather than node loads bound it (node_format below).
+// entries and larger register set).  Over trees of points the radius walks
+// run over quantized nodes (half the node loads; a point's leaf is exact in
+// its parent), the CSR count one query per thread; kNN over float nodes up to
+// 3D, where its top-k insertions rather than node loads bound it
+// (node_format_of below).
 static Tuning default_tuning(int op)
 {
     Tuning t;
@@ -158,21 +159,21 @@ static bool g_pool_ready[64] = {};
 
 const Tuning &tuning(int op) { return g_tuning[op >= 0 && op < OP_KINDS ? op : 0]; }
 
-int node_format_of(const Tuning &t, int op, int dim, bool forest)
+int node_format_of(const Tuning &t, int op, int dim, int kind, bool forest)
 {
     if (!t.by_dim)
         return t.nodes;
-    if (forest)
+    if (forest || kind == ARBORX_BOXES)  // a box leaf is not exact in the node: its record is fetched again
         return 0;
     return op == OP_KNN && dim >= 6 ? 1 : t.nodes;
 }
 
-int node_format(int op, int dim, bool forest) { return node_format_of(tuning(op), op, dim, forest); }
+int node_format(int op, int dim, int kind, bool forest) { return node_format_of(tuning(op), op, dim, kind, forest); }
 
-bool format_requested(int format, int dim, bool forest)
+bool format_requested(int format, int dim, int kind, bool forest)
 {
     for (int op = 0; op < OP_KINDS; ++op)
-        if (node_format(op, dim, forest) == format)
+        if (node_format(op, dim, kind, forest) == format)
             return true;
     return false;
 }
@@ -187,11 +188,11 @@ bool forest_has_format(arborx_forest forest, int format)
     return forest && (format == 0 || (format == 1 && forest->dev.qnodes) || (format == 2 && forest->dev.wnodes));
 }
 
-int walk_format(int op, int dim)
+int walk_format(int op, int dim, int kind)
 {
     const Tuning &t = tuning(op);
     const bool thread_walk = op == OP_KNN ? t.schedule != 1 : t.schedule == 0;  // kNN has no rope walk
-    return thread_walk ? node_format(op, dim, false) : 0;
+    return thread_walk ? node_format(op, dim, kind, false) : 0;
 }
 
 arborx_status check_nodes(const void *qnodes, const void *wnodes, int64_t n, int fmt)

@@ -342,7 +342,7 @@ arborx_status forest_reduce_impl(ForestDev &f, const float *q, int64_t m, const 
     const QNode<D> *qnodes = static_cast<const QNode<D> *>(f.qnodes);
     const Node4<D> *wnodes = static_cast<const Node4<D> *>(f.wnodes);
     const int nn = (int)(f.n > 0 ? f.n : 1);
-    const int fmt = node_format(OP_REDUCE, D, true);
+    const int fmt = node_format(OP_REDUCE, D, f.kind, true);
     const int nq = tu.packet ? tu.packet : (D <= 3 ? 4 : 1);
     if (fmt == 0 && nq > 1) {
 #define AX_FRP(SD, N)                                                                                            \
@@ -408,7 +408,7 @@ arborx_status forest_knn_launch(ForestDev &f, const float *q, int64_t m, const i
         return st;
     fill_kernel<unsigned long long><<<1, 64, 0, s>>>(counter, 1, 0ull);
     const Tuning &tu = tuning(OP_KNN);
-    const int fmt = node_format(OP_KNN, D, true);
+    const int fmt = node_format(OP_KNN, D, f.kind, true);
     int block_unused = 0, cap = 0;
     launch_shape(OP_KNN, D, block_unused, cap);
     while (cap > 1 && (size_t)cap * kForestBlock * sizeof(KnnEntry) > 65536)
@@ -461,7 +461,7 @@ arborx_status forest_query_reduce(ForestDev &f, const float *q, int64_t m, const
 {
     if (m == 0)
         return ARBORX_OK;
-    arborx_status st = check_nodes(f.qnodes, f.wnodes, f.n, node_format(OP_REDUCE, f.dim, true));
+    arborx_status st = check_nodes(f.qnodes, f.wnodes, f.n, node_format(OP_REDUCE, f.dim, f.kind, true));
     if (st == ARBORX_OK)
         st = reserve_ws(f, m, s);
     if (st != ARBORX_OK)
@@ -479,7 +479,7 @@ arborx_status forest_query_knn(ForestDev &f, const float *q, int64_t m, const in
 {
     if (m == 0)
         return ARBORX_OK;
-    arborx_status st = check_nodes(f.qnodes, f.wnodes, f.n, node_format(OP_KNN, f.dim, true));
+    arborx_status st = check_nodes(f.qnodes, f.wnodes, f.n, node_format(OP_KNN, f.dim, f.kind, true));
     if (st == ARBORX_OK)
         st = reserve_ws(f, m, s);
     if (st != ARBORX_OK)

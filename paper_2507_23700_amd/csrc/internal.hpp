@@ -60,16 +60,17 @@ enum Op { OP_SPATIAL = 0, OP_REDUCE = 1, OP_KNN = 2, OP_KINDS = 3 };
 const Tuning &tuning(int op = OP_SPATIAL);
 void set_tuning_op(int op, const Tuning &t);
 // Node format the thread schedule of `op` walks on a tree (or forest) of
-// dimension `dim`: the tuning's; under the library's defaults, also 1 for kNN
-// in 6D, and 0 for every forest walk.
-int node_format(int op, int dim, bool forest);
-int node_format_of(const Tuning &t, int op, int dim, bool forest);
+// dimension `dim` over values of `kind`: the tuning's; under the library's
+// defaults 1 for the radius walks over points and for kNN over points in 6D,
+// and 0 for every other walk (kNN up to 3D, box values, forests).
+int node_format(int op, int dim, int kind, bool forest);
+int node_format_of(const Tuning &t, int op, int dim, int kind, bool forest);
 // Quantized (1) and four-wide (2) nodes are built only while some operation
-// asks for that format on a structure of this dimension and kind.
-bool format_requested(int format, int dim, bool forest);
+// asks for that format on a structure of this dimension, kind and form.
+bool format_requested(int format, int dim, int kind, bool forest);
 // Node format a single-tree walk of `op` uses: node_format for the thread
 // schedule (kNN: any schedule but the wavefront packet), else binary.
-int walk_format(int op, int dim);
+int walk_format(int op, int dim, int kind);
 // ARBORX_E_INVALID unless the structure holds the nodes of format `fmt`.
 arborx_status check_nodes(const void *qnodes, const void *wnodes, int64_t n, int fmt);
 bool tree_has_format(arborx_tree tree, int format);

@@ -924,7 +924,7 @@ Launch traversal_launch(int64_t m, size_t entry_bytes, int op, int dim, bool wav
 // quantized ones (a request the caller made for a missing format is an error).
 int tree_format(int op, const TreeDev &t)
 {
-    const int f = walk_format(op, t.dim);
+    const int f = walk_format(op, t.dim, t.kind);
     return (f == 1 && !t.qnodes && tuning(op).by_dim) ? 0 : f;
 }
 
