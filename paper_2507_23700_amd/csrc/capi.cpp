@@ -195,6 +195,12 @@ int walk_format(int op, int dim, int kind)
     return thread_walk ? node_format(op, dim, kind, false) : 0;
 }
 
+int tree_format(int op, const TreeDev &t)
+{
+    const int f = walk_format(op, t.dim, t.kind);
+    return (f == 1 && !t.qnodes && tuning(op).by_dim) ? 0 : f;
+}
+
 arborx_status check_nodes(const void *qnodes, const void *wnodes, int64_t n, int fmt)
 {
     if (n > 0 && ((fmt == 1 && !qnodes) || (fmt == 2 && !wnodes)))

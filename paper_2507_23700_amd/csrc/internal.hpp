@@ -159,12 +159,16 @@ struct TreeDev {
     int dim = 0;
     int kind = 0;
     void *nodes = nullptr;  // Node<dim>[max(n-1, 1)]
-    void *qnodes = nullptr; // QNode<dim>[max(n-1, 1)]: the same tree with 16-bit child boxes
+    void *qnodes = nullptr; // QNode<dim>[max(n-1, 1)]: the same tree, 16-bit internal boxes, exact point leaves
     void *wnodes = nullptr; // Node4<dim>[max(n-1, 1)]: the same tree two levels per node
     uint64_t *codes = nullptr;  // [n] sorted Morton codes of the leaves (the build's sort keys)
     float *leaves = nullptr; // n leaf records in sorted order (see leaf_floats)
     TreeHeader *hdr = nullptr;
 };
+// Node format a walk of `op` takes on tree t: walk_format's, except that the
+// library's defaults fall back to float nodes on a tree built without the
+// quantized ones (a request the caller made for a missing format is an error).
+int tree_format(int op, const TreeDev &t);
 size_t node_bytes(int dim);
 // Number of node slots allocated for a tree of n values.
 inline int tree_nodes(const TreeDev &t) { return t.n > 1 ? (int)(t.n - 1) : 1; }

@@ -62,9 +62,11 @@ __device__ __forceinline__ int leaf_index(const float *__restrict__ leaves, int6
 }
 
 // Pass 1: deg[q] = partners of the point at sorted position q.  NQ leaves per
-// thread over the packet walk, or (NQ = 0) one leaf per thread over its rope.
-template <int D, int NQ>
-__global__ void k_pair_degree(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+// thread over the packet walk, or (NQ = 0) one leaf per thread over its rope;
+// Q: one leaf per thread over the quantized nodes.
+template <int D, int NQ, bool Q = false>
+__global__ void k_pair_degree(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
+                              const TreeHeader *__restrict__ hdr,
                               const float *__restrict__ leaves, int64_t n, float r2, int32_t *__restrict__ deg,
                               int stack_cap)
 {
@@ -101,7 +103,12 @@ __global__ void k_pair_degree(const Node<D> *__restrict__ nodes, const TreeHeade
                     ++c[jj];
             atomicAdd(deg + q, 1);
         };
-        traverse_pairs_packet<D, W>(nodes, hdr->root, (int)(n - 1), (int)p0, pred, st, f);
+        if constexpr (Q) {
+            auto f1 = [&](int q, int qid, float d) { f(0, q, qid, d); };
+            traverse_pairs_q<D>(qnodes, *hdr, (int)(n - 1), (int)p0, pred[0], st, f1);
+        } else {
+            traverse_pairs_packet<D, W>(nodes, hdr->root, (int)(n - 1), (int)p0, pred, st, f);
+        }
     }
 #pragma unroll
     for (int j = 0; j < W; ++j)
@@ -189,10 +196,12 @@ __global__ void k_dbscan_init(int32_t *__restrict__ parent, int32_t *__restrict_
     }
 }
 
-// Pass 2: one pair walk, NQ leaves per thread (NQ = 0: the rope walk).
-// parent is indexed by value index, deg and border by sorted position.
-template <int D, int NQ>
-__global__ void k_dbscan_pairs(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+// Pass 2: one pair walk, NQ leaves per thread (NQ = 0: the rope walk; Q: one
+// leaf per thread over the quantized nodes).  parent is indexed by value
+// index, deg and border by sorted position.
+template <int D, int NQ, bool Q = false>
+__global__ void k_dbscan_pairs(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
+                               const TreeHeader *__restrict__ hdr,
                                const float *__restrict__ leaves, int64_t n, float r2, int min_pts,
                                const int32_t *__restrict__ deg, int32_t *__restrict__ parent,
                                int32_t *__restrict__ border, int stack_cap)
@@ -238,7 +247,12 @@ __global__ void k_dbscan_pairs(const Node<D> *__restrict__ nodes, const TreeHead
         int spill[kSpill];
         ShortStack<int> st(s_stack + threadIdx.x, blockDim.x, stack_cap, spill);
         auto f = [&](int j, int q, int qid, float) { pair(j, q, qid); };
-        traverse_pairs_packet<D, W>(nodes, hdr->root, (int)(n - 1), (int)p0, pred, st, f);
+        if constexpr (Q) {
+            auto f1 = [&](int q, int qid, float) { pair(0, q, qid); };
+            traverse_pairs_q<D>(qnodes, *hdr, (int)(n - 1), (int)p0, pred[0], st, f1);
+        } else {
+            traverse_pairs_packet<D, W>(nodes, hdr->root, (int)(n - 1), (int)p0, pred, st, f);
+        }
     }
 #pragma unroll
     for (int j = 0; j < W; ++j)
@@ -279,18 +293,27 @@ __global__ void k_dbscan_border_labels(const int32_t *__restrict__ deg, const in
 // rope walk for schedule 2), with NQ leaves per thread over the packet walk
 // (queries_per_thread, else 2 up to 3D and 1 in 6D: at 10^7 points in 3D, two
 // leaves per thread ran DBSCAN's pair pass fastest and the pair count as fast
-// as four).
+// as four, on float nodes).  On quantized nodes the default is one leaf per
+// thread over them: at 10^7 points in 3D the pair count took 2.22 ms against
+// 2.44 ms for two leaves per thread on float nodes, DBSCAN 8.3 against 9.2 ms.
 struct PairLaunch {
     int nq, block, cap;
+    bool q;  // one leaf per thread over the quantized nodes
     unsigned grid;
     size_t lds;
 };
 
-PairLaunch pair_launch(int64_t n, int dim)
+// The pair walks follow the reductions' tuning (schedule, queries per thread,
+// node format, launch shape).
+PairLaunch pair_launch(const TreeDev &t)
 {
+    const int64_t n = t.n;
+    const int dim = t.dim;
     const Tuning &tu = tuning(OP_REDUCE);
     PairLaunch L;
-    L.nq = tu.schedule == 2 ? 0 : (tu.packet ? tu.packet : (dim <= 3 ? 2 : 1));
+    const bool qf = tree_format(OP_REDUCE, t) == 1 && t.qnodes;
+    L.nq = tu.schedule == 2 ? 0 : (tu.packet ? tu.packet : (dim <= 3 && !qf ? 2 : 1));
+    L.q = L.nq == 1 && qf;
     launch_shape(OP_REDUCE, dim, L.block, L.cap);
     while (L.cap > 1 && (size_t)L.cap * L.block * sizeof(int) > 65536)
         L.cap >>= 1;
@@ -306,18 +329,22 @@ arborx_status degree_by_position(const TreeDev &t, float r2, int32_t *deg, hipSt
     const int64_t n = t.n;
     fill_kernel<int32_t><<<grid_for(n, 256, 65536), 256, 0, s>>>(deg, n, 0);
     if (n > 1) {
-        const PairLaunch L = pair_launch(n, D);
+        const PairLaunch L = pair_launch(t);
         const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
         ProfScope ps("pair_degree", s);
-#define AX_PD(NQ) k_pair_degree<D, NQ><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, t.leaves, n, r2, deg, L.cap)
+        const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
+#define AX_PD(NQ, QF) \
+    k_pair_degree<D, NQ, QF><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, t.hdr, t.leaves, n, r2, deg, L.cap)
         if (L.nq == 0)
-            AX_PD(0);
+            AX_PD(0, false);
+        else if (L.q)
+            AX_PD(1, true);
         else if (L.nq == 1)
-            AX_PD(1);
+            AX_PD(1, false);
         else if (L.nq == 2)
-            AX_PD(2);
+            AX_PD(2, false);
         else
-            AX_PD(4);
+            AX_PD(4, false);
 #undef AX_PD
     }
     AX_HIP(hipGetLastError());
@@ -352,18 +379,22 @@ arborx_status dbscan_impl(const TreeDev &t, float eps, int min_pts, int32_t *lab
     const unsigned g = grid_for(n, 256, 65536);
     k_dbscan_init<<<g, 256, 0, s>>>(parent, border, n);
     if (n > 1) {
-        const PairLaunch L = pair_launch(n, D);
+        const PairLaunch L = pair_launch(t);
         const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
-#define AX_DP(NQ) k_dbscan_pairs<D, NQ><<<L.grid, L.block, L.lds, s>>>(nodes, t.hdr, t.leaves, n, r2, min_pts, deg, \
-                                                                       parent, border, L.cap)
+        const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
+#define AX_DP(NQ, QF)                                                                                             \
+    k_dbscan_pairs<D, NQ, QF><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, t.hdr, t.leaves, n, r2, min_pts, deg, \
+                                                             parent, border, L.cap)
         if (L.nq == 0)
-            AX_DP(0);
+            AX_DP(0, false);
+        else if (L.q)
+            AX_DP(1, true);
         else if (L.nq == 1)
-            AX_DP(1);
+            AX_DP(1, false);
         else if (L.nq == 2)
-            AX_DP(2);
+            AX_DP(2, false);
         else
-            AX_DP(4);
+            AX_DP(4, false);
 #undef AX_DP
     }
     k_dbscan_core_labels<D><<<g, 256, 0, s>>>(parent, deg, n, min_pts, t.leaves, labels);

@@ -919,15 +919,6 @@ Launch traversal_launch(int64_t m, size_t entry_bytes, int op, int dim, bool wav
 
 // Schedule 0 over quantized nodes runs as internal schedule 3, over four-wide
 // nodes as internal schedule 4.
-// Node format a walk of `op` takes on tree t: walk_format's, except that the
-// library's defaults fall back to float nodes on a tree built without the
-// quantized ones (a request the caller made for a missing format is an error).
-int tree_format(int op, const TreeDev &t)
-{
-    const int f = walk_format(op, t.dim, t.kind);
-    return (f == 1 && !t.qnodes && tuning(op).by_dim) ? 0 : f;
-}
-
 int effective_schedule(int op, const TreeDev &t)
 {
     const Tuning &tu = tuning(op);

@@ -652,6 +652,57 @@ __device__ __forceinline__ void traverse_spatial_packet_q(const QNode<D> *__rest
     }
 }
 
+// Pair walk over the quantized nodes of a tree of points, one leaf (sorted
+// position p) per thread: f(q, index, d2) for every later position q whose
+// point is in range.  A node is entered only when its leaf range holds a
+// position after p: the root unless p is the last leaf; a left child [l, c]
+// when c > p; a right child always, as its range ends where its parent's does.
+// So only the leaf children need a position test (the left leaf sits at c,
+// the right one at c + 1) and the node needs no stored range.
+template <int D, class P, class F>
+__device__ __forceinline__ void traverse_pairs_q(const QNode<D> *__restrict__ nodes, const TreeHeader &h,
+                                                 int n_nodes, int p, const P &pred, ShortStack<int> &st, F &f)
+{
+    if (p >= h.start + h.n - 1)
+        return;
+    float flo[D], fsc[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        flo[d] = h.lo[d];
+        fsc[d] = h.qscale[d];
+    }
+    int cur = h.root;
+    for (int iter = 0; iter <= n_nodes; ++iter) {
+        if ((unsigned)cur >= (unsigned)n_nodes)
+            break;
+        QNode<D> nd;
+        load_qnode(nodes, cur, nd);
+        float lo[2][D], hi[2][D];
+        qboxes<D>(nd, true, flo, fsc, lo, hi);
+        const int c0 = nd.child[0], c1 = nd.child[1];
+        float d0, d1;
+        const bool h0 = cur > p && pred.hit(lo[0], hi[0], d0);
+        const bool h1 = (c1 >= 0 || cur + 1 > p) && pred.hit(lo[1], hi[1], d1);
+        if (h0 && c0 < 0 && c0 != kEmptyRef)
+            f(cur, ~c0, d0);
+        if (h1 && c1 < 0 && c1 != kEmptyRef)
+            f(cur + 1, ~c1, d1);
+        const bool g0 = h0 && c0 >= 0;
+        const bool g1 = h1 && c1 >= 0;
+        if (g0) {
+            if (g1)
+                st.push(c1);
+            cur = c0;
+        } else if (g1) {
+            cur = c1;
+        } else {
+            if (st.empty())
+                break;
+            cur = st.pop();
+        }
+    }
+}
+
 // One term of the fixed-point distance sum: trunc(sqrtf(d2) * scale), scale
 // a power of two.
 __device__ __forceinline__ long long fixed_term(float d2, float scale)

@@ -148,7 +148,9 @@ def test_self_join_rejects_boxes_and_bad_radius():
 
 
 @pytest.mark.parametrize("tuning", [dict(schedule=2), dict(queries_per_thread=1), dict(queries_per_thread=2),
-                                    dict(queries_per_thread=4), dict(block=64, stack=1)])
+                                    dict(queries_per_thread=4), dict(block=64, stack=1),
+                                    dict(queries_per_thread=1, node_format=1),
+                                    dict(queries_per_thread=1, node_format=1, block=64, stack=1)])
 def test_pair_walk_forms_identical(tuning):
     pts = clustered(9000, 3, 61)
     pts[::53] = pts[1::53][: len(pts[::53])]

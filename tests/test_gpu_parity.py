@@ -278,6 +278,38 @@ def test_shell_and_gmm6():
     check_reduce(t6, g["data"], g["queries"], r6, dim=6)
 
 
+@pytest.mark.parametrize("case", ["shell3", "gmm6", "dim2", "boxes", "duplicates"])
+@pytest.mark.parametrize("node_format", [0, 1])
+def test_knn_node_formats(case, node_format):
+    # kNN on float and quantized nodes over ragged query counts, 2D/3D/6D,
+    # box values and many equal points (ties decided by index)
+    g = np.random.default_rng(404)
+    dim, kind, k = 3, oracle.POINTS, 16
+    if case == "shell3":
+        s = inputs.config_paper("shell", n=30_000, m=3001)
+        data, q = s["data"], s["queries"]
+    elif case == "gmm6":
+        s = inputs.config_gmm6(n=20_000, m=2003)
+        data, q, dim, k = s["data"], s["queries"], 6, 8
+    elif case == "dim2":
+        data, q, dim, k = g.random((7000, 2)).astype(np.float32), g.random((902, 2)).astype(np.float32), 2, 5
+    elif case == "boxes":
+        c = g.random((6000, 3)).astype(np.float32)
+        h = (g.random((6000, 3)) * 0.01).astype(np.float32)
+        data, kind, k = np.ascontiguousarray(np.stack([c - h, c + h], axis=1)), oracle.BOXES, 10
+        q = g.random((2001, 3)).astype(np.float32)
+    else:  # many equal points: ties decided by index
+        data = np.repeat(g.random((500, 3)).astype(np.float32), 8, axis=0)
+        q = np.concatenate([data[::7], g.random((300, 3)).astype(np.float32)])
+    ax.arborx_set_tuning(node_format=node_format)
+    try:
+        t = ax.arborx_bvh_build(dev(data), ax.BOXES if kind == oracle.BOXES else ax.POINTS)
+        check_knn(t, data, q, k, dim=dim, kind=kind)
+        check_knn(t, data, q[:3], 1, dim=dim, kind=kind)
+    finally:
+        ax.arborx_reset_tuning()
+
+
 def test_dim2():
     g = np.random.default_rng(2)
     data = g.random((7000, 2)).astype(np.float32)
@@ -448,6 +480,8 @@ def test_query_packets_identical(nq):
             check_reduce(t, data, q[:3], float("inf"))
             check_spatial(t, data, q, r)
             check_spatial(t, data, q[:5], 0.3)  # rows longer than the register stash
+            check_knn(t, data, q, 10)  # kNN ignores queries_per_thread: same rows under every setting
+            check_knn(t, data, q[:6], 3)
         finally:
             ax.arborx_reset_tuning()
     g = np.random.default_rng(nq)
@@ -458,6 +492,7 @@ def test_query_packets_identical(nq):
         try:
             check_reduce(ts, small, q[:7], 0.4)
             check_spatial(ts, small, q[:7], 0.4)
+            check_knn(ts, small, q[:7], 4)  # k above n: padded rows
         finally:
             ax.arborx_reset_tuning()
 
