@@ -559,6 +559,22 @@ def main():
         ms = timed(call, 5)
         comps[f"{name}_standalone_qps"] = m / ms * 1e3
     del q_alt, qs
+    # walk statistics (the debug entry point, outside the step): node fetches per query of the
+    # one-query-per-thread radius walk and of the seeded kNN walk, and the node bytes those fetches
+    # touch in float nodes (16*dim + 16 B) and in quantized nodes (8*dim + 8 B, 16-byte aligned)
+    vr = ax.arborx_debug_node_visits(tree, q, radius=radius).double()
+    vk = ax.arborx_debug_node_visits(tree, q, k=k).double()
+    fb, qb = 16 * dim + 16, (8 * dim + 8 + 15) // 16 * 16
+    p99 = max(1, int(0.99 * m))
+    comps["walk_statistics"] = {
+        "radius_visits_mean": vr.mean().item(), "radius_visits_p99": vr.kthvalue(p99).values.item(),
+        f"knn{k}_visits_mean": vk.mean().item(), f"knn{k}_visits_p99": vk.kthvalue(p99).values.item(),
+        "node_bytes_float": fb, "node_bytes_quantized": qb,
+        "radius_touched_bytes_float": vr.mean().item() * fb, "radius_touched_bytes_quantized": vr.mean().item() * qb,
+        f"knn{k}_touched_bytes_float": vk.mean().item() * fb, f"knn{k}_touched_bytes_quantized": vk.mean().item() * qb,
+        "tree_height": ax.arborx_bvh_info(tree)["height"],
+    }
+    del vr, vk
 
     # dominant kernel by GPU time in the timed region
     dom = max((kn for kn in prof if algorithmic_bytes(kn, n, m, dim, k, total)), key=lambda kn: prof[kn][0])

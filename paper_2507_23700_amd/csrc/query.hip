@@ -714,8 +714,21 @@ __global__ void k_spatial_reduce_packet(const Node<D> *__restrict__ nodes, const
         }
 }
 
+// Waves per SIMD the kNN kernel asks the register allocator for.  The 3D
+// k = 16 thread walk on float nodes needed 65 registers, one above the
+// 8-wave limit: held to 64 (63, no spill) it runs 8 waves per SIMD, and kNN-16
+// at 10^7 points took 7.7 ms instead of 8.4 (shell 6.8 instead of 7.4).  The
+// 6D k = 8 walk on quantized nodes, held from 88 to 80 registers (6 waves
+// instead of 5), spilled and ran slower (7.0 against 6.8 ms), so the other
+// shapes are left to the compiler.
 template <int D, int K, bool WAVE, int FMT>
-__global__ void k_knn(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
+constexpr int knn_waves()
+{
+    return (!WAVE && D <= 3 && K == 16 && FMT == 0) ? 8 : 1;
+}
+
+template <int D, int K, bool WAVE, int FMT>
+__global__ __attribute__((amdgpu_waves_per_eu(knn_waves<D, K, WAVE, FMT>()))) void k_knn(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
                       const Node4<D> *__restrict__ wnodes, const uint64_t *__restrict__ codes, int n_nodes,
                       const float *__restrict__ leaves, int kind,
                       const TreeHeader *__restrict__ hdr, const float *__restrict__ queries, int64_t m, int k_out,
