@@ -517,6 +517,12 @@ def main():
     # of the same distances over the step's finished CSR result
     ms = timed(lambda: ax.arborx_query_spatial_with_distances(tree, q, radius), 5)
     comps["spatial_with_distances_qps"] = m / ms * 1e3
+    # the same search with rows left in the order the walk found their matches (no row sorts);
+    # compare with the same standalone call in ascending order
+    ms = timed(lambda: ax.arborx_query_spatial(tree, q, radius), 5)
+    comps["spatial_csr_standalone_qps"] = m / ms * 1e3
+    ms = timed(lambda: ax.arborx_query_spatial(tree, q, radius, ordered=False), 5)
+    comps["spatial_csr_unsorted_qps"] = m / ms * 1e3
     ms = timed(lambda: ax.arborx_query_match_distances(tree, d, q, state["off"], state["idx"]), 5)
     comps["match_distances_per_s"] = total / ms * 1e3
     # rays against 2*10^6 small random boxes: hit counts and the first hit of 10^6 rays

@@ -232,6 +232,19 @@ arborx_status arborx_query_finish(arborx_plan plan, int32_t *indices, int64_t ca
 arborx_status arborx_plan_destroy(arborx_plan plan);
 
 /*
+ * Storage query without the canonical row order (Section 2.1, query call (3),
+ * whose results come in the order the search meets them): as
+ * arborx_query_finish, but each row holds its matches in the order the walk
+ * found them (a row longer than the per-query register stash: the stash part,
+ * then the rest as found) instead of ascending, which saves the row sorts.
+ * The set of indices in every row, offsets and total are those of the sorted
+ * form; the order inside a row may change from call to call.  Indices only:
+ * a plan begun with distances writes its indices and no distances; a plan of
+ * arborx_query_ray_ordered_intersect is ARBORX_E_INVALID.  Asynchronous.
+ */
+arborx_status arborx_query_finish_unsorted(arborx_plan plan, int32_t *indices, int64_t capacity);
+
+/*
  * Box-overlap search with CSR output (Section 2.1, intersects predicate).
  *   qboxes  [m][2][dim] query boxes; a value matches if its box (a point is a
  *           degenerate box) overlaps the closed query box in every dimension.

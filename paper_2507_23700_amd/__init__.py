@@ -217,8 +217,9 @@ def _queries(tree, q, boxes):
     return q
 
 
-def _csr(begin, tree, q, extra, stream):
-    """Count (begin), size indices exactly, fill (finish), release the plan."""
+def _csr(begin, tree, q, extra, stream, ordered=True):
+    """Count (begin), size indices exactly, fill (finish, or the unsorted finish when not
+    ordered), release the plan."""
     torch = _torch()
     m = q.shape[0]
     offsets = torch.empty(m + 1, dtype=torch.int64, device=q.device)
@@ -229,22 +230,25 @@ def _csr(begin, tree, q, extra, stream):
                  _stream(stream)))
     try:
         indices = torch.empty(max(total.value, 1), dtype=torch.int32, device=q.device)
-        _check(L.arborx_query_finish(plan, _ptr(indices), indices.numel()))
+        finish = L.arborx_query_finish if ordered else L.arborx_query_finish_unsorted
+        _check(finish(plan, _ptr(indices), indices.numel()))
     finally:
         L.arborx_plan_destroy(plan)
     return offsets, indices[:total.value]
 
 
-def arborx_query_spatial(tree: Tree, queries, radius: float, stream=None):
-    """Radius search: (offsets int64[m+1], indices int32[total]), rows ascending."""
+def arborx_query_spatial(tree: Tree, queries, radius: float, stream=None, ordered=True):
+    """Radius search: (offsets int64[m+1], indices int32[total]), rows ascending; with
+    ordered=False each row in the order the walk found its matches (same sets)."""
     q = _queries(tree, queries, False)
-    return _csr(_lib.lib().arborx_query_spatial_begin, tree, q, [ctypes.c_float(radius)], stream)
+    return _csr(_lib.lib().arborx_query_spatial_begin, tree, q, [ctypes.c_float(radius)], stream, ordered)
 
 
-def arborx_query_intersects(tree: Tree, qboxes, stream=None):
-    """Box-overlap search with [m, 2, dim] query boxes: CSR (offsets, indices)."""
+def arborx_query_intersects(tree: Tree, qboxes, stream=None, ordered=True):
+    """Box-overlap search with [m, 2, dim] query boxes: CSR (offsets, indices); ordered as in
+    arborx_query_spatial."""
     q = _queries(tree, qboxes, True)
-    return _csr(_lib.lib().arborx_query_intersects_begin, tree, q, [], stream)
+    return _csr(_lib.lib().arborx_query_intersects_begin, tree, q, [], stream, ordered)
 
 
 def arborx_query_knn(tree: Tree, queries, k: int, stream=None):

@@ -51,6 +51,7 @@ SIGNATURES = {
     "arborx_query_spatial_begin": (I32, [P, P, I64, F32, P, P, P, P]),
     "arborx_query_intersects_begin": (I32, [P, P, I64, P, P, P, P]),
     "arborx_query_finish": (I32, [P, P, I64]),
+    "arborx_query_finish_unsorted": (I32, [P, P, I64]),
     "arborx_query_spatial_with_distances": (I32, [P, P, I64, F32, P, P, P, I64, P, P]),
     "arborx_query_spatial_with_distances_begin": (I32, [P, P, I64, F32, P, P, P, P]),
     "arborx_query_finish_with_distances": (I32, [P, P, P, I64]),

@@ -753,10 +753,13 @@ static arborx_status csr_begin(arborx_tree t, Pred pred, const float *queries, i
     return ARBORX_OK;
 }
 
-static arborx_status csr_finish(arborx_plan p, int32_t *indices, int64_t capacity, float *dist = nullptr)
+static arborx_status csr_finish(arborx_plan p, int32_t *indices, int64_t capacity, float *dist = nullptr,
+                                bool sorted = true)
 {
     if (!p)
         return fail(ARBORX_E_INVALID, "plan is NULL");
+    if (!sorted && p->mode == VALUES_ORDERED)
+        return fail(ARBORX_E_INVALID, "rows of an ordered plan are always ordered by their values");
     if (capacity < 0)
         return fail(ARBORX_E_INVALID, "capacity must be >= 0");
     if (dist && !p->stash_d2)
@@ -773,8 +776,8 @@ static arborx_status csr_finish(arborx_plan p, int32_t *indices, int64_t capacit
     NoteUse note_use{p->tree->uses, p->stream};
     st = spatial_fill(p->tree->dev, p->pred, p->queries, p->m, p->radius, p->counts, p->stash, p->stash_d2, p->ovf,
                       p->offsets, p->big_list, (int64_t)p->h.big_rows, p->huge_list, (int64_t)p->h.huge_rows,
-                      indices, dist, p->mode, p->stream);
-    if (st != ARBORX_OK)
+                      indices, dist, p->mode, p->stream, sorted);
+    if (st != ARBORX_OK || !sorted)
         return st;
     if ((st = sort_big_rows(p->offsets, indices, dist, p->mode, p->big_list, (int64_t)p->h.big_rows, p->stream)) !=
         ARBORX_OK)
@@ -817,6 +820,11 @@ arborx_status arborx_query_intersects_begin(arborx_tree t, const float *qboxes, 
 arborx_status arborx_query_finish(arborx_plan plan, int32_t *indices, int64_t capacity)
 {
     return csr_finish(plan, indices, capacity);
+}
+
+arborx_status arborx_query_finish_unsorted(arborx_plan plan, int32_t *indices, int64_t capacity)
+{
+    return csr_finish(plan, indices, capacity, nullptr, false);
 }
 
 arborx_status arborx_query_spatial_with_distances_begin(arborx_tree t, const float *queries, int64_t m, float radius,

@@ -257,12 +257,14 @@ arborx_status spatial_count(const TreeDev &t, Pred pred, const float *queries, i
 // stash and their overflow chunks, and the rest (huge rows, rows whose chunks
 // did not fit) are walked again.
 // With dist, each match's value is written beside its index, rows sorted as
-// `mode` says (VALUES_BY_INDEX or VALUES_ORDERED).
+// `mode` says (VALUES_BY_INDEX or VALUES_ORDERED).  sorted = false (indices
+// only) leaves the stash rows in the order the walk found their matches, and
+// the caller then skips the row sorts.
 arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, int64_t m, float radius,
                            const int32_t *counts, const int32_t *stash, const float *stash_d2,
                            const OverflowPool &ovf, const int64_t *offsets, const int32_t *big_list, int64_t nbig,
                            const int32_t *huge_list, int64_t nhuge, int32_t *indices, float *dist, int mode,
-                           hipStream_t s);
+                           hipStream_t s, bool sorted = true);
 // Row sorts; with dist, each value moves with its index, rows sorted by
 // index or (mode VALUES_ORDERED) by (value, index).
 arborx_status sort_big_rows(const int64_t *offsets, int32_t *indices, float *dist, int mode, const int32_t *big_list,

@@ -296,8 +296,9 @@ __device__ __forceinline__ float match_value(uint64_t w)
 // network, empty slots padded to sort last) and copy it to the CSR slot.
 // Thread i handles query i, so consecutive lanes fill adjacent rows.  With a
 // value mode, the stashed values are sorted along with the indices (packed
-// with them into one word) and copied to the same slots of dist.
-template <int R, int MODE>
+// with them into one word) and copied to the same slots of dist.  Without
+// SORT (index rows only) the row is copied in the order the walk found it.
+template <int R, int MODE, bool SORT = true>
 __global__ void k_copy_stash(const int32_t *__restrict__ stash, const float *__restrict__ stash_d2, int64_t m,
                              const int32_t *__restrict__ counts, const int64_t *__restrict__ offsets,
                              int32_t *__restrict__ indices, float *__restrict__ dist)
@@ -341,10 +342,12 @@ __global__ void k_copy_stash(const int32_t *__restrict__ stash, const float *__r
                 dist[o + k] = match_value<MODE>(w[k]);
             }
     } else {
+        if constexpr (SORT) {
 #pragma unroll
-        for (int k = 0; k < R; ++k)
-            v[k] = k < c ? v[k] : INT32_MAX;
-        sort_network<R>(v);
+            for (int k = 0; k < R; ++k)
+                v[k] = k < c ? v[k] : INT32_MAX;
+            sort_network<R>(v);
+        }
 #pragma unroll
         for (int k = 0; k < R; ++k)
             if (k < c)
@@ -1298,7 +1301,7 @@ arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, in
                            const int32_t *counts, const int32_t *stash, const float *stash_d2,
                            const OverflowPool &ovf, const int64_t *offsets, const int32_t *big_list, int64_t nbig,
                            const int32_t *huge_list, int64_t nhuge, int32_t *indices, float *dist, int mode,
-                           hipStream_t s)
+                           hipStream_t s, bool sorted)
 {
     if (m == 0 || t.n == 0)
         return ARBORX_OK;
@@ -1309,21 +1312,25 @@ arborx_status spatial_fill(const TreeDev &t, Pred pred, const float *queries, in
         ProfScope ps("copy_stash", s);
         const unsigned g = grid_for(m, 256, INT32_MAX);
         const int md = dist ? (mode == VALUES_ORDERED ? 2 : 1) : 0;
-#define AX_CS(R, M) k_copy_stash<R, M><<<g, 256, 0, s>>>(stash, stash_d2, m, counts, offsets, indices, dist)
+#define AX_CS(R, M, S) k_copy_stash<R, M, S><<<g, 256, 0, s>>>(stash, stash_d2, m, counts, offsets, indices, dist)
         if (stash_regs(t.dim) == 32) {
             if (md == 2)
-                AX_CS(32, 2);
+                AX_CS(32, 2, true);
             else if (md == 1)
-                AX_CS(32, 1);
+                AX_CS(32, 1, true);
+            else if (sorted)
+                AX_CS(32, 0, true);
             else
-                AX_CS(32, 0);
+                AX_CS(32, 0, false);
         } else {
             if (md == 2)
-                AX_CS(16, 2);
+                AX_CS(16, 2, true);
             else if (md == 1)
-                AX_CS(16, 1);
+                AX_CS(16, 1, true);
+            else if (sorted)
+                AX_CS(16, 0, true);
             else
-                AX_CS(16, 0);
+                AX_CS(16, 0, false);
         }
 #undef AX_CS
         AX_HIP(hipGetLastError());

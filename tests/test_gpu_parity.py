@@ -633,6 +633,97 @@ def test_overflow_chains(case):
         assert np.diff(o_off).max() > 16 + 5 * 31
 
 
+def check_spatial_unsorted(tree, data, q, r, dim=3, kind=oracle.POINTS, boxes=False):
+    """The unsorted storage form: offsets exact, each row the oracle's set (compared sorted)."""
+    if boxes:
+        off, idx = ax.arborx_query_intersects(tree, dev(q), ordered=False)
+        o_off, o_idx = oracle.intersects(data, q, dim=dim, kind=kind)
+    else:
+        off, idx = ax.arborx_query_spatial(tree, dev(q), float(r), ordered=False)
+        o_off, o_idx = oracle.spatial(data, q, r, dim=dim, kind=kind)
+    off, idx = host(off), host(idx)
+    assert np.array_equal(off, o_off)
+    rows = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    order = np.lexsort((idx, rows))  # sort inside each row
+    assert np.array_equal(idx[order], o_idx)
+    return off, idx
+
+
+@pytest.mark.parametrize("case", ["cube", "gmm6", "long_rows", "pool_runs_out", "boxes", "wave"])
+def test_spatial_unsorted(case):
+    # rows in the order the walk found them: same offsets and the same set per row as the
+    # oracle, through the stash (16 or 32 entries), overflow chains and second walks
+    g = np.random.default_rng(23)
+    dim, kind, boxes, tuning = 3, oracle.POINTS, False, {}
+    if case == "gmm6":
+        cfg = inputs.config_gmm6(n=20_000, m=2001)
+        data, q, r, dim = cfg["data"], cfg["queries"], float(cfg["radius"]), 6
+    elif case in ("long_rows", "pool_runs_out", "wave"):
+        hot = g.random((20, 3))
+        blob = hot[g.integers(0, 20, 12000)] + 0.003 * g.standard_normal((12000, 3))
+        data = np.concatenate([g.random((30000, 3)), blob]).astype(np.float32)
+        near = hot[g.integers(0, 20, 60)] + 0.001 * g.standard_normal((60, 3))
+        q = (near if case == "pool_runs_out" else np.concatenate([g.random((20000, 3)), near])).astype(np.float32)
+        r = 0.01
+        tuning = dict(schedule=1) if case == "wave" else {}
+    elif case == "boxes":
+        data = g.random((20000, 3)).astype(np.float32)
+        c = g.random((3001, 3)).astype(np.float32)
+        q = np.ascontiguousarray(np.stack([c - 0.02, c + 0.02], axis=1)).astype(np.float32)
+        r, boxes = 0.0, True
+    else:
+        cfg = inputs.config_small(n=20_000, m=4001)
+        data, q, r = cfg["data"], cfg["queries"], float(cfg["radius"])
+    ax.arborx_set_tuning(**tuning)
+    try:
+        t = ax.arborx_bvh_build(dev(data))
+        off, _ = check_spatial_unsorted(t, data, q, r, dim=dim, kind=kind, boxes=boxes)
+        if case in ("long_rows", "pool_runs_out"):
+            assert np.diff(off).max() > 4096 or np.diff(off).max() > 16 + 5 * 31
+        if case == "cube":  # r = 0 and an empty query set
+            check_spatial_unsorted(t, data, q, 0.0)
+            check_spatial_unsorted(t, data, q[:0], r)
+    finally:
+        ax.arborx_reset_tuning()
+
+
+def test_spatial_unsorted_plans():
+    # a plan begun with distances gives its indices unsorted (no distances); an ordered ray plan refuses
+    import ctypes
+    cfg = inputs.config_small(n=5000, m=500)
+    data, q, r = cfg["data"], cfg["queries"], float(cfg["radius"])
+    t = ax.arborx_bvh_build(dev(data))
+    L = ax._lib.lib()
+    qd = dev(q)
+    off = torch.empty(len(q) + 1, dtype=torch.int64, device="cuda")
+    total, plan = ctypes.c_int64(), ctypes.c_void_p()
+    assert L.arborx_query_spatial_with_distances_begin(t.handle, ctypes.c_void_p(qd.data_ptr()), len(q),
+                                                       ctypes.c_float(r), ctypes.c_void_p(off.data_ptr()),
+                                                       ctypes.byref(total), ctypes.byref(plan), None) == ax.OK
+    try:
+        idx = torch.empty(max(total.value, 1), dtype=torch.int32, device="cuda")
+        assert L.arborx_query_finish_unsorted(plan, ctypes.c_void_p(idx.data_ptr()), 0) == ax.E_CAPACITY
+        assert L.arborx_query_finish_unsorted(plan, ctypes.c_void_p(idx.data_ptr()), idx.numel()) == ax.OK
+        o_off, o_idx = oracle.spatial(data, q, r)
+        h = host(idx)[:total.value]
+        rows = np.repeat(np.arange(len(q)), np.diff(o_off))
+        assert np.array_equal(host(off), o_off) and np.array_equal(h[np.lexsort((h, rows))], o_idx)
+    finally:
+        L.arborx_plan_destroy(plan)
+    g = np.random.default_rng(5)
+    rays = np.ascontiguousarray(np.stack([g.random((50, 3)), g.standard_normal((50, 3))], axis=1)).astype(np.float32)
+    rd = dev(rays)
+    off = torch.empty(51, dtype=torch.int64, device="cuda")
+    assert L.arborx_query_ray_ordered_intersect_begin(t.handle, ctypes.c_void_p(rd.data_ptr()), 50,
+                                                      ctypes.c_void_p(off.data_ptr()), ctypes.byref(total),
+                                                      ctypes.byref(plan), None) == ax.OK
+    try:
+        idx = torch.empty(max(total.value, 1), dtype=torch.int32, device="cuda")
+        assert L.arborx_query_finish_unsorted(plan, ctypes.c_void_p(idx.data_ptr()), idx.numel()) == ax.E_INVALID
+    finally:
+        L.arborx_plan_destroy(plan)
+
+
 @pytest.mark.parametrize("k", [1, 16, 64])
 def test_knn_seeding_off_identical(k):
     s = inputs.config_paper("shell", n=30_000, m=3000)
