@@ -593,6 +593,17 @@ def main():
                 "valu_busy": profiled(dom, cfg["workload"], "valu_busy"),
                 "algorithmic_bytes_per_launch": alg, "avg_launch_ms": avg_ms,
                 "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs}
+    # node bytes the dominant walk touches (served mostly by L1/L2): node fetches per query from the
+    # walk statistics times the node size of the format the library's defaults walk (kNN on float
+    # nodes up to 3D and quantized in 6D; the radius walks on quantized nodes)
+    ws = comps["walk_statistics"]
+    visits = ws[f"knn{k}_visits_mean"] if dom == "knn" else (ws["radius_visits_mean"] if dom in (
+        "spatial_count", "reduce_count", "reduce_sumdist") else None)
+    if visits is not None:
+        nbytes = ws["node_bytes_float"] if (dom == "knn" and dim <= 3) else ws["node_bytes_quantized"]
+        touched = visits * nbytes * m
+        roofline["touched_node_bytes_per_launch"] = touched
+        roofline["touched_node_gbs"] = touched / (avg_ms * 1e-3) / 1e9
 
     cpu = None
     parity = None
