@@ -568,13 +568,12 @@ def main():
     # walk statistics (the debug entry point, outside the step): node fetches per query of the
     # one-query-per-thread radius walk and of the seeded kNN walk, and the node bytes those fetches
     # touch in float nodes (16*dim + 16 B) and in quantized nodes (8*dim + 8 B, 16-byte aligned)
-    vr = ax.arborx_debug_node_visits(tree, q, radius=radius).double()
-    vk = ax.arborx_debug_node_visits(tree, q, k=k).double()
+    vr = ax.arborx_debug_node_visits(tree, q, radius=radius).cpu().numpy().astype(np.float64)
+    vk = ax.arborx_debug_node_visits(tree, q, k=k).cpu().numpy().astype(np.float64)
     fb, qb = 16 * dim + 16, (8 * dim + 8 + 15) // 16 * 16
-    p99 = max(1, int(0.99 * m))
     comps["walk_statistics"] = {
-        "radius_visits_mean": vr.mean().item(), "radius_visits_p99": vr.kthvalue(p99).values.item(),
-        f"knn{k}_visits_mean": vk.mean().item(), f"knn{k}_visits_p99": vk.kthvalue(p99).values.item(),
+        "radius_visits_mean": vr.mean().item(), "radius_visits_p99": np.percentile(vr, 99).item(),
+        f"knn{k}_visits_mean": vk.mean().item(), f"knn{k}_visits_p99": np.percentile(vk, 99).item(),
         "node_bytes_float": fb, "node_bytes_quantized": qb,
         "radius_touched_bytes_float": vr.mean().item() * fb, "radius_touched_bytes_quantized": vr.mean().item() * qb,
         f"knn{k}_touched_bytes_float": vk.mean().item() * fb, f"knn{k}_touched_bytes_quantized": vk.mean().item() * qb,
