@@ -96,6 +96,12 @@ def test_full_size_sampled_parity_and_properties(name):
     _, idw_t, dw_t = ax.arborx_query_spatial_with_distances(t, qd, r)
     same_w = bool(torch.equal(idw_t, idx_t)) and bool(torch.equal(dw_t.view(torch.int32), md_t.view(torch.int32)))
     del idw_t, dw_t
+    # the storage query with rows in the order found: the same offsets, and every row the same set
+    off_u, idx_u = ax.arborx_query_spatial(t, qd, r, ordered=False)
+    rows = torch.repeat_interleave(torch.arange(m, device="cuda", dtype=torch.int64), torch.diff(off_t))
+    same_u = bool(torch.equal(off_u, off_t)) and bool(torch.equal(
+        torch.sort(rows * n + idx_u.to(torch.int64)).values, rows * n + idx_t.to(torch.int64)))
+    del off_u, idx_u, rows
     torch.cuda.synchronize()
     off, idx = off_t.cpu().numpy(), idx_t.cpu().numpy()
     c, c2, s2 = c_t.cpu().numpy(), c2_t.cpu().numpy(), s2_t.cpu().numpy()
@@ -109,7 +115,7 @@ def test_full_size_sampled_parity_and_properties(name):
     del off_t, idx_t, c_t, c2_t, s2_t, d2_t, ix_t, u5_t, md_t, t
 
     # every query: properties
-    assert same_w
+    assert same_w and same_u
     assert off[0] == 0 and off[-1] == len(idx) and np.all(np.diff(off) >= 0)
     assert np.array_equal(np.diff(off), c) and np.array_equal(c, c2)
     assert np.all((idx >= 0) & (idx < n))
