@@ -167,14 +167,16 @@ __device__ __forceinline__ int32_t find_root(int32_t *parent, int32_t x)
 // by a device-wide exchange.  When it fails, the value it returns is that
 // root's true parent, smaller than it, and the walk goes on from there; so
 // every failure moves one of the two ends to a smaller index, and at most 2n
-// rounds finish.
-__device__ __forceinline__ void unite(int32_t *parent, int32_t a, int32_t b, int64_t n)
+// rounds finish.  Returns the root the merged component had when the link
+// was made: an ancestor of both a and b from then on (links are never
+// undone), so a caller may start its next find there instead of at a.
+__device__ __forceinline__ int32_t unite(int32_t *parent, int32_t a, int32_t b, int64_t n)
 {
     a = find_root(parent, a);
     b = find_root(parent, b);
     for (int64_t iter = 0; iter <= 2 * n + 1; ++iter) {
         if (a == b)
-            return;
+            return a;
         if (a < b) {
             const int32_t t = a;
             a = b;
@@ -182,10 +184,11 @@ __device__ __forceinline__ void unite(int32_t *parent, int32_t a, int32_t b, int
         }
         const int32_t old = atomicCAS(parent + a, a, b);
         if (old == a)
-            return;
+            return b;
         a = find_root(parent, old);
         b = find_root(parent, b);
     }
+    return b;
 }
 
 __global__ void k_dbscan_init(int32_t *__restrict__ parent, int32_t *__restrict__ border, int64_t n)
@@ -212,7 +215,7 @@ __global__ void k_dbscan_pairs(const Node<D> *__restrict__ nodes, const QNode<D>
     if (p0 >= n - 1)
         return;
     Sphere<D> pred[W];
-    int id[W], best[W];
+    int id[W], best[W], root[W];  // root: an ancestor of id in the union-find forest, where finds start
     bool core[W];
 #pragma unroll
     for (int j = 0; j < W; ++j) {
@@ -227,13 +230,16 @@ __global__ void k_dbscan_pairs(const Node<D> *__restrict__ nodes, const QNode<D>
             pred[j].dead();
         }
     }
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+        root[j] = id[j];
     auto pair = [&](int j, int q, int qid) {
         const bool core_q = deg[q] + 1 >= min_pts;
 #pragma unroll
         for (int jj = 0; jj < W; ++jj)
             if (jj == j) {
                 if (core[jj] && core_q)
-                    unite(parent, id[jj], qid, n);
+                    root[jj] = unite(parent, root[jj], qid, n);
                 else if (core[jj])
                     atomicMin(border + q, id[jj]);
                 else if (core_q)
