@@ -801,10 +801,12 @@ __global__ void k_match_distances(const float *__restrict__ values, int64_t n, i
     }
 }
 
-// Early-terminating count (Section 2.2): a query's walk over binary nodes ends
-// once it has counted n_max matches; the result is min(count, n_max).
-template <int D>
-__global__ void k_count_up_to(const Node<D> *__restrict__ nodes, const TreeHeader *__restrict__ hdr,
+// Early-terminating count (Section 2.2): a query's walk over binary nodes
+// (float, or with Q the quantized ones) ends once it has counted n_max
+// matches; the result is min(count, n_max).
+template <int D, bool Q>
+__global__ void k_count_up_to(const Node<D> *__restrict__ nodes, const QNode<D> *__restrict__ qnodes,
+                              const float *__restrict__ leaves, int kind, const TreeHeader *__restrict__ hdr,
                               const float *__restrict__ queries, int64_t m, float r2, int n_max,
                               const uint32_t *__restrict__ perm, int32_t *__restrict__ counts, int stack_cap)
 {
@@ -822,8 +824,12 @@ __global__ void k_count_up_to(const Node<D> *__restrict__ nodes, const TreeHeade
     int c = 0;
     auto f = [&](int, float) { ++c; };
     auto stop = [&]() { return c >= n_max; };
-    if (n_max > 0)
-        traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f, stop);
+    if (n_max > 0) {
+        if constexpr (Q)
+            traverse_spatial_q<D>(qnodes, *hdr, node_count(hdr), leaves, kind, pred, st, f, stop);
+        else
+            traverse_spatial<D>(nodes, hdr->root, node_count(hdr), pred, st, f, stop);
+    }
     counts[qi] = c < n_max ? c : n_max;
 }
 
@@ -1458,10 +1464,18 @@ template <int D>
 arborx_status count_up_to_impl(const TreeDev &t, const float *q, int64_t m, float r2, int n_max,
                                const uint32_t *perm, int32_t *counts, hipStream_t s)
 {
+    // the reductions' node format: quantized nodes where the tree holds them and the tuning walks them
+    const bool qf = tree_format(OP_REDUCE, t) == 1 && t.qnodes;
     const Launch L = traversal_launch(m, sizeof(int), OP_REDUCE, D);
     ProfScope ps("count_up_to", s);
-    k_count_up_to<D><<<L.grid, L.block, L.lds, s>>>(static_cast<const Node<D> *>(t.nodes), t.hdr, q, m, r2, n_max,
-                                                      perm, counts, L.cap);
+    const Node<D> *nodes = static_cast<const Node<D> *>(t.nodes);
+    const QNode<D> *qnodes = static_cast<const QNode<D> *>(t.qnodes);
+    if (qf)
+        k_count_up_to<D, true><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, t.leaves, t.kind, t.hdr, q, m, r2, n_max,
+                                                              perm, counts, L.cap);
+    else
+        k_count_up_to<D, false><<<L.grid, L.block, L.lds, s>>>(nodes, qnodes, t.leaves, t.kind, t.hdr, q, m, r2,
+                                                               n_max, perm, counts, L.cap);
     AX_HIP(hipGetLastError());
     return ARBORX_OK;
 }

@@ -534,10 +534,11 @@ __device__ __forceinline__ void qboxes(const QNode<D> &nd, bool points, const fl
 // tree's leaf child is exact in the node and reported from it; a box tree's
 // leaf whose decoded box passes is tested exactly on its leaf record.  (An
 // empty slot's bytes are never reported: its reference is checked first.)
-template <int D, class P, class F>
+// An optional stop functor ends the walk as in traverse_spatial.
+template <int D, class P, class F, class S = NeverStop>
 __device__ __forceinline__ void traverse_spatial_q(const QNode<D> *__restrict__ nodes, const TreeHeader &h,
                                                    int n_nodes, const float *__restrict__ leaves, int kind,
-                                                   const P &pred, ShortStack<int> &st, F &f)
+                                                   const P &pred, ShortStack<int> &st, F &f, const S &stop = S())
 {
     const bool points = kind != ARBORX_BOXES;
     float flo[D], fsc[D];
@@ -576,6 +577,8 @@ __device__ __forceinline__ void traverse_spatial_q(const QNode<D> *__restrict__ 
             }
             h1 = false;
         }
+        if (stop())
+            break;
         if (h0) {
             if (h1)
                 st.push(c1);

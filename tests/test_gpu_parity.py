@@ -943,6 +943,9 @@ def test_deepest_tree_one_entry_ring(tuning):
         for r in (float("inf"), 2.0 ** -20, 0.0):  # every value deferred and found again at r = inf
             check_spatial(t, data, q, r)
             check_reduce(t, data, q, r)
+            for n_max in (1, 40):  # the early-terminating walk stops with deferred subtrees left
+                got = host(ax.arborx_query_spatial_count_up_to(t, dev(q), r, n_max))
+                assert np.array_equal(got, oracle.count_up_to(data, q, r, n_max))
         check_knn(t, data, q, 64)
         check_knn(t, data, q, 3)
     finally:
