@@ -80,6 +80,7 @@ def test_query_argument_validation():
     assert L.arborx_query_spatial_begin(None, FAKE, 1, f(1), FAKE, ctypes.byref(tot), ctypes.byref(plan), None) == 1
     assert L.arborx_query_intersects_begin(None, FAKE, 1, FAKE, ctypes.byref(tot), ctypes.byref(plan), None) == 1
     assert L.arborx_query_finish(None, FAKE, 1) == 1
+    assert L.arborx_query_finish_unsorted(None, FAKE, 1) == 1
     assert L.arborx_plan_destroy(None) == 0
 
 
