@@ -1212,6 +1212,7 @@ arborx_status forest_rebuild_impl(const float *values, const int64_t *offs, Fore
         forest_headers<D><<<grid_for(T, 256), 256, 0, s>>>(f.seg, T, w.tmin, w.tmax, f.hdrs);
     }
     AX_HIP(hipGetLastError());
+    f.keys = nullptr;
     if (n == 0)
         return ARBORX_OK;
     int tb = 1;
@@ -1234,6 +1235,8 @@ arborx_status forest_rebuild_impl(const float *values, const int64_t *offs, Fore
         codes = codes2;
         ids = ids2;
     }
+    f.keys = codes;  // kept in the build workspace until the next rebuild: kNN seeds search them
+    f.mbits = mbits;
     constexpr int C = chunk_leaves<D>();
     const int chunks = (int)((n + C - 1) / C);
     Escape<D> *esc = static_cast<Escape<D> *>(w.esc);

@@ -210,7 +210,7 @@ __global__ __launch_bounds__(kForestBlock) void k_forest_knn(
     const TreeHeader *__restrict__ hdrs, int T, const float *__restrict__ queries, int64_t m,
     const uint32_t *__restrict__ perm, const int64_t *__restrict__ boff, int B, const int32_t *__restrict__ btree,
     int k_out, float *__restrict__ out_d2, int32_t *__restrict__ out_idx, unsigned long long *counter, int stack_cap,
-    int seed)
+    int seed, const uint64_t *__restrict__ keys, int mbits)
 {
     extern __shared__ int s_stack[];
     KnnEntry spill[kSpill];
@@ -237,12 +237,14 @@ __global__ __launch_bounds__(kForestBlock) void k_forest_knn(
         for (int d = 0; d < D; ++d)
             q[d] = queries[qi * D + d];
         ShortStack<KnnEntry> st(reinterpret_cast<KnnEntry *>(s_stack) + threadIdx.x, blockDim.x, stack_cap, spill);
+        // the seed searches this tree's segment of the forest's sorted build keys
+        const SeedKeys sk{keys, tr >= 0 && tr < T ? (uint64_t)tr << mbits : 0, mbits / D};
         if (FMT == 1)
-            knn_search_q<D, K>(qnodes, n_nodes, leaves, kind, h, q, best, st, seed, nullptr);
+            knn_search_q<D, K>(qnodes, n_nodes, leaves, kind, h, q, best, st, seed, sk);
         else if (FMT == 2)
-            knn_search4<D, K>(nodes, wnodes, n_nodes, leaves, kind, h, q, best, st, seed, nullptr);
+            knn_search4<D, K>(nodes, wnodes, n_nodes, leaves, kind, h, q, best, st, seed, sk);
         else
-            knn_search<D, K>(nodes, n_nodes, leaves, kind, h, q, best, st, seed, nullptr);
+            knn_search<D, K>(nodes, n_nodes, leaves, kind, h, q, best, st, seed, sk);
         best.store(k_out, out_d2 + qi * k_out, out_idx + qi * k_out, h.start);  // indices local to the tree
     }
 }
@@ -421,7 +423,7 @@ arborx_status forest_knn_launch(ForestDev &f, const float *q, int64_t m, const i
         k_forest_knn<D, K, F><<<grid, kForestBlock, lds, s>>>(                                                    \
             static_cast<const Node<D> *>(f.nodes), static_cast<const QNode<D> *>(f.qnodes),                        \
             static_cast<const Node4<D> *>(f.wnodes), (int)(f.n > 0 ? f.n : 1), f.leaves, f.kind, f.hdrs, f.T, q, m, \
-            perm, boff, B, btree, k, d2, idx, counter, cap, tu.seed);                                              \
+            perm, boff, B, btree, k, d2, idx, counter, cap, tu.seed, f.keys, f.mbits);                             \
     } while (0)
     if (fmt == 1)
         AX_FKNN(1);

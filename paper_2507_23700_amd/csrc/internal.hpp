@@ -184,6 +184,8 @@ struct ForestDev {
     void *qnodes = nullptr;    // QNode<dim>[n]
     void *wnodes = nullptr;    // Node4<dim>[n]
     float *leaves = nullptr;   // n leaf records, sorted inside each tree
+    uint64_t *keys = nullptr;  // [n] sorted build keys (tree << mbits | tree-local Morton code), in the build workspace
+    int mbits = 0;             // bits of the tree-local code in a key
     TreeHeader *hdrs = nullptr;  // [T]
     int64_t *seg = nullptr;    // [T+1] device copy of the tree offsets
     void *ws = nullptr;        // query workspace, grown on demand (reserve before graph capture)

@@ -758,11 +758,11 @@ __global__ __attribute__((amdgpu_waves_per_eu(knn_waves<D, K, WAVE, FMT>()))) vo
         KnnEntry spill[kSpill];
         ShortStack<KnnEntry> st(reinterpret_cast<KnnEntry *>(s_stack) + threadIdx.x, blockDim.x, stack_cap, spill);
         if (FMT == 1)
-            knn_search_q<D, K>(qnodes, n_nodes, leaves, kind, *hdr, q, best, st, seed, codes);
+            knn_search_q<D, K>(qnodes, n_nodes, leaves, kind, *hdr, q, best, st, seed, SeedKeys{codes, 0, 63 / D});
         else if (FMT == 2)
-            knn_search4<D, K>(nodes, wnodes, n_nodes, leaves, kind, *hdr, q, best, st, seed, codes);
+            knn_search4<D, K>(nodes, wnodes, n_nodes, leaves, kind, *hdr, q, best, st, seed, SeedKeys{codes, 0, 63 / D});
         else
-            knn_search<D, K>(nodes, n_nodes, leaves, kind, *hdr, q, best, st, seed, codes);
+            knn_search<D, K>(nodes, n_nodes, leaves, kind, *hdr, q, best, st, seed, SeedKeys{codes, 0, 63 / D});
     }
     if (active)
         best.store(k_out, out_d2 + qi * k_out, out_idx + qi * k_out, 0);
@@ -866,7 +866,7 @@ __global__ void k_debug_visits(const Node<D> *__restrict__ nodes, const uint64_t
         TopK<K> best;
         KnnEntry spill[kSpill];
         ShortStack<KnnEntry> st(reinterpret_cast<KnnEntry *>(s_stack) + threadIdx.x, blockDim.x, stack_cap, spill);
-        knn_search<D, K>(nodes, n_nodes, leaves, kind, *hdr, q, best, st, 0, codes, &v);
+        knn_search<D, K>(nodes, n_nodes, leaves, kind, *hdr, q, best, st, 0, SeedKeys{codes, 0, 63 / D}, &v);
     }
     visits[qi] = v;
 }

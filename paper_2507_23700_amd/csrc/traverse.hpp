@@ -821,20 +821,31 @@ __device__ __forceinline__ float leaf_d2(const float *__restrict__ leaves, int k
     return box_d2<D>(q, lo, hi);
 }
 
+// Sorted leaf keys a kNN seed searches for the query's position: a tree's
+// Morton codes (no prefix, 63/D bits per dimension), or a forest's keys, whose
+// segment for tree t holds (t << mbits) | the tree-local code (mbits/D bits per
+// dimension, on that tree's bounds).  Without codes a greedy descent finds the
+// position.
+struct SeedKeys {
+    const uint64_t *codes = nullptr;
+    uint64_t prefix = 0;
+    int bits = 0;
+};
+
 // Position of q among the sorted leaves of the tree of hdr: the first leaf
-// whose Morton code (the build's, on the tree's bounds) is not below q's,
-// found by binary search over the kept codes, clamped to the tree.
+// whose key (the build's, on the tree's bounds) is not below q's, found by
+// binary search over the tree's segment of the keys, clamped to the tree.
 template <int D>
-__device__ __forceinline__ int leaf_position(const uint64_t *__restrict__ codes, const TreeHeader &hdr, const float *q)
+__device__ __forceinline__ int leaf_position(const SeedKeys &keys, const TreeHeader &hdr, const float *q)
 {
-    constexpr int bits = 63 / D;
     uint32_t c[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         const float ext = hdr.hi[d] - hdr.lo[d];
-        c[d] = quantise(q[d], hdr.lo[d], ext > 0.0f ? 1.0f / ext : 0.0f, bits);
+        c[d] = quantise(q[d], hdr.lo[d], ext > 0.0f ? 1.0f / ext : 0.0f, keys.bits);
     }
-    const uint64_t key = interleave<D>(c, bits);
+    const uint64_t key = keys.prefix | interleave<D>(c, keys.bits);
+    const uint64_t *__restrict__ codes = keys.codes;
     int lo = hdr.start, hi = hdr.start + hdr.n;  // first code >= key in [lo, hi)
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -946,8 +957,8 @@ __device__ __forceinline__ void seed_window(const float *__restrict__ leaves, in
 }
 
 // Seeding of a kNN walk: the query's position in the tree's sorted leaves
-// (binary search over the kept leaf codes, or a greedy nearer-child descent
-// when there are none); the K-th smallest distance among the 2K leaves around
+// (binary search over the kept leaf keys, a tree's codes or its segment of a
+// forest's keys, or a greedy nearer-child descent when there are none); the K-th smallest distance among the 2K leaves around
 // it bounds the K-th nearest distance from above, so the walk starts with that
 // bound instead of +inf.  The heap then starts as K copies of
 // (bound, INT32_MAX): every value at distance < bound, or == bound, orders
@@ -956,12 +967,12 @@ __device__ __forceinline__ void seed_window(const float *__restrict__ leaves, in
 template <int D, int K>
 __device__ __forceinline__ void knn_seed(const Node<D> *__restrict__ nodes, int n_nodes,
                                          const float *__restrict__ leaves, int kind, const TreeHeader &hdr,
-                                         const float *q, TopK<K> &best, int seed, const uint64_t *__restrict__ codes)
+                                         const float *q, TopK<K> &best, int seed, const SeedKeys &keys)
 {
     const int n = hdr.n;
     best.reset(INFINITY);
     if (seed != 1 && n >= K) {
-        int cur = codes ? -1 : hdr.root, pos = codes ? leaf_position<D>(codes, hdr, q) : hdr.start;
+        int cur = keys.codes ? -1 : hdr.root, pos = keys.codes ? leaf_position<D>(keys, hdr, q) : hdr.start;
         for (int iter = 0; iter <= n_nodes; ++iter) {
             if ((unsigned)cur >= (unsigned)n_nodes)
                 break;
@@ -993,9 +1004,9 @@ template <int D, int K>
 __device__ __forceinline__ void knn_search(const Node<D> *__restrict__ nodes, int n_nodes,
                                            const float *__restrict__ leaves, int kind, const TreeHeader &hdr,
                                            const float *q, TopK<K> &best, ShortStack<KnnEntry> &st, int seed,
-                                           const uint64_t *__restrict__ codes, int *visits = nullptr)
+                                           const SeedKeys &keys, int *visits = nullptr)
 {
-    knn_seed<D, K>(nodes, n_nodes, leaves, kind, hdr, q, best, seed, codes);
+    knn_seed<D, K>(nodes, n_nodes, leaves, kind, hdr, q, best, seed, keys);
     if (hdr.n <= 0)
         return;
     int cur = hdr.root;
@@ -1065,14 +1076,14 @@ template <int D, int K>
 __device__ __forceinline__ void knn_search4(const Node<D> *__restrict__ nodes, const Node4<D> *__restrict__ wnodes,
                                             int n_nodes, const float *__restrict__ leaves, int kind,
                                             const TreeHeader &hdr, const float *q, TopK<K> &best,
-                                            ShortStack<KnnEntry> &st, int seed, const uint64_t *__restrict__ codes)
+                                            ShortStack<KnnEntry> &st, int seed, const SeedKeys &keys)
 {
     const int n = hdr.n;
     best.reset(INFINITY);
     if (n <= 0)
         return;
     if (seed != 1 && n >= K) {
-        int cur = codes ? -1 : hdr.root, pos = codes ? leaf_position<D>(codes, hdr, q) : hdr.start;
+        int cur = keys.codes ? -1 : hdr.root, pos = keys.codes ? leaf_position<D>(keys, hdr, q) : hdr.start;
         for (int iter = 0; iter <= n_nodes; ++iter) {
             if ((unsigned)cur >= (unsigned)n_nodes)
                 break;
@@ -1158,7 +1169,7 @@ __device__ __forceinline__ void knn_search_wave(const Node<D> *__restrict__ node
                                                 KnnEntry *wstack, int seed)
 {
     const int n = hdr.n;
-best.reset(INFINITY);
+    best.reset(INFINITY);
     if (n <= 0)
         return;
     if (active && seed != 1 && n >= K) {
@@ -1236,7 +1247,7 @@ template <int D, int K>
 __device__ __forceinline__ void knn_search_q(const QNode<D> *__restrict__ nodes, int n_nodes,
                                              const float *__restrict__ leaves, int kind, const TreeHeader &hdr,
                                              const float *q, TopK<K> &best, ShortStack<KnnEntry> &st,
-                                             int seed, const uint64_t *__restrict__ codes)
+                                             int seed, const SeedKeys &keys)
 {
     const int n = hdr.n;
     best.reset(INFINITY);
@@ -1250,7 +1261,7 @@ __device__ __forceinline__ void knn_search_q(const QNode<D> *__restrict__ nodes,
         fsc[d] = hdr.qscale[d];
     }
     if (seed != 1 && n >= K) {
-        int cur = codes ? -1 : hdr.root, pos = codes ? leaf_position<D>(codes, hdr, q) : hdr.start;
+        int cur = keys.codes ? -1 : hdr.root, pos = keys.codes ? leaf_position<D>(keys, hdr, q) : hdr.start;
         for (int iter = 0; iter <= n_nodes; ++iter) {
             if ((unsigned)cur >= (unsigned)n_nodes)
                 break;
